@@ -1,0 +1,310 @@
+"""Fully discrete adaptive dynamical low-rank step (oracle, float64).
+
+TEST INFRASTRUCTURE ONLY -- see oracle/__init__.py.
+
+Follows the paper:
+  * state f = sum_ij X_i S_ij V_j with <X_i,X_j>_x = <V_i,V_j>_v = delta_ij
+    (eqs. lowrank decomposition, orthogonality); inner products by the
+    midpoint rule, <a,b>_x = dx sum a b, <a,b>_v = dv^d sum a b (Sec. 2.4);
+  * first-order upwind "discretise then project" transport, v^+ D_+ with a
+    backward and v^- D_- with a forward difference (eq. scheme:fullupwind);
+  * ghost values of K from the projected boundary function f^b (eq. boundary
+    general), inflow Maxwellian on the inflow half, the outflow half taken
+    from the adjacent interior cell (Sec. 2.3);
+  * K-step, S-step, L-step with forward Euler and QR (Sec. 2.4), the
+    collision terms written with the symmetrised pair values Q_s(V_m, V_n)
+    for m <= n and weights (2 - delta_mn);
+  * residual err from the pieces dK, dS, dL and the cross terms I, II, III
+    (eqs. err low rank1, err low rank2, Sec. 5.1);
+  * adaptivity: add the boundary basis at the start of a step (Sec. 3.1),
+    drop singular values of S below drop_tol = c * err at its end (Sec. 3.2,
+    Sec. 5.1 with c = 0.2), err_ada evaluated exactly from the factors.
+
+Space is one-dimensional here (x along the first velocity axis), which is the
+geometry of the normal-shock workload.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import collision as oc
+
+
+@dataclass
+class Problem1D:
+    vs: oc.VelocitySetup
+    nx: int
+    x_lo: float
+    x_hi: float
+    fL: np.ndarray            # inflow Maxwellian at the left wall, (n,)
+    fR: np.ndarray            # inflow Maxwellian at the right wall, (n,)
+    conserve: bool = True     # conservation projection of each Q_s
+    collision: object = None  # pair evaluator: (V, pairs, vs, conserve) -> (Q, Q+)
+
+    @property
+    def dx(self):
+        return (self.x_hi - self.x_lo) / self.nx
+
+    @property
+    def dvd(self):
+        return self.vs.dv ** self.vs.d
+
+    def v1(self):
+        return oc.grid(self.vs)[0].reshape(-1)
+
+
+@dataclass
+class State:
+    X: np.ndarray   # (nx, r)
+    S: np.ndarray   # (r, r)
+    V: np.ndarray   # (r, n), rows are V_j
+
+    @property
+    def r(self):
+        return self.S.shape[0]
+
+    def full(self):
+        return self.X @ self.S @ self.V
+
+
+@dataclass
+class StepInfo:
+    err: float = 0.0
+    err_ada: float = 0.0
+    drop_tol: float = 0.0
+    r_in: int = 0
+    r_added: int = 0
+    r_out: int = 0
+    sigma_dropped: float = 0.0
+    extra: dict = field(default_factory=dict)
+
+
+# ----------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------
+def pair_list(r: int):
+    return [(m, n) for m in range(r) for n in range(m, r)]
+
+
+def qr_pos(A: np.ndarray):
+    """Householder QR (numpy) with diag(R) >= 0."""
+    Q, R = np.linalg.qr(A)
+    s = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return Q * s[None, :], R * s[:, None]
+
+
+def weighted_qr_cols(A: np.ndarray, w: float):
+    """A = Q R with <Q_i, Q_j> = delta_ij in the inner product w * sum."""
+    Q, R = qr_pos(math.sqrt(w) * A)
+    return Q / math.sqrt(w), R
+
+
+def transport_matrices(V: np.ndarray, prob: Problem1D):
+    """A^+_{jl} = <v^+ V_j V_l>_v, A^-_{jl} = <v^- V_j V_l>_v."""
+    v1 = prob.v1()
+    vp = np.maximum(v1, 0.0)
+    vm = np.minimum(v1, 0.0)
+    return prob.dvd * (V * vp) @ V.T, prob.dvd * (V * vm) @ V.T
+
+
+def ghosts(K: np.ndarray, V: np.ndarray, prob: Problem1D):
+    """Ghost values of K_j at both walls from the projected boundary function:
+    K_j = <f_bdy 1_in, V_j>_v + sum_l K_l(adjacent cell) <1_out V_l V_j>_v.
+    Left wall (outward normal -e1): inflow v1 > 0.  Right wall: inflow v1 < 0."""
+    v1 = prob.v1()
+    inL = (v1 > 0).astype(np.float64)
+    inR = (v1 < 0).astype(np.float64)
+    outL, outR = 1.0 - inL, 1.0 - inR
+    gl = prob.dvd * V @ (prob.fL * inL) + prob.dvd * ((V * outL) @ V.T) @ K[0]
+    gr = prob.dvd * V @ (prob.fR * inR) + prob.dvd * ((V * outR) @ V.T) @ K[-1]
+    return gl, gr
+
+
+def d_plus(K, gl, dx):
+    """(K_p - K_{p-1}) / dx with the left ghost."""
+    prev = np.vstack([gl[None, :], K[:-1]])
+    return (K - prev) / dx
+
+
+def d_minus(K, gr, dx):
+    """(K_{p+1} - K_p) / dx with the right ghost."""
+    nxt = np.vstack([K[1:], gr[None, :]])
+    return (nxt - K) / dx
+
+
+def collision_tensor(V, Qs, prob):
+    """C_{j,(mn)} = <V_j, Q_s(V_m, V_n)>_v, shape (r, P)."""
+    return prob.dvd * V @ Qs.T
+
+
+def pair_products(K, pairs, wts):
+    """(2 - delta_mn) K_m K_n for each pair, shape (nx, P)."""
+    return np.stack([w * K[:, m] * K[:, n] for (m, n), w in zip(pairs, wts)], axis=1)
+
+
+def evaluate_pairs(V, pairs, prob):
+    if prob.collision is not None:
+        return prob.collision(V, pairs, prob.vs, prob.conserve)
+    return oc.q_pairs(V, pairs, prob.vs, conserve=prob.conserve)
+
+
+# ----------------------------------------------------------------------------
+# one fixed-rank step (Sec. 2.4)
+# ----------------------------------------------------------------------------
+def ksl_step(st: State, prob: Problem1D, dt: float, Qs=None):
+    """One K -> S -> L step with forward Euler; returns (new State, err, pieces)."""
+    X, S, V = st.X, st.S, st.V
+    r = S.shape[0]
+    dx, dvd = prob.dx, prob.dvd
+    pairs = pair_list(r)
+    wts = np.array([1.0 if m == n else 2.0 for (m, n) in pairs])
+    if Qs is None:
+        Qs, _ = evaluate_pairs(V, pairs, prob)            # (P, n) reused by K, S, L
+    Ap, Am = transport_matrices(V, prob)
+    Cj = collision_tensor(V, Qs, prob)                    # (r, P)
+
+    # K-step
+    K = X @ S
+    gl, gr = ghosts(K, V, prob)
+    rhsK = -d_plus(K, gl, dx) @ Ap.T - d_minus(K, gr, dx) @ Am.T \
+        + pair_products(K, pairs, wts) @ Cj.T
+    K1 = K + dt * rhsK
+    X1, S1 = weighted_qr_cols(K1, dx)
+
+    # S-step (uses K^{n+1} = X1 S1 and its own ghosts)
+    Kn = X1 @ S1
+    gl, gr = ghosts(Kn, V, prob)
+    Dp = dx * X1.T @ d_plus(Kn, gl, dx)                   # <X_i, D_+ K_l>_x, (r, r)
+    Dm = dx * X1.T @ d_minus(Kn, gr, dx)
+    T = dx * X1.T @ pair_products(Kn, pairs, wts)         # (r, P)
+    S2 = S1 + dt * (Dp @ Ap.T + Dm @ Am.T - T @ Cj.T)
+
+    # L-step
+    L = S2 @ V                                            # (r, n)
+    Kt = X1 @ S2
+    gl, gr = ghosts(Kt, V, prob)
+    Dpt = dx * X1.T @ d_plus(Kt, gl, dx)
+    Dmt = dx * X1.T @ d_minus(Kt, gr, dx)
+    Tt = dx * X1.T @ pair_products(Kt, pairs, wts)        # (r, P)
+    v1 = prob.v1()
+    vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
+    L1 = L - dt * ((Dpt @ V) * vp[None, :] + (Dmt @ V) * vm[None, :]) + dt * Tt @ Qs
+    Vq, R = weighted_qr_cols(L1.T, dvd)
+    V1 = Vq.T
+    Snew = R.T
+
+    # residual from the pieces (Sec. 5.1)
+    dK = K1 - K
+    dS = S2 - S1
+    dL = L1 - L
+    kx = dx * X1.T @ dK                                   # <dK_j, X_i>, indexed [i, j]
+    lv = dvd * dL @ V.T                                   # <dL_i, V_j>, [i, j]
+    e2 = dx * (dK ** 2).sum() + (dS ** 2).sum() + dvd * (dL ** 2).sum() \
+        + 2.0 * (kx * dS).sum() + 2.0 * (lv * dS).sum() + 2.0 * (kx * lv).sum()
+    err = math.sqrt(max(e2, 0.0))
+    pieces = dict(K1=K1, S1=S1, S2=S2, L1=L1, X1=X1, Qs=Qs, Cj=Cj, e2=e2)
+    return State(X1, Snew, V1), err, pieces
+
+
+# ----------------------------------------------------------------------------
+# adaptivity (Sec. 3)
+# ----------------------------------------------------------------------------
+def boundary_matrix(st: State, prob: Problem1D):
+    """F_b rows f^b(x_b, .) at the two walls: inflow half from the prescribed
+    Maxwellian, outflow half from the adjacent interior cell."""
+    v1 = prob.v1()
+    K = st.X @ st.S
+    fin = K[0] @ st.V
+    fout = K[-1] @ st.V
+    left = np.where(v1 > 0, prob.fL, fin)
+    right = np.where(v1 < 0, prob.fR, fout)
+    return np.vstack([left, right])
+
+
+def add_boundary_basis(st: State, prob: Problem1D, add_tol: float = 1e-10,
+                       r_max: int = 10 ** 9, rng=None):
+    """Append the right singular vectors of F_b with sigma > add_tol (capped at
+    r_max), a random X_h, zero-padded S; re-orthonormalise both sides by QR;
+    S_q = S_x S^ S_v^T.  Leaves f unchanged."""
+    Fb = boundary_matrix(st, prob)
+    _, sb, Qbt = np.linalg.svd(Fb, full_matrices=False)
+    rb = int((sb > add_tol).sum())
+    rb = max(0, min(rb, r_max - st.r))
+    if rb == 0:
+        return st, 0
+    if rng is None:
+        rng = np.random.default_rng(0)
+    Xh = rng.standard_normal((st.X.shape[0], rb))
+    Xhat = np.hstack([st.X, Xh])
+    Vhat = np.vstack([st.V, Qbt[:rb]])
+    Shat = np.zeros((st.r + rb, st.r + rb))
+    Shat[:st.r, :st.r] = st.S
+    Xq, Sx = weighted_qr_cols(Xhat, prob.dx)
+    Vq, Sv = weighted_qr_cols(Vhat.T, prob.dvd)
+    return State(Xq, Sx @ Shat @ Sv.T, Vq.T), rb
+
+
+def drop_basis(st: State, drop_tol: float, r_min: int = 1, r_max: int = 10 ** 9):
+    """SVD of S; keep sigma >= drop_tol (clamped to [r_min, r_max]); rotate."""
+    U, s, Qt = np.linalg.svd(st.S)
+    keep = int((s >= drop_tol).sum())
+    keep = max(min(keep, r_max, len(s)), min(r_min, len(s)))
+    X = st.X @ U[:, :keep]
+    V = Qt[:keep] @ st.V
+    return State(X, np.diag(s[:keep]), V), s, keep, U, Qt
+
+
+def adaptive_step(st: State, prob: Problem1D, dt: float, c: float = 0.2,
+                  add: bool = True, drop: bool = True, add_tol: float = 1e-10,
+                  r_min: int = 1, r_max: int = 30, rng=None):
+    info = StepInfo(r_in=st.r)
+    if add:
+        st, rb = add_boundary_basis(st, prob, add_tol, r_max, rng)
+        info.r_added = rb
+    start = st
+    new, err, pieces = ksl_step(st, prob, dt)
+    info.err = err
+    if not drop:
+        info.err_ada = err
+        info.r_out = new.r
+        return new, info
+    drop_tol = c * err
+    info.drop_tol = drop_tol
+    out, s, keep, U, Qt = drop_basis(new, drop_tol, r_min, r_max)
+    # err_ada^2 = err^2 - |Sigma_perp|^2 + 2 <f^n, D>,  D = X1 U_p Sig_p Q_p^T V1
+    sp = s[keep:]
+    M = U[:, keep:] @ np.diag(sp) @ Qt[keep:]
+    A = prob.dx * start.X.T @ new.X                       # <X^n_k, X1_i>
+    B = prob.dvd * start.V @ new.V.T                      # <V^n_l, V1_j>
+    fnD = (start.S * (A @ M @ B.T)).sum()
+    e2 = err ** 2 - (sp ** 2).sum() + 2.0 * fnD
+    info.err_ada = math.sqrt(max(e2, 0.0))
+    info.sigma_dropped = float(math.sqrt((sp ** 2).sum()))
+    info.r_out = keep
+    return out, info
+
+
+def steady_solve(st: State, prob: Problem1D, dt: float, res_tol: float,
+                 max_steps: int, **kw):
+    hist = []
+    for n in range(max_steps):
+        st, info = adaptive_step(st, prob, dt, **kw)
+        hist.append(info)
+        if info.err_ada <= res_tol:
+            return st, hist, True
+    return st, hist, False
+
+
+def macroscopic(st: State, prob: Problem1D):
+    """rho, u_1, T per cell (gas constant 1): E = rho|u|^2/2 + d rho T / 2."""
+    vs = prob.vs
+    C = oc.moment_matrix(vs)                              # (d+2, n)
+    m = (st.X @ st.S) @ (st.V @ C.T)                      # (nx, d+2)
+    rho = m[:, 0]
+    u = m[:, 1:1 + vs.d] / rho[:, None]
+    E = 0.5 * m[:, -1]
+    T = (2.0 * E / rho - (u ** 2).sum(axis=1)) / vs.d
+    return rho, u[:, 0], T
