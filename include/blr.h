@@ -1,0 +1,190 @@
+/* blr.h -- C ABI of the MI355X (gfx950) collision hot path for the adaptive
+ * dynamical low-rank (DLR) Boltzmann method.
+ *
+ * Reference: J. Hu and Y. Wang, "An adaptive dynamical low rank method for the
+ * nonlinear Boltzmann equation".  Every entry point below names the passage of
+ * the paper that defines the operation.
+ *
+ * Conventions shared by all calls
+ *   - Every call returns blr_status; no C++ exception crosses this boundary.
+ *     On failure blr_last_error(ctx) returns a message valid until the next
+ *     call on the same context.
+ *   - Arrays passed in are DEVICE pointers (memory of the context's device)
+ *     unless stated otherwise, and are owned by the caller.  The library owns
+ *     only its context (tables, workspace, events).
+ *   - Work is issued on the context's HIP stream.  blr_collision_pairs is
+ *     asynchronous; blr_dlr_step and blr_steady_solve synchronise once per
+ *     step (the rank decision needs the singular values on the host).
+ *   - One context per host thread.
+ *
+ * Velocity grid (Sec. 2.1: the collision solver is a discrete velocity method
+ * on a uniform grid of [-L, L]^d): nodes v_q = -L + q * 2L/n, q in
+ * {0..n-1}^d, stored in C order (last axis fastest), n^d values per function.
+ */
+#ifndef BLR_H_
+#define BLR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct blr_ctx_t* blr_ctx;
+
+typedef enum {
+  BLR_OK = 0,
+  BLR_ERR_ARG = 1,            /* invalid argument (shape, range, null pointer)   */
+  BLR_ERR_NOMEM = 2,          /* device allocation failed                        */
+  BLR_ERR_HIP = 3,            /* a HIP runtime call failed                       */
+  BLR_ERR_UNSUPPORTED = 4,    /* valid but not built (grid size, dimension)      */
+  BLR_ERR_NUMERIC = 5,        /* NaN/Inf or a failed factorisation               */
+  BLR_ERR_NOT_CONVERGED = 6   /* steady solve reached max_steps                  */
+} blr_status;
+
+typedef enum { BLR_FP32 = 0, BLR_FP64 = 1 } blr_precision;
+
+/* blr_vgrid.flags */
+#define BLR_NO_CONSERVE      0x1u  /* skip the FP64 moment-conservation projection   */
+#define BLR_PLAIN_SCHEDULE   0x2u  /* one pair at a time, no shift reuse (baseline)   */
+#define BLR_GENERIC_FFT      0x4u  /* force the multi-pass FFT path (no fused kernels) */
+
+/* Velocity discretisation and collision kernel.
+ *   d       velocity dimension, 2 or 3
+ *   n       points per axis: 3D n in {8, 16, 24, 32}; 2D n in {16, 32, 48, 64}
+ *   L       half width of the velocity box
+ *   R       truncation radius of |v - v*|; R <= 0 selects 4L/(3 + sqrt 2)
+ *   C,gamma B(|v - v*|) = C |v - v*|^gamma (isotropic: Maxwell gamma = 0,
+ *           hard spheres gamma = 1)
+ *   m_rho   Gauss-Legendre nodes on [0, R] (1..64)
+ *   m_sigma sphere nodes: 2D an even count of equispaced angles (2..64);
+ *           3D must be 38 (Lebedev rule exact to degree 9); 0 = default 8 / 38
+ */
+typedef struct {
+  int32_t d, n;
+  double L, R;
+  double C, gamma;
+  int32_t m_rho, m_sigma;
+  uint32_t flags;
+} blr_vgrid;
+
+blr_status blr_create(int device, void* hip_stream, blr_ctx* out);
+blr_status blr_destroy(blr_ctx ctx);
+const char* blr_last_error(blr_ctx ctx);
+
+/* Bytes of device workspace that blr_collision_pairs (and the steps built on
+ * it) will hold for rank up to r_max at this grid and precision. */
+blr_status blr_workspace_bytes(blr_ctx ctx, const blr_vgrid* vg, int32_t r_max,
+                               blr_precision prec, size_t* out);
+
+/* Symmetrised pair collisions Q_s(V_i, V_j) = (Q(V_i,V_j) + Q(V_j,V_i)) / 2.
+ *
+ * Defines: the bilinear collision operator of eq. (collision_operator) with
+ * the post-collision velocities of eq. (collision velocity); the low-rank
+ * method needs Q only on pairs of velocity basis functions because Q is
+ * bilinear and local in x (remark after eq. K-step detailed).  The operator
+ * is the Fourier-Galerkin one on the grid: Nyquist modes of the inputs are
+ * dropped, convolutions are circular, the radial integral uses m_rho Gauss-
+ * Legendre nodes and the angular one the sigma rule (the loss term uses the
+ * same sigma rule, so mass is conserved exactly); unless BLR_NO_CONSERVE,
+ * each Q_s is then corrected in FP64 by the least-squares projection that
+ * zeroes its d+2 discrete moments (mass, momentum, energy).
+ *
+ *   V      r rows of n^d values (row i = V_i), float (BLR_FP32) or double
+ *   r      number of basis functions, 1 <= r <= 64
+ *   pairs  HOST int32 [npairs][2], 0 <= i, j < r (order within a pair is
+ *          free); read during the call to plan the launch, not retained
+ *   Q_out  npairs rows of n^d values, same type as V; row p = Q_s(pairs[p])
+ * FP32: FFTs, products and sums in float; the projection in double.
+ * FP64: everything in double.  Async on the context stream. */
+blr_status blr_collision_pairs(blr_ctx ctx, const blr_vgrid* vg, blr_precision prec,
+                               const void* V, int32_t r, const int32_t* pairs,
+                               int32_t npairs, void* Q_out);
+/* npairs may be 0 (no work).  1 <= npairs <= 4096. */
+
+/* ------------------------------------------------------------------ DLR -- */
+
+/* One-dimensional physical space along the first velocity axis (the normal
+ * shock geometry of Sec. 4 and 5.2).  Cells x_p = x_lo + (p + 1/2) dx,
+ * dx = (x_hi - x_lo)/nx.  Inflow boundary values (Sec. 2.3): f_left is used
+ * where v_1 > 0 at x_lo, f_right where v_1 < 0 at x_hi (device, n^d doubles
+ * each); the outflow halves come from the adjacent interior cell. */
+typedef struct {
+  int32_t nx;
+  double x_lo, x_hi;
+  const double* f_left;
+  const double* f_right;
+  blr_vgrid v;
+} blr_problem;
+
+/* Low-rank state f = sum_ij X_i S_ij V_j (eq. lowrank decomposition) with
+ * <X_i,X_j>_x = dx sum X_i X_j = delta_ij and <V_i,V_j>_v = dv^d sum V_i V_j
+ * = delta_ij (eq. orthogonality).  Device FP64, caller-owned, sized for r_cap:
+ *   X  r_cap rows of nx   (row i = X_i)
+ *   S  r_cap x r_cap row-major, leading r x r block used
+ *   V  r_cap rows of n^d  (row j = V_j)
+ * r is updated by the adaptive steps; 1 <= r <= r_cap <= 64. */
+typedef struct {
+  int32_t r, r_cap;
+  double* X;
+  double* S;
+  double* V;
+  int64_t step;
+  uint64_t seed;
+} blr_state;
+
+/* blr_step_params.flags */
+#define BLR_STEP_ADD            0x1u  /* add the boundary basis first (Sec. 3.1) */
+#define BLR_STEP_DROP           0x2u  /* drop small singular values of S (Sec. 3.2) */
+#define BLR_STEP_FP64_COLLISION 0x4u  /* pair collisions in FP64 (default FP32) */
+
+typedef struct {
+  double dt;
+  double c_drop;     /* drop_tol = c_drop * err (Sec. 5.1 uses 0.2)            */
+  double add_tol;    /* boundary singular values kept if > add_tol (1e-10)    */
+  int32_t r_min, r_max;
+  uint32_t flags;
+} blr_step_params;
+
+typedef struct {
+  double err, err_ada, drop_tol;
+  int32_t r_in, r_added, r_out;
+  float ms_collision, ms_step;
+} blr_step_info;
+
+/* Truncated SVD of a full f0 (Sec. 2.4, first paragraph): f0 is device FP64,
+ * nx rows of n^d values; writes rank-r factors into *state (state->r = r). */
+blr_status blr_state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0,
+                               int32_t r, blr_state* state);
+
+/* One time step: [add boundary basis] -> K-step -> S-step -> L-step with
+ * forward Euler and QR (Sec. 2.4, first-order upwind transport of eq.
+ * scheme:fullupwind, ghost values of eq. boundary general) -> residual err
+ * from the pieces (eqs. err low rank1, err low rank2) -> [drop with
+ * drop_tol = c_drop * err] -> err_ada.  On error *state is left unchanged. */
+blr_status blr_dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* state,
+                        const blr_step_params* sp, blr_step_info* info);
+
+typedef struct {
+  blr_step_params step;
+  double res_tol;     /* stop when err_ada <= res_tol (Sec. 5.1)  */
+  int64_t max_steps;
+} blr_solve_params;
+
+typedef struct {
+  int64_t steps;
+  double err_ada;
+  int32_t r, converged;
+  double ms_wall;
+} blr_solve_info;
+
+/* Repeated blr_dlr_step until err_ada <= res_tol (Sec. 5.1) or max_steps
+ * (then BLR_ERR_NOT_CONVERGED with the state of the last step). */
+blr_status blr_steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state,
+                            const blr_solve_params* p, blr_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BLR_H_ */

@@ -1,0 +1,218 @@
+"""Python binding of libblr (the MI355X collision hot path of the adaptive
+dynamical low-rank Boltzmann method).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libblr.so`` built from ``csrc/`` (see ``build.py``).  PyTorch
+supplies device memory and the stream.  Loading fails loudly when the library
+is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libblr.so")
+
+BLR_FP32, BLR_FP64 = 0, 1
+BLR_NO_CONSERVE = 0x1
+BLR_PLAIN_SCHEDULE = 0x2
+BLR_GENERIC_FFT = 0x4
+BLR_STEP_ADD = 0x1
+BLR_STEP_DROP = 0x2
+BLR_STEP_FP64_COLLISION = 0x4
+
+STATUS = {0: "BLR_OK", 1: "BLR_ERR_ARG", 2: "BLR_ERR_NOMEM", 3: "BLR_ERR_HIP",
+          4: "BLR_ERR_UNSUPPORTED", 5: "BLR_ERR_NUMERIC", 6: "BLR_ERR_NOT_CONVERGED"}
+
+EXPORTS = ["blr_create", "blr_destroy", "blr_last_error", "blr_workspace_bytes",
+           "blr_collision_pairs", "blr_state_from_full", "blr_dlr_step", "blr_steady_solve"]
+
+
+class BlrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class VGrid(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("n", ctypes.c_int32), ("L", ctypes.c_double),
+                ("R", ctypes.c_double), ("C", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("m_rho", ctypes.c_int32), ("m_sigma", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
+                ("f_left", ctypes.c_void_p), ("f_right", ctypes.c_void_p), ("v", VGrid)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("r_cap", ctypes.c_int32), ("X", ctypes.c_void_p),
+                ("S", ctypes.c_void_p), ("V", ctypes.c_void_p), ("step", ctypes.c_int64),
+                ("seed", ctypes.c_uint64)]
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("c_drop", ctypes.c_double), ("add_tol", ctypes.c_double),
+                ("r_min", ctypes.c_int32), ("r_max", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("err", ctypes.c_double), ("err_ada", ctypes.c_double), ("drop_tol", ctypes.c_double),
+                ("r_in", ctypes.c_int32), ("r_added", ctypes.c_int32), ("r_out", ctypes.c_int32),
+                ("ms_collision", ctypes.c_float), ("ms_step", ctypes.c_float)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("step", StepParams), ("res_tol", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("err_ada", ctypes.c_double), ("r", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("ms_wall", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libblr.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"libblr.so not built at {path}; run __graft_entry__.build() "
+                          f"or python paper_2112_02695_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.blr_create.argtypes = [ctypes.c_int, P, ctypes.POINTER(P)]
+    lib.blr_destroy.argtypes = [P]
+    lib.blr_last_error.argtypes = [P]
+    lib.blr_last_error.restype = ctypes.c_char_p
+    lib.blr_workspace_bytes.argtypes = [P, ctypes.POINTER(VGrid), ctypes.c_int32, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_size_t)]
+    lib.blr_collision_pairs.argtypes = [P, ctypes.POINTER(VGrid), ctypes.c_int, P, ctypes.c_int32,
+                                        P, ctypes.c_int32, P]
+    if hasattr(lib, "blr_dlr_step"):
+        lib.blr_state_from_full.argtypes = [P, ctypes.POINTER(Problem), P, ctypes.c_int32,
+                                            ctypes.POINTER(State)]
+        lib.blr_dlr_step.argtypes = [P, ctypes.POINTER(Problem), ctypes.POINTER(State),
+                                     ctypes.POINTER(StepParams), ctypes.POINTER(StepInfo)]
+        lib.blr_steady_solve.argtypes = [P, ctypes.POINTER(Problem), ctypes.POINTER(State),
+                                         ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)]
+    for name in EXPORTS:
+        if hasattr(lib, name):
+            getattr(lib, name).restype = ctypes.c_int if name != "blr_last_error" else ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def make_vgrid(d: int, n: int, L: float, C: float = 1.0, gamma: float = 0.0, m_rho: int = 16,
+               m_sigma: int = 0, R: float = 0.0, flags: int = 0) -> VGrid:
+    return VGrid(d, n, float(L), float(R), float(C), float(gamma), m_rho, m_sigma, flags)
+
+
+def vgrid_from_spec(spec, flags: int = 0) -> VGrid:
+    return make_vgrid(spec.d, spec.n, spec.L, spec.C, spec.gamma, spec.m_rho, spec.m_sigma,
+                      flags=flags)
+
+
+class Context:
+    """A libblr context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.blr_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise BlrError(rc, "blr_create failed")
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = self.lib.blr_last_error(self.h)
+            raise BlrError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.blr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, vg: VGrid, r_max: int, precision: int) -> int:
+        out = ctypes.c_size_t()
+        self._check(self.lib.blr_workspace_bytes(self.h, ctypes.byref(vg), r_max, precision,
+                                                 ctypes.byref(out)))
+        return out.value
+
+    def collision_pairs(self, vg: VGrid, V, pairs, out=None):
+        """Q_s(V_i, V_j) for each row (i, j) of ``pairs``; V is a CUDA tensor
+        (r, n^d) of float32 or float64.  Returns (npairs, n^d) on the stream."""
+        import torch
+        if not (V.is_cuda and V.dim() == 2 and V.is_contiguous()):
+            raise ValueError("V must be a contiguous 2-D CUDA tensor (r, n^d)")
+        prec = {torch.float32: BLR_FP32, torch.float64: BLR_FP64}[V.dtype]
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        npairs = pr.shape[0]
+        if out is None:
+            out = torch.empty((npairs, V.shape[1]), dtype=V.dtype, device=V.device)
+        assert out.is_contiguous() and out.dtype == V.dtype and out.shape[0] >= npairs
+        self._check(self.lib.blr_collision_pairs(
+            self.h, ctypes.byref(vg), prec, ctypes.c_void_p(V.data_ptr()), V.shape[0],
+            pr.ctypes.data_as(ctypes.c_void_p), npairs, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    # -------------------------------------------------------------- DLR --
+    def make_problem(self, vg: VGrid, nx: int, x_lo: float, x_hi: float, fL, fR) -> Problem:
+        assert fL.dtype.itemsize == 8 and fR.dtype.itemsize == 8
+        pb = Problem(nx, float(x_lo), float(x_hi), ctypes.c_void_p(fL.data_ptr()),
+                     ctypes.c_void_p(fR.data_ptr()), vg)
+        pb._keep = (fL, fR)
+        return pb
+
+    def make_state(self, X, S, V, r: int, seed: int = 0) -> State:
+        """X (r_cap, nx), S (r_cap, r_cap), V (r_cap, n^d): float64 CUDA tensors."""
+        r_cap = X.shape[0]
+        assert S.shape == (r_cap, r_cap) and V.shape[0] == r_cap
+        st = State(r, r_cap, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                   ctypes.c_void_p(V.data_ptr()), 0, seed)
+        st._keep = (X, S, V)
+        return st
+
+    def state_from_full(self, pb: Problem, f0, r: int, st: State):
+        self._check(self.lib.blr_state_from_full(self.h, ctypes.byref(pb),
+                                                 ctypes.c_void_p(f0.data_ptr()), r, ctypes.byref(st)))
+        return st
+
+    def dlr_step(self, pb: Problem, st: State, sp: StepParams) -> StepInfo:
+        info = StepInfo()
+        self._check(self.lib.blr_dlr_step(self.h, ctypes.byref(pb), ctypes.byref(st),
+                                          ctypes.byref(sp), ctypes.byref(info)))
+        return info
+
+    def steady_solve(self, pb: Problem, st: State, p: SolveParams, allow_unconverged=False):
+        info = SolveInfo()
+        rc = self.lib.blr_steady_solve(self.h, ctypes.byref(pb), ctypes.byref(st), ctypes.byref(p),
+                                       ctypes.byref(info))
+        if rc == 6 and allow_unconverged:
+            return info
+        self._check(rc)
+        return info
+
+
+def upper_pairs(r: int):
+    return [(i, j) for i in range(r) for j in range(i, r)]

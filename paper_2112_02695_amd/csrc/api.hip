@@ -1,0 +1,182 @@
+// C ABI entry points, context, workspace and table cache.
+#include <cmath>
+#include <cstring>
+
+#include "collision_common.hpp"
+#include "internal.hpp"
+
+void* blr_ctx_t::buf(const std::string& name, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  auto& b = bufs[name];
+  if (b.bytes < bytes) {
+    if (b.p) {
+      BLR_HIP(hipStreamSynchronize(stream));
+      BLR_HIP(hipFree(b.p));
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    BLR_HIP(hipMalloc(&b.p, bytes));
+    b.bytes = bytes;
+  }
+  return b.p;
+}
+
+void* blr_ctx_t::upload(const std::string& name, const void* host, size_t bytes) {
+  void* dst = buf(name, bytes);
+  if (bytes == 0) return dst;
+  // the pinned stage is reused: wait for the previous upload to be consumed
+  if (stage_done) BLR_HIP(hipEventSynchronize(stage_done));
+  if (stage_bytes < bytes) {
+    if (stage) BLR_HIP(hipHostFree(stage));
+    stage = nullptr;
+    stage_bytes = 0;
+    BLR_HIP(hipHostMalloc(&stage, bytes));
+    stage_bytes = bytes;
+  }
+  std::memcpy(stage, host, bytes);
+  BLR_HIP(hipMemcpyAsync(dst, stage, bytes, hipMemcpyHostToDevice, stream));
+  if (!stage_done) BLR_HIP(hipEventCreateWithFlags(&stage_done, hipEventDisableTiming));
+  BLR_HIP(hipEventRecord(stage_done, stream));
+  return dst;
+}
+
+void blr_ctx_t::release_all() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  for (auto& kv : bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  bufs.clear();
+  tables.clear();
+  if (stage) (void)hipHostFree(stage);
+  stage = nullptr;
+  if (stage_done) (void)hipEventDestroy(stage_done);
+  stage_done = nullptr;
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+namespace blr {
+
+DevTables::~DevTables() {
+  for (void* p : owned)
+    if (p) (void)hipFree(p);
+}
+
+template <typename T>
+static void* upload_vec(DevTables& t, const std::vector<T>& v) {
+  void* p = nullptr;
+  BLR_HIP(hipMalloc(&p, std::max<size_t>(v.size() * sizeof(T), 16)));
+  t.owned.push_back(p);
+  if (!v.empty()) BLR_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+template <typename T>
+static std::vector<T> cast_vec(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
+  validate_vgrid(vg);
+  const int ms = vg.m_sigma ? vg.m_sigma : (vg.d == 2 ? 8 : 38);
+  auto key = std::make_tuple(vg.d, vg.n, vg.L, vg.R, vg.C, vg.gamma, vg.m_rho, ms, prec);
+  auto it = ctx->tables.find(key);
+  if (it != ctx->tables.end()) return *it->second;
+  auto t = std::make_unique<DevTables>();
+  t->h = build_tables(vg);
+  t->prec = prec;
+  const HostTables& h = t->h;
+  std::vector<double> wbp(h.nbp);
+  for (int p = 0; p < h.nbp; ++p) wbp[p] = h.wsig[h.bp_b[p]];
+  if (prec == BLR_FP32) {
+    t->phase = upload_vec(*t, cast_vec<float>(h.phase));
+    t->fw = upload_vec(*t, cast_vec<float>(h.fw));
+    t->gloss = upload_vec(*t, cast_vec<float>(h.gloss));
+    t->wbp = upload_vec(*t, cast_vec<float>(wbp));
+  } else {
+    t->phase = upload_vec(*t, h.phase);
+    t->fw = upload_vec(*t, h.fw);
+    t->gloss = upload_vec(*t, h.gloss);
+    t->wbp = upload_vec(*t, wbp);
+  }
+  t->bp_b = (int*)upload_vec(*t, h.bp_b);
+  t->bp_bb = (int*)upload_vec(*t, h.bp_bb);
+  auto& slot = ctx->tables[key];
+  slot = std::move(t);
+  return *slot;
+}
+
+}  // namespace blr
+
+// ----------------------------------------------------------------- C ABI --
+template <class F>
+static blr_status guarded(blr_ctx ctx, F&& f) {
+  if (!ctx) return BLR_ERR_ARG;
+  ctx->err.clear();
+  try {
+    BLR_HIP(hipSetDevice(ctx->device));
+    f();
+    return BLR_OK;
+  } catch (const blr::Error& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return BLR_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return BLR_ERR_HIP;
+  }
+}
+
+extern "C" {
+
+blr_status blr_create(int device, void* hip_stream, blr_ctx* out) {
+  if (!out) return BLR_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return BLR_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return BLR_ERR_HIP;
+  blr_ctx c = new (std::nothrow) blr_ctx_t();
+  if (!c) return BLR_ERR_NOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return BLR_ERR_HIP;
+    }
+  *out = c;
+  return BLR_OK;
+}
+
+blr_status blr_destroy(blr_ctx ctx) {
+  if (!ctx) return BLR_ERR_ARG;
+  (void)hipSetDevice(ctx->device);
+  ctx->release_all();
+  delete ctx;
+  return BLR_OK;
+}
+
+const char* blr_last_error(blr_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+blr_status blr_workspace_bytes(blr_ctx ctx, const blr_vgrid* vg, int32_t r_max,
+                               blr_precision prec, size_t* out) {
+  return guarded(ctx, [&] {
+    blr::require(vg && out, "null pointer argument");
+    blr::require(r_max >= 1 && r_max <= 64, "r_max must be in [1, 64]");
+    blr::require(prec == BLR_FP32 || prec == BLR_FP64, "bad precision");
+    *out = blr::collision_workspace_bytes(*vg, r_max, prec);
+  });
+}
+
+blr_status blr_collision_pairs(blr_ctx ctx, const blr_vgrid* vg, blr_precision prec,
+                               const void* V, int32_t r, const int32_t* pairs,
+                               int32_t npairs, void* Q_out) {
+  return guarded(ctx, [&] {
+    blr::require(vg != nullptr, "null vgrid");
+    blr::require(prec == BLR_FP32 || prec == BLR_FP64, "bad precision");
+    blr::collision_pairs(ctx, *vg, prec, V, r, pairs, npairs, Q_out);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,704 @@
+// Pair collisions Q_s(V_i, V_j) on the velocity grid: the generic pipeline.
+//
+// Steps (for a basis set {V_i} and a list of pairs; T = float or double):
+//   1. V^_i = DFT(V_i)/n with the Nyquist modes dropped; from it the projected
+//      basis V_i~ = IDFT(V^_i) and the loss field Lam_i = IDFT(G- V^_i).
+//   2. shifts S_i(a,b)(v) = V_i~(v - rho_a sigma_b / 2) for every radial node a
+//      and sphere node b: for an antipodal pair (b, bbar) one complex inverse
+//      transform of V^_i (cos x - sin x), x = theta_a sigma_b . k, yields
+//      W with S(b) = Re W - Im W and S(bbar) = Re W + Im W.
+//   3. per radial node a and pair (i,j):
+//        P_ij,a = sum_b w_b S_i(a,b) S_j(a,bbar)           (pointwise, sigma sum)
+//   4. G_ij += w_a rho_a^(d-1) B(rho_a) A_d(theta_a |k|) DFT(P_ij,a)/n
+//   5. Q_ij = IDFT(G_ij) - (V_j~ Lam_i + V_i~ Lam_j)/2
+//   6. optional FP64 projection removing the d+2 discrete moments.
+// Every transform here is done as one kernel per axis ("line pass"): each
+// thread holds one line of N complex values in registers (fft.hpp).  This path
+// serves every size and both precisions; the fused FP32 kernels in
+// collision_fast.hip replace steps 2-5 for the 3D grids when they apply.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "collision_common.hpp"
+
+namespace blr {
+
+// ------------------------------------------------------------------ loaders
+template <typename T>
+struct LdComplex {
+  const typename Vec2<T>::t* p;
+  int n;
+  template <int N>
+  __device__ void load(long f, int base, int stride, T (&re)[N], T (&im)[N]) const {
+    const auto* q = p + f * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const auto v = q[(long)j * stride];
+      re[j] = v.x;
+      im[j] = v.y;
+    }
+  }
+};
+
+template <typename T>
+struct LdReal {
+  const T* p;
+  int n;
+  template <int N>
+  __device__ void load(long f, int base, int stride, T (&re)[N], T (&im)[N]) const {
+    const T* q = p + f * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      re[j] = q[(long)j * stride];
+      im[j] = T(0);
+    }
+  }
+};
+
+// field f < rb: V^_f; field f >= rb: G- V^_(f-rb).  Both inverse transforms
+// are real; they are kept in separate fields because |G-| can exceed 1e4 and
+// packing the two into one complex transform would leak the rounding of the
+// loss field into the projected basis.
+template <typename T>
+struct LdBasisMode {
+  const typename Vec2<T>::t* vh;
+  const T* gl;
+  int n, rb;
+  template <int N>
+  __device__ void load(long f, int base, int stride, T (&re)[N], T (&im)[N]) const {
+    const bool loss = f >= rb;
+    const auto* q = vh + (loss ? f - rb : f) * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const auto v = q[(long)j * stride];
+      const T g = loss ? gl[base + j * stride] : T(1);
+      re[j] = v.x * g;
+      im[j] = v.y * g;
+    }
+  }
+};
+
+// V^_ib (cos x - sin x) for field f = (ib, a, p) of the shift batch
+template <typename T, int N, int D>
+struct LdShift {
+  const typename Vec2<T>::t* vh;
+  const typename Vec2<T>::t* phase;  // (mrho*nbp) x D x N
+  int n, mrho, nbp;
+  long f0;
+  template <int NN>
+  __device__ void load(long fl, int base, int stride, T (&re)[NN], T (&im)[NN]) const {
+    const long f = f0 + fl;
+    const int p = (int)(f % nbp);
+    const int a = (int)((f / nbp) % mrho);
+    const long ib = f / ((long)nbp * mrho);
+    const auto* ph = phase + ((long)a * nbp + p) * D * N;
+    const auto* q = vh + ib * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int e = base + j * stride;
+      typename Vec2<T>::t c;
+      if constexpr (D == 3) {
+        const int k0 = e / (N * N), k1 = (e / N) % N, k2 = e % N;
+        c = cmul(cmul(ph[k0], ph[N + k1]), ph[2 * N + k2]);
+      } else {
+        const int k0 = e / N, k1 = e % N;
+        c = cmul(ph[k0], ph[N + k1]);
+      }
+      const T fac = c.x + c.y;
+      const auto v = q[(long)j * stride];
+      re[j] = v.x * fac;
+      im[j] = v.y * fac;
+    }
+  }
+};
+
+// one pair-product field (real) per complex transform: pairs are not packed
+// two to a transform because their magnitudes can differ by orders of
+// magnitude and the smaller one would inherit the larger one's rounding.
+template <typename T>
+struct LdPair1 {
+  const T* pa;  // P x n
+  int n;
+  template <int N>
+  __device__ void load(long p, int base, int stride, T (&re)[N], T (&im)[N]) const {
+    const T* q = pa + p * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      re[j] = q[(long)j * stride];
+      im[j] = T(0);
+    }
+  }
+};
+
+// ------------------------------------------------------------------- storers
+template <typename T>
+struct StComplex {
+  typename Vec2<T>::t* p;
+  int n;
+  template <int N>
+  __device__ void store(long f, int base, int stride, const T (&re)[N], const T (&im)[N]) const {
+    auto* q = p + f * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) q[(long)j * stride] = make2<T>(re[j], im[j]);
+  }
+};
+
+// basis spectrum: scale by 1/n and drop every mode with a Nyquist component
+template <typename T, int N, int D>
+struct StBasisSpec {
+  typename Vec2<T>::t* p;
+  int n;
+  T scale;
+  template <int NN>
+  __device__ void store(long f, int base, int stride, const T (&re)[NN], const T (&im)[NN]) const {
+    auto* q = p + f * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int e = base + j * stride;
+      bool nyq;
+      if constexpr (D == 3)
+        nyq = (e / (N * N) == N / 2) || ((e / N) % N == N / 2) || (e % N == N / 2);
+      else
+        nyq = (e / N == N / 2) || (e % N == N / 2);
+      q[(long)j * stride] = nyq ? make2<T>(T(0), T(0)) : make2<T>(re[j] * scale, im[j] * scale);
+    }
+  }
+};
+
+template <typename T>
+struct StRe {
+  T* o;
+  int n;
+  template <int N>
+  __device__ void store(long f, int base, int stride, const T (&re)[N], const T (&im)[N]) const {
+#pragma unroll
+    for (int j = 0; j < N; ++j) o[f * n + base + (long)j * stride] = re[j];
+  }
+};
+
+template <typename T>
+struct StSplit {
+  T* o1;
+  T* o2;
+  int n;
+  template <int N>
+  __device__ void store(long f, int base, int stride, const T (&re)[N], const T (&im)[N]) const {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      o1[f * n + base + (long)j * stride] = re[j];
+      o2[f * n + base + (long)j * stride] = im[j];
+    }
+  }
+};
+
+// shift batch: field (ib, a, p) -> S(ib, a, b) = re - im, S(ib, a, bbar) = re + im
+template <typename T>
+struct StShiftSplit {
+  T* sh;  // (rb*mrho*msig) x n
+  const int* bp_b;
+  const int* bp_bb;
+  int n, mrho, nbp, msig;
+  long f0;
+  template <int N>
+  __device__ void store(long fl, int base, int stride, const T (&re)[N], const T (&im)[N]) const {
+    const long f = f0 + fl;
+    const int p = (int)(f % nbp);
+    const long iba = f / nbp;  // ib*mrho + a
+    T* s1 = sh + (iba * msig + bp_b[p]) * n + base;
+    T* s2 = sh + (iba * msig + bp_bb[p]) * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      s1[(long)j * stride] = re[j] - im[j];
+      s2[(long)j * stride] = re[j] + im[j];
+    }
+  }
+};
+
+// accumulate w(a, |k|^2) * value into the couple spectrum
+template <typename T, int N, int D>
+struct StAccumF {
+  typename Vec2<T>::t* G;
+  const T* fw;  // nkk weights of this radial node
+  int n;
+  template <int NN>
+  __device__ void store(long c, int base, int stride, const T (&re)[NN], const T (&im)[NN]) const {
+    auto* g = G + c * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int e = base + j * stride;
+      int kk;
+      if constexpr (D == 3) {
+        const int k0 = ctr<N>(e / (N * N)), k1 = ctr<N>((e / N) % N), k2 = ctr<N>(e % N);
+        kk = k0 * k0 + k1 * k1 + k2 * k2;
+      } else {
+        const int k0 = ctr<N>(e / N), k1 = ctr<N>(e % N);
+        kk = k0 * k0 + k1 * k1;
+      }
+      const T w = fw[kk];
+      auto v = g[(long)j * stride];
+      v.x += w * re[j];
+      v.y += w * im[j];
+      g[(long)j * stride] = v;
+    }
+  }
+};
+
+// Q = gain - loss for pair p
+template <typename T>
+struct StFinal {
+  T* Q;
+  const T* vp;
+  const T* lam;
+  const int* pi;  // local basis index per pair
+  const int* pj;
+  const int* prow;  // output row per pair
+  int n;
+  template <int N>
+  __device__ void store(long p, int base, int stride, const T (&re)[N], const T (&im)[N]) const {
+    const long i = pi[p], jj = pj[p];
+    T* q = Q + (long)prow[p] * n + base;
+    const T* vi = vp + i * n + base;
+    const T* vj = vp + jj * n + base;
+    const T* li = lam + i * n + base;
+    const T* lj = lam + jj * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const long o = (long)j * stride;
+      q[o] = re[j] - T(0.5) * (vj[o] * li[o] + vi[o] * lj[o]);
+    }
+  }
+};
+
+// ------------------------------------------------------------ line pass
+template <typename T, int N, int D, int DIR, class Ld, class St>
+__global__ __launch_bounds__(128) void k_line_pass(Ld ld, St st, int axis, long nlines) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= nlines) return;
+  constexpr int lines = (D == 2 ? N : N * N);
+  const long f = t / lines;
+  const int l = (int)(t % lines);
+  const int stride = axis == D - 1 ? 1 : (axis == D - 2 ? N : N * N);
+  const int base = (l / stride) * stride * N + (l % stride);
+  T re[N], im[N];
+  ld.template load<N>(f, base, stride, re, im);
+  fft::dft<T, N, DIR>(re, im);
+  st.template store<N>(f, base, stride, re, im);
+}
+
+template <typename T, int N, int D, int DIR, class Ld, class St>
+static void line_pass(hipStream_t s, const Ld& ld, const St& st, int axis, long nfields) {
+  constexpr int lines = (D == 2 ? N : N * N);
+  const long nl = nfields * lines;
+  const int bs = 128;
+  const long nb = (nl + bs - 1) / bs;
+  hipLaunchKernelGGL((k_line_pass<T, N, D, DIR, Ld, St>), dim3((unsigned)nb), dim3(bs), 0, s, ld,
+                     st, axis, nl);
+  BLR_CHECK_LAUNCH();
+}
+
+// full D-dimensional transform: first axis (D-1) uses ld, last (0) uses st
+template <typename T, int N, int D, int DIR, class Ld, class St>
+static void transform(hipStream_t s, const Ld& ld, const St& st, typename Vec2<T>::t* tmp,
+                      long nfields) {
+  constexpr int n = (D == 2 ? N * N : N * N * N);
+  StComplex<T> stc{tmp, n};
+  LdComplex<T> ldc{tmp, n};
+  line_pass<T, N, D, DIR>(s, ld, stc, D - 1, nfields);
+  if constexpr (D == 3) line_pass<T, N, D, DIR>(s, ldc, stc, 1, nfields);
+  line_pass<T, N, D, DIR>(s, ldc, st, 0, nfields);
+}
+
+// ------------------------------------------------------------- sigma reduce
+// One thread per grid point; a tile of basis functions (ni on the left, nj on
+// the right, or one set of ni on both sides for a diagonal tile) whose pair
+// products are accumulated in registers over the antipodal sphere pairs:
+//   P_uv += w_b (S_u(b) S_v(bbar) + S_u(bbar) S_v(b)).
+template <typename T, int G, bool DIAG>
+__global__ __launch_bounds__(256) void k_sigma_reduce(const T* __restrict__ sh, T* __restrict__ pa,
+                                                      ReduceTile tile, const T* __restrict__ wbp,
+                                                      const int* __restrict__ bp_b,
+                                                      const int* __restrict__ bp_bb, int n,
+                                                      int mrho, int msig, int nbp, int a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  constexpr int NP = DIAG ? G * (G + 1) / 2 : G * G;
+  T acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = T(0);
+  for (int bp = 0; bp < nbp; ++bp) {
+    const int b = bp_b[bp], bb = bp_bb[bp];
+    const T w = wbp[bp];
+    T xi[G], yi[G], xj[G], yj[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      T x = T(0), y = T(0);
+      if (u < tile.ni) {
+        const long fi = ((long)tile.bi[u] * mrho + a) * msig;
+        x = sh[(fi + b) * n + q];
+        y = sh[(fi + bb) * n + q];
+      }
+      xi[u] = w * x;
+      yi[u] = w * y;
+      if constexpr (DIAG) {
+        xj[u] = x;
+        yj[u] = y;
+      } else {
+        x = y = T(0);
+        if (u < tile.nj) {
+          const long fj = ((long)tile.bj[u] * mrho + a) * msig;
+          x = sh[(fj + b) * n + q];
+          y = sh[(fj + bb) * n + q];
+        }
+        xj[u] = x;
+        yj[u] = y;
+      }
+    }
+    int p = 0;
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+#pragma unroll
+      for (int v = DIAG ? u : 0; v < G; ++v) {
+        acc[p] += xi[u] * yj[v] + yi[u] * xj[v];
+        ++p;
+      }
+    }
+  }
+  int p = 0;
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+#pragma unroll
+    for (int v = DIAG ? u : 0; v < G; ++v) {
+      const int row = tile.out[u * G + v];
+      if (row >= 0) pa[(long)row * n + q] = acc[p];
+      ++p;
+    }
+  }
+}
+
+// ------------------------------------------------------------ utilities
+template <typename T>
+__global__ void k_fill(T* p, long count, T v) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+template <typename T>
+void fill(hipStream_t s, T* p, long count, T v) {
+  if (count <= 0) return;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((count + bs - 1) / bs)), dim3(bs), 0, s, p, count, v);
+  BLR_CHECK_LAUNCH();
+}
+template void fill<float>(hipStream_t, float*, long, float);
+template void fill<double>(hipStream_t, double*, long, double);
+
+// FP64 least-squares moment projection of each row of Q (one block per row):
+// m = C q, lambda = (C C^T)^-1 m, q <- q - C^T lambda, with C the rows
+// dv^d {1, v_1..v_d, |v|^2}.  Deterministic block reduction.
+template <typename T>
+__global__ __launch_bounds__(256) void k_conserve(T* Q, int n, MomentArgs ma) {
+  T* q = Q + (long)blockIdx.x * n;
+  const int d = ma.d, m = d + 2, N = ma.N;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    double v[3] = {0, 0, 0};
+    int rem = e;
+    for (int ax = d - 1; ax >= 0; --ax) {
+      v[ax] = -ma.L + (rem % N) * ma.dv;
+      rem /= N;
+    }
+    const double val = (double)q[e] * ma.w;
+    acc[0] += val;
+    double v2 = 0;
+    for (int ax = 0; ax < d; ++ax) {
+      acc[1 + ax] += val * v[ax];
+      v2 += v[ax] * v[ax];
+    }
+    acc[d + 1] += val * v2;
+  }
+  __shared__ double red[5][256];
+  for (int i = 0; i < 5; ++i) red[i][threadIdx.x] = acc[i];
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + st];
+    __syncthreads();
+  }
+  double lam[5] = {0, 0, 0, 0, 0};
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) lam[i] += ma.minv[i * m + j] * red[j][0];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    double v[3] = {0, 0, 0};
+    int rem = e;
+    for (int ax = d - 1; ax >= 0; --ax) {
+      v[ax] = -ma.L + (rem % N) * ma.dv;
+      rem /= N;
+    }
+    double c = lam[0];
+    double v2 = 0;
+    for (int ax = 0; ax < d; ++ax) {
+      c += lam[1 + ax] * v[ax];
+      v2 += v[ax] * v[ax];
+    }
+    c += lam[d + 1] * v2;
+    q[e] = (T)((double)q[e] - ma.w * c);
+  }
+}
+
+template <typename T>
+void conserve_rows(hipStream_t s, const HostTables& h, T* Q, int rows) {
+  if (rows <= 0) return;
+  MomentArgs ma{};
+  ma.L = h.L;
+  ma.dv = h.dv;
+  ma.w = std::pow(h.dv, h.d);
+  for (size_t i = 0; i < h.minv.size() && i < 25; ++i) ma.minv[i] = h.minv[i];
+  ma.N = h.N;
+  ma.d = h.d;
+  hipLaunchKernelGGL(k_conserve<T>, dim3(rows), dim3(256), 0, s, Q, h.n, ma);
+  BLR_CHECK_LAUNCH();
+}
+template void conserve_rows<float>(hipStream_t, const HostTables&, float*, int);
+template void conserve_rows<double>(hipStream_t, const HostTables&, double*, int);
+
+// ------------------------------------------------------------ planning
+// Tiles of the pair products: compact basis indices grouped by G; one tile per
+// (group, group) block that holds at least one requested pair.
+std::vector<ReduceTile> plan_tiles(int rb, const std::vector<int>& li, const std::vector<int>& lj,
+                                   int G, bool& diag_only) {
+  std::vector<ReduceTile> tiles;
+  const int ng = (rb + G - 1) / G;
+  diag_only = (ng == 1);
+  for (int g1 = 0; g1 < ng; ++g1)
+    for (int g2 = g1; g2 < ng; ++g2) {
+      ReduceTile t;
+      std::memset(&t, 0, sizeof(t));
+      for (int k = 0; k < 256; ++k) t.out[k] = -1;
+      t.ni = std::min(G, rb - g1 * G);
+      t.nj = std::min(G, rb - g2 * G);
+      for (int u = 0; u < t.ni; ++u) t.bi[u] = g1 * G + u;
+      for (int v = 0; v < t.nj; ++v) t.bj[v] = g2 * G + v;
+      bool any = false;
+      for (size_t p = 0; p < li.size(); ++p) {
+        int i = std::min(li[p], lj[p]), j = std::max(li[p], lj[p]);
+        if (i / G == g1 && j / G == g2) {
+          t.out[(i - g1 * G) * G + (j - g2 * G)] = (int)p;
+          any = true;
+        }
+      }
+      if (any) tiles.push_back(t);
+    }
+  return tiles;
+}
+
+struct PairPlan {
+  std::vector<int> bidx;     // compact basis -> row of V
+  std::vector<int> li, lj;   // per pair, compact indices (li <= lj)
+};
+
+static PairPlan make_plan(int r, const int32_t* pairs, int npairs) {
+  PairPlan pl;
+  std::vector<int> map(r, -1);
+  for (int p = 0; p < npairs; ++p)
+    for (int h = 0; h < 2; ++h) {
+      const int i = pairs[2 * p + h];
+      require(i >= 0 && i < r, "pair index out of range [0, r)");
+      map[i] = 1;
+    }
+  for (int i = 0; i < r; ++i)
+    if (map[i] > 0) {
+      map[i] = (int)pl.bidx.size();
+      pl.bidx.push_back(i);
+    }
+  for (int p = 0; p < npairs; ++p) {
+    int a = map[pairs[2 * p]], b = map[pairs[2 * p + 1]];
+    pl.li.push_back(std::min(a, b));
+    pl.lj.push_back(std::max(a, b));
+  }
+  return pl;
+}
+
+// ------------------------------------------------------------ generic run
+template <typename T, int N, int D>
+struct Generic {
+  static constexpr int n = (D == 2 ? N * N : N * N * N);
+  using T2 = typename Vec2<T>::t;
+
+  static size_t workspace(const HostTables& h, int rb, int P) {
+    const long nc = P;
+    const long shift_fields = (long)rb * h.mrho * h.nbp;
+    const long batch = std::min<long>(shift_fields, 512);
+    size_t b = 0;
+    b += (size_t)rb * n * sizeof(T);                       // Vc
+    b += (size_t)rb * n * sizeof(T2);                      // Vh
+    b += (size_t)2 * rb * n * sizeof(T);                   // Vp, Lam
+    b += (size_t)rb * h.mrho * h.msig * n * sizeof(T);     // shifts
+    b += (size_t)std::max<long>(batch, std::max<long>(nc, 2 * rb)) * n * sizeof(T2);  // tmp
+    b += (size_t)P * n * sizeof(T);                        // Pa
+    b += (size_t)nc * n * sizeof(T2);                      // G
+    return b;
+  }
+
+  // Q rows prow[p] receive Q_s(bidx[li[p]], bidx[lj[p]]) of the compact basis Vc.
+  static void run(blr_ctx ctx, const DevTables& tb, const T* Vsrc, const PairPlan& pl,
+                  const std::vector<int>& prow, T* Q) {
+    const HostTables& h = tb.h;
+    hipStream_t s = ctx->stream;
+    const int rb = (int)pl.bidx.size();
+    const int P = (int)pl.li.size();
+    const long nc = P;
+    const long shift_fields = (long)rb * h.mrho * h.nbp;
+    const long batch = std::min<long>(shift_fields, 512);
+    const std::string tag = std::string("gen") + (sizeof(T) == 4 ? "f" : "d");
+    T* Vc = (T*)ctx->buf(tag + ".Vc", (size_t)rb * n * sizeof(T));
+    T2* Vh = (T2*)ctx->buf(tag + ".Vh", (size_t)rb * n * sizeof(T2));
+    T* Vp = (T*)ctx->buf(tag + ".VpLam", (size_t)2 * rb * n * sizeof(T));
+    T* Lam = Vp + (size_t)rb * n;
+    T* Sh = (T*)ctx->buf(tag + ".Sh", (size_t)rb * h.mrho * h.msig * n * sizeof(T));
+    T2* tmp = (T2*)ctx->buf(tag + ".tmp",
+                            (size_t)std::max<long>(batch, std::max<long>(nc, 2 * rb)) * n * sizeof(T2));
+    T* Pa = (T*)ctx->buf(tag + ".Pa", (size_t)P * n * sizeof(T));
+    T2* G = (T2*)ctx->buf(tag + ".G", (size_t)nc * n * sizeof(T2));
+    // per-call index arrays (pi, pj, prow) through the pinned stage
+    std::vector<int> idx(3 * P);
+    for (int p = 0; p < P; ++p) {
+      idx[p] = pl.li[p];
+      idx[P + p] = pl.lj[p];
+      idx[2 * P + p] = prow[p];
+    }
+    int* didx = (int*)ctx->upload(tag + ".idx", idx.data(), idx.size() * sizeof(int));
+    for (int ib = 0; ib < rb; ++ib)
+      BLR_HIP(hipMemcpyAsync(Vc + (size_t)ib * n, Vsrc + (size_t)pl.bidx[ib] * n, n * sizeof(T),
+                             hipMemcpyDeviceToDevice, s));
+    const T2* phase = (const T2*)tb.phase;
+    const T* fw = (const T*)tb.fw;
+    const T* gl = (const T*)tb.gloss;
+    // 1. spectra, projected basis and loss fields
+    transform<T, N, D, -1>(s, LdReal<T>{Vc, n}, StBasisSpec<T, N, D>{Vh, n, T(1) / T(n)}, tmp, rb);
+    transform<T, N, D, +1>(s, LdBasisMode<T>{Vh, gl, n, rb}, StRe<T>{Vp, n}, tmp, 2 * rb);
+    // 2. shifts
+    for (long f0 = 0; f0 < shift_fields; f0 += batch) {
+      const long nb = std::min(batch, shift_fields - f0);
+      transform<T, N, D, +1>(s, LdShift<T, N, D>{Vh, phase, n, h.mrho, h.nbp, f0},
+                             StShiftSplit<T>{Sh, tb.bp_b, tb.bp_bb, n, h.mrho, h.nbp, h.msig, f0},
+                             tmp, nb);
+    }
+    // 3-4. sigma sums, transforms and radial weights, one radial node at a time
+    fill<T>(s, (T*)G, 2 * nc * n, T(0));
+    bool diag_only = false;
+    const int Gt = sizeof(T) == 4 ? 12 : 8;
+    auto tiles = plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
+    for (int a = 0; a < h.mrho; ++a) {
+      for (const auto& t : tiles) {
+        const bool diag = t.bi[0] == t.bj[0];
+        const int bs = 256;
+        const dim3 grid((n + bs - 1) / bs);
+        if (sizeof(T) == 4) {
+          if (diag)
+            hipLaunchKernelGGL((k_sigma_reduce<T, 12, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
+                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a);
+          else
+            hipLaunchKernelGGL((k_sigma_reduce<T, 12, false>), grid, dim3(bs), 0, s, Sh, Pa, t,
+                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a);
+        } else {
+          if (diag)
+            hipLaunchKernelGGL((k_sigma_reduce<T, 8, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
+                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a);
+          else
+            hipLaunchKernelGGL((k_sigma_reduce<T, 8, false>), grid, dim3(bs), 0, s, Sh, Pa, t,
+                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a);
+        }
+        BLR_CHECK_LAUNCH();
+      }
+      transform<T, N, D, -1>(s, LdPair1<T>{Pa, n}, StAccumF<T, N, D>{G, fw + (size_t)a * h.nkk, n},
+                             tmp, nc);
+    }
+    // 5. back to velocity space, minus the loss
+    transform<T, N, D, +1>(s, LdComplex<T>{G, n},
+                           StFinal<T>{Q, Vp, Lam, didx, didx + P, didx + 2 * P, n}, tmp, nc);
+  }
+};
+
+// dispatch over (T, N, D)
+template <typename T, class F>
+static void dispatch_size(int d, int N, F&& f) {
+  if (d == 3) {
+    switch (N) {
+      case 8: f(std::integral_constant<int, 8>{}, std::integral_constant<int, 3>{}); return;
+      case 16: f(std::integral_constant<int, 16>{}, std::integral_constant<int, 3>{}); return;
+      case 24: f(std::integral_constant<int, 24>{}, std::integral_constant<int, 3>{}); return;
+      case 32: f(std::integral_constant<int, 32>{}, std::integral_constant<int, 3>{}); return;
+    }
+  } else {
+    switch (N) {
+      case 16: f(std::integral_constant<int, 16>{}, std::integral_constant<int, 2>{}); return;
+      case 32: f(std::integral_constant<int, 32>{}, std::integral_constant<int, 2>{}); return;
+      case 48: f(std::integral_constant<int, 48>{}, std::integral_constant<int, 2>{}); return;
+      case 64: f(std::integral_constant<int, 64>{}, std::integral_constant<int, 2>{}); return;
+    }
+  }
+  throw Error(BLR_ERR_UNSUPPORTED, "velocity grid size not built");
+}
+
+bool fast_collision_f32(blr_ctx ctx, const DevTables& tb, const float* V, const PairPlan& pl,
+                        const std::vector<int>& prow, float* Q);
+
+template <typename T>
+static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const int32_t* pairs,
+                      int npairs, T* Q, uint32_t flags) {
+  const HostTables& h = tb.h;
+  if (npairs == 0) return;
+  if (flags & BLR_PLAIN_SCHEDULE) {
+    // the baseline schedule: every pair on its own, shifts recomputed per pair
+    for (int p = 0; p < npairs; ++p) {
+      PairPlan pl = make_plan(r, pairs + 2 * p, 1);
+      std::vector<int> prow{p};
+      dispatch_size<T>(h.d, h.N, [&](auto Nc, auto Dc) {
+        Generic<T, decltype(Nc)::value, decltype(Dc)::value>::run(ctx, tb, V, pl, prow, Q);
+      });
+    }
+  } else {
+    PairPlan pl = make_plan(r, pairs, npairs);
+    std::vector<int> prow(npairs);
+    for (int p = 0; p < npairs; ++p) prow[p] = p;
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (!(flags & BLR_GENERIC_FFT)) done = fast_collision_f32(ctx, tb, V, pl, prow, Q);
+    }
+    if (!done)
+      dispatch_size<T>(h.d, h.N, [&](auto Nc, auto Dc) {
+        Generic<T, decltype(Nc)::value, decltype(Dc)::value>::run(ctx, tb, V, pl, prow, Q);
+      });
+  }
+  if (!(flags & BLR_NO_CONSERVE)) conserve_rows<T>(ctx->stream, h, Q, npairs);
+}
+
+void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
+                     const int32_t* pairs, int npairs, void* Q) {
+  require(r >= 1 && r <= 64, "r must be in [1, 64]");
+  require(npairs >= 0 && npairs <= 4096, "npairs must be in [0, 4096]");
+  require(npairs == 0 || (pairs && V && Q), "null pointer argument");
+  const DevTables& tb = get_tables(ctx, vg, prec);
+  if (prec == BLR_FP32)
+    run_pairs<float>(ctx, tb, (const float*)V, r, pairs, npairs, (float*)Q, vg.flags);
+  else
+    run_pairs<double>(ctx, tb, (const double*)V, r, pairs, npairs, (double*)Q, vg.flags);
+}
+
+size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec) {
+  HostTables h = build_tables(vg);
+  const int P = r * (r + 1) / 2;
+  size_t out = 0;
+  auto f = [&](auto Tc) {
+    using T = decltype(Tc);
+    dispatch_size<T>(h.d, h.N, [&](auto Nc, auto Dc) {
+      out = Generic<T, decltype(Nc)::value, decltype(Dc)::value>::workspace(h, r, P);
+    });
+  };
+  if (prec == BLR_FP32) f(float{});
+  else f(double{});
+  return out;
+}
+
+}  // namespace blr

@@ -1,0 +1,58 @@
+// Shared device helpers of the collision kernels.
+#pragma once
+
+#include "fft.hpp"
+#include "internal.hpp"
+
+namespace blr {
+
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+  using t = float2;
+};
+template <>
+struct Vec2<double> {
+  using t = double2;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ typename Vec2<T>::t make2(T x, T y) {
+  typename Vec2<T>::t v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
+
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// centred integer mode of a DFT index
+template <int N>
+__host__ __device__ __forceinline__ int ctr(int k) {
+  return k >= N / 2 ? k - N : k;
+}
+
+// A tile of the pair products computed by one sigma-reduce launch: basis
+// indices (compact numbering) on the left and right, and the output row of
+// each (u, v) slot (-1 = not requested).
+struct ReduceTile {
+  int ni, nj;
+  int bi[16];
+  int bj[16];
+  int out[256];
+};
+
+// moment projection parameters
+struct MomentArgs {
+  double L, dv, w;      // box half width, spacing, dv^d
+  double minv[25];      // (C C^T)^-1, (d+2)^2 row-major
+  int N, d;
+};
+
+}  // namespace blr

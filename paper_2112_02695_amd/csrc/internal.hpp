@@ -1,0 +1,114 @@
+// Internal declarations of the blr library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/blr.h"
+
+namespace blr {
+
+// Error carrying a blr_status across the C++ layers; caught at the C ABI.
+struct Error : std::runtime_error {
+  blr_status code;
+  Error(blr_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define BLR_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      if (e_ == hipErrorOutOfMemory)                                                    \
+        throw ::blr::Error(BLR_ERR_NOMEM, std::string(#call) + ": out of device memory"); \
+      throw ::blr::Error(BLR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    }                                                                                   \
+  } while (0)
+
+#define BLR_CHECK_LAUNCH() BLR_HIP(hipGetLastError())
+
+inline void require(bool ok, const std::string& msg, blr_status code = BLR_ERR_ARG) {
+  if (!ok) throw Error(code, msg);
+}
+
+// ----------------------------------------------------------------- tables --
+// Host-side (FP64) description of one velocity discretisation.
+struct HostTables {
+  int d = 0, N = 0, n = 0, mrho = 0, msig = 0, nbp = 0, nkk = 0;
+  double L = 0, R = 0, C = 0, gamma = 0, dv = 0;
+  std::vector<double> rho, wrho, cw;          // radial nodes, weights, w*rho^(d-1)
+  std::vector<double> sig, wsig;              // msig x 3, msig
+  std::vector<int> bp_b, bp_bb;               // antipodal pairs (b, bbar), b < bbar
+  std::vector<double> phase;                  // (mrho*nbp) x d x N x 2 : exp(-i th sigma_b,ax k)
+  std::vector<double> fw;                     // mrho x nkk : cw B A_d(th |k|) / n
+  std::vector<double> gloss;                  // n     : G-(k) (DFT order)
+  std::vector<double> minv;                   // (d+2)^2 : (C C^T)^-1, C rows dv^d{1,v,|v|^2}
+};
+
+HostTables build_tables(const blr_vgrid& vg);
+double bessel_j0(double z);
+void gauss_legendre(int m, double R, std::vector<double>& x, std::vector<double>& w);
+
+// Device copies of the tables in one precision.
+struct DevTables {
+  HostTables h;
+  int prec = 0;
+  void* phase = nullptr;   // T2 : (mrho*nbp) x d x N
+  void* fw = nullptr;      // T  : mrho x nkk
+  void* gloss = nullptr;   // T  : n
+  void* wbp = nullptr;     // T  : nbp sphere weights of the antipodal pairs
+  int* bp_b = nullptr;     // nbp
+  int* bp_bb = nullptr;    // nbp
+  std::vector<void*> owned;
+  ~DevTables();
+};
+
+// ---------------------------------------------------------------- context --
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace blr
+
+struct blr_ctx_t {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<std::tuple<int, int, double, double, double, double, int, int, int>,
+           std::unique_ptr<blr::DevTables>>
+      tables;
+  std::map<std::string, blr::Buffer> bufs;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint64_t calls = 0;
+
+  // pinned staging for small per-call host->device uploads
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  size_t stage_used = 0;
+  hipEvent_t stage_done = nullptr;
+
+  void* buf(const std::string& name, size_t bytes);  // grow-only named workspace
+  // copy a small host array to a named device buffer, asynchronously
+  void* upload(const std::string& name, const void* host, size_t bytes);
+  void release_all();
+};
+
+namespace blr {
+
+const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec);
+void validate_vgrid(const blr_vgrid& vg);
+
+// collision pipeline (collision.hip)
+void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
+                     const int32_t* pairs_dev, int npairs, void* Q);
+size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec);
+
+}  // namespace blr

@@ -175,7 +175,7 @@ def smooth_basis(r: int, spec: VGridSpec, seed: int = 7, orthonormal: bool = Tru
         dvd = (2.0 * spec.L / spec.n) ** d
         q, _ = np.linalg.qr(W.T)
         W = q.T / math.sqrt(dvd)
-    return W
+    return np.ascontiguousarray(W)
 
 
 def shock_initial(mach: float, spec: VGridSpec, nx: int, x_lo: float = -30.0,
@@ -240,7 +240,7 @@ def lowrank_state(f0: np.ndarray, r: int, dx: float, dvd: float):
         if U[j, i] < 0:
             U[:, i] *= -1.0
             Wt[i] *= -1.0
-    X = U / math.sqrt(dx)
-    V = Wt / math.sqrt(dvd)
+    X = np.ascontiguousarray(U / math.sqrt(dx))
+    V = np.ascontiguousarray(Wt / math.sqrt(dvd))
     S = np.diag(s)
     return X, S, V
