@@ -184,6 +184,23 @@ typedef struct {
 blr_status blr_steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state,
                             const blr_solve_params* p, blr_solve_info* info);
 
+/* ----------------------------------------------------------- timing -- */
+
+/* Per-kernel timing for measurement.  mode 1: from now on every kernel launch
+ * of the library is bracketed by HIP events on the context stream; mode 0:
+ * stop recording; mode 2: discard what was accumulated.  Not part of the
+ * method; adds two event records per launch while on. */
+blr_status blr_timing(blr_ctx ctx, int32_t mode);
+
+/* Accumulated time of the idx-th distinct kernel name seen since the last
+ * reset (synchronises on the recorded events).  name: caller buffer of
+ * name_len bytes (NUL-terminated, truncated); ms: total milliseconds;
+ * launches: number of launches; bytes: total algorithmic bytes of those
+ * launches (the compulsory reads and writes of each kernel's inputs and
+ * outputs, counted once).  BLR_ERR_ARG when idx is past the end. */
+blr_status blr_timing_read(blr_ctx ctx, int32_t idx, char* name, int32_t name_len,
+                           double* ms, int64_t* launches, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

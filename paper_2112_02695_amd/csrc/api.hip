@@ -52,9 +52,59 @@ void blr_ctx_t::release_all() {
   stage_done = nullptr;
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
+  timer.release();
 }
 
 namespace blr {
+
+hipEvent_t KernelTimer::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  BLR_HIP(hipEventCreate(&e));
+  return e;
+}
+void KernelTimer::begin(hipStream_t s, const std::string& name, double bytes) {
+  if (!on) return;
+  Rec r{name, take(), take(), bytes};
+  BLR_HIP(hipEventRecord(r.a, s));
+  pending.push_back(r);
+}
+void KernelTimer::end(hipStream_t s) {
+  if (!on || pending.empty()) return;
+  BLR_HIP(hipEventRecord(pending.back().b, s));
+}
+void KernelTimer::collect() {
+  for (auto& r : pending) {
+    BLR_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    BLR_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    auto it = acc.find(r.name);
+    if (it == acc.end()) {
+      order.push_back(r.name);
+      acc[r.name] = Acc{};
+      it = acc.find(r.name);
+    }
+    it->second.ms += ms;
+    it->second.bytes += r.bytes;
+    it->second.launches += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+}
+void KernelTimer::release() {
+  for (auto& r : pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  pending.clear();
+  for (auto e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+}
 
 DevTables::~DevTables() {
   for (void* p : owned)
@@ -176,6 +226,34 @@ blr_status blr_collision_pairs(blr_ctx ctx, const blr_vgrid* vg, blr_precision p
     blr::require(vg != nullptr, "null vgrid");
     blr::require(prec == BLR_FP32 || prec == BLR_FP64, "bad precision");
     blr::collision_pairs(ctx, *vg, prec, V, r, pairs, npairs, Q_out);
+  });
+}
+
+blr_status blr_timing(blr_ctx ctx, int32_t mode) {
+  return guarded(ctx, [&] {
+    blr::require(mode >= 0 && mode <= 2, "mode must be 0 (off), 1 (on) or 2 (reset)");
+    if (mode == 2) {
+      ctx->timer.collect();
+      ctx->timer.acc.clear();
+      ctx->timer.order.clear();
+      return;
+    }
+    ctx->timer.on = mode == 1;
+  });
+}
+
+blr_status blr_timing_read(blr_ctx ctx, int32_t idx, char* name, int32_t name_len, double* ms,
+                           int64_t* launches, double* bytes) {
+  return guarded(ctx, [&] {
+    blr::require(name && name_len > 0 && ms && launches && bytes, "null pointer argument");
+    ctx->timer.collect();
+    blr::require(idx >= 0 && idx < (int)ctx->timer.order.size(), "timer index out of range");
+    const std::string& nm = ctx->timer.order[idx];
+    const auto& v = ctx->timer.acc[nm];
+    std::snprintf(name, name_len, "%s", nm.c_str());
+    *ms = v.ms;
+    *launches = v.launches;
+    *bytes = v.bytes;
   });
 }
 

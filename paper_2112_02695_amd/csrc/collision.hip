@@ -27,6 +27,7 @@ namespace blr {
 // ------------------------------------------------------------------ loaders
 template <typename T>
 struct LdComplex {
+  static constexpr int bpe = 2;  // algorithmic bytes per element / sizeof(T)
   const typename Vec2<T>::t* p;
   int n;
   template <int N>
@@ -43,6 +44,7 @@ struct LdComplex {
 
 template <typename T>
 struct LdReal {
+  static constexpr int bpe = 1;  // algorithmic bytes per element / sizeof(T)
   const T* p;
   int n;
   template <int N>
@@ -62,6 +64,7 @@ struct LdReal {
 // loss field into the projected basis.
 template <typename T>
 struct LdBasisMode {
+  static constexpr int bpe = 2;  // algorithmic bytes per element / sizeof(T)
   const typename Vec2<T>::t* vh;
   const T* gl;
   int n, rb;
@@ -82,6 +85,7 @@ struct LdBasisMode {
 // V^_ib (cos x - sin x) for field f = (ib, a, p) of the shift batch
 template <typename T, int N, int D>
 struct LdShift {
+  static constexpr int bpe = 2;  // algorithmic bytes per element / sizeof(T)
   const typename Vec2<T>::t* vh;
   const typename Vec2<T>::t* phase;  // (mrho*nbp) x D x N
   int n, mrho, nbp;
@@ -118,6 +122,7 @@ struct LdShift {
 // magnitude and the smaller one would inherit the larger one's rounding.
 template <typename T>
 struct LdPair1 {
+  static constexpr int bpe = 1;  // algorithmic bytes per element / sizeof(T)
   const T* pa;  // P x n
   int n;
   template <int N>
@@ -134,6 +139,7 @@ struct LdPair1 {
 // ------------------------------------------------------------------- storers
 template <typename T>
 struct StComplex {
+  static constexpr int bpe = 2;  // algorithmic bytes per element / sizeof(T)
   typename Vec2<T>::t* p;
   int n;
   template <int N>
@@ -147,6 +153,7 @@ struct StComplex {
 // basis spectrum: scale by 1/n and drop every mode with a Nyquist component
 template <typename T, int N, int D>
 struct StBasisSpec {
+  static constexpr int bpe = 2;  // algorithmic bytes per element / sizeof(T)
   typename Vec2<T>::t* p;
   int n;
   T scale;
@@ -168,6 +175,7 @@ struct StBasisSpec {
 
 template <typename T>
 struct StRe {
+  static constexpr int bpe = 1;  // algorithmic bytes per element / sizeof(T)
   T* o;
   int n;
   template <int N>
@@ -179,6 +187,7 @@ struct StRe {
 
 template <typename T>
 struct StSplit {
+  static constexpr int bpe = 2;  // algorithmic bytes per element / sizeof(T)
   T* o1;
   T* o2;
   int n;
@@ -195,6 +204,7 @@ struct StSplit {
 // shift batch: field (ib, a, p) -> S(ib, a, b) = re - im, S(ib, a, bbar) = re + im
 template <typename T>
 struct StShiftSplit {
+  static constexpr int bpe = 2;  // algorithmic bytes per element / sizeof(T)
   T* sh;  // (rb*mrho*msig) x n
   const int* bp_b;
   const int* bp_bb;
@@ -218,6 +228,7 @@ struct StShiftSplit {
 // accumulate w(a, |k|^2) * value into the couple spectrum
 template <typename T, int N, int D>
 struct StAccumF {
+  static constexpr int bpe = 4;  // algorithmic bytes per element / sizeof(T)
   typename Vec2<T>::t* G;
   const T* fw;  // nkk weights of this radial node
   int n;
@@ -247,6 +258,7 @@ struct StAccumF {
 // Q = gain - loss for pair p
 template <typename T>
 struct StFinal {
+  static constexpr int bpe = 5;  // algorithmic bytes per element / sizeof(T)
   T* Q;
   const T* vp;
   const T* lam;
@@ -286,12 +298,36 @@ __global__ __launch_bounds__(128) void k_line_pass(Ld ld, St st, int axis, long 
   st.template store<N>(f, base, stride, re, im);
 }
 
+// the timer of the context issuing the current launches (set per call)
+static thread_local KernelTimer* g_timer = nullptr;
+static thread_local const char* g_stage = "";
+
+struct TimedScope {
+  hipStream_t s;
+  TimedScope(hipStream_t st, const std::string& name, double bytes) : s(st) {
+    if (g_timer && g_timer->on) g_timer->begin(s, name, bytes);
+  }
+  ~TimedScope() {
+    if (g_timer && g_timer->on) g_timer->end(s);
+  }
+};
+
+void timed_begin(const std::string& name, double bytes, hipStream_t s) {
+  if (g_timer && g_timer->on) g_timer->begin(s, name, bytes);
+}
+void timed_end(hipStream_t s) {
+  if (g_timer && g_timer->on) g_timer->end(s);
+}
+
 template <typename T, int N, int D, int DIR, class Ld, class St>
 static void line_pass(hipStream_t s, const Ld& ld, const St& st, int axis, long nfields) {
   constexpr int lines = (D == 2 ? N : N * N);
   const long nl = nfields * lines;
   const int bs = 128;
   const long nb = (nl + bs - 1) / bs;
+  constexpr int n = (D == 2 ? N * N : N * N * N);
+  TimedScope ts(s, std::string(g_stage) + ".axis" + std::to_string(axis),
+                (double)nfields * n * (Ld::bpe + St::bpe) * sizeof(T));
   hipLaunchKernelGGL((k_line_pass<T, N, D, DIR, Ld, St>), dim3((unsigned)nb), dim3(bs), 0, s, ld,
                      st, axis, nl);
   BLR_CHECK_LAUNCH();
@@ -456,6 +492,7 @@ void conserve_rows(hipStream_t s, const HostTables& h, T* Q, int rows) {
   for (size_t i = 0; i < h.minv.size() && i < 25; ++i) ma.minv[i] = h.minv[i];
   ma.N = h.N;
   ma.d = h.d;
+  TimedScope ts(s, "conserve", 2.0 * rows * h.n * sizeof(T));
   hipLaunchKernelGGL(k_conserve<T>, dim3(rows), dim3(256), 0, s, Q, h.n, ma);
   BLR_CHECK_LAUNCH();
 }
@@ -491,11 +528,6 @@ std::vector<ReduceTile> plan_tiles(int rb, const std::vector<int>& li, const std
     }
   return tiles;
 }
-
-struct PairPlan {
-  std::vector<int> bidx;     // compact basis -> row of V
-  std::vector<int> li, lj;   // per pair, compact indices (li <= lj)
-};
 
 static PairPlan make_plan(int r, const int32_t* pairs, int npairs) {
   PairPlan pl;
@@ -540,6 +572,30 @@ struct Generic {
     return b;
   }
 
+  // step 1 only: compact copy, spectra, projected basis and loss fields
+  static void basis(blr_ctx ctx, const DevTables& tb, const T* Vsrc, const PairPlan& pl, T2** pVh,
+                    T** pVp, T** pLam) {
+    const HostTables& h = tb.h;
+    hipStream_t s = ctx->stream;
+    const int rb = (int)pl.bidx.size();
+    const std::string tag = std::string("bas") + (sizeof(T) == 4 ? "f" : "d");
+    T* Vc = (T*)ctx->buf(tag + ".Vc", (size_t)rb * n * sizeof(T));
+    T2* Vh = (T2*)ctx->buf(tag + ".Vh", (size_t)rb * n * sizeof(T2));
+    T* Vp = (T*)ctx->buf(tag + ".VpLam", (size_t)2 * rb * n * sizeof(T));
+    T2* tmp = (T2*)ctx->buf(tag + ".tmp", (size_t)2 * rb * n * sizeof(T2));
+    for (int ib = 0; ib < rb; ++ib)
+      BLR_HIP(hipMemcpyAsync(Vc + (size_t)ib * n, Vsrc + (size_t)pl.bidx[ib] * n, n * sizeof(T),
+                             hipMemcpyDeviceToDevice, s));
+    g_stage = "basis";
+    transform<T, N, D, -1>(s, LdReal<T>{Vc, n}, StBasisSpec<T, N, D>{Vh, n, T(1) / T(n)}, tmp, rb);
+    transform<T, N, D, +1>(s, LdBasisMode<T>{Vh, (const T*)tb.gloss, n, rb}, StRe<T>{Vp, n}, tmp,
+                           2 * rb);
+    (void)h;
+    *pVh = Vh;
+    *pVp = Vp;
+    *pLam = Vp + (size_t)rb * n;
+  }
+
   // Q rows prow[p] receive Q_s(bidx[li[p]], bidx[lj[p]]) of the compact basis Vc.
   static void run(blr_ctx ctx, const DevTables& tb, const T* Vsrc, const PairPlan& pl,
                   const std::vector<int>& prow, T* Q) {
@@ -575,9 +631,11 @@ struct Generic {
     const T* fw = (const T*)tb.fw;
     const T* gl = (const T*)tb.gloss;
     // 1. spectra, projected basis and loss fields
+    g_stage = "gen.basis";
     transform<T, N, D, -1>(s, LdReal<T>{Vc, n}, StBasisSpec<T, N, D>{Vh, n, T(1) / T(n)}, tmp, rb);
     transform<T, N, D, +1>(s, LdBasisMode<T>{Vh, gl, n, rb}, StRe<T>{Vp, n}, tmp, 2 * rb);
     // 2. shifts
+    g_stage = "gen.shift";
     for (long f0 = 0; f0 < shift_fields; f0 += batch) {
       const long nb = std::min(batch, shift_fields - f0);
       transform<T, N, D, +1>(s, LdShift<T, N, D>{Vh, phase, n, h.mrho, h.nbp, f0},
@@ -589,11 +647,16 @@ struct Generic {
     bool diag_only = false;
     const int Gt = sizeof(T) == 4 ? 12 : 8;
     auto tiles = plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
+    g_stage = "gen.pairfft";
     for (int a = 0; a < h.mrho; ++a) {
       for (const auto& t : tiles) {
         const bool diag = t.bi[0] == t.bj[0];
         const int bs = 256;
         const dim3 grid((n + bs - 1) / bs);
+        int nvalid = 0;
+        for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
+        const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
+        TimedScope ts(s, "gen.sigma_reduce", (double)n * (nload * h.nbp + nvalid) * sizeof(T));
         if (sizeof(T) == 4) {
           if (diag)
             hipLaunchKernelGGL((k_sigma_reduce<T, 12, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
@@ -615,6 +678,7 @@ struct Generic {
                              tmp, nc);
     }
     // 5. back to velocity space, minus the loss
+    g_stage = "gen.final";
     transform<T, N, D, +1>(s, LdComplex<T>{G, n},
                            StFinal<T>{Q, Vp, Lam, didx, didx + P, didx + 2 * P, n}, tmp, nc);
   }
@@ -641,8 +705,6 @@ static void dispatch_size(int d, int N, F&& f) {
   throw Error(BLR_ERR_UNSUPPORTED, "velocity grid size not built");
 }
 
-bool fast_collision_f32(blr_ctx ctx, const DevTables& tb, const float* V, const PairPlan& pl,
-                        const std::vector<int>& prow, float* Q);
 
 template <typename T>
 static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const int32_t* pairs,
@@ -664,18 +726,20 @@ static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const
     for (int p = 0; p < npairs; ++p) prow[p] = p;
     bool done = false;
     if constexpr (sizeof(T) == 4) {
-      if (!(flags & BLR_GENERIC_FFT)) done = fast_collision_f32(ctx, tb, V, pl, prow, Q);
+      if (!(flags & BLR_GENERIC_FFT))
+        done = fast_collision_f32(ctx, tb, V, pl, prow, Q, !(flags & BLR_NO_CONSERVE));
     }
-    if (!done)
-      dispatch_size<T>(h.d, h.N, [&](auto Nc, auto Dc) {
-        Generic<T, decltype(Nc)::value, decltype(Dc)::value>::run(ctx, tb, V, pl, prow, Q);
-      });
+    if (done) return;  // the fused final kernel applied the projection
+    dispatch_size<T>(h.d, h.N, [&](auto Nc, auto Dc) {
+      Generic<T, decltype(Nc)::value, decltype(Dc)::value>::run(ctx, tb, V, pl, prow, Q);
+    });
   }
   if (!(flags & BLR_NO_CONSERVE)) conserve_rows<T>(ctx->stream, h, Q, npairs);
 }
 
 void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
                      const int32_t* pairs, int npairs, void* Q) {
+  g_timer = &ctx->timer;
   require(r >= 1 && r <= 64, "r must be in [1, 64]");
   require(npairs >= 0 && npairs <= 4096, "npairs must be in [0, 4096]");
   require(npairs == 0 || (pairs && V && Q), "null pointer argument");
@@ -684,6 +748,13 @@ void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, 
     run_pairs<float>(ctx, tb, (const float*)V, r, pairs, npairs, (float*)Q, vg.flags);
   else
     run_pairs<double>(ctx, tb, (const double*)V, r, pairs, npairs, (double*)Q, vg.flags);
+}
+
+void basis_spectra_f32(blr_ctx ctx, const DevTables& tb, const float* V, const PairPlan& pl,
+                       float2** Vh, float** Vp, float** Lam) {
+  dispatch_size<float>(tb.h.d, tb.h.N, [&](auto Nc, auto Dc) {
+    Generic<float, decltype(Nc)::value, decltype(Dc)::value>::basis(ctx, tb, V, pl, Vh, Vp, Lam);
+  });
 }
 
 size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec) {

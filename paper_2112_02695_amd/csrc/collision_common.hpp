@@ -48,6 +48,23 @@ struct ReduceTile {
   int out[256];
 };
 
+// compact basis and pair list of one call
+struct PairPlan {
+  std::vector<int> bidx;     // compact basis -> row of V
+  std::vector<int> li, lj;   // per pair, compact indices (li <= lj)
+};
+
+std::vector<ReduceTile> plan_tiles(int rb, const std::vector<int>& li, const std::vector<int>& lj,
+                                   int G, bool& diag_only);
+template <typename T>
+void fill(hipStream_t s, T* p, long count, T v);
+void timed_begin(const std::string& name, double bytes, hipStream_t s);
+void timed_end(hipStream_t s);
+bool fast_collision_f32(blr_ctx ctx, const DevTables& tb, const float* V, const PairPlan& pl,
+                        const std::vector<int>& prow, float* Q, bool conserve);
+void basis_spectra_f32(blr_ctx ctx, const DevTables& tb, const float* V, const PairPlan& pl,
+                       float2** Vh, float** Vp, float** Lam);
+
 // moment projection parameters
 struct MomentArgs {
   double L, dv, w;      // box half width, spacing, dv^d

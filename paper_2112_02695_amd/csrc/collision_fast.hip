@@ -1,11 +1,464 @@
-// Fused FP32 collision kernels (placeholder until written): returning false
-// selects the generic pipeline.
+// Fused FP32 collision kernels for 3D grids n in {16, 24, 32}.
+//
+// A workgroup of N^2 threads holds one whole N^3 complex field in registers:
+// thread t owns one line of N values along the axis being transformed, the
+// in-register DFT of fft.hpp transforms it, and the lines are re-dealt between
+// the three axis stages through LDS (one real component at a time, rows
+// padded to N+1 floats so that both the writes and the reads of every
+// exchange are free of bank conflicts).  For N = 32 that is 1024 threads and
+// 132 KiB of LDS: one workgroup per CU, the FFT never leaves the CU.
+//
+// Kernels (same arithmetic as the generic pipeline in collision.hip):
+//   k_shift_fused  one antipodal shift pair S(b), S(bbar) of one basis
+//                  function at one radial node per workgroup iteration:
+//                  spectrum x (cos x - sin x) -> 3D inverse DFT -> two real
+//                  fields written coalesced (the only HBM-heavy output)
+//   k_reduce_all   sigma sums of all pair products for all radial nodes in
+//                  one launch (thread per grid point, pairs in registers)
+//   k_pair_spec    3D DFT of one pair product at one radial node, times the
+//                  radial weight, written as the half spectrum k_2 <= N/2
+//   k_final_fused  sum over radial nodes, 3D inverse DFT from the half
+//                  spectrum, minus the loss, FP64 moment projection, store
+#include <cmath>
+#include <cstring>
+
 #include "collision_common.hpp"
 
 namespace blr {
-struct PairPlan;
-bool fast_collision_f32(blr_ctx, const DevTables&, const float*, const PairPlan&,
-                        const std::vector<int>&, float*) {
-  return false;
+
+
+namespace fastk {
+
+template <int N>
+struct Geo {
+  static constexpr int NT = N * N;
+  static constexpr int n = N * N * N;
+  static constexpr int H = N / 2 + 1;
+  static constexpr int LDS = N * N * (N + 1);
+};
+
+// element j of the line owned by (u, w) at a stage along axis A
+template <int A>
+__device__ __forceinline__ void coords(int u, int w, int j, int& i0, int& i1, int& i2) {
+  if constexpr (A == 2) {
+    i0 = u; i1 = w; i2 = j;
+  } else if constexpr (A == 1) {
+    i0 = u; i1 = j; i2 = w;
+  } else {
+    i0 = j; i1 = u; i2 = w;
+  }
 }
+
+// Re-deal lines from a stage along axis AF to a stage along axis AT.
+template <int N, int AF, int AT>
+__device__ __forceinline__ void exchange(float (&v)[N], float* L, int u, int w) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    int i0, i1, i2;
+    coords<AF>(u, w, j, i0, i1, i2);
+    L[(i0 * N + i1) * (N + 1) + i2] = v[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    int i0, i1, i2;
+    coords<AT>(u, w, j, i0, i1, i2);
+    v[j] = L[(i0 * N + i1) * (N + 1) + i2];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ shifts
+template <int N>
+__global__ __launch_bounds__(N * N) void k_shift_fused(const float2* __restrict__ vh,
+                                                       const float2* __restrict__ phase,
+                                                       float* __restrict__ sh,
+                                                       const int* __restrict__ bp_b,
+                                                       const int* __restrict__ bp_bb, int mrho,
+                                                       int nbp, int msig, long nfields) {
+  __shared__ float L[Geo<N>::LDS];
+  constexpr int n = Geo<N>::n;
+  const int t = threadIdx.x;
+  const int u = t / N, w = t % N;
+  for (long f = blockIdx.x; f < nfields; f += gridDim.x) {
+    const int p = (int)(f % nbp);
+    const int a = (int)((f / nbp) % mrho);
+    const long ib = f / ((long)nbp * mrho);
+    const float2* ph = phase + ((long)a * nbp + p) * 3 * N;
+    // stage along axis 2: thread (k0, k1) = (u, w)
+    const float2 c01 = cmul(ph[u], ph[N + w]);
+    const float4* src = reinterpret_cast<const float4*>(vh + ib * n + (long)(u * N + w) * N);
+    float re[N], im[N];
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const float4 v = src[j];
+      const float2 ca = cmul(c01, ph[2 * N + 2 * j]);
+      const float2 cb = cmul(c01, ph[2 * N + 2 * j + 1]);
+      const float fa = ca.x + ca.y, fb = cb.x + cb.y;
+      re[2 * j] = v.x * fa;
+      im[2 * j] = v.y * fa;
+      re[2 * j + 1] = v.z * fb;
+      im[2 * j + 1] = v.w * fb;
+    }
+    fft::dft<float, N, +1>(re, im);
+    exchange<N, 2, 1>(re, L, u, w);
+    exchange<N, 2, 1>(im, L, u, w);
+    fft::dft<float, N, +1>(re, im);
+    exchange<N, 1, 0>(re, L, u, w);
+    exchange<N, 1, 0>(im, L, u, w);
+    fft::dft<float, N, +1>(re, im);
+    // thread (i1, i2) = (u, w) holds the line over i0: coalesced stores
+    const long base = ((ib * mrho + a) * msig) * (long)n + u * N + w;
+    float* s1 = sh + base + (long)bp_b[p] * n;
+    float* s2 = sh + base + (long)bp_bb[p] * n;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      s1[j * N * N] = re[j] - im[j];
+      s2[j * N * N] = re[j] + im[j];
+    }
+  }
+}
+
+// ------------------------------------------------------------ sigma sums
+// All radial nodes in one launch (blockIdx.y = a); one thread per point.
+template <int G, bool DIAG>
+__global__ __launch_bounds__(256) void k_reduce_all(const float* __restrict__ sh,
+                                                    float* __restrict__ pa, ReduceTile tile,
+                                                    const float* __restrict__ wbp,
+                                                    const int* __restrict__ bp_b,
+                                                    const int* __restrict__ bp_bb, int n, int mrho,
+                                                    int msig, int nbp, int P) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (q >= n) return;
+  constexpr int NP = DIAG ? G * (G + 1) / 2 : G * G;
+  float acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = 0.f;
+  for (int bp = 0; bp < nbp; ++bp) {
+    const int b = bp_b[bp], bb = bp_bb[bp];
+    const float wt = wbp[bp];
+    float xi[G], yi[G], xj[G], yj[G];
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      float x = 0.f, y = 0.f;
+      if (s < tile.ni) {
+        const long fi = ((long)tile.bi[s] * mrho + a) * msig;
+        x = sh[(fi + b) * n + q];
+        y = sh[(fi + bb) * n + q];
+      }
+      xi[s] = wt * x;
+      yi[s] = wt * y;
+      if constexpr (DIAG) {
+        xj[s] = x;
+        yj[s] = y;
+      } else {
+        x = y = 0.f;
+        if (s < tile.nj) {
+          const long fj = ((long)tile.bj[s] * mrho + a) * msig;
+          x = sh[(fj + b) * n + q];
+          y = sh[(fj + bb) * n + q];
+        }
+        xj[s] = x;
+        yj[s] = y;
+      }
+    }
+    int p = 0;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+#pragma unroll
+      for (int v = DIAG ? s : 0; v < G; ++v) {
+        acc[p] += xi[s] * yj[v] + yi[s] * xj[v];
+        ++p;
+      }
+    }
+  }
+  float* out = pa + (long)a * P * n + q;
+  int p = 0;
+#pragma unroll
+  for (int s = 0; s < G; ++s) {
+#pragma unroll
+    for (int v = DIAG ? s : 0; v < G; ++v) {
+      const int row = tile.out[s * G + v];
+      if (row >= 0) out[(long)row * n] = acc[p];
+      ++p;
+    }
+  }
+}
+
+// ------------------------------------------------------- pair transforms
+// workgroup = (pair p, radial node a); writes w_a(|k|^2) DFT(P_pa)/n for k_2 <= N/2
+template <int N>
+__global__ __launch_bounds__(N * N) void k_pair_spec(const float* __restrict__ pa,
+                                                     const float* __restrict__ fw,
+                                                     float2* __restrict__ wsp, int P, int mrho,
+                                                     int nkk) {
+  __shared__ float L[Geo<N>::LDS];
+  constexpr int n = Geo<N>::n, H = Geo<N>::H;
+  const int t = threadIdx.x;
+  const int u = t / N, w = t % N;
+  const int p = blockIdx.x % P;
+  const int a = blockIdx.x / P;
+  // stage along axis 0: thread (i1, i2) = (u, w), coalesced loads
+  const float* src = pa + ((long)a * P + p) * n + u * N + w;
+  float re[N], im[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    re[j] = src[j * N * N];
+    im[j] = 0.f;
+  }
+  fft::dft<float, N, -1>(re, im);
+  exchange<N, 0, 1>(re, L, u, w);
+  exchange<N, 0, 1>(im, L, u, w);
+  fft::dft<float, N, -1>(re, im);
+  exchange<N, 1, 2>(re, L, u, w);
+  exchange<N, 1, 2>(im, L, u, w);
+  fft::dft<float, N, -1>(re, im);
+  // thread (k0, k1) = (u, w) holds k2 = 0..N-1; keep k2 <= N/2
+  const int k0 = ctr<N>(u), k1 = ctr<N>(w);
+  const float* f = fw + (long)a * nkk;
+  float2* dst = wsp + (((long)p * mrho + a) * N * N + (long)(u * N + w)) * H;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const int k2 = ctr<N>(j);
+    const float wt = f[k0 * k0 + k1 * k1 + k2 * k2];
+    dst[j] = make_float2(wt * re[j], wt * im[j]);
+  }
+}
+
+// --------------------------------------------------------------- final
+struct FinalArgs {
+  double L, dv, w;
+  double minv[25];
+  int conserve;
+};
+
+template <int N>
+__global__ __launch_bounds__(N * N) void k_final_fused(const float2* __restrict__ wsp,
+                                                       const float* __restrict__ vp,
+                                                       const float* __restrict__ lam,
+                                                       const int* __restrict__ pidx, float* Q,
+                                                       int P, int mrho, FinalArgs fa) {
+  constexpr int n = Geo<N>::n, H = Geo<N>::H, NT = Geo<N>::NT;
+  constexpr int HP = H + 1;  // padded half row
+  __shared__ float LR[N * N * HP];
+  __shared__ float LI[N * N * HP];
+  __shared__ double red[5][NT / 64];
+  __shared__ double lamb[5];
+  const int t = threadIdx.x;
+  const int p = blockIdx.x;
+  const int li = pidx[p], lj = pidx[P + p], row = pidx[2 * P + p];
+  // stage A, axis 0 over k0 at fixed (k1, k2h): N*H active lines
+  {
+    float re[N], im[N];
+    const bool act = t < N * H;
+    const int k1 = t / H, k2 = t % H;
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        re[j] = 0.f;
+        im[j] = 0.f;
+      }
+      for (int a = 0; a < mrho; ++a) {
+        const float2* src = wsp + ((long)p * mrho + a) * N * N * H + (long)k1 * H + k2;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const float2 v = src[(long)j * N * H];
+          re[j] += v.x;
+          im[j] += v.y;
+        }
+      }
+      fft::dft<float, N, +1>(re, im);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {  // (i0 = j, k1, k2)
+        LR[(j * N + k1) * HP + k2] = re[j];
+        LI[(j * N + k1) * HP + k2] = im[j];
+      }
+    }
+    __syncthreads();
+    // stage B, axis 1 over k1 at fixed (i0, k2h)
+    const int i0 = t / H;
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        re[j] = LR[(i0 * N + j) * HP + k2];
+        im[j] = LI[(i0 * N + j) * HP + k2];
+      }
+    }
+    __syncthreads();
+    if (act) {
+      fft::dft<float, N, +1>(re, im);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {  // (i0, i1 = j, k2)
+        LR[(i0 * N + j) * HP + k2] = re[j];
+        LI[(i0 * N + j) * HP + k2] = im[j];
+      }
+    }
+    __syncthreads();
+  }
+  // stage C, axis 2: thread (i0, i1); full Hermitian line from the half
+  const int i0 = t / N, i1 = t % N;
+  float re[N], im[N];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    re[j] = LR[(i0 * N + i1) * HP + j];
+    im[j] = LI[(i0 * N + i1) * HP + j];
+  }
+#pragma unroll
+  for (int j = H; j < N; ++j) {
+    re[j] = re[N - j];
+    im[j] = -im[N - j];
+  }
+  fft::dft<float, N, +1>(re, im);
+  // gain - loss
+  const long off = (long)(i0 * N + i1) * N;
+  const float* vi = vp + (long)li * n + off;
+  const float* vj = vp + (long)lj * n + off;
+  const float* lmi = lam + (long)li * n + off;
+  const float* lmj = lam + (long)lj * n + off;
+#pragma unroll
+  for (int j = 0; j < N; ++j) re[j] = re[j] - 0.5f * (vj[j] * lmi[j] + vi[j] * lmj[j]);
+  if (fa.conserve) {
+    const double v0 = -fa.L + i0 * fa.dv, v1 = -fa.L + i1 * fa.dv;
+    double m[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const double v2 = -fa.L + j * fa.dv;
+      const double q = (double)re[j];
+      m[0] += q;
+      m[1] += q * v0;
+      m[2] += q * v1;
+      m[3] += q * v2;
+      m[4] += q * (v0 * v0 + v1 * v1 + v2 * v2);
+    }
+    // deterministic reduction: wave sums then a fixed-order sum of waves
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      double x = m[k];
+      for (int off2 = 32; off2 > 0; off2 >>= 1) x += __shfl_down(x, off2, 64);
+      if ((t & 63) == 0) red[k][t >> 6] = x;
+    }
+    __syncthreads();
+    if (t < 5) {
+      double s = 0;
+      for (int k = 0; k < NT / 64; ++k) s += red[t][k];
+      lamb[t] = s * fa.w;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double l[5];
+      for (int i = 0; i < 5; ++i) {
+        l[i] = 0;
+        for (int k = 0; k < 5; ++k) l[i] += fa.minv[i * 5 + k] * lamb[k];
+      }
+      for (int i = 0; i < 5; ++i) red[i][0] = l[i];
+    }
+    __syncthreads();
+    const double l0 = red[0][0], l1 = red[1][0], l2 = red[2][0], l3 = red[3][0], l4 = red[4][0];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const double v2 = -fa.L + j * fa.dv;
+      const double c = l0 + l1 * v0 + l2 * v1 + l3 * v2 + l4 * (v0 * v0 + v1 * v1 + v2 * v2);
+      re[j] = (float)((double)re[j] - fa.w * c);
+    }
+  }
+  float* dst = Q + (long)row * n + off;
+#pragma unroll
+  for (int j = 0; j < N; ++j) dst[j] = re[j];
+}
+
+}  // namespace fastk
+
+
+template <int N>
+static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const std::vector<int>& prow,
+                     const float2* Vh, const float* Vp, const float* Lam, float* Q, bool conserve) {
+  using namespace fastk;
+  const HostTables& h = tb.h;
+  hipStream_t s = ctx->stream;
+  constexpr int n = Geo<N>::n, H = Geo<N>::H;
+  const int rb = (int)pl.bidx.size();
+  const int P = (int)pl.li.size();
+  const long nfields = (long)rb * h.mrho * h.nbp;
+  float* Sh = (float*)ctx->buf("fast.Sh", (size_t)rb * h.mrho * h.msig * n * sizeof(float));
+  float* Pa = (float*)ctx->buf("fast.Pa", (size_t)h.mrho * P * n * sizeof(float));
+  float2* Wsp = (float2*)ctx->buf("fast.Wsp", (size_t)P * h.mrho * N * N * H * sizeof(float2));
+  std::vector<int> idx(3 * P);
+  for (int p = 0; p < P; ++p) {
+    idx[p] = pl.li[p];
+    idx[P + p] = pl.lj[p];
+    idx[2 * P + p] = prow[p];
+  }
+  int* didx = (int*)ctx->upload("fast.idx", idx.data(), idx.size() * sizeof(int));
+  // shifts: persistent-style grid, each workgroup loops over fields
+  {
+    const long grid = std::min<long>(nfields, 2048);
+    timed_begin("fast.shift", (double)nfields * n * (2 * sizeof(float)), s);
+    hipLaunchKernelGGL(k_shift_fused<N>, dim3((unsigned)grid), dim3(N * N), 0, s, Vh,
+                       (const float2*)tb.phase, Sh, tb.bp_b, tb.bp_bb, h.mrho, h.nbp, h.msig, nfields);
+    BLR_CHECK_LAUNCH();
+    timed_end(s);
+  }
+  // sigma sums for every radial node
+  {
+    bool diag_only = false;
+    auto tiles = plan_tiles(rb, pl.li, pl.lj, 12, diag_only);
+    for (const auto& t : tiles) {
+      const bool diag = t.bi[0] == t.bj[0];
+      int nvalid = 0;
+      for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
+      const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
+      timed_begin("fast.reduce", (double)h.mrho * n * (nload * h.nbp + nvalid) * sizeof(float), s);
+      const dim3 grid((n + 255) / 256, h.mrho);
+      if (diag)
+        hipLaunchKernelGGL((k_reduce_all<12, true>), grid, dim3(256), 0, s, Sh, Pa, t,
+                           (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
+      else
+        hipLaunchKernelGGL((k_reduce_all<12, false>), grid, dim3(256), 0, s, Sh, Pa, t,
+                           (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
+      BLR_CHECK_LAUNCH();
+      timed_end(s);
+    }
+  }
+  // transforms of the pair products with the radial weights
+  timed_begin("fast.pair_spec",
+              (double)P * h.mrho * ((double)n * sizeof(float) + (double)N * N * H * sizeof(float2)), s);
+  hipLaunchKernelGGL(k_pair_spec<N>, dim3(P * h.mrho), dim3(N * N), 0, s, Pa, (const float*)tb.fw,
+                     Wsp, P, h.mrho, h.nkk);
+  BLR_CHECK_LAUNCH();
+  timed_end(s);
+  // radial sum, inverse transform, loss, projection
+  FinalArgs fa{};
+  fa.L = h.L;
+  fa.dv = h.dv;
+  fa.w = std::pow(h.dv, 3);
+  for (int i = 0; i < 25 && i < (int)h.minv.size(); ++i) fa.minv[i] = h.minv[i];
+  fa.conserve = conserve ? 1 : 0;
+  timed_begin("fast.final",
+              (double)P * ((double)h.mrho * N * N * H * sizeof(float2) + 5.0 * n * sizeof(float)), s);
+  hipLaunchKernelGGL(k_final_fused<N>, dim3(P), dim3(N * N), 0, s, Wsp, Vp, Lam, didx, Q, P, h.mrho,
+                     fa);
+  BLR_CHECK_LAUNCH();
+  timed_end(s);
+}
+
+// Basis spectra and loss fields come from the generic kernels (collision.hip).
+
+bool fast_collision_f32(blr_ctx ctx, const DevTables& tb, const float* V, const PairPlan& pl,
+                        const std::vector<int>& prow, float* Q, bool conserve) {
+  const HostTables& h = tb.h;
+  if (h.d != 3 || (h.N != 16 && h.N != 24 && h.N != 32)) return false;
+  if (pl.bidx.size() > 64 || h.msig != 38) return false;
+  float2* Vh;
+  float* Vp;
+  float* Lam;
+  basis_spectra_f32(ctx, tb, V, pl, &Vh, &Vp, &Lam);
+  switch (h.N) {
+    case 16: run_fast<16>(ctx, tb, pl, prow, Vh, Vp, Lam, Q, conserve); break;
+    case 24: run_fast<24>(ctx, tb, pl, prow, Vh, Vp, Lam, Q, conserve); break;
+    case 32: run_fast<32>(ctx, tb, pl, prow, Vh, Vp, Lam, Q, conserve); break;
+  }
+  return true;
+}
+
 }  // namespace blr

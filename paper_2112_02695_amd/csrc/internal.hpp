@@ -76,6 +76,30 @@ struct Buffer {
   size_t bytes = 0;
 };
 
+// Optional per-kernel timing: launches bracketed by HIP events on the
+// context stream, accumulated per kernel name when read.
+struct KernelTimer {
+  bool on = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::string> order;
+  struct Acc {
+    double ms = 0, bytes = 0;
+    long launches = 0;
+  };
+  std::map<std::string, Acc> acc;
+  hipEvent_t take();
+  void begin(hipStream_t s, const std::string& name, double bytes);
+  void end(hipStream_t s);
+  void collect();
+  void release();
+};
+
 }  // namespace blr
 
 struct blr_ctx_t {
@@ -94,6 +118,7 @@ struct blr_ctx_t {
   size_t stage_bytes = 0;
   size_t stage_used = 0;
   hipEvent_t stage_done = nullptr;
+  blr::KernelTimer timer;
 
   void* buf(const std::string& name, size_t bytes);  // grow-only named workspace
   // copy a small host array to a named device buffer, asynchronously
