@@ -1,19 +1,913 @@
-// Low-rank step: not written yet; the entry points report BLR_ERR_UNSUPPORTED.
-#include "internal.hpp"
+// Adaptive dynamical low-rank step on the GPU (FP64 except the pair
+// collisions, which are FP32 unless BLR_STEP_FP64_COLLISION).
+//
+// Physical space is 1D along the first velocity axis; cells x_p, spacing dx;
+// inner products <a,b>_x = dx sum_p a_p b_p and <a,b>_v = dv^d sum_q a_q b_q.
+// Upwind transport v^+ D_+ (backward difference) and v^- D_- (forward
+// difference); ghost values of K from the projected boundary function: at the
+// left wall K_j = <f_L 1_{v1>0}, V_j>_v + sum_l K_l(x_0) <1_{v1<=0} V_l V_j>_v,
+// at the right wall with f_R, 1_{v1<0} and the last cell.
+//
+// Layouts (device, FP64): X rows [i][x] (r x nx), V rows [j][q] (r x n),
+// S row-major.  All reductions have a fixed order (no atomics), so a step is
+// bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "collision_common.hpp"
+#include "linalg.hpp"
+
+namespace blr {
+namespace dk {
+
+// weight of mode m at velocity point q (v1 = first velocity coordinate)
+enum Mode { W_ONE = 0, W_VPLUS, W_VMINUS, W_OUT_LEFT, W_OUT_RIGHT, W_IN_LEFT, W_IN_RIGHT };
+
+struct VGeo {
+  double L, dv;
+  int N, d, n;
+  __device__ __forceinline__ double v1(int q) const {
+    const int q0 = d == 3 ? q / (N * N) : q / N;
+    return -L + q0 * dv;
+  }
+};
+
+__device__ __forceinline__ double weight(int mode, double v1) {
+  switch (mode) {
+    case W_VPLUS: return v1 > 0 ? v1 : 0.0;
+    case W_VMINUS: return v1 < 0 ? v1 : 0.0;
+    case W_OUT_LEFT: return v1 <= 0 ? 1.0 : 0.0;
+    case W_OUT_RIGHT: return v1 >= 0 ? 1.0 : 0.0;
+    case W_IN_LEFT: return v1 > 0 ? 1.0 : 0.0;
+    case W_IN_RIGHT: return v1 < 0 ? 1.0 : 0.0;
+    default: return 1.0;
+  }
+}
+
+constexpr int GT = 64;      // output tile (rows of A, rows of B)
+constexpr int GQ = 64;      // points per LDS stage
+constexpr int NCHUNK = 64;  // velocity chunks (first reduction stage)
+
+// partial[c][i][j] = sum_{q in chunk c} w(q) A[i][q] B[j][q]
+template <typename TB>
+__global__ __launch_bounds__(256) void k_vgram(const double* __restrict__ A, int ra, long lda,
+                                               const TB* __restrict__ B, int rb, long ldb, int mode,
+                                               VGeo g, double* __restrict__ part) {
+  __shared__ double As[GT][GQ + 1];
+  __shared__ double Bs[GT][GQ + 1];
+  __shared__ double ws[GQ];
+  const int c = blockIdx.x;
+  const int i0 = blockIdx.y * GT, j0 = blockIdx.z * GT;
+  const long q_begin = (long)c * g.n / NCHUNK, q_end = (long)(c + 1) * g.n / NCHUNK;
+  const int t = threadIdx.x;
+  double acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  const int ti = t / 16, tj = t % 16;  // outputs (ti + 16 a, tj + 16 b), a,b < 4
+  for (long q0 = q_begin; q0 < q_end; q0 += GQ) {
+    const int nq = (int)min((long)GQ, q_end - q0);
+    for (int e = t; e < GT * GQ; e += 256) {
+      const int r = e / GQ, qq = e % GQ;
+      As[r][qq] = (i0 + r < ra && qq < nq) ? A[(long)(i0 + r) * lda + q0 + qq] : 0.0;
+      Bs[r][qq] = (j0 + r < rb && qq < nq) ? (double)B[(long)(j0 + r) * ldb + q0 + qq] : 0.0;
+    }
+    if (t < GQ) ws[t] = t < nq ? weight(mode, g.v1((int)(q0 + t))) : 0.0;
+    __syncthreads();
+    for (int qq = 0; qq < nq; ++qq) {
+      const double w = ws[qq];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double x = w * As[ti + 16 * a][qq];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a * 4 + b] += x * Bs[tj + 16 * b][qq];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + ti + 16 * a, j = j0 + tj + 16 * b;
+      if (i < ra && j < rb) part[((long)c * ra + i) * rb + j] = acc[a * 4 + b];
+    }
+}
+
+__global__ void k_vgram_finish(const double* __restrict__ part, int ra, int rb, double scale,
+                               double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ra * rb) return;
+  double s = 0.0;
+  for (int c = 0; c < NCHUNK; ++c) s += part[(long)c * ra * rb + t];
+  out[t] = scale * s;
+}
+
+// K[j][x] = sum_i X[i][x] S[i][j]
+__global__ void k_xmul(const double* __restrict__ X, int r, int nx, const double* __restrict__ S,
+                       int lds, double* __restrict__ K) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r * nx) return;
+  const int j = t / nx, x = t % nx;
+  double s = 0.0;
+  for (int i = 0; i < r; ++i) s += X[(long)i * nx + x] * S[i * lds + j];
+  K[t] = s;
+}
+
+// ghost values g[0][j] (left), g[1][j] (right) of the columns of K
+__global__ void k_ghosts(const double* __restrict__ K, int r, int nx, const double* __restrict__ ginL,
+                         const double* __restrict__ ginR, const double* __restrict__ MoL,
+                         const double* __restrict__ MoR, double* __restrict__ g) {
+  const int j = threadIdx.x;
+  if (j >= r) return;
+  double sl = ginL[j], sr = ginR[j];
+  for (int l = 0; l < r; ++l) {
+    sl += K[(long)l * nx + 0] * MoL[l * r + j];
+    sr += K[(long)l * nx + nx - 1] * MoR[l * r + j];
+  }
+  g[j] = sl;
+  g[r + j] = sr;
+}
+
+__device__ __forceinline__ double dplus(const double* K, const double* g, int l, int x, int nx,
+                                        double dx) {
+  const double prev = x == 0 ? g[l] : K[(long)l * nx + x - 1];
+  return (K[(long)l * nx + x] - prev) / dx;
+}
+__device__ __forceinline__ double dminus(const double* K, const double* g, int r, int l, int x,
+                                         int nx, double dx) {
+  const double next = x == nx - 1 ? g[r + l] : K[(long)l * nx + x + 1];
+  return (next - K[(long)l * nx + x]) / dx;
+}
+
+// K-step: K1 = K + dt (-sum_l A+_{jl} D+K_l - sum_l A-_{jl} D-K_l + sum_p C_{jp} w_p K_m K_n)
+__global__ void k_kstep(const double* __restrict__ K, const double* __restrict__ g, int r, int nx,
+                        double dx, double dt, const double* __restrict__ Ap,
+                        const double* __restrict__ Am, const double* __restrict__ C, int P,
+                        const int* __restrict__ pm, const int* __restrict__ pn,
+                        double* __restrict__ K1, double* __restrict__ dK) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r * nx) return;
+  const int j = t / nx, x = t % nx;
+  double rhs = 0.0;
+  for (int l = 0; l < r; ++l)
+    rhs -= Ap[j * r + l] * dplus(K, g, l, x, nx, dx) + Am[j * r + l] * dminus(K, g, r, l, x, nx, dx);
+  for (int p = 0; p < P; ++p) {
+    const int m = pm[p], nn = pn[p];
+    const double w = (m == nn) ? 1.0 : 2.0;
+    rhs += C[j * P + p] * w * K[(long)m * nx + x] * K[(long)nn * nx + x];
+  }
+  const double k1 = K[t] + dt * rhs;
+  K1[t] = k1;
+  dK[t] = k1 - K[t];
+}
+
+// x-side reductions: out[i][c] = dx sum_x X1[i][x] Y_c(x) for
+//   c <  r        : Y = D+ K_c
+//   c <  2r       : Y = D- K_(c-r)
+//   c <  2r + P   : Y = w_p K_m K_n
+// (mode 1: Y_c = Z[c][x], a plain matrix with cols columns)
+__global__ void k_xreduce(const double* __restrict__ X1, int r, int nx, double dx,
+                          const double* __restrict__ K, const double* __restrict__ g, int P,
+                          const int* __restrict__ pm, const int* __restrict__ pn,
+                          const double* __restrict__ Z, int zc, int mode, double* __restrict__ out,
+                          int ncols, double* __restrict__ oDp, double* __restrict__ oDm,
+                          double* __restrict__ oT) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r * ncols) return;
+  const int i = t / ncols, c = t % ncols;
+  double s = 0.0;
+  for (int x = 0; x < nx; ++x) {
+    double y;
+    if (mode == 1) {
+      y = Z[(long)c * nx + x];
+    } else if (c < r) {
+      y = dplus(K, g, c, x, nx, dx);
+    } else if (c < 2 * r) {
+      y = dminus(K, g, r, c - r, x, nx, dx);
+    } else {
+      const int p = c - 2 * r;
+      const int m = pm[p], nn = pn[p];
+      y = ((m == nn) ? 1.0 : 2.0) * K[(long)m * nx + x] * K[(long)nn * nx + x];
+    }
+    s += X1[(long)i * nx + x] * y;
+  }
+  s *= dx;
+  (void)zc;
+  if (mode == 1) {
+    out[t] = s;
+  } else if (c < r) {
+    oDp[i * r + c] = s;
+  } else if (c < 2 * r) {
+    oDm[i * r + c - r] = s;
+  } else {
+    oT[i * P + c - 2 * r] = s;
+  }
+}
+
+// L-step on the velocity grid, rows i of this block's chunk of 8:
+//   L_i  = sum_l S2_il V_l
+//   L1_i = L_i - dt (v+ sum_l Dp_il V_l + v- sum_l Dm_il V_l) + dt sum_p T_ip Q_p
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_lstep(const double* __restrict__ V, int r, int n,
+                                               const double* __restrict__ S2,
+                                               const double* __restrict__ Dp,
+                                               const double* __restrict__ Dm,
+                                               const double* __restrict__ T,
+                                               const TQ* __restrict__ Q, int P, double dt, VGeo g,
+                                               double* __restrict__ L1, double* __restrict__ dL) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i0 = blockIdx.y * 8;
+  if (q >= n) return;
+  double l[8], dp[8], dm[8], cq[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) l[k] = dp[k] = dm[k] = cq[k] = 0.0;
+  for (int m = 0; m < r; ++m) {
+    const double v = V[(long)m * n + q];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = min(i0 + k, r - 1);
+      l[k] += S2[i * r + m] * v;
+      dp[k] += Dp[i * r + m] * v;
+      dm[k] += Dm[i * r + m] * v;
+    }
+  }
+  for (int p = 0; p < P; ++p) {
+    const double qv = (double)Q[(long)p * n + q];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cq[k] += T[min(i0 + k, r - 1) * P + p] * qv;
+  }
+  const double v1 = g.v1(q);
+  const double vp = v1 > 0 ? v1 : 0.0, vm = v1 < 0 ? v1 : 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int i = i0 + k;
+    if (i < r) {
+      const double d = -dt * (vp * dp[k] + vm * dm[k]) + dt * cq[k];
+      L1[(long)i * n + q] = l[k] + d;
+      dL[(long)i * n + q] = d;
+    }
+  }
+}
+
+// out[i][e] = scale * sum_l M[l * ldm + i] in[l][e]   (combination of rows)
+__global__ void k_rows_comb(const double* __restrict__ in, int rin, long len,
+                            const double* __restrict__ M, int ldm, int rout, double scale,
+                            double* __restrict__ out, long ldo) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (e >= len || i >= rout) return;
+  double s = 0.0;
+  for (int l = 0; l < rin; ++l) s += M[l * ldm + i] * in[(long)l * len + e];
+  out[(long)i * ldo + e] = scale * s;
+}
+
+__global__ void k_scale_copy(const double* __restrict__ in, long count, double scale,
+                             double* __restrict__ out) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < count) out[e] = scale * in[e];
+}
+
+__global__ void k_to_f32(const double* __restrict__ in, long count, float* __restrict__ out) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < count) out[e] = (float)in[e];
+}
+
+// boundary rows F_b^T (column-major n x 2): left = f_L on v1 > 0 else K(x_0).V,
+// right = f_R on v1 < 0 else K(x_last).V
+__global__ void k_fb(const double* __restrict__ K, const double* __restrict__ V, int r, int nx,
+                     const double* __restrict__ fL, const double* __restrict__ fR, VGeo g,
+                     double* __restrict__ Fb) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.n) return;
+  double a = 0.0, b = 0.0;
+  for (int l = 0; l < r; ++l) {
+    const double v = V[(long)l * g.n + q];
+    a += K[(long)l * nx] * v;
+    b += K[(long)l * nx + nx - 1] * v;
+  }
+  const double v1 = g.v1(q);
+  Fb[q] = v1 > 0 ? fL[q] : a;
+  Fb[g.n + q] = v1 < 0 ? fR[q] : b;
+}
+
+// standard normal entries from a counter-based hash (splitmix64 + Box-Muller)
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void k_randn(double* out, long count, unsigned long long seed) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const unsigned long long h1 = mix64(seed ^ (2ull * e)), h2 = mix64(seed ^ (2ull * e + 1));
+  const double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+  const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+  out[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// small dense algebra (one block)
+// S2 = S1 + dt (Dp Ap^T + Dm Am^T - T C^T);  dS = S2 - S1
+__global__ void k_supdate(const double* S1, const double* Dp, const double* Dm, const double* T,
+                          const double* Ap, const double* Am, const double* C, int r, int P,
+                          double dt, double* S2, double* dS) {
+  for (int t = threadIdx.x; t < r * r; t += blockDim.x) {
+  const int i = t / r, j = t % r;
+  double s = 0.0;
+  for (int l = 0; l < r; ++l) s += Dp[i * r + l] * Ap[j * r + l] + Dm[i * r + l] * Am[j * r + l];
+  for (int p = 0; p < P; ++p) s -= T[i * P + p] * C[j * P + p];
+  S2[t] = S1[t] + dt * s;
+  dS[t] = dt * s;
+  }
+}
+
+__global__ void k_transpose(const double* A, int r, double* B) {
+  for (int t = threadIdx.x; t < r * r; t += blockDim.x) B[(t % r) * r + t / r] = A[t];
+}
+
+// out = A * B^T-style products on small matrices: out = Sx Shat Sv^T (r x r)
+__global__ void k_sq(const double* Sx, const double* Sh, const double* Sv, int r, double* out) {
+  for (int t = threadIdx.x; t < r * r; t += blockDim.x) {
+  const int i = t / r, j = t % r;
+  double s = 0.0;
+  for (int a = 0; a < r; ++a) {
+    double u = 0.0;
+    for (int b = 0; b < r; ++b) u += Sh[a * r + b] * Sv[j * r + b];
+    s += Sx[i * r + a] * u;
+  }
+  out[t] = s;
+  }
+}
+
+// err^2 from the pieces; sums written to res[0..5]
+__global__ void k_err(const double* dK, long nK, double dx, const double* dS, int r,
+                      const double* GdL, const double* kx, const double* lv, double* res) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (long e = t; e < nK; e += blockDim.x) s += dK[e] * dK[e];
+  red[t] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st) red[t] += red[t + st];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double a = dx * red[0];
+    double b = 0.0, c = 0.0, I = 0.0, II = 0.0, III = 0.0;
+    for (int e = 0; e < r * r; ++e) {
+      b += dS[e] * dS[e];
+      I += kx[e] * dS[e];
+      II += lv[e] * dS[e];
+      III += kx[e] * lv[e];
+    }
+    for (int i = 0; i < r; ++i) c += GdL[i * r + i];
+    res[0] = a + b + c + 2.0 * (I + II + III);
+    res[1] = a;
+    res[2] = b;
+    res[3] = c;
+  }
+}
+
+// <f^n, D> = sum_kl S[k][l] (A M B^T)[k][l],  M = U_perp Sig_perp W_perp^T
+// (one block, three r x r products in LDS; fixed summation order)
+__global__ __launch_bounds__(256) void k_fnD(const double* S, const double* A, const double* U,
+                                             const double* sig, const double* W, const double* B,
+                                             int r, int keep, double* res) {
+  __shared__ double M[64 * 64];
+  __shared__ double AM[64 * 64];
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  for (int e = t; e < r * r; e += blockDim.x) {
+    const int i = e / r, j = e % r;
+    double m = 0.0;
+    for (int q = keep; q < r; ++q) m += U[i * r + q] * sig[q] * W[j * r + q];
+    M[e] = m;
+  }
+  __syncthreads();
+  for (int e = t; e < r * r; e += blockDim.x) {
+    const int k = e / r, j = e % r;
+    double v = 0.0;
+    for (int i = 0; i < r; ++i) v += A[k * r + i] * M[i * r + j];
+    AM[e] = v;
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int e = t; e < r * r; e += blockDim.x) {
+    const int k = e / r, l = e % r;
+    double v = 0.0;
+    for (int j = 0; j < r; ++j) v += AM[k * r + j] * B[l * r + j];
+    part += S[e] * v;
+  }
+  red[t] = part;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st) red[t] += red[t + st];
+    __syncthreads();
+  }
+  if (t == 0) {
+    double sp2 = 0.0;
+    for (int j = keep; j < r; ++j) sp2 += sig[j] * sig[j];
+    res[0] = red[0];
+    res[1] = sp2;
+  }
+}
+
+__global__ void k_diag(const double* sig, int r, double* S, int lds) {
+  for (int t = threadIdx.x; t < r * r; t += blockDim.x) {
+    const int i = t / r, j = t % r;
+    S[i * lds + j] = (i == j) ? sig[i] : 0.0;
+  }
+}
+
+__global__ void k_copy_S(const double* src, int lds_src, int r, double* dst, int lds_dst) {
+  const int t = threadIdx.x + blockIdx.x * blockDim.x;
+  if (t >= r * r) return;
+  dst[(t / r) * lds_dst + t % r] = src[(t / r) * lds_src + t % r];
+}
+
+}  // namespace dk
+
+// ------------------------------------------------------------------ host --
+namespace {
+
+inline unsigned blocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+struct StepWork {
+  blr_ctx ctx;
+  hipStream_t s;
+  dk::VGeo g;
+  int nx, n;
+  double dx, dvd;
+  double* get(const char* name, size_t count) {
+    return (double*)ctx->buf(std::string("dlr.") + name, count * sizeof(double));
+  }
+};
+
+// G = scale * sum_q w(q) A_i B_j   (ra x rb row-major)
+template <typename TB>
+void vgram(StepWork& w, const double* A, int ra, const TB* B, int rb, int mode, double scale,
+           double* out) {
+  double* part = w.get("vgram.part", (size_t)dk::NCHUNK * ra * rb);
+  const dim3 grid(dk::NCHUNK, blocks(ra, dk::GT), blocks(rb, dk::GT));
+  timed_begin("dlr.vgram", (double)w.n * (ra + rb) * 8.0, w.s);
+  hipLaunchKernelGGL(dk::k_vgram<TB>, grid, dim3(256), 0, w.s, A, ra, (long)w.n, B, rb, (long)w.n,
+                     mode, w.g, part);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_vgram_finish, dim3(blocks((long)ra * rb, 256)), dim3(256), 0, w.s, part, ra,
+                     rb, scale, out);
+  BLR_CHECK_LAUNCH();
+  timed_end(w.s);
+}
+
+void d2h(blr_ctx ctx, void* host, const void* dev, size_t bytes) {
+  BLR_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  BLR_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+void validate_problem(const blr_problem* pb, const blr_state* st) {
+  require(pb && st, "null problem or state");
+  require(pb->nx >= 2 && pb->nx <= (1 << 20), "problem.nx must be in [2, 2^20]");
+  require(pb->x_hi > pb->x_lo, "problem.x_hi must exceed x_lo");
+  require(pb->f_left && pb->f_right, "null inflow boundary arrays");
+  validate_vgrid(pb->v);
+  require(st->X && st->S && st->V, "null state arrays");
+  require(st->r_cap >= 1 && st->r_cap <= 64, "state.r_cap must be in [1, 64]");
+  require(st->r >= 1 && st->r <= st->r_cap, "state.r must be in [1, r_cap]");
+}
+
+}  // namespace
+
+void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_params* sp,
+              blr_step_info* info) {
+  validate_problem(pb, st);
+  require(sp != nullptr, "null step params");
+  require(sp->dt > 0 && std::isfinite(sp->dt), "step.dt must be positive");
+  const int r_max = std::min(sp->r_max > 0 ? sp->r_max : st->r_cap, st->r_cap);
+  const int r_min = std::max(1, std::min(sp->r_min, r_max));
+  const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;
+  StepWork w{ctx, ctx->stream, {h.L, h.dv, h.N, h.d, h.n}, pb->nx, h.n,
+             (pb->x_hi - pb->x_lo) / pb->nx, std::pow(h.dv, h.d)};
+  hipStream_t s = w.s;
+  const int nx = w.nx, n = w.n;
+  const double dx = w.dx, dvd = w.dvd, dt = sp->dt;
+  blr_step_info inf{};
+  inf.r_in = st->r;
+  BLR_HIP(hipEventRecord(ctx->ev[0], s));
+
+  // working copies (rank up to r_cap); the caller's state is written only at the end
+  const int rc = st->r_cap;
+  double* Xw = w.get("Xw", (size_t)rc * nx);
+  double* Vw = w.get("Vw", (size_t)rc * n);
+  double* Sw = w.get("Sw", (size_t)rc * rc);
+  int r = st->r;
+  BLR_HIP(hipMemcpyAsync(Xw, st->X, (size_t)r * nx * 8, hipMemcpyDeviceToDevice, s));
+  BLR_HIP(hipMemcpyAsync(Vw, st->V, (size_t)r * n * 8, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r * r, 256)), dim3(256), 0, s, st->S, rc, r, Sw, r);
+  BLR_CHECK_LAUNCH();
+
+  // velocity-side boundary integrals of the current basis
+  double* ginL = w.get("ginL", 64);
+  double* ginR = w.get("ginR", 64);
+  double* MoL = w.get("MoL", 64 * 64);
+  double* MoR = w.get("MoR", 64 * 64);
+  double* gh = w.get("ghost", 128);
+  double* K = w.get("K", (size_t)rc * nx);
+  auto boundary_integrals = [&](const double* Vb, int rr) {
+    vgram<double>(w, Vb, rr, pb->f_left, 1, dk::W_IN_LEFT, dvd, ginL);
+    vgram<double>(w, Vb, rr, pb->f_right, 1, dk::W_IN_RIGHT, dvd, ginR);
+    vgram<double>(w, Vb, rr, Vb, rr, dk::W_OUT_LEFT, dvd, MoL);
+    vgram<double>(w, Vb, rr, Vb, rr, dk::W_OUT_RIGHT, dvd, MoR);
+  };
+
+  // ---------------------------------------------------------- add basis
+  if ((sp->flags & BLR_STEP_ADD) && r < r_max) {
+    hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, Xw, r, nx, Sw, r,
+                       K);
+    BLR_CHECK_LAUNCH();
+    double* Fb = w.get("Fb", (size_t)2 * n);
+    hipLaunchKernelGGL(dk::k_fb, dim3(blocks(n, 256)), dim3(256), 0, s, K, Vw, r, nx, pb->f_left,
+                       pb->f_right, w.g, Fb);
+    BLR_CHECK_LAUNCH();
+    double* QF = w.get("QF", (size_t)2 * n);
+    double* RF = w.get("RF", 4);
+    tsqr(ctx, Fb, n, n, 2, QF, n, RF, "qr.fb");
+    // F_b = R_F^T Q_F^T;  R_F^T = U Sig W^T  ->  right singular vectors Q_F W
+    double* RFt = w.get("RFt", 4);
+    hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(64), 0, s, RF, 2, RFt);
+    BLR_CHECK_LAUNCH();
+    double* Ub = w.get("Ub", 4);
+    double* sb = w.get("sb", 2);
+    double* Wb = w.get("Wb", 4);
+    svd_small(ctx, RFt, 2, Ub, sb, Wb);
+    double sbh[2];
+    d2h(ctx, sbh, sb, sizeof(sbh));
+    int rb = 0;
+    for (int k = 0; k < 2; ++k) rb += sbh[k] > sp->add_tol ? 1 : 0;
+    rb = std::min(rb, r_max - r);
+    if (rb > 0) {
+      // V^ = [V; (Q_F W)^T[:rb]],  X^ = [X, X_h],  S^ = blockdiag(S, 0)
+      hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), rb), dim3(256), 0, s, QF, 2, (long)n,
+                         Wb, 2, rb, 1.0, Vw + (size_t)r * n, (long)n);
+      BLR_CHECK_LAUNCH();
+      hipLaunchKernelGGL(dk::k_randn, dim3(blocks((long)rb * nx, 256)), dim3(256), 0, s,
+                         Xw + (size_t)r * nx, (long)rb * nx,
+                         (unsigned long long)(st->seed * 0x100000001B3ull + (uint64_t)st->step));
+      BLR_CHECK_LAUNCH();
+      const int rk = r + rb;
+      double* Shat = w.get("Shat", (size_t)rk * rk);
+      fill<double>(s, Shat, (long)rk * rk, 0.0);
+      hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r * r, 256)), dim3(256), 0, s, Sw, r, r, Shat, rk);
+      BLR_CHECK_LAUNCH();
+      double* tmpX = w.get("tmpX", (size_t)rk * nx);
+      double* tmpV = w.get("tmpV", (size_t)rk * n);
+      double* Sx = w.get("Sx", (size_t)rk * rk);
+      double* Sv = w.get("Sv", (size_t)rk * rk);
+      hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)rk * nx, 256)), dim3(256), 0, s, Xw,
+                         (long)rk * nx, std::sqrt(dx), tmpX);
+      BLR_CHECK_LAUNCH();
+      tsqr(ctx, tmpX, nx, nx, rk, Xw, nx, Sx, "qr.x");
+      hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)rk * nx, 256)), dim3(256), 0, s, Xw,
+                         (long)rk * nx, 1.0 / std::sqrt(dx), Xw);
+      BLR_CHECK_LAUNCH();
+      hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)rk * n, 256)), dim3(256), 0, s, Vw,
+                         (long)rk * n, std::sqrt(dvd), tmpV);
+      BLR_CHECK_LAUNCH();
+      tsqr(ctx, tmpV, n, n, rk, Vw, n, Sv, "qr.v");
+      hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)rk * n, 256)), dim3(256), 0, s, Vw,
+                         (long)rk * n, 1.0 / std::sqrt(dvd), Vw);
+      BLR_CHECK_LAUNCH();
+      hipLaunchKernelGGL(dk::k_sq, dim3(1), dim3(1024), 0, s, Sx, Shat, Sv, rk, Sw);
+      BLR_CHECK_LAUNCH();
+      r = rk;
+      inf.r_added = rb;
+    }
+  }
+
+  // ------------------------------------------------------- collisions
+  const int P = r * (r + 1) / 2;
+  std::vector<int> pidx(2 * P);
+  std::vector<int32_t> pairs(2 * P);
+  {
+    int p = 0;
+    for (int m = 0; m < r; ++m)
+      for (int nn = m; nn < r; ++nn, ++p) {
+        pidx[p] = m;
+        pidx[P + p] = nn;
+        pairs[2 * p] = m;
+        pairs[2 * p + 1] = nn;
+      }
+  }
+  int* dpidx = (int*)ctx->upload("dlr.pidx", pidx.data(), pidx.size() * sizeof(int));
+  const bool fp64c = (sp->flags & BLR_STEP_FP64_COLLISION) != 0;
+  void* Qs;
+  BLR_HIP(hipEventRecord(ctx->ev[1], s));
+  if (fp64c) {
+    Qs = w.get("Q64", (size_t)P * n);
+    collision_pairs(ctx, pb->v, BLR_FP64, Vw, r, pairs.data(), P, Qs);
+  } else {
+    float* V32 = (float*)ctx->buf("dlr.V32", (size_t)r * n * sizeof(float));
+    hipLaunchKernelGGL(dk::k_to_f32, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, Vw, (long)r * n,
+                       V32);
+    BLR_CHECK_LAUNCH();
+    Qs = ctx->buf("dlr.Q32", (size_t)P * n * sizeof(float));
+    collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
+  }
+  BLR_HIP(hipEventRecord(ctx->ev[2], s));
+
+  // velocity-side contractions
+  double* Ap = w.get("Ap", (size_t)r * r);
+  double* Am = w.get("Am", (size_t)r * r);
+  double* Cj = w.get("C", (size_t)r * P);
+  vgram<double>(w, Vw, r, Vw, r, dk::W_VPLUS, dvd, Ap);
+  vgram<double>(w, Vw, r, Vw, r, dk::W_VMINUS, dvd, Am);
+  if (fp64c)
+    vgram<double>(w, Vw, r, (const double*)Qs, P, dk::W_ONE, dvd, Cj);
+  else
+    vgram<float>(w, Vw, r, (const float*)Qs, P, dk::W_ONE, dvd, Cj);
+  boundary_integrals(Vw, r);
+
+  // ---------------------------------------------------------- K-step
+  double* K1 = w.get("K1", (size_t)r * nx);
+  double* dK = w.get("dK", (size_t)r * nx);
+  double* X1 = w.get("X1", (size_t)r * nx);
+  double* S1 = w.get("S1", (size_t)r * r);
+  double* tmpK = w.get("tmpK", (size_t)r * nx);
+  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, Xw, r, nx, Sw, r, K);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_kstep, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, K, gh, r, nx, dx,
+                     dt, Ap, Am, Cj, P, dpidx, dpidx + P, K1, dK);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, K1,
+                     (long)r * nx, std::sqrt(dx), tmpK);
+  BLR_CHECK_LAUNCH();
+  tsqr(ctx, tmpK, nx, nx, r, X1, nx, S1, "qr.k");
+  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, X1,
+                     (long)r * nx, 1.0 / std::sqrt(dx), X1);
+  BLR_CHECK_LAUNCH();
+
+  // ---------------------------------------------------------- S-step
+  const int ncols = 2 * r + P;
+  double* S2 = w.get("S2", (size_t)r * r);
+  double* dS = w.get("dS", (size_t)r * r);
+  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, X1, r, nx, S1, r, K);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
+  BLR_CHECK_LAUNCH();
+  double* Dp = w.get("Dp", (size_t)r * r);
+  double* Dm = w.get("Dm", (size_t)r * r);
+  double* T = w.get("T", (size_t)r * P);
+  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 256)), dim3(256), 0, s, X1, r, nx,
+                     dx, K, gh, P, dpidx, dpidx + P, nullptr, 0, 0, nullptr, ncols, Dp, Dm, T);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_supdate, dim3(1), dim3(1024), 0, s, S1, Dp, Dm, T, Ap, Am, Cj, r, P, dt, S2,
+                     dS);
+  BLR_CHECK_LAUNCH();
+
+  // ---------------------------------------------------------- L-step
+  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, X1, r, nx, S2, r, K);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 256)), dim3(256), 0, s, X1, r, nx,
+                     dx, K, gh, P, dpidx, dpidx + P, nullptr, 0, 0, nullptr, ncols, Dp, Dm, T);
+  BLR_CHECK_LAUNCH();
+  double* L1 = w.get("L1", (size_t)r * n);
+  double* dL = w.get("dL", (size_t)r * n);
+  {
+    const dim3 grid(blocks(n, 256), (r + 7) / 8);
+    timed_begin("dlr.lstep", (double)n * (r + P + 2 * r) * 8.0, s);
+    if (fp64c)
+      hipLaunchKernelGGL(dk::k_lstep<double>, grid, dim3(256), 0, s, Vw, r, n, S2, Dp, Dm, T,
+                         (const double*)Qs, P, dt, w.g, L1, dL);
+    else
+      hipLaunchKernelGGL(dk::k_lstep<float>, grid, dim3(256), 0, s, Vw, r, n, S2, Dp, Dm, T,
+                         (const float*)Qs, P, dt, w.g, L1, dL);
+    BLR_CHECK_LAUNCH();
+    timed_end(s);
+  }
+  double* V1 = w.get("V1", (size_t)r * n);
+  double* tmpL = w.get("tmpL", (size_t)r * n);
+  double* Rl = w.get("Rl", (size_t)r * r);
+  double* Snew = w.get("Snew", (size_t)r * r);
+  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, L1,
+                     (long)r * n, std::sqrt(dvd), tmpL);
+  BLR_CHECK_LAUNCH();
+  tsqr(ctx, tmpL, n, n, r, V1, n, Rl, "qr.l");
+  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, V1,
+                     (long)r * n, 1.0 / std::sqrt(dvd), V1);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(1024), 0, s, Rl, r, Snew);
+  BLR_CHECK_LAUNCH();
+
+  // --------------------------------------------------------- residual
+  double* kx = w.get("kx", (size_t)r * r);
+  double* lv = w.get("lv", (size_t)r * r);
+  double* GdL = w.get("GdL", (size_t)r * r);
+  double* res = w.get("res", 8);
+  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, X1, r, nx, dx,
+                     nullptr, nullptr, 0, nullptr, nullptr, dK, r, 1, kx, r, nullptr, nullptr, nullptr);
+  BLR_CHECK_LAUNCH();
+  vgram<double>(w, dL, r, Vw, r, dk::W_ONE, dvd, lv);
+  vgram<double>(w, dL, r, dL, r, dk::W_ONE, dvd, GdL);
+  hipLaunchKernelGGL(dk::k_err, dim3(1), dim3(256), 0, s, dK, (long)r * nx, dx, dS, r, GdL, kx, lv, res);
+  BLR_CHECK_LAUNCH();
+
+  // ------------------------------------------------------------- drop
+  double* Xo = X1;
+  double* Vo = V1;
+  int r_out = r;
+  double resh[4];
+  if (sp->flags & BLR_STEP_DROP) {
+    double* U = w.get("U", (size_t)r * r);
+    double* sg = w.get("sig", (size_t)r);
+    double* Wm = w.get("W", (size_t)r * r);
+    svd_small(ctx, Snew, r, U, sg, Wm);
+    // err_ada needs A = <X^n_k, X1_i>_x and B = <V^n_l, V1_j>_v
+    double* Aad = w.get("Aad", (size_t)r * r);
+    double* Bad = w.get("Bad", (size_t)r * r);
+    hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, Xw, r, nx, dx,
+                       nullptr, nullptr, 0, nullptr, nullptr, X1, r, 1, Aad, r, nullptr, nullptr,
+                       nullptr);
+    BLR_CHECK_LAUNCH();
+    vgram<double>(w, Vw, r, V1, r, dk::W_ONE, dvd, Bad);
+    std::vector<double> sgh(r);
+    BLR_HIP(hipMemcpyAsync(resh, res, sizeof(resh), hipMemcpyDeviceToHost, s));
+    d2h(ctx, sgh.data(), sg, r * sizeof(double));
+    const double err = std::sqrt(std::max(resh[0], 0.0));
+    require(std::isfinite(err), "non-finite residual", BLR_ERR_NUMERIC);
+    for (double v : sgh) require(std::isfinite(v), "non-finite singular value", BLR_ERR_NUMERIC);
+    const double tol = sp->c_drop * err;
+    int keep = 0;
+    for (double v : sgh) keep += v >= tol ? 1 : 0;
+    keep = std::max(std::min(keep, r_max), std::min(r_min, r));
+    double* fnd = w.get("fnd", 2);
+    hipLaunchKernelGGL(dk::k_fnD, dim3(1), dim3(256), 0, s, Sw, Aad, U, sg, Wm, Bad, r, keep, fnd);
+    BLR_CHECK_LAUNCH();
+    double fh[2];
+    d2h(ctx, fh, fnd, sizeof(fh));
+    inf.err = err;
+    inf.drop_tol = tol;
+    inf.err_ada = std::sqrt(std::max(err * err - fh[1] + 2.0 * fh[0], 0.0));
+    // rotate and truncate
+    double* Xd = w.get("Xd", (size_t)r * nx);
+    double* Vd = w.get("Vd", (size_t)r * n);
+    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(nx, 256), keep), dim3(256), 0, s, X1, r, (long)nx, U,
+                       r, keep, 1.0, Xd, (long)nx);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), keep), dim3(256), 0, s, V1, r, (long)n, Wm,
+                       r, keep, 1.0, Vd, (long)n);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_diag, dim3(1), dim3(1024), 0, s, sg, keep, Snew, keep);
+    BLR_CHECK_LAUNCH();
+    Xo = Xd;
+    Vo = Vd;
+    r_out = keep;
+  } else {
+    d2h(ctx, resh, res, sizeof(resh));
+    const double err = std::sqrt(std::max(resh[0], 0.0));
+    require(std::isfinite(err), "non-finite residual", BLR_ERR_NUMERIC);
+    inf.err = err;
+    inf.err_ada = err;
+  }
+  // ------------------------------------------------------------ commit
+  BLR_HIP(hipMemcpyAsync(st->X, Xo, (size_t)r_out * nx * 8, hipMemcpyDeviceToDevice, s));
+  BLR_HIP(hipMemcpyAsync(st->V, Vo, (size_t)r_out * n * 8, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r_out * r_out, 256)), dim3(256), 0, s, Snew, r_out,
+                     r_out, st->S, rc);
+  BLR_CHECK_LAUNCH();
+  BLR_HIP(hipEventRecord(ctx->ev[3], s));
+  BLR_HIP(hipEventSynchronize(ctx->ev[3]));
+  float ms = 0.f;
+  BLR_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
+  inf.ms_step = ms;
+  BLR_HIP(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+  inf.ms_collision = ms;
+  inf.r_out = r_out;
+  st->r = r_out;
+  st->step += 1;
+  if (info) *info = inf;
+}
+
+// Truncated SVD of f0 (nx x n, row-major) via the weighted Gram matrix
+// G = w f0 f0^T (nx x nx) is not used: the factors come from a QR of
+// sqrt(w) f0^T (n x nx) and an SVD of its nx x nx R factor, which needs
+// nx <= 64.  Larger nx is rejected (initial states are then built by the
+// caller).
+void state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0, int r, blr_state* st) {
+  require(pb && st && f0, "null argument");
+  validate_vgrid(pb->v);
+  require(st->r_cap >= r && r >= 1, "r must be in [1, r_cap]");
+  require(pb->nx <= 64, "state_from_full: nx must be <= 64", BLR_ERR_UNSUPPORTED);
+  const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;
+  const int nx = pb->nx, n = h.n;
+  const double dx = (pb->x_hi - pb->x_lo) / nx, dvd = std::pow(h.dv, h.d);
+  hipStream_t s = ctx->stream;
+  auto get = [&](const char* nm, size_t c) {
+    return (double*)ctx->buf(std::string("sff.") + nm, c * sizeof(double));
+  };
+  // f0 row-major (nx x n) is column-major (n x nx) with ld n
+  double* A = get("A", (size_t)nx * n);
+  double* Qf = get("Q", (size_t)nx * n);
+  double* Rf = get("R", (size_t)nx * nx);
+  double* Rt = get("Rt", (size_t)nx * nx);
+  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)nx * n, 256)), dim3(256), 0, s, f0,
+                     (long)nx * n, std::sqrt(dx * dvd), A);
+  BLR_CHECK_LAUNCH();
+  tsqr(ctx, A, n, n, nx, Qf, n, Rf, "qr.sff");
+  // sqrt(w) f0 = R^T Q^T ; R^T = U Sig W^T -> left factors U, right Q W
+  hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(1024), 0, s, Rf, nx, Rt);
+  BLR_CHECK_LAUNCH();
+  double* U = get("U", (size_t)nx * nx);
+  double* sg = get("sig", nx);
+  double* W = get("W", (size_t)nx * nx);
+  svd_small(ctx, Rt, nx, U, sg, W);
+  // X_i = U[:, i] / sqrt(dx), V_i = (Q W)[:, i] / sqrt(dvd), S = diag(sig)
+  // U row-major (nx x nx): column i over rows x = rows combination of the identity
+  double* I = get("I", (size_t)nx * nx);
+  std::vector<double> eye((size_t)nx * nx, 0.0);
+  for (int i = 0; i < nx; ++i) eye[(size_t)i * nx + i] = 1.0;
+  BLR_HIP(hipMemcpyAsync(I, eye.data(), eye.size() * 8, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(nx, 256), r), dim3(256), 0, s, I, nx, (long)nx, U,
+                     nx, r, 1.0 / std::sqrt(dx), st->X, (long)nx);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), r), dim3(256), 0, s, Qf, nx, (long)n, W, nx,
+                     r, 1.0 / std::sqrt(dvd), st->V, (long)n);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_diag, dim3(1), dim3(1024), 0, s, sg, r, st->S, st->r_cap);
+  BLR_CHECK_LAUNCH();
+  BLR_HIP(hipStreamSynchronize(s));
+  st->r = r;
+}
+
+}  // namespace blr
+
+// ------------------------------------------------------------------ C ABI --
+template <class F>
+static blr_status guarded_dlr(blr_ctx ctx, F&& f) {
+  if (!ctx) return BLR_ERR_ARG;
+  ctx->err.clear();
+  try {
+    BLR_HIP(hipSetDevice(ctx->device));
+    f();
+    return BLR_OK;
+  } catch (const blr::Error& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return BLR_ERR_HIP;
+  }
+}
 
 extern "C" {
-blr_status blr_state_from_full(blr_ctx ctx, const blr_problem*, const double*, int32_t, blr_state*) {
-  if (ctx) ctx->err = "blr_state_from_full: not built";
-  return BLR_ERR_UNSUPPORTED;
+
+blr_status blr_state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0, int32_t r,
+                               blr_state* state) {
+  return guarded_dlr(ctx, [&] { blr::state_from_full(ctx, pb, f0, r, state); });
 }
-blr_status blr_dlr_step(blr_ctx ctx, const blr_problem*, blr_state*, const blr_step_params*,
-                        blr_step_info*) {
-  if (ctx) ctx->err = "blr_dlr_step: not built";
-  return BLR_ERR_UNSUPPORTED;
+
+blr_status blr_dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* state,
+                        const blr_step_params* sp, blr_step_info* info) {
+  return guarded_dlr(ctx, [&] { blr::dlr_step(ctx, pb, state, sp, info); });
 }
-blr_status blr_steady_solve(blr_ctx ctx, const blr_problem*, blr_state*, const blr_solve_params*,
-                            blr_solve_info*) {
-  if (ctx) ctx->err = "blr_steady_solve: not built";
-  return BLR_ERR_UNSUPPORTED;
+
+blr_status blr_steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state,
+                            const blr_solve_params* p, blr_solve_info* info) {
+  blr_solve_info out{};
+  const blr_status rc = guarded_dlr(ctx, [&] {
+    blr::require(p != nullptr, "null solve params");
+    blr::require(p->max_steps >= 1, "max_steps must be >= 1");
+    blr::require(p->res_tol >= 0, "res_tol must be >= 0");
+    hipEvent_t e0, e1;
+    BLR_HIP(hipEventCreate(&e0));
+    BLR_HIP(hipEventCreate(&e1));
+    BLR_HIP(hipEventRecord(e0, ctx->stream));
+    for (int64_t k = 0; k < p->max_steps; ++k) {
+      blr_step_info si{};
+      blr::dlr_step(ctx, pb, state, &p->step, &si);
+      out.steps = k + 1;
+      out.err_ada = si.err_ada;
+      out.r = state->r;
+      if (si.err_ada <= p->res_tol) {
+        out.converged = 1;
+        break;
+      }
+    }
+    BLR_HIP(hipEventRecord(e1, ctx->stream));
+    BLR_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BLR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    out.ms_wall = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  });
+  if (info) *info = out;
+  if (rc != BLR_OK) return rc;
+  return out.converged ? BLR_OK : BLR_ERR_NOT_CONVERGED;
 }
-}
+
+}  // extern "C"

@@ -1,2 +1,361 @@
-// FP64 dense linear algebra for the low-rank step (placeholder).
-#include "internal.hpp"
+// FP64 dense linear algebra of the low-rank step.
+//
+//   tsqr   Householder QR of a tall-skinny column-major matrix (rows >= 1,
+//          1 <= r <= 64) as a reduction tree: blocks of 256 rows are
+//          factorised in LDS by one workgroup each (rows padded with zeros to
+//          at least r), their R factors are stacked and factorised again until
+//          one block remains; Q is formed top-down by applying each level's
+//          reflectors to the next level's Q block.  The sign of every row of R
+//          is chosen so that diag(R) >= 0 (the top-level Q starts from
+//          D = sign(diag R) instead of the identity).  Householder reflections
+//          stay orthogonal when the matrix is rank deficient, which the basis-
+//          augmentation step produces on purpose (zero block of S).
+//   svd    one-sided Jacobi SVD of an r x r matrix (one workgroup), singular
+//          values in descending order, zero columns of U completed to an
+//          orthonormal set.
+#include <cmath>
+#include <cstring>
+
+#include "linalg.hpp"
+
+namespace blr {
+namespace la {
+
+constexpr int MB = 256;  // rows per QR block (= threads per workgroup)
+
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  // deterministic: wave shuffles, then a fixed-order sum of the 4 wave totals
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+// Factor block b of a column-major matrix A (rows x r, leading dim lda).
+// Writes the Householder vectors (unit diagonal implied) into Y (same layout,
+// leading dim ldy = padded rows), tau[b*r + k], and R into Rst (stacked
+// column-major, leading dim nb*r) rows [b*r, b*r + r).
+template <int RM>
+__global__ __launch_bounds__(MB) void k_qr_block(const double* __restrict__ A, long lda, long rows,
+                                                 int r, double* __restrict__ Y, long ldy,
+                                                 double* __restrict__ tau,
+                                                 double* __restrict__ Rst, long ldr) {
+  __shared__ double T[MB * RM];
+  __shared__ double red[8];
+  __shared__ double sh[RM + 4];
+  const int b = blockIdx.x;
+  const int i = threadIdx.x;
+  const long row = (long)b * MB + i;
+  const int m = (int)max((long)r, min((long)MB, rows - (long)b * MB));  // active rows (>= r)
+  for (int c = 0; c < r; ++c) T[i * RM + c] = (i < m && row < rows) ? A[c * lda + row] : 0.0;
+  __syncthreads();
+  for (int k = 0; k < r; ++k) {
+    // x = T[k:m, k]
+    const double xi = (i > k && i < m) ? T[i * RM + k] : 0.0;
+    const double tail = block_sum(xi * xi, red);
+    const double x0 = T[k * RM + k];
+    double beta, tk, scale;
+    if (tail == 0.0) {
+      tk = 0.0;
+      beta = x0;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(x0 * x0 + tail);
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      tk = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    __syncthreads();
+    if (i > k && i < m) T[i * RM + k] *= scale;
+    if (i == k) T[k * RM + k] = beta;
+    __syncthreads();
+    // apply H = I - tau v v^T to columns k+1..r-1 (v_k = 1)
+    for (int c = k + 1; c < r; ++c) {
+      const double vi = (i > k && i < m) ? T[i * RM + k] : 0.0;
+      const double part = vi * T[i * RM + c];
+      double wsum = block_sum(part, red) + T[k * RM + c];
+      if (i == 0) sh[0] = wsum;
+      __syncthreads();
+      wsum = sh[0];
+      if (i > k && i < m) T[i * RM + c] -= tk * wsum * vi;
+      __syncthreads();
+      if (i == k) T[k * RM + c] -= tk * wsum;
+      __syncthreads();
+    }
+    if (i == 0) tau[(long)b * r + k] = tk;
+  }
+  __syncthreads();
+  // Householder vectors and R out
+  for (int c = 0; c < r; ++c) {
+    Y[c * ldy + (long)b * MB + i] = (i > c && i < m) ? T[i * RM + c] : 0.0;
+    if (i < r) Rst[c * ldr + (long)b * r + i] = (i <= c) ? T[i * RM + c] : 0.0;
+  }
+}
+
+// Q block b = H_0 .. H_{r-1} [C_b; 0], C_b = rows [b*r, b*r+r) of Cst (col-major, ldc).
+template <int RM>
+__global__ __launch_bounds__(MB) void k_qr_apply(const double* __restrict__ Y, long ldy, long rows,
+                                                 int r, const double* __restrict__ tau,
+                                                 const double* __restrict__ Cst, long ldc,
+                                                 double* __restrict__ Q, long ldq) {
+  __shared__ double T[MB * RM];
+  __shared__ double red[8];
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  const int i = threadIdx.x;
+  const long row = (long)b * MB + i;
+  const int m = (int)max((long)r, min((long)MB, rows - (long)b * MB));
+  for (int c = 0; c < r; ++c) T[i * RM + c] = (i < r) ? Cst[c * ldc + (long)b * r + i] : 0.0;
+  __syncthreads();
+  for (int k = r - 1; k >= 0; --k) {
+    const double tk = tau[(long)b * r + k];
+    if (tk == 0.0) continue;  // uniform across the block
+    const double vi = (i > k && i < m) ? Y[k * ldy + (long)b * MB + i] : (i == k ? 1.0 : 0.0);
+    for (int c = 0; c < r; ++c) {
+      double wsum = block_sum(vi * T[i * RM + c], red);
+      if (i == 0) sh[0] = wsum;
+      __syncthreads();
+      wsum = sh[0];
+      T[i * RM + c] -= tk * wsum * vi;
+      __syncthreads();
+    }
+  }
+  if (i < m && row < rows)
+    for (int c = 0; c < r; ++c) Q[c * ldq + row] = T[i * RM + c];
+}
+
+// final sign fix: D = sign(diag R) (0 -> +1); R <- D R; C <- D (the top-level
+// Q seed, an r x r col-major matrix with leading dimension ldc)
+__global__ void k_qr_sign(double* R, long ldr, int r, double* C, long ldc) {
+  const int i = threadIdx.x;
+  if (i >= r) return;
+  const double s = R[i * ldr + i] < 0.0 ? -1.0 : 1.0;
+  for (int c = 0; c < r; ++c) {
+    R[c * ldr + i] *= s;
+    C[c * ldc + i] = (c == i) ? s : 0.0;
+  }
+}
+
+__global__ void k_copy_R(const double* Rst, long ldr, int r, double* R) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r * r) return;
+  const int i = t % r, c = t / r;
+  R[i * r + c] = Rst[c * ldr + i];  // row-major out
+}
+
+// ------------------------------------------------------------------ SVD --
+// One-sided Jacobi on the columns of B = A (r x r row-major): B W = U Sigma.
+__global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A, int r,
+                                                   double* __restrict__ U, double* __restrict__ sig,
+                                                   double* __restrict__ W, int sweeps) {
+  __shared__ double B[64 * 64];  // column-major: B[c*64 + i]
+  __shared__ double V[64 * 64];
+  __shared__ double nrm[64];
+  __shared__ int order[64];
+  __shared__ int rot_any;
+  const int t = threadIdx.x;
+  for (int c = 0; c < r; ++c)
+    if (t < r) {
+      B[c * 64 + t] = A[t * r + c];
+      V[c * 64 + t] = (t == c) ? 1.0 : 0.0;
+    }
+  __syncthreads();
+  const int rr = (r % 2) ? r + 1 : r;  // round-robin with a dummy column if odd
+  for (int sw = 0; sw < sweeps; ++sw) {
+    if (t == 0) rot_any = 0;
+    __syncthreads();
+    for (int round = 0; round < rr - 1; ++round) {
+      // pair t: (p, q) from the circle method
+      if (t < rr / 2) {
+        int p, q;
+        if (t == 0) {
+          p = rr - 1;
+          q = round;
+        } else {
+          p = (round + t) % (rr - 1);
+          q = (round - t + rr - 1) % (rr - 1);
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q < r) {
+          double al = 0, be = 0, ga = 0;
+          for (int i = 0; i < r; ++i) {
+            const double x = B[p * 64 + i], y = B[q * 64 + i];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
+          if (fabs(ga) > 1e-300 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+            for (int i = 0; i < r; ++i) {
+              const double x = B[p * 64 + i], y = B[q * 64 + i];
+              B[p * 64 + i] = c * x - s * y;
+              B[q * 64 + i] = s * x + c * y;
+              const double vx = V[p * 64 + i], vy = V[q * 64 + i];
+              V[p * 64 + i] = c * vx - s * vy;
+              V[q * 64 + i] = s * vx + c * vy;
+            }
+            rot_any = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!rot_any) break;
+    __syncthreads();
+  }
+  if (t < r) {
+    double s = 0;
+    for (int i = 0; i < r; ++i) s += B[t * 64 + i] * B[t * 64 + i];
+    nrm[t] = sqrt(s);
+  }
+  __syncthreads();
+  if (t == 0) {  // stable selection sort, descending
+    for (int i = 0; i < r; ++i) order[i] = i;
+    for (int i = 0; i < r; ++i) {
+      int best = i;
+      for (int j = i + 1; j < r; ++j)
+        if (nrm[order[j]] > nrm[order[best]]) best = j;
+      const int tmp = order[i];
+      order[i] = order[best];
+      order[best] = tmp;
+    }
+  }
+  __syncthreads();
+  // U columns (normalised), W columns, sigma; row-major outputs
+  if (t < r) {
+    const int src = order[t];
+    const double s = nrm[src];
+    sig[t] = s;
+    for (int i = 0; i < r; ++i) {
+      U[i * r + t] = s > 0 ? B[src * 64 + i] / s : 0.0;
+      W[i * r + t] = V[src * 64 + i];
+    }
+  }
+  __syncthreads();
+  // complete U where sigma underflows (tiny or zero columns)
+  if (t == 0) {
+    const double tiny = 1e-300;
+    for (int j = 0; j < r; ++j) {
+      if (sig[j] > tiny && sig[j] > 1e-14 * sig[0]) continue;
+      for (int e = 0; e < r; ++e) {
+        double v[64];
+        for (int i = 0; i < r; ++i) v[i] = (i == e) ? 1.0 : 0.0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int k = 0; k < r; ++k) {
+            if (k == j) continue;
+            if (k > j && !(sig[k] > tiny && sig[k] > 1e-14 * sig[0])) continue;
+            double d = 0;
+            for (int i = 0; i < r; ++i) d += U[i * r + k] * v[i];
+            for (int i = 0; i < r; ++i) v[i] -= d * U[i * r + k];
+          }
+        double nn = 0;
+        for (int i = 0; i < r; ++i) nn += v[i] * v[i];
+        nn = sqrt(nn);
+        if (nn > 0.5) {
+          for (int i = 0; i < r; ++i) U[i * r + j] = v[i] / nn;
+          break;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace la
+
+// ------------------------------------------------------------------- host --
+void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, long ldq,
+          double* R_rowmajor, const std::string& tag) {
+  require(r >= 1 && r <= 64, "tsqr: r must be in [1, 64]");
+  require(rows >= 1, "tsqr: rows must be >= 1");
+  hipStream_t s = ctx->stream;
+  struct Level {
+    const double* A;
+    long lda, rows;
+    int nb;
+    double *Y, *tau, *Rst;
+    long ldy, ldr;
+  };
+  std::vector<Level> lv;
+  const double* cur = A;
+  long ld = lda, rws = rows;
+  int depth = 0;
+  while (true) {
+    Level L;
+    L.A = cur;
+    L.lda = ld;
+    L.rows = rws;
+    L.nb = (int)((rws + la::MB - 1) / la::MB);
+    L.ldy = (long)L.nb * la::MB;
+    L.ldr = (long)L.nb * r;
+    const std::string t = tag + ".l" + std::to_string(depth);
+    L.Y = (double*)ctx->buf(t + ".Y", (size_t)L.ldy * r * sizeof(double));
+    L.tau = (double*)ctx->buf(t + ".tau", (size_t)L.nb * r * sizeof(double));
+    L.Rst = (double*)ctx->buf(t + ".R", (size_t)L.ldr * r * sizeof(double));
+    if (r <= 16)
+      hipLaunchKernelGGL(la::k_qr_block<16>, dim3(L.nb), dim3(la::MB), 0, s, L.A, L.lda, L.rows, r,
+                         L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+    else
+      hipLaunchKernelGGL(la::k_qr_block<64>, dim3(L.nb), dim3(la::MB), 0, s, L.A, L.lda, L.rows, r,
+                         L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+    BLR_CHECK_LAUNCH();
+    lv.push_back(L);
+    if (L.nb == 1) break;
+    cur = L.Rst;
+    ld = L.ldr;
+    rws = L.ldr;
+    ++depth;
+    require(depth < 16, "tsqr: too many levels");
+  }
+  // top: sign fix, seed C = D
+  Level& top = lv.back();
+  double* C = (double*)ctx->buf(tag + ".C", (size_t)r * r * sizeof(double));
+  hipLaunchKernelGGL(la::k_qr_sign, dim3(1), dim3(64), 0, s, top.Rst, top.ldr, r, C, (long)r);
+  BLR_CHECK_LAUNCH();
+  if (R_rowmajor) {
+    hipLaunchKernelGGL(la::k_copy_R, dim3((r * r + 255) / 256), dim3(256), 0, s, top.Rst, top.ldr, r,
+                       R_rowmajor);
+    BLR_CHECK_LAUNCH();
+  }
+  if (!Q) return;
+  // down the tree
+  const double* Cst = C;
+  long ldc = r;
+  for (int l = (int)lv.size() - 1; l >= 0; --l) {
+    Level& L = lv[l];
+    double* out;
+    long ldo;
+    if (l == 0) {
+      out = Q;
+      ldo = ldq;
+    } else {
+      out = (double*)ctx->buf(tag + ".q" + std::to_string(l), (size_t)L.rows * r * sizeof(double));
+      ldo = L.rows;
+    }
+    if (r <= 16)
+      hipLaunchKernelGGL(la::k_qr_apply<16>, dim3(L.nb), dim3(la::MB), 0, s, L.Y, L.ldy, L.rows, r,
+                         L.tau, Cst, ldc, out, ldo);
+    else
+      hipLaunchKernelGGL(la::k_qr_apply<64>, dim3(L.nb), dim3(la::MB), 0, s, L.Y, L.ldy, L.rows, r,
+                         L.tau, Cst, ldc, out, ldo);
+    BLR_CHECK_LAUNCH();
+    Cst = out;
+    ldc = ldo;
+  }
+}
+
+void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W) {
+  require(r >= 1 && r <= 64, "svd: r must be in [1, 64]");
+  hipLaunchKernelGGL(la::k_svd_jacobi, dim3(1), dim3(64), 0, ctx->stream, A, r, U, sig, W, 40);
+  BLR_CHECK_LAUNCH();
+}
+
+}  // namespace blr

@@ -1,0 +1,170 @@
+"""GPU parity of blr_dlr_step / blr_steady_solve against the oracle's step.
+
+Factors are unique only up to rotations, so the comparison is on the
+reconstructed f = X S V, the residual err, err_ada and the rank decisions.
+FP64 collisions: f to 1e-12 relative.  FP32 collisions: each pair collision
+carries an error below 1e-5 ||Q+|| (the collision tolerance), which enters
+the step linearly through dt Q, so the bound is
+||f_gpu - f_ref|| <= 1e-5 dt ||sum_mn K_m K_n Q+(V_m, V_n)||.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import collision as oc
+from oracle import dlr
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2112_02695_amd as blr  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = blr.Context(0)
+    yield c
+    c.close()
+
+
+def _setup(d, N, nx, r, m_rho, mach=1.5, pert=1e-2):
+    if d == 2:
+        spec = synth.VGridSpec(d=2, n=N, L=8.0, gamma=0.0, C=1 / (2 * math.pi), m_rho=m_rho, m_sigma=8)
+    else:
+        spec = synth.VGridSpec(d=3, n=N, L=8.0, gamma=1.0, C=1.0, m_rho=m_rho, m_sigma=38)
+    vs = oc.setup_from_spec(spec)
+    ini = synth.shock_initial(mach, spec, nx, -30.0, 30.0, pert=pert, pert_rank=3, seed=3)
+    prob = dlr.Problem1D(vs=vs, nx=nx, x_lo=-30.0, x_hi=30.0, fL=ini["fL"], fR=ini["fR"])
+    X, S, V = synth.lowrank_state(ini["f0"], r, prob.dx, prob.dvd)
+    return spec, prob, dlr.State(X, S, V), ini
+
+
+class Gpu:
+    def __init__(self, ctx, spec, prob, st, r_cap, flags=0):
+        dev = "cuda"
+        self.ctx = ctx
+        self.nx, self.n = prob.nx, prob.vs.n
+        self.X = torch.zeros((r_cap, self.nx), dtype=torch.float64, device=dev)
+        self.S = torch.zeros((r_cap, r_cap), dtype=torch.float64, device=dev)
+        self.V = torch.zeros((r_cap, self.n), dtype=torch.float64, device=dev)
+        r = st.r
+        self.X[:r] = torch.tensor(st.X.T, device=dev)
+        self.S[:r, :r] = torch.tensor(st.S, device=dev)
+        self.V[:r] = torch.tensor(st.V, device=dev)
+        self.fL = torch.tensor(prob.fL, device=dev)
+        self.fR = torch.tensor(prob.fR, device=dev)
+        self.vg = blr.vgrid_from_spec(spec, flags)
+        self.pb = ctx.make_problem(self.vg, prob.nx, prob.x_lo, prob.x_hi, self.fL, self.fR)
+        self.st = ctx.make_state(self.X, self.S, self.V, r, seed=11)
+
+    def full(self):
+        r = self.st.r
+        X = self.X[:r].double().cpu().numpy().T
+        S = self.S[:r, :r].double().cpu().numpy()
+        V = self.V[:r].double().cpu().numpy()
+        return X @ S @ V
+
+    def factors(self):
+        r = self.st.r
+        return (self.X[:r].cpu().numpy(), self.S[:r, :r].cpu().numpy(), self.V[:r].cpu().numpy())
+
+
+def _params(dt, flags, r_max=30, r_min=1):
+    return blr.StepParams(dt, 0.2, 1e-10, r_min, r_max, flags)
+
+
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(2, 16, 24, 4, 8), (3, 8, 16, 3, 4), (3, 16, 40, 5, 2)])
+def test_fixed_rank_step_fp64(ctx, d, N, nx, r, m_rho):
+    print(f"fixed-rank d={d} N={N} nx={nx} r={r}", flush=True)
+    spec, prob, st, _ = _setup(d, N, nx, r, m_rho)
+    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    info = ctx.dlr_step(g.pb, g.st, _params(0.05, blr.BLR_STEP_FP64_COLLISION))
+    new, err, _ = dlr.ksl_step(st, prob, 0.05)
+    f_ref = new.full()
+    f_gpu = g.full()
+    e = np.abs(f_gpu - f_ref).max() / np.abs(f_ref).max()
+    print("f rel err", e, "err", info.err, err, flush=True)
+    assert e < 1e-12
+    assert abs(info.err - err) < 1e-10 * err
+    assert info.r_out == r and g.st.r == r
+    X, S, V = g.factors()
+    assert np.abs(prob.dx * X @ X.T - np.eye(r)).max() < 1e-12
+    assert np.abs(prob.dvd * V @ V.T - np.eye(r)).max() < 1e-12
+
+
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(2, 16, 24, 4, 8), (3, 16, 40, 5, 2)])
+def test_fixed_rank_step_fp32_collisions(ctx, d, N, nx, r, m_rho):
+    spec, prob, st, _ = _setup(d, N, nx, r, m_rho)
+    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    dt = 0.05
+    info = ctx.dlr_step(g.pb, g.st, _params(dt, 0))
+    new, err, _ = dlr.ksl_step(st, prob, dt)
+    pairs = dlr.pair_list(r)
+    wts = np.array([1.0 if m == n else 2.0 for (m, n) in pairs])
+    _, gains = oc.q_pairs(st.V, pairs, prob.vs, conserve=True)
+    gain_scale = np.linalg.norm(dlr.pair_products(st.X @ st.S, pairs, wts) @ gains)
+    e = np.linalg.norm(g.full() - new.full()) / (dt * gain_scale)
+    print("fp32 step error / (dt ||gain||)", e, flush=True)
+    assert e < 1e-5
+    assert abs(info.err - err) < 1e-3 * err
+
+
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(2, 16, 24, 3, 8), (3, 16, 40, 4, 2)])
+def test_adaptive_steps_fp64(ctx, d, N, nx, r, m_rho):
+    print(f"adaptive d={d} N={N}", flush=True)
+    spec, prob, st, _ = _setup(d, N, nx, r, m_rho)
+    g = Gpu(ctx, spec, prob, st, r_cap=12)
+    flags = blr.BLR_STEP_FP64_COLLISION | blr.BLR_STEP_ADD | blr.BLR_STEP_DROP
+    cur = st
+    for k in range(3):
+        info = ctx.dlr_step(g.pb, g.st, _params(0.05, flags, r_max=12))
+        cur, oinfo = dlr.adaptive_step(cur, prob, 0.05, c=0.2, r_max=12,
+                                       rng=np.random.default_rng(k))
+        print(k, "r", info.r_added, info.r_out, oinfo.r_added, oinfo.r_out, "err", info.err, oinfo.err,
+              "ada", info.err_ada, oinfo.err_ada, flush=True)
+        assert info.r_added == oinfo.r_added and info.r_out == oinfo.r_out
+        assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
+        assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
+        f_ref = cur.full()
+        assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+        # the bound of Sec. 5.1 holds on the GPU too
+        bound = math.sqrt(max(info.r_in + info.r_added - info.r_out, 0)) * info.drop_tol
+        assert abs(info.err - info.err_ada) <= bound * (1 + 1e-12) + 1e-15
+
+
+def test_steady_solve_runs_and_reports(ctx):
+    spec, prob, st, _ = _setup(2, 16, 24, 3, 4)
+    g = Gpu(ctx, spec, prob, st, r_cap=12)
+    flags = blr.BLR_STEP_FP64_COLLISION | blr.BLR_STEP_ADD | blr.BLR_STEP_DROP
+    sp = blr.SolveParams(_params(0.05, flags, r_max=12), 1e-30, 4)
+    info = ctx.steady_solve(g.pb, g.st, sp, allow_unconverged=True)
+    assert info.steps == 4 and info.converged == 0 and info.r == g.st.r
+    ref = st
+    for k in range(4):
+        ref, oi = dlr.adaptive_step(ref, prob, 0.05, c=0.2, r_max=12, rng=np.random.default_rng(k))
+    rho_g, u_g, T_g = dlr.macroscopic(dlr.State(*[np.asarray(a) for a in (
+        g.factors()[0].T, g.factors()[1], g.factors()[2])]), prob)
+    rho_o, u_o, T_o = dlr.macroscopic(ref, prob)
+    for a, b in ((rho_g, rho_o), (u_g, u_o), (T_g, T_o)):
+        assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
+    # converged immediately with a loose tolerance
+    sp2 = blr.SolveParams(_params(0.05, flags, r_max=12), 1e10, 5)
+    info2 = ctx.steady_solve(g.pb, g.st, sp2)
+    assert info2.converged == 1 and info2.steps == 1
+
+
+def test_step_errors_leave_state_untouched(ctx):
+    spec, prob, st, _ = _setup(2, 16, 24, 3, 4)
+    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    before = g.full()
+    with pytest.raises(blr.BlrError) as ei:
+        ctx.dlr_step(g.pb, g.st, _params(-1.0, 0))
+    assert ei.value.code == 1
+    bad = ctx.make_state(g.X, g.S, g.V, 9)   # r > r_cap
+    with pytest.raises(blr.BlrError):
+        ctx.dlr_step(g.pb, bad, _params(0.05, 0))
+    assert np.array_equal(g.full(), before)
