@@ -1,12 +1,16 @@
 """Benchmark of the collision hot path on one MI355X.
 
-Workload: the pair collisions Q_s(V_i, V_j), i <= j, of the rank-10 velocity
-basis of a Mach-1.5 normal-shock state (N_x = 256 cells on [-30, 30],
-N_v = 32^3 on [-8, 8]^3, hard spheres B = |v - v*|, 16 Gauss-Legendre radial
-nodes x 38 Lebedev sphere nodes): 55 pairs per step, FP32 FFTs/products/sums
-with the FP64 moment projection.  With ``--mode step`` a step is one full
-adaptive low-rank time step (add -> K -> S -> L -> drop) of the same state,
-whose 55 pair collisions are counted.
+Workload: a Mach-1.5 normal-shock state in low-rank form (N_x = 256 cells on
+[-30, 30], N_v = 32^3 on [-8, 8]^3, hard spheres B = |v - v*|, 16 Gauss-
+Legendre radial nodes x 38 Lebedev sphere nodes, rank 10).
+
+  --mode step  (default) one step = one full adaptive low-rank time step:
+               add the boundary basis (rank 10 -> 12), the 78 pair
+               collisions Q_s(V_i, V_j) in FP32 (+ FP64 moment projection),
+               K-step, S-step, L-step with FP64 QR, the residual, and the
+               drop back to rank >= 10 (SVD of S).  value = pair collisions
+               evaluated per second of whole steps.
+  --mode pairs one step = the 55 pair collisions of the rank-10 basis alone.
 
 Prints ONE JSON line (rank 0, N = 1 only).  Inputs are resident in HBM before
 the timed region starts.
@@ -32,10 +36,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["pairs", "step"], default="pairs")
+    ap.add_argument("--mode", choices=["pairs", "step"], default="step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the multi-pass FFT path")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM traffic per launch from rocprofv3 counters (if present)")
     return ap.parse_args()
@@ -75,7 +81,8 @@ def main():
                                     ctypes.POINTER(ctypes.c_double)]
 
     spec = synth.C3
-    nx, r = 256, 10
+    nx, r, r_cap = 256, 10, 12
+    dt = 0.01
     ini = synth.shock_initial(1.5, spec, nx, -30.0, 30.0, pert=1e-3, pert_rank=10, seed=3)
     dx = 60.0 / nx
     dvd = (2 * spec.L / spec.n) ** 3
@@ -86,16 +93,47 @@ def main():
     vg = blr.vgrid_from_spec(spec, flags)
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = blr.Context(0)
     V32 = torch.tensor(V, dtype=torch.float32, device=dev)
     Q = torch.empty((P, V.shape[1]), dtype=torch.float32, device=dev)
 
-    def one_step():
-        ctx.collision_pairs(vg, V32, pairs, out=Q)
+    counted = [0]
+    if args.mode == "pairs":
+        def one_step():
+            ctx.collision_pairs(vg, V32, pairs, out=Q)
+            counted[0] += P
+    else:
+        Xd = torch.zeros((r_cap, nx), dtype=torch.float64, device=dev)
+        Sd = torch.zeros((r_cap, r_cap), dtype=torch.float64, device=dev)
+        Vd = torch.zeros((r_cap, V.shape[1]), dtype=torch.float64, device=dev)
+        Xd[:r] = torch.tensor(X.T, device=dev)
+        Sd[:r, :r] = torch.tensor(S, device=dev)
+        Vd[:r] = torch.tensor(V, device=dev)
+        fL = torch.tensor(ini["fL"], device=dev)
+        fR = torch.tensor(ini["fR"], device=dev)
+        pb = ctx.make_problem(vg, nx, -30.0, 30.0, fL, fR)
+        st = ctx.make_state(Xd, Sd, Vd, r, seed=1)
+        sp = blr.StepParams(dt, 0.2, 1e-10, r, r_cap, blr.BLR_STEP_ADD | blr.BLR_STEP_DROP)
+        infos = []
+
+        def one_step():
+            info = ctx.dlr_step(pb, st, sp)
+            rr = info.r_in + info.r_added
+            counted[0] += rr * (rr + 1) // 2
+            infos.append((info.r_in, info.r_added, info.r_out, info.err, info.err_ada,
+                          info.ms_collision, info.ms_step))
 
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
+    counted[0] = 0
     lib.blr_timing(ctx.h, 2)
     lib.blr_timing(ctx.h, 1)
     torch.cuda.synchronize()
@@ -108,7 +146,24 @@ def main():
     timers = read_timers(ctx)
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
-    value = P * args.steps / elapsed
+    value = counted[0] / elapsed
+    step_extra = None
+    if args.mode == "step":
+        last = infos[-args.steps:]
+        step_extra = {"rank_in_added_out": [list(x[:3]) for x in last[:3]],
+                      "err_last": last[-1][3], "err_ada_last": last[-1][4],
+                      "ms_collision_avg": round(sum(x[5] for x in last) / len(last), 4),
+                      "ms_step_avg": round(sum(x[6] for x in last) / len(last), 4),
+                      "pairs_per_step": counted[0] / args.steps}
+        # collision-only rate of the rank-10 batch, for reference
+        for _ in range(2):
+            ctx.collision_pairs(vg, V32, pairs, out=Q)
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        for _ in range(5):
+            ctx.collision_pairs(vg, V32, pairs, out=Q)
+        torch.cuda.synchronize()
+        step_extra["collision_only_pair_evals_per_s"] = round(5 * P / (time.perf_counter() - tq), 1)
 
     # dominant kernel and its roofline
     dom = max(timers, key=lambda t: t["ms"]) if timers else None
@@ -150,11 +205,11 @@ def main():
         vs = oc.setup_from_spec(spec)
         tc = time.perf_counter()
         oc.q_pairs(V, [pairs[1]], vs, conserve=True)
-        dt = time.perf_counter() - tc
-        cpu = {"value": round(1.0 / dt, 5), "unit": "pair evals/s", "cores": 1, "kind": "oracle",
+        t_cpu = time.perf_counter() - tc
+        cpu = {"value": round(1.0 / t_cpu, 5), "unit": "pair evals/s", "cores": 1, "kind": "oracle",
                "sample": "1 of the 55 pairs (Q_s(V_0,V_1)) on the full 32^3 grid, float64 oracle "
                          "(FFT form of the operator, numpy, single thread)",
-               "seconds": round(dt, 2)}
+               "seconds": round(t_cpu, 2)}
 
     line = {
         "metric": "Q(V_i,V_j) evals/s at N_v=32^3",
@@ -169,10 +224,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "55 pair collisions Q_s(V_i,V_j) of the rank-10 basis of a Mach-1.5 "
-                               "shock state, N_v=32^3 on [-8,8]^3, hard spheres, M_rho=16 x M_sigma=38",
-                   "mode": args.mode, "r": r, "pairs": P, "n_v": spec.n, "nx": nx,
+        "config": {"workload": ("adaptive low-rank step of a Mach-1.5 shock state (N_x=256, N_v=32^3 "
+                                "on [-8,8]^3, hard spheres, M_rho=16 x M_sigma=38, rank 10 -> +2 "
+                                "boundary basis -> drop to >=10; 78 pair collisions per step)")
+                   if args.mode == "step" else
+                   ("55 pair collisions Q_s(V_i,V_j) of the rank-10 basis of a Mach-1.5 shock "
+                    "state, N_v=32^3 on [-8,8]^3, hard spheres, M_rho=16 x M_sigma=38"),
+                   "mode": args.mode, "r": r, "n_v": spec.n, "nx": nx, "dt": dt,
+                   "collisions": "fp32 (+fp64 moment projection)", "linear_algebra": "fp64",
                    "path": "generic" if args.generic else "default"},
+        "step": step_extra,
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_fp64_pair_evals_per_s": round(plain, 2) if plain else None,

@@ -42,6 +42,28 @@ struct LdComplex {
   }
 };
 
+// rows of a matrix picked through an index map (at most 64 rows)
+struct Idx64 {
+  int v[64];
+};
+
+template <typename T>
+struct LdRealIdx {
+  static constexpr int bpe = 1;  // algorithmic bytes per element / sizeof(T)
+  const T* p;
+  int n;
+  Idx64 idx;
+  template <int N>
+  __device__ void load(long f, int base, int stride, T (&re)[N], T (&im)[N]) const {
+    const T* q = p + (long)idx.v[f] * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      re[j] = q[(long)j * stride];
+      im[j] = T(0);
+    }
+  }
+};
+
 template <typename T>
 struct LdReal {
   static constexpr int bpe = 1;  // algorithmic bytes per element / sizeof(T)
@@ -578,16 +600,16 @@ struct Generic {
     const HostTables& h = tb.h;
     hipStream_t s = ctx->stream;
     const int rb = (int)pl.bidx.size();
+    require(rb <= 64, "at most 64 distinct basis functions per call");
     const std::string tag = std::string("bas") + (sizeof(T) == 4 ? "f" : "d");
-    T* Vc = (T*)ctx->buf(tag + ".Vc", (size_t)rb * n * sizeof(T));
     T2* Vh = (T2*)ctx->buf(tag + ".Vh", (size_t)rb * n * sizeof(T2));
     T* Vp = (T*)ctx->buf(tag + ".VpLam", (size_t)2 * rb * n * sizeof(T));
     T2* tmp = (T2*)ctx->buf(tag + ".tmp", (size_t)2 * rb * n * sizeof(T2));
-    for (int ib = 0; ib < rb; ++ib)
-      BLR_HIP(hipMemcpyAsync(Vc + (size_t)ib * n, Vsrc + (size_t)pl.bidx[ib] * n, n * sizeof(T),
-                             hipMemcpyDeviceToDevice, s));
+    Idx64 idx{};
+    for (int ib = 0; ib < rb; ++ib) idx.v[ib] = pl.bidx[ib];
     g_stage = "basis";
-    transform<T, N, D, -1>(s, LdReal<T>{Vc, n}, StBasisSpec<T, N, D>{Vh, n, T(1) / T(n)}, tmp, rb);
+    transform<T, N, D, -1>(s, LdRealIdx<T>{Vsrc, n, idx}, StBasisSpec<T, N, D>{Vh, n, T(1) / T(n)},
+                           tmp, rb);
     transform<T, N, D, +1>(s, LdBasisMode<T>{Vh, (const T*)tb.gloss, n, rb}, StRe<T>{Vp, n}, tmp,
                            2 * rb);
     (void)h;
@@ -607,10 +629,6 @@ struct Generic {
     const long shift_fields = (long)rb * h.mrho * h.nbp;
     const long batch = std::min<long>(shift_fields, 512);
     const std::string tag = std::string("gen") + (sizeof(T) == 4 ? "f" : "d");
-    T* Vc = (T*)ctx->buf(tag + ".Vc", (size_t)rb * n * sizeof(T));
-    T2* Vh = (T2*)ctx->buf(tag + ".Vh", (size_t)rb * n * sizeof(T2));
-    T* Vp = (T*)ctx->buf(tag + ".VpLam", (size_t)2 * rb * n * sizeof(T));
-    T* Lam = Vp + (size_t)rb * n;
     T* Sh = (T*)ctx->buf(tag + ".Sh", (size_t)rb * h.mrho * h.msig * n * sizeof(T));
     T2* tmp = (T2*)ctx->buf(tag + ".tmp",
                             (size_t)std::max<long>(batch, std::max<long>(nc, 2 * rb)) * n * sizeof(T2));
@@ -624,16 +642,13 @@ struct Generic {
       idx[2 * P + p] = prow[p];
     }
     int* didx = (int*)ctx->upload(tag + ".idx", idx.data(), idx.size() * sizeof(int));
-    for (int ib = 0; ib < rb; ++ib)
-      BLR_HIP(hipMemcpyAsync(Vc + (size_t)ib * n, Vsrc + (size_t)pl.bidx[ib] * n, n * sizeof(T),
-                             hipMemcpyDeviceToDevice, s));
     const T2* phase = (const T2*)tb.phase;
     const T* fw = (const T*)tb.fw;
-    const T* gl = (const T*)tb.gloss;
     // 1. spectra, projected basis and loss fields
-    g_stage = "gen.basis";
-    transform<T, N, D, -1>(s, LdReal<T>{Vc, n}, StBasisSpec<T, N, D>{Vh, n, T(1) / T(n)}, tmp, rb);
-    transform<T, N, D, +1>(s, LdBasisMode<T>{Vh, gl, n, rb}, StRe<T>{Vp, n}, tmp, 2 * rb);
+    T2* Vh;
+    T* Vp;
+    T* Lam;
+    basis(ctx, tb, Vsrc, pl, &Vh, &Vp, &Lam);
     // 2. shifts
     g_stage = "gen.shift";
     for (long f0 = 0; f0 < shift_fields; f0 += batch) {

@@ -45,62 +45,72 @@ __device__ __forceinline__ double weight(int mode, double v1) {
   }
 }
 
-constexpr int GT = 64;      // output tile (rows of A, rows of B)
-constexpr int GQ = 64;      // points per LDS stage
-constexpr int NCHUNK = 64;  // velocity chunks (first reduction stage)
+constexpr int GT = 16;       // output tile edge (rows of A x rows of B)
+constexpr int NCHUNK = 256;  // velocity chunks (first reduction stage)
+constexpr int GQ = 128;      // max points per chunk staged in LDS
+constexpr int MAXM = 4;      // weight modes evaluated together
 
-// partial[c][i][j] = sum_{q in chunk c} w(q) A[i][q] B[j][q]
+struct Modes {
+  int m[MAXM];
+  int count;
+};
+
+// partial[c][k][i][j] = sum_{q in chunk c} w_k(q) A[i][q] B[j][q]: one block
+// per (chunk, 16 rows of B, 16 rows of A), one thread per (i, j) output.
 template <typename TB>
 __global__ __launch_bounds__(256) void k_vgram(const double* __restrict__ A, int ra, long lda,
-                                               const TB* __restrict__ B, int rb, long ldb, int mode,
+                                               const TB* __restrict__ B, int rb, long ldb, Modes md,
                                                VGeo g, double* __restrict__ part) {
   __shared__ double As[GT][GQ + 1];
   __shared__ double Bs[GT][GQ + 1];
-  __shared__ double ws[GQ];
+  __shared__ double ws[MAXM][GQ];
   const int c = blockIdx.x;
-  const int i0 = blockIdx.y * GT, j0 = blockIdx.z * GT;
-  const long q_begin = (long)c * g.n / NCHUNK, q_end = (long)(c + 1) * g.n / NCHUNK;
+  const int j0 = blockIdx.y * GT, i0 = blockIdx.z * GT;
+  const long q0 = (long)c * g.n / NCHUNK, q1 = (long)(c + 1) * g.n / NCHUNK;
   const int t = threadIdx.x;
-  double acc[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-  const int ti = t / 16, tj = t % 16;  // outputs (ti + 16 a, tj + 16 b), a,b < 4
-  for (long q0 = q_begin; q0 < q_end; q0 += GQ) {
-    const int nq = (int)min((long)GQ, q_end - q0);
+  const int ti = t / GT, tj = t % GT;
+  double acc[MAXM] = {0.0, 0.0, 0.0, 0.0};
+  for (long qb = q0; qb < q1; qb += GQ) {
+    const int nq = (int)min((long)GQ, q1 - qb);
     for (int e = t; e < GT * GQ; e += 256) {
-      const int r = e / GQ, qq = e % GQ;
-      As[r][qq] = (i0 + r < ra && qq < nq) ? A[(long)(i0 + r) * lda + q0 + qq] : 0.0;
-      Bs[r][qq] = (j0 + r < rb && qq < nq) ? (double)B[(long)(j0 + r) * ldb + q0 + qq] : 0.0;
+      const int rr = e / GQ, qq = e % GQ;
+      As[rr][qq] = (i0 + rr < ra && qq < nq) ? A[(long)(i0 + rr) * lda + qb + qq] : 0.0;
+      Bs[rr][qq] = (j0 + rr < rb && qq < nq) ? (double)B[(long)(j0 + rr) * ldb + qb + qq] : 0.0;
     }
-    if (t < GQ) ws[t] = t < nq ? weight(mode, g.v1((int)(q0 + t))) : 0.0;
+    for (int e = t; e < MAXM * GQ; e += 256) {
+      const int k = e / GQ, qq = e % GQ;
+      ws[k][qq] = (k < md.count && qq < nq) ? weight(md.m[k], g.v1((int)(qb + qq))) : 0.0;
+    }
     __syncthreads();
     for (int qq = 0; qq < nq; ++qq) {
-      const double w = ws[qq];
+      const double p = As[ti][qq] * Bs[tj][qq];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const double x = w * As[ti + 16 * a][qq];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a * 4 + b] += x * Bs[tj + 16 * b][qq];
-      }
+      for (int k = 0; k < MAXM; ++k) acc[k] += ws[k][qq] * p;
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = i0 + ti + 16 * a, j = j0 + tj + 16 * b;
-      if (i < ra && j < rb) part[((long)c * ra + i) * rb + j] = acc[a * 4 + b];
-    }
+  const int i = i0 + ti, j = j0 + tj;
+  if (i < ra && j < rb)
+    for (int k = 0; k < md.count; ++k) part[(((long)c * md.count + k) * ra + i) * rb + j] = acc[k];
 }
 
-__global__ void k_vgram_finish(const double* __restrict__ part, int ra, int rb, double scale,
-                               double* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ra * rb) return;
+// sum of the chunk partials: one wavefront per output, fixed order
+__global__ __launch_bounds__(256) void k_vgram_finish(const double* __restrict__ part, int nm, int ra,
+                                                      int rb, double scale, double* __restrict__ o0,
+                                                      double* __restrict__ o1,
+                                                      double* __restrict__ o2,
+                                                      double* __restrict__ o3) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int per = ra * rb;
+  if (t >= nm * per) return;
+  const int k = t / per, e = t % per;
   double s = 0.0;
-  for (int c = 0; c < NCHUNK; ++c) s += part[(long)c * ra * rb + t];
-  out[t] = scale * s;
+  for (int c = lane; c < NCHUNK; c += 64) s += part[((long)c * nm + k) * per + e];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane != 0) return;
+  double* o = k == 0 ? o0 : (k == 1 ? o1 : (k == 2 ? o2 : o3));
+  o[e] = scale * s;
 }
 
 // K[j][x] = sum_i X[i][x] S[i][j]
@@ -166,18 +176,23 @@ __global__ void k_kstep(const double* __restrict__ K, const double* __restrict__
 //   c <  r        : Y = D+ K_c
 //   c <  2r       : Y = D- K_(c-r)
 //   c <  2r + P   : Y = w_p K_m K_n
-// (mode 1: Y_c = Z[c][x], a plain matrix with cols columns)
-__global__ void k_xreduce(const double* __restrict__ X1, int r, int nx, double dx,
-                          const double* __restrict__ K, const double* __restrict__ g, int P,
-                          const int* __restrict__ pm, const int* __restrict__ pn,
-                          const double* __restrict__ Z, int zc, int mode, double* __restrict__ out,
-                          int ncols, double* __restrict__ oDp, double* __restrict__ oDm,
-                          double* __restrict__ oT) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// (mode 1: Y_c = Z[c][x], a plain matrix with ncols columns).
+// One wavefront per output: lanes stride over x, then a shuffle tree.
+__global__ __launch_bounds__(256) void k_xreduce(const double* __restrict__ X1, int r, int nx,
+                                                 double dx, const double* __restrict__ K,
+                                                 const double* __restrict__ g, int P,
+                                                 const int* __restrict__ pm,
+                                                 const int* __restrict__ pn,
+                                                 const double* __restrict__ Z, int zc, int mode,
+                                                 double* __restrict__ out, int ncols,
+                                                 double* __restrict__ oDp, double* __restrict__ oDm,
+                                                 double* __restrict__ oT) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= r * ncols) return;
   const int i = t / ncols, c = t % ncols;
   double s = 0.0;
-  for (int x = 0; x < nx; ++x) {
+  for (int x = lane; x < nx; x += 64) {
     double y;
     if (mode == 1) {
       y = Z[(long)c * nx + x];
@@ -192,6 +207,8 @@ __global__ void k_xreduce(const double* __restrict__ X1, int r, int nx, double d
     }
     s += X1[(long)i * nx + x] * y;
   }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane != 0) return;
   s *= dx;
   (void)zc;
   if (mode == 1) {
@@ -370,47 +387,37 @@ __global__ void k_err(const double* dK, long nK, double dx, const double* dS, in
   }
 }
 
-// <f^n, D> = sum_kl S[k][l] (A M B^T)[k][l],  M = U_perp Sig_perp W_perp^T
-// (one block, three r x r products in LDS; fixed summation order)
-__global__ __launch_bounds__(256) void k_fnD(const double* S, const double* A, const double* U,
-                                             const double* sig, const double* W, const double* B,
-                                             int r, int keep, double* res) {
-  __shared__ double M[64 * 64];
-  __shared__ double AM[64 * 64];
-  __shared__ double red[256];
+// Terms of <f^n, D_keep> for every truncation point: with S^{n+1} = U Sig W^T,
+// D_keep = X1 (sum_{s >= keep} sig_s u_s w_s^T) V1 and A_ki = <X^n_k, X1_i>,
+// B_lj = <V^n_l, V1_j>,
+//   <f^n, D_keep> = sum_{s >= keep} g_s,  g_s = sig_s (A u_s)^T S^n (B w_s).
+// One block; g[s] written for s < r.
+__global__ __launch_bounds__(256) void k_fnD_terms(const double* S, const double* A,
+                                                   const double* U, const double* sig,
+                                                   const double* W, const double* B, int r,
+                                                   double* g) {
+  __shared__ double AU[64 * 64];  // AU[k][s] = sum_i A[k][i] U[i][s]
+  __shared__ double BW[64 * 64];  // BW[l][s] = sum_j B[l][j] W[j][s]
   const int t = threadIdx.x;
   for (int e = t; e < r * r; e += blockDim.x) {
-    const int i = e / r, j = e % r;
-    double m = 0.0;
-    for (int q = keep; q < r; ++q) m += U[i * r + q] * sig[q] * W[j * r + q];
-    M[e] = m;
+    const int k = e / r, q = e % r;
+    double au = 0.0, bw = 0.0;
+    for (int i = 0; i < r; ++i) {
+      au += A[k * r + i] * U[i * r + q];
+      bw += B[k * r + i] * W[i * r + q];
+    }
+    AU[e] = au;
+    BW[e] = bw;
   }
   __syncthreads();
-  for (int e = t; e < r * r; e += blockDim.x) {
-    const int k = e / r, j = e % r;
+  for (int q = t; q < r; q += blockDim.x) {
     double v = 0.0;
-    for (int i = 0; i < r; ++i) v += A[k * r + i] * M[i * r + j];
-    AM[e] = v;
-  }
-  __syncthreads();
-  double part = 0.0;
-  for (int e = t; e < r * r; e += blockDim.x) {
-    const int k = e / r, l = e % r;
-    double v = 0.0;
-    for (int j = 0; j < r; ++j) v += AM[k * r + j] * B[l * r + j];
-    part += S[e] * v;
-  }
-  red[t] = part;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (t < st) red[t] += red[t + st];
-    __syncthreads();
-  }
-  if (t == 0) {
-    double sp2 = 0.0;
-    for (int j = keep; j < r; ++j) sp2 += sig[j] * sig[j];
-    res[0] = red[0];
-    res[1] = sp2;
+    for (int k = 0; k < r; ++k) {
+      double sb = 0.0;
+      for (int l = 0; l < r; ++l) sb += S[k * r + l] * BW[l * r + q];
+      v += AU[k * r + q] * sb;
+    }
+    g[q] = sig[q] * v;
   }
 }
 
@@ -445,20 +452,34 @@ struct StepWork {
   }
 };
 
-// G = scale * sum_q w(q) A_i B_j   (ra x rb row-major)
+// G_k = scale * sum_q w_k(q) A_i B_j   (ra x rb row-major), up to 4 weights at once
+template <typename TB>
+void vgram_multi(StepWork& w, const double* A, int ra, const TB* B, int rb,
+                 std::initializer_list<std::pair<int, double*>> outs, double scale) {
+  dk::Modes md{};
+  double* o[4] = {nullptr, nullptr, nullptr, nullptr};
+  md.count = 0;
+  for (const auto& pr : outs) {
+    md.m[md.count] = pr.first;
+    o[md.count] = pr.second;
+    ++md.count;
+  }
+  double* part = w.get("vgram.part", (size_t)dk::NCHUNK * md.count * ra * rb);
+  const dim3 grid(dk::NCHUNK, blocks(rb, dk::GT), blocks(ra, dk::GT));
+  timed_begin("dlr.vgram", (double)w.n * (ra * 8.0 + rb * (double)sizeof(TB)), w.s);
+  hipLaunchKernelGGL(dk::k_vgram<TB>, grid, dim3(256), 0, w.s, A, ra, (long)w.n, B, rb, (long)w.n,
+                     md, w.g, part);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_vgram_finish, dim3(blocks((long)md.count * ra * rb, 4)), dim3(256), 0,
+                     w.s, part, md.count, ra, rb, scale, o[0], o[1], o[2], o[3]);
+  BLR_CHECK_LAUNCH();
+  timed_end(w.s);
+}
+
 template <typename TB>
 void vgram(StepWork& w, const double* A, int ra, const TB* B, int rb, int mode, double scale,
            double* out) {
-  double* part = w.get("vgram.part", (size_t)dk::NCHUNK * ra * rb);
-  const dim3 grid(dk::NCHUNK, blocks(ra, dk::GT), blocks(rb, dk::GT));
-  timed_begin("dlr.vgram", (double)w.n * (ra + rb) * 8.0, w.s);
-  hipLaunchKernelGGL(dk::k_vgram<TB>, grid, dim3(256), 0, w.s, A, ra, (long)w.n, B, rb, (long)w.n,
-                     mode, w.g, part);
-  BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_vgram_finish, dim3(blocks((long)ra * rb, 256)), dim3(256), 0, w.s, part, ra,
-                     rb, scale, out);
-  BLR_CHECK_LAUNCH();
-  timed_end(w.s);
+  vgram_multi<TB>(w, A, ra, B, rb, {{mode, out}}, scale);
 }
 
 void d2h(blr_ctx ctx, void* host, const void* dev, size_t bytes) {
@@ -517,8 +538,6 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   auto boundary_integrals = [&](const double* Vb, int rr) {
     vgram<double>(w, Vb, rr, pb->f_left, 1, dk::W_IN_LEFT, dvd, ginL);
     vgram<double>(w, Vb, rr, pb->f_right, 1, dk::W_IN_RIGHT, dvd, ginR);
-    vgram<double>(w, Vb, rr, Vb, rr, dk::W_OUT_LEFT, dvd, MoL);
-    vgram<double>(w, Vb, rr, Vb, rr, dk::W_OUT_RIGHT, dvd, MoR);
   };
 
   // ---------------------------------------------------------- add basis
@@ -620,8 +639,10 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   double* Ap = w.get("Ap", (size_t)r * r);
   double* Am = w.get("Am", (size_t)r * r);
   double* Cj = w.get("C", (size_t)r * P);
-  vgram<double>(w, Vw, r, Vw, r, dk::W_VPLUS, dvd, Ap);
-  vgram<double>(w, Vw, r, Vw, r, dk::W_VMINUS, dvd, Am);
+  vgram_multi<double>(w, Vw, r, Vw, r,
+                      {{dk::W_VPLUS, Ap}, {dk::W_VMINUS, Am}, {dk::W_OUT_LEFT, MoL},
+                       {dk::W_OUT_RIGHT, MoR}},
+                      dvd);
   if (fp64c)
     vgram<double>(w, Vw, r, (const double*)Qs, P, dk::W_ONE, dvd, Cj);
   else
@@ -660,7 +681,7 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   double* Dp = w.get("Dp", (size_t)r * r);
   double* Dm = w.get("Dm", (size_t)r * r);
   double* T = w.get("T", (size_t)r * P);
-  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 256)), dim3(256), 0, s, X1, r, nx,
+  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 4)), dim3(256), 0, s, X1, r, nx,
                      dx, K, gh, P, dpidx, dpidx + P, nullptr, 0, 0, nullptr, ncols, Dp, Dm, T);
   BLR_CHECK_LAUNCH();
   hipLaunchKernelGGL(dk::k_supdate, dim3(1), dim3(1024), 0, s, S1, Dp, Dm, T, Ap, Am, Cj, r, P, dt, S2,
@@ -672,7 +693,7 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   BLR_CHECK_LAUNCH();
   hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
   BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 256)), dim3(256), 0, s, X1, r, nx,
+  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 4)), dim3(256), 0, s, X1, r, nx,
                      dx, K, gh, P, dpidx, dpidx + P, nullptr, 0, 0, nullptr, ncols, Dp, Dm, T);
   BLR_CHECK_LAUNCH();
   double* L1 = w.get("L1", (size_t)r * n);
@@ -708,7 +729,7 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   double* lv = w.get("lv", (size_t)r * r);
   double* GdL = w.get("GdL", (size_t)r * r);
   double* res = w.get("res", 8);
-  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, X1, r, nx, dx,
+  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, X1, r, nx, dx,
                      nullptr, nullptr, 0, nullptr, nullptr, dK, r, 1, kx, r, nullptr, nullptr, nullptr);
   BLR_CHECK_LAUNCH();
   vgram<double>(w, dL, r, Vw, r, dk::W_ONE, dvd, lv);
@@ -729,13 +750,18 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
     // err_ada needs A = <X^n_k, X1_i>_x and B = <V^n_l, V1_j>_v
     double* Aad = w.get("Aad", (size_t)r * r);
     double* Bad = w.get("Bad", (size_t)r * r);
-    hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, Xw, r, nx, dx,
+    hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, Xw, r, nx, dx,
                        nullptr, nullptr, 0, nullptr, nullptr, X1, r, 1, Aad, r, nullptr, nullptr,
                        nullptr);
     BLR_CHECK_LAUNCH();
     vgram<double>(w, Vw, r, V1, r, dk::W_ONE, dvd, Bad);
-    std::vector<double> sgh(r);
+    double* gterm = w.get("gterm", (size_t)r);
+    hipLaunchKernelGGL(dk::k_fnD_terms, dim3(1), dim3(256), 0, s, Sw, Aad, U, sg, Wm, Bad, r, gterm);
+    BLR_CHECK_LAUNCH();
+    // one synchronisation: residual pieces, singular values and err_ada terms
+    std::vector<double> sgh(r), gh(r);
     BLR_HIP(hipMemcpyAsync(resh, res, sizeof(resh), hipMemcpyDeviceToHost, s));
+    BLR_HIP(hipMemcpyAsync(gh.data(), gterm, r * sizeof(double), hipMemcpyDeviceToHost, s));
     d2h(ctx, sgh.data(), sg, r * sizeof(double));
     const double err = std::sqrt(std::max(resh[0], 0.0));
     require(std::isfinite(err), "non-finite residual", BLR_ERR_NUMERIC);
@@ -744,14 +770,15 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
     int keep = 0;
     for (double v : sgh) keep += v >= tol ? 1 : 0;
     keep = std::max(std::min(keep, r_max), std::min(r_min, r));
-    double* fnd = w.get("fnd", 2);
-    hipLaunchKernelGGL(dk::k_fnD, dim3(1), dim3(256), 0, s, Sw, Aad, U, sg, Wm, Bad, r, keep, fnd);
-    BLR_CHECK_LAUNCH();
-    double fh[2];
-    d2h(ctx, fh, fnd, sizeof(fh));
+    double sp2 = 0.0, fnD = 0.0;
+    for (int q = keep; q < r; ++q) {
+      sp2 += sgh[q] * sgh[q];
+      fnD += gh[q];
+    }
     inf.err = err;
     inf.drop_tol = tol;
-    inf.err_ada = std::sqrt(std::max(err * err - fh[1] + 2.0 * fh[0], 0.0));
+    // err_ada^2 = err^2 - |Sigma_perp|^2 + 2 <f^n, D>
+    inf.err_ada = std::sqrt(std::max(err * err - sp2 + 2.0 * fnD, 0.0));
     // rotate and truncate
     double* Xd = w.get("Xd", (size_t)r * nx);
     double* Vd = w.get("Vd", (size_t)r * n);

@@ -2,8 +2,9 @@
 //
 //   tsqr   Householder QR of a tall-skinny column-major matrix (rows >= 1,
 //          1 <= r <= 64) as a reduction tree: blocks of 256 rows are
-//          factorised in LDS by one workgroup each (rows padded with zeros to
-//          at least r), their R factors are stacked and factorised again until
+//          factorised by one wavefront each (up to four rows per lane held
+//          in registers, all column sums of a reflector in one LDS pass;
+//          rows padded with zeros to at least r), their R factors are stacked and factorised again until
 //          one block remains; Q is formed top-down by applying each level's
 //          reflectors to the next level's Q block.  The sign of every row of R
 //          is chosen so that diag(R) >= 0 (the top-level Q starts from
@@ -21,7 +22,6 @@
 namespace blr {
 namespace la {
 
-constexpr int MB = 256;  // rows per QR block (= threads per workgroup)
 
 __device__ __forceinline__ double block_sum(double x, double* red) {
   // deterministic: wave shuffles, then a fixed-order sum of the 4 wave totals
@@ -34,29 +34,72 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
-// Factor block b of a column-major matrix A (rows x r, leading dim lda).
-// Writes the Householder vectors (unit diagonal implied) into Y (same layout,
-// leading dim ldy = padded rows), tau[b*r + k], and R into Rst (stacked
-// column-major, leading dim nb*r) rows [b*r, b*r + r).
+// rows per lane for a column bucket RM: one wavefront per block, no barriers
 template <int RM>
-__global__ __launch_bounds__(MB) void k_qr_block(const double* __restrict__ A, long lda, long rows,
+struct QRShape {
+  static constexpr int RPL = RM <= 8 ? 4 : (RM <= 16 ? 2 : 1);
+  static constexpr int MBR = 64 * RPL;  // rows per block
+};
+
+// Column sums over the 64 lanes of a wavefront for NV values per lane,
+// identical in every lane: partials go to LDS, lane c adds column c in lane
+// order (fixed order, so the result is reproducible), and every lane reads
+// the NV sums back.  buf: LDS scratch of 64 * (NV + 1) + NV doubles.
+template <int NV>
+__device__ __forceinline__ void wave_sums(double (&v)[NV], double* buf) {
+  const int lane = threadIdx.x;
+  double* part = buf;
+  double* tot = buf + 64 * (NV + 1);
+#pragma unroll
+  for (int c = 0; c < NV; ++c) part[lane * (NV + 1) + c] = v[c];
+  __syncthreads();
+  if (lane < NV) {
+    double s = 0.0;
+    for (int l = 0; l < 64; ++l) s += part[l * (NV + 1) + lane];
+    tot[lane] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NV; ++c) v[c] = tot[c];
+  __syncthreads();
+}
+
+// Factor block b of a column-major matrix A (rows x r, leading dim lda):
+// one wavefront, lane l owns rows l, l+64, l+128, l+192 of the block in
+// registers.  Writes the Householder vectors (unit diagonal implied) into Y
+// (leading dim ldy = padded rows), tau[b*r + k], and R into Rst (stacked
+// column-major, leading dim nb*r), rows [b*r, b*r + r).
+template <int RM, int RPL = QRShape<RM>::RPL, int MB = QRShape<RM>::MBR>
+__global__ __launch_bounds__(64) void k_qr_block(const double* __restrict__ A, long lda, long rows,
                                                  int r, double* __restrict__ Y, long ldy,
                                                  double* __restrict__ tau,
                                                  double* __restrict__ Rst, long ldr) {
-  __shared__ double T[MB * RM];
-  __shared__ double red[8];
-  __shared__ double sh[RM + 4];
+  __shared__ double buf[64 * (RM + 1) + RM];
   const int b = blockIdx.x;
-  const int i = threadIdx.x;
-  const long row = (long)b * MB + i;
+  const int lane = threadIdx.x;
   const int m = (int)max((long)r, min((long)MB, rows - (long)b * MB));  // active rows (>= r)
-  for (int c = 0; c < r; ++c) T[i * RM + c] = (i < m && row < rows) ? A[c * lda + row] : 0.0;
-  __syncthreads();
-  for (int k = 0; k < r; ++k) {
-    // x = T[k:m, k]
-    const double xi = (i > k && i < m) ? T[i * RM + k] : 0.0;
-    const double tail = block_sum(xi * xi, red);
-    const double x0 = T[k * RM + k];
+  double a[RPL][RM];
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int i = lane + 64 * h;
+    const long row = (long)b * MB + i;
+    const bool live = i < m && row < rows;
+#pragma unroll
+    for (int c = 0; c < RM; ++c) a[h][c] = (live && c < r) ? A[c * lda + row] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < RM; ++k) {
+   if (k < r) {
+    double tl = 0.0, xl = 0.0;
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const int i = lane + 64 * h;
+      if (i > k && i < m) tl += a[h][k] * a[h][k];
+      if (i == k) xl = a[h][k];
+    }
+    double tx[2] = {tl, xl};
+    wave_sums<2>(tx, buf);
+    const double tail = tx[0], x0 = tx[1];
     double beta, tk, scale;
     if (tail == 0.0) {
       tk = 0.0;
@@ -68,63 +111,108 @@ __global__ __launch_bounds__(MB) void k_qr_block(const double* __restrict__ A, l
       tk = (beta - x0) / beta;
       scale = 1.0 / (x0 - beta);
     }
-    __syncthreads();
-    if (i > k && i < m) T[i * RM + k] *= scale;
-    if (i == k) T[k * RM + k] = beta;
-    __syncthreads();
-    // apply H = I - tau v v^T to columns k+1..r-1 (v_k = 1)
-    for (int c = k + 1; c < r; ++c) {
-      const double vi = (i > k && i < m) ? T[i * RM + k] : 0.0;
-      const double part = vi * T[i * RM + c];
-      double wsum = block_sum(part, red) + T[k * RM + c];
-      if (i == 0) sh[0] = wsum;
-      __syncthreads();
-      wsum = sh[0];
-      if (i > k && i < m) T[i * RM + c] -= tk * wsum * vi;
-      __syncthreads();
-      if (i == k) T[k * RM + c] -= tk * wsum;
-      __syncthreads();
+    double vi[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const int i = lane + 64 * h;
+      vi[h] = 0.0;
+      if (i > k && i < m) {
+        a[h][k] *= scale;
+        vi[h] = a[h][k];
+      } else if (i == k) {
+        a[h][k] = beta;
+        vi[h] = 1.0;
+      }
     }
-    if (i == 0) tau[(long)b * r + k] = tk;
+    double wv[RM];
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+      double part = 0.0;
+      if (c > k && c < r) {
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) part += vi[h] * a[h][c];
+      }
+      wv[c] = part;
+    }
+    wave_sums<RM>(wv, buf);
+#pragma unroll
+    for (int c = k + 1; c < RM; ++c) {
+      if (c < r) {
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) a[h][c] -= tk * wv[c] * vi[h];
+      }
+    }
+    if (lane == 0) tau[(long)b * r + k] = tk;
+   }
   }
-  __syncthreads();
-  // Householder vectors and R out
-  for (int c = 0; c < r; ++c) {
-    Y[c * ldy + (long)b * MB + i] = (i > c && i < m) ? T[i * RM + c] : 0.0;
-    if (i < r) Rst[c * ldr + (long)b * r + i] = (i <= c) ? T[i * RM + c] : 0.0;
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int i = lane + 64 * h;
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+      if (c < r) {
+        Y[c * ldy + (long)b * MB + i] = (i > c && i < m) ? a[h][c] : 0.0;
+        if (i < r) Rst[c * ldr + (long)b * r + i] = (i <= c) ? a[h][c] : 0.0;
+      }
+    }
   }
 }
 
 // Q block b = H_0 .. H_{r-1} [C_b; 0], C_b = rows [b*r, b*r+r) of Cst (col-major, ldc).
-template <int RM>
-__global__ __launch_bounds__(MB) void k_qr_apply(const double* __restrict__ Y, long ldy, long rows,
+template <int RM, int RPL = QRShape<RM>::RPL, int MB = QRShape<RM>::MBR>
+__global__ __launch_bounds__(64) void k_qr_apply(const double* __restrict__ Y, long ldy, long rows,
                                                  int r, const double* __restrict__ tau,
                                                  const double* __restrict__ Cst, long ldc,
                                                  double* __restrict__ Q, long ldq) {
-  __shared__ double T[MB * RM];
-  __shared__ double red[8];
-  __shared__ double sh[4];
+  __shared__ double buf[64 * (RM + 1) + RM];
   const int b = blockIdx.x;
-  const int i = threadIdx.x;
-  const long row = (long)b * MB + i;
+  const int lane = threadIdx.x;
   const int m = (int)max((long)r, min((long)MB, rows - (long)b * MB));
-  for (int c = 0; c < r; ++c) T[i * RM + c] = (i < r) ? Cst[c * ldc + (long)b * r + i] : 0.0;
-  __syncthreads();
-  for (int k = r - 1; k >= 0; --k) {
-    const double tk = tau[(long)b * r + k];
-    if (tk == 0.0) continue;  // uniform across the block
-    const double vi = (i > k && i < m) ? Y[k * ldy + (long)b * MB + i] : (i == k ? 1.0 : 0.0);
-    for (int c = 0; c < r; ++c) {
-      double wsum = block_sum(vi * T[i * RM + c], red);
-      if (i == 0) sh[0] = wsum;
-      __syncthreads();
-      wsum = sh[0];
-      T[i * RM + c] -= tk * wsum * vi;
-      __syncthreads();
+  double y[RPL][RM];
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int i = lane + 64 * h;
+#pragma unroll
+    for (int c = 0; c < RM; ++c) y[h][c] = (i < r && c < r) ? Cst[c * ldc + (long)b * r + i] : 0.0;
+  }
+#pragma unroll
+  for (int k = RM - 1; k >= 0; --k) {
+   const double tk = k < r ? tau[(long)b * r + k] : 0.0;
+   if (tk != 0.0) {  // uniform across the wavefront
+    double v[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const int i = lane + 64 * h;
+      v[h] = (i > k && i < m) ? Y[k * ldy + (long)b * MB + i] : (i == k ? 1.0 : 0.0);
+    }
+    double wv[RM];
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+      double part = 0.0;
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) part += v[h] * y[h][c];
+      wv[c] = part;
+    }
+    wave_sums<RM>(wv, buf);
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+      if (c < r) {
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) y[h][c] -= tk * wv[c] * v[h];
+      }
+    }
+   }
+  }
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int i = lane + 64 * h;
+    const long row = (long)b * MB + i;
+    if (i < m && row < rows) {
+#pragma unroll
+      for (int c = 0; c < RM; ++c)
+        if (c < r) Q[c * ldq + row] = y[h][c];
     }
   }
-  if (i < m && row < rows)
-    for (int c = 0; c < r; ++c) Q[c * ldq + row] = T[i * RM + c];
 }
 
 // final sign fix: D = sign(diag R) (0 -> +1); R <- D R; C <- D (the top-level
@@ -293,19 +381,24 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
     L.A = cur;
     L.lda = ld;
     L.rows = rws;
-    L.nb = (int)((rws + la::MB - 1) / la::MB);
-    L.ldy = (long)L.nb * la::MB;
+    const int mbr = r <= 8 ? la::QRShape<8>::MBR : (r <= 16 ? la::QRShape<16>::MBR : la::QRShape<64>::MBR);
+    L.nb = (int)((rws + mbr - 1) / mbr);
+    L.ldy = (long)L.nb * mbr;
     L.ldr = (long)L.nb * r;
     const std::string t = tag + ".l" + std::to_string(depth);
     L.Y = (double*)ctx->buf(t + ".Y", (size_t)L.ldy * r * sizeof(double));
     L.tau = (double*)ctx->buf(t + ".tau", (size_t)L.nb * r * sizeof(double));
     L.Rst = (double*)ctx->buf(t + ".R", (size_t)L.ldr * r * sizeof(double));
-    if (r <= 16)
-      hipLaunchKernelGGL(la::k_qr_block<16>, dim3(L.nb), dim3(la::MB), 0, s, L.A, L.lda, L.rows, r,
-                         L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+    if (r <= 4)
+      hipLaunchKernelGGL(la::k_qr_block<4>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+    else if (r <= 8)
+      hipLaunchKernelGGL(la::k_qr_block<8>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+    else if (r <= 16)
+      hipLaunchKernelGGL(la::k_qr_block<16>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+    else if (r <= 32)
+      hipLaunchKernelGGL(la::k_qr_block<32>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
     else
-      hipLaunchKernelGGL(la::k_qr_block<64>, dim3(L.nb), dim3(la::MB), 0, s, L.A, L.lda, L.rows, r,
-                         L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+      hipLaunchKernelGGL(la::k_qr_block<64>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
     BLR_CHECK_LAUNCH();
     lv.push_back(L);
     if (L.nb == 1) break;
@@ -340,12 +433,16 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
       out = (double*)ctx->buf(tag + ".q" + std::to_string(l), (size_t)L.rows * r * sizeof(double));
       ldo = L.rows;
     }
-    if (r <= 16)
-      hipLaunchKernelGGL(la::k_qr_apply<16>, dim3(L.nb), dim3(la::MB), 0, s, L.Y, L.ldy, L.rows, r,
-                         L.tau, Cst, ldc, out, ldo);
+    if (r <= 4)
+      hipLaunchKernelGGL(la::k_qr_apply<4>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
+    else if (r <= 8)
+      hipLaunchKernelGGL(la::k_qr_apply<8>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
+    else if (r <= 16)
+      hipLaunchKernelGGL(la::k_qr_apply<16>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
+    else if (r <= 32)
+      hipLaunchKernelGGL(la::k_qr_apply<32>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
     else
-      hipLaunchKernelGGL(la::k_qr_apply<64>, dim3(L.nb), dim3(la::MB), 0, s, L.Y, L.ldy, L.rows, r,
-                         L.tau, Cst, ldc, out, ldo);
+      hipLaunchKernelGGL(la::k_qr_apply<64>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
     BLR_CHECK_LAUNCH();
     Cst = out;
     ldc = ldo;
