@@ -15,9 +15,10 @@
 //                  fields written coalesced (the only HBM-heavy output)
 //   k_reduce_all   sigma sums of all pair products for all radial nodes in
 //                  one launch (thread per grid point, pairs in registers)
-//   k_pair_spec    3D DFT of one pair product at one radial node, times the
-//                  radial weight, written as the half spectrum k_2 <= N/2
-//   k_final_fused  sum over radial nodes, 3D inverse DFT from the half
+//   k_pair_spec    3D DFTs of one pair product at a group of radial nodes,
+//                  times the radial weights, summed in registers and written
+//                  as one half spectrum (k_2 <= N/2) per group
+//   k_final_fused  sum over the groups, 3D inverse DFT from the half
 //                  spectrum, minus the loss, FP64 moment projection, store
 #include <cmath>
 #include <cstring>
@@ -187,43 +188,54 @@ __global__ __launch_bounds__(256) void k_reduce_all(const float* __restrict__ sh
 }
 
 // ------------------------------------------------------- pair transforms
-// workgroup = (pair p, radial node a); writes w_a(|k|^2) DFT(P_pa)/n for k_2 <= N/2
+// workgroup = (pair p, group g of ga consecutive radial nodes): for each node
+// a of the group, DFT(P_pa) times w_a(|k|^2)/n is added into a register
+// accumulator of the half spectrum k_2 <= N/2, written once per group.
 template <int N>
 __global__ __launch_bounds__(N * N) void k_pair_spec(const float* __restrict__ pa,
                                                      const float* __restrict__ fw,
                                                      float2* __restrict__ wsp, int P, int mrho,
-                                                     int nkk) {
+                                                     int nkk, int ga, int ng) {
   __shared__ float L[Geo<N>::LDS];
   constexpr int n = Geo<N>::n, H = Geo<N>::H;
   const int t = threadIdx.x;
   const int u = t / N, w = t % N;
   const int p = blockIdx.x % P;
-  const int a = blockIdx.x / P;
-  // stage along axis 0: thread (i1, i2) = (u, w), coalesced loads
-  const float* src = pa + ((long)a * P + p) * n + u * N + w;
-  float re[N], im[N];
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    re[j] = src[j * N * N];
-    im[j] = 0.f;
-  }
-  fft::dft<float, N, -1>(re, im);
-  exchange<N, 0, 1>(re, L, u, w);
-  exchange<N, 0, 1>(im, L, u, w);
-  fft::dft<float, N, -1>(re, im);
-  exchange<N, 1, 2>(re, L, u, w);
-  exchange<N, 1, 2>(im, L, u, w);
-  fft::dft<float, N, -1>(re, im);
-  // thread (k0, k1) = (u, w) holds k2 = 0..N-1; keep k2 <= N/2
+  const int g = blockIdx.x / P;
+  const int a0 = g * ga, a1 = min(mrho, a0 + ga);
   const int k0 = ctr<N>(u), k1 = ctr<N>(w);
-  const float* f = fw + (long)a * nkk;
-  float2* dst = wsp + (((long)p * mrho + a) * N * N + (long)(u * N + w)) * H;
+  float accr[H], acci[H];
 #pragma unroll
-  for (int j = 0; j < H; ++j) {
-    const int k2 = ctr<N>(j);
-    const float wt = f[k0 * k0 + k1 * k1 + k2 * k2];
-    dst[j] = make_float2(wt * re[j], wt * im[j]);
+  for (int j = 0; j < H; ++j) accr[j] = acci[j] = 0.f;
+  for (int a = a0; a < a1; ++a) {
+    // stage along axis 0: thread (i1, i2) = (u, w), coalesced loads
+    const float* src = pa + ((long)a * P + p) * n + u * N + w;
+    float re[N], im[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      re[j] = src[j * N * N];
+      im[j] = 0.f;
+    }
+    fft::dft<float, N, -1>(re, im);
+    exchange<N, 0, 1>(re, L, u, w);
+    exchange<N, 0, 1>(im, L, u, w);
+    fft::dft<float, N, -1>(re, im);
+    exchange<N, 1, 2>(re, L, u, w);
+    exchange<N, 1, 2>(im, L, u, w);
+    fft::dft<float, N, -1>(re, im);
+    // thread (k0, k1) = (u, w) holds k2 = 0..N-1; keep k2 <= N/2
+    const float* f = fw + (long)a * nkk;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const int k2 = ctr<N>(j);
+      const float wt = f[k0 * k0 + k1 * k1 + k2 * k2];
+      accr[j] += wt * re[j];
+      acci[j] += wt * im[j];
+    }
   }
+  float2* dst = wsp + (((long)p * ng + g) * N * N + (long)(u * N + w)) * H;
+#pragma unroll
+  for (int j = 0; j < H; ++j) dst[j] = make_float2(accr[j], acci[j]);
 }
 
 // --------------------------------------------------------------- final
@@ -238,7 +250,7 @@ __global__ __launch_bounds__(N * N) void k_final_fused(const float2* __restrict_
                                                        const float* __restrict__ vp,
                                                        const float* __restrict__ lam,
                                                        const int* __restrict__ pidx, float* Q,
-                                                       int P, int mrho, FinalArgs fa) {
+                                                       int P, int ng, FinalArgs fa) {
   constexpr int n = Geo<N>::n, H = Geo<N>::H, NT = Geo<N>::NT;
   constexpr int HP = H + 1;  // padded half row
   __shared__ float LR[N * N * HP];
@@ -259,8 +271,8 @@ __global__ __launch_bounds__(N * N) void k_final_fused(const float2* __restrict_
         re[j] = 0.f;
         im[j] = 0.f;
       }
-      for (int a = 0; a < mrho; ++a) {
-        const float2* src = wsp + ((long)p * mrho + a) * N * N * H + (long)k1 * H + k2;
+      for (int g = 0; g < ng; ++g) {
+        const float2* src = wsp + ((long)p * ng + g) * N * N * H + (long)k1 * H + k2;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           const float2 v = src[(long)j * N * H];
@@ -382,7 +394,9 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   const long nfields = (long)rb * h.mrho * h.nbp;
   float* Sh = (float*)ctx->buf("fast.Sh", (size_t)rb * h.mrho * h.msig * n * sizeof(float));
   float* Pa = (float*)ctx->buf("fast.Pa", (size_t)h.mrho * P * n * sizeof(float));
-  float2* Wsp = (float2*)ctx->buf("fast.Wsp", (size_t)P * h.mrho * N * N * H * sizeof(float2));
+  const int ga = 4;                          // radial nodes per pair-transform workgroup
+  const int ng = (h.mrho + ga - 1) / ga;
+  float2* Wsp = (float2*)ctx->buf("fast.Wsp", (size_t)P * ng * N * N * H * sizeof(float2));
   std::vector<int> idx(3 * P);
   for (int p = 0; p < P; ++p) {
     idx[p] = pl.li[p];
@@ -422,9 +436,9 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   }
   // transforms of the pair products with the radial weights
   timed_begin("fast.pair_spec",
-              (double)P * h.mrho * ((double)n * sizeof(float) + (double)N * N * H * sizeof(float2)), s);
-  hipLaunchKernelGGL(k_pair_spec<N>, dim3(P * h.mrho), dim3(N * N), 0, s, Pa, (const float*)tb.fw,
-                     Wsp, P, h.mrho, h.nkk);
+              (double)P * ((double)h.mrho * n * sizeof(float) + (double)ng * N * N * H * sizeof(float2)), s);
+  hipLaunchKernelGGL(k_pair_spec<N>, dim3(P * ng), dim3(N * N), 0, s, Pa, (const float*)tb.fw,
+                     Wsp, P, h.mrho, h.nkk, ga, ng);
   BLR_CHECK_LAUNCH();
   timed_end(s);
   // radial sum, inverse transform, loss, projection
@@ -435,9 +449,8 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   for (int i = 0; i < 25 && i < (int)h.minv.size(); ++i) fa.minv[i] = h.minv[i];
   fa.conserve = conserve ? 1 : 0;
   timed_begin("fast.final",
-              (double)P * ((double)h.mrho * N * N * H * sizeof(float2) + 5.0 * n * sizeof(float)), s);
-  hipLaunchKernelGGL(k_final_fused<N>, dim3(P), dim3(N * N), 0, s, Wsp, Vp, Lam, didx, Q, P, h.mrho,
-                     fa);
+              (double)P * ((double)ng * N * N * H * sizeof(float2) + 5.0 * n * sizeof(float)), s);
+  hipLaunchKernelGGL(k_final_fused<N>, dim3(P), dim3(N * N), 0, s, Wsp, Vp, Lam, didx, Q, P, ng, fa);
   BLR_CHECK_LAUNCH();
   timed_end(s);
 }

@@ -579,24 +579,10 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
       fill<double>(s, Shat, (long)rk * rk, 0.0);
       hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r * r, 256)), dim3(256), 0, s, Sw, r, r, Shat, rk);
       BLR_CHECK_LAUNCH();
-      double* tmpX = w.get("tmpX", (size_t)rk * nx);
-      double* tmpV = w.get("tmpV", (size_t)rk * n);
       double* Sx = w.get("Sx", (size_t)rk * rk);
       double* Sv = w.get("Sv", (size_t)rk * rk);
-      hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)rk * nx, 256)), dim3(256), 0, s, Xw,
-                         (long)rk * nx, std::sqrt(dx), tmpX);
-      BLR_CHECK_LAUNCH();
-      tsqr(ctx, tmpX, nx, nx, rk, Xw, nx, Sx, "qr.x");
-      hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)rk * nx, 256)), dim3(256), 0, s, Xw,
-                         (long)rk * nx, 1.0 / std::sqrt(dx), Xw);
-      BLR_CHECK_LAUNCH();
-      hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)rk * n, 256)), dim3(256), 0, s, Vw,
-                         (long)rk * n, std::sqrt(dvd), tmpV);
-      BLR_CHECK_LAUNCH();
-      tsqr(ctx, tmpV, n, n, rk, Vw, n, Sv, "qr.v");
-      hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)rk * n, 256)), dim3(256), 0, s, Vw,
-                         (long)rk * n, 1.0 / std::sqrt(dvd), Vw);
-      BLR_CHECK_LAUNCH();
+      tsqr(ctx, Xw, nx, nx, rk, Xw, nx, Sx, "qr.x", std::sqrt(dx), 1.0 / std::sqrt(dx));
+      tsqr(ctx, Vw, n, n, rk, Vw, n, Sv, "qr.v", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
       hipLaunchKernelGGL(dk::k_sq, dim3(1), dim3(1024), 0, s, Sx, Shat, Sv, rk, Sw);
       BLR_CHECK_LAUNCH();
       r = rk;
@@ -654,7 +640,6 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   double* dK = w.get("dK", (size_t)r * nx);
   double* X1 = w.get("X1", (size_t)r * nx);
   double* S1 = w.get("S1", (size_t)r * r);
-  double* tmpK = w.get("tmpK", (size_t)r * nx);
   hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, Xw, r, nx, Sw, r, K);
   BLR_CHECK_LAUNCH();
   hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
@@ -662,13 +647,7 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   hipLaunchKernelGGL(dk::k_kstep, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, K, gh, r, nx, dx,
                      dt, Ap, Am, Cj, P, dpidx, dpidx + P, K1, dK);
   BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, K1,
-                     (long)r * nx, std::sqrt(dx), tmpK);
-  BLR_CHECK_LAUNCH();
-  tsqr(ctx, tmpK, nx, nx, r, X1, nx, S1, "qr.k");
-  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, X1,
-                     (long)r * nx, 1.0 / std::sqrt(dx), X1);
-  BLR_CHECK_LAUNCH();
+  tsqr(ctx, K1, nx, nx, r, X1, nx, S1, "qr.k", std::sqrt(dx), 1.0 / std::sqrt(dx));
 
   // ---------------------------------------------------------- S-step
   const int ncols = 2 * r + P;
@@ -711,16 +690,9 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
     timed_end(s);
   }
   double* V1 = w.get("V1", (size_t)r * n);
-  double* tmpL = w.get("tmpL", (size_t)r * n);
   double* Rl = w.get("Rl", (size_t)r * r);
   double* Snew = w.get("Snew", (size_t)r * r);
-  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, L1,
-                     (long)r * n, std::sqrt(dvd), tmpL);
-  BLR_CHECK_LAUNCH();
-  tsqr(ctx, tmpL, n, n, r, V1, n, Rl, "qr.l");
-  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, V1,
-                     (long)r * n, 1.0 / std::sqrt(dvd), V1);
-  BLR_CHECK_LAUNCH();
+  tsqr(ctx, L1, n, n, r, V1, n, Rl, "qr.l", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
   hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(1024), 0, s, Rl, r, Snew);
   BLR_CHECK_LAUNCH();
 
@@ -837,14 +809,10 @@ void state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0, int r
     return (double*)ctx->buf(std::string("sff.") + nm, c * sizeof(double));
   };
   // f0 row-major (nx x n) is column-major (n x nx) with ld n
-  double* A = get("A", (size_t)nx * n);
   double* Qf = get("Q", (size_t)nx * n);
   double* Rf = get("R", (size_t)nx * nx);
   double* Rt = get("Rt", (size_t)nx * nx);
-  hipLaunchKernelGGL(dk::k_scale_copy, dim3(blocks((long)nx * n, 256)), dim3(256), 0, s, f0,
-                     (long)nx * n, std::sqrt(dx * dvd), A);
-  BLR_CHECK_LAUNCH();
-  tsqr(ctx, A, n, n, nx, Qf, n, Rf, "qr.sff");
+  tsqr(ctx, f0, n, n, nx, Qf, n, Rf, "qr.sff", std::sqrt(dx * dvd), 1.0);
   // sqrt(w) f0 = R^T Q^T ; R^T = U Sig W^T -> left factors U, right Q W
   hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(1024), 0, s, Rf, nx, Rt);
   BLR_CHECK_LAUNCH();

@@ -2,9 +2,9 @@
 //
 //   tsqr   Householder QR of a tall-skinny column-major matrix (rows >= 1,
 //          1 <= r <= 64) as a reduction tree: blocks of 256 rows are
-//          factorised by one wavefront each (up to four rows per lane held
-//          in registers, all column sums of a reflector in one LDS pass;
-//          rows padded with zeros to at least r), their R factors are stacked and factorised again until
+//          factorised by one 256-thread workgroup each (up to four rows
+//          per thread held in registers, all column sums of a reflector in
+//          one two-stage LDS pass; rows padded with zeros to at least r), their R factors are stacked and factorised again until
 //          one block remains; Q is formed top-down by applying each level's
 //          reflectors to the next level's Q block.  The sign of every row of R
 //          is chosen so that diag(R) >= 0 (the top-level Q starts from
@@ -34,71 +34,81 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
-// rows per lane for a column bucket RM: one wavefront per block, no barriers
+// Blocks of QT = 256 threads (4 wavefronts); each thread owns RPL rows of the
+// block in registers, so a block covers MBR = 256 * RPL rows and a
+// 32768-row matrix is a two-level tree for r <= 16.
+constexpr int QT = 256;
 template <int RM>
 struct QRShape {
-  static constexpr int RPL = RM <= 8 ? 4 : (RM <= 16 ? 2 : 1);
-  static constexpr int MBR = 64 * RPL;  // rows per block
+  static constexpr int RPL = RM <= 16 ? 4 : (RM <= 32 ? 2 : 1);
+  static constexpr int MBR = QT * RPL;  // rows per block
 };
 
-// Column sums over the 64 lanes of a wavefront for NV values per lane,
-// identical in every lane: partials go to LDS, lane c adds column c in lane
-// order (fixed order, so the result is reproducible), and every lane reads
-// the NV sums back.  buf: LDS scratch of 64 * (NV + 1) + NV doubles.
+// Column sums over the block for NV values per thread, identical in every
+// thread: per-thread partials to LDS, 16 threads per column add 16 rows each,
+// one thread per column adds the 16 partial sums (fixed order everywhere, so
+// the result is reproducible), then every thread reads the NV totals.
+// buf: LDS scratch of QT * (NV + 1) + 16 * NV + NV doubles.
 template <int NV>
-__device__ __forceinline__ void wave_sums(double (&v)[NV], double* buf) {
-  const int lane = threadIdx.x;
-  double* part = buf;
-  double* tot = buf + 64 * (NV + 1);
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* buf) {
+  const int t = threadIdx.x;
+  double* part = buf;                       // [QT][NV + 1]
+  double* mid = buf + QT * (NV + 1);        // [16][NV]
+  double* tot = mid + 16 * NV;              // [NV]
 #pragma unroll
-  for (int c = 0; c < NV; ++c) part[lane * (NV + 1) + c] = v[c];
+  for (int c = 0; c < NV; ++c) part[t * (NV + 1) + c] = v[c];
   __syncthreads();
-  if (lane < NV) {
+  for (int e = t; e < 16 * NV; e += QT) {
+    const int c = e / 16, seg = e % 16;
     double s = 0.0;
-    for (int l = 0; l < 64; ++l) s += part[l * (NV + 1) + lane];
-    tot[lane] = s;
+    for (int l = 0; l < 16; ++l) s += part[(seg * 16 + l) * (NV + 1) + c];
+    mid[seg * NV + c] = s;
+  }
+  __syncthreads();
+  for (int c = t; c < NV; c += QT) {
+    double s = 0.0;
+    for (int seg = 0; seg < 16; ++seg) s += mid[seg * NV + c];
+    tot[c] = s;
   }
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < NV; ++c) v[c] = tot[c];
-  __syncthreads();
 }
 
-// Factor block b of a column-major matrix A (rows x r, leading dim lda):
-// one wavefront, lane l owns rows l, l+64, l+128, l+192 of the block in
-// registers.  Writes the Householder vectors (unit diagonal implied) into Y
-// (leading dim ldy = padded rows), tau[b*r + k], and R into Rst (stacked
-// column-major, leading dim nb*r), rows [b*r, b*r + r).
+// Factor block b of a column-major matrix A (rows x r, leading dim lda),
+// scaled by in_scale on load.  Thread t owns rows t, t+QT, .. of the block.
+// Writes the Householder vectors (unit diagonal implied) into Y (leading dim
+// ldy = padded rows), tau[b*r + k], and R into Rst (stacked column-major,
+// leading dim nb*r), rows [b*r, b*r + r).
 template <int RM, int RPL = QRShape<RM>::RPL, int MB = QRShape<RM>::MBR>
-__global__ __launch_bounds__(64) void k_qr_block(const double* __restrict__ A, long lda, long rows,
-                                                 int r, double* __restrict__ Y, long ldy,
-                                                 double* __restrict__ tau,
+__global__ __launch_bounds__(QT) void k_qr_block(const double* __restrict__ A, long lda, long rows,
+                                                 int r, double in_scale, double* __restrict__ Y,
+                                                 long ldy, double* __restrict__ tau,
                                                  double* __restrict__ Rst, long ldr) {
-  __shared__ double buf[64 * (RM + 1) + RM];
+  __shared__ double buf[QT * (RM + 1) + 16 * RM + RM];
   const int b = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x;
   const int m = (int)max((long)r, min((long)MB, rows - (long)b * MB));  // active rows (>= r)
   double a[RPL][RM];
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
-    const int i = lane + 64 * h;
+    const int i = t + QT * h;
     const long row = (long)b * MB + i;
     const bool live = i < m && row < rows;
 #pragma unroll
-    for (int c = 0; c < RM; ++c) a[h][c] = (live && c < r) ? A[c * lda + row] : 0.0;
+    for (int c = 0; c < RM; ++c) a[h][c] = (live && c < r) ? in_scale * A[c * lda + row] : 0.0;
   }
 #pragma unroll
   for (int k = 0; k < RM; ++k) {
    if (k < r) {
-    double tl = 0.0, xl = 0.0;
+    double tx[2] = {0.0, 0.0};
 #pragma unroll
     for (int h = 0; h < RPL; ++h) {
-      const int i = lane + 64 * h;
-      if (i > k && i < m) tl += a[h][k] * a[h][k];
-      if (i == k) xl = a[h][k];
+      const int i = t + QT * h;
+      if (i > k && i < m) tx[0] += a[h][k] * a[h][k];
+      if (i == k) tx[1] = a[h][k];
     }
-    double tx[2] = {tl, xl};
-    wave_sums<2>(tx, buf);
+    block_sums<2>(tx, buf);
     const double tail = tx[0], x0 = tx[1];
     double beta, tk, scale;
     if (tail == 0.0) {
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(64) void k_qr_block(const double* __restrict__ A, l
     double vi[RPL];
 #pragma unroll
     for (int h = 0; h < RPL; ++h) {
-      const int i = lane + 64 * h;
+      const int i = t + QT * h;
       vi[h] = 0.0;
       if (i > k && i < m) {
         a[h][k] *= scale;
@@ -134,7 +144,7 @@ __global__ __launch_bounds__(64) void k_qr_block(const double* __restrict__ A, l
       }
       wv[c] = part;
     }
-    wave_sums<RM>(wv, buf);
+    block_sums<RM>(wv, buf);
 #pragma unroll
     for (int c = k + 1; c < RM; ++c) {
       if (c < r) {
@@ -142,12 +152,12 @@ __global__ __launch_bounds__(64) void k_qr_block(const double* __restrict__ A, l
         for (int h = 0; h < RPL; ++h) a[h][c] -= tk * wv[c] * vi[h];
       }
     }
-    if (lane == 0) tau[(long)b * r + k] = tk;
+    if (t == 0) tau[(long)b * r + k] = tk;
    }
   }
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
-    const int i = lane + 64 * h;
+    const int i = t + QT * h;
 #pragma unroll
     for (int c = 0; c < RM; ++c) {
       if (c < r) {
@@ -158,31 +168,32 @@ __global__ __launch_bounds__(64) void k_qr_block(const double* __restrict__ A, l
   }
 }
 
-// Q block b = H_0 .. H_{r-1} [C_b; 0], C_b = rows [b*r, b*r+r) of Cst (col-major, ldc).
+// Q block b = out_scale * H_0 .. H_{r-1} [C_b; 0], C_b = rows [b*r, b*r+r) of Cst.
 template <int RM, int RPL = QRShape<RM>::RPL, int MB = QRShape<RM>::MBR>
-__global__ __launch_bounds__(64) void k_qr_apply(const double* __restrict__ Y, long ldy, long rows,
+__global__ __launch_bounds__(QT) void k_qr_apply(const double* __restrict__ Y, long ldy, long rows,
                                                  int r, const double* __restrict__ tau,
                                                  const double* __restrict__ Cst, long ldc,
-                                                 double* __restrict__ Q, long ldq) {
-  __shared__ double buf[64 * (RM + 1) + RM];
+                                                 double out_scale, double* __restrict__ Q,
+                                                 long ldq) {
+  __shared__ double buf[QT * (RM + 1) + 16 * RM + RM];
   const int b = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int t = threadIdx.x;
   const int m = (int)max((long)r, min((long)MB, rows - (long)b * MB));
   double y[RPL][RM];
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
-    const int i = lane + 64 * h;
+    const int i = t + QT * h;
 #pragma unroll
     for (int c = 0; c < RM; ++c) y[h][c] = (i < r && c < r) ? Cst[c * ldc + (long)b * r + i] : 0.0;
   }
 #pragma unroll
   for (int k = RM - 1; k >= 0; --k) {
    const double tk = k < r ? tau[(long)b * r + k] : 0.0;
-   if (tk != 0.0) {  // uniform across the wavefront
+   if (tk != 0.0) {  // uniform across the block
     double v[RPL];
 #pragma unroll
     for (int h = 0; h < RPL; ++h) {
-      const int i = lane + 64 * h;
+      const int i = t + QT * h;
       v[h] = (i > k && i < m) ? Y[k * ldy + (long)b * MB + i] : (i == k ? 1.0 : 0.0);
     }
     double wv[RM];
@@ -193,7 +204,7 @@ __global__ __launch_bounds__(64) void k_qr_apply(const double* __restrict__ Y, l
       for (int h = 0; h < RPL; ++h) part += v[h] * y[h][c];
       wv[c] = part;
     }
-    wave_sums<RM>(wv, buf);
+    block_sums<RM>(wv, buf);
 #pragma unroll
     for (int c = 0; c < RM; ++c) {
       if (c < r) {
@@ -205,12 +216,12 @@ __global__ __launch_bounds__(64) void k_qr_apply(const double* __restrict__ Y, l
   }
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
-    const int i = lane + 64 * h;
+    const int i = t + QT * h;
     const long row = (long)b * MB + i;
     if (i < m && row < rows) {
 #pragma unroll
       for (int c = 0; c < RM; ++c)
-        if (c < r) Q[c * ldq + row] = y[h][c];
+        if (c < r) Q[c * ldq + row] = out_scale * y[h][c];
     }
   }
 }
@@ -361,7 +372,7 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
 
 // ------------------------------------------------------------------- host --
 void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, long ldq,
-          double* R_rowmajor, const std::string& tag) {
+          double* R_rowmajor, const std::string& tag, double in_scale, double out_scale) {
   require(r >= 1 && r <= 64, "tsqr: r must be in [1, 64]");
   require(rows >= 1, "tsqr: rows must be >= 1");
   hipStream_t s = ctx->stream;
@@ -381,7 +392,7 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
     L.A = cur;
     L.lda = ld;
     L.rows = rws;
-    const int mbr = r <= 8 ? la::QRShape<8>::MBR : (r <= 16 ? la::QRShape<16>::MBR : la::QRShape<64>::MBR);
+    const int mbr = r <= 16 ? la::QRShape<16>::MBR : (r <= 32 ? la::QRShape<32>::MBR : la::QRShape<64>::MBR);
     L.nb = (int)((rws + mbr - 1) / mbr);
     L.ldy = (long)L.nb * mbr;
     L.ldr = (long)L.nb * r;
@@ -390,15 +401,15 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
     L.tau = (double*)ctx->buf(t + ".tau", (size_t)L.nb * r * sizeof(double));
     L.Rst = (double*)ctx->buf(t + ".R", (size_t)L.ldr * r * sizeof(double));
     if (r <= 4)
-      hipLaunchKernelGGL(la::k_qr_block<4>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+      hipLaunchKernelGGL(la::k_qr_block<4>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
     else if (r <= 8)
-      hipLaunchKernelGGL(la::k_qr_block<8>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+      hipLaunchKernelGGL(la::k_qr_block<8>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
     else if (r <= 16)
-      hipLaunchKernelGGL(la::k_qr_block<16>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+      hipLaunchKernelGGL(la::k_qr_block<16>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
     else if (r <= 32)
-      hipLaunchKernelGGL(la::k_qr_block<32>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+      hipLaunchKernelGGL(la::k_qr_block<32>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
     else
-      hipLaunchKernelGGL(la::k_qr_block<64>, dim3(L.nb), dim3(64), 0, s, L.A, L.lda, L.rows, r, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+      hipLaunchKernelGGL(la::k_qr_block<64>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
     BLR_CHECK_LAUNCH();
     lv.push_back(L);
     if (L.nb == 1) break;
@@ -434,15 +445,15 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
       ldo = L.rows;
     }
     if (r <= 4)
-      hipLaunchKernelGGL(la::k_qr_apply<4>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
+      hipLaunchKernelGGL(la::k_qr_apply<4>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
     else if (r <= 8)
-      hipLaunchKernelGGL(la::k_qr_apply<8>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
+      hipLaunchKernelGGL(la::k_qr_apply<8>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
     else if (r <= 16)
-      hipLaunchKernelGGL(la::k_qr_apply<16>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
+      hipLaunchKernelGGL(la::k_qr_apply<16>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
     else if (r <= 32)
-      hipLaunchKernelGGL(la::k_qr_apply<32>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
+      hipLaunchKernelGGL(la::k_qr_apply<32>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
     else
-      hipLaunchKernelGGL(la::k_qr_apply<64>, dim3(L.nb), dim3(64), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, out, ldo);
+      hipLaunchKernelGGL(la::k_qr_apply<64>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
     BLR_CHECK_LAUNCH();
     Cst = out;
     ldc = ldo;
