@@ -2,9 +2,9 @@
 //
 //   tsqr   Householder QR of a tall-skinny column-major matrix (rows >= 1,
 //          1 <= r <= 64) as a reduction tree: blocks of 256 rows are
-//          factorised by one 256-thread workgroup each (up to four rows
-//          per thread held in registers, all column sums of a reflector in
-//          one two-stage LDS pass; rows padded with zeros to at least r), their R factors are stacked and factorised again until
+//          factorised by one wavefront each (up to four rows per lane held in
+//          registers, column sums by DPP cross-lane reductions, no barriers;
+//          rows padded with zeros to at least r), their R factors are stacked and factorised again until
 //          one block remains; Q is formed top-down by applying each level's
 //          reflectors to the next level's Q block.  The sign of every row of R
 //          is chosen so that diag(R) >= 0 (the top-level Q starts from
@@ -34,45 +34,46 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
-// Blocks of QT = 256 threads (4 wavefronts); each thread owns RPL rows of the
-// block in registers, so a block covers MBR = 256 * RPL rows and a
-// 32768-row matrix is a two-level tree for r <= 16.
-constexpr int QT = 256;
+// One wavefront per block; each lane owns RPL rows of the block in
+// registers, so a block covers MBR = 64 * RPL rows.
+constexpr int QT = 64;
 template <int RM>
 struct QRShape {
-  static constexpr int RPL = RM <= 16 ? 4 : (RM <= 32 ? 2 : 1);
+  static constexpr int RPL = (48 / RM) < 1 ? 1 : ((48 / RM) > 4 ? 4 : (48 / RM));
   static constexpr int MBR = QT * RPL;  // rows per block
 };
 
-// Column sums over the block for NV values per thread, identical in every
-// thread: per-thread partials to LDS, 16 threads per column add 16 rows each,
-// one thread per column adds the 16 partial sums (fixed order everywhere, so
-// the result is reproducible), then every thread reads the NV totals.
-// buf: LDS scratch of QT * (NV + 1) + 16 * NV + NV doubles.
+// Cross-lane move of a double with a DPP control (two 32-bit moves); lanes
+// whose source is outside the row read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes, returned to every lane: quad permutations and row
+// rotations sum each row of 16 lanes, two row broadcasts carry the row sums
+// into lane 63, whose value is read back as a scalar.  Fixed instruction
+// sequence, so the result is reproducible.
+__device__ __forceinline__ double wave_allsum(double x) {
+  x += dpp_move<0xb1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_move<0x4e>(x);   // quad_perm [2,3,0,1]
+  x += dpp_move<0x124>(x);  // row_ror:4
+  x += dpp_move<0x128>(x);  // row_ror:8
+  x += dpp_move<0x142>(x);  // row_bcast:15
+  x += dpp_move<0x143>(x);  // row_bcast:31
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int NV>
-__device__ __forceinline__ void block_sums(double (&v)[NV], double* buf) {
-  const int t = threadIdx.x;
-  double* part = buf;                       // [QT][NV + 1]
-  double* mid = buf + QT * (NV + 1);        // [16][NV]
-  double* tot = mid + 16 * NV;              // [NV]
+__device__ __forceinline__ void block_sums(double (&v)[NV], double*) {
 #pragma unroll
-  for (int c = 0; c < NV; ++c) part[t * (NV + 1) + c] = v[c];
-  __syncthreads();
-  for (int e = t; e < 16 * NV; e += QT) {
-    const int c = e / 16, seg = e % 16;
-    double s = 0.0;
-    for (int l = 0; l < 16; ++l) s += part[(seg * 16 + l) * (NV + 1) + c];
-    mid[seg * NV + c] = s;
-  }
-  __syncthreads();
-  for (int c = t; c < NV; c += QT) {
-    double s = 0.0;
-    for (int seg = 0; seg < 16; ++seg) s += mid[seg * NV + c];
-    tot[c] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < NV; ++c) v[c] = tot[c];
+  for (int c = 0; c < NV; ++c) v[c] = wave_allsum(v[c]);
 }
 
 // Factor block b of a column-major matrix A (rows x r, leading dim lda),
@@ -85,10 +86,13 @@ __global__ __launch_bounds__(QT) void k_qr_block(const double* __restrict__ A, l
                                                  int r, double in_scale, double* __restrict__ Y,
                                                  long ldy, double* __restrict__ tau,
                                                  double* __restrict__ Rst, long ldr) {
-  __shared__ double buf[QT * (RM + 1) + 16 * RM + RM];
+  double* buf = nullptr;
   const int b = blockIdx.x;
   const int t = threadIdx.x;
   const int m = (int)max((long)r, min((long)MB, rows - (long)b * MB));  // active rows (>= r)
+  // The pivot column is always a[.][0]: after step k the finished column is
+  // written out and the remaining columns shift left, so every register index
+  // is static while the column loop stays rolled.
   double a[RPL][RM];
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
@@ -98,15 +102,14 @@ __global__ __launch_bounds__(QT) void k_qr_block(const double* __restrict__ A, l
 #pragma unroll
     for (int c = 0; c < RM; ++c) a[h][c] = (live && c < r) ? in_scale * A[c * lda + row] : 0.0;
   }
-#pragma unroll
-  for (int k = 0; k < RM; ++k) {
-   if (k < r) {
+#pragma unroll 1
+  for (int k = 0; k < r; ++k) {
     double tx[2] = {0.0, 0.0};
 #pragma unroll
     for (int h = 0; h < RPL; ++h) {
       const int i = t + QT * h;
-      if (i > k && i < m) tx[0] += a[h][k] * a[h][k];
-      if (i == k) tx[1] = a[h][k];
+      if (i > k && i < m) tx[0] += a[h][0] * a[h][0];
+      if (i == k) tx[1] = a[h][0];
     }
     block_sums<2>(tx, buf);
     const double tail = tx[0], x0 = tx[1];
@@ -127,43 +130,37 @@ __global__ __launch_bounds__(QT) void k_qr_block(const double* __restrict__ A, l
       const int i = t + QT * h;
       vi[h] = 0.0;
       if (i > k && i < m) {
-        a[h][k] *= scale;
-        vi[h] = a[h][k];
+        a[h][0] *= scale;
+        vi[h] = a[h][0];
       } else if (i == k) {
-        a[h][k] = beta;
+        a[h][0] = beta;
         vi[h] = 1.0;
       }
     }
-    double wv[RM];
+    // columns past r are zero and stay zero, so no column guard is needed
+    double wv[RM - 1];
 #pragma unroll
-    for (int c = 0; c < RM; ++c) {
+    for (int c = 1; c < RM; ++c) {
       double part = 0.0;
-      if (c > k && c < r) {
 #pragma unroll
-        for (int h = 0; h < RPL; ++h) part += vi[h] * a[h][c];
-      }
-      wv[c] = part;
+      for (int h = 0; h < RPL; ++h) part += vi[h] * a[h][c];
+      wv[c - 1] = part;
     }
-    block_sums<RM>(wv, buf);
+    block_sums<RM - 1>(wv, buf);
 #pragma unroll
-    for (int c = k + 1; c < RM; ++c) {
-      if (c < r) {
+    for (int c = 1; c < RM; ++c) {
 #pragma unroll
-        for (int h = 0; h < RPL; ++h) a[h][c] -= tk * wv[c] * vi[h];
-      }
+      for (int h = 0; h < RPL; ++h) a[h][c] -= tk * wv[c - 1] * vi[h];
     }
     if (t == 0) tau[(long)b * r + k] = tk;
-   }
-  }
 #pragma unroll
-  for (int h = 0; h < RPL; ++h) {
-    const int i = t + QT * h;
+    for (int h = 0; h < RPL; ++h) {
+      const int i = t + QT * h;
+      Y[k * ldy + (long)b * MB + i] = (i > k && i < m) ? a[h][0] : 0.0;
+      if (i < r) Rst[k * ldr + (long)b * r + i] = (i <= k) ? a[h][0] : 0.0;
 #pragma unroll
-    for (int c = 0; c < RM; ++c) {
-      if (c < r) {
-        Y[c * ldy + (long)b * MB + i] = (i > c && i < m) ? a[h][c] : 0.0;
-        if (i < r) Rst[c * ldr + (long)b * r + i] = (i <= c) ? a[h][c] : 0.0;
-      }
+      for (int c = 0; c + 1 < RM; ++c) a[h][c] = a[h][c + 1];
+      a[h][RM - 1] = 0.0;
     }
   }
 }
@@ -175,7 +172,7 @@ __global__ __launch_bounds__(QT) void k_qr_apply(const double* __restrict__ Y, l
                                                  const double* __restrict__ Cst, long ldc,
                                                  double out_scale, double* __restrict__ Q,
                                                  long ldq) {
-  __shared__ double buf[QT * (RM + 1) + 16 * RM + RM];
+  double* buf = nullptr;
   const int b = blockIdx.x;
   const int t = threadIdx.x;
   const int m = (int)max((long)r, min((long)MB, rows - (long)b * MB));
@@ -371,6 +368,18 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
 }  // namespace la
 
 // ------------------------------------------------------------------- host --
+// column bucket of the QR kernels for rank r
+template <class F>
+static void qr_bucket(int r, F&& f) {
+  if (r <= 4) f(std::integral_constant<int, 4>{});
+  else if (r <= 8) f(std::integral_constant<int, 8>{});
+  else if (r <= 12) f(std::integral_constant<int, 12>{});
+  else if (r <= 16) f(std::integral_constant<int, 16>{});
+  else if (r <= 24) f(std::integral_constant<int, 24>{});
+  else if (r <= 32) f(std::integral_constant<int, 32>{});
+  else f(std::integral_constant<int, 64>{});
+}
+
 void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, long ldq,
           double* R_rowmajor, const std::string& tag, double in_scale, double out_scale) {
   require(r >= 1 && r <= 64, "tsqr: r must be in [1, 64]");
@@ -392,7 +401,8 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
     L.A = cur;
     L.lda = ld;
     L.rows = rws;
-    const int mbr = r <= 16 ? la::QRShape<16>::MBR : (r <= 32 ? la::QRShape<32>::MBR : la::QRShape<64>::MBR);
+    int mbr = 0;
+    qr_bucket(r, [&](auto rm) { mbr = la::QRShape<decltype(rm)::value>::MBR; });
     L.nb = (int)((rws + mbr - 1) / mbr);
     L.ldy = (long)L.nb * mbr;
     L.ldr = (long)L.nb * r;
@@ -400,16 +410,11 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
     L.Y = (double*)ctx->buf(t + ".Y", (size_t)L.ldy * r * sizeof(double));
     L.tau = (double*)ctx->buf(t + ".tau", (size_t)L.nb * r * sizeof(double));
     L.Rst = (double*)ctx->buf(t + ".R", (size_t)L.ldr * r * sizeof(double));
-    if (r <= 4)
-      hipLaunchKernelGGL(la::k_qr_block<4>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
-    else if (r <= 8)
-      hipLaunchKernelGGL(la::k_qr_block<8>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
-    else if (r <= 16)
-      hipLaunchKernelGGL(la::k_qr_block<16>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
-    else if (r <= 32)
-      hipLaunchKernelGGL(la::k_qr_block<32>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
-    else
-      hipLaunchKernelGGL(la::k_qr_block<64>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r, depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+    qr_bucket(r, [&](auto rm) {
+      constexpr int RM = decltype(rm)::value;
+      hipLaunchKernelGGL(la::k_qr_block<RM>, dim3(L.nb), dim3(la::QT), 0, s, L.A, L.lda, L.rows, r,
+                         depth == 0 ? in_scale : 1.0, L.Y, L.ldy, L.tau, L.Rst, L.ldr);
+    });
     BLR_CHECK_LAUNCH();
     lv.push_back(L);
     if (L.nb == 1) break;
@@ -444,16 +449,11 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
       out = (double*)ctx->buf(tag + ".q" + std::to_string(l), (size_t)L.rows * r * sizeof(double));
       ldo = L.rows;
     }
-    if (r <= 4)
-      hipLaunchKernelGGL(la::k_qr_apply<4>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
-    else if (r <= 8)
-      hipLaunchKernelGGL(la::k_qr_apply<8>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
-    else if (r <= 16)
-      hipLaunchKernelGGL(la::k_qr_apply<16>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
-    else if (r <= 32)
-      hipLaunchKernelGGL(la::k_qr_apply<32>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
-    else
-      hipLaunchKernelGGL(la::k_qr_apply<64>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau, Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
+    qr_bucket(r, [&](auto rm) {
+      constexpr int RM = decltype(rm)::value;
+      hipLaunchKernelGGL(la::k_qr_apply<RM>, dim3(L.nb), dim3(la::QT), 0, s, L.Y, L.ldy, L.rows, r, L.tau,
+                         Cst, ldc, l == 0 ? out_scale : 1.0, out, ldo);
+    });
     BLR_CHECK_LAUNCH();
     Cst = out;
     ldc = ldo;
