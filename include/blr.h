@@ -13,8 +13,10 @@
  *     unless stated otherwise, and are owned by the caller.  The library owns
  *     only its context (tables, workspace, events).
  *   - Work is issued on the context's HIP stream.  blr_collision_pairs is
- *     asynchronous; blr_dlr_step and blr_steady_solve synchronise once per
- *     step (the rank decision needs the singular values on the host).
+ *     asynchronous; blr_dlr_step and blr_steady_solve wait once per step
+ *     (the rank decision needs the singular values on the host), and the
+ *     write of the new state after that wait stays queued on the stream:
+ *     readers on another stream order themselves after it.
  *   - One context per host thread.
  *
  * Velocity grid (Sec. 2.1: the collision solver is a discrete velocity method
@@ -124,7 +126,10 @@ typedef struct {
  *   X  r_cap rows of nx   (row i = X_i)
  *   S  r_cap x r_cap row-major, leading r x r block used
  *   V  r_cap rows of n^d  (row j = V_j)
- * r is updated by the adaptive steps; 1 <= r <= r_cap <= 64. */
+ * r is updated by the adaptive steps; 1 <= r <= r_cap <= 64.  step counts
+ * the steps taken; seed is reserved (the step draws no random numbers: the
+ * random block X_h of the basis augmentation, Sec. 3.1, multiplies a zero
+ * block of S, so the step never reads it and uses zero rows). */
 typedef struct {
   int32_t r, r_cap;
   double* X;
@@ -138,6 +143,11 @@ typedef struct {
 #define BLR_STEP_ADD            0x1u  /* add the boundary basis first (Sec. 3.1) */
 #define BLR_STEP_DROP           0x2u  /* drop small singular values of S (Sec. 3.2) */
 #define BLR_STEP_FP64_COLLISION 0x4u  /* pair collisions in FP64 (default FP32) */
+/* Orthogonalise the added boundary functions against V by Householder QR of
+ * [V; V_b] (default: two projection passes with a Cholesky normalisation,
+ * which fall back to Householder QR by themselves when a new function lies
+ * almost inside span V).  Both give the same step up to rounding. */
+#define BLR_STEP_HOUSEHOLDER_ADD 0x8u
 
 typedef struct {
   double dt;
@@ -147,6 +157,11 @@ typedef struct {
   uint32_t flags;
 } blr_step_params;
 
+/* err: residual estimate of the step; err_ada: the same after the drop
+ * (exact, Sec. 5.1); drop_tol = c_drop * err; ranks before the step, added
+ * boundary functions, after the drop.  ms_collision: GPU time of the pair
+ * collisions; ms_step: GPU time from the start of the step to the rank
+ * decision (the final write of the state is not included). */
 typedef struct {
   double err, err_ada, drop_tol;
   int32_t r_in, r_added, r_out;

@@ -24,20 +24,43 @@ void* blr_ctx_t::buf(const std::string& name, size_t bytes) {
 void* blr_ctx_t::upload(const std::string& name, const void* host, size_t bytes) {
   void* dst = buf(name, bytes);
   if (bytes == 0) return dst;
-  // the pinned stage is reused: wait for the previous upload to be consumed
-  if (stage_done) BLR_HIP(hipEventSynchronize(stage_done));
-  if (stage_bytes < bytes) {
-    if (stage) BLR_HIP(hipHostFree(stage));
-    stage = nullptr;
-    stage_bytes = 0;
-    BLR_HIP(hipHostMalloc(&stage, bytes));
-    stage_bytes = bytes;
+  auto& last = uploaded[name];
+  const unsigned char* hb = (const unsigned char*)host;
+  if (last.first == dst && last.second.size() == bytes && std::memcmp(last.second.data(), hb, bytes) == 0)
+    return dst;
+  StageSlot& sl = stage[stage_next];
+  stage_next = (stage_next + 1) % kStageSlots;
+  if (sl.done) BLR_HIP(hipEventSynchronize(sl.done));
+  if (sl.bytes < bytes) {
+    if (sl.p) BLR_HIP(hipHostFree(sl.p));
+    sl.p = nullptr;
+    sl.bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 64 << 10);
+    BLR_HIP(hipHostMalloc(&sl.p, want));
+    sl.bytes = want;
   }
-  std::memcpy(stage, host, bytes);
-  BLR_HIP(hipMemcpyAsync(dst, stage, bytes, hipMemcpyHostToDevice, stream));
-  if (!stage_done) BLR_HIP(hipEventCreateWithFlags(&stage_done, hipEventDisableTiming));
-  BLR_HIP(hipEventRecord(stage_done, stream));
+  std::memcpy(sl.p, host, bytes);
+  BLR_HIP(hipMemcpyAsync(dst, sl.p, bytes, hipMemcpyHostToDevice, stream));
+  if (!sl.done) BLR_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+  BLR_HIP(hipEventRecord(sl.done, stream));
+  last.first = dst;
+  last.second.assign(hb, hb + bytes);
   return dst;
+}
+
+void* blr_ctx_t::host_readback(size_t bytes) {
+  if (readback_bytes < bytes) {
+    if (readback) {
+      BLR_HIP(hipStreamSynchronize(stream));
+      BLR_HIP(hipHostFree(readback));
+    }
+    readback = nullptr;
+    readback_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 4096);
+    BLR_HIP(hipHostMalloc(&readback, want));
+    readback_bytes = want;
+  }
+  return readback;
 }
 
 void blr_ctx_t::release_all() {
@@ -46,10 +69,15 @@ void blr_ctx_t::release_all() {
     if (kv.second.p) (void)hipFree(kv.second.p);
   bufs.clear();
   tables.clear();
-  if (stage) (void)hipHostFree(stage);
-  stage = nullptr;
-  if (stage_done) (void)hipEventDestroy(stage_done);
-  stage_done = nullptr;
+  for (auto& sl : stage) {
+    if (sl.p) (void)hipHostFree(sl.p);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    sl = StageSlot{};
+  }
+  uploaded.clear();
+  if (readback) (void)hipHostFree(readback);
+  readback = nullptr;
+  readback_bytes = 0;
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   timer.release();

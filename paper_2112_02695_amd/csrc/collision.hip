@@ -450,6 +450,7 @@ void fill(hipStream_t s, T* p, long count, T v) {
 }
 template void fill<float>(hipStream_t, float*, long, float);
 template void fill<double>(hipStream_t, double*, long, double);
+template void fill<int>(hipStream_t, int*, long, int);
 
 // FP64 least-squares moment projection of each row of Q (one block per row):
 // m = C q, lambda = (C C^T)^-1 m, q <- q - C^T lambda, with C the rows

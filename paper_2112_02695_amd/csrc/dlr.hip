@@ -308,22 +308,6 @@ __global__ void k_fb(const double* __restrict__ K, const double* __restrict__ V,
   Fb[g.n + q] = v1 < 0 ? fR[q] : b;
 }
 
-// standard normal entries from a counter-based hash (splitmix64 + Box-Muller)
-__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-__global__ void k_randn(double* out, long count, unsigned long long seed) {
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= count) return;
-  const unsigned long long h1 = mix64(seed ^ (2ull * e)), h2 = mix64(seed ^ (2ull * e + 1));
-  const double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740993.0);
-  const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
-  out[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-}
-
 // small dense algebra (one block)
 // S2 = S1 + dt (Dp Ap^T + Dm Am^T - T C^T);  dS = S2 - S1
 __global__ void k_supdate(const double* S1, const double* Dp, const double* Dm, const double* T,
@@ -341,20 +325,6 @@ __global__ void k_supdate(const double* S1, const double* Dp, const double* Dm, 
 
 __global__ void k_transpose(const double* A, int r, double* B) {
   for (int t = threadIdx.x; t < r * r; t += blockDim.x) B[(t % r) * r + t / r] = A[t];
-}
-
-// out = A * B^T-style products on small matrices: out = Sx Shat Sv^T (r x r)
-__global__ void k_sq(const double* Sx, const double* Sh, const double* Sv, int r, double* out) {
-  for (int t = threadIdx.x; t < r * r; t += blockDim.x) {
-  const int i = t / r, j = t % r;
-  double s = 0.0;
-  for (int a = 0; a < r; ++a) {
-    double u = 0.0;
-    for (int b = 0; b < r; ++b) u += Sh[a * r + b] * Sv[j * r + b];
-    s += Sx[i * r + a] * u;
-  }
-  out[t] = s;
-  }
 }
 
 // err^2 from the pieces; sums written to res[0..5]
@@ -434,6 +404,99 @@ __global__ void k_copy_S(const double* src, int lds_src, int r, double* dst, int
   dst[(t / r) * lds_dst + t % r] = src[(t / r) * lds_src + t % r];
 }
 
+// out (rk x rk, row-major) = [[S, 0], [0, 0]] with S r x r (leading dim r)
+__global__ void k_pad_S(const double* S, int r, int rk, double* out) {
+  for (int t = threadIdx.x; t < rk * rk; t += blockDim.x) {
+    const int i = t / rk, j = t % rk;
+    out[t] = (i < r && j < r) ? S[i * r + j] : 0.0;
+  }
+}
+
+// out = A B^T for r x r row-major A, B
+__global__ void k_mul_bt(const double* A, const double* B, int r, double* out) {
+  for (int t = threadIdx.x; t < r * r; t += blockDim.x) {
+    const int i = t / r, j = t % r;
+    double s = 0.0;
+    for (int k = 0; k < r; ++k) s += A[i * r + k] * B[j * r + k];
+    out[t] = s;
+  }
+}
+
+// One pass of block Gram-Schmidt with Cholesky normalisation of rb <= 2 new
+// rows B (stored right after the r rows of V, row length n) against the r
+// rows of V, orthonormal in <.,.>_v.  With G = <B, [V; B]>_v (rb x (r + rb),
+// row-major), C = G[:, :r] and M = G[:, r:] - C C^T = L L^T (Cholesky),
+//   B <- L^{-1} (B - C V),
+// so that [V; B] spans the same space with orthonormal rows.  Two passes give
+// orthogonality to rounding as long as each new row keeps a part outside
+// span V of relative size above 1e-6; flag[0] is set (pass 0 writes, pass 1
+// ors) when a pivot of M is below 1e-12 of the matching diagonal of G or not
+// finite, and the caller then orthogonalises by Householder QR instead.
+__global__ __launch_bounds__(256) void k_orth_pass(double* __restrict__ V, int r, int rb, long n,
+                                                   const double* __restrict__ G, int pass,
+                                                   int* __restrict__ flag) {
+  __shared__ double C[2 * 64];
+  __shared__ double Li[4];  // L^{-1}, row-major 2 x 2
+  const int ld = r + rb;
+  for (int e = threadIdx.x; e < rb * r; e += blockDim.x) C[e] = G[(e / r) * ld + e % r];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int i = 0; i < rb; ++i)
+      for (int k = 0; k < rb; ++k) {
+        double t = G[i * ld + r + k];
+        for (int j = 0; j < r; ++j) t -= C[i * r + j] * C[k * r + j];
+        m[i][k] = t;
+      }
+    bool bad = !(m[0][0] > 1e-12 * G[r]) || !isfinite(m[0][0]);
+    double l00 = bad ? 1.0 : sqrt(m[0][0]), l10 = 0.0, l11 = 1.0;
+    if (rb == 2) {
+      l10 = m[1][0] / l00;
+      const double piv = m[1][1] - l10 * l10;
+      const bool bad1 = !(piv > 1e-12 * G[ld + r + 1]) || !isfinite(piv) || !isfinite(l10);
+      bad = bad || bad1;
+      l11 = bad1 ? 1.0 : sqrt(piv);
+    }
+    if (bad) {
+      l00 = 1.0;
+      l10 = 0.0;
+      l11 = 1.0;
+    }
+    Li[0] = 1.0 / l00;
+    Li[1] = 0.0;
+    Li[2] = -l10 / (l00 * l11);
+    Li[3] = 1.0 / l11;
+    if (blockIdx.x == 0) flag[0] = (pass == 0 ? 0 : flag[0]) | (bad ? 1 : 0);
+  }
+  __syncthreads();
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double b0 = V[(long)r * n + e];
+  double b1 = rb == 2 ? V[(long)(r + 1) * n + e] : 0.0;
+  for (int j = 0; j < r; ++j) {
+    const double v = V[(long)j * n + e];
+    b0 -= C[j] * v;
+    if (rb == 2) b1 -= C[r + j] * v;
+  }
+  V[(long)r * n + e] = Li[0] * b0;
+  if (rb == 2) V[(long)(r + 1) * n + e] = Li[2] * b0 + Li[3] * b1;
+}
+
+// Read-back record of a step: res[0..3], flag, sigma_b[0..1], pad,
+// sigma[0..r), g[0..r)  (absent inputs read as 0).
+__global__ void k_pack(const double* res, const int* flag, const double* sb, const double* sg,
+                       const double* g, int r, double* out) {
+  const int t = threadIdx.x;
+  if (t < 4) out[t] = res[t];
+  if (t == 4) out[4] = flag ? (double)flag[0] : 0.0;
+  if (t == 5 || t == 6) out[t] = sb ? sb[t - 5] : 0.0;
+  if (t == 7) out[7] = 0.0;
+  for (int i = t; i < r; i += blockDim.x) {
+    out[8 + i] = sg ? sg[i] : 0.0;
+    out[8 + r + i] = g ? g[i] : 0.0;
+  }
+}
+
 }  // namespace dk
 
 // ------------------------------------------------------------------ host --
@@ -482,11 +545,6 @@ void vgram(StepWork& w, const double* A, int ra, const TB* B, int rb, int mode, 
   vgram_multi<TB>(w, A, ra, B, rb, {{mode, out}}, scale);
 }
 
-void d2h(blr_ctx ctx, void* host, const void* dev, size_t bytes) {
-  BLR_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
-  BLR_HIP(hipStreamSynchronize(ctx->stream));
-}
-
 void validate_problem(const blr_problem* pb, const blr_state* st) {
   require(pb && st, "null problem or state");
   require(pb->nx >= 2 && pb->nx <= (1 << 20), "problem.nx must be in [2, 2^20]");
@@ -500,24 +558,38 @@ void validate_problem(const blr_problem* pb, const blr_state* st) {
 
 }  // namespace
 
-void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_params* sp,
-              blr_step_info* info) {
-  validate_problem(pb, st);
-  require(sp != nullptr, "null step params");
-  require(sp->dt > 0 && std::isfinite(sp->dt), "step.dt must be positive");
-  const int r_max = std::min(sp->r_max > 0 ? sp->r_max : st->r_cap, st->r_cap);
-  const int r_min = std::max(1, std::min(sp->r_min, r_max));
-  const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;
+namespace {
+
+// How the boundary basis is added in one attempt of a step: rb functions,
+// orthogonalised against V by two projection passes or by Householder QR.
+struct Attempt {
+  int rb;
+  bool householder;
+};
+
+// Device-side results of one attempt, the host read-back and the buffers
+// the commit reads.
+struct Outcome {
+  int r = 0;                 // rank after the add
+  double res[4] = {0, 0, 0, 0};
+  bool orth_failed = false;
+  double sb[2] = {0, 0};     // singular values of F_b (when the add ran)
+  std::vector<double> sg, g; // singular values of S^{n+1}, err_ada terms (drop only)
+  double *X1 = nullptr, *V1 = nullptr, *Snew = nullptr, *U = nullptr, *Wm = nullptr,
+         *sgd = nullptr;
+};
+
+// Everything up to the rank decision, then one read-back and one wait.
+void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const blr_step_params* sp,
+                  const HostTables& h, bool add, Attempt at, Outcome& o) {
   StepWork w{ctx, ctx->stream, {h.L, h.dv, h.N, h.d, h.n}, pb->nx, h.n,
              (pb->x_hi - pb->x_lo) / pb->nx, std::pow(h.dv, h.d)};
   hipStream_t s = w.s;
   const int nx = w.nx, n = w.n;
   const double dx = w.dx, dvd = w.dvd, dt = sp->dt;
-  blr_step_info inf{};
-  inf.r_in = st->r;
   BLR_HIP(hipEventRecord(ctx->ev[0], s));
 
-  // working copies (rank up to r_cap); the caller's state is written only at the end
+  // working copies (rank up to r_cap); the caller's state is written only at commit
   const int rc = st->r_cap;
   double* Xw = w.get("Xw", (size_t)rc * nx);
   double* Vw = w.get("Vw", (size_t)rc * n);
@@ -528,20 +600,22 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r * r, 256)), dim3(256), 0, s, st->S, rc, r, Sw, r);
   BLR_CHECK_LAUNCH();
 
-  // velocity-side boundary integrals of the current basis
   double* ginL = w.get("ginL", 64);
   double* ginR = w.get("ginR", 64);
   double* MoL = w.get("MoL", 64 * 64);
   double* MoR = w.get("MoR", 64 * 64);
   double* gh = w.get("ghost", 128);
   double* K = w.get("K", (size_t)rc * nx);
-  auto boundary_integrals = [&](const double* Vb, int rr) {
-    vgram<double>(w, Vb, rr, pb->f_left, 1, dk::W_IN_LEFT, dvd, ginL);
-    vgram<double>(w, Vb, rr, pb->f_right, 1, dk::W_IN_RIGHT, dvd, ginR);
-  };
+  int* flag = (int*)ctx->buf("dlr.flag", 256);
+  const double* sbd = nullptr;
 
   // ---------------------------------------------------------- add basis
-  if ((sp->flags & BLR_STEP_ADD) && r < r_max) {
+  // F_b = [boundary rows] = U_b Sig_b (right singular vectors); the rb
+  // leading right singular vectors are the rows of Sig_b^{-1} U_b^T F_b, and
+  // their positive scale does not matter for the orthogonalisation, so the
+  // new rows are U_b[:, :rb]^T F_b.  X gains zero rows: with S^ = [[S, 0],
+  // [0, 0]] the product X^ S^ (all the step reads of X^n) is unchanged.
+  if (add) {
     hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, Xw, r, nx, Sw, r,
                        K);
     BLR_CHECK_LAUNCH();
@@ -549,46 +623,53 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
     hipLaunchKernelGGL(dk::k_fb, dim3(blocks(n, 256)), dim3(256), 0, s, K, Vw, r, nx, pb->f_left,
                        pb->f_right, w.g, Fb);
     BLR_CHECK_LAUNCH();
-    double* QF = w.get("QF", (size_t)2 * n);
     double* RF = w.get("RF", 4);
-    tsqr(ctx, Fb, n, n, 2, QF, n, RF, "qr.fb");
-    // F_b = R_F^T Q_F^T;  R_F^T = U Sig W^T  ->  right singular vectors Q_F W
+    tsqr(ctx, Fb, n, n, 2, nullptr, 0, RF, "qr.fb");
     double* RFt = w.get("RFt", 4);
     hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(64), 0, s, RF, 2, RFt);
     BLR_CHECK_LAUNCH();
     double* Ub = w.get("Ub", 4);
     double* sb = w.get("sb", 2);
     double* Wb = w.get("Wb", 4);
-    svd_small(ctx, RFt, 2, Ub, sb, Wb);
-    double sbh[2];
-    d2h(ctx, sbh, sb, sizeof(sbh));
-    int rb = 0;
-    for (int k = 0; k < 2; ++k) rb += sbh[k] > sp->add_tol ? 1 : 0;
-    rb = std::min(rb, r_max - r);
+    svd_small(ctx, RFt, 2, Ub, sb, Wb);  // F_b = R_F^T Q_F^T,  R_F^T = U_b Sig_b W_b^T
+    sbd = sb;
+    const int rb = at.rb;
     if (rb > 0) {
-      // V^ = [V; (Q_F W)^T[:rb]],  X^ = [X, X_h],  S^ = blockdiag(S, 0)
-      hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), rb), dim3(256), 0, s, QF, 2, (long)n,
-                         Wb, 2, rb, 1.0, Vw + (size_t)r * n, (long)n);
-      BLR_CHECK_LAUNCH();
-      hipLaunchKernelGGL(dk::k_randn, dim3(blocks((long)rb * nx, 256)), dim3(256), 0, s,
-                         Xw + (size_t)r * nx, (long)rb * nx,
-                         (unsigned long long)(st->seed * 0x100000001B3ull + (uint64_t)st->step));
+      double* Vb = Vw + (size_t)r * n;
+      hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), rb), dim3(256), 0, s, Fb, 2, (long)n,
+                         Ub, 2, rb, 1.0, Vb, (long)n);
       BLR_CHECK_LAUNCH();
       const int rk = r + rb;
+      fill<double>(s, Xw + (size_t)r * nx, (long)rb * nx, 0.0);
       double* Shat = w.get("Shat", (size_t)rk * rk);
-      fill<double>(s, Shat, (long)rk * rk, 0.0);
-      hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r * r, 256)), dim3(256), 0, s, Sw, r, r, Shat, rk);
+      hipLaunchKernelGGL(dk::k_pad_S, dim3(1), dim3(256), 0, s, Sw, r, rk, Shat);
       BLR_CHECK_LAUNCH();
-      double* Sx = w.get("Sx", (size_t)rk * rk);
-      double* Sv = w.get("Sv", (size_t)rk * rk);
-      tsqr(ctx, Xw, nx, nx, rk, Xw, nx, Sx, "qr.x", std::sqrt(dx), 1.0 / std::sqrt(dx));
-      tsqr(ctx, Vw, n, n, rk, Vw, n, Sv, "qr.v", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
-      hipLaunchKernelGGL(dk::k_sq, dim3(1), dim3(1024), 0, s, Sx, Shat, Sv, rk, Sw);
-      BLR_CHECK_LAUNCH();
+      if (!at.householder) {
+        // [V; Vb] with V orthonormal: two projection passes keep V and
+        // orthonormalise Vb against it; S^ is unchanged (the triangular
+        // factor is [[I, 0], [C, L]] and S^ has zero rows and columns there)
+        double* G = w.get("orthG", (size_t)2 * 66);
+        for (int pass = 0; pass < 2; ++pass) {
+          vgram<double>(w, Vb, rb, Vw, rk, dk::W_ONE, dvd, G);
+          hipLaunchKernelGGL(dk::k_orth_pass, dim3(blocks(n, 256)), dim3(256), 0, s, Vw, r, rb, (long)n,
+                             G, pass, flag);
+          BLR_CHECK_LAUNCH();
+        }
+        hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(rk * rk, 256)), dim3(256), 0, s, Shat, rk, rk, Sw,
+                           rk);
+        BLR_CHECK_LAUNCH();
+      } else {
+        // Householder QR of [V; Vb]^T (weighted): V^ = Sv^T V_q, S <- S^ Sv^T
+        double* Sv = w.get("Sv", (size_t)rk * rk);
+        tsqr(ctx, Vw, n, n, rk, Vw, n, Sv, "qr.v", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
+        hipLaunchKernelGGL(dk::k_mul_bt, dim3(1), dim3(1024), 0, s, Shat, Sv, rk, Sw);
+        BLR_CHECK_LAUNCH();
+      }
       r = rk;
-      inf.r_added = rb;
     }
   }
+  if (!(add && at.rb > 0 && !at.householder)) fill<int>(s, flag, 1, 0);
+  o.r = r;
 
   // ------------------------------------------------------- collisions
   const int P = r * (r + 1) / 2;
@@ -633,7 +714,8 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
     vgram<double>(w, Vw, r, (const double*)Qs, P, dk::W_ONE, dvd, Cj);
   else
     vgram<float>(w, Vw, r, (const float*)Qs, P, dk::W_ONE, dvd, Cj);
-  boundary_integrals(Vw, r);
+  vgram<double>(w, Vw, r, pb->f_left, 1, dk::W_IN_LEFT, dvd, ginL);
+  vgram<double>(w, Vw, r, pb->f_right, 1, dk::W_IN_RIGHT, dvd, ginR);
 
   // ---------------------------------------------------------- K-step
   double* K1 = w.get("K1", (size_t)r * nx);
@@ -709,17 +791,18 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   hipLaunchKernelGGL(dk::k_err, dim3(1), dim3(256), 0, s, dK, (long)r * nx, dx, dS, r, GdL, kx, lv, res);
   BLR_CHECK_LAUNCH();
 
-  // ------------------------------------------------------------- drop
-  double* Xo = X1;
-  double* Vo = V1;
-  int r_out = r;
-  double resh[4];
+  // ---------------------------------------------- drop ingredients (device)
+  double* sg = nullptr;
+  double* gterm = nullptr;
+  o.X1 = X1;
+  o.V1 = V1;
+  o.Snew = Snew;
   if (sp->flags & BLR_STEP_DROP) {
     double* U = w.get("U", (size_t)r * r);
-    double* sg = w.get("sig", (size_t)r);
+    sg = w.get("sig", (size_t)r);
     double* Wm = w.get("W", (size_t)r * r);
     svd_small(ctx, Snew, r, U, sg, Wm);
-    // err_ada needs A = <X^n_k, X1_i>_x and B = <V^n_l, V1_j>_v
+    // err_ada needs A = <X^n_k, X1_i> and B = <V^n_l, V1_j>
     double* Aad = w.get("Aad", (size_t)r * r);
     double* Bad = w.get("Bad", (size_t)r * r);
     hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, Xw, r, nx, dx,
@@ -727,59 +810,117 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
                        nullptr);
     BLR_CHECK_LAUNCH();
     vgram<double>(w, Vw, r, V1, r, dk::W_ONE, dvd, Bad);
-    double* gterm = w.get("gterm", (size_t)r);
+    gterm = w.get("gterm", (size_t)r);
     hipLaunchKernelGGL(dk::k_fnD_terms, dim3(1), dim3(256), 0, s, Sw, Aad, U, sg, Wm, Bad, r, gterm);
     BLR_CHECK_LAUNCH();
-    // one synchronisation: residual pieces, singular values and err_ada terms
-    std::vector<double> sgh(r), gh(r);
-    BLR_HIP(hipMemcpyAsync(resh, res, sizeof(resh), hipMemcpyDeviceToHost, s));
-    BLR_HIP(hipMemcpyAsync(gh.data(), gterm, r * sizeof(double), hipMemcpyDeviceToHost, s));
-    d2h(ctx, sgh.data(), sg, r * sizeof(double));
-    const double err = std::sqrt(std::max(resh[0], 0.0));
-    require(std::isfinite(err), "non-finite residual", BLR_ERR_NUMERIC);
-    for (double v : sgh) require(std::isfinite(v), "non-finite singular value", BLR_ERR_NUMERIC);
+    o.U = U;
+    o.Wm = Wm;
+    o.sgd = sg;
+  }
+
+  // ------------------------------------- one read-back, one wait
+  BLR_HIP(hipEventRecord(ctx->ev[3], s));
+  const bool drop = (sp->flags & BLR_STEP_DROP) != 0;
+  const int nrb = drop ? r : 0;
+  double* pk = w.get("pack", (size_t)8 + 2 * 64);
+  hipLaunchKernelGGL(dk::k_pack, dim3(1), dim3(64), 0, s, res, flag, sbd, sg, gterm, nrb, pk);
+  BLR_CHECK_LAUNCH();
+  const size_t nbytes = (8 + 2 * (size_t)nrb) * sizeof(double);
+  double* hb = (double*)ctx->host_readback(nbytes);
+  BLR_HIP(hipMemcpyAsync(hb, pk, nbytes, hipMemcpyDeviceToHost, s));
+  BLR_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < 4; ++k) o.res[k] = hb[k];
+  o.orth_failed = hb[4] != 0.0;
+  o.sb[0] = hb[5];
+  o.sb[1] = hb[6];
+  o.sg.assign(hb + 8, hb + 8 + nrb);
+  o.g.assign(hb + 8 + nrb, hb + 8 + 2 * nrb);
+}
+
+}  // namespace
+
+void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_params* sp,
+              blr_step_info* info) {
+  validate_problem(pb, st);
+  require(sp != nullptr, "null step params");
+  require(sp->dt > 0 && std::isfinite(sp->dt), "step.dt must be positive");
+  const int r_max = std::min(sp->r_max > 0 ? sp->r_max : st->r_cap, st->r_cap);
+  const int r_min = std::max(1, std::min(sp->r_min, r_max));
+  const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;
+  hipStream_t s = ctx->stream;
+  const int nx = pb->nx, n = h.n, rc = st->r_cap;
+  blr_step_info inf{};
+  inf.r_in = st->r;
+
+  // The number of boundary functions to add is known only from the singular
+  // values of F_b on the device.  The step runs with the count of the
+  // previous step (2 at first) and is repeated, from the unchanged state,
+  // when the read-back shows another count or a failed projection.
+  const bool add = (sp->flags & BLR_STEP_ADD) && st->r < r_max;
+  const int room = r_max - st->r;
+  Attempt at{add ? std::min(ctx->add_hint < 0 ? 2 : ctx->add_hint, room) : 0,
+             (sp->flags & BLR_STEP_HOUSEHOLDER_ADD) != 0};
+  Outcome o;
+  for (int attempt = 0;; ++attempt) {
+    require(attempt < 4, "boundary basis: no consistent attempt", BLR_ERR_NUMERIC);
+    o = Outcome{};
+    step_attempt(ctx, pb, st, sp, h, add, at, o);
+    if (!add) break;
+    require(std::isfinite(o.sb[0]) && std::isfinite(o.sb[1]), "non-finite boundary singular value",
+            BLR_ERR_NUMERIC);
+    int cnt = 0;
+    for (double v : o.sb) cnt += v > sp->add_tol ? 1 : 0;
+    ctx->add_hint = cnt;
+    const int rb = std::min(cnt, room);
+    if (rb != at.rb) {
+      at = Attempt{rb, at.householder};
+      continue;
+    }
+    if (rb > 0 && o.orth_failed && !at.householder) {
+      at.householder = true;
+      continue;
+    }
+    break;
+  }
+  inf.r_added = at.rb;
+  const int r = o.r;
+
+  const double err = std::sqrt(std::max(o.res[0], 0.0));
+  require(std::isfinite(err), "non-finite residual", BLR_ERR_NUMERIC);
+  inf.err = err;
+  int r_out = r;
+  if (sp->flags & BLR_STEP_DROP) {
+    for (double v : o.sg) require(std::isfinite(v), "non-finite singular value", BLR_ERR_NUMERIC);
     const double tol = sp->c_drop * err;
     int keep = 0;
-    for (double v : sgh) keep += v >= tol ? 1 : 0;
+    for (double v : o.sg) keep += v >= tol ? 1 : 0;
     keep = std::max(std::min(keep, r_max), std::min(r_min, r));
     double sp2 = 0.0, fnD = 0.0;
     for (int q = keep; q < r; ++q) {
-      sp2 += sgh[q] * sgh[q];
-      fnD += gh[q];
+      sp2 += o.sg[q] * o.sg[q];
+      fnD += o.g[q];
     }
-    inf.err = err;
     inf.drop_tol = tol;
     // err_ada^2 = err^2 - |Sigma_perp|^2 + 2 <f^n, D>
     inf.err_ada = std::sqrt(std::max(err * err - sp2 + 2.0 * fnD, 0.0));
-    // rotate and truncate
-    double* Xd = w.get("Xd", (size_t)r * nx);
-    double* Vd = w.get("Vd", (size_t)r * n);
-    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(nx, 256), keep), dim3(256), 0, s, X1, r, (long)nx, U,
-                       r, keep, 1.0, Xd, (long)nx);
+    // commit: rotate and truncate straight into the state
+    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(nx, 256), keep), dim3(256), 0, s, o.X1, r, (long)nx,
+                       o.U, r, keep, 1.0, st->X, (long)nx);
     BLR_CHECK_LAUNCH();
-    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), keep), dim3(256), 0, s, V1, r, (long)n, Wm,
-                       r, keep, 1.0, Vd, (long)n);
+    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), keep), dim3(256), 0, s, o.V1, r, (long)n,
+                       o.Wm, r, keep, 1.0, st->V, (long)n);
     BLR_CHECK_LAUNCH();
-    hipLaunchKernelGGL(dk::k_diag, dim3(1), dim3(1024), 0, s, sg, keep, Snew, keep);
+    hipLaunchKernelGGL(dk::k_diag, dim3(1), dim3(1024), 0, s, o.sgd, keep, st->S, rc);
     BLR_CHECK_LAUNCH();
-    Xo = Xd;
-    Vo = Vd;
     r_out = keep;
   } else {
-    d2h(ctx, resh, res, sizeof(resh));
-    const double err = std::sqrt(std::max(resh[0], 0.0));
-    require(std::isfinite(err), "non-finite residual", BLR_ERR_NUMERIC);
-    inf.err = err;
     inf.err_ada = err;
+    BLR_HIP(hipMemcpyAsync(st->X, o.X1, (size_t)r * nx * 8, hipMemcpyDeviceToDevice, s));
+    BLR_HIP(hipMemcpyAsync(st->V, o.V1, (size_t)r * n * 8, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r * r, 256)), dim3(256), 0, s, o.Snew, r, r, st->S, rc);
+    BLR_CHECK_LAUNCH();
   }
-  // ------------------------------------------------------------ commit
-  BLR_HIP(hipMemcpyAsync(st->X, Xo, (size_t)r_out * nx * 8, hipMemcpyDeviceToDevice, s));
-  BLR_HIP(hipMemcpyAsync(st->V, Vo, (size_t)r_out * n * 8, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r_out * r_out, 256)), dim3(256), 0, s, Snew, r_out,
-                     r_out, st->S, rc);
-  BLR_CHECK_LAUNCH();
-  BLR_HIP(hipEventRecord(ctx->ev[3], s));
-  BLR_HIP(hipEventSynchronize(ctx->ev[3]));
+  // the commit stays queued on the stream; both timed spans ended before the wait
   float ms = 0.f;
   BLR_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
   inf.ms_step = ms;

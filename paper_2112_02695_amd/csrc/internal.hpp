@@ -113,16 +113,30 @@ struct blr_ctx_t {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   uint64_t calls = 0;
 
-  // pinned staging for small per-call host->device uploads
-  void* stage = nullptr;
-  size_t stage_bytes = 0;
-  size_t stage_used = 0;
-  hipEvent_t stage_done = nullptr;
+  // pinned staging for small per-call host->device uploads: a ring of slots,
+  // each reused only after its previous copy has completed
+  struct StageSlot {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+  };
+  static constexpr int kStageSlots = 8;
+  StageSlot stage[kStageSlots];
+  int stage_next = 0;
+  // last content uploaded to each named buffer (identical uploads are skipped)
+  std::map<std::string, std::pair<void*, std::vector<unsigned char>>> uploaded;
+  // pinned host buffer for small device->host read-backs
+  void* readback = nullptr;
+  size_t readback_bytes = 0;
+  // number of boundary basis functions added by the previous adaptive step
+  int add_hint = -1;
   blr::KernelTimer timer;
 
   void* buf(const std::string& name, size_t bytes);  // grow-only named workspace
   // copy a small host array to a named device buffer, asynchronously
   void* upload(const std::string& name, const void* host, size_t bytes);
+  // pinned host memory of at least `bytes` for read-backs (grow-only)
+  void* host_readback(size_t bytes);
   void release_all();
 };
 

@@ -136,6 +136,51 @@ def test_adaptive_steps_fp64(ctx, d, N, nx, r, m_rho):
         assert abs(info.err - info.err_ada) <= bound * (1 + 1e-12) + 1e-15
 
 
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(3, 16, 40, 4, 2)])
+def test_add_projection_matches_householder(ctx, d, N, nx, r, m_rho):
+    """The two ways of orthogonalising the added boundary functions give the
+    same step (only the span of [V; V_b] enters the K, S and L steps)."""
+    spec, prob, st, _ = _setup(d, N, nx, r, m_rho)
+    out = []
+    for extra in (0, blr.BLR_STEP_HOUSEHOLDER_ADD):
+        g = Gpu(ctx, spec, prob, st, r_cap=12)
+        flags = blr.BLR_STEP_FP64_COLLISION | blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | extra
+        infos = [ctx.dlr_step(g.pb, g.st, _params(0.05, flags, r_max=12)) for _ in range(2)]
+        X, S, V = g.factors()
+        assert np.abs(prob.dvd * V @ V.T - np.eye(g.st.r)).max() < 1e-12
+        out.append((g.full(), [(i.r_added, i.r_out, i.err, i.err_ada) for i in infos]))
+    (fa, ia), (fb, ib) = out
+    assert np.abs(fa - fb).max() < 1e-12 * np.abs(fb).max()
+    for a, b in zip(ia, ib):
+        assert a[:2] == b[:2]
+        assert abs(a[2] - b[2]) < 1e-10 * b[2] and abs(a[3] - b[3]) < 1e-10 * b[3]
+
+
+def test_add_count_change_is_redone(ctx):
+    """The step guesses the number of added boundary functions from the
+    previous step and redoes itself when the singular values disagree: a
+    step with add_tol so large that nothing is added (guess 2), then one
+    whose rank cap leaves room for one function (guess 0).  Both match the
+    oracle."""
+    spec, prob, st, _ = _setup(2, 16, 24, 3, 8)
+    g = Gpu(ctx, spec, prob, st, r_cap=12)
+    flags = blr.BLR_STEP_FP64_COLLISION | blr.BLR_STEP_ADD | blr.BLR_STEP_DROP
+    cur = st
+    plan = [(1e-10, 12), (1e10, 12), (1e-10, None)]
+    for k, (add_tol, r_max) in enumerate(plan):
+        r_max = r_max or g.st.r + 1
+        info = ctx.dlr_step(g.pb, g.st, blr.StepParams(0.05, 0.2, add_tol, 1, r_max, flags))
+        cur, oinfo = dlr.adaptive_step(cur, prob, 0.05, c=0.2, add_tol=add_tol, r_max=r_max,
+                                       rng=np.random.default_rng(k))
+        print(k, info.r_added, oinfo.r_added, info.r_out, oinfo.r_out, flush=True)
+        assert info.r_added == oinfo.r_added == [2, 0, 1][k]
+        assert info.r_out == oinfo.r_out
+        assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
+        assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
+        f_ref = cur.full()
+        assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+
+
 def test_steady_solve_runs_and_reports(ctx):
     spec, prob, st, _ = _setup(2, 16, 24, 3, 4)
     g = Gpu(ctx, spec, prob, st, r_cap=12)
