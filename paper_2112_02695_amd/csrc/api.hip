@@ -48,6 +48,14 @@ void* blr_ctx_t::upload(const std::string& name, const void* host, size_t bytes)
   return dst;
 }
 
+int blr_ctx_t::cu_count() {
+  if (ncu <= 0) {
+    BLR_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+    if (ncu <= 0) ncu = 1;
+  }
+  return ncu;
+}
+
 void* blr_ctx_t::host_readback(size_t bytes) {
   if (readback_bytes < bytes) {
     if (readback) {

@@ -394,7 +394,22 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   const long nfields = (long)rb * h.mrho * h.nbp;
   float* Sh = (float*)ctx->buf("fast.Sh", (size_t)rb * h.mrho * h.msig * n * sizeof(float));
   float* Pa = (float*)ctx->buf("fast.Pa", (size_t)h.mrho * P * n * sizeof(float));
-  const int ga = 4;                          // radial nodes per pair-transform workgroup
+  // radial nodes per pair-transform workgroup: one workgroup fills a CU, so
+  // the launch takes about ceil(P * ng / CUs) rounds of ga transforms; each
+  // extra group costs the final kernel one more half-spectrum read
+  int ga = 1;
+  {
+    double best = 1e300;
+    for (int g = 1; g <= h.mrho; ++g) {
+      const int ngc = (h.mrho + g - 1) / g;
+      const double rounds = std::ceil((double)P * ngc / ctx->cu_count());
+      const double cost = rounds * g + 0.1 * ngc;
+      if (cost < best - 1e-9) {
+        best = cost;
+        ga = g;
+      }
+    }
+  }
   const int ng = (h.mrho + ga - 1) / ga;
   float2* Wsp = (float2*)ctx->buf("fast.Wsp", (size_t)P * ng * N * N * H * sizeof(float2));
   std::vector<int> idx(3 * P);

@@ -130,6 +130,9 @@ struct blr_ctx_t {
   size_t readback_bytes = 0;
   // number of boundary basis functions added by the previous adaptive step
   int add_hint = -1;
+  // compute units of the device (queried once)
+  int ncu = 0;
+  int cu_count();
   blr::KernelTimer timer;
 
   void* buf(const std::string& name, size_t bytes);  // grow-only named workspace

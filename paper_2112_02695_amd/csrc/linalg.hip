@@ -259,54 +259,63 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
       V[c * 64 + t] = (t == c) ? 1.0 : 0.0;
     }
   __syncthreads();
-  const int rr = (r % 2) ? r + 1 : r;  // round-robin with a dummy column if odd
+  // Each round rotates rr/2 disjoint column pairs (circle method, with a
+  // dummy column when r is odd); a pair is handled by lpp lanes, each taking
+  // the rows i = sub, sub + lpp, ..; the three column sums are completed by
+  // butterfly exchanges inside the lane group, so every lane of the group
+  // computes the same rotation.
+  const int rr = (r % 2) ? r + 1 : r;
+  const int np = rr / 2;
+  const int lpp = np <= 8 ? 8 : (np <= 16 ? 4 : 2);
+  const int slot = t / lpp, sub = t % lpp;
+  (void)rot_any;
   for (int sw = 0; sw < sweeps; ++sw) {
-    if (t == 0) rot_any = 0;
-    __syncthreads();
+    int rotated = 0;
     for (int round = 0; round < rr - 1; ++round) {
-      // pair t: (p, q) from the circle method
-      if (t < rr / 2) {
-        int p, q;
-        if (t == 0) {
-          p = rr - 1;
-          q = round;
-        } else {
-          p = (round + t) % (rr - 1);
-          q = (round - t + rr - 1) % (rr - 1);
+      int p = 0, q = 0;
+      if (slot == 0) {
+        p = rr - 1;
+        q = round;
+      } else {
+        p = (round + slot) % (rr - 1);
+        q = (round - slot + rr - 1) % (rr - 1);
+      }
+      if (p > q) {
+        const int tmp = p;
+        p = q;
+        q = tmp;
+      }
+      const bool live = slot < np && q < r;
+      double al = 0, be = 0, ga = 0;
+      if (live)
+        for (int i = sub; i < r; i += lpp) {
+          const double x = B[p * 64 + i], y = B[q * 64 + i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
         }
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
+      for (int off = lpp / 2; off > 0; off >>= 1) {
+        al += __shfl_xor(al, off, 64);
+        be += __shfl_xor(be, off, 64);
+        ga += __shfl_xor(ga, off, 64);
+      }
+      if (live && fabs(ga) > 1e-300 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+        for (int i = sub; i < r; i += lpp) {
+          const double x = B[p * 64 + i], y = B[q * 64 + i];
+          B[p * 64 + i] = c * x - sn * y;
+          B[q * 64 + i] = sn * x + c * y;
+          const double vx = V[p * 64 + i], vy = V[q * 64 + i];
+          V[p * 64 + i] = c * vx - sn * vy;
+          V[q * 64 + i] = sn * vx + c * vy;
         }
-        if (q < r) {
-          double al = 0, be = 0, ga = 0;
-          for (int i = 0; i < r; ++i) {
-            const double x = B[p * 64 + i], y = B[q * 64 + i];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
-          }
-          if (fabs(ga) > 1e-300 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-            for (int i = 0; i < r; ++i) {
-              const double x = B[p * 64 + i], y = B[q * 64 + i];
-              B[p * 64 + i] = c * x - s * y;
-              B[q * 64 + i] = s * x + c * y;
-              const double vx = V[p * 64 + i], vy = V[q * 64 + i];
-              V[p * 64 + i] = c * vx - s * vy;
-              V[q * 64 + i] = s * vx + c * vy;
-            }
-            rot_any = 1;
-          }
-        }
+        rotated = 1;
       }
       __syncthreads();
     }
-    if (!rot_any) break;
-    __syncthreads();
+    if (!__any(rotated)) break;
   }
   if (t < r) {
     double s = 0;
