@@ -148,6 +148,11 @@ typedef struct {
  * which fall back to Householder QR by themselves when a new function lies
  * almost inside span V).  Both give the same step up to rounding. */
 #define BLR_STEP_HOUSEHOLDER_ADD 0x8u
+/* K- and L-step QR factorisations by Householder QR (default for r <= 16:
+ * shifted Cholesky QR in three passes, which falls back to Householder QR
+ * by itself when the matrix is numerically rank deficient).  Both give the
+ * same step up to rounding. */
+#define BLR_STEP_HOUSEHOLDER_QR  0x10u
 
 typedef struct {
   double dt;

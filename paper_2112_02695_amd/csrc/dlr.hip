@@ -482,7 +482,7 @@ __global__ __launch_bounds__(256) void k_orth_pass(double* __restrict__ V, int r
   if (rb == 2) V[(long)(r + 1) * n + e] = Li[2] * b0 + Li[3] * b1;
 }
 
-// Read-back record of a step: res[0..3], flag, sigma_b[0..1], pad,
+// Read-back record of a step: res[0..3], flag[0], sigma_b[0..1], flag[1],
 // sigma[0..r), g[0..r)  (absent inputs read as 0).
 __global__ void k_pack(const double* res, const int* flag, const double* sb, const double* sg,
                        const double* g, int r, double* out) {
@@ -490,7 +490,7 @@ __global__ void k_pack(const double* res, const int* flag, const double* sb, con
   if (t < 4) out[t] = res[t];
   if (t == 4) out[4] = flag ? (double)flag[0] : 0.0;
   if (t == 5 || t == 6) out[t] = sb ? sb[t - 5] : 0.0;
-  if (t == 7) out[7] = 0.0;
+  if (t == 7) out[7] = flag ? (double)flag[1] : 0.0;
   for (int i = t; i < r; i += blockDim.x) {
     out[8 + i] = sg ? sg[i] : 0.0;
     out[8 + r + i] = g ? g[i] : 0.0;
@@ -564,7 +564,8 @@ namespace {
 // orthogonalised against V by two projection passes or by Householder QR.
 struct Attempt {
   int rb;
-  bool householder;
+  bool householder;     // boundary functions by Householder QR
+  bool householder_qr;  // K- and L-step QRs by Householder QR (else Cholesky QR when r <= 16)
 };
 
 // Device-side results of one attempt, the host read-back and the buffers
@@ -573,6 +574,7 @@ struct Outcome {
   int r = 0;                 // rank after the add
   double res[4] = {0, 0, 0, 0};
   bool orth_failed = false;
+  bool qr_failed = false;
   double sb[2] = {0, 0};     // singular values of F_b (when the add ran)
   std::vector<double> sg, g; // singular values of S^{n+1}, err_ada terms (drop only)
   double *X1 = nullptr, *V1 = nullptr, *Snew = nullptr, *U = nullptr, *Wm = nullptr,
@@ -606,8 +608,17 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   double* MoR = w.get("MoR", 64 * 64);
   double* gh = w.get("ghost", 128);
   double* K = w.get("K", (size_t)rc * nx);
-  int* flag = (int*)ctx->buf("dlr.flag", 256);
+  int* flag = (int*)ctx->buf("dlr.flag", 256);  // [0] projection failed, [1] Cholesky QR failed
+  fill<int>(s, flag, 2, 0);
   const double* sbd = nullptr;
+  // QR of sqrt(w) M with Q scaled back by 1/sqrt(w)
+  auto qr = [&](const double* M, long ld, long rows, int rr, double* Qo, double* Ro, const char* tag,
+                double w) {
+    if (rr <= 16 && !at.householder_qr)
+      cholqr(ctx, M, ld, rows, rr, Qo, ld, Ro, tag, std::sqrt(w), 1.0 / std::sqrt(w), flag + 1);
+    else
+      tsqr(ctx, M, ld, rows, rr, Qo, ld, Ro, tag, std::sqrt(w), 1.0 / std::sqrt(w));
+  };
 
   // ---------------------------------------------------------- add basis
   // F_b = [boundary rows] = U_b Sig_b (right singular vectors); the rb
@@ -668,7 +679,6 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
       r = rk;
     }
   }
-  if (!(add && at.rb > 0 && !at.householder)) fill<int>(s, flag, 1, 0);
   o.r = r;
 
   // ------------------------------------------------------- collisions
@@ -729,7 +739,7 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   hipLaunchKernelGGL(dk::k_kstep, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, K, gh, r, nx, dx,
                      dt, Ap, Am, Cj, P, dpidx, dpidx + P, K1, dK);
   BLR_CHECK_LAUNCH();
-  tsqr(ctx, K1, nx, nx, r, X1, nx, S1, "qr.k", std::sqrt(dx), 1.0 / std::sqrt(dx));
+  qr(K1, nx, nx, r, X1, S1, "qr.k", dx);
 
   // ---------------------------------------------------------- S-step
   const int ncols = 2 * r + P;
@@ -774,7 +784,7 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   double* V1 = w.get("V1", (size_t)r * n);
   double* Rl = w.get("Rl", (size_t)r * r);
   double* Snew = w.get("Snew", (size_t)r * r);
-  tsqr(ctx, L1, n, n, r, V1, n, Rl, "qr.l", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
+  qr(L1, n, n, r, V1, Rl, "qr.l", dvd);
   hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(1024), 0, s, Rl, r, Snew);
   BLR_CHECK_LAUNCH();
 
@@ -831,6 +841,7 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   BLR_HIP(hipStreamSynchronize(s));
   for (int k = 0; k < 4; ++k) o.res[k] = hb[k];
   o.orth_failed = hb[4] != 0.0;
+  o.qr_failed = hb[7] != 0.0;
   o.sb[0] = hb[5];
   o.sb[1] = hb[6];
   o.sg.assign(hb + 8, hb + 8 + nrb);
@@ -859,12 +870,16 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   const bool add = (sp->flags & BLR_STEP_ADD) && st->r < r_max;
   const int room = r_max - st->r;
   Attempt at{add ? std::min(ctx->add_hint < 0 ? 2 : ctx->add_hint, room) : 0,
-             (sp->flags & BLR_STEP_HOUSEHOLDER_ADD) != 0};
+             (sp->flags & BLR_STEP_HOUSEHOLDER_ADD) != 0, (sp->flags & BLR_STEP_HOUSEHOLDER_QR) != 0};
   Outcome o;
   for (int attempt = 0;; ++attempt) {
     require(attempt < 4, "boundary basis: no consistent attempt", BLR_ERR_NUMERIC);
     o = Outcome{};
     step_attempt(ctx, pb, st, sp, h, add, at, o);
+    if (o.qr_failed && !at.householder_qr) {
+      at.householder_qr = true;
+      continue;
+    }
     if (!add) break;
     require(std::isfinite(o.sb[0]) && std::isfinite(o.sb[1]), "non-finite boundary singular value",
             BLR_ERR_NUMERIC);

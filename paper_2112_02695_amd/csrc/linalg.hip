@@ -374,6 +374,187 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
   }
 }
 
+
+// ------------------------------------------------------- Cholesky QR --
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Orders the LDS accesses of one wavefront (its DS instructions execute in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky R^T R = G + shift I of the leading r x r block of G (16 x 16,
+// row-major, in LDS; overwritten by R), on one wavefront: right-looking, the
+// trailing update spread over the lanes.  Rows and columns r..15 are
+// completed with the identity.  Writes R (r x r row-major, upper) and
+// 1 / diag(R).  flag[0] = 1 when a pivot R_kk^2 is not finite or not above
+// pivot_tol times the diagonal of G + shift I.
+__device__ void chol_wave(double* G, int r, double shift_coef, double pivot_tol,
+                          double* __restrict__ Rout, double* __restrict__ dinv_out, int* flag) {
+  const int lane = threadIdx.x & 63;
+  double tr = 0.0;
+  for (int k = 0; k < r; ++k) tr += G[k * 16 + k];
+  const double sh = shift_coef * tr;
+  wave_sync();
+  for (int e = lane; e < 256; e += 64) {
+    const int i = e / 16, j = e % 16;
+    if (i >= r || j >= r) G[e] = (i == j) ? 1.0 : 0.0;
+    else if (i == j) G[e] += sh;
+  }
+  wave_sync();
+  const double dg = lane < 16 ? G[lane * 16 + lane] : 1.0;
+  double piv_mine = 1.0, inv_mine = 1.0;
+  const int cj = lane & 15;
+  for (int k = 0; k < r; ++k) {
+    const double piv = G[k * 16 + k];
+    const double d = piv > 0.0 ? sqrt(piv) : 1.0;
+    const double inv = 1.0 / d;
+    if (lane == k) {
+      piv_mine = piv;
+      inv_mine = inv;
+    }
+    wave_sync();
+    if (lane == k) G[k * 16 + k] = d;
+    else if (lane > k && lane < 16) G[k * 16 + lane] *= inv;
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = (lane >> 4) + 4 * m;
+      if (i > k && cj >= i) G[i * 16 + cj] -= G[k * 16 + i] * G[k * 16 + cj];
+    }
+    wave_sync();
+  }
+  const bool bad = lane < r && (!(piv_mine > pivot_tol * dg) || !isfinite(piv_mine));
+  if (lane < r) {
+    for (int i = 0; i < r; ++i) Rout[i * r + lane] = i <= lane ? G[i * 16 + lane] : 0.0;
+    dinv_out[lane] = inv_mine;
+  }
+  if (__any(bad) && lane == 0) flag[0] = 1;
+}
+
+// One pass of the Cholesky QR over the rows of a column-major A (rows x r,
+// r <= RM <= 16), tiles of 256 rows: each row a is optionally replaced by
+// the solution q of q R_in = scale a (forward substitution with the upper-
+// triangular R_in and 1 / diag(R_in); written to Q, which may alias A), and
+// with part != null the Gram matrix of the resulting rows is accumulated on
+// the FP64 matrix cores.  v_mfma_f64_16x16x4f64 takes a 16x4 and a 4x16
+// operand, one double per lane: lane l supplies element (l % 16, l / 16) of
+// the first and (l / 16, l % 16) of the second, so the tile entry (row
+// 4g + l / 16, column l % 16) is at once the transposed first operand and
+// the second, and D += T_g^T T_g; lane l holds D entries (4v + l / 16,
+// l % 16).  Each block writes its 16 x 16 sum (waves in order) to part.
+template <int RM>
+__global__ __launch_bounds__(256) void k_cqr_apply(const double* A, long lda, long rows, int r,
+                                                   const double* __restrict__ Rin,
+                                                   const double* __restrict__ dinv_in,
+                                                   double scale, double* Q, long ldq,
+                                                   double* __restrict__ part) {
+  __shared__ double tile[256][17];
+  __shared__ double rs[16 * 16];
+  __shared__ double di[16];
+  __shared__ double red[4][256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  if (Rin) {
+    const int ia = t / 16, ib = t % 16;
+    rs[t] = (ia < r && ib < r) ? Rin[ia * r + ib] : 0.0;
+    if (t < 16) di[t] = t < r ? dinv_in[t] : 0.0;
+    __syncthreads();
+  }
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (long base = (long)blockIdx.x * 256; base < rows; base += (long)gridDim.x * 256) {
+    const long row = base + t;
+    double q[RM];
+    if (row < rows) {
+      double a[RM];
+#pragma unroll
+      for (int c = 0; c < RM; ++c) a[c] = c < r ? scale * A[c * lda + row] : 0.0;
+      if (Rin) {
+#pragma unroll
+        for (int jj = 0; jj < RM; ++jj) {
+          double v = a[jj];
+#pragma unroll
+          for (int c = 0; c < jj; ++c) v -= q[c] * rs[c * 16 + jj];
+          q[jj] = v * di[jj];
+          if (jj < r) Q[jj * ldq + row] = q[jj];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < RM; ++c) q[c] = a[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < RM; ++c) q[c] = 0.0;
+    }
+    if (part) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) tile[t][c] = c < RM ? q[c] : 0.0;
+      __syncthreads();
+#pragma unroll
+      for (int gi = 0; gi < 16; ++gi) {
+        const double x = tile[64 * wv + 4 * gi + (lane >> 4)][lane & 15];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  if (!part) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wv][(4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc[v];
+  __syncthreads();
+  part[(long)blockIdx.x * 256 + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+}
+
+// Sum of the nblk partial Gram matrices (block order: thread quarter qd adds
+// blocks qd, qd + 4, .., then the quarters in order), times gscale2, then
+// chol_wave; with Rp0 != null also Rout = R Rp1 Rp0 (r x r, upper).
+__global__ __launch_bounds__(1024) void k_cqr_chol(const double* __restrict__ part, int nblk, int r,
+                                                   double gscale2, double shift_coef,
+                                                   double pivot_tol, double* __restrict__ Rnew,
+                                                   double* __restrict__ dinv_new,
+                                                   const double* __restrict__ Rp1,
+                                                   const double* __restrict__ Rp0,
+                                                   double* __restrict__ Rout, int* flag) {
+  __shared__ double q4[4][256];
+  __shared__ double G[256];
+  __shared__ double P1[256], P0[256];
+  const int t = threadIdx.x, e = t & 255, qd = t >> 8;
+  double g = 0.0;
+  for (int b0 = qd; b0 < nblk; b0 += 64) {
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int b = b0 + 4 * k;
+      v[k] = b < nblk ? part[(long)b * 256 + e] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) g += v[k];
+  }
+  q4[qd][e] = g;
+  if (Rp0 && t < 256) {
+    const int i = t / 16, j = t % 16;
+    P1[t] = (i < r && j < r) ? Rp1[i * r + j] : 0.0;
+    P0[t] = (i < r && j < r) ? Rp0[i * r + j] : 0.0;
+  }
+  __syncthreads();
+  if (t < 256) G[t] = gscale2 * (((q4[0][t] + q4[1][t]) + q4[2][t]) + q4[3][t]);
+  __syncthreads();
+  if (t < 64) chol_wave(G, r, shift_coef, pivot_tol, Rnew, dinv_new, flag);
+  __syncthreads();
+  if (Rp0 && t < r * r) {
+    const int i = t / r, j = t % r;
+    double v = 0.0;
+    for (int k = i; k <= j; ++k) {
+      double w = 0.0;
+      for (int l = k; l <= j; ++l) w += P1[k * 16 + l] * P0[l * 16 + j];
+      v += G[i * 16 + k] * w;
+    }
+    Rout[i * r + j] = v;
+  }
+}
+
 }  // namespace la
 
 // ------------------------------------------------------------------- host --
@@ -466,6 +647,48 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
     BLR_CHECK_LAUNCH();
     Cst = out;
     ldc = ldo;
+  }
+}
+
+void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, long ldq,
+            double* R_rowmajor, const std::string& tag, double in_scale, double out_scale,
+            int* flag) {
+  require(r >= 1 && r <= 16, "cholqr: r must be in [1, 16]");
+  require(rows >= r, "cholqr: rows must be >= r");
+  require(Q && R_rowmajor && flag, "cholqr: null output");
+  hipStream_t s = ctx->stream;
+  const int nblk = (int)std::max<long>(1, std::min<long>(128, (rows + 255) / 256));
+  double* part = (double*)ctx->buf(tag + ".part", (size_t)nblk * 256 * sizeof(double));
+  double* Rk = (double*)ctx->buf(tag + ".rk", (size_t)3 * r * r * sizeof(double));
+  double* Dk = (double*)ctx->buf(tag + ".dk", (size_t)3 * 16 * sizeof(double));
+  // shift of the first pass: 11 (rows r + r (r + 1)) u ||A||_F^2 (shifted CholeskyQR3)
+  const double u = std::ldexp(1.0, -53);
+  const double shift = 11.0 * ((double)rows * r + (double)r * (r + 1)) * u;
+  auto R = [&](int k) { return Rk + (size_t)k * r * r; };
+  auto D = [&](int k) { return Dk + (size_t)k * 16; };
+  auto pass = [&](auto rm, int k) {
+    constexpr int RM = decltype(rm)::value;
+    // k = 0: Gram of in_scale A -> R_0; k = 1, 2: solve with R_{k-1}, Gram -> R_k
+    // (k = 2 also forms R = R_2 R_1 R_0); k = 3: solve with R_2, times out_scale
+    const double* src = k <= 1 ? A : Q;
+    const long ld = k <= 1 ? lda : ldq;
+    const double sc = k == 0 ? 1.0 : ((k == 1 ? in_scale : 1.0) * (k == 3 ? out_scale : 1.0));
+    hipLaunchKernelGGL(la::k_cqr_apply<RM>, dim3(nblk), dim3(256), 0, s, src, ld, rows, r,
+                       k == 0 ? nullptr : R(k - 1), k == 0 ? nullptr : D(k - 1), sc, Q, ldq,
+                       k < 3 ? part : nullptr);
+    BLR_CHECK_LAUNCH();
+    if (k == 3) return;
+    hipLaunchKernelGGL(la::k_cqr_chol, dim3(1), dim3(1024), 0, s, part, nblk, r,
+                       k == 0 ? in_scale * in_scale : 1.0, k == 0 ? shift : 0.0, k == 0 ? 0.0 : 1e-12,
+                       R(k), D(k), k == 2 ? R(1) : nullptr, k == 2 ? R(0) : nullptr,
+                       k == 2 ? R_rowmajor : nullptr, flag);
+    BLR_CHECK_LAUNCH();
+  };
+  for (int k = 0; k < 4; ++k) {
+    if (r <= 4) pass(std::integral_constant<int, 4>{}, k);
+    else if (r <= 8) pass(std::integral_constant<int, 8>{}, k);
+    else if (r <= 12) pass(std::integral_constant<int, 12>{}, k);
+    else pass(std::integral_constant<int, 16>{}, k);
   }
 }
 

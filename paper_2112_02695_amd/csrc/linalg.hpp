@@ -14,6 +14,17 @@ void tsqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, l
           double* R_rowmajor, const std::string& tag, double in_scale = 1.0,
           double out_scale = 1.0);
 
+// Shifted Cholesky QR in three passes (r <= 16): the first Cholesky
+// factorisation is of A^T A + s I with s = 11 (rows r + r (r + 1)) u
+// ||A||_F^2, which keeps it defined for any A, and two plain passes on the
+// result restore orthogonality to rounding; Gram matrices on the FP64
+// matrix cores.  Same contract as tsqr (Q and R_rowmajor required), except
+// for numerically rank-deficient A: then flag[0] is set to 1 (never cleared
+// here) and Q, R are not valid.
+void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q, long ldq,
+            double* R_rowmajor, const std::string& tag, double in_scale, double out_scale,
+            int* flag);
+
 // A = U diag(sig) W^T for an r x r row-major A (U, W row-major; sig descending).
 void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W);
 

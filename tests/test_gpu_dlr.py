@@ -156,6 +156,28 @@ def test_add_projection_matches_householder(ctx, d, N, nx, r, m_rho):
         assert abs(a[2] - b[2]) < 1e-10 * b[2] and abs(a[3] - b[3]) < 1e-10 * b[3]
 
 
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(3, 16, 40, 5, 2), (2, 16, 300, 4, 4)])
+def test_cholesky_qr_matches_householder(ctx, d, N, nx, r, m_rho):
+    """K- and L-step QRs by shifted Cholesky QR (default) and by Householder
+    QR give the same adaptive steps; nx = 300 spans several Gram blocks."""
+    spec, prob, st, _ = _setup(d, N, nx, r, m_rho)
+    out = []
+    for extra in (0, blr.BLR_STEP_HOUSEHOLDER_QR):
+        g = Gpu(ctx, spec, prob, st, r_cap=12)
+        flags = blr.BLR_STEP_FP64_COLLISION | blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | extra
+        infos = [ctx.dlr_step(g.pb, g.st, _params(0.05, flags, r_max=12)) for _ in range(2)]
+        X, S, V = g.factors()
+        rr = g.st.r
+        assert np.abs(prob.dx * X @ X.T - np.eye(rr)).max() < 1e-12
+        assert np.abs(prob.dvd * V @ V.T - np.eye(rr)).max() < 1e-12
+        out.append((g.full(), [(i.r_added, i.r_out, i.err, i.err_ada) for i in infos]))
+    (fa, ia), (fb, ib) = out
+    assert np.abs(fa - fb).max() < 1e-12 * np.abs(fb).max()
+    for a, b in zip(ia, ib):
+        assert a[:2] == b[:2]
+        assert abs(a[2] - b[2]) < 1e-10 * b[2] and abs(a[3] - b[3]) < 1e-10 * b[3]
+
+
 def test_add_count_change_is_redone(ctx):
     """The step guesses the number of added boundary functions from the
     previous step and redoes itself when the singular values disagree: a
