@@ -45,72 +45,96 @@ __device__ __forceinline__ double weight(int mode, double v1) {
   }
 }
 
-constexpr int GT = 16;       // output tile edge (rows of A x rows of B)
-constexpr int NCHUNK = 256;  // velocity chunks (first reduction stage)
-constexpr int GQ = 128;      // max points per chunk staged in LDS
-constexpr int MAXM = 4;      // weight modes evaluated together
+constexpr int GT = 16;  // output tile edge (rows of A x rows of B)
 
-struct Modes {
-  int m[MAXM];
-  int count;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// A batch of weighted Gram products out = scale * sum_q w(q) A_i(q) B_j(q)
+// (ra x rb row-major, ra <= 64), evaluated together: every 16 x 16 output
+// tile of every product is one grid row, every velocity chunk one grid
+// column; each block writes its tile's chunk sum (waves in order) and a
+// second kernel adds the chunks in order.
+constexpr int MAXSEG = 8;
+struct GramSeg {
+  const double* A;
+  const void* B;  // double, or float when bfloat
+  double* out;
+  double scale;
+  int ra, rb, mode, bfloat;
+  int tile0;  // first grid row of this product
+  int ntb;    // tiles along B
+  long part0; // offset of its partial sums ([chunk][i][j])
+  int out0;   // first flat output index of this product
+};
+struct GramBatch {
+  GramSeg seg[MAXSEG];
+  int nseg, ntiles, nout;
 };
 
-// partial[c][k][i][j] = sum_{q in chunk c} w_k(q) A[i][q] B[j][q]: one block
-// per (chunk, 16 rows of B, 16 rows of A), one thread per (i, j) output.
-template <typename TB>
-__global__ __launch_bounds__(256) void k_vgram(const double* __restrict__ A, int ra, long lda,
-                                               const TB* __restrict__ B, int rb, long ldb, Modes md,
-                                               VGeo g, double* __restrict__ part) {
-  __shared__ double As[GT][GQ + 1];
-  __shared__ double Bs[GT][GQ + 1];
-  __shared__ double ws[MAXM][GQ];
+__global__ __launch_bounds__(256) void k_gram_batch(GramBatch gb, long n, int nchunk, VGeo g,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4][256];
+  const int tile = blockIdx.y;
+  int si = 0;
+  while (si + 1 < gb.nseg && tile >= gb.seg[si + 1].tile0) ++si;
+  const GramSeg sg = gb.seg[si];
+  const int tl = tile - sg.tile0;
+  const int i0 = (tl / sg.ntb) * GT, j0 = (tl % sg.ntb) * GT;
   const int c = blockIdx.x;
-  const int j0 = blockIdx.y * GT, i0 = blockIdx.z * GT;
-  const long q0 = (long)c * g.n / NCHUNK, q1 = (long)(c + 1) * g.n / NCHUNK;
-  const int t = threadIdx.x;
-  const int ti = t / GT, tj = t % GT;
-  double acc[MAXM] = {0.0, 0.0, 0.0, 0.0};
-  for (long qb = q0; qb < q1; qb += GQ) {
-    const int nq = (int)min((long)GQ, q1 - qb);
-    for (int e = t; e < GT * GQ; e += 256) {
-      const int rr = e / GQ, qq = e % GQ;
-      As[rr][qq] = (i0 + rr < ra && qq < nq) ? A[(long)(i0 + rr) * lda + qb + qq] : 0.0;
-      Bs[rr][qq] = (j0 + rr < rb && qq < nq) ? (double)B[(long)(j0 + rr) * ldb + qb + qq] : 0.0;
-    }
-    for (int e = t; e < MAXM * GQ; e += 256) {
-      const int k = e / GQ, qq = e % GQ;
-      ws[k][qq] = (k < md.count && qq < nq) ? weight(md.m[k], g.v1((int)(qb + qq))) : 0.0;
-    }
-    __syncthreads();
-    for (int qq = 0; qq < nq; ++qq) {
-      const double p = As[ti][qq] * Bs[tj][qq];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const long q0 = (long)c * n / nchunk, q1 = (long)(c + 1) * n / nchunk;
+  const long len = q1 - q0;
+  const long w0 = q0 + len * wv / 4, w1 = q0 + len * (wv + 1) / 4;
+  const int ii = lane & 15, kk = lane >> 4;
+  const bool arow = i0 + ii < sg.ra, brow = j0 + ii < sg.rb;
+  const double* pa = sg.A + (long)(arow ? i0 + ii : 0) * n;
+  const double* pbd = (const double*)sg.B + (long)(brow ? j0 + ii : 0) * n;
+  const float* pbf = (const float*)sg.B + (long)(brow ? j0 + ii : 0) * n;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (long qb = w0; qb < w1; qb += 32) {
+    double xa[8], yb[8];
 #pragma unroll
-      for (int k = 0; k < MAXM; ++k) acc[k] += ws[k][qq] * p;
+    for (int u = 0; u < 8; ++u) {
+      const long q = qb + 4 * u + kk;
+      const bool in = q < w1;
+      xa[u] = (in && arow) ? pa[q] * weight(sg.mode, g.v1((int)q)) : 0.0;
+      yb[u] = (in && brow) ? (sg.bfloat ? (double)pbf[q] : pbd[q]) : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], yb[u], acc, 0, 0, 0);
   }
-  const int i = i0 + ti, j = j0 + tj;
-  if (i < ra && j < rb)
-    for (int k = 0; k < md.count; ++k) part[(((long)c * md.count + k) * ra + i) * rb + j] = acc[k];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wv][(4 * v + kk) * 16 + ii] = acc[v];
+  __syncthreads();
+  const int i = t / 16, j = t % 16;
+  if (i0 + i < sg.ra && j0 + j < sg.rb)
+    part[sg.part0 + ((long)c * sg.ra + i0 + i) * sg.rb + j0 + j] =
+        ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
-// sum of the chunk partials: one wavefront per output, fixed order
-__global__ __launch_bounds__(256) void k_vgram_finish(const double* __restrict__ part, int nm, int ra,
-                                                      int rb, double scale, double* __restrict__ o0,
-                                                      double* __restrict__ o1,
-                                                      double* __restrict__ o2,
-                                                      double* __restrict__ o3) {
+// chunk sums of a batch: one wavefront per output, fixed order
+__global__ __launch_bounds__(256) void k_gram_batch_finish(GramBatch gb, int nchunk,
+                                                           const double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int per = ra * rb;
-  if (t >= nm * per) return;
-  const int k = t / per, e = t % per;
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (o >= gb.nout) return;
+  int si = 0;
+  while (si + 1 < gb.nseg && o >= gb.seg[si + 1].out0) ++si;
+  const GramSeg& sg = gb.seg[si];
+  const int e = o - sg.out0;
+  const long per = (long)sg.ra * sg.rb;
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int c = lane + 64 * k;
+    v[k] = c < nchunk ? part[sg.part0 + c * per + e] : 0.0;
+  }
   double s = 0.0;
-  for (int c = lane; c < NCHUNK; c += 64) s += part[((long)c * nm + k) * per + e];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += v[k];
+  for (int c = lane + 512; c < nchunk; c += 64) s += part[sg.part0 + c * per + e];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane != 0) return;
-  double* o = k == 0 ? o0 : (k == 1 ? o1 : (k == 2 ? o2 : o3));
-  o[e] = scale * s;
+  if (lane == 0) sg.out[e] = sg.scale * s;
 }
 
 // K[j][x] = sum_i X[i][x] S[i][j]
@@ -473,10 +497,17 @@ __global__ __launch_bounds__(256) void k_orth_pass(double* __restrict__ V, int r
   if (e >= n) return;
   double b0 = V[(long)r * n + e];
   double b1 = rb == 2 ? V[(long)(r + 1) * n + e] : 0.0;
-  for (int j = 0; j < r; ++j) {
-    const double v = V[(long)j * n + e];
-    b0 -= C[j] * v;
-    if (rb == 2) b1 -= C[r + j] * v;
+  for (int j0 = 0; j0 < r; j0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = j0 + u < r ? V[(long)(j0 + u) * n + e] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (j0 + u < r) {
+        b0 -= C[j0 + u] * v[u];
+        if (rb == 2) b1 -= C[r + j0 + u] * v[u];
+      }
+    }
   }
   V[(long)r * n + e] = Li[0] * b0;
   if (rb == 2) V[(long)(r + 1) * n + e] = Li[2] * b0 + Li[3] * b1;
@@ -515,35 +546,50 @@ struct StepWork {
   }
 };
 
-// G_k = scale * sum_q w_k(q) A_i B_j   (ra x rb row-major), up to 4 weights at once
-template <typename TB>
-void vgram_multi(StepWork& w, const double* A, int ra, const TB* B, int rb,
-                 std::initializer_list<std::pair<int, double*>> outs, double scale) {
-  dk::Modes md{};
-  double* o[4] = {nullptr, nullptr, nullptr, nullptr};
-  md.count = 0;
-  for (const auto& pr : outs) {
-    md.m[md.count] = pr.first;
-    o[md.count] = pr.second;
-    ++md.count;
-  }
-  double* part = w.get("vgram.part", (size_t)dk::NCHUNK * md.count * ra * rb);
-  const dim3 grid(dk::NCHUNK, blocks(rb, dk::GT), blocks(ra, dk::GT));
-  timed_begin("dlr.vgram", (double)w.n * (ra * 8.0 + rb * (double)sizeof(TB)), w.s);
-  hipLaunchKernelGGL(dk::k_vgram<TB>, grid, dim3(256), 0, w.s, A, ra, (long)w.n, B, rb, (long)w.n,
-                     md, w.g, part);
-  BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_vgram_finish, dim3(blocks((long)md.count * ra * rb, 4)), dim3(256), 0,
-                     w.s, part, md.count, ra, rb, scale, o[0], o[1], o[2], o[3]);
-  BLR_CHECK_LAUNCH();
-  timed_end(w.s);
-}
-
-template <typename TB>
-void vgram(StepWork& w, const double* A, int ra, const TB* B, int rb, int mode, double scale,
+// Products evaluated by one launch pair (see k_gram_batch).
+struct GramJob {
+  dk::GramBatch gb{};
+  void add(const double* A, int ra, const void* B, int rb, bool bfloat, int mode, double scale,
            double* out) {
-  vgram_multi<TB>(w, A, ra, B, rb, {{mode, out}}, scale);
-}
+    require(gb.nseg < dk::MAXSEG, "gram batch: too many products");
+    require(ra >= 1 && ra <= 64 && rb >= 1, "gram batch: bad shape");
+    dk::GramSeg& s = gb.seg[gb.nseg++];
+    s.A = A;
+    s.B = B;
+    s.out = out;
+    s.scale = scale;
+    s.ra = ra;
+    s.rb = rb;
+    s.mode = mode;
+    s.bfloat = bfloat ? 1 : 0;
+    s.ntb = (rb + dk::GT - 1) / dk::GT;
+    s.tile0 = gb.ntiles;
+    gb.ntiles += s.ntb * ((ra + dk::GT - 1) / dk::GT);
+    s.out0 = gb.nout;
+    gb.nout += ra * rb;
+  }
+  void run(StepWork& w) {
+    if (gb.nseg == 0) return;
+    // chunks of 64 points: each wave takes 16 points, one round of loads
+    const int nchunk = (int)std::max<long>(1, std::min<long>(2048, (long)w.n / 64));
+    long off = 0;
+    double bytes = 0.0;
+    for (int k = 0; k < gb.nseg; ++k) {
+      gb.seg[k].part0 = off;
+      off += (long)nchunk * gb.seg[k].ra * gb.seg[k].rb;
+      bytes += (double)w.n * (gb.seg[k].ra * 8.0 + gb.seg[k].rb * (gb.seg[k].bfloat ? 4.0 : 8.0));
+    }
+    double* part = w.get("gram.part", (size_t)off);
+    timed_begin("dlr.gram", bytes, w.s);
+    hipLaunchKernelGGL(dk::k_gram_batch, dim3(nchunk, gb.ntiles), dim3(256), 0, w.s, gb, (long)w.n,
+                       nchunk, w.g, part);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_gram_batch_finish, dim3(blocks(gb.nout, 4)), dim3(256), 0, w.s, gb,
+                       nchunk, part);
+    BLR_CHECK_LAUNCH();
+    timed_end(w.s);
+  }
+};
 
 void validate_problem(const blr_problem* pb, const blr_state* st) {
   require(pb && st, "null problem or state");
@@ -661,7 +707,9 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
         // factor is [[I, 0], [C, L]] and S^ has zero rows and columns there)
         double* G = w.get("orthG", (size_t)2 * 66);
         for (int pass = 0; pass < 2; ++pass) {
-          vgram<double>(w, Vb, rb, Vw, rk, dk::W_ONE, dvd, G);
+          GramJob gj;
+          gj.add(Vb, rb, Vw, rk, false, dk::W_ONE, dvd, G);
+          gj.run(w);
           hipLaunchKernelGGL(dk::k_orth_pass, dim3(blocks(n, 256)), dim3(256), 0, s, Vw, r, rb, (long)n,
                              G, pass, flag);
           BLR_CHECK_LAUNCH();
@@ -716,16 +764,17 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   double* Ap = w.get("Ap", (size_t)r * r);
   double* Am = w.get("Am", (size_t)r * r);
   double* Cj = w.get("C", (size_t)r * P);
-  vgram_multi<double>(w, Vw, r, Vw, r,
-                      {{dk::W_VPLUS, Ap}, {dk::W_VMINUS, Am}, {dk::W_OUT_LEFT, MoL},
-                       {dk::W_OUT_RIGHT, MoR}},
-                      dvd);
-  if (fp64c)
-    vgram<double>(w, Vw, r, (const double*)Qs, P, dk::W_ONE, dvd, Cj);
-  else
-    vgram<float>(w, Vw, r, (const float*)Qs, P, dk::W_ONE, dvd, Cj);
-  vgram<double>(w, Vw, r, pb->f_left, 1, dk::W_IN_LEFT, dvd, ginL);
-  vgram<double>(w, Vw, r, pb->f_right, 1, dk::W_IN_RIGHT, dvd, ginR);
+  {
+    GramJob gj;
+    gj.add(Vw, r, Vw, r, false, dk::W_VPLUS, dvd, Ap);
+    gj.add(Vw, r, Vw, r, false, dk::W_VMINUS, dvd, Am);
+    gj.add(Vw, r, Vw, r, false, dk::W_OUT_LEFT, dvd, MoL);
+    gj.add(Vw, r, Vw, r, false, dk::W_OUT_RIGHT, dvd, MoR);
+    gj.add(Vw, r, Qs, P, !fp64c, dk::W_ONE, dvd, Cj);
+    gj.add(Vw, r, pb->f_left, 1, false, dk::W_IN_LEFT, dvd, ginL);
+    gj.add(Vw, r, pb->f_right, 1, false, dk::W_IN_RIGHT, dvd, ginR);
+    gj.run(w);
+  }
 
   // ---------------------------------------------------------- K-step
   double* K1 = w.get("K1", (size_t)r * nx);
@@ -796,8 +845,15 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, X1, r, nx, dx,
                      nullptr, nullptr, 0, nullptr, nullptr, dK, r, 1, kx, r, nullptr, nullptr, nullptr);
   BLR_CHECK_LAUNCH();
-  vgram<double>(w, dL, r, Vw, r, dk::W_ONE, dvd, lv);
-  vgram<double>(w, dL, r, dL, r, dk::W_ONE, dvd, GdL);
+  // Gram products of the residual and of err_ada (B = <V^n_l, V1_j>)
+  double* Bad = w.get("Bad", (size_t)r * r);
+  {
+    GramJob gj;
+    gj.add(dL, r, Vw, r, false, dk::W_ONE, dvd, lv);
+    gj.add(dL, r, dL, r, false, dk::W_ONE, dvd, GdL);
+    if (sp->flags & BLR_STEP_DROP) gj.add(Vw, r, V1, r, false, dk::W_ONE, dvd, Bad);
+    gj.run(w);
+  }
   hipLaunchKernelGGL(dk::k_err, dim3(1), dim3(256), 0, s, dK, (long)r * nx, dx, dS, r, GdL, kx, lv, res);
   BLR_CHECK_LAUNCH();
 
@@ -814,12 +870,10 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     svd_small(ctx, Snew, r, U, sg, Wm);
     // err_ada needs A = <X^n_k, X1_i> and B = <V^n_l, V1_j>
     double* Aad = w.get("Aad", (size_t)r * r);
-    double* Bad = w.get("Bad", (size_t)r * r);
     hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, Xw, r, nx, dx,
                        nullptr, nullptr, 0, nullptr, nullptr, X1, r, 1, Aad, r, nullptr, nullptr,
                        nullptr);
     BLR_CHECK_LAUNCH();
-    vgram<double>(w, Vw, r, V1, r, dk::W_ONE, dvd, Bad);
     gterm = w.get("gterm", (size_t)r);
     hipLaunchKernelGGL(dk::k_fnD_terms, dim3(1), dim3(256), 0, s, Sw, Aad, U, sg, Wm, Bad, r, gterm);
     BLR_CHECK_LAUNCH();
