@@ -153,6 +153,11 @@ typedef struct {
  * by itself when the matrix is numerically rank deficient).  Both give the
  * same step up to rounding. */
 #define BLR_STEP_HOUSEHOLDER_QR  0x10u
+/* Issue every kernel of the step one by one (default: the device work of a
+ * step attempt is recorded as a HIP graph the second time the same
+ * configuration -- shapes, arrays, parameters -- is seen, and replayed from
+ * then on; kernel timing turns graphs off).  Results are identical. */
+#define BLR_STEP_EAGER           0x20u
 
 typedef struct {
   double dt;
@@ -165,8 +170,9 @@ typedef struct {
 /* err: residual estimate of the step; err_ada: the same after the drop
  * (exact, Sec. 5.1); drop_tol = c_drop * err; ranks before the step, added
  * boundary functions, after the drop.  ms_collision: GPU time of the pair
- * collisions; ms_step: GPU time from the start of the step to the rank
- * decision (the final write of the state is not included). */
+ * collisions (0 when the step ran as a recorded graph); ms_step: GPU time
+ * from the start of the step to the rank decision (the final write of the
+ * state is not included). */
 typedef struct {
   double err, err_ada, drop_tol;
   int32_t r_in, r_added, r_out;

@@ -27,6 +27,7 @@ BLR_STEP_DROP = 0x2
 BLR_STEP_FP64_COLLISION = 0x4
 BLR_STEP_HOUSEHOLDER_ADD = 0x8
 BLR_STEP_HOUSEHOLDER_QR = 0x10
+BLR_STEP_EAGER = 0x20
 
 STATUS = {0: "BLR_OK", 1: "BLR_ERR_ARG", 2: "BLR_ERR_NOMEM", 3: "BLR_ERR_HIP",
           4: "BLR_ERR_UNSUPPORTED", 5: "BLR_ERR_NUMERIC", 6: "BLR_ERR_NOT_CONVERGED"}

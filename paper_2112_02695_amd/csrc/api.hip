@@ -9,6 +9,11 @@ void* blr_ctx_t::buf(const std::string& name, size_t bytes) {
   if (bytes == 0) bytes = 256;
   auto& b = bufs[name];
   if (b.bytes < bytes) {
+    if (capturing) {  // no allocation while a graph is recorded
+      capture_broken = true;
+      return b.p;
+    }
+    ++buf_gen;
     if (b.p) {
       BLR_HIP(hipStreamSynchronize(stream));
       BLR_HIP(hipFree(b.p));
@@ -22,12 +27,21 @@ void* blr_ctx_t::buf(const std::string& name, size_t bytes) {
 }
 
 void* blr_ctx_t::upload(const std::string& name, const void* host, size_t bytes) {
-  void* dst = buf(name, bytes);
-  if (bytes == 0) return dst;
-  auto& last = uploaded[name];
+  // one device copy per distinct content (FNV-1a of the bytes in the name):
+  // work recorded into a graph keeps reading its own index arrays
   const unsigned char* hb = (const unsigned char*)host;
+  uint64_t hsh = 1469598103934665603ull;
+  for (size_t k = 0; k < bytes; ++k) hsh = (hsh ^ hb[k]) * 1099511628211ull;
+  const std::string key = name + "#" + std::to_string(bytes) + "#" + std::to_string(hsh);
+  void* dst = buf(key, bytes);
+  if (bytes == 0) return dst;
+  auto& last = uploaded[key];
   if (last.first == dst && last.second.size() == bytes && std::memcmp(last.second.data(), hb, bytes) == 0)
     return dst;
+  if (capturing) {  // a staged copy cannot be replayed
+    capture_broken = true;
+    return dst;
+  }
   StageSlot& sl = stage[stage_next];
   stage_next = (stage_next + 1) % kStageSlots;
   if (sl.done) BLR_HIP(hipEventSynchronize(sl.done));
@@ -58,6 +72,11 @@ int blr_ctx_t::cu_count() {
 
 void* blr_ctx_t::host_readback(size_t bytes) {
   if (readback_bytes < bytes) {
+    if (capturing) {
+      capture_broken = true;
+      return readback;
+    }
+    ++buf_gen;
     if (readback) {
       BLR_HIP(hipStreamSynchronize(stream));
       BLR_HIP(hipHostFree(readback));
@@ -86,6 +105,13 @@ void blr_ctx_t::release_all() {
   if (readback) (void)hipHostFree(readback);
   readback = nullptr;
   readback_bytes = 0;
+  for (auto& g : graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  graphs.clear();
+  if (cap_stream) {
+    (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
+  }
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   timer.release();

@@ -460,37 +460,44 @@ __global__ __launch_bounds__(256) void k_orth_pass(double* __restrict__ V, int r
                                                    const double* __restrict__ G, int pass,
                                                    int* __restrict__ flag) {
   __shared__ double C[2 * 64];
+  __shared__ double Gb[4];  // G[:, r:]
   __shared__ double Li[4];  // L^{-1}, row-major 2 x 2
+  __shared__ int fl;
   const int ld = r + rb;
   for (int e = threadIdx.x; e < rb * r; e += blockDim.x) C[e] = G[(e / r) * ld + e % r];
+  if (threadIdx.x < rb * rb) Gb[threadIdx.x] = G[(threadIdx.x / rb) * ld + r + threadIdx.x % rb];
+  if (threadIdx.x == 0) fl = (pass == 0 || blockIdx.x != 0) ? 0 : flag[0];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int i = 0; i < rb; ++i)
-      for (int k = 0; k < rb; ++k) {
-        double t = G[i * ld + r + k];
-        for (int j = 0; j < r; ++j) t -= C[i * r + j] * C[k * r + j];
-        m[i][k] = t;
+  // M = G[:, r:] - C C^T: wave 0, lanes 16 q + u add the terms j = u, u + 16, ..
+  // of entry q = (i, k), then sums over the 16 lanes (butterfly)
+  if (threadIdx.x < 64) {
+    const int q = threadIdx.x >> 4, u = threadIdx.x & 15;
+    const int i = q >> 1, k = q & 1;
+    double part = 0.0;
+    if (i < rb && k < rb)
+      for (int j = u; j < r; j += 16) part += C[i * r + j] * C[k * r + j];
+    for (int off = 8; off > 0; off >>= 1) part += __shfl_xor(part, off, 16);
+    const double m00 = Gb[0] - __shfl(part, 0, 64);
+    const double m10 = rb == 2 ? Gb[2] - __shfl(part, 32, 64) : 0.0;
+    const double m11 = rb == 2 ? Gb[3] - __shfl(part, 48, 64) : 1.0;
+    if (threadIdx.x == 0) {
+      // L = [[l00, 0], [l10, l11]], L^{-1} from reciprocal square roots
+      bool bad = !(m00 > 1e-12 * Gb[0]) || !isfinite(m00);
+      const double i00 = bad ? 1.0 : rsqrt(m00);
+      const double l10 = m10 * i00;
+      double i11 = 1.0;
+      if (rb == 2) {
+        const double piv = m11 - l10 * l10;
+        const bool bad1 = !(piv > 1e-12 * Gb[3]) || !isfinite(piv) || !isfinite(l10);
+        bad = bad || bad1;
+        i11 = bad1 ? 1.0 : rsqrt(piv);
       }
-    bool bad = !(m[0][0] > 1e-12 * G[r]) || !isfinite(m[0][0]);
-    double l00 = bad ? 1.0 : sqrt(m[0][0]), l10 = 0.0, l11 = 1.0;
-    if (rb == 2) {
-      l10 = m[1][0] / l00;
-      const double piv = m[1][1] - l10 * l10;
-      const bool bad1 = !(piv > 1e-12 * G[ld + r + 1]) || !isfinite(piv) || !isfinite(l10);
-      bad = bad || bad1;
-      l11 = bad1 ? 1.0 : sqrt(piv);
+      Li[0] = bad ? 1.0 : i00;
+      Li[1] = 0.0;
+      Li[2] = bad ? 0.0 : -l10 * i00 * i11;
+      Li[3] = bad ? 1.0 : i11;
+      if (blockIdx.x == 0) flag[0] = fl | (bad ? 1 : 0);
     }
-    if (bad) {
-      l00 = 1.0;
-      l10 = 0.0;
-      l11 = 1.0;
-    }
-    Li[0] = 1.0 / l00;
-    Li[1] = 0.0;
-    Li[2] = -l10 / (l00 * l11);
-    Li[3] = 1.0 / l11;
-    if (blockIdx.x == 0) flag[0] = (pass == 0 ? 0 : flag[0]) | (bad ? 1 : 0);
   }
   __syncthreads();
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -525,6 +532,344 @@ __global__ void k_pack(const double* res, const int* flag, const double* sb, con
   for (int i = t; i < r; i += blockDim.x) {
     out[8 + i] = sg ? sg[i] : 0.0;
     out[8 + r + i] = g ? g[i] : 0.0;
+  }
+}
+
+// ---------------------------------------------- fused x-side kernels --
+// For r <= RM <= 16.  K = X S (K_l(x) = sum_i X_i(x) S_il) is formed where
+// it is needed instead of being stored; every block computes the ghost
+// values of K itself (from K at the two wall cells).
+
+// Loads a row-major r x r matrix into a zero-padded 16 x 16 LDS array.
+__device__ __forceinline__ void lds_mat16(double* dst, const double* src, int r, int ld) {
+  for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+    const int i = e / 16, j = e % 16;
+    dst[e] = (i < r && j < r) ? src[i * ld + j] : 0.0;
+  }
+}
+
+// Ghost values of K = X S at both walls into g[0][j] (left), g[1][j]
+// (right); S, MoL, MoR in LDS (16 x 16).  Ends with a barrier.
+template <int RM>
+__device__ void block_ghosts(const double* X, int r, int nx, const double* Ss, const double* ginL,
+                             const double* ginR, const double* MoLs, const double* MoRs,
+                             double (*kb)[16], double (*g)[16]) {
+  const int t = threadIdx.x;
+  if (t < 32) {
+    const int side = t / 16, l = t % 16;
+    const int x = side ? nx - 1 : 0;
+    double xv[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) xv[i] = i < r ? X[(long)i * nx + x] : 0.0;
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < RM; ++i) v += xv[i] * Ss[i * 16 + l];
+    kb[side][l] = l < r ? v : 0.0;
+  }
+  __syncthreads();
+  if (t < 32) {
+    const int side = t / 16, j = t % 16;
+    double v = 0.0;
+    if (j < r) {
+      v = side ? ginR[j] : ginL[j];
+      const double* Mo = side ? MoRs : MoLs;
+      for (int l = 0; l < r; ++l) v += kb[side][l] * Mo[l * 16 + j];
+    }
+    g[side][j] = v;
+  }
+  __syncthreads();
+}
+
+// K = X S for the cells x0 - 1 .. x0 + KB (those outside 0..nx-1 are the
+// ghost values) into Ks[l][1 + x - x0]; thread t computes cell x0 - 1 + t.
+// S, ghosts in LDS.  Ends with a barrier.
+template <int RM, int KB>
+__device__ void block_K(const double* X, int r, int nx, int x0, const double* Ss,
+                        const double (*g)[16], double (*Ks)[KB + 3]) {
+#pragma unroll 1
+  for (int t = threadIdx.x; t < KB + 2; t += blockDim.x) {
+    const int x = x0 - 1 + t;
+    double xv[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) xv[i] = (i < r && x >= 0 && x < nx) ? X[(long)i * nx + x] : 0.0;
+    // column loop kept rolled: S is read from LDS per column, not held in registers
+#pragma unroll 1
+    for (int l = 0; l < RM; ++l) {
+      double v = 0.0;
+#pragma unroll
+      for (int i = 0; i < RM; ++i) v += xv[i] * Ss[i * 16 + l];
+      if (x < 0) v = g[0][l];
+      else if (x >= nx) v = g[1][l];
+      Ks[l][t] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// K-step: K = X S, ghosts, and
+// K1_j = K_j + dt (-sum_l A+_jl D+K_l - sum_l A-_jl D-K_l + sum_{m<=n} C_j,(mn) w K_m K_n),
+// dK = K1 - K; pairs (m, n), m <= n, in row order (index m r - m (m - 1) / 2 + n - m).
+// Block (cells x0 .. x0 + 63, outputs j = JB blockIdx.y .. + JB - 1).
+constexpr int KSB = 64;
+template <int RM>
+__global__ __launch_bounds__(KSB) void k_kstep_fused(const double* __restrict__ X,
+                                                     const double* __restrict__ S, int r, int nx,
+                                                     double dx, double dt, int JB,
+                                                     const double* __restrict__ ginL,
+                                                     const double* __restrict__ ginR,
+                                                     const double* __restrict__ MoL,
+                                                     const double* __restrict__ MoR,
+                                                     const double* __restrict__ Ap,
+                                                     const double* __restrict__ Am,
+                                                     const double* __restrict__ C, int P,
+                                                     double* __restrict__ K1,
+                                                     double* __restrict__ dK) {
+  __shared__ double Ss[256], MoLs[256], MoRs[256];
+  __shared__ double kb[2][16], g[2][16];
+  __shared__ double Ks[16][KSB + 3];
+  lds_mat16(Ss, S, r, r);
+  lds_mat16(MoLs, MoL, r, r);
+  lds_mat16(MoRs, MoR, r, r);
+  __syncthreads();
+  block_ghosts<RM>(X, r, nx, Ss, ginL, ginR, MoLs, MoRs, kb, g);
+  const int x0 = blockIdx.x * KSB;
+  block_K<RM, KSB>(X, r, nx, x0, Ss, g, Ks);
+  const int t = threadIdx.x, x = x0 + t;
+  if (x >= nx) return;
+  double kc[RM], dp[RM], dm[RM];
+#pragma unroll
+  for (int l = 0; l < RM; ++l) {
+    const double b = Ks[l][t + 1];
+    kc[l] = b;
+    dp[l] = (b - Ks[l][t]) / dx;
+    dm[l] = (Ks[l][t + 2] - b) / dx;
+  }
+  const int j0 = blockIdx.y * JB, j1 = min(r, j0 + JB);
+  for (int j = j0; j < j1; ++j) {
+    double v = 0.0, kj = 0.0;
+#pragma unroll
+    for (int l = 0; l < RM; ++l) {
+      if (l < r) v -= Ap[j * r + l] * dp[l] + Am[j * r + l] * dm[l];
+      if (l == j) kj = kc[l];
+    }
+    // sum_{m <= n} C_j,(mn) w K_m K_n = sum_m K_m (C_j,(mm) K_m + sum_{n > m} C_j,(mn) 2 K_n)
+    const double* cj = C + (long)j * P;
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      if (m < r) {
+        const int p0 = m * r - m * (m - 1) / 2 - m;
+        double tm = cj[p0 + m] * kc[m];
+#pragma unroll
+        for (int n2 = m + 1; n2 < RM; ++n2)
+          if (n2 < r) tm += cj[p0 + n2] * (2.0 * kc[n2]);
+        v += kc[m] * tm;
+      }
+    }
+    const double d = dt * v;
+    K1[(long)j * nx + x] = kj + d;
+    dK[(long)j * nx + x] = d;
+  }
+}
+
+// x-side inner products out[i][c] = dx sum_x X1_i(x) Y_c(x) with K = X1 S:
+//   c < r: D+K_c;  c < 2r: D-K_(c-r);  c < 2r + P: w_p K_m K_n;
+//   next r columns (when Zk): Zk rows;  next r (when Zx): Zx rows,
+// written to Dp, Dm, T (r x r, r x r, r x P), kx (r x r, kx[i][c]) and
+// AadT (Aad[c][i] = <Zx_c, X1_i>).  One block per 16 columns; K of the
+// 256-cell chunk in LDS; the sum over x on the FP64 matrix cores (operand
+// layout as in k_gram_batch).
+template <int RM>
+__global__ __launch_bounds__(256) void k_xside(const double* __restrict__ X1, int r, int nx, double dx,
+                                               const double* __restrict__ S,
+                                               const double* __restrict__ ginL,
+                                               const double* __restrict__ ginR,
+                                               const double* __restrict__ MoL,
+                                               const double* __restrict__ MoR, int P,
+                                               const int* __restrict__ pm,
+                                               const int* __restrict__ pn,
+                                               const double* __restrict__ Zk,
+                                               const double* __restrict__ Zx, double* __restrict__ Dp,
+                                               double* __restrict__ Dm, double* __restrict__ T,
+                                               double* __restrict__ kx, double* __restrict__ Aad) {
+  __shared__ double Ss[256], MoLs[256], MoRs[256];
+  __shared__ double kb[2][16], g[2][16];
+  __shared__ double Ks[16][256 + 3];
+  __shared__ double Xs[16][257];
+  __shared__ double Ys[16][257];
+  __shared__ int pms[136], pns[136];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  lds_mat16(Ss, S, r, r);
+  lds_mat16(MoLs, MoL, r, r);
+  lds_mat16(MoRs, MoR, r, r);
+  for (int e = t; e < P; e += blockDim.x) {
+    pms[e] = pm[e];
+    pns[e] = pn[e];
+  }
+  __syncthreads();
+  block_ghosts<RM>(X1, r, nx, Ss, ginL, ginR, MoLs, MoRs, kb, g);
+  const int nzk = Zk ? r : 0, nzx = Zx ? r : 0;
+  const int ncols = 2 * r + P + nzk + nzx;
+  const int c0 = blockIdx.x * 16;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int x0 = 0; x0 < nx; x0 += 256) {
+    block_K<RM, 256>(X1, r, nx, x0, Ss, g, Ks);
+    const int x = x0 + t;
+    const bool xin = x < nx;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Xs[i][t] = (i < r && xin) ? X1[(long)i * nx + x] : 0.0;
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = c0 + cc;
+      double y = 0.0;
+      if (xin && c < ncols) {
+        if (c < r) {
+          y = (Ks[c][t + 1] - Ks[c][t]) / dx;
+        } else if (c < 2 * r) {
+          y = (Ks[c - r][t + 2] - Ks[c - r][t + 1]) / dx;
+        } else if (c < 2 * r + P) {
+          const int p = c - 2 * r, m = pms[p], n2 = pns[p];
+          y = (m == n2 ? 1.0 : 2.0) * Ks[m][t + 1] * Ks[n2][t + 1];
+        } else if (c < 2 * r + P + nzk) {
+          y = Zk[(long)(c - 2 * r - P) * nx + x];
+        } else {
+          y = Zx[(long)(c - 2 * r - P - nzk) * nx + x];
+        }
+      }
+      Ys[cc][t] = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int xx = 64 * wv + 4 * st + (lane >> 4);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[lane & 15][xx], Ys[lane & 15][xx], acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // four waves' tiles, in order
+  double* red = &Xs[0][0];  // 4 x 256 doubles
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wv * 256 + (4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc[v];
+  __syncthreads();
+  const int i = t / 16, c = c0 + t % 16;
+  if (i < r && c < ncols) {
+    const double o = dx * (((red[t] + red[256 + t]) + red[512 + t]) + red[768 + t]);
+    if (c < r) Dp[i * r + c] = o;
+    else if (c < 2 * r) Dm[i * r + c - r] = o;
+    else if (c < 2 * r + P) T[i * P + c - 2 * r] = o;
+    else if (c < 2 * r + P + nzk) kx[i * r + c - 2 * r - P] = o;
+    else Aad[(c - 2 * r - P - nzk) * r + i] = o;
+  }
+}
+
+// S2 = S1 + dt (Dp Ap^T + Dm Am^T - T C^T), dS = S2 - S1, for r <= 16
+__global__ __launch_bounds__(256) void k_supdate16(const double* __restrict__ S1,
+                                                   const double* __restrict__ Dp,
+                                                   const double* __restrict__ Dm,
+                                                   const double* __restrict__ T,
+                                                   const double* __restrict__ Ap,
+                                                   const double* __restrict__ Am,
+                                                   const double* __restrict__ C, int r, int P,
+                                                   double dt, double* __restrict__ S2,
+                                                   double* __restrict__ dS) {
+  __shared__ double D1[256], D2[256], A1[256], A2[256];
+  __shared__ double Ts[16 * 136], Cs[16 * 136];
+  lds_mat16(D1, Dp, r, r);
+  lds_mat16(D2, Dm, r, r);
+  lds_mat16(A1, Ap, r, r);
+  lds_mat16(A2, Am, r, r);
+#pragma unroll 4
+  for (int e = threadIdx.x; e < r * P; e += blockDim.x) {
+    Ts[e] = T[e];
+    Cs[e] = C[e];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= r * r) return;
+  const int i = t / r, j = t % r;
+  double v = 0.0;
+  for (int l = 0; l < r; ++l) v += D1[i * 16 + l] * A1[j * 16 + l] + D2[i * 16 + l] * A2[j * 16 + l];
+  for (int p = 0; p < P; ++p) v -= Ts[i * P + p] * Cs[j * P + p];
+  S2[t] = S1[t] + dt * v;
+  dS[t] = dt * v;
+}
+
+// err^2 pieces (as k_err), one block: sum of dK^2 with loads in batches,
+// the r x r sums one entry per thread, then fixed-order tree sums.
+__global__ __launch_bounds__(256) void k_err16(const double* __restrict__ dK, long nK, double dx,
+                                               const double* __restrict__ dS, int r,
+                                               const double* __restrict__ GdL,
+                                               const double* __restrict__ kx,
+                                               const double* __restrict__ lv,
+                                               double* __restrict__ res) {
+  __shared__ double red[5][256];
+  const int t = threadIdx.x;
+  double a = 0.0;
+  for (long e0 = 0; e0 < nK; e0 += 256 * 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const long e = e0 + k * 256 + t;
+      v[k] = e < nK ? dK[e] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a += v[k] * v[k];
+  }
+  double b = 0.0, c = 0.0, I = 0.0, II = 0.0, III = 0.0;
+  if (t < r * r) {
+    const double ds = dS[t], kv = kx[t], lvv = lv[t];
+    b = ds * ds;
+    I = kv * ds;
+    II = lvv * ds;
+    III = kv * lvv;
+    if (t / r == t % r) c = GdL[t];
+  }
+  red[0][t] = a;
+  red[1][t] = b;
+  red[2][t] = c;
+  red[3][t] = I;
+  red[4][t] = II + III;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st)
+      for (int k = 0; k < 5; ++k) red[k][t] += red[k][t + st];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double A = dx * red[0][0];
+    res[0] = A + red[1][0] + red[2][0] + 2.0 * (red[3][0] + red[4][0]);
+    res[1] = A;
+    res[2] = red[1][0];
+    res[3] = red[2][0];
+  }
+}
+
+// <f^n, D_keep> terms (as k_fnD_terms) for r <= 16, inputs staged in LDS
+__global__ __launch_bounds__(256) void k_fnD16(const double* S, const double* A, const double* U,
+                                               const double* sig, const double* W, const double* B,
+                                               int r, double* g) {
+  __shared__ double Sm[256], Am_[256], Um[256], Wm[256], Bm[256], AU[256], BW[256];
+  lds_mat16(Sm, S, r, r);
+  lds_mat16(Am_, A, r, r);
+  lds_mat16(Um, U, r, r);
+  lds_mat16(Wm, W, r, r);
+  lds_mat16(Bm, B, r, r);
+  __syncthreads();
+  const int t = threadIdx.x, k = t / 16, q = t % 16;
+  double au = 0.0, bw = 0.0;
+  for (int i = 0; i < r; ++i) {
+    au += Am_[k * 16 + i] * Um[i * 16 + q];
+    bw += Bm[k * 16 + i] * Wm[i * 16 + q];
+  }
+  AU[t] = au;
+  BW[t] = bw;
+  __syncthreads();
+  if (t < r) {
+    double v = 0.0;
+    for (int kk = 0; kk < r; ++kk) {
+      double sb = 0.0;
+      for (int l = 0; l < r; ++l) sb += Sm[kk * 16 + l] * BW[l * 16 + t];
+      v += AU[kk * 16 + t] * sb;
+    }
+    g[t] = sig[t] * v;
   }
 }
 
@@ -625,17 +970,22 @@ struct Outcome {
   std::vector<double> sg, g; // singular values of S^{n+1}, err_ada terms (drop only)
   double *X1 = nullptr, *V1 = nullptr, *Snew = nullptr, *U = nullptr, *Wm = nullptr,
          *sgd = nullptr;
+  double* hb = nullptr;  // pinned read-back record
+  int nrb = 0;           // singular values in it
+  bool timed_collision = false;
 };
 
-// Everything up to the rank decision, then one read-back and one wait.
-void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const blr_step_params* sp,
-                  const HostTables& h, bool add, Attempt at, Outcome& o) {
+// The device work of one attempt, up to the copy of the read-back record
+// into pinned host memory (o.hb); no wait.  Timing events only when
+// rec_events (not while a graph is recorded).
+void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const blr_step_params* sp,
+                  const HostTables& h, bool add, Attempt at, Outcome& o, bool rec_events) {
   StepWork w{ctx, ctx->stream, {h.L, h.dv, h.N, h.d, h.n}, pb->nx, h.n,
              (pb->x_hi - pb->x_lo) / pb->nx, std::pow(h.dv, h.d)};
   hipStream_t s = w.s;
   const int nx = w.nx, n = w.n;
   const double dx = w.dx, dvd = w.dvd, dt = sp->dt;
-  BLR_HIP(hipEventRecord(ctx->ev[0], s));
+  if (rec_events) BLR_HIP(hipEventRecord(ctx->ev[0], s));
 
   // working copies (rank up to r_cap); the caller's state is written only at commit
   const int rc = st->r_cap;
@@ -746,7 +1096,7 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   int* dpidx = (int*)ctx->upload("dlr.pidx", pidx.data(), pidx.size() * sizeof(int));
   const bool fp64c = (sp->flags & BLR_STEP_FP64_COLLISION) != 0;
   void* Qs;
-  BLR_HIP(hipEventRecord(ctx->ev[1], s));
+  if (rec_events) BLR_HIP(hipEventRecord(ctx->ev[1], s));
   if (fp64c) {
     Qs = w.get("Q64", (size_t)P * n);
     collision_pairs(ctx, pb->v, BLR_FP64, Vw, r, pairs.data(), P, Qs);
@@ -758,7 +1108,8 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     Qs = ctx->buf("dlr.Q32", (size_t)P * n * sizeof(float));
     collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
   }
-  BLR_HIP(hipEventRecord(ctx->ev[2], s));
+  if (rec_events) BLR_HIP(hipEventRecord(ctx->ev[2], s));
+  o.timed_collision = rec_events;
 
   // velocity-side contractions
   double* Ap = w.get("Ap", (size_t)r * r);
@@ -781,41 +1132,90 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   double* dK = w.get("dK", (size_t)r * nx);
   double* X1 = w.get("X1", (size_t)r * nx);
   double* S1 = w.get("S1", (size_t)r * r);
-  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, Xw, r, nx, Sw, r, K);
-  BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
-  BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_kstep, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, K, gh, r, nx, dx,
-                     dt, Ap, Am, Cj, P, dpidx, dpidx + P, K1, dK);
-  BLR_CHECK_LAUNCH();
+  const bool small = r <= 16;  // fused x-side kernels
+  auto bucket16 = [&](auto&& f) {
+    if (r <= 4) f(std::integral_constant<int, 4>{});
+    else if (r <= 8) f(std::integral_constant<int, 8>{});
+    else if (r <= 12) f(std::integral_constant<int, 12>{});
+    else f(std::integral_constant<int, 16>{});
+  };
+  if (small) {
+    bucket16([&](auto rm) {
+      constexpr int RM = decltype(rm)::value;
+      const int JB = 2;  // outputs per block
+      hipLaunchKernelGGL(dk::k_kstep_fused<RM>, dim3(blocks(nx, dk::KSB), (r + JB - 1) / JB),
+                         dim3(dk::KSB), 0, s, Xw, Sw, r, nx, dx, dt, JB, ginL, ginR, MoL, MoR, Ap, Am,
+                         Cj, P, K1, dK);
+    });
+    BLR_CHECK_LAUNCH();
+  } else {
+    hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, Xw, r, nx, Sw, r,
+                       K);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_kstep, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, K, gh, r, nx, dx,
+                       dt, Ap, Am, Cj, P, dpidx, dpidx + P, K1, dK);
+    BLR_CHECK_LAUNCH();
+  }
   qr(K1, nx, nx, r, X1, S1, "qr.k", dx);
 
   // ---------------------------------------------------------- S-step
   const int ncols = 2 * r + P;
   double* S2 = w.get("S2", (size_t)r * r);
   double* dS = w.get("dS", (size_t)r * r);
-  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, X1, r, nx, S1, r, K);
-  BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
-  BLR_CHECK_LAUNCH();
   double* Dp = w.get("Dp", (size_t)r * r);
   double* Dm = w.get("Dm", (size_t)r * r);
   double* T = w.get("T", (size_t)r * P);
-  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 4)), dim3(256), 0, s, X1, r, nx,
-                     dx, K, gh, P, dpidx, dpidx + P, nullptr, 0, 0, nullptr, ncols, Dp, Dm, T);
-  BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_supdate, dim3(1), dim3(1024), 0, s, S1, Dp, Dm, T, Ap, Am, Cj, r, P, dt, S2,
-                     dS);
+  double* kx = w.get("kx", (size_t)r * r);
+  double* Aad = w.get("Aad", (size_t)r * r);
+  const bool drop_on = (sp->flags & BLR_STEP_DROP) != 0;
+  // x-side products of X1 with D+-K, w K_m K_n for K = X1 Sx (and, in the
+  // L-step pass, with dK and X^n)
+  auto xside = [&](const double* Sx, bool extra) {
+    if (small) {
+      const int nc = ncols + (extra ? r : 0) + (extra && drop_on ? r : 0);
+      bucket16([&](auto rm) {
+        constexpr int RM = decltype(rm)::value;
+        hipLaunchKernelGGL(dk::k_xside<RM>, dim3(blocks(nc, 16)), dim3(256), 0, s, X1, r, nx, dx, Sx,
+                           ginL, ginR, MoL, MoR, P, dpidx, dpidx + P, extra ? dK : nullptr,
+                           (extra && drop_on) ? Xw : nullptr, Dp, Dm, T, kx, Aad);
+      });
+      BLR_CHECK_LAUNCH();
+      return;
+    }
+    hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, X1, r, nx, Sx, r,
+                       K);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 4)), dim3(256), 0, s, X1, r, nx,
+                       dx, K, gh, P, dpidx, dpidx + P, nullptr, 0, 0, nullptr, ncols, Dp, Dm, T);
+    BLR_CHECK_LAUNCH();
+    if (extra) {
+      hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, X1, r, nx, dx,
+                         nullptr, nullptr, 0, nullptr, nullptr, dK, r, 1, kx, r, nullptr, nullptr,
+                         nullptr);
+      BLR_CHECK_LAUNCH();
+      if (drop_on) {
+        hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, Xw, r, nx,
+                           dx, nullptr, nullptr, 0, nullptr, nullptr, X1, r, 1, Aad, r, nullptr,
+                           nullptr, nullptr);
+        BLR_CHECK_LAUNCH();
+      }
+    }
+  };
+  xside(S1, false);
+  if (small)
+    hipLaunchKernelGGL(dk::k_supdate16, dim3(1), dim3(256), 0, s, S1, Dp, Dm, T, Ap, Am, Cj, r, P, dt,
+                       S2, dS);
+  else
+    hipLaunchKernelGGL(dk::k_supdate, dim3(1), dim3(1024), 0, s, S1, Dp, Dm, T, Ap, Am, Cj, r, P, dt,
+                       S2, dS);
   BLR_CHECK_LAUNCH();
 
   // ---------------------------------------------------------- L-step
-  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, X1, r, nx, S2, r, K);
-  BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_ghosts, dim3(1), dim3(64), 0, s, K, r, nx, ginL, ginR, MoL, MoR, gh);
-  BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * ncols, 4)), dim3(256), 0, s, X1, r, nx,
-                     dx, K, gh, P, dpidx, dpidx + P, nullptr, 0, 0, nullptr, ncols, Dp, Dm, T);
-  BLR_CHECK_LAUNCH();
+  xside(S2, true);
   double* L1 = w.get("L1", (size_t)r * n);
   double* dL = w.get("dL", (size_t)r * n);
   {
@@ -838,13 +1238,9 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   BLR_CHECK_LAUNCH();
 
   // --------------------------------------------------------- residual
-  double* kx = w.get("kx", (size_t)r * r);
   double* lv = w.get("lv", (size_t)r * r);
   double* GdL = w.get("GdL", (size_t)r * r);
   double* res = w.get("res", 8);
-  hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, X1, r, nx, dx,
-                     nullptr, nullptr, 0, nullptr, nullptr, dK, r, 1, kx, r, nullptr, nullptr, nullptr);
-  BLR_CHECK_LAUNCH();
   // Gram products of the residual and of err_ada (B = <V^n_l, V1_j>)
   double* Bad = w.get("Bad", (size_t)r * r);
   {
@@ -854,7 +1250,12 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     if (sp->flags & BLR_STEP_DROP) gj.add(Vw, r, V1, r, false, dk::W_ONE, dvd, Bad);
     gj.run(w);
   }
-  hipLaunchKernelGGL(dk::k_err, dim3(1), dim3(256), 0, s, dK, (long)r * nx, dx, dS, r, GdL, kx, lv, res);
+  if (small)
+    hipLaunchKernelGGL(dk::k_err16, dim3(1), dim3(256), 0, s, dK, (long)r * nx, dx, dS, r, GdL, kx, lv,
+                       res);
+  else
+    hipLaunchKernelGGL(dk::k_err, dim3(1), dim3(256), 0, s, dK, (long)r * nx, dx, dS, r, GdL, kx, lv,
+                       res);
   BLR_CHECK_LAUNCH();
 
   // ---------------------------------------------- drop ingredients (device)
@@ -868,22 +1269,20 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     sg = w.get("sig", (size_t)r);
     double* Wm = w.get("W", (size_t)r * r);
     svd_small(ctx, Snew, r, U, sg, Wm);
-    // err_ada needs A = <X^n_k, X1_i> and B = <V^n_l, V1_j>
-    double* Aad = w.get("Aad", (size_t)r * r);
-    hipLaunchKernelGGL(dk::k_xreduce, dim3(blocks((long)r * r, 4)), dim3(256), 0, s, Xw, r, nx, dx,
-                       nullptr, nullptr, 0, nullptr, nullptr, X1, r, 1, Aad, r, nullptr, nullptr,
-                       nullptr);
-    BLR_CHECK_LAUNCH();
+    // err_ada uses A = <X^n_k, X1_i> (x-side pass of the L-step) and B = <V^n_l, V1_j>
     gterm = w.get("gterm", (size_t)r);
-    hipLaunchKernelGGL(dk::k_fnD_terms, dim3(1), dim3(256), 0, s, Sw, Aad, U, sg, Wm, Bad, r, gterm);
+    if (small)
+      hipLaunchKernelGGL(dk::k_fnD16, dim3(1), dim3(256), 0, s, Sw, Aad, U, sg, Wm, Bad, r, gterm);
+    else
+      hipLaunchKernelGGL(dk::k_fnD_terms, dim3(1), dim3(256), 0, s, Sw, Aad, U, sg, Wm, Bad, r, gterm);
     BLR_CHECK_LAUNCH();
     o.U = U;
     o.Wm = Wm;
     o.sgd = sg;
   }
 
-  // ------------------------------------- one read-back, one wait
-  BLR_HIP(hipEventRecord(ctx->ev[3], s));
+  // ------------------------------------------------------ read-back
+  if (rec_events) BLR_HIP(hipEventRecord(ctx->ev[3], s));
   const bool drop = (sp->flags & BLR_STEP_DROP) != 0;
   const int nrb = drop ? r : 0;
   double* pk = w.get("pack", (size_t)8 + 2 * 64);
@@ -892,7 +1291,14 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   const size_t nbytes = (8 + 2 * (size_t)nrb) * sizeof(double);
   double* hb = (double*)ctx->host_readback(nbytes);
   BLR_HIP(hipMemcpyAsync(hb, pk, nbytes, hipMemcpyDeviceToHost, s));
-  BLR_HIP(hipStreamSynchronize(s));
+  o.hb = hb;
+  o.nrb = nrb;
+}
+
+// Host side of the read-back record (after the wait).
+void step_parse(Outcome& o) {
+  const double* hb = o.hb;
+  const int nrb = o.nrb;
   for (int k = 0; k < 4; ++k) o.res[k] = hb[k];
   o.orth_failed = hb[4] != 0.0;
   o.qr_failed = hb[7] != 0.0;
@@ -900,6 +1306,145 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   o.sb[1] = hb[6];
   o.sg.assign(hb + 8, hb + 8 + nrb);
   o.g.assign(hb + 8 + nrb, hb + 8 + 2 * nrb);
+}
+
+// Key of a step attempt: every input that shapes the recorded work.
+std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_params* sp, bool add,
+                     const Attempt& at) {
+  struct {
+    int32_t nx;
+    double x_lo, x_hi;
+    const void *fl, *fr;
+    blr_vgrid v;
+    int32_t r, r_cap;
+    const void *X, *S, *V;
+    blr_step_params p;
+    int32_t add, rb, hh, hq;
+  } k;
+  std::memset(&k, 0, sizeof(k));
+  k.nx = pb->nx;
+  k.x_lo = pb->x_lo;
+  k.x_hi = pb->x_hi;
+  k.fl = pb->f_left;
+  k.fr = pb->f_right;
+  k.v = pb->v;
+  k.r = st->r;
+  k.r_cap = st->r_cap;
+  k.X = st->X;
+  k.S = st->S;
+  k.V = st->V;
+  k.p = *sp;
+  k.add = add;
+  k.rb = at.rb;
+  k.hh = at.householder;
+  k.hq = at.householder_qr;
+  return std::string((const char*)&k, sizeof(k));
+}
+
+// One attempt of the step up to the rank decision, one wait.  Unless the
+// step is eager or kernels are timed, the device work is recorded as a
+// graph the second time a configuration is seen and replayed from then on.
+void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const blr_step_params* sp,
+                  const HostTables& h, bool add, Attempt at, Outcome& o) {
+  hipStream_t s = ctx->stream;
+  const bool graphs = !(sp->flags & BLR_STEP_EAGER) && !ctx->timer.on;
+  auto eager = [&]() {
+    step_enqueue(ctx, pb, st, sp, h, add, at, o, true);
+    BLR_HIP(hipStreamSynchronize(s));
+    step_parse(o);
+  };
+  if (!graphs) {
+    eager();
+    return;
+  }
+  const std::string key = step_key(pb, st, sp, add, at);
+  auto& gs = ctx->graphs;
+  size_t gi = gs.size();
+  for (size_t k = 0; k < gs.size(); ++k)
+    if (gs[k].key == key) gi = k;
+  if (gi == gs.size()) {
+    if (gs.size() >= 8) {  // forget the oldest
+      if (gs.front().exec) (void)hipGraphExecDestroy(gs.front().exec);
+      gs.erase(gs.begin());
+    }
+    gs.push_back(blr_ctx_t::StepGraph{});
+    gi = gs.size() - 1;
+    gs[gi].key = key;
+  }
+  auto& g = gs[gi];
+  if (g.gen != ctx->buf_gen) {  // addresses moved: start over
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.seen = 0;
+    g.gen = ctx->buf_gen;
+  }
+  if (!g.exec && g.seen == 0) {
+    eager();
+    g.seen = 1;
+    g.gen = ctx->buf_gen;
+    return;
+  }
+  if (!g.exec) {
+    // record on the capture stream, then replay on the caller's stream
+    if (!ctx->cap_stream) BLR_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    const uint64_t gen0 = ctx->buf_gen;
+    ctx->stream = ctx->cap_stream;
+    ctx->capturing = true;
+    ctx->capture_broken = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        step_enqueue(ctx, pb, st, sp, h, add, at, o, false);
+      } catch (...) {
+        (void)hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        ctx->stream = s;
+        ctx->capturing = false;
+        throw;
+      }
+      e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    }
+    ctx->stream = s;
+    ctx->capturing = false;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess && graph && !ctx->capture_broken && ctx->buf_gen == gen0)
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess || !exec) {
+      (void)hipGetLastError();
+      eager();  // not recordable this time: run it directly
+      g.gen = ctx->buf_gen;
+      return;
+    }
+    g.exec = exec;
+    g.gen = ctx->buf_gen;
+    g.r = o.r;
+    g.nrb = o.nrb;
+    g.X1 = o.X1;
+    g.V1 = o.V1;
+    g.Snew = o.Snew;
+    g.U = o.U;
+    g.Wm = o.Wm;
+    g.sgd = o.sgd;
+    g.hb = o.hb;
+  } else {
+    o.r = g.r;
+    o.nrb = g.nrb;
+    o.X1 = g.X1;
+    o.V1 = g.V1;
+    o.Snew = g.Snew;
+    o.U = g.U;
+    o.Wm = g.Wm;
+    o.sgd = g.sgd;
+    o.hb = g.hb;
+  }
+  BLR_HIP(hipEventRecord(ctx->ev[0], s));
+  BLR_HIP(hipGraphLaunch(g.exec, s));
+  BLR_HIP(hipEventRecord(ctx->ev[3], s));
+  BLR_HIP(hipStreamSynchronize(s));
+  o.timed_collision = false;
+  step_parse(o);
 }
 
 }  // namespace
@@ -993,8 +1538,11 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   float ms = 0.f;
   BLR_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]));
   inf.ms_step = ms;
-  BLR_HIP(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
-  inf.ms_collision = ms;
+  inf.ms_collision = 0.f;
+  if (o.timed_collision) {
+    BLR_HIP(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+    inf.ms_collision = ms;
+  }
   inf.r_out = r_out;
   st->r = r_out;
   st->step += 1;

@@ -133,6 +133,25 @@ struct blr_ctx_t {
   // compute units of the device (queried once)
   int ncu = 0;
   int cu_count();
+  // bumped whenever a workspace buffer or the read-back buffer moves: graphs
+  // recorded before hold stale addresses
+  uint64_t buf_gen = 0;
+  // step graphs: the device work of one step attempt recorded once per
+  // configuration (key) and replayed; capture runs on cap_stream
+  struct StepGraph {
+    std::string key;
+    uint64_t gen = 0;
+    int seen = 0;
+    hipGraphExec_t exec = nullptr;
+    // where the recorded work leaves its results
+    int r = 0, nrb = 0;
+    double *X1 = nullptr, *V1 = nullptr, *Snew = nullptr, *U = nullptr, *Wm = nullptr,
+           *sgd = nullptr, *hb = nullptr;
+  };
+  std::vector<StepGraph> graphs;
+  hipStream_t cap_stream = nullptr;
+  bool capturing = false;
+  bool capture_broken = false;  // an operation that cannot be recorded was requested
   blr::KernelTimer timer;
 
   void* buf(const std::string& name, size_t bytes);  // grow-only named workspace

@@ -253,11 +253,24 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
   __shared__ int order[64];
   __shared__ int rot_any;
   const int t = threadIdx.x;
-  for (int c = 0; c < r; ++c)
-    if (t < r) {
-      B[c * 64 + t] = A[t * r + c];
-      V[c * 64 + t] = (t == c) ? 1.0 : 0.0;
+  // all r^2 loads in flight at once (lane t: entries t, t + 64, ..)
+  for (int e0 = 0; e0 < r * r; e0 += 64 * 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = e0 + 64 * k + t;
+      v[k] = e < r * r ? A[e] : 0.0;
     }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = e0 + 64 * k + t;
+      if (e < r * r) {
+        const int row = e / r, c = e % r;
+        B[c * 64 + row] = v[k];
+        V[c * 64 + row] = (row == c) ? 1.0 : 0.0;
+      }
+    }
+  }
   __syncthreads();
   // Each round rotates rr/2 disjoint column pairs (circle method, with a
   // dummy column when r is odd); a pair is handled by lpp lanes, each taking
@@ -299,10 +312,12 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
         be += __shfl_xor(be, off, 64);
         ga += __shfl_xor(ga, off, 64);
       }
-      if (live && fabs(ga) > 1e-300 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+      if (live && fabs(ga) > 1e-300 && ga * ga > 1e-30 * (al * be)) {
+        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = tau / g2, written
+        // without dividing by g2: t = sign(tau) g2 / (|tau| + sqrt(tau^2 + g2^2))
+        const double tau = be - al, g2 = 2.0 * ga;
+        const double tt = (tau >= 0 ? g2 : -g2) / (fabs(tau) + sqrt(tau * tau + g2 * g2));
+        const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
         for (int i = sub; i < r; i += lpp) {
           const double x = B[p * 64 + i], y = B[q * 64 + i];
           B[p * 64 + i] = c * x - sn * y;
@@ -387,49 +402,58 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Cholesky R^T R = G + shift I of the leading r x r block of G (16 x 16,
-// row-major, in LDS; overwritten by R), on one wavefront: right-looking, the
-// trailing update spread over the lanes.  Rows and columns r..15 are
-// completed with the identity.  Writes R (r x r row-major, upper) and
-// 1 / diag(R).  flag[0] = 1 when a pivot R_kk^2 is not finite or not above
-// pivot_tol times the diagonal of G + shift I.
-__device__ void chol_wave(double* G, int r, double shift_coef, double pivot_tol,
+// row-major, in LDS), on one wavefront: lane j keeps column j in registers
+// (right-looking; pivot and row k move between lanes by shuffles, 1 / R_kk
+// from a reciprocal square root).  Rows and columns r..15 are completed with
+// the identity.  Writes R (r x r row-major, upper; also 16 x 16 to Rl in
+// LDS) and 1 / diag(R).
+// flag[0] = 1 when a pivot R_kk^2 is not finite or not above pivot_tol times
+// the diagonal of G + shift I.
+__device__ void chol_wave(const double* G, double* Rl, int r, double shift_coef, double pivot_tol,
                           double* __restrict__ Rout, double* __restrict__ dinv_out, int* flag) {
   const int lane = threadIdx.x & 63;
+  const int j = lane & 15;
   double tr = 0.0;
   for (int k = 0; k < r; ++k) tr += G[k * 16 + k];
   const double sh = shift_coef * tr;
-  wave_sync();
-  for (int e = lane; e < 256; e += 64) {
-    const int i = e / 16, j = e % 16;
-    if (i >= r || j >= r) G[e] = (i == j) ? 1.0 : 0.0;
-    else if (i == j) G[e] += sh;
-  }
-  wave_sync();
-  const double dg = lane < 16 ? G[lane * 16 + lane] : 1.0;
-  double piv_mine = 1.0, inv_mine = 1.0;
-  const int cj = lane & 15;
-  for (int k = 0; k < r; ++k) {
-    const double piv = G[k * 16 + k];
-    const double d = piv > 0.0 ? sqrt(piv) : 1.0;
-    const double inv = 1.0 / d;
-    if (lane == k) {
-      piv_mine = piv;
-      inv_mine = inv;
-    }
-    wave_sync();
-    if (lane == k) G[k * 16 + k] = d;
-    else if (lane > k && lane < 16) G[k * 16 + lane] *= inv;
-    wave_sync();
+  double c[16];
+  double dg = 1.0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int i = (lane >> 4) + 4 * m;
-      if (i > k && cj >= i) G[i * 16 + cj] -= G[k * 16 + i] * G[k * 16 + cj];
-    }
-    wave_sync();
+  for (int i = 0; i < 16; ++i) {
+    double v = (i < r && j < r) ? G[i * 16 + j] : (i == j ? 1.0 : 0.0);
+    if (i == j && i < r) v += sh;
+    c[i] = v;
+    if (i == j) dg = v;
   }
-  const bool bad = lane < r && (!(piv_mine > pivot_tol * dg) || !isfinite(piv_mine));
+  double piv_mine = 1.0, inv_mine = 1.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k < r) {
+      const double piv = __shfl(c[k], k, 64);
+      const double inv = piv > 0.0 ? rsqrt(piv) : 1.0;
+      if (j == k) {
+        piv_mine = piv;
+        inv_mine = inv;
+        c[k] = piv * inv;
+      } else if (j > k) {
+        c[k] *= inv;
+      }
+#pragma unroll
+      for (int i = k + 1; i < 16; ++i) {
+        const double rki = __shfl(c[k], i, 64);
+        if (j >= i) c[i] -= rki * c[k];
+      }
+    }
+  }
+  const bool bad = j < r && lane < 16 && (!(piv_mine > pivot_tol * dg) || !isfinite(piv_mine));
+  if (lane < 16) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Rl[i * 16 + lane] = i <= lane ? c[i] : 0.0;
+  }
   if (lane < r) {
-    for (int i = 0; i < r; ++i) Rout[i * r + lane] = i <= lane ? G[i * 16 + lane] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i < r) Rout[i * r + lane] = i <= lane ? c[i] : 0.0;
     dinv_out[lane] = inv_mine;
   }
   if (__any(bad) && lane == 0) flag[0] = 1;
@@ -519,7 +543,7 @@ __global__ __launch_bounds__(1024) void k_cqr_chol(const double* __restrict__ pa
                                                    double* __restrict__ Rout, int* flag) {
   __shared__ double q4[4][256];
   __shared__ double G[256];
-  __shared__ double P1[256], P0[256];
+  __shared__ double P1[256], P0[256], Rl[256];
   const int t = threadIdx.x, e = t & 255, qd = t >> 8;
   double g = 0.0;
   for (int b0 = qd; b0 < nblk; b0 += 64) {
@@ -541,7 +565,7 @@ __global__ __launch_bounds__(1024) void k_cqr_chol(const double* __restrict__ pa
   __syncthreads();
   if (t < 256) G[t] = gscale2 * (((q4[0][t] + q4[1][t]) + q4[2][t]) + q4[3][t]);
   __syncthreads();
-  if (t < 64) chol_wave(G, r, shift_coef, pivot_tol, Rnew, dinv_new, flag);
+  if (t < 64) chol_wave(G, Rl, r, shift_coef, pivot_tol, Rnew, dinv_new, flag);
   __syncthreads();
   if (Rp0 && t < r * r) {
     const int i = t / r, j = t % r;
@@ -549,7 +573,7 @@ __global__ __launch_bounds__(1024) void k_cqr_chol(const double* __restrict__ pa
     for (int k = i; k <= j; ++k) {
       double w = 0.0;
       for (int l = k; l <= j; ++l) w += P1[k * 16 + l] * P0[l * 16 + j];
-      v += G[i * 16 + k] * w;
+      v += Rl[i * 16 + k] * w;
     }
     Rout[i * r + j] = v;
   }

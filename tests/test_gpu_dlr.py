@@ -31,13 +31,13 @@ def ctx():
     c.close()
 
 
-def _setup(d, N, nx, r, m_rho, mach=1.5, pert=1e-2):
+def _setup(d, N, nx, r, m_rho, mach=1.5, pert=1e-2, pert_rank=3):
     if d == 2:
         spec = synth.VGridSpec(d=2, n=N, L=8.0, gamma=0.0, C=1 / (2 * math.pi), m_rho=m_rho, m_sigma=8)
     else:
         spec = synth.VGridSpec(d=3, n=N, L=8.0, gamma=1.0, C=1.0, m_rho=m_rho, m_sigma=38)
     vs = oc.setup_from_spec(spec)
-    ini = synth.shock_initial(mach, spec, nx, -30.0, 30.0, pert=pert, pert_rank=3, seed=3)
+    ini = synth.shock_initial(mach, spec, nx, -30.0, 30.0, pert=pert, pert_rank=pert_rank, seed=3)
     prob = dlr.Problem1D(vs=vs, nx=nx, x_lo=-30.0, x_hi=30.0, fL=ini["fL"], fR=ini["fR"])
     X, S, V = synth.lowrank_state(ini["f0"], r, prob.dx, prob.dvd)
     return spec, prob, dlr.State(X, S, V), ini
@@ -77,11 +77,19 @@ def _params(dt, flags, r_max=30, r_min=1):
     return blr.StepParams(dt, 0.2, 1e-10, r_min, r_max, flags)
 
 
-@pytest.mark.parametrize("d,N,nx,r,m_rho", [(2, 16, 24, 4, 8), (3, 8, 16, 3, 4), (3, 16, 40, 5, 2)])
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(2, 16, 24, 4, 8), (3, 8, 16, 3, 4), (3, 16, 40, 5, 2),
+                                             (2, 16, 40, 17, 4), (2, 16, 300, 16, 4)])
 def test_fixed_rank_step_fp64(ctx, d, N, nx, r, m_rho):
+    """r = 16 takes the widest fused x-side and Cholesky QR kernels, r = 17 the
+    general ones (Householder QR, separate x-side kernels); nx = 300 spans
+    two cell blocks."""
     print(f"fixed-rank d={d} N={N} nx={nx} r={r}", flush=True)
     spec, prob, st, _ = _setup(d, N, nx, r, m_rho)
-    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    if r > 8:
+        # the smooth state has singular values down to rounding at this rank:
+        # lift them so that the comparison is well conditioned
+        st = dlr.State(st.X, st.S + 1e-3 * np.abs(st.S).max() * np.eye(r), st.V)
+    g = Gpu(ctx, spec, prob, st, r_cap=max(8, r))
     info = ctx.dlr_step(g.pb, g.st, _params(0.05, blr.BLR_STEP_FP64_COLLISION))
     new, err, _ = dlr.ksl_step(st, prob, 0.05)
     f_ref = new.full()
@@ -201,6 +209,28 @@ def test_add_count_change_is_redone(ctx):
         assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
         f_ref = cur.full()
         assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+
+
+def test_graph_replay_matches_eager(ctx):
+    """Steps recorded as graphs and replayed give the same results as steps
+    issued kernel by kernel: two copies of one state advanced side by side,
+    the eager one in between the replays, compared after every step."""
+    spec, prob, st, _ = _setup(2, 16, 24, 3, 8)   # rank 3 -> +2 -> 3 every step
+    ga = Gpu(ctx, spec, prob, st, r_cap=12)
+    ge = Gpu(ctx, spec, prob, st, r_cap=12)
+    base = blr.BLR_STEP_ADD | blr.BLR_STEP_DROP
+    replays = 0
+    for k in range(7):
+        ia = ctx.dlr_step(ga.pb, ga.st, _params(0.01, base, r_max=12))
+        ie = ctx.dlr_step(ge.pb, ge.st, _params(0.01, base | blr.BLR_STEP_EAGER, r_max=12))
+        torch.cuda.synchronize()
+        replays += ia.ms_collision == 0.0
+        assert ie.ms_collision > 0.0
+        assert (ia.r_added, ia.r_out) == (ie.r_added, ie.r_out)
+        assert ia.err == ie.err and ia.err_ada == ie.err_ada
+        assert np.array_equal(ga.full(), ge.full())
+    print("replayed steps:", replays, flush=True)
+    assert replays >= 4
 
 
 def test_steady_solve_runs_and_reports(ctx):
