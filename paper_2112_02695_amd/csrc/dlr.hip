@@ -915,8 +915,8 @@ struct GramJob {
   }
   void run(StepWork& w) {
     if (gb.nseg == 0) return;
-    // chunks of 64 points: each wave takes 16 points, one round of loads
-    const int nchunk = (int)std::max<long>(1, std::min<long>(2048, (long)w.n / 64));
+    // chunks of 128 points: each wave takes 32 points, one round of eight loads
+    const int nchunk = (int)std::max<long>(1, std::min<long>(2048, (long)w.n / 128));
     long off = 0;
     double bytes = 0.0;
     for (int k = 0; k < gb.nseg; ++k) {

@@ -243,15 +243,32 @@ __global__ void k_copy_R(const double* Rst, long ldr, int r, double* R) {
 }
 
 // ------------------------------------------------------------------ SVD --
+// Sum over aligned groups of lpp in {1, 2, 4, 8} lanes, returned to every lane
+// of the group (quad permutations, then the half-row mirror, which pairs
+// each lane with one of the other quad).
+__device__ __forceinline__ double group_sum(double x, int lpp) {
+  if (lpp >= 2) x += dpp_move<0xb1>(x);   // quad_perm [1,0,3,2]
+  if (lpp >= 4) x += dpp_move<0x4e>(x);   // quad_perm [2,3,0,1]
+  if (lpp >= 8) x += dpp_move<0x141>(x);  // row_half_mirror
+  return x;
+}
+
 // One-sided Jacobi on the columns of B = A (r x r row-major): B W = U Sigma.
+// Columns live in LDS (stride 65 doubles: the column pairs of one round sit
+// in different banks).  Each round rotates rr/2 disjoint column pairs
+// (circle method, a dummy column when r is odd); a pair is handled by a
+// group of lpp lanes, each taking the rows i = sub, sub + lpp, ..; the three
+// column sums are completed inside the group by DPP, so every lane of the
+// group computes the same rotation.  One wavefront: the rounds are ordered
+// by wavefront barriers.
+constexpr int SVS = 65;
 __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A, int r,
                                                    double* __restrict__ U, double* __restrict__ sig,
                                                    double* __restrict__ W, int sweeps) {
-  __shared__ double B[64 * 64];  // column-major: B[c*64 + i]
-  __shared__ double V[64 * 64];
+  __shared__ double B[64 * SVS];  // column c: B[c * SVS + i]
+  __shared__ double V[64 * SVS];
   __shared__ double nrm[64];
   __shared__ int order[64];
-  __shared__ int rot_any;
   const int t = threadIdx.x;
   // all r^2 loads in flight at once (lane t: entries t, t + 64, ..)
   for (int e0 = 0; e0 < r * r; e0 += 64 * 8) {
@@ -266,32 +283,30 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
       const int e = e0 + 64 * k + t;
       if (e < r * r) {
         const int row = e / r, c = e % r;
-        B[c * 64 + row] = v[k];
-        V[c * 64 + row] = (row == c) ? 1.0 : 0.0;
+        B[c * SVS + row] = v[k];
+        V[c * SVS + row] = (row == c) ? 1.0 : 0.0;
       }
     }
   }
   __syncthreads();
-  // Each round rotates rr/2 disjoint column pairs (circle method, with a
-  // dummy column when r is odd); a pair is handled by lpp lanes, each taking
-  // the rows i = sub, sub + lpp, ..; the three column sums are completed by
-  // butterfly exchanges inside the lane group, so every lane of the group
-  // computes the same rotation.
   const int rr = (r % 2) ? r + 1 : r;
   const int np = rr / 2;
   const int lpp = np <= 8 ? 8 : (np <= 16 ? 4 : 2);
   const int slot = t / lpp, sub = t % lpp;
-  (void)rot_any;
+  // slot's pair in round 0 and the circle-method walk: position k (k >= 1)
+  // moves to k + 1 mod (rr - 1) each round, position 0 stays (column rr - 1)
   for (int sw = 0; sw < sweeps; ++sw) {
     int rotated = 0;
     for (int round = 0; round < rr - 1; ++round) {
-      int p = 0, q = 0;
+      int p, q;
       if (slot == 0) {
         p = rr - 1;
         q = round;
       } else {
-        p = (round + slot) % (rr - 1);
-        q = (round - slot + rr - 1) % (rr - 1);
+        p = round + slot;
+        if (p >= rr - 1) p -= rr - 1;
+        q = round - slot;
+        if (q < 0) q += rr - 1;
       }
       if (p > q) {
         const int tmp = p;
@@ -302,16 +317,14 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
       double al = 0, be = 0, ga = 0;
       if (live)
         for (int i = sub; i < r; i += lpp) {
-          const double x = B[p * 64 + i], y = B[q * 64 + i];
+          const double x = B[p * SVS + i], y = B[q * SVS + i];
           al += x * x;
           be += y * y;
           ga += x * y;
         }
-      for (int off = lpp / 2; off > 0; off >>= 1) {
-        al += __shfl_xor(al, off, 64);
-        be += __shfl_xor(be, off, 64);
-        ga += __shfl_xor(ga, off, 64);
-      }
+      al = group_sum(al, lpp);
+      be = group_sum(be, lpp);
+      ga = group_sum(ga, lpp);
       if (live && fabs(ga) > 1e-300 && ga * ga > 1e-30 * (al * be)) {
         // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = tau / g2, written
         // without dividing by g2: t = sign(tau) g2 / (|tau| + sqrt(tau^2 + g2^2))
@@ -319,12 +332,12 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
         const double tt = (tau >= 0 ? g2 : -g2) / (fabs(tau) + sqrt(tau * tau + g2 * g2));
         const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
         for (int i = sub; i < r; i += lpp) {
-          const double x = B[p * 64 + i], y = B[q * 64 + i];
-          B[p * 64 + i] = c * x - sn * y;
-          B[q * 64 + i] = sn * x + c * y;
-          const double vx = V[p * 64 + i], vy = V[q * 64 + i];
-          V[p * 64 + i] = c * vx - sn * vy;
-          V[q * 64 + i] = sn * vx + c * vy;
+          const double x = B[p * SVS + i], y = B[q * SVS + i];
+          B[p * SVS + i] = c * x - sn * y;
+          B[q * SVS + i] = sn * x + c * y;
+          const double vx = V[p * SVS + i], vy = V[q * SVS + i];
+          V[p * SVS + i] = c * vx - sn * vy;
+          V[q * SVS + i] = sn * vx + c * vy;
         }
         rotated = 1;
       }
@@ -334,34 +347,38 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
   }
   if (t < r) {
     double s = 0;
-    for (int i = 0; i < r; ++i) s += B[t * 64 + i] * B[t * 64 + i];
+    for (int i = 0; i < r; ++i) s += B[t * SVS + i] * B[t * SVS + i];
     nrm[t] = sqrt(s);
   }
   __syncthreads();
-  if (t == 0) {  // stable selection sort, descending
-    for (int i = 0; i < r; ++i) order[i] = i;
-    for (int i = 0; i < r; ++i) {
-      int best = i;
-      for (int j = i + 1; j < r; ++j)
-        if (nrm[order[j]] > nrm[order[best]]) best = j;
-      const int tmp = order[i];
-      order[i] = order[best];
-      order[best] = tmp;
+  // descending, ties by index: column t goes to position rank(t)
+  if (t < r) {
+    const double mine = nrm[t];
+    int rank = 0;
+    for (int c = 0; c < r; ++c) {
+      const double o = nrm[c];
+      rank += (o > mine || (o == mine && c < t)) ? 1 : 0;
     }
+    order[rank] = t;
   }
   __syncthreads();
   // U columns (normalised), W columns, sigma; row-major outputs
+  double s_mine = 0.0;
   if (t < r) {
     const int src = order[t];
-    const double s = nrm[src];
-    sig[t] = s;
+    s_mine = nrm[src];
+    sig[t] = s_mine;
+    const double inv = s_mine > 0 ? 1.0 / s_mine : 0.0;
     for (int i = 0; i < r; ++i) {
-      U[i * r + t] = s > 0 ? B[src * 64 + i] / s : 0.0;
-      W[i * r + t] = V[src * 64 + i];
+      U[i * r + t] = B[src * SVS + i] * inv;
+      W[i * r + t] = V[src * SVS + i];
     }
   }
+  // complete U where sigma underflows (tiny or zero columns); rare
+  const double s0 = __shfl(s_mine, 0, 64);
+  const bool small = t < r && !(s_mine > 1e-300 && s_mine > 1e-14 * s0);
+  if (!__any(small)) return;
   __syncthreads();
-  // complete U where sigma underflows (tiny or zero columns)
   if (t == 0) {
     const double tiny = 1e-300;
     for (int j = 0; j < r; ++j) {
