@@ -191,13 +191,18 @@ def main():
         avg_s = dom["ms"] / dom["launches"] / 1e3
         bytes_per_launch = dom["bytes"] / dom["launches"]
         achieved = bytes_per_launch / avg_s / 1e9
+        # HBM bytes per launch from rocprofv3 counters, valid only while the
+        # kernel source is the one they were taken on
         traffic = None
         try:
+            import hashlib
             with open(args.traffic) as fh:
                 tr = json.load(fh)
-            if tr.get("kernel") == dom["name"]:
+            with open(os.path.join(ROOT, tr["source"]), "rb") as fh:
+                same = hashlib.sha256(fh.read()).hexdigest() == tr.get("source_sha256")
+            if tr.get("kernel") == dom["name"] and same:
                 traffic = tr.get("bytes_per_launch")
-        except (OSError, ValueError):
+        except (OSError, ValueError, KeyError):
             pass
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
