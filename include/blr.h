@@ -126,7 +126,8 @@ typedef struct {
  *   X  r_cap rows of nx   (row i = X_i)
  *   S  r_cap x r_cap row-major, leading r x r block used
  *   V  r_cap rows of n^d  (row j = V_j)
- * r is updated by the adaptive steps; 1 <= r <= r_cap <= 64.  step counts
+ * r is updated by the adaptive steps; 1 <= r <= r_cap <= 64.  Rows r ..
+ * r_cap - 1 of X and V are scratch: a step may write them.  step counts
  * the steps taken; seed is reserved (the step draws no random numbers: the
  * random block X_h of the basis augmentation, Sec. 3.1, multiplies a zero
  * block of S, so the step never reads it and uses zero rows). */
@@ -188,7 +189,8 @@ blr_status blr_state_from_full(blr_ctx ctx, const blr_problem* pb, const double*
  * forward Euler and QR (Sec. 2.4, first-order upwind transport of eq.
  * scheme:fullupwind, ghost values of eq. boundary general) -> residual err
  * from the pieces (eqs. err low rank1, err low rank2) -> [drop with
- * drop_tol = c_drop * err] -> err_ada.  On error *state is left unchanged. */
+ * drop_tol = c_drop * err] -> err_ada.  On error the state (r, S and the first
+ * r rows of X and V) is left unchanged. */
 blr_status blr_dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* state,
                         const blr_step_params* sp, blr_step_info* info);
 

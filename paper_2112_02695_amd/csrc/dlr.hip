@@ -535,6 +535,66 @@ __global__ void k_pack(const double* res, const int* flag, const double* sb, con
   }
 }
 
+// L-step on the FP64 matrix cores, for r <= 16: each wavefront takes 16
+// velocity points q0..q0+15 and forms the 16 x 16 tiles (rows i < 16)
+//   l = S2 V,  dp = Dp V,  dm = Dm V   (sum over m < r)
+//   cq = T Q                          (sum over pairs p < P)
+// with v_mfma_f64_16x16x4f64 (lane l supplies the first operand's element
+// (l % 16, l / 16) and the second's (l / 16, l % 16); it holds result
+// entries (4v + l / 16, l % 16)), then
+//   L1_i = l_i - dt (v1+ dp_i + v1- dm_i) + dt cq_i,  dL_i = L1_i - l_i.
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_lstep_mfma(const double* __restrict__ V, int r, int n,
+                                                    const double* __restrict__ S2,
+                                                    const double* __restrict__ Dp,
+                                                    const double* __restrict__ Dm,
+                                                    const double* __restrict__ T,
+                                                    const TQ* __restrict__ Q, int P, double dt,
+                                                    VGeo g, double* __restrict__ L1,
+                                                    double* __restrict__ dL) {
+  const int lane = threadIdx.x & 63;
+  const int q0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (q0 >= n) return;
+  const int li = lane & 15, lk = lane >> 4;
+  const int qq = q0 + li;  // this lane's point in the second operand and the result
+  const bool qin = qq < n;
+  v4d al = {0.0, 0.0, 0.0, 0.0}, ap = al, am = al, ac = al;
+  for (int m0 = 0; m0 < r; m0 += 4) {
+    const int m = m0 + lk;
+    const double v = (m < r && qin) ? V[(long)m * n + qq] : 0.0;
+    const bool rin = li < r && m < r;
+    const double s2 = rin ? S2[li * r + m] : 0.0;
+    const double dpv = rin ? Dp[li * r + m] : 0.0;
+    const double dmv = rin ? Dm[li * r + m] : 0.0;
+    al = __builtin_amdgcn_mfma_f64_16x16x4f64(s2, v, al, 0, 0, 0);
+    ap = __builtin_amdgcn_mfma_f64_16x16x4f64(dpv, v, ap, 0, 0, 0);
+    am = __builtin_amdgcn_mfma_f64_16x16x4f64(dmv, v, am, 0, 0, 0);
+  }
+  for (int p0 = 0; p0 < P; p0 += 16) {
+    double qv[4], tv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int p = p0 + 4 * u + lk;
+      qv[u] = (p < P && qin) ? (double)Q[(long)p * n + qq] : 0.0;
+      tv[u] = (p < P && li < r) ? T[li * P + p] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ac = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[u], qv[u], ac, 0, 0, 0);
+  }
+  if (!qin) return;
+  const double v1 = g.v1(qq);
+  const double vp = v1 > 0 ? v1 : 0.0, vm = v1 < 0 ? v1 : 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * v + lk;
+    if (i < r) {
+      const double d = -dt * (vp * ap[v] + vm * am[v]) + dt * ac[v];
+      L1[(long)i * n + qq] = al[v] + d;
+      dL[(long)i * n + qq] = d;
+    }
+  }
+}
+
 // ---------------------------------------------- fused x-side kernels --
 // For r <= RM <= 16.  K = X S (K_l(x) = sum_i X_i(x) S_il) is formed where
 // it is needed instead of being stored; every block computes the ghost
@@ -989,12 +1049,18 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
 
   // working copies (rank up to r_cap); the caller's state is written only at commit
   const int rc = st->r_cap;
-  double* Xw = w.get("Xw", (size_t)rc * nx);
-  double* Vw = w.get("Vw", (size_t)rc * n);
+  // X and V are read in place: the step reads their first r rows only and
+  // uses rows r.. (scratch of the state, below r_cap) for the added
+  // functions; the Householder variant of the add rewrites every row of V and
+  // works on a copy
+  double* Xw = st->X;
+  double* Vw = st->V;
   double* Sw = w.get("Sw", (size_t)rc * rc);
   int r = st->r;
-  BLR_HIP(hipMemcpyAsync(Xw, st->X, (size_t)r * nx * 8, hipMemcpyDeviceToDevice, s));
-  BLR_HIP(hipMemcpyAsync(Vw, st->V, (size_t)r * n * 8, hipMemcpyDeviceToDevice, s));
+  if (add && at.rb > 0 && at.householder) {
+    Vw = w.get("Vw", (size_t)rc * n);
+    BLR_HIP(hipMemcpyAsync(Vw, st->V, (size_t)r * n * 8, hipMemcpyDeviceToDevice, s));
+  }
   hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r * r, 256)), dim3(256), 0, s, st->S, rc, r, Sw, r);
   BLR_CHECK_LAUNCH();
 
@@ -1218,7 +1284,18 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   xside(S2, true);
   double* L1 = w.get("L1", (size_t)r * n);
   double* dL = w.get("dL", (size_t)r * n);
-  {
+  if (r <= 16) {
+    timed_begin("dlr.lstep", (double)n * (r + P + 2 * r) * 8.0, s);
+    const dim3 grid(blocks(n, 64));
+    if (fp64c)
+      hipLaunchKernelGGL(dk::k_lstep_mfma<double>, grid, dim3(256), 0, s, Vw, r, n, S2, Dp, Dm, T,
+                         (const double*)Qs, P, dt, w.g, L1, dL);
+    else
+      hipLaunchKernelGGL(dk::k_lstep_mfma<float>, grid, dim3(256), 0, s, Vw, r, n, S2, Dp, Dm, T,
+                         (const float*)Qs, P, dt, w.g, L1, dL);
+    BLR_CHECK_LAUNCH();
+    timed_end(s);
+  } else {
     const dim3 grid(blocks(n, 256), (r + 7) / 8);
     timed_begin("dlr.lstep", (double)n * (r + P + 2 * r) * 8.0, s);
     if (fp64c)

@@ -419,59 +419,68 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Cholesky R^T R = G + shift I of the leading r x r block of G (16 x 16,
-// row-major, in LDS), on one wavefront: lane j keeps column j in registers
-// (right-looking; pivot and row k move between lanes by shuffles, 1 / R_kk
-// from a reciprocal square root).  Rows and columns r..15 are completed with
-// the identity.  Writes R (r x r row-major, upper; also 16 x 16 to Rl in
-// LDS) and 1 / diag(R).
-// flag[0] = 1 when a pivot R_kk^2 is not finite or not above pivot_tol times
-// the diagonal of G + shift I.
-__device__ void chol_wave(const double* G, double* Rl, int r, double shift_coef, double pivot_tol,
+// row-major, in LDS; overwritten), on one wavefront, in outer-product form:
+// step k subtracts G_ki G_kj / G_kk from the trailing entries (two per lane,
+// one wavefront barrier per step); afterwards R_kj = G_kj / sqrt(G_kk) for
+// j >= k.  Rows and columns r..15 are completed with the identity.  Writes
+// R (r x r row-major, upper; also 16 x 16 to Rl in LDS) and 1 / diag(R).
+// flag[0] = 1 when a pivot is not finite or not above pivot_tol times the
+// diagonal of G + shift I.
+__device__ void chol_wave(double* G, double* Rl, int r, double shift_coef, double pivot_tol,
                           double* __restrict__ Rout, double* __restrict__ dinv_out, int* flag) {
   const int lane = threadIdx.x & 63;
-  const int j = lane & 15;
   double tr = 0.0;
   for (int k = 0; k < r; ++k) tr += G[k * 16 + k];
   const double sh = shift_coef * tr;
-  double c[16];
-  double dg = 1.0;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    double v = (i < r && j < r) ? G[i * 16 + j] : (i == j ? 1.0 : 0.0);
-    if (i == j && i < r) v += sh;
-    c[i] = v;
-    if (i == j) dg = v;
+  wave_sync();
+  for (int e = lane; e < 256; e += 64) {
+    const int i = e / 16, j = e % 16;
+    if (i >= r || j >= r) G[e] = (i == j) ? 1.0 : 0.0;
+    else if (i == j) G[e] += sh;
   }
-  double piv_mine = 1.0, inv_mine = 1.0;
+  wave_sync();
+  const double dg = lane < 16 ? G[lane * 16 + lane] : 1.0;  // diagonal before elimination
+  // lane owns the upper-triangle entries (i, j) = (lane / 16 + 4 m, lane % 16)
+  const int cj = lane & 15, i0 = lane >> 4;
+  for (int k = 0; k < r; ++k) {
+    const double d = G[k * 16 + k];
+    const double inv = d != 0.0 ? 1.0 / d : 0.0;
+    double upd[4];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (k < r) {
-      const double piv = __shfl(c[k], k, 64);
-      const double inv = piv > 0.0 ? rsqrt(piv) : 1.0;
-      if (j == k) {
-        piv_mine = piv;
-        inv_mine = inv;
-        c[k] = piv * inv;
-      } else if (j > k) {
-        c[k] *= inv;
-      }
-#pragma unroll
-      for (int i = k + 1; i < 16; ++i) {
-        const double rki = __shfl(c[k], i, 64);
-        if (j >= i) c[i] -= rki * c[k];
-      }
+    for (int m = 0; m < 4; ++m) {
+      const int i = i0 + 4 * m;
+      upd[m] = (i > k && cj >= i) ? G[i * 16 + cj] - G[k * 16 + i] * inv * G[k * 16 + cj] : 0.0;
     }
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = i0 + 4 * m;
+      if (i > k && cj >= i) G[i * 16 + cj] = upd[m];
+    }
+    wave_sync();
   }
-  const bool bad = j < r && lane < 16 && (!(piv_mine > pivot_tol * dg) || !isfinite(piv_mine));
+  // G_kk now holds the pivots; R_kj = G_kj / sqrt(G_kk)
+  bool bad = false;
   if (lane < 16) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Rl[i * 16 + lane] = i <= lane ? c[i] : 0.0;
+    const double piv = G[lane * 16 + lane];
+    if (lane < r && (!(piv > pivot_tol * dg) || !isfinite(piv))) bad = true;
   }
-  if (lane < r) {
+  double rs[4];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if (i < r) Rout[i * r + lane] = i <= lane ? c[i] : 0.0;
-    dinv_out[lane] = inv_mine;
+  for (int m = 0; m < 4; ++m) {
+    const int i = i0 + 4 * m;
+    const double piv = G[i * 16 + i];
+    const double q = piv > 0.0 ? rsqrt(piv) : 1.0;
+    rs[m] = cj >= i ? G[i * 16 + cj] * q : 0.0;
+  }
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) Rl[(i0 + 4 * m) * 16 + cj] = rs[m];
+  wave_sync();
+  if (lane < r) {
+    for (int i = 0; i < r; ++i) Rout[i * r + lane] = Rl[i * 16 + lane];
+    const double piv = G[lane * 16 + lane];
+    dinv_out[lane] = piv > 0.0 ? rsqrt(piv) : 1.0;
   }
   if (__any(bad) && lane == 0) flag[0] = 1;
 }
