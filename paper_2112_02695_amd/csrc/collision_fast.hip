@@ -188,33 +188,50 @@ __global__ __launch_bounds__(256) void k_reduce_all(const float* __restrict__ sh
 }
 
 // ------------------------------------------------------- pair transforms
-// workgroup = (pair p, group g of ga consecutive radial nodes): for each node
-// a of the group, DFT(P_pa) times w_a(|k|^2)/n is added into a register
-// accumulator of the half spectrum k_2 <= N/2, written once per group.
+// workgroup = (pair p, group g of ga consecutive radial nodes).  Two nodes a,
+// b of the group share one complex transform Z = DFT(P_pa + i P_pb); with
+// Zc(k) = conj(Z(-k)) (the partner line of thread (-k0, -k1), exchanged
+// through LDS) the two real-field spectra are (Z + Zc) / 2 and (Z - Zc) / 2i.
+// The two nodes belong to one pair at neighbouring radii, so the magnitudes
+// sharing a transform are alike.  w_a(|k|^2)/n times each spectrum is added
+// into a register accumulator of the half spectrum k_2 <= N/2, written once
+// per group.
 template <int N>
 __global__ __launch_bounds__(N * N) void k_pair_spec(const float* __restrict__ pa,
                                                      const float* __restrict__ fw,
                                                      float2* __restrict__ wsp, int P, int mrho,
                                                      int nkk, int ga, int ng) {
-  __shared__ float L[Geo<N>::LDS];
-  constexpr int n = Geo<N>::n, H = Geo<N>::H;
+  constexpr int n = Geo<N>::n, H = Geo<N>::H, NT = Geo<N>::NT;
+  // partner exchange: per thread the line elements 0 and N/2 .. N-1 (H values)
+  // of both components, rows of 2H + 1 floats (odd: no bank conflicts)
+  constexpr int XR = 2 * H + 1;
+  constexpr int LSZ = Geo<N>::LDS > NT * XR ? Geo<N>::LDS : NT * XR;
+  __shared__ float L[LSZ];
   const int t = threadIdx.x;
   const int u = t / N, w = t % N;
   const int p = blockIdx.x % P;
   const int g = blockIdx.x / P;
   const int a0 = g * ga, a1 = min(mrho, a0 + ga);
   const int k0 = ctr<N>(u), k1 = ctr<N>(w);
+  // the thread holding line (-k0, -k1) after the last stage
+  const int partner = ((N - u) % N) * N + (N - w) % N;
   float accr[H], acci[H];
 #pragma unroll
   for (int j = 0; j < H; ++j) accr[j] = acci[j] = 0.f;
-  for (int a = a0; a < a1; ++a) {
+  for (int a = a0; a < a1; a += 2) {
+    const bool two = a + 1 < a1;
     // stage along axis 0: thread (i1, i2) = (u, w), coalesced loads
-    const float* src = pa + ((long)a * P + p) * n + u * N + w;
+    // uniform field bases, per-thread 32-bit offsets; a lone last node reads
+    // its own field twice and drops the copy
+    const float* src = pa + ((long)a * P + p) * n;
+    const float* src2 = two ? src + (long)P * n : src;
     float re[N], im[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      re[j] = src[j * N * N];
-      im[j] = 0.f;
+      const int o = j * N * N + t;
+      re[j] = src[o];
+      const float v = src2[o];
+      im[j] = two ? v : 0.f;
     }
     fft::dft<float, N, -1>(re, im);
     exchange<N, 0, 1>(re, L, u, w);
@@ -224,13 +241,44 @@ __global__ __launch_bounds__(N * N) void k_pair_spec(const float* __restrict__ p
     exchange<N, 1, 2>(im, L, u, w);
     fft::dft<float, N, -1>(re, im);
     // thread (k0, k1) = (u, w) holds k2 = 0..N-1; keep k2 <= N/2
-    const float* f = fw + (long)a * nkk;
+    // a lone node (im = 0) takes the same path: Zc = Z there, and node b's
+    // weight is zero
+    const float* fa = fw + (long)a * nkk;
+    const float* fb = two ? fa + nkk : fa;
+    const float hb = two ? 0.5f : 0.f;
+    // Z(-k) for k2 = 0..H-1 is the partner's element (N - j) % N: each thread
+    // publishes its elements 0 and N/2 .. N-1
+    float* row = L + t * XR;
+    const float* prow = L + partner * XR;
+    row[0] = re[0];
+    row[H] = im[0];
+#pragma unroll
+    for (int m = 1; m < H; ++m) {
+      row[m] = re[N / 2 + m - 1];
+      row[H + m] = im[N / 2 + m - 1];
+    }
+    __syncthreads();
+    float cr[H], ci[H];
+    // partner element (N - j) % N sits at slot 0 for j = 0, else N - j - N/2 + 1
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const int m = j == 0 ? 0 : N - j - N / 2 + 1;
+      cr[j] = prow[m];
+      ci[j] = -prow[H + m];
+    }
+    __syncthreads();
+    // weights are fetched here, not during the transform (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < H; ++j) {
       const int k2 = ctr<N>(j);
-      const float wt = f[k0 * k0 + k1 * k1 + k2 * k2];
-      accr[j] += wt * re[j];
-      acci[j] += wt * im[j];
+      const int kk = k0 * k0 + k1 * k1 + k2 * k2;
+      const float wa = 0.5f * fa[kk], wb = hb * fb[kk];
+      // node a: (Z + Zc) / 2;  node b: (Z - Zc) / 2i = (Im(Z - Zc) - i Re(Z - Zc)) / 2
+      const float sr = re[j] + cr[j], si = im[j] + ci[j];
+      const float dr = re[j] - cr[j], di = im[j] - ci[j];
+      accr[j] += wa * sr + wb * di;
+      acci[j] += wa * si - wb * dr;
     }
   }
   float2* dst = wsp + (((long)p * ng + g) * N * N + (long)(u * N + w)) * H;
@@ -253,10 +301,13 @@ __global__ __launch_bounds__(N * N) void k_final_fused(const float2* __restrict_
                                                        int P, int ng, FinalArgs fa) {
   constexpr int n = Geo<N>::n, H = Geo<N>::H, NT = Geo<N>::NT;
   constexpr int HP = H + 1;  // padded half row
-  __shared__ float LR[N * N * HP];
-  __shared__ float LI[N * N * HP];
+  // two half-spectrum planes during the transform, then one padded real field
+  static_assert(N * N * (N + 1) <= 2 * N * N * HP, "gain field must fit the transform buffer");
+  __shared__ float LB[2 * N * N * HP];
   __shared__ double red[5][NT / 64];
   __shared__ double lamb[5];
+  float* LR = LB;
+  float* LI = LB + N * N * HP;
   const int t = threadIdx.x;
   const int p = blockIdx.x;
   const int li = pidx[p], lj = pidx[P + p], row = pidx[2 * P + p];
@@ -309,51 +360,66 @@ __global__ __launch_bounds__(N * N) void k_final_fused(const float2* __restrict_
     __syncthreads();
   }
   // stage C, axis 2: thread (i0, i1); full Hermitian line from the half
-  const int i0 = t / N, i1 = t % N;
-  float re[N], im[N];
+  {
+    const int i0 = t / N, i1 = t % N;
+    float re[N], im[N];
 #pragma unroll
-  for (int j = 0; j < H; ++j) {
-    re[j] = LR[(i0 * N + i1) * HP + j];
-    im[j] = LI[(i0 * N + i1) * HP + j];
-  }
-#pragma unroll
-  for (int j = H; j < N; ++j) {
-    re[j] = re[N - j];
-    im[j] = -im[N - j];
-  }
-  fft::dft<float, N, +1>(re, im);
-  // gain - loss
-  const long off = (long)(i0 * N + i1) * N;
-  const float* vi = vp + (long)li * n + off;
-  const float* vj = vp + (long)lj * n + off;
-  const float* lmi = lam + (long)li * n + off;
-  const float* lmj = lam + (long)lj * n + off;
-#pragma unroll
-  for (int j = 0; j < N; ++j) re[j] = re[j] - 0.5f * (vj[j] * lmi[j] + vi[j] * lmj[j]);
-  if (fa.conserve) {
-    const double v0 = -fa.L + i0 * fa.dv, v1 = -fa.L + i1 * fa.dv;
-    double m[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const double v2 = -fa.L + j * fa.dv;
-      const double q = (double)re[j];
-      m[0] += q;
-      m[1] += q * v0;
-      m[2] += q * v1;
-      m[3] += q * v2;
-      m[4] += q * (v0 * v0 + v1 * v1 + v2 * v2);
+    for (int j = 0; j < H; ++j) {
+      re[j] = LR[(i0 * N + i1) * HP + j];
+      im[j] = LI[(i0 * N + i1) * HP + j];
     }
+#pragma unroll
+    for (int j = H; j < N; ++j) {
+      re[j] = re[N - j];
+      im[j] = -im[N - j];
+    }
+    fft::dft<float, N, +1>(re, im);
+    __syncthreads();  // every half row has been read
+    // the gain field back to LDS, rows of N + 1
+#pragma unroll
+    for (int j = 0; j < N; ++j) LB[(i0 * N + i1) * (N + 1) + j] = re[j];
+  }
+  __syncthreads();
+  // gain - loss with coalesced access: thread t holds the points e = k * NT + t,
+  // (i0, i1, i2) = (k, t / N, t % N)
+  const int u1 = t / N, u2 = t % N;
+  const float* vi = vp + (long)li * n + t;
+  const float* vj = vp + (long)lj * n + t;
+  const float* lmi = lam + (long)li * n + t;
+  const float* lmj = lam + (long)lj * n + t;
+  const double v1 = -fa.L + u1 * fa.dv, v2 = -fa.L + u2 * fa.dv;
+  const double s12 = v1 * v1 + v2 * v2;
+  double m[5] = {0, 0, 0, 0, 0};
+  float q[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const long o = (long)k * NT;
+    q[k] = LB[(k * N + u1) * (N + 1) + u2] - 0.5f * (vj[o] * lmi[o] + vi[o] * lmj[o]);
+    const double v0 = -fa.L + k * fa.dv;
+    const double x = (double)q[k];
+    m[0] += x;
+    m[1] += x * v0;
+    m[2] += x * v1;
+    m[3] += x * v2;
+    m[4] += x * (v0 * v0 + s12);
+    // keep the five sums plane by plane (otherwise all N widened values are
+    // held at once and spill); at most eight planes of loads in flight
+    asm volatile("" : "+v"(m[0]), "+v"(m[1]), "+v"(m[2]), "+v"(m[3]), "+v"(m[4]));
+    if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+  }
+  if (fa.conserve) {
     // deterministic reduction: wave sums then a fixed-order sum of waves
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      double x = m[k];
+    for (int c = 0; c < 5; ++c) {
+      double x = m[c];
+#pragma unroll
       for (int off2 = 32; off2 > 0; off2 >>= 1) x += __shfl_down(x, off2, 64);
-      if ((t & 63) == 0) red[k][t >> 6] = x;
+      if ((t & 63) == 0) red[c][t >> 6] = x;
     }
     __syncthreads();
     if (t < 5) {
       double s = 0;
-      for (int k = 0; k < NT / 64; ++k) s += red[t][k];
+      for (int c = 0; c < NT / 64; ++c) s += red[t][c];
       lamb[t] = s * fa.w;
     }
     __syncthreads();
@@ -361,22 +427,26 @@ __global__ __launch_bounds__(N * N) void k_final_fused(const float2* __restrict_
       double l[5];
       for (int i = 0; i < 5; ++i) {
         l[i] = 0;
-        for (int k = 0; k < 5; ++k) l[i] += fa.minv[i * 5 + k] * lamb[k];
+        for (int c = 0; c < 5; ++c) l[i] += fa.minv[i * 5 + c] * lamb[c];
       }
       for (int i = 0; i < 5; ++i) red[i][0] = l[i];
     }
     __syncthreads();
     const double l0 = red[0][0], l1 = red[1][0], l2 = red[2][0], l3 = red[3][0], l4 = red[4][0];
+    const double base = l0 + l2 * v1 + l3 * v2 + l4 * s12;
+    // v0 advanced by dv per plane (not the closed form above), so that the
+    // 32 nodes are not kept live in registers across the reduction
+    double v0 = -fa.L;
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const double v2 = -fa.L + j * fa.dv;
-      const double c = l0 + l1 * v0 + l2 * v1 + l3 * v2 + l4 * (v0 * v0 + v1 * v1 + v2 * v2);
-      re[j] = (float)((double)re[j] - fa.w * c);
+    for (int k = 0; k < N; ++k) {
+      const double c = base + l1 * v0 + l4 * v0 * v0;
+      q[k] = (float)((double)q[k] - fa.w * c);
+      v0 += fa.dv;
     }
   }
-  float* dst = Q + (long)row * n + off;
+  float* dst = Q + (long)row * n + t;
 #pragma unroll
-  for (int j = 0; j < N; ++j) dst[j] = re[j];
+  for (int k = 0; k < N; ++k) dst[(long)k * NT] = q[k];
 }
 
 }  // namespace fastk
@@ -395,15 +465,16 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   float* Sh = (float*)ctx->buf("fast.Sh", (size_t)rb * h.mrho * h.msig * n * sizeof(float));
   float* Pa = (float*)ctx->buf("fast.Pa", (size_t)h.mrho * P * n * sizeof(float));
   // radial nodes per pair-transform workgroup: one workgroup fills a CU, so
-  // the launch takes about ceil(P * ng / CUs) rounds of ga transforms; each
-  // extra group costs the final kernel one more half-spectrum read
+  // the launch takes about ceil(P * ng / CUs) rounds of ceil(ga / 2)
+  // transforms (two nodes per transform); each extra group costs the final
+  // kernel one more half-spectrum read
   int ga = 1;
   {
     double best = 1e300;
     for (int g = 1; g <= h.mrho; ++g) {
       const int ngc = (h.mrho + g - 1) / g;
       const double rounds = std::ceil((double)P * ngc / ctx->cu_count());
-      const double cost = rounds * g + 0.1 * ngc;
+      const double cost = rounds * ((g + 1) / 2) + 0.1 * ngc;
       if (cost < best - 1e-9) {
         best = cost;
         ga = g;
