@@ -81,21 +81,24 @@ __global__ __launch_bounds__(N * N) void k_shift_fused(const float2* __restrict_
   constexpr int n = Geo<N>::n;
   const int t = threadIdx.x;
   const int u = t / N, w = t % N;
-  for (long f = blockIdx.x; f < nfields; f += gridDim.x) {
-    const int p = (int)(f % nbp);
-    const int a = (int)((f / nbp) % mrho);
-    const long ib = f / ((long)nbp * mrho);
-    const float2* ph = phase + ((long)a * nbp + p) * 3 * N;
-    // stage along axis 2: thread (k0, k1) = (u, w)
+  // field count < 2^31 (checked by the host): 32-bit index arithmetic
+  const int nf = (int)nfields;
+  for (int f = blockIdx.x; f < nf; f += gridDim.x) {
+    const int p = f % nbp;
+    const int a = (f / nbp) % mrho;
+    const int ib = f / (nbp * mrho);
+    const float2* ph = phase + (a * nbp + p) * 3 * N;
+    // stage along axis 2: thread (k0, k1) = (u, w).  cos x + sin x is the real
+    // part of e^{ix} (1 - i): with C = c01 (1 - i), Re(C ph2) = C.x ph2.x - C.y ph2.y
     const float2 c01 = cmul(ph[u], ph[N + w]);
-    const float4* src = reinterpret_cast<const float4*>(vh + ib * n + (long)(u * N + w) * N);
+    const float cx = c01.x + c01.y, cy = c01.y - c01.x;
+    const float4* src = reinterpret_cast<const float4*>(vh + (long)ib * n + (u * N + w) * N);
     float re[N], im[N];
 #pragma unroll
     for (int j = 0; j < N / 2; ++j) {
       const float4 v = src[j];
-      const float2 ca = cmul(c01, ph[2 * N + 2 * j]);
-      const float2 cb = cmul(c01, ph[2 * N + 2 * j + 1]);
-      const float fa = ca.x + ca.y, fb = cb.x + cb.y;
+      const float2 pa = ph[2 * N + 2 * j], pb = ph[2 * N + 2 * j + 1];
+      const float fa = cx * pa.x - cy * pa.y, fb = cx * pb.x - cy * pb.y;
       re[2 * j] = v.x * fa;
       im[2 * j] = v.y * fa;
       re[2 * j + 1] = v.z * fb;
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(N * N) void k_shift_fused(const float2* __restrict_
     exchange<N, 1, 0>(im, L, u, w);
     fft::dft<float, N, +1>(re, im);
     // thread (i1, i2) = (u, w) holds the line over i0: coalesced stores
-    const long base = ((ib * mrho + a) * msig) * (long)n + u * N + w;
+    const long base = (((long)ib * mrho + a) * msig) * (long)n + t;
     float* s1 = sh + base + (long)bp_b[p] * n;
     float* s2 = sh + base + (long)bp_bb[p] * n;
 #pragma unroll
@@ -180,6 +183,79 @@ __global__ __launch_bounds__(256) void k_reduce_all(const float* __restrict__ sh
   for (int s = 0; s < G; ++s) {
 #pragma unroll
     for (int v = DIAG ? s : 0; v < G; ++v) {
+      const int row = tile.out[s * G + v];
+      if (row >= 0) out[(long)row * n] = acc[p];
+      ++p;
+    }
+  }
+}
+
+// Diagonal tile with the antipodal pairs in the kernel arguments (element
+// offsets of the two fields and the weight, uniform registers) and the next
+// pair's 2G values loaded while the current pair's products accumulate.
+constexpr int kMaxBp = 32;
+struct BpArgs {
+  int off_b[kMaxBp];
+  int off_bb[kMaxBp];
+  float w[kMaxBp];
+};
+
+template <int G>
+__global__ __launch_bounds__(256) void k_reduce_diag(const float* __restrict__ sh,
+                                                     float* __restrict__ pa, ReduceTile tile,
+                                                     BpArgs bpa, int n, int mrho, int msig,
+                                                     int nbp, int P) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (q >= n) return;
+  constexpr int NP = G * (G + 1) / 2;
+  // field (bi[s], a, sigma) starts at ((bi[s] mrho + a) msig + sigma) n.  Slots
+  // s >= ni read basis bi[0]: their sums belong to no output row (out < 0)
+  // and are never stored, so no masking is needed.
+  const float* base = sh + (long)a * msig * n + q;
+  long so[G];
+#pragma unroll
+  for (int s = 0; s < G; ++s) so[s] = (long)tile.bi[s < tile.ni ? s : 0] * mrho * msig * n;
+  float acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = 0.f;
+  auto load = [&](int b, float(&x)[G], float(&y)[G]) {
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      x[s] = base[so[s] + bpa.off_b[b]];
+      y[s] = base[so[s] + bpa.off_bb[b]];
+    }
+  };
+  auto accum = [&](float wt, const float(&x)[G], const float(&y)[G]) {
+    int p = 0;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      const float xs = wt * x[s], ys = wt * y[s];
+#pragma unroll
+      for (int v = s; v < G; ++v) {
+        acc[p] += xs * y[v] + ys * x[v];
+        ++p;
+      }
+    }
+  };
+  // two register sets alternate (unrolled by two, no copies): the loads of
+  // the next sigma pair are in flight while the current one accumulates
+  float x0[G], y0[G], x1[G], y1[G];
+  load(0, x0, y0);
+  int bp = 0;
+  for (; bp + 1 < nbp; bp += 2) {
+    load(bp + 1, x1, y1);
+    accum(bpa.w[bp], x0, y0);
+    load(bp + 2 < nbp ? bp + 2 : bp + 1, x0, y0);
+    accum(bpa.w[bp + 1], x1, y1);
+  }
+  if (bp < nbp) accum(bpa.w[bp], x0, y0);
+  float* out = pa + (long)a * P * n + q;
+  int p = 0;
+#pragma unroll
+  for (int s = 0; s < G; ++s) {
+#pragma unroll
+    for (int v = s; v < G; ++v) {
       const int row = tile.out[s * G + v];
       if (row >= 0) out[(long)row * n] = acc[p];
       ++p;
@@ -492,6 +568,7 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   int* didx = (int*)ctx->upload("fast.idx", idx.data(), idx.size() * sizeof(int));
   // shifts: persistent-style grid, each workgroup loops over fields
   {
+    require(nfields < (1L << 31), "fast collision: too many shift fields");
     const long grid = std::min<long>(nfields, 2048);
     timed_begin("fast.shift", (double)nfields * n * (2 * sizeof(float)), s);
     hipLaunchKernelGGL(k_shift_fused<N>, dim3((unsigned)grid), dim3(N * N), 0, s, Vh,
@@ -503,6 +580,12 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   {
     bool diag_only = false;
     auto tiles = plan_tiles(rb, pl.li, pl.lj, 12, diag_only);
+    BpArgs bpa{};
+    for (int p = 0; p < h.nbp && p < kMaxBp; ++p) {
+      bpa.off_b[p] = h.bp_b[p] * n;
+      bpa.off_bb[p] = h.bp_bb[p] * n;
+      bpa.w[p] = (float)h.wsig[h.bp_b[p]];
+    }
     for (const auto& t : tiles) {
       const bool diag = t.bi[0] == t.bj[0];
       int nvalid = 0;
@@ -510,7 +593,10 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
       const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
       timed_begin("fast.reduce", (double)h.mrho * n * (nload * h.nbp + nvalid) * sizeof(float), s);
       const dim3 grid((n + 255) / 256, h.mrho);
-      if (diag)
+      if (diag && h.nbp <= kMaxBp)
+        hipLaunchKernelGGL((k_reduce_diag<12>), grid, dim3(256), 0, s, Sh, Pa, t, bpa, n, h.mrho,
+                           h.msig, h.nbp, P);
+      else if (diag)
         hipLaunchKernelGGL((k_reduce_all<12, true>), grid, dim3(256), 0, s, Sh, Pa, t,
                            (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
       else
