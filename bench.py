@@ -17,6 +17,12 @@ step of a configuration on, as a replayed HIP graph).  A second, shorter pass
 of the same steps with the library's kernel events on gives the per-kernel
 times and the roofline of the dominant kernel.
 
+Latency: the wall time of each timed step (p50, p99) on the batched FP32
+path, and of three steps of the same workload on the plain FP64 per-pair
+schedule.  A steady solve is a sequence of such steps (one host wait each),
+so its latency is the step count times these; a steady state at this size
+takes more than 10^4 steps, so no solve is timed here.
+
 Prints ONE JSON line (rank 0, N = 1 only).  Inputs are resident in HBM before
 the timed region starts.
 """
@@ -140,8 +146,11 @@ def main():
     torch.cuda.synchronize()
     counted[0] = 0
     t0 = time.perf_counter()
+    step_wall = []
     for _ in range(args.steps):
-        one_step()
+        ts = time.perf_counter()
+        one_step()   # a step ends with the library's one host wait (the rank decision)
+        step_wall.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -211,6 +220,38 @@ def main():
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "share_of_step": round(dom["ms"] / (ktime * 1e3), 3)}
 
+    def pct(xs, q):
+        xs = sorted(xs)
+        return xs[min(len(xs) - 1, int(math.ceil(q * len(xs))) - 1)]
+
+    latency = {"batched_step_ms_p50": round(1e3 * pct(step_wall, 0.50), 4),
+               "batched_step_ms_p99": round(1e3 * pct(step_wall, 0.99), 4),
+               "batched_samples": len(step_wall)}
+    # the same step on the plain FP64 per-pair schedule (fresh copy of the
+    # initial factors; one untimed step first)
+    if args.mode == "step" and not args.no_plain:
+        vgp = blr.vgrid_from_spec(spec, blr.BLR_PLAIN_SCHEDULE)
+        pbp = ctx.make_problem(vgp, nx, -30.0, 30.0, fL, fR)
+        Xp, Sp, Vp = Xd.clone(), Sd.clone(), Vd.clone()
+        Xp.zero_(); Sp.zero_(); Vp.zero_()
+        Xp[:r] = torch.tensor(X.T, device=dev)
+        Sp[:r, :r] = torch.tensor(S, device=dev)
+        Vp[:r] = torch.tensor(V, device=dev)
+        stp = ctx.make_state(Xp, Sp, Vp, r, seed=1)
+        spp = blr.StepParams(dt, 0.2, 1e-10, r, r_cap,
+                             blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | blr.BLR_STEP_FP64_COLLISION)
+        ctx.dlr_step(pbp, stp, spp)
+        torch.cuda.synchronize()
+        pw = []
+        for _ in range(3):
+            ts = time.perf_counter()
+            ctx.dlr_step(pbp, stp, spp)
+            pw.append(time.perf_counter() - ts)
+        latency.update({"plain_fp64_step_ms_p50": round(1e3 * pct(pw, 0.50), 3),
+                        "plain_fp64_step_ms_max": round(1e3 * max(pw), 3),
+                        "plain_samples": len(pw),
+                        "plain_over_batched_p50": round(pct(pw, 0.5) / pct(step_wall, 0.5), 1)})
+
     # plain FP64 per-pair GPU path (the baseline schedule), on a few pairs
     plain = None
     if not args.no_plain:
@@ -237,7 +278,7 @@ def main():
                "seconds": round(t_cpu, 2)}
 
     line = {
-        "metric": "Q(V_i,V_j) evals/s at N_v=32^3",
+        "metric": "Q(V_i,V_j) evals/s at N_v=32^3 + p50/p99 solve latency, batched vs plain",
         "value": round(value, 2),
         "unit": "pair evals/s",
         "n_gpus": 1,
@@ -262,6 +303,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_fp64_pair_evals_per_s": round(plain, 2) if plain else None,
+        "latency": latency,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                     for t in sorted(timers, key=lambda t: -t["ms"])[:8]],
     }
