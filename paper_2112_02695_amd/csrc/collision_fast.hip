@@ -13,11 +13,13 @@
 //                  function at one radial node per workgroup iteration:
 //                  spectrum x (cos x - sin x) -> 3D inverse DFT -> two real
 //                  fields written coalesced (the only HBM-heavy output)
-//   k_reduce_all   sigma sums of all pair products for all radial nodes in
-//                  one launch (thread per grid point, pairs in registers)
-//   k_pair_spec    3D DFTs of one pair product at a group of radial nodes,
-//                  times the radial weights, summed in registers and written
-//                  as one half spectrum (k_2 <= N/2) per group
+//   k_reduce_diag  sigma sums of all pair products for all radial nodes in
+//   k_reduce_all   one launch (thread per grid point, pairs in registers;
+//                  the diagonal tile with the sphere pairs in the arguments)
+//   k_pair_spec    3D DFTs of one pair product at a group of radial nodes
+//                  (two nodes per complex transform), times the radial
+//                  weights, summed in registers and written as one half
+//                  spectrum (k_2 <= N/2) per group
 //   k_final_fused  sum over the groups, 3D inverse DFT from the half
 //                  spectrum, minus the loss, FP64 moment projection, store
 #include <cmath>
