@@ -17,6 +17,10 @@ step of a configuration on, as a replayed HIP graph).  A second, shorter pass
 of the same steps with the library's kernel events on gives the per-kernel
 times and the roofline of the dominant kernel.
 
+Full tensor: the reference step of the same discretisation on the full grid
+(Q(f(x_p), f(x_p)) for all 256 cells, FP32 collisions, and upwind transport),
+three timed steps, and its time over the low-rank step's.
+
 Latency: the wall time of each timed step (p50, p99) on the batched FP32
 path, and of three steps of the same workload on the plain FP64 per-pair
 schedule.  A steady solve is a sequence of such steps (one host wait each),
@@ -50,6 +54,8 @@ def parse():
     ap.add_argument("--mode", choices=["pairs", "step"], default="step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-full", action="store_true",
+                    help="skip the full-tensor reference step (N_x collisions per step)")
     ap.add_argument("--generic", action="store_true", help="force the multi-pass FFT path")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration)")
@@ -252,6 +258,24 @@ def main():
                         "plain_samples": len(pw),
                         "plain_over_batched_p50": round(pct(pw, 0.5) / pct(step_wall, 0.5), 1)})
 
+    # the full-tensor reference step on the same grid (Q(f(x_p), f(x_p)) for
+    # all N_x cells plus upwind transport), FP32 collisions as in the step
+    full = None
+    if args.mode == "step" and not args.no_full:
+        Ff = torch.tensor(ini["f0"], device=dev)
+        ctx.full_step(pb, Ff, dt, blr.BLR_FP32)
+        torch.cuda.synchronize()
+        tf = []
+        for _ in range(3):
+            ts = time.perf_counter()
+            e_full = ctx.full_step(pb, Ff, dt, blr.BLR_FP32)
+            tf.append(time.perf_counter() - ts)
+        full = {"step_ms_p50": round(1e3 * pct(tf, 0.5), 3), "samples": len(tf), "cells": nx,
+                "cell_collisions_per_s": round(nx / pct(tf, 0.5), 1),
+                "err_full_last": e_full,
+                "low_rank_step_speedup": round(pct(tf, 0.5) / pct(step_wall, 0.5), 2)}
+        del Ff
+
     # plain FP64 per-pair GPU path (the baseline schedule), on a few pairs
     plain = None
     if not args.no_plain:
@@ -304,6 +328,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64_pair_evals_per_s": round(plain, 2) if plain else None,
         "latency": latency,
+        "full_tensor": full,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                     for t in sorted(timers, key=lambda t: -t["ms"])[:8]],
     }

@@ -212,6 +212,26 @@ typedef struct {
 blr_status blr_steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state,
                             const blr_solve_params* p, blr_solve_info* info);
 
+/* --------------------------------------------------------- full tensor -- */
+
+/* One forward-Euler step of the full-tensor discretisation that the low-rank
+ * method is projected from (first-order upwind transport, eq. scheme:fullupwind
+ * of Sec. 2.2; walls of Sec. 2.3; the reference method of Sec. 5):
+ *   f_p <- f_p - dt (v1+ (f_p - f_{p-1}) + v1- (f_{p+1} - f_p)) / dx + dt Q_s(f_p, f_p)
+ * for every cell p, with the ghost f_{-1} = f_left where v1 > 0 and
+ * f_{nx} = f_right where v1 < 0.  Q_s is the pair operator of
+ * blr_collision_pairs (conservation projection unless pb->v.flags has
+ * BLR_NO_CONSERVE) in `prec`: FP32 runs the collisions on a float copy of the
+ * cells, FP64 in double; transport and the update are FP64.
+ *   F         device FP64, nx rows of n^d values (row p = cell p), caller-owned,
+ *             updated in place
+ *   err_full  host; ||f^{n+1} - f^n||_{L2(x,v)} (eq. err full grid), the
+ *             midpoint inner product dx dv^d sum
+ * Waits for the step (one host wait).  dt >= 0.  On error F is unchanged
+ * unless the error is reported by the device after the update was issued. */
+blr_status blr_full_step(blr_ctx ctx, const blr_problem* pb, blr_precision prec, double* F,
+                         double dt, double* err_full);
+
 /* ----------------------------------------------------------- timing -- */
 
 /* Per-kernel timing for measurement.  mode 1: from now on every kernel launch

@@ -298,6 +298,26 @@ def steady_solve(st: State, prob: Problem1D, dt: float, res_tol: float,
     return st, hist, False
 
 
+# ----------------------------------------------------------------------------
+# full-tensor reference step (eq. scheme:fullupwind, Sec. 2.2; walls of Sec. 2.3)
+# ----------------------------------------------------------------------------
+def full_step(F: np.ndarray, prob: Problem1D, dt: float):
+    """One forward-Euler step of the full-tensor discretisation the low-rank
+    equations are projected from: for every cell,
+    f_p <- f_p - dt (v^+ D_+ f + v^- D_- f)_p + dt Q_s(f_p, f_p), the left ghost
+    being the inflow Maxwellian where v1 > 0 (the adjacent cell elsewhere) and
+    the right ghost likewise where v1 < 0.  F is (nx, n).  Returns (F_new,
+    err_full) with err_full = ||F_new - F||_{L2(x,v)} (eq. err full grid)."""
+    v1 = prob.v1()
+    vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
+    left = np.where(v1 > 0, prob.fL, F[0])
+    right = np.where(v1 < 0, prob.fR, F[-1])
+    Q, _ = evaluate_pairs(F, [(p, p) for p in range(F.shape[0])], prob)
+    Fn = F - dt * (vp * d_plus(F, left, prob.dx) + vm * d_minus(F, right, prob.dx)) + dt * Q
+    err = math.sqrt(prob.dx * prob.dvd * float(((Fn - F) ** 2).sum()))
+    return Fn, err
+
+
 def macroscopic(st: State, prob: Problem1D):
     """rho, u_1, T per cell (gas constant 1): E = rho|u|^2/2 + d rho T / 2."""
     vs = prob.vs

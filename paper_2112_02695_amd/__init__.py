@@ -33,7 +33,8 @@ STATUS = {0: "BLR_OK", 1: "BLR_ERR_ARG", 2: "BLR_ERR_NOMEM", 3: "BLR_ERR_HIP",
           4: "BLR_ERR_UNSUPPORTED", 5: "BLR_ERR_NUMERIC", 6: "BLR_ERR_NOT_CONVERGED"}
 
 EXPORTS = ["blr_create", "blr_destroy", "blr_last_error", "blr_workspace_bytes",
-           "blr_collision_pairs", "blr_state_from_full", "blr_dlr_step", "blr_steady_solve"]
+           "blr_collision_pairs", "blr_state_from_full", "blr_dlr_step", "blr_steady_solve",
+           "blr_full_step"]
 
 
 class BlrError(RuntimeError):
@@ -107,6 +108,9 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(StepParams), ctypes.POINTER(StepInfo)]
         lib.blr_steady_solve.argtypes = [P, ctypes.POINTER(Problem), ctypes.POINTER(State),
                                          ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo)]
+    if hasattr(lib, "blr_full_step"):
+        lib.blr_full_step.argtypes = [P, ctypes.POINTER(Problem), ctypes.c_int, P, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
         if hasattr(lib, name):
             getattr(lib, name).restype = ctypes.c_int if name != "blr_last_error" else ctypes.c_char_p
@@ -215,6 +219,17 @@ class Context:
             return info
         self._check(rc)
         return info
+
+    # ------------------------------------------------------ full tensor --
+    def full_step(self, pb: Problem, F, dt: float, prec: int = BLR_FP32) -> float:
+        """One full-tensor step of F (float64 CUDA tensor, nx x n^d, updated
+        in place); returns err_full."""
+        assert F.dtype.itemsize == 8 and F.is_contiguous() and F.shape[0] == pb.nx
+        err = ctypes.c_double()
+        self._check(self.lib.blr_full_step(self.h, ctypes.byref(pb), prec,
+                                           ctypes.c_void_p(F.data_ptr()), float(dt),
+                                           ctypes.byref(err)))
+        return err.value
 
 
 def upper_pairs(r: int):

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libblr.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "tables.cpp", "collision.hip", "collision_fast.hip", "linalg.hip", "dlr.hip"]
+SOURCES = ["api.hip", "tables.cpp", "collision.hip", "collision_fast.hip", "linalg.hip", "dlr.hip",
+           "full.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,152 @@
+// Full-tensor reference step on the GPU: the discretisation the low-rank
+// method is projected from (first-order upwind in x, eq. scheme:fullupwind of
+// Sec. 2.2, forward Euler in time, walls of Sec. 2.3), with the collision
+// term Q(f(x_p,.), f(x_p,.)) of every cell evaluated by the pair pipeline
+// (the cells of a chunk are its basis, the pairs are (p, p)).  err_full is
+// eq. err full grid.
+//
+// F is row-major nx x n^d FP64 (row p = cell p); the update is written to a
+// second array and copied back once every cell's collision term is in, since
+// the transport of cell p reads cells p - 1 and p + 1.
+#include <cmath>
+#include <vector>
+
+#include "collision_common.hpp"
+
+namespace blr {
+namespace fk {
+
+constexpr int kChunk = 64;  // cells per collision call (the pair pipeline's basis limit)
+
+// F_new = F - dt (v1+ (F_p - F_{p-1}) + v1- (F_{p+1} - F_p)) / dx + dt Q_p for the
+// cells p0 .. p0 + gridDim.y - 1; the ghost F_{-1} is f_L where v1 > 0 and
+// F_{nx} is f_R where v1 < 0 (the outflow halves multiply a zero velocity
+// part).  Writes each block's sum of (F_new - F)^2 (wave sums, then the waves
+// in order) to part[p * gridDim.x + blockIdx.x].
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_full_update(const double* __restrict__ F, int nx, int n,
+                                                     int p0, const TQ* __restrict__ Q,
+                                                     const double* __restrict__ fL,
+                                                     const double* __restrict__ fR, double dt,
+                                                     double dx, double L, double dv, int plane,
+                                                     double* __restrict__ Fn,
+                                                     double* __restrict__ part) {
+  __shared__ double ws[4];
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  const int p = p0 + blockIdx.y;
+  double e2 = 0.0;
+  if (q < n) {
+    const double v1 = -L + (q / plane) * dv;
+    const double* fp = F + (long)p * n + q;
+    const double f = fp[0];
+    const double fm = p > 0 ? fp[-n] : (v1 > 0 ? fL[q] : f);
+    const double fn = p < nx - 1 ? fp[n] : (v1 < 0 ? fR[q] : f);
+    const double vp = v1 > 0 ? v1 : 0.0, vm = v1 < 0 ? v1 : 0.0;
+    const double d = -dt * (vp * (f - fm) + vm * (fn - f)) / dx +
+                     dt * (double)Q[(long)blockIdx.y * n + q];
+    Fn[(long)p * n + q] = f + d;
+    e2 = d * d;
+  }
+  for (int off = 32; off > 0; off >>= 1) e2 += __shfl_down(e2, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(long)p * gridDim.x + blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+// err = sqrt(w sum part) over cnt partials, one block, fixed order
+__global__ __launch_bounds__(256) void k_err_total(const double* __restrict__ part, long cnt,
+                                                   double w, double* __restrict__ err) {
+  __shared__ double ws[4];
+  double s = 0.0;
+  for (long i = threadIdx.x; i < cnt; i += 256) s += part[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) err[0] = std::sqrt(w * (((ws[0] + ws[1]) + ws[2]) + ws[3]));
+}
+
+__global__ void k_cast_f32(const double* __restrict__ in, long count, float* __restrict__ out) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < count) out[e] = (float)in[e];
+}
+
+}  // namespace fk
+
+static unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double dt,
+               double* err_out) {
+  require(pb != nullptr && F != nullptr && err_out != nullptr, "null argument");
+  require(pb->nx >= 1, "nx must be >= 1");
+  require(pb->x_hi > pb->x_lo, "x_hi must exceed x_lo");
+  require(pb->f_left && pb->f_right, "null inflow function");
+  require(prec == BLR_FP32 || prec == BLR_FP64, "bad precision");
+  require(std::isfinite(dt) && dt >= 0.0, "dt must be finite and >= 0");
+  const DevTables& tb = get_tables(ctx, pb->v, prec);
+  const HostTables& h = tb.h;
+  hipStream_t s = ctx->stream;
+  const int nx = pb->nx, n = h.n;
+  const double dx = (pb->x_hi - pb->x_lo) / nx, dvd = std::pow(h.dv, h.d);
+  const int plane = h.d == 3 ? h.N * h.N : h.N;
+  const int esz = prec == BLR_FP32 ? 4 : 8;
+  const int chunk = std::min(nx, fk::kChunk);
+  double* Fn = (double*)ctx->buf("full.Fn", (size_t)nx * n * sizeof(double));
+  void* Q = ctx->buf("full.Q", (size_t)chunk * n * esz);
+  float* F32 = prec == BLR_FP32 ? (float*)ctx->buf("full.F32", (size_t)chunk * n * sizeof(float))
+                                : nullptr;
+  const unsigned nbx = nblocks(n, 256);
+  double* part = (double*)ctx->buf("full.part", (size_t)nx * nbx * sizeof(double));
+  double* err = (double*)ctx->buf("full.err", sizeof(double));
+  std::vector<int32_t> pairs(2 * chunk);
+  for (int p0 = 0; p0 < nx; p0 += chunk) {
+    const int np = std::min(chunk, nx - p0);
+    for (int i = 0; i < np; ++i) pairs[2 * i] = pairs[2 * i + 1] = i;
+    const double* rows = F + (long)p0 * n;
+    if (prec == BLR_FP32) {
+      hipLaunchKernelGGL(fk::k_cast_f32, dim3(nblocks((long)np * n, 256)), dim3(256), 0, s, rows,
+                         (long)np * n, F32);
+      BLR_CHECK_LAUNCH();
+      collision_pairs(ctx, pb->v, BLR_FP32, F32, np, pairs.data(), np, Q);
+    } else {
+      collision_pairs(ctx, pb->v, BLR_FP64, rows, np, pairs.data(), np, Q);
+    }
+    timed_begin("full.update", (double)np * n * 8.0 * (3.0 + 1.0) + (double)np * n * esz, s);
+    if (prec == BLR_FP32)
+      hipLaunchKernelGGL(fk::k_full_update<float>, dim3(nbx, np), dim3(256), 0, s, F, nx, n, p0,
+                         (const float*)Q, pb->f_left, pb->f_right, dt, dx, h.L, h.dv, plane, Fn,
+                         part);
+    else
+      hipLaunchKernelGGL(fk::k_full_update<double>, dim3(nbx, np), dim3(256), 0, s, F, nx, n, p0,
+                         (const double*)Q, pb->f_left, pb->f_right, dt, dx, h.L, h.dv, plane, Fn,
+                         part);
+    BLR_CHECK_LAUNCH();
+    timed_end(s);
+  }
+  hipLaunchKernelGGL(fk::k_err_total, dim3(1), dim3(256), 0, s, part, (long)nx * nbx, dx * dvd, err);
+  BLR_CHECK_LAUNCH();
+  BLR_HIP(hipMemcpyAsync(F, Fn, (size_t)nx * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double* hb = (double*)ctx->host_readback(sizeof(double));
+  BLR_HIP(hipMemcpyAsync(hb, err, sizeof(double), hipMemcpyDeviceToHost, s));
+  BLR_HIP(hipStreamSynchronize(s));
+  *err_out = hb[0];
+}
+
+}  // namespace blr
+
+// ------------------------------------------------------------------ C ABI --
+extern "C" blr_status blr_full_step(blr_ctx ctx, const blr_problem* pb, blr_precision prec,
+                                    double* F, double dt, double* err_full) {
+  if (!ctx) return BLR_ERR_ARG;
+  ctx->err.clear();
+  try {
+    BLR_HIP(hipSetDevice(ctx->device));
+    blr::full_step(ctx, pb, prec, F, dt, err_full);
+    return BLR_OK;
+  } catch (const blr::Error& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return BLR_ERR_HIP;
+  }
+}

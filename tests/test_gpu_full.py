@@ -1,0 +1,103 @@
+"""GPU parity of blr_full_step (the full-tensor reference step, eq.
+scheme:fullupwind of Sec. 2.2, walls of Sec. 2.3, err_full of eq. err full
+grid) against the oracle's full_step, on seeded shock-like inputs.
+
+Error measure: ||dF_gpu - dF_ref|| / ||dF_ref|| for the update dF = F_new - F,
+bounded by 1e-12 with FP64 collisions.  With FP32 collisions the bound is the
+pair operator's: ||dF_gpu - dF_ref|| / (dt ||Q+_ref||) <= 1e-5, Q+ the gain
+part of every cell's Q_s(f_p, f_p) (transport is FP64 on both sides; near
+equilibrium Q_s is a small difference of large gain and loss terms).
+err_full to 1e-12 / 1e-5 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import collision as oc
+from oracle import dlr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2112_02695_amd as blr  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = blr.Context(0)
+    yield c
+    c.close()
+
+
+def _spec(d, n, m_rho):
+    if d == 2:
+        return synth.VGridSpec(d=2, n=n, L=8.0, gamma=0.0, C=1 / (2 * math.pi), m_rho=m_rho,
+                               m_sigma=8)
+    return synth.VGridSpec(d=3, n=n, L=8.0, gamma=1.0, C=1.0, m_rho=m_rho, m_sigma=38)
+
+
+def _case(ctx, d, n, m_rho, nx, prec, dt=0.01, conserve=True, seed=5):
+    spec = _spec(d, n, m_rho)
+    vs = oc.setup_from_spec(spec)
+    ini = synth.shock_initial(1.5, spec, nx, -30.0, 30.0, pert=1e-2, pert_rank=3, seed=seed)
+    F = ini["f0"]
+    prob = dlr.Problem1D(vs=vs, nx=nx, x_lo=-30.0, x_hi=30.0, fL=ini["fL"], fR=ini["fR"],
+                         conserve=conserve)
+    Fref, eref = dlr.full_step(F, prob, dt)
+    flags = 0 if conserve else blr.BLR_NO_CONSERVE
+    vg = blr.vgrid_from_spec(spec, flags)
+    fL = torch.tensor(ini["fL"], device="cuda")
+    fR = torch.tensor(ini["fR"], device="cuda")
+    pb = ctx.make_problem(vg, nx, -30.0, 30.0, fL, fR)
+    Fd = torch.tensor(F, device="cuda")
+    e = ctx.full_step(pb, Fd, dt, prec)
+    torch.cuda.synchronize()
+    Fg = Fd.cpu().numpy()
+    diff = np.linalg.norm((Fg - F) - (Fref - F))
+    rel = diff / np.linalg.norm(Fref - F)
+    if prec == blr.BLR_FP32:
+        _, gain = oc.q_pairs(F, [(p, p) for p in range(nx)], vs, conserve=conserve)
+        rel = diff / (dt * np.linalg.norm(gain))
+    return rel, e, eref
+
+
+@pytest.mark.parametrize("d,n,m_rho,nx", [(3, 8, 8, 5), (2, 16, 8, 7), (2, 32, 4, 1)])
+def test_full_step_fp64_matches_oracle(ctx, d, n, m_rho, nx):
+    print(f"full step fp64 d={d} n={n} nx={nx}", flush=True)
+    rel, e, eref = _case(ctx, d, n, m_rho, nx, blr.BLR_FP64)
+    print("rel", rel, "err", e, eref, flush=True)
+    assert rel < 1e-12
+    assert abs(e - eref) < 1e-12 * eref
+
+
+def test_full_step_fp32_two_chunks_matches_oracle(ctx):
+    """66 cells: two collision calls (64 + 2) on the fused FP32 kernels."""
+    print("full step fp32 3d n=16 nx=66", flush=True)
+    rel, e, eref = _case(ctx, 3, 16, 4, 66, blr.BLR_FP32)
+    print("rel", rel, "err", e, eref, flush=True)
+    assert rel < 1e-5
+    assert abs(e - eref) < 1e-5 * eref
+
+
+def test_full_step_without_projection(ctx):
+    rel, e, eref = _case(ctx, 2, 16, 8, 4, blr.BLR_FP64, conserve=False)
+    assert rel < 1e-12
+
+
+def test_full_step_rejects_bad_arguments(ctx):
+    spec = _spec(2, 16, 4)
+    vg = blr.vgrid_from_spec(spec)
+    fL = torch.zeros(256, dtype=torch.float64, device="cuda")
+    pb = ctx.make_problem(vg, 3, 0.0, 1.0, fL, fL)
+    F = torch.zeros((3, 256), dtype=torch.float64, device="cuda")
+    with pytest.raises(blr.BlrError) as ei:
+        ctx.full_step(pb, F, -1.0, blr.BLR_FP64)
+    assert ei.value.code == 1
+    before = F.clone()
+    e = ctx.full_step(pb, F, 0.0, blr.BLR_FP64)   # dt = 0: nothing moves
+    assert e == 0.0 and torch.equal(F, before)
