@@ -605,6 +605,87 @@ __global__ __launch_bounds__(1024) void k_cqr_chol(const double* __restrict__ pa
   }
 }
 
+
+// The whole shifted Cholesky QR3 of a short matrix (rows <= 256 RPT) in one
+// workgroup: thread t keeps rows t + 256 k (k < RPT) of in_scale A in
+// registers; each of the three passes forms the Gram matrix on the FP64
+// matrix cores (as in k_cqr_apply, one 256-row tile at a time, the four
+// waves' sums added in order), factors it with chol_wave (shifted on the
+// first pass) and replaces every row a by q with q R = a.  Afterwards
+// R = R_2 R_1 R_0 and Q = out_scale q.
+template <int RM, int RPT>
+__global__ __launch_bounds__(256) void k_cqr_small(const double* A, long lda, long rows, int r,
+                                                   double in_scale, double out_scale,
+                                                   double shift_coef, double* Q, long ldq,
+                                                   double* __restrict__ Rout, int* flag) {
+  __shared__ double tile[256][17];
+  __shared__ double G[256];
+  __shared__ double Rs[3][256];
+  __shared__ double di[16];
+  __shared__ double red[4][256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double a[RPT][RM];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const long row = t + 256L * k;
+#pragma unroll
+    for (int c = 0; c < RM; ++c) a[k][c] = (row < rows && c < r) ? in_scale * A[c * lda + row] : 0.0;
+  }
+  for (int pass = 0; pass < 3; ++pass) {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) tile[t][c] = c < RM ? a[k][c] : 0.0;
+      __syncthreads();
+#pragma unroll
+      for (int gi = 0; gi < 16; ++gi) {
+        const double x = tile[64 * wv + 4 * gi + (lane >> 4)][lane & 15];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv][(4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc[v];
+    if (t < 16) di[t] = 0.0;
+    __syncthreads();
+    G[t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    __syncthreads();
+    if (wv == 0)
+      chol_wave(G, Rs[pass], r, pass == 0 ? shift_coef : 0.0, pass == 0 ? 0.0 : 1e-12, nullptr, di,
+                flag);
+    __syncthreads();
+    // q R = a, forward substitution with 1 / diag(R)
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+#pragma unroll
+      for (int jj = 0; jj < RM; ++jj) {
+        double v = a[k][jj];
+#pragma unroll
+        for (int c = 0; c < jj; ++c) v -= a[k][c] * Rs[pass][c * 16 + jj];
+        a[k][jj] = v * di[jj];
+      }
+    }
+  }
+  if (t < r * r) {
+    const int i = t / r, j = t % r;
+    double v = 0.0;
+    for (int k = i; k <= j; ++k) {
+      double w = 0.0;
+      for (int l = k; l <= j; ++l) w += Rs[1][k * 16 + l] * Rs[0][l * 16 + j];
+      v += Rs[2][i * 16 + k] * w;
+    }
+    Rout[i * r + j] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const long row = t + 256L * k;
+    if (row < rows)
+#pragma unroll
+      for (int c = 0; c < RM; ++c)
+        if (c < r) Q[c * ldq + row] = out_scale * a[k][c];
+  }
+}
 }  // namespace la
 
 // ------------------------------------------------------------------- host --
@@ -707,6 +788,27 @@ void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q,
   require(rows >= r, "cholqr: rows must be >= r");
   require(Q && R_rowmajor && flag, "cholqr: null output");
   hipStream_t s = ctx->stream;
+  // shift of the first pass: 11 (rows r + r (r + 1)) u ||A||_F^2 (shifted CholeskyQR3)
+  const double u53 = std::ldexp(1.0, -53);
+  const double shift0 = 11.0 * ((double)rows * r + (double)r * (r + 1)) * u53;
+  if (rows <= 512) {
+    // short matrices: all three passes in one workgroup
+    auto small = [&](auto rm) {
+      constexpr int RM = decltype(rm)::value;
+      if (rows <= 256)
+        hipLaunchKernelGGL((la::k_cqr_small<RM, 1>), dim3(1), dim3(256), 0, s, A, lda, rows, r,
+                           in_scale, out_scale, shift0, Q, ldq, R_rowmajor, flag);
+      else
+        hipLaunchKernelGGL((la::k_cqr_small<RM, 2>), dim3(1), dim3(256), 0, s, A, lda, rows, r,
+                           in_scale, out_scale, shift0, Q, ldq, R_rowmajor, flag);
+      BLR_CHECK_LAUNCH();
+    };
+    if (r <= 4) small(std::integral_constant<int, 4>{});
+    else if (r <= 8) small(std::integral_constant<int, 8>{});
+    else if (r <= 12) small(std::integral_constant<int, 12>{});
+    else small(std::integral_constant<int, 16>{});
+    return;
+  }
   const int nblk = (int)std::max<long>(1, std::min<long>(128, (rows + 255) / 256));
   double* part = (double*)ctx->buf(tag + ".part", (size_t)nblk * 256 * sizeof(double));
   double* Rk = (double*)ctx->buf(tag + ".rk", (size_t)3 * r * r * sizeof(double));

@@ -164,10 +164,13 @@ def test_add_projection_matches_householder(ctx, d, N, nx, r, m_rho):
         assert abs(a[2] - b[2]) < 1e-10 * b[2] and abs(a[3] - b[3]) < 1e-10 * b[3]
 
 
-@pytest.mark.parametrize("d,N,nx,r,m_rho", [(3, 16, 40, 5, 2), (2, 16, 300, 4, 4)])
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(3, 16, 40, 5, 2), (2, 16, 300, 4, 4),
+                                            (2, 16, 600, 4, 4)])
 def test_cholesky_qr_matches_householder(ctx, d, N, nx, r, m_rho):
     """K- and L-step QRs by shifted Cholesky QR (default) and by Householder
-    QR give the same adaptive steps; nx = 300 spans several Gram blocks."""
+    QR give the same adaptive steps.  Up to 512 rows the three passes run in
+    one workgroup (nx = 40: one row per thread, 300: two); nx = 600 and the
+    4096-row V side take the multi-block passes."""
     spec, prob, st, _ = _setup(d, N, nx, r, m_rho)
     out = []
     for extra in (0, blr.BLR_STEP_HOUSEHOLDER_QR):
