@@ -57,6 +57,15 @@ def parse():
     ap.add_argument("--no-full", action="store_true",
                     help="skip the full-tensor reference step (N_x collisions per step)")
     ap.add_argument("--generic", action="store_true", help="force the multi-pass FFT path")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving traces")
+    ap.add_argument("--serve-count", type=int, default=8,
+                    help="requests of the trace both paths run")
+    ap.add_argument("--serve-steps", type=int, default=10,
+                    help="step cap per solve in the trace both paths run")
+    ap.add_argument("--serve-long-count", type=int, default=16,
+                    help="requests of the longer trace (batched path only; 0 skips it)")
+    ap.add_argument("--serve-long-steps", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -76,6 +85,137 @@ def read_timers(ctx):
                               ctypes.byref(by)) == 0:
         out.append(dict(name=buf.value.decode(), ms=ms.value, launches=nl.value, bytes=by.value))
         i += 1
+    return out
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(math.ceil(q * len(xs))) - 1)]
+
+
+def prepare_trace(trace, synth):
+    """Initial low-rank factors of each request of a serving trace (host,
+    before any clock): shock data of the request's Mach number, truncated to
+    its initial rank."""
+    out = []
+    for q in trace:
+        spec = synth.VGridSpec(d=3, n=q["n"], L=q["L"], gamma=1.0, C=1.0, m_rho=16, m_sigma=38)
+        ini = synth.shock_initial(q["mach"], spec, q["nx"], q["x_lo"], q["x_hi"], pert=1e-3,
+                                  pert_rank=10, seed=100 + q["index"])
+        dx = (q["x_hi"] - q["x_lo"]) / q["nx"]
+        dvd = (2.0 * q["L"] / q["n"]) ** 3
+        X, S, V = synth.lowrank_state_sketch(ini["f0"], q["r0"], dx, dvd, seed=q["index"])
+        out.append(dict(q=q, spec=spec, X=X, S=S, V=V, fL=ini["fL"], fR=ini["fR"]))
+    return out
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol=1e-6):
+    """Serve the requests at their arrival times; latency = completion time -
+    arrival (submit) time on the server's clock."""
+    dev = torch.device("cuda:0")
+
+    def device_request(p):
+        q = p["q"]
+        r = q["r0"]
+        X = torch.zeros((r_cap, q["nx"]), dtype=torch.float64, device=dev)
+        S = torch.zeros((r_cap, r_cap), dtype=torch.float64, device=dev)
+        V = torch.zeros((r_cap, p["V"].shape[1]), dtype=torch.float64, device=dev)
+        X[:r] = torch.tensor(p["X"].T, device=dev)
+        S[:r, :r] = torch.tensor(p["S"], device=dev)
+        V[:r] = torch.tensor(p["V"], device=dev)
+        fL = torch.tensor(p["fL"], device=dev)
+        fR = torch.tensor(p["fR"], device=dev)
+        vg = blr.vgrid_from_spec(p["spec"], blr.BLR_PLAIN_SCHEDULE if plain else 0)
+        pb = helper.make_problem(vg, q["nx"], q["x_lo"], q["x_hi"], fL, fR)
+        st = helper.make_state(X, S, V, r)
+        return pb, st
+
+    def params(q, steps):
+        flags = blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | (blr.BLR_STEP_FP64_COLLISION if plain else 0)
+        return blr.SolveParams(blr.StepParams(q["dt"], 0.2, 1e-10, 1, r_cap, flags), res_tol, steps)
+
+    progress(f"serving trace: {len(prepared)} requests, {slots} slot(s), "
+             f"{'plain fp64' if plain else 'batched fp32'}, cap {cap} steps")
+    sv = blr.Server(0, slots=slots)
+    try:
+        # warm-up (untimed): every slot runs two steps of the largest-rank
+        # request of each velocity grid (allocations, tables, recorded graphs)
+        tag = -1
+        for nv in sorted({p["q"]["n"] for p in prepared}):
+            big = max((p for p in prepared if p["q"]["n"] == nv), key=lambda p: p["q"]["r0"])
+            for _ in range(slots):
+                pb, st = device_request(big)
+                torch.cuda.synchronize()
+                sv.submit(pb, st, params(big["q"], 2), tag)
+                tag -= 1
+            got = 0
+            while got < slots:
+                got += len(sv.wait(timeout=300.0))
+        reqs = [device_request(p) for p in prepared]
+        torch.cuda.synchronize()
+        comps = []
+        t0 = time.perf_counter()
+        i = 0
+        while len(comps) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and prepared[i]["q"]["arrival"] <= now:
+                sv.submit(reqs[i][0], reqs[i][1], params(prepared[i]["q"], cap), i)
+                i += 1
+            if i < len(reqs):
+                wait = max(0.0, prepared[i]["q"]["arrival"] - (time.perf_counter() - t0))
+                if sv.load() == (0, 0):
+                    time.sleep(wait)   # nothing live: idle until the next arrival
+                else:
+                    comps += sv.wait(timeout=wait)
+            else:
+                got = sv.wait(timeout=600.0)
+                if not got:
+                    raise RuntimeError("serving trace made no progress")
+                comps += got
+        wall = time.perf_counter() - t0
+    finally:
+        sv.close()
+    lat = [c.t_done - c.t_submit for c in comps]
+    ok = [c for c in comps if c.status in (blr.BLR_OK, blr.BLR_ERR_NOT_CONVERGED)]
+    return {"slots": slots, "requests": len(comps), "step_cap": cap,
+            "latency_s_p50": round(pct(lat, 0.50), 4), "latency_s_p99": round(pct(lat, 0.99), 4),
+            "queue_wait_s_p50": round(pct([c.t_admit - c.t_submit for c in comps], 0.5), 4),
+            "wall_s": round(wall, 3), "solves_per_s": round(len(comps) / wall, 3),
+            "steps": int(sum(c.info.steps for c in comps)),
+            "pair_evals": int(sum(c.info.pair_evals for c in comps)),
+            "pair_evals_per_s": round(sum(c.info.pair_evals for c in comps) / wall, 1),
+            "converged": sum(1 for c in comps if c.status == blr.BLR_OK),
+            "failed": len(comps) - len(ok),
+            "final_rank_range": [min(c.info.r for c in ok), max(c.info.r for c in ok)] if ok else None}
+
+
+def serving_leg(args, blr, synth, torch, helper):
+    """The serving trace on the batched FP32 path (slots solves at once) and on
+    the plain FP64 per-pair path (one solve at a time, first in first out),
+    then a longer trace on the batched path."""
+    base = dict(count=args.serve_count, seed=5, rate=4.0)
+    trace = synth.serving_trace(**base)
+    prepared = prepare_trace(trace, synth)
+    batched = run_trace(blr, torch, helper, prepared, args.serve_slots, False, args.serve_steps)
+    plain = run_trace(blr, torch, helper, prepared, 1, True, args.serve_steps)
+    out = {"trace": (f"{args.serve_count} steady normal-shock solves, seed 5, Poisson arrivals 4/s, "
+                     "Mach~U[1.2,3], N_x in {128,256,512}, N_v in {24^3 (L=8), 32^3 (L=10)}, "
+                     "initial rank U{5..25}, r_max 30, hard spheres M_rho=16 x M_sigma=38, "
+                     f"each to err_ada<=1e-6 or {args.serve_steps} steps"),
+           "batched_fp32": batched, "plain_fp64_fifo": plain,
+           "plain_over_batched_latency_p50": round(plain["latency_s_p50"] /
+                                                   batched["latency_s_p50"], 1)}
+    if args.serve_long_count > 0:
+        long_trace = synth.serving_trace(count=args.serve_long_count, seed=5, rate=4.0)
+        lp = prepare_trace(long_trace, synth)
+        out["long_trace"] = f"the first {args.serve_long_count} requests of the same recipe, " \
+                            f"each to err_ada<=1e-6 or {args.serve_long_steps} steps"
+        out["long_batched_fp32"] = run_trace(blr, torch, helper, lp, args.serve_slots, False,
+                                             args.serve_long_steps)
     return out
 
 
@@ -147,6 +287,7 @@ def main():
             infos.append((info.r_in, info.r_added, info.r_out, info.err, info.err_ada,
                           info.ms_collision, info.ms_step))
 
+    progress(f"{args.mode}: {args.warmup} warm-up + {args.steps} timed steps")
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -226,16 +367,13 @@ def main():
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "share_of_step": round(dom["ms"] / (ktime * 1e3), 3)}
 
-    def pct(xs, q):
-        xs = sorted(xs)
-        return xs[min(len(xs) - 1, int(math.ceil(q * len(xs))) - 1)]
-
     latency = {"batched_step_ms_p50": round(1e3 * pct(step_wall, 0.50), 4),
                "batched_step_ms_p99": round(1e3 * pct(step_wall, 0.99), 4),
                "batched_samples": len(step_wall)}
     # the same step on the plain FP64 per-pair schedule (fresh copy of the
     # initial factors; one untimed step first)
     if args.mode == "step" and not args.no_plain:
+        progress("plain fp64 per-pair steps")
         vgp = blr.vgrid_from_spec(spec, blr.BLR_PLAIN_SCHEDULE)
         pbp = ctx.make_problem(vgp, nx, -30.0, 30.0, fL, fR)
         Xp, Sp, Vp = Xd.clone(), Sd.clone(), Vd.clone()
@@ -262,6 +400,7 @@ def main():
     # all N_x cells plus upwind transport), FP32 collisions as in the step
     full = None
     if args.mode == "step" and not args.no_full:
+        progress("full-tensor steps")
         Ff = torch.tensor(ini["f0"], device=dev)
         ctx.full_step(pb, Ff, dt, blr.BLR_FP32)
         torch.cuda.synchronize()
@@ -289,8 +428,13 @@ def main():
         torch.cuda.synchronize()
         plain = len(sub) / (time.perf_counter() - tp)
 
+    serving = None
+    if args.mode == "step" and not args.no_serve:
+        serving = serving_leg(args, blr, synth, torch, ctx)
+
     cpu = None
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         from oracle import collision as oc
         vs = oc.setup_from_spec(spec)
         tc = time.perf_counter()
@@ -329,6 +473,7 @@ def main():
         "plain_fp64_pair_evals_per_s": round(plain, 2) if plain else None,
         "latency": latency,
         "full_tensor": full,
+        "serving": serving,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                     for t in sorted(timers, key=lambda t: -t["ms"])[:8]],
     }

@@ -205,6 +205,10 @@ typedef struct {
   double err_ada;
   int32_t r, converged;
   double ms_wall;
+  int64_t pair_evals;   /* Q_s(V_i, V_j) evaluations over the steps taken: each
+                           step evaluates r(r+1)/2 pairs at its rank after the
+                           basis augmentation (a step attempt that is redone
+                           counts once) */
 } blr_solve_info;
 
 /* Repeated blr_dlr_step until err_ada <= res_tol (Sec. 5.1) or max_steps
@@ -231,6 +235,80 @@ blr_status blr_steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state
  * unless the error is reported by the device after the update was issued. */
 blr_status blr_full_step(blr_ctx ctx, const blr_problem* pb, blr_precision prec, double* F,
                          double dt, double* err_full);
+
+/* ------------------------------------------------------------ serving -- */
+
+/* A server runs many steady solves (blr_steady_solve, Sec. 5.1: the method's
+ * target is the steady state of each problem) on one device at once.  It owns
+ * `slots` contexts, each with its own HIP stream (default priority) and host
+ * thread, so the steps of different solves overlap on the device.  Requests
+ * are admitted first in, first out, as soon as a slot is free and the device
+ * memory held by the live solves plus the new one's estimate fits in
+ * hbm_budget (continuous batching: a request that arrives while others run
+ * starts when one of them ends, not when all have).  An idle slot's
+ * workspace is released when the budget needs the room.  Each solve runs the
+ * same kernels in the same order as blr_steady_solve on a fresh context, so
+ * its result does not depend on what else is running. */
+typedef struct blr_server_t* blr_server;
+
+typedef struct {
+  int32_t slots;        /* solves on the device at once, 1..16 */
+  int64_t hbm_budget;   /* bytes of device workspace the slots may hold;
+                           <= 0: no limit */
+} blr_server_params;
+
+typedef struct {
+  blr_problem problem;      /* copied at submit; f_left, f_right stay
+                               caller-owned and unchanged until completion */
+  blr_state* state;         /* caller-owned (struct and arrays); updated in
+                               place; neither read nor written by the caller
+                               until this request's completion is returned */
+  blr_solve_params solve;
+  int64_t tag;              /* caller's identifier, returned in the completion */
+} blr_request;
+
+typedef struct {
+  int64_t tag;
+  int32_t status;           /* blr_status of the solve: BLR_OK (converged),
+                               BLR_ERR_NOT_CONVERGED (max_steps reached), or
+                               the error that stopped it (state as after the
+                               last successful step) */
+  int32_t slot;             /* slot that ran it */
+  blr_solve_info info;
+  double t_submit, t_admit, t_done;  /* seconds since blr_server_create */
+  int64_t bytes;            /* device workspace its slot held at the end */
+  char message[128];        /* error text when status is not OK/NOT_CONVERGED */
+} blr_completion;
+
+/* Start a server on `device`.  Creates the slot threads and streams. */
+blr_status blr_server_create(int device, const blr_server_params* params, blr_server* out);
+
+/* Queue one request (returns at once).  BLR_ERR_ARG for a malformed request
+ * (null state, r or r_cap out of range, bad grid); BLR_ERR_NOMEM when its
+ * estimate alone exceeds hbm_budget.  Other errors arrive in the completion. */
+blr_status blr_server_submit(blr_server sv, const blr_request* req);
+
+/* Completions in the order they finished: waits until at least one is
+ * available, or timeout_s seconds (< 0: no limit) have passed, or no request
+ * is queued or running; then copies up to max_out of them into out (host)
+ * and sets *n_out. */
+blr_status blr_server_wait(blr_server sv, int32_t max_out, double timeout_s,
+                           blr_completion* out, int32_t* n_out);
+
+/* Requests queued (not yet admitted) and running. */
+blr_status blr_server_load(blr_server sv, int64_t* queued, int64_t* running);
+
+/* Seconds since blr_server_create on the server's clock (the clock of the
+ * completion times). */
+blr_status blr_server_clock(blr_server sv, double* t);
+
+/* Message of the last failed blr_server_submit (valid until the next one). */
+const char* blr_server_last_error(blr_server sv);
+
+/* Stop: queued requests are dropped (their states untouched, no completion),
+ * running solves end at their next step boundary, threads are joined and the
+ * slot contexts freed. */
+blr_status blr_server_destroy(blr_server sv);
 
 /* ----------------------------------------------------------- timing -- */
 

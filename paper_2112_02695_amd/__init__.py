@@ -29,12 +29,15 @@ BLR_STEP_HOUSEHOLDER_ADD = 0x8
 BLR_STEP_HOUSEHOLDER_QR = 0x10
 BLR_STEP_EAGER = 0x20
 
+(BLR_OK, BLR_ERR_ARG, BLR_ERR_NOMEM, BLR_ERR_HIP, BLR_ERR_UNSUPPORTED, BLR_ERR_NUMERIC,
+ BLR_ERR_NOT_CONVERGED) = range(7)
 STATUS = {0: "BLR_OK", 1: "BLR_ERR_ARG", 2: "BLR_ERR_NOMEM", 3: "BLR_ERR_HIP",
           4: "BLR_ERR_UNSUPPORTED", 5: "BLR_ERR_NUMERIC", 6: "BLR_ERR_NOT_CONVERGED"}
 
 EXPORTS = ["blr_create", "blr_destroy", "blr_last_error", "blr_workspace_bytes",
            "blr_collision_pairs", "blr_state_from_full", "blr_dlr_step", "blr_steady_solve",
-           "blr_full_step"]
+           "blr_full_step", "blr_server_create", "blr_server_submit", "blr_server_wait",
+           "blr_server_load", "blr_server_clock", "blr_server_last_error", "blr_server_destroy"]
 
 
 class BlrError(RuntimeError):
@@ -77,7 +80,24 @@ class SolveParams(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("err_ada", ctypes.c_double), ("r", ctypes.c_int32),
-                ("converged", ctypes.c_int32), ("ms_wall", ctypes.c_double)]
+                ("converged", ctypes.c_int32), ("ms_wall", ctypes.c_double),
+                ("pair_evals", ctypes.c_int64)]
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("hbm_budget", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("problem", Problem), ("state", ctypes.POINTER(State)), ("solve", SolveParams),
+                ("tag", ctypes.c_int64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("info", SolveInfo), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("bytes", ctypes.c_int64),
+                ("message", ctypes.c_char * 128)]
 
 
 _LIB = None
@@ -111,9 +131,21 @@ def load_library(path: str = LIB_PATH):
     if hasattr(lib, "blr_full_step"):
         lib.blr_full_step.argtypes = [P, ctypes.POINTER(Problem), ctypes.c_int, P, ctypes.c_double,
                                       ctypes.POINTER(ctypes.c_double)]
+    if hasattr(lib, "blr_server_create"):
+        lib.blr_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(ServerParams),
+                                          ctypes.POINTER(P)]
+        lib.blr_server_submit.argtypes = [P, ctypes.POINTER(Request)]
+        lib.blr_server_wait.argtypes = [P, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.POINTER(Completion), ctypes.POINTER(ctypes.c_int32)]
+        lib.blr_server_load.argtypes = [P, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]
+        lib.blr_server_clock.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+        lib.blr_server_last_error.argtypes = [P]
+        lib.blr_server_destroy.argtypes = [P]
     for name in EXPORTS:
         if hasattr(lib, name):
-            getattr(lib, name).restype = ctypes.c_int if name != "blr_last_error" else ctypes.c_char_p
+            getattr(lib, name).restype = (ctypes.c_char_p if name.endswith("last_error")
+                                          else ctypes.c_int)
     _LIB = lib
     return lib
 
@@ -230,6 +262,71 @@ class Context:
                                            ctypes.c_void_p(F.data_ptr()), float(dt),
                                            ctypes.byref(err)))
         return err.value
+
+
+class Server:
+    """Steady solves served on one device (``blr_server_*``): ``slots`` solves
+    at once, each on its own context, stream and host thread, admitted first
+    in, first out as slots and the device-memory budget allow.
+
+    ``submit`` keeps the problem, the state and their tensors alive until the
+    request's completion has been returned by ``wait``."""
+
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        rc = self.lib.blr_server_create(device, ctypes.byref(ServerParams(slots, hbm_budget)),
+                                        ctypes.byref(h))
+        if rc != 0:
+            raise BlrError(rc, "blr_server_create failed")
+        self.h = h
+        self._live = {}
+
+    def submit(self, pb: Problem, st: State, sp: SolveParams, tag: int):
+        if tag in self._live:
+            raise ValueError(f"tag {tag} is already in flight")
+        req = Request(pb, ctypes.pointer(st), sp, tag)
+        rc = self.lib.blr_server_submit(self.h, ctypes.byref(req))
+        if rc != 0:
+            msg = self.lib.blr_server_last_error(self.h)
+            raise BlrError(rc, msg.decode() if msg else "")
+        self._live[tag] = (pb, st, req)
+
+    def wait(self, max_out: int = 64, timeout: float | None = None):
+        """Completions finished since the last call (at least one unless the
+        timeout passed or nothing is queued or running)."""
+        buf = (Completion * max(1, max_out))()
+        n = ctypes.c_int32()
+        rc = self.lib.blr_server_wait(self.h, max_out, -1.0 if timeout is None else float(timeout),
+                                      buf, ctypes.byref(n))
+        if rc != 0:
+            raise BlrError(rc, "blr_server_wait failed")
+        out = [buf[i] for i in range(n.value)]
+        for c in out:
+            self._live.pop(c.tag, None)
+        return out
+
+    def load(self):
+        q, r = ctypes.c_int64(), ctypes.c_int64()
+        self.lib.blr_server_load(self.h, ctypes.byref(q), ctypes.byref(r))
+        return q.value, r.value
+
+    def clock(self) -> float:
+        t = ctypes.c_double()
+        self.lib.blr_server_clock(self.h, ctypes.byref(t))
+        return t.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.blr_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def upper_pairs(r: int):

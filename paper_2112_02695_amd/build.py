@@ -12,7 +12,7 @@ OUT = os.path.join(HERE, "libblr.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "tables.cpp", "collision.hip", "collision_fast.hip", "linalg.hip", "dlr.hip",
-           "full.hip"]
+           "full.hip", "serve.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

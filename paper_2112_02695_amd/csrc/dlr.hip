@@ -12,6 +12,7 @@
 // S row-major.  All reductions have a fixed order (no atomics), so a step is
 // bitwise reproducible.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 
@@ -1473,6 +1474,21 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     if (e == hipSuccess) {
       try {
         step_enqueue(ctx, pb, st, sp, h, add, at, o, false);
+      } catch (const Error&) {
+        // A device-wide operation of another host thread (a device
+        // synchronisation, a free) invalidates the recording; the step then
+        // runs directly.  Any other error is the step's own.
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        (void)hipStreamIsCapturing(ctx->cap_stream, &cs);
+        (void)hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        ctx->stream = s;
+        ctx->capturing = false;
+        (void)hipGetLastError();
+        if (cs != hipStreamCaptureStatusInvalidated) throw;
+        eager();
+        g.gen = ctx->buf_gen;
+        return;
       } catch (...) {
         (void)hipStreamEndCapture(ctx->cap_stream, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1673,6 +1689,63 @@ void state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0, int r
   st->r = r;
 }
 
+// Repeated steps until err_ada <= res_tol or max_steps (Sec. 5.1).  *info
+// holds the steps taken so far also when a step fails (the exception
+// propagates) or `cancel` is raised between steps (info->converged = 0).
+void steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state, const blr_solve_params* p,
+                  blr_solve_info* info, const std::atomic<bool>* cancel) {
+  require(p != nullptr && info != nullptr, "null solve params");
+  require(p->max_steps >= 1, "max_steps must be >= 1");
+  require(p->res_tol >= 0, "res_tol must be >= 0");
+  *info = blr_solve_info{};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BLR_HIP(hipEventCreate(&e0));
+  BLR_HIP(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  BLR_HIP(hipEventRecord(e0, ctx->stream));
+  for (int64_t k = 0; k < p->max_steps; ++k) {
+    if (cancel && cancel->load(std::memory_order_relaxed)) break;
+    blr_step_info si{};
+    dlr_step(ctx, pb, state, &p->step, &si);
+    const int64_t rk = si.r_in + si.r_added;
+    info->pair_evals += rk * (rk + 1) / 2;
+    info->steps = k + 1;
+    info->err_ada = si.err_ada;
+    info->r = state->r;
+    if (si.err_ada <= p->res_tol) {
+      info->converged = 1;
+      break;
+    }
+  }
+  BLR_HIP(hipEventRecord(e1, ctx->stream));
+  BLR_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  BLR_HIP(hipEventElapsedTime(&ms, e0, e1));
+  info->ms_wall = ms;
+}
+
+// Device bytes a context holds for solves of this shape: the collision
+// workspace at r_cap plus the step's named buffers (velocity-side arrays of
+// r_cap rows: working copy, L-step result and update, new basis, QR scratch;
+// the pair collisions; x-side arrays).  An estimate used for admission.
+size_t solve_workspace_bytes(const blr_vgrid& vg, int nx, int r_cap, bool fp64_collision) {
+  validate_vgrid(vg);
+  require(nx >= 1 && r_cap >= 1 && r_cap <= 64, "bad solve shape");
+  const size_t n = (size_t)std::llround(std::pow((double)vg.n, vg.d));
+  const size_t P = (size_t)r_cap * (r_cap + 1) / 2;
+  size_t b = collision_workspace_bytes(vg, r_cap, fp64_collision ? BLR_FP64 : BLR_FP32);
+  b += (size_t)r_cap * n * 8 * 6;
+  b += fp64_collision ? P * n * 8 : P * n * 4 + (size_t)r_cap * n * 4;
+  b += (size_t)r_cap * nx * 8 * 8 + (size_t)P * r_cap * 8 * 4 + (8u << 20);
+  return b;
+}
+
 }  // namespace blr
 
 // ------------------------------------------------------------------ C ABI --
@@ -1708,33 +1781,7 @@ blr_status blr_dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* state,
 blr_status blr_steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state,
                             const blr_solve_params* p, blr_solve_info* info) {
   blr_solve_info out{};
-  const blr_status rc = guarded_dlr(ctx, [&] {
-    blr::require(p != nullptr, "null solve params");
-    blr::require(p->max_steps >= 1, "max_steps must be >= 1");
-    blr::require(p->res_tol >= 0, "res_tol must be >= 0");
-    hipEvent_t e0, e1;
-    BLR_HIP(hipEventCreate(&e0));
-    BLR_HIP(hipEventCreate(&e1));
-    BLR_HIP(hipEventRecord(e0, ctx->stream));
-    for (int64_t k = 0; k < p->max_steps; ++k) {
-      blr_step_info si{};
-      blr::dlr_step(ctx, pb, state, &p->step, &si);
-      out.steps = k + 1;
-      out.err_ada = si.err_ada;
-      out.r = state->r;
-      if (si.err_ada <= p->res_tol) {
-        out.converged = 1;
-        break;
-      }
-    }
-    BLR_HIP(hipEventRecord(e1, ctx->stream));
-    BLR_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    BLR_HIP(hipEventElapsedTime(&ms, e0, e1));
-    out.ms_wall = ms;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-  });
+  const blr_status rc = guarded_dlr(ctx, [&] { blr::steady_solve(ctx, pb, state, p, &out); });
   if (info) *info = out;
   if (rc != BLR_OK) return rc;
   return out.converged ? BLR_OK : BLR_ERR_NOT_CONVERGED;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -171,5 +172,12 @@ void validate_vgrid(const blr_vgrid& vg);
 void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
                      const int32_t* pairs_dev, int npairs, void* Q);
 size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec);
+
+// DLR step and steady solve (dlr.hip)
+void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_params* sp,
+              blr_step_info* info);
+void steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state, const blr_solve_params* p,
+                  blr_solve_info* info, const std::atomic<bool>* cancel = nullptr);
+size_t solve_workspace_bytes(const blr_vgrid& vg, int nx, int r_cap, bool fp64_collision);
 
 }  // namespace blr

@@ -21,7 +21,8 @@ import numpy as np
 __all__ = [
     "vgrid_points", "xgrid_centres", "maxwellian", "rh_downstream", "shock_states",
     "c1_distribution", "c2_bimaxwellian", "c2_bkw", "smooth_basis", "shock_initial",
-    "lowrank_state", "VGridSpec", "C1", "C2", "C3", "small_3d", "small_2d",
+    "lowrank_state", "lowrank_state_sketch", "serving_trace", "VGridSpec", "C1", "C2", "C3",
+    "small_3d", "small_2d",
 ]
 
 
@@ -244,3 +245,71 @@ def lowrank_state(f0: np.ndarray, r: int, dx: float, dvd: float):
     V = np.ascontiguousarray(Wt / math.sqrt(dvd))
     S = np.diag(s)
     return X, S, V
+
+
+def lowrank_state_sketch(f0: np.ndarray, r: int, dx: float, dvd: float, seed: int = 0,
+                         oversample: int = 10, power: int = 2):
+    """Rank-r factors like ``lowrank_state``, from a randomized range finder
+    (Gaussian sketch of ``r + oversample`` columns, ``power`` subspace
+    iterations with re-orthonormalisation, then the SVD of the small
+    projected matrix).  Input preparation for large f0, where a full SVD
+    takes seconds; the factors are orthonormal to rounding and the rank-r
+    truncation is accurate when the singular values decay fast."""
+    w = math.sqrt(dx * dvd)
+    A = f0 * w
+    rng = np.random.default_rng(seed)
+    k = min(r + oversample, min(A.shape))
+    Y = A @ rng.standard_normal((A.shape[1], k))
+    Qm, _ = np.linalg.qr(Y)
+    for _ in range(power):
+        Z, _ = np.linalg.qr(A.T @ Qm)
+        Qm, _ = np.linalg.qr(A @ Z)
+    B = Qm.T @ A
+    Ub, s, Wt = np.linalg.svd(B, full_matrices=False)
+    U = Qm @ Ub
+    U, s, Wt = U[:, :r], s[:r], Wt[:r]
+    for i in range(r):
+        j = np.argmax(np.abs(U[:, i]))
+        if U[j, i] < 0:
+            U[:, i] *= -1.0
+            Wt[i] *= -1.0
+    X = np.ascontiguousarray(U / math.sqrt(dx))
+    V = np.ascontiguousarray(Wt / math.sqrt(dvd))
+    return X, np.diag(s), V
+
+
+def serving_trace(count: int = 64, seed: int = 5, rate: float = 4.0, mach=(1.2, 3.0),
+                  nx_choices=(128, 256, 512), n_choices=(24, 32), r0=(5, 25),
+                  half_width=None, x_lo: float = -30.0, x_hi: float = 30.0, cfl: float = 0.35,
+                  nu_frac: float = 1.5, safety: float = 0.5, C: float = 1.0):
+    """A stream of steady normal-shock solves (hard spheres in 3D velocity):
+    Poisson arrivals of the given rate (exponential gaps, first request at
+    t = 0), Mach ~ U[mach], N_x and N_v drawn uniformly from the choices,
+    initial rank ~ U{r0}.
+
+    Velocity box: L_v = 8 at N_v = 24 and 10 at N_v = 32 (``half_width``
+    overrides), so the grid step stays at or below 2/3 of the upstream
+    thermal speed.  dt = safety * min(cfl dx / L_v, nu_frac / nu): the upwind
+    CFL on the fastest grid velocity, and the relaxation limit with nu =
+    4 pi C R rho_R a bound of the hard-sphere loss rate (B = C |q| truncated
+    at R = 4 L_v / (3 + sqrt 2), downstream density rho_R).
+    Returns a list of dicts."""
+    hw = {24: 8.0, 32: 10.0} if half_width is None else dict(half_width)
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for k in range(count):   # one draw sequence per request: a longer trace extends a shorter one
+        gap = float(rng.exponential(1.0 / rate))
+        t = 0.0 if k == 0 else t + gap
+        m = float(rng.uniform(*mach))
+        nx = int(rng.choice(nx_choices))
+        n = int(rng.choice(n_choices))
+        r = int(rng.integers(r0[0], r0[1] + 1))
+        L = float(hw[n])
+        dx = (x_hi - x_lo) / nx
+        R = 4.0 * L / (3.0 + math.sqrt(2.0))
+        rho_r = rh_downstream(m, 3)[1][0]
+        dt = safety * min(cfl * dx / L, nu_frac / (4.0 * math.pi * C * R * rho_r))
+        out.append(dict(index=k, arrival=t, mach=m, nx=nx, n=n, r0=r, L=L,
+                        dt=dt, x_lo=x_lo, x_hi=x_hi))
+    return out

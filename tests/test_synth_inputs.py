@@ -45,3 +45,38 @@ def test_seeded_inputs_are_deterministic():
     b = synth.c1_distribution()
     assert np.array_equal(a, b)
     assert np.array_equal(synth.smooth_basis(3, synth.C2, seed=4), synth.smooth_basis(3, synth.C2, seed=4))
+
+
+def test_sketched_lowrank_state_matches_the_svd():
+    """The randomized range finder gives the same truncation as the full SVD
+    (singular values, reconstruction) on shock data, with orthonormal factors."""
+    spec = synth.VGridSpec(d=2, n=16, L=8.0)
+    ini = synth.shock_initial(2.0, spec, 64, pert=1e-3, pert_rank=6, seed=9)
+    dx, dvd = 60.0 / 64, (16.0 / 16) ** 2
+    X, S, V = synth.lowrank_state(ini["f0"], 8, dx, dvd)
+    Xs, Ss, Vs = synth.lowrank_state_sketch(ini["f0"], 8, dx, dvd, seed=1)
+    assert np.abs(dx * Xs.T @ Xs - np.eye(8)).max() < 1e-12
+    assert np.abs(dvd * Vs @ Vs.T - np.eye(8)).max() < 1e-12
+    assert np.abs(np.diag(Ss) - np.diag(S)).max() < 1e-9 * S[0, 0]
+    f = X @ S @ V
+    assert np.abs(Xs @ Ss @ Vs - f).max() < 1e-8 * np.abs(f).max()
+
+
+def test_serving_trace_recipe():
+    tr = synth.serving_trace(count=400, seed=5, rate=4.0)
+    assert tr[:16] == synth.serving_trace(count=16, seed=5, rate=4.0)   # prefix-stable
+    t = np.array([q["arrival"] for q in tr])
+    assert t[0] == 0.0 and np.all(np.diff(t) > 0)
+    gaps = np.diff(t)
+    assert abs(gaps.mean() - 0.25) < 0.04          # Poisson arrivals at 4 per second
+    assert abs(gaps.std() / gaps.mean() - 1.0) < 0.15   # exponential gaps: CV = 1
+    for q in tr:
+        assert 1.2 <= q["mach"] <= 3.0 and 5 <= q["r0"] <= 25
+        assert q["nx"] in (128, 256, 512) and q["n"] in (24, 32)
+        assert q["L"] == {24: 8.0, 32: 10.0}[q["n"]]
+        dx = 60.0 / q["nx"]
+        R = 4.0 * q["L"] / (3.0 + math.sqrt(2.0))
+        nu = 4.0 * math.pi * R * synth.rh_downstream(q["mach"], 3)[1][0]
+        assert q["dt"] <= 0.5 * 0.35 * dx / q["L"] + 1e-15
+        assert q["dt"] * nu <= 0.75 + 1e-12
+        assert q["dt"] == min(0.5 * 0.35 * dx / q["L"], 0.5 * 1.5 / nu)
