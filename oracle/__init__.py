@@ -17,4 +17,9 @@ collision   the discrete collision operator: its definition as a direct
 dlr         the fully discrete K-S-L low-rank step (Sec. 2.4), boundary
             ghost values (Sec. 2.3), error pieces (Sec. 5.1), basis add/drop
             (Sec. 3) and the steady-state driver
+shock       the Mott-Smith shock quantities of Sec. 4 (alpha, beta, the
+            logistic density profile)
+carleman    the Carleman-form fast spectral operator (2D Maxwell molecules,
+            3D hard spheres): its definition as a weighted direct sum and the
+            fast form with filtered transforms
 """

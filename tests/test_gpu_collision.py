@@ -170,3 +170,37 @@ def test_full_size_sampled_modes_match_direct_sum(ctx):
     err = np.abs(qh_gpu[ks] - ref).max() / scale
     print("sampled-mode err", err, flush=True)
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("d,n,m_rho,mach", [(2, 32, 16, 1.4), (3, 16, 8, 1.5), (3, 32, 16, 1.5)])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_mott_smith_alpha_matches_oracle(ctx, d, n, m_rho, mach, dtype):
+    """alpha = int v_1^2 (Q(f_L, f_R) + Q(f_R, f_L)) dv (Sec. 4, eq. alpha) for
+    the Rankine-Hugoniot Maxwellians, from the library's pair collision
+    Q_s(f_L, f_R) against the oracle's (hard spheres in 3D, Maxwell
+    molecules in 2D).  FP64: 1e-12 relative.  FP32: the pair bound
+    ||dQ||_2 <= 1e-5 ||Q+||_2 and Cauchy-Schwarz give
+    |d alpha| <= 2 dv^d ||v_1^2||_2 1e-5 ||Q+||_2."""
+    from oracle import shock
+    spec = _spec(d, n, m_rho)
+    vs = oc.setup_from_spec(spec)
+    left, right = synth.rh_downstream(mach, d)
+    v = synth.vgrid_points(d, n, spec.L)
+    fL = synth.maxwellian(v, left[0], (left[1],) + (0.0,) * (d - 1), left[2]).reshape(-1)
+    fR = synth.maxwellian(v, right[0], (right[1],) + (0.0,) * (d - 1), right[2]).reshape(-1)
+    print(f"mott-smith alpha d={d} n={n} {dtype}", flush=True)
+    a_ref = shock.mott_smith_alpha(fL, fR, vs)
+    _, gain = oc.q_pairs(np.array([fL, fR]), [(0, 1)], vs, conserve=False)
+    vg = blr.vgrid_from_spec(spec, blr.BLR_NO_CONSERVE)
+    dt = getattr(torch, dtype)
+    Q = ctx.collision_pairs(vg, torch.tensor(np.array([fL, fR]), dtype=dt, device="cuda"),
+                            [(0, 1)]).double().cpu().numpy()[0]
+    v1sq = (v[0].reshape(-1)) ** 2
+    dvd = vs.dv ** d
+    a_gpu = 2.0 * dvd * float(np.dot(v1sq, Q))
+    if dt == torch.float64:
+        assert abs(a_gpu - a_ref) <= 1e-12 * abs(a_ref)
+    else:
+        bound = 2.0 * dvd * np.linalg.norm(v1sq) * 1e-5 * np.linalg.norm(gain[0])
+        assert abs(a_gpu - a_ref) <= bound
+        print("fp32 alpha error", abs(a_gpu - a_ref), "bound", bound, flush=True)
