@@ -30,7 +30,7 @@ written out from the Carleman representation of eq. (collision_operator):
   closed forms
       2D: phi(s) = 2 sin(a R)/a,  a = pi s / L   (2R at a = 0);
           psi(l, e) = phi(l.e_perp)  (the disc is a segment);
-      3D: phi(s) = 2 [R sin(aR)/a + (cos(aR) - 1)/a^2]   (R^2 at a = 0);
+      3D: phi(s) = 2 [R sin(aR)/a - 2 sin^2(aR/2)/a^2]   (R^2 at a = 0);
           psi(l, e) = 2 pi R J1(b R) / b,  b = pi |l - (l.e) e| / L   (pi R^2 at 0).
   The direction integral is the quadrature that makes beta separable:
       2D: e_p = (cos t_p, sin t_p), t_p = p pi / M, weights pi / M (M even);
@@ -121,7 +121,8 @@ def phi(cs: CarlemanSetup, s):
     if cs.d == 2:
         v = 2.0 * np.sin(a_safe * R) / a_safe
         return np.where(small, 2.0 * R, v)
-    v = 2.0 * (R * np.sin(a_safe * R) / a_safe + (np.cos(a_safe * R) - 1.0) / a_safe ** 2)
+    # cos(aR) - 1 written as -2 sin^2(aR/2): the same value without cancellation
+    v = 2.0 * (R * np.sin(a_safe * R) / a_safe - 2.0 * np.sin(0.5 * a_safe * R) ** 2 / a_safe ** 2)
     return np.where(small, R * R, v)
 
 
