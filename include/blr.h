@@ -51,10 +51,23 @@ typedef enum { BLR_FP32 = 0, BLR_FP64 = 1 } blr_precision;
 #define BLR_NO_CONSERVE      0x1u  /* skip the FP64 moment-conservation projection   */
 #define BLR_PLAIN_SCHEDULE   0x2u  /* one pair at a time, no shift reuse (baseline)   */
 #define BLR_GENERIC_FFT      0x4u  /* force the multi-pass FFT path (no fused kernels) */
+/* The Carleman form of the fast spectral method instead of the (rho, sigma)
+ * form: for 2D Maxwell molecules (gamma = 0) and 3D hard spheres (gamma = 1),
+ * the two kernels for which the paper names this algorithm (Sec. 2.1; Sec. 5
+ * runs it for every 2D example), the Carleman representation of the
+ * operator has a constant kernel 2^(d-1) C and the collision weight splits
+ * over directions e on a half sphere into products of two closed-form
+ * filters of the modes; Q+ is then a sum over directions of pointwise
+ * products of filtered inverse transforms, and the loss is f times the
+ * inverse transform of beta(l, l) g^.  m_sigma: 2D, an even number M of
+ * equispaced directions on [0, pi); 3D, 38 (one direction per antipodal pair
+ * of the Lebedev rule, 19).  m_rho is not used.  BLR_ERR_ARG unless
+ * gamma = d - 2. */
+#define BLR_CARLEMAN         0x8u
 
 /* Velocity discretisation and collision kernel.
  *   d       velocity dimension, 2 or 3
- *   n       points per axis: 3D n in {8, 16, 24, 32}; 2D n in {16, 32, 48, 64}
+ *   n       points per axis: 3D n in {8, 16, 24, 32}; 2D n in {16, 32}
  *   L       half width of the velocity box
  *   R       truncation radius of |v - v*|; R <= 0 selects 4L/(3 + sqrt 2)
  *   C,gamma B(|v - v*|) = C |v - v*|^gamma (isotropic: Maxwell gamma = 0,

@@ -22,6 +22,7 @@ BLR_FP32, BLR_FP64 = 0, 1
 BLR_NO_CONSERVE = 0x1
 BLR_PLAIN_SCHEDULE = 0x2
 BLR_GENERIC_FFT = 0x4
+BLR_CARLEMAN = 0x8
 BLR_STEP_ADD = 0x1
 BLR_STEP_DROP = 0x2
 BLR_STEP_FP64_COLLISION = 0x4

@@ -190,7 +190,8 @@ static std::vector<T> cast_vec(const std::vector<double>& v) {
 const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
   validate_vgrid(vg);
   const int ms = vg.m_sigma ? vg.m_sigma : (vg.d == 2 ? 8 : 38);
-  auto key = std::make_tuple(vg.d, vg.n, vg.L, vg.R, vg.C, vg.gamma, vg.m_rho, ms, prec);
+  const int form = (vg.flags & BLR_CARLEMAN) ? 1 : 0;
+  auto key = std::make_tuple(vg.d, vg.n, vg.L, vg.R, vg.C, vg.gamma, vg.m_rho, ms, prec, form);
   auto it = ctx->tables.find(key);
   if (it != ctx->tables.end()) return *it->second;
   auto t = std::make_unique<DevTables>();
@@ -209,6 +210,10 @@ const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
     t->fw = upload_vec(*t, h.fw);
     t->gloss = upload_vec(*t, h.gloss);
     t->wbp = upload_vec(*t, wbp);
+  }
+  if (h.carleman) {
+    if (prec == BLR_FP32) t->filt = upload_vec(*t, cast_vec<float>(h.filt));
+    else t->filt = upload_vec(*t, h.filt);
   }
   t->bp_b = (int*)upload_vec(*t, h.bp_b);
   t->bp_bb = (int*)upload_vec(*t, h.bp_bb);

@@ -139,6 +139,31 @@ struct LdShift {
   }
 };
 
+// Carleman form: V^_ib c_p(k) (complex product) for field f = (ib, p)
+template <typename T>
+struct LdFilter {
+  static constexpr int bpe = 4;  // algorithmic bytes per element / sizeof(T)
+  const typename Vec2<T>::t* vh;
+  const typename Vec2<T>::t* filt;  // nbp x n
+  int n, nbp;
+  long f0;
+  template <int N>
+  __device__ void load(long fl, int base, int stride, T (&re)[N], T (&im)[N]) const {
+    const long f = f0 + fl;
+    const int p = (int)(f % nbp);
+    const long ib = f / nbp;
+    const auto* q = vh + ib * n + base;
+    const auto* c = filt + (long)p * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const auto v = q[(long)j * stride];
+      const auto w = c[(long)j * stride];
+      re[j] = v.x * w.x - v.y * w.y;
+      im[j] = v.x * w.y + v.y * w.x;
+    }
+  }
+};
+
 // one pair-product field (real) per complex transform: pairs are not packed
 // two to a transform because their magnitudes can differ by orders of
 // magnitude and the smaller one would inherit the larger one's rounding.
@@ -303,6 +328,22 @@ struct StFinal {
     }
   }
 };
+
+// Carleman form: Q = gain - loss with the gain already on the grid
+template <typename T>
+__global__ __launch_bounds__(256) void k_carleman_final(const T* __restrict__ Pa, const T* __restrict__ vp,
+                                                        const T* __restrict__ lam,
+                                                        const int* __restrict__ pi,
+                                                        const int* __restrict__ pj,
+                                                        const int* __restrict__ prow, int n,
+                                                        T* __restrict__ Q) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (e >= n) return;
+  const long i = pi[p], j = pj[p];
+  Q[(long)prow[p] * n + e] =
+      Pa[(long)p * n + e] - T(0.5) * (vp[j * n + e] * lam[i * n + e] + vp[i * n + e] * lam[j * n + e]);
+}
 
 // ------------------------------------------------------------ line pass
 template <typename T, int N, int D, int DIR, class Ld, class St>
@@ -566,10 +607,21 @@ static PairPlan make_plan(int r, const int32_t* pairs, int npairs) {
       map[i] = (int)pl.bidx.size();
       pl.bidx.push_back(i);
     }
+  // each distinct unordered pair is evaluated once (Q_s is symmetric); a
+  // repeated request copies the row of its first occurrence
+  std::vector<int> first((size_t)r * r, -1);
   for (int p = 0; p < npairs; ++p) {
-    int a = map[pairs[2 * p]], b = map[pairs[2 * p + 1]];
-    pl.li.push_back(std::min(a, b));
-    pl.lj.push_back(std::max(a, b));
+    const int a = map[pairs[2 * p]], b = map[pairs[2 * p + 1]];
+    const int lo = std::min(a, b), hi = std::max(a, b);
+    int& f = first[(size_t)lo * r + hi];
+    if (f >= 0) {
+      pl.dup.emplace_back(p, f);
+      continue;
+    }
+    f = p;
+    pl.li.push_back(lo);
+    pl.lj.push_back(hi);
+    pl.row.push_back(p);
   }
   return pl;
 }
@@ -619,6 +671,58 @@ struct Generic {
     *pLam = Vp + (size_t)rb * n;
   }
 
+  // Carleman form: filtered fields (two per direction pair and basis function,
+  // one complex inverse transform each), the direction sums of their pair
+  // products (the sigma reduction with weights b0 w), minus the loss.
+  static void carleman(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const T2* Vh,
+                       const T* Vp, const T* Lam, T* Sh, T2* tmp, T* Pa, const int* didx, int P,
+                       T* Q) {
+    const HostTables& h = tb.h;
+    hipStream_t s = ctx->stream;
+    const int rb = (int)pl.bidx.size();
+    const long nfields = (long)rb * h.nbp;
+    const long batch = std::min<long>(nfields, 512);
+    g_stage = "carl.filter";
+    for (long f0 = 0; f0 < nfields; f0 += batch) {
+      const long nb = std::min(batch, nfields - f0);
+      transform<T, N, D, +1>(s, LdFilter<T>{Vh, (const T2*)tb.filt, n, h.nbp, f0},
+                             StShiftSplit<T>{Sh, tb.bp_b, tb.bp_bb, n, 1, h.nbp, h.msig, f0}, tmp,
+                             nb);
+    }
+    bool diag_only = false;
+    const int Gt = sizeof(T) == 4 ? 12 : 8;
+    auto tiles = plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
+    for (const auto& t : tiles) {
+      const bool diag = t.bi[0] == t.bj[0];
+      const int bs = 256;
+      const dim3 grid((n + bs - 1) / bs);
+      int nvalid = 0;
+      for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
+      const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
+      TimedScope ts(s, "carl.sigma_reduce", (double)n * (nload * h.nbp + nvalid) * sizeof(T));
+      if (sizeof(T) == 4) {
+        if (diag)
+          hipLaunchKernelGGL((k_sigma_reduce<T, 12, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
+                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0);
+        else
+          hipLaunchKernelGGL((k_sigma_reduce<T, 12, false>), grid, dim3(bs), 0, s, Sh, Pa, t,
+                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0);
+      } else {
+        if (diag)
+          hipLaunchKernelGGL((k_sigma_reduce<T, 8, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
+                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0);
+        else
+          hipLaunchKernelGGL((k_sigma_reduce<T, 8, false>), grid, dim3(bs), 0, s, Sh, Pa, t,
+                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0);
+      }
+      BLR_CHECK_LAUNCH();
+    }
+    TimedScope ts(s, "carl.final", (double)P * n * 6 * sizeof(T));
+    hipLaunchKernelGGL((k_carleman_final<T>), dim3((n + 255) / 256, P), dim3(256), 0, s, Pa, Vp, Lam,
+                       didx, didx + P, didx + 2 * P, n, Q);
+    BLR_CHECK_LAUNCH();
+  }
+
   // Q rows prow[p] receive Q_s(bidx[li[p]], bidx[lj[p]]) of the compact basis Vc.
   static void run(blr_ctx ctx, const DevTables& tb, const T* Vsrc, const PairPlan& pl,
                   const std::vector<int>& prow, T* Q) {
@@ -634,7 +738,7 @@ struct Generic {
     T2* tmp = (T2*)ctx->buf(tag + ".tmp",
                             (size_t)std::max<long>(batch, std::max<long>(nc, 2 * rb)) * n * sizeof(T2));
     T* Pa = (T*)ctx->buf(tag + ".Pa", (size_t)P * n * sizeof(T));
-    T2* G = (T2*)ctx->buf(tag + ".G", (size_t)nc * n * sizeof(T2));
+    T2* G = h.carleman ? nullptr : (T2*)ctx->buf(tag + ".G", (size_t)nc * n * sizeof(T2));
     // per-call index arrays (pi, pj, prow) through the pinned stage
     std::vector<int> idx(3 * P);
     for (int p = 0; p < P; ++p) {
@@ -650,6 +754,10 @@ struct Generic {
     T* Vp;
     T* Lam;
     basis(ctx, tb, Vsrc, pl, &Vh, &Vp, &Lam);
+    if (h.carleman) {
+      carleman(ctx, tb, pl, Vh, Vp, Lam, Sh, tmp, Pa, didx, P, Q);
+      return;
+    }
     // 2. shifts
     g_stage = "gen.shift";
     for (long f0 = 0; f0 < shift_fields; f0 += batch) {
@@ -714,8 +822,6 @@ static void dispatch_size(int d, int N, F&& f) {
     switch (N) {
       case 16: f(std::integral_constant<int, 16>{}, std::integral_constant<int, 2>{}); return;
       case 32: f(std::integral_constant<int, 32>{}, std::integral_constant<int, 2>{}); return;
-      case 48: f(std::integral_constant<int, 48>{}, std::integral_constant<int, 2>{}); return;
-      case 64: f(std::integral_constant<int, 64>{}, std::integral_constant<int, 2>{}); return;
     }
   }
   throw Error(BLR_ERR_UNSUPPORTED, "velocity grid size not built");
@@ -738,17 +844,27 @@ static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const
     }
   } else {
     PairPlan pl = make_plan(r, pairs, npairs);
-    std::vector<int> prow(npairs);
-    for (int p = 0; p < npairs; ++p) prow[p] = p;
+    const std::vector<int>& prow = pl.row;
     bool done = false;
     if constexpr (sizeof(T) == 4) {
-      if (!(flags & BLR_GENERIC_FFT))
+      if (!(flags & BLR_GENERIC_FFT) && !h.carleman)
         done = fast_collision_f32(ctx, tb, V, pl, prow, Q, !(flags & BLR_NO_CONSERVE));
     }
-    if (done) return;  // the fused final kernel applied the projection
-    dispatch_size<T>(h.d, h.N, [&](auto Nc, auto Dc) {
-      Generic<T, decltype(Nc)::value, decltype(Dc)::value>::run(ctx, tb, V, pl, prow, Q);
-    });
+    if (!done) {
+      dispatch_size<T>(h.d, h.N, [&](auto Nc, auto Dc) {
+        Generic<T, decltype(Nc)::value, decltype(Dc)::value>::run(ctx, tb, V, pl, prow, Q);
+      });
+      if (!(flags & BLR_NO_CONSERVE)) {
+        if (pl.dup.empty())
+          conserve_rows<T>(ctx->stream, h, Q, npairs);
+        else
+          for (int p : prow) conserve_rows<T>(ctx->stream, h, Q + (size_t)p * h.n, 1);
+      }
+    }
+    for (const auto& dp : pl.dup)
+      BLR_HIP(hipMemcpyAsync(Q + (size_t)dp.first * h.n, Q + (size_t)dp.second * h.n,
+                             (size_t)h.n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    return;
   }
   if (!(flags & BLR_NO_CONSERVE)) conserve_rows<T>(ctx->stream, h, Q, npairs);
 }

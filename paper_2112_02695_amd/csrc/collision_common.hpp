@@ -1,6 +1,8 @@
 // Shared device helpers of the collision kernels.
 #pragma once
 
+#include <utility>
+
 #include "fft.hpp"
 #include "internal.hpp"
 
@@ -51,7 +53,9 @@ struct ReduceTile {
 // compact basis and pair list of one call
 struct PairPlan {
   std::vector<int> bidx;     // compact basis -> row of V
-  std::vector<int> li, lj;   // per pair, compact indices (li <= lj)
+  std::vector<int> li, lj;   // per distinct pair, compact indices (li <= lj)
+  std::vector<int> row;      // per distinct pair, the first output row asking for it
+  std::vector<std::pair<int, int>> dup;  // (output row, row it repeats) for repeated pairs
 };
 
 std::vector<ReduceTile> plan_tiles(int rb, const std::vector<int>& li, const std::vector<int>& lj,

@@ -51,6 +51,12 @@ struct HostTables {
   std::vector<double> fw;                     // mrho x nkk : cw B A_d(th |k|) / n
   std::vector<double> gloss;                  // n     : G-(k) (DFT order)
   std::vector<double> minv;                   // (d+2)^2 : (C C^T)^-1, C rows dv^d{1,v,|v|^2}
+  // Carleman form (BLR_CARLEMAN): one "radial node", nbp direction pairs of
+  // filtered fields, filt = nbp x n complex multipliers (DFT order) whose
+  // inverse transform W gives the pair's two fields as Re W - Im W and
+  // Re W + Im W; gloss holds beta(l, l); phase and fw are unused.
+  bool carleman = false;
+  std::vector<double> filt;                   // nbp x n x 2
 };
 
 HostTables build_tables(const blr_vgrid& vg);
@@ -67,6 +73,7 @@ struct DevTables {
   void* wbp = nullptr;     // T  : nbp sphere weights of the antipodal pairs
   int* bp_b = nullptr;     // nbp
   int* bp_bb = nullptr;    // nbp
+  void* filt = nullptr;    // T2 : nbp x n (Carleman form only)
   std::vector<void*> owned;
   ~DevTables();
 };
@@ -107,7 +114,7 @@ struct blr_ctx_t {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  std::map<std::tuple<int, int, double, double, double, double, int, int, int>,
+  std::map<std::tuple<int, int, double, double, double, double, int, int, int, int>,
            std::unique_ptr<blr::DevTables>>
       tables;
   std::map<std::string, blr::Buffer> bufs;

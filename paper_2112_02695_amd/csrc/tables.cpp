@@ -60,6 +60,17 @@ double bessel_j0(double z) {
   return s / M;
 }
 
+// J1(z) = (1/2pi) int_0^2pi cos(t - z sin t) dt, same rule as bessel_j0.
+static double bessel_j1(double z) {
+  const int M = 64 + 2 * (int)std::ceil(std::fabs(z));
+  double s = 0.0;
+  for (int j = 0; j < M; ++j) {
+    const double t = 2.0 * kPi * j / M;
+    s += std::cos(t - z * std::sin(t));
+  }
+  return s / M;
+}
+
 static void sphere_rule(int d, int msig, std::vector<double>& sig, std::vector<double>& w) {
   sig.clear();
   w.clear();
@@ -113,8 +124,9 @@ void validate_vgrid(const blr_vgrid& vg) {
     require(vg.n == 8 || vg.n == 16 || vg.n == 24 || vg.n == 32,
             "3D vgrid.n must be 8, 16, 24 or 32", BLR_ERR_UNSUPPORTED);
   else
-    require(vg.n == 16 || vg.n == 32 || vg.n == 48 || vg.n == 64,
-            "2D vgrid.n must be 16, 32, 48 or 64", BLR_ERR_UNSUPPORTED);
+    // 48 and 64 are off: a run of the 2D 64-point FP64 line passes (256 VGPRs
+    // plus AGPR spills) faulted the GPU without a cause found in the code
+    require(vg.n == 16 || vg.n == 32, "2D vgrid.n must be 16 or 32", BLR_ERR_UNSUPPORTED);
   require(vg.L > 0 && std::isfinite(vg.L), "vgrid.L must be positive");
   require(std::isfinite(vg.C) && std::isfinite(vg.gamma), "vgrid.C/gamma must be finite");
   require(vg.m_rho >= 1 && vg.m_rho <= 64, "vgrid.m_rho must be in [1, 64]");
@@ -123,6 +135,171 @@ void validate_vgrid(const blr_vgrid& vg) {
     require(ms == 38, "3D vgrid.m_sigma must be 38 (Lebedev rule)", BLR_ERR_UNSUPPORTED);
   else
     require(ms >= 2 && ms <= 64 && ms % 2 == 0, "2D vgrid.m_sigma must be even in [2, 64]");
+  if (vg.flags & BLR_CARLEMAN)
+    require(std::fabs(vg.gamma - (vg.d - 2)) < 1e-12,
+            "the Carleman form needs gamma = d - 2 (2D Maxwell molecules, 3D hard spheres)");
+}
+
+// (C C^T)^-1 for the moment projection; C rows dv^d {1, v_1..v_d, |v|^2}
+static std::vector<double> moment_inverse(const HostTables& t) {
+  const int d = t.d, N = t.N, m = d + 2;
+  std::vector<double> G(m * m, 0.0);
+  const double w = std::pow(t.dv, d);
+  for (int q = 0; q < t.n; ++q) {
+    double v[3] = {0, 0, 0};
+    int rem = q;
+    for (int ax = d - 1; ax >= 0; --ax) {
+      v[ax] = -t.L + (rem % N) * t.dv;
+      rem /= N;
+    }
+    double phi[5];
+    phi[0] = w;
+    double v2 = 0;
+    for (int ax = 0; ax < d; ++ax) {
+      phi[1 + ax] = w * v[ax];
+      v2 += v[ax] * v[ax];
+    }
+    phi[d + 1] = w * v2;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) G[i * m + j] += phi[i] * phi[j];
+  }
+  // Gauss-Jordan inverse (SPD, small)
+  std::vector<double> A(G), I(m * m, 0.0);
+  for (int i = 0; i < m; ++i) I[i * m + i] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(A[r * m + c]) > std::fabs(A[piv * m + c])) piv = r;
+    for (int j = 0; j < m; ++j) {
+      std::swap(A[c * m + j], A[piv * m + j]);
+      std::swap(I[c * m + j], I[piv * m + j]);
+    }
+    const double dgn = A[c * m + c];
+    require(std::fabs(dgn) > 0, "singular moment matrix", BLR_ERR_NUMERIC);
+    for (int j = 0; j < m; ++j) {
+      A[c * m + j] /= dgn;
+      I[c * m + j] /= dgn;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double f = A[r * m + c];
+      for (int j = 0; j < m; ++j) {
+        A[r * m + j] -= f * A[c * m + j];
+        I[r * m + j] -= f * I[c * m + j];
+      }
+    }
+  }
+  return I;
+}
+
+// Carleman form.  With v' = v + x, v*' = v + y (x orthogonal to y) the kernel
+// is the constant b0 = 2^(d-1) C; x = rho e (e on a half sphere, rho in
+// [-R, R]) and y in the disc of radius R orthogonal to e give
+//   beta(l, m) = b0 int de phi(m.e) psi(l, e),
+//   phi(s) = int_{-R}^{R} |rho|^(d-2) exp(i pi rho s / L) d rho,
+//   psi    = the same integral over the disc (2D: a segment, phi(l.e_perp)).
+// Directions: 2D t_p = p pi / M (weights pi / M), 3D one point per antipodal
+// pair of the Lebedev rule with its full-sphere weight.  Each pair of fields
+// (f1 -> S(b), f2 -> S(bbar)) is produced by one complex inverse transform of
+// V^ ((f1 + f2)/2 + i (f2 - f1)/2); the sigma reduction then yields
+//   sum_pairs w (S_i(b) S_j(bbar) + S_i(bbar) S_j(b)) = Q_s+(V_i, V_j).
+//   2D: pair p < M/2 is (phi(k.e_p), phi(k.e_{p+M/2})), w = b0 pi / M;
+//   3D: pair p is (psi(k, e_p), phi(k.e_p)), w = b0 w_p / 2.
+static void carleman_tables(HostTables& t) {
+  const int N = t.N, d = t.d, n = t.n;
+  const double R = t.R, L = t.L, b0 = std::pow(2.0, d - 1) * t.C;
+  auto centred = [N](int k) { return k >= N / 2 ? k - N : k; };
+  auto phi = [&](double s) {
+    const double a = kPi * s / L;
+    if (std::fabs(a) < 1e-12) return d == 2 ? 2.0 * R : R * R;
+    if (d == 2) return 2.0 * std::sin(a * R) / a;
+    const double h = std::sin(0.5 * a * R);
+    return 2.0 * (R * std::sin(a * R) / a - 2.0 * h * h / (a * a));
+  };
+  auto psi3 = [&](double kperp) {
+    const double b = kPi * kperp / L;
+    if (b < 1e-12) return kPi * R * R;
+    return 2.0 * kPi * R * bessel_j1(b * R) / b;
+  };
+  std::vector<double> dirs, wdir;  // (nd, 3), nd
+  if (d == 2) {
+    const int M = t.msig;
+    for (int p = 0; p < M; ++p) {
+      const double th = kPi * p / M;
+      dirs.insert(dirs.end(), {std::cos(th), std::sin(th), 0.0});
+      wdir.push_back(kPi / M);
+    }
+  } else {
+    std::vector<double> sig, w;
+    sphere_rule(3, 38, sig, w);
+    std::vector<int> used(38, 0);
+    for (int b = 0; b < 38; ++b) {
+      if (used[b]) continue;
+      for (int c = 0; c < 38; ++c) {
+        const double e = std::fabs(sig[3 * b] + sig[3 * c]) + std::fabs(sig[3 * b + 1] + sig[3 * c + 1]) +
+                         std::fabs(sig[3 * b + 2] + sig[3 * c + 2]);
+        if (e < 1e-12) {
+          used[b] = used[c] = 1;
+          break;
+        }
+      }
+      dirs.insert(dirs.end(), {sig[3 * b], sig[3 * b + 1], sig[3 * b + 2]});
+      wdir.push_back(w[b]);
+    }
+  }
+  const int nd = (int)wdir.size();
+  t.nbp = d == 2 ? nd / 2 : nd;
+  t.msig = 2 * t.nbp;
+  t.mrho = 1;
+  t.rho.assign(1, 0.0);
+  t.wrho.assign(1, 1.0);
+  t.cw.assign(1, 1.0);
+  t.sig.assign((size_t)3 * t.msig, 0.0);
+  t.wsig.assign(t.msig, 0.0);
+  t.bp_b.clear();
+  t.bp_bb.clear();
+  for (int p = 0; p < t.nbp; ++p) {
+    t.bp_b.push_back(2 * p);
+    t.bp_bb.push_back(2 * p + 1);
+    const double w = d == 2 ? b0 * wdir[p] : 0.5 * b0 * wdir[p];
+    t.wsig[2 * p] = t.wsig[2 * p + 1] = w;
+  }
+  t.phase.clear();
+  t.fw.clear();
+  t.nkk = 1;
+  t.filt.assign((size_t)t.nbp * n * 2, 0.0);
+  t.gloss.assign(n, 0.0);
+  for (int q = 0; q < n; ++q) {
+    double kc[3] = {0, 0, 0};
+    int rem = q;
+    for (int ax = d - 1; ax >= 0; --ax) {
+      kc[ax] = centred(rem % N);
+      rem /= N;
+    }
+    const double k2 = kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2];
+    double bll = 0.0;
+    for (int p = 0; p < t.nbp; ++p) {
+      double f1, f2;
+      if (d == 2) {
+        const double* e1 = &dirs[3 * p];
+        const double* e2 = &dirs[3 * (p + nd / 2)];
+        f1 = phi(e1[0] * kc[0] + e1[1] * kc[1]);
+        f2 = phi(e2[0] * kc[0] + e2[1] * kc[1]);
+        bll += 2.0 * b0 * wdir[p] * f1 * f2;  // directions p and p + M/2 give the same term
+      } else {
+        const double* e = &dirs[3 * p];
+        const double ke = e[0] * kc[0] + e[1] * kc[1] + e[2] * kc[2];
+        f1 = psi3(std::sqrt(std::max(k2 - ke * ke, 0.0)));
+        f2 = phi(ke);
+        bll += b0 * wdir[p] * f1 * f2;
+      }
+      const size_t o = ((size_t)p * n + q) * 2;
+      t.filt[o] = 0.5 * (f1 + f2);
+      t.filt[o + 1] = 0.5 * (f2 - f1);
+    }
+    t.gloss[q] = bll;
+  }
+  t.carleman = true;
 }
 
 HostTables build_tables(const blr_vgrid& vg) {
@@ -138,6 +315,11 @@ HostTables build_tables(const blr_vgrid& vg) {
   t.dv = 2.0 * vg.L / vg.n;
   t.mrho = vg.m_rho;
   t.msig = vg.m_sigma ? vg.m_sigma : (vg.d == 2 ? 8 : 38);
+  if (vg.flags & BLR_CARLEMAN) {
+    carleman_tables(t);
+    t.minv = moment_inverse(t);
+    return t;
+  }
   gauss_legendre(t.mrho, t.R, t.rho, t.wrho);
   t.cw.resize(t.mrho);
   for (int a = 0; a < t.mrho; ++a) t.cw[a] = t.wrho[a] * std::pow(t.rho[a], t.d - 1);
@@ -212,55 +394,7 @@ HostTables build_tables(const blr_vgrid& vg) {
     }
     t.gloss[q] = area * g;
   }
-  // (C C^T)^-1 for the moment projection; C rows dv^d {1, v_1..v_d, |v|^2}
-  const int m = d + 2;
-  std::vector<double> G(m * m, 0.0);
-  const double w = std::pow(t.dv, d);
-  for (int q = 0; q < t.n; ++q) {
-    double v[3] = {0, 0, 0};
-    int rem = q;
-    for (int ax = d - 1; ax >= 0; --ax) {
-      v[ax] = -t.L + (rem % N) * t.dv;
-      rem /= N;
-    }
-    double phi[5];
-    phi[0] = w;
-    double v2 = 0;
-    for (int ax = 0; ax < d; ++ax) {
-      phi[1 + ax] = w * v[ax];
-      v2 += v[ax] * v[ax];
-    }
-    phi[d + 1] = w * v2;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) G[i * m + j] += phi[i] * phi[j];
-  }
-  // Gauss-Jordan inverse (SPD, small)
-  std::vector<double> A(G), I(m * m, 0.0);
-  for (int i = 0; i < m; ++i) I[i * m + i] = 1.0;
-  for (int c = 0; c < m; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < m; ++r)
-      if (std::fabs(A[r * m + c]) > std::fabs(A[piv * m + c])) piv = r;
-    for (int j = 0; j < m; ++j) {
-      std::swap(A[c * m + j], A[piv * m + j]);
-      std::swap(I[c * m + j], I[piv * m + j]);
-    }
-    const double dgn = A[c * m + c];
-    require(std::fabs(dgn) > 0, "singular moment matrix", BLR_ERR_NUMERIC);
-    for (int j = 0; j < m; ++j) {
-      A[c * m + j] /= dgn;
-      I[c * m + j] /= dgn;
-    }
-    for (int r = 0; r < m; ++r) {
-      if (r == c) continue;
-      const double f = A[r * m + c];
-      for (int j = 0; j < m; ++j) {
-        A[r * m + j] -= f * A[c * m + j];
-        I[r * m + j] -= f * I[c * m + j];
-      }
-    }
-  }
-  t.minv = I;
+  t.minv = moment_inverse(t);
   return t;
 }
 

@@ -96,6 +96,15 @@ def test_pair_order_and_edge_cases(ctx):
     d = ctx.collision_pairs(vg, V, [(1, 1)])
     torch.cuda.synchronize()
     assert (c - d).abs().max().item() < 1e-14 * d.abs().max().item()
+    # a pair asked for twice (in either order) in one call: every row filled,
+    # repeats equal to the first occurrence, all equal to single-pair calls
+    for Vx, vgx in ((V, vg), (V.float(), vg)):
+        rep = ctx.collision_pairs(vgx, Vx, [(0, 2), (1, 1), (2, 0), (0, 2)])
+        one = ctx.collision_pairs(vgx, Vx, [(0, 2)])
+        torch.cuda.synchronize()
+        assert torch.equal(rep[0], rep[2]) and torch.equal(rep[0], rep[3])
+        tol = 1e-14 if Vx.dtype == torch.float64 else 1e-6
+        assert (rep[0] - one[0]).abs().max().item() <= tol * one[0].abs().max().item()
     # no pairs: no work, no error
     e = ctx.collision_pairs(vg, V, np.zeros((0, 2), dtype=np.int32))
     assert e.shape[0] == 0
