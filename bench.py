@@ -58,6 +58,8 @@ def parse():
                     help="skip the full-tensor reference step (N_x collisions per step)")
     ap.add_argument("--generic", action="store_true", help="force the multi-pass FFT path")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving traces")
+    ap.add_argument("--no-carleman", action="store_true",
+                    help="skip the Carleman-form measurement")
     ap.add_argument("--serve-count", type=int, default=8,
                     help="requests of the trace both paths run")
     ap.add_argument("--serve-steps", type=int, default=10,
@@ -191,6 +193,66 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
             "converged": sum(1 for c in comps if c.status == blr.BLR_OK),
             "failed": len(comps) - len(ok),
             "final_rank_range": [min(c.info.r for c in ok), max(c.info.r for c in ok)] if ok else None}
+
+
+def carleman_leg(args, blr, synth, torch, ctx, lib, spec, V, X, S, ini, nx, r, r_cap, dt):
+    """The same workload with the Carleman form of the operator (the paper's
+    fast algorithm for 3D hard spheres): the 55 pair collisions of the
+    rank-10 basis, and the adaptive step on them; per-kernel times; the
+    two forms are different discretisations of one operator (see the design
+    notes for how far apart they are on this basis)."""
+    dev = torch.device("cuda:0")
+    pairs = blr.upper_pairs(r)
+    P = len(pairs)
+    vgc = blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN)
+    V32 = torch.tensor(V, dtype=torch.float32, device=dev)
+    Q = torch.empty((P, V.shape[1]), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        ctx.collision_pairs(vgc, V32, pairs, out=Q)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.collision_pairs(vgc, V32, pairs, out=Q)
+    torch.cuda.synchronize()
+    coll_rate = reps * P / (time.perf_counter() - t0)
+    # per-kernel times of the collision batch
+    lib.blr_timing(ctx.h, 2)
+    lib.blr_timing(ctx.h, 1)
+    ctx.collision_pairs(vgc, V32, pairs, out=Q)
+    torch.cuda.synchronize()
+    lib.blr_timing(ctx.h, 0)
+    timers = read_timers(ctx)
+    # the adaptive step with Carleman collisions
+    Xd = torch.zeros((r_cap, nx), dtype=torch.float64, device=dev)
+    Sd = torch.zeros((r_cap, r_cap), dtype=torch.float64, device=dev)
+    Vd = torch.zeros((r_cap, V.shape[1]), dtype=torch.float64, device=dev)
+    Xd[:r] = torch.tensor(X.T, device=dev)
+    Sd[:r, :r] = torch.tensor(S, device=dev)
+    Vd[:r] = torch.tensor(V, device=dev)
+    fL = torch.tensor(ini["fL"], device=dev)
+    fR = torch.tensor(ini["fR"], device=dev)
+    pb = ctx.make_problem(vgc, nx, -30.0, 30.0, fL, fR)
+    st = ctx.make_state(Xd, Sd, Vd, r, seed=1)
+    sp = blr.StepParams(dt, 0.2, 1e-10, r, r_cap, blr.BLR_STEP_ADD | blr.BLR_STEP_DROP)
+    for _ in range(3):
+        ctx.dlr_step(pb, st, sp)
+    torch.cuda.synchronize()
+    wall, counted = [], 0
+    for _ in range(max(5, args.steps)):
+        ts = time.perf_counter()
+        info = ctx.dlr_step(pb, st, sp)
+        wall.append(time.perf_counter() - ts)
+        rr = info.r_in + info.r_added
+        counted += rr * (rr + 1) // 2
+    return {"form": "Carleman (constant kernel 4C for hard spheres, 19 directions of the "
+                    "Lebedev-38 rule, no radial quadrature)",
+            "collision_only_pair_evals_per_s": round(coll_rate, 1),
+            "step_pair_evals_per_s": round(counted / sum(wall), 1),
+            "step_ms_p50": round(1e3 * pct(wall, 0.5), 4),
+            "step_ms_p99": round(1e3 * pct(wall, 0.99), 4),
+            "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
+                        for t in sorted(timers, key=lambda t: -t["ms"])[:6]]}
 
 
 def serving_leg(args, blr, synth, torch, helper):
@@ -428,6 +490,12 @@ def main():
         torch.cuda.synchronize()
         plain = len(sub) / (time.perf_counter() - tp)
 
+    carleman = None
+    if args.mode == "step" and not args.no_carleman:
+        progress("carleman form")
+        carleman = carleman_leg(args, blr, synth, torch, ctx, lib, spec, V, X, S, ini, nx, r,
+                                r_cap, dt)
+
     serving = None
     if args.mode == "step" and not args.no_serve:
         serving = serving_leg(args, blr, synth, torch, ctx)
@@ -473,6 +541,7 @@ def main():
         "plain_fp64_pair_evals_per_s": round(plain, 2) if plain else None,
         "latency": latency,
         "full_tensor": full,
+        "carleman": carleman,
         "serving": serving,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                     for t in sorted(timers, key=lambda t: -t["ms"])[:8]],

@@ -493,29 +493,37 @@ template void fill<float>(hipStream_t, float*, long, float);
 template void fill<double>(hipStream_t, double*, long, double);
 template void fill<int>(hipStream_t, int*, long, int);
 
-// FP64 least-squares moment projection of each row of Q (one block per row):
-// m = C q, lambda = (C C^T)^-1 m, q <- q - C^T lambda, with C the rows
-// dv^d {1, v_1..v_d, |v|^2}.  Deterministic block reduction.
+// FP64 least-squares moment projection of rows of Q: m = C q,
+// lambda = (C C^T)^-1 m, q <- q - C^T lambda, with C the rows
+// dv^d {1, v_1..v_d, |v|^2}.  Two passes over (chunk, row) blocks: the moments
+// of each chunk, then every chunk's block sums its row's partial moments in a
+// fixed order and corrects its chunk (deterministic, no atomics).
+constexpr int kMomChunk = 2048;  // grid points per block
+
+__device__ inline double grid_coords(int e, const MomentArgs& ma, double (&v)[3]) {
+  v[0] = v[1] = v[2] = 0.0;
+  int rem = e;
+  for (int ax = ma.d - 1; ax >= 0; --ax) {
+    v[ax] = -ma.L + (rem % ma.N) * ma.dv;
+    rem /= ma.N;
+  }
+  return v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_conserve(T* Q, int n, MomentArgs ma) {
-  T* q = Q + (long)blockIdx.x * n;
-  const int d = ma.d, m = d + 2, N = ma.N;
+__global__ __launch_bounds__(256) void k_moment_part(const T* __restrict__ Q, int n, MomentArgs ma,
+                                                     double* __restrict__ part) {
+  const int b = blockIdx.x, row = blockIdx.y, nb = gridDim.x;
+  const T* q = Q + (long)row * n;
+  const int e0 = b * kMomChunk, e1 = min(n, e0 + kMomChunk);
   double acc[5] = {0, 0, 0, 0, 0};
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    double v[3] = {0, 0, 0};
-    int rem = e;
-    for (int ax = d - 1; ax >= 0; --ax) {
-      v[ax] = -ma.L + (rem % N) * ma.dv;
-      rem /= N;
-    }
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    double v[3];
+    const double v2 = grid_coords(e, ma, v);
     const double val = (double)q[e] * ma.w;
     acc[0] += val;
-    double v2 = 0;
-    for (int ax = 0; ax < d; ++ax) {
-      acc[1 + ax] += val * v[ax];
-      v2 += v[ax] * v[ax];
-    }
-    acc[d + 1] += val * v2;
+    for (int ax = 0; ax < ma.d; ++ax) acc[1 + ax] += val * v[ax];
+    acc[ma.d + 1] += val * v2;
   }
   __shared__ double red[5][256];
   for (int i = 0; i < 5; ++i) red[i][threadIdx.x] = acc[i];
@@ -525,30 +533,42 @@ __global__ __launch_bounds__(256) void k_conserve(T* Q, int n, MomentArgs ma) {
       for (int i = 0; i < 5; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + st];
     __syncthreads();
   }
-  double lam[5] = {0, 0, 0, 0, 0};
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < m; ++j) lam[i] += ma.minv[i * m + j] * red[j][0];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    double v[3] = {0, 0, 0};
-    int rem = e;
-    for (int ax = d - 1; ax >= 0; --ax) {
-      v[ax] = -ma.L + (rem % N) * ma.dv;
-      rem /= N;
+  if (threadIdx.x < 5) part[((long)row * nb + b) * 5 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_moment_apply(T* __restrict__ Q, int n, MomentArgs ma,
+                                                      const double* __restrict__ part) {
+  const int b = blockIdx.x, row = blockIdx.y, nb = gridDim.x;
+  const int m = ma.d + 2;
+  __shared__ double lam[5];
+  if (threadIdx.x == 0) {
+    double mo[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < nb; ++k)
+      for (int i = 0; i < 5; ++i) mo[i] += part[((long)row * nb + k) * 5 + i];
+    for (int i = 0; i < 5; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < m && i < m; ++j) s += ma.minv[i * m + j] * mo[j];
+      lam[i] = i < m ? s : 0.0;
     }
+  }
+  __syncthreads();
+  T* q = Q + (long)row * n;
+  const int e0 = b * kMomChunk, e1 = min(n, e0 + kMomChunk);
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    double v[3];
+    const double v2 = grid_coords(e, ma, v);
     double c = lam[0];
-    double v2 = 0;
-    for (int ax = 0; ax < d; ++ax) {
-      c += lam[1 + ax] * v[ax];
-      v2 += v[ax] * v[ax];
-    }
-    c += lam[d + 1] * v2;
+    for (int ax = 0; ax < ma.d; ++ax) c += lam[1 + ax] * v[ax];
+    c += lam[ma.d + 1] * v2;
     q[e] = (T)((double)q[e] - ma.w * c);
   }
 }
 
 template <typename T>
-void conserve_rows(hipStream_t s, const HostTables& h, T* Q, int rows) {
+void conserve_rows(blr_ctx ctx, const HostTables& h, T* Q, int rows) {
   if (rows <= 0) return;
+  hipStream_t s = ctx->stream;
   MomentArgs ma{};
   ma.L = h.L;
   ma.dv = h.dv;
@@ -556,12 +576,16 @@ void conserve_rows(hipStream_t s, const HostTables& h, T* Q, int rows) {
   for (size_t i = 0; i < h.minv.size() && i < 25; ++i) ma.minv[i] = h.minv[i];
   ma.N = h.N;
   ma.d = h.d;
-  TimedScope ts(s, "conserve", 2.0 * rows * h.n * sizeof(T));
-  hipLaunchKernelGGL(k_conserve<T>, dim3(rows), dim3(256), 0, s, Q, h.n, ma);
+  const int nb = (h.n + kMomChunk - 1) / kMomChunk;
+  double* part = (double*)ctx->buf("mom.part", (size_t)rows * nb * 5 * sizeof(double));
+  TimedScope ts(s, "conserve", 3.0 * rows * h.n * sizeof(T));
+  hipLaunchKernelGGL(k_moment_part<T>, dim3(nb, rows), dim3(256), 0, s, Q, h.n, ma, part);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_moment_apply<T>, dim3(nb, rows), dim3(256), 0, s, Q, h.n, ma, part);
   BLR_CHECK_LAUNCH();
 }
-template void conserve_rows<float>(hipStream_t, const HostTables&, float*, int);
-template void conserve_rows<double>(hipStream_t, const HostTables&, double*, int);
+template void conserve_rows<float>(blr_ctx, const HostTables&, float*, int);
+template void conserve_rows<double>(blr_ctx, const HostTables&, double*, int);
 
 // ------------------------------------------------------------ planning
 // Tiles of the pair products: compact basis indices grouped by G; one tile per
@@ -856,9 +880,9 @@ static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const
       });
       if (!(flags & BLR_NO_CONSERVE)) {
         if (pl.dup.empty())
-          conserve_rows<T>(ctx->stream, h, Q, npairs);
+          conserve_rows<T>(ctx, h, Q, npairs);
         else
-          for (int p : prow) conserve_rows<T>(ctx->stream, h, Q + (size_t)p * h.n, 1);
+          for (int p : prow) conserve_rows<T>(ctx, h, Q + (size_t)p * h.n, 1);
       }
     }
     for (const auto& dp : pl.dup)
@@ -866,7 +890,7 @@ static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const
                              (size_t)h.n * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     return;
   }
-  if (!(flags & BLR_NO_CONSERVE)) conserve_rows<T>(ctx->stream, h, Q, npairs);
+  if (!(flags & BLR_NO_CONSERVE)) conserve_rows<T>(ctx, h, Q, npairs);
 }
 
 void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,

@@ -1475,17 +1475,16 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
       try {
         step_enqueue(ctx, pb, st, sp, h, add, at, o, false);
       } catch (const Error&) {
-        // A device-wide operation of another host thread (a device
-        // synchronisation, a free) invalidates the recording; the step then
-        // runs directly.  Any other error is the step's own.
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        (void)hipStreamIsCapturing(ctx->cap_stream, &cs);
+        // The recording failed: a device-wide operation of another host
+        // thread (a device synchronisation, an allocation or free) can
+        // invalidate it or make a recorded launch report an error.  The step
+        // then runs directly, the same kernels in the same order, where an
+        // error of the step's own is reported as usual.
         (void)hipStreamEndCapture(ctx->cap_stream, &graph);
         if (graph) (void)hipGraphDestroy(graph);
         ctx->stream = s;
         ctx->capturing = false;
         (void)hipGetLastError();
-        if (cs != hipStreamCaptureStatusInvalidated) throw;
         eager();
         g.gen = ctx->buf_gen;
         return;
