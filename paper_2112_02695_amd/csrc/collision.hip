@@ -707,7 +707,10 @@ struct Generic {
     const long nfields = (long)rb * h.nbp;
     const long batch = std::min<long>(nfields, 512);
     g_stage = "carl.filter";
-    for (long f0 = 0; f0 < nfields; f0 += batch) {
+    bool fused = false;
+    if constexpr (sizeof(T) == 4 && D == 3)
+      if (!pl.generic_only) fused = carleman_filter_f32(ctx, tb, (const float2*)Vh, (float*)Sh, rb);
+    for (long f0 = 0; !fused && f0 < nfields; f0 += batch) {
       const long nb = std::min(batch, nfields - f0);
       transform<T, N, D, +1>(s, LdFilter<T>{Vh, (const T2*)tb.filt, n, h.nbp, f0},
                              StShiftSplit<T>{Sh, tb.bp_b, tb.bp_bb, n, 1, h.nbp, h.msig, f0}, tmp,
@@ -861,6 +864,7 @@ static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const
     // the baseline schedule: every pair on its own, shifts recomputed per pair
     for (int p = 0; p < npairs; ++p) {
       PairPlan pl = make_plan(r, pairs + 2 * p, 1);
+      pl.generic_only = (flags & BLR_GENERIC_FFT) != 0;
       std::vector<int> prow{p};
       dispatch_size<T>(h.d, h.N, [&](auto Nc, auto Dc) {
         Generic<T, decltype(Nc)::value, decltype(Dc)::value>::run(ctx, tb, V, pl, prow, Q);
@@ -868,6 +872,7 @@ static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const
     }
   } else {
     PairPlan pl = make_plan(r, pairs, npairs);
+    pl.generic_only = (flags & BLR_GENERIC_FFT) != 0;
     const std::vector<int>& prow = pl.row;
     bool done = false;
     if constexpr (sizeof(T) == 4) {

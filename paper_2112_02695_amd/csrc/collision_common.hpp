@@ -56,6 +56,7 @@ struct PairPlan {
   std::vector<int> li, lj;   // per distinct pair, compact indices (li <= lj)
   std::vector<int> row;      // per distinct pair, the first output row asking for it
   std::vector<std::pair<int, int>> dup;  // (output row, row it repeats) for repeated pairs
+  bool generic_only = false;             // BLR_GENERIC_FFT: no fused kernels
 };
 
 std::vector<ReduceTile> plan_tiles(int rb, const std::vector<int>& li, const std::vector<int>& lj,
@@ -66,6 +67,7 @@ void timed_begin(const std::string& name, double bytes, hipStream_t s);
 void timed_end(hipStream_t s);
 bool fast_collision_f32(blr_ctx ctx, const DevTables& tb, const float* V, const PairPlan& pl,
                         const std::vector<int>& prow, float* Q, bool conserve);
+bool carleman_filter_f32(blr_ctx ctx, const DevTables& tb, const float2* Vh, float* Sh, int rb);
 void basis_spectra_f32(blr_ctx ctx, const DevTables& tb, const float* V, const PairPlan& pl,
                        float2** Vh, float** Vp, float** Lam);
 

@@ -125,6 +125,55 @@ __global__ __launch_bounds__(N * N) void k_shift_fused(const float2* __restrict_
   }
 }
 
+// Carleman form: the two filtered fields of one basis function and one
+// direction pair per workgroup iteration.  Same transform and stores as
+// k_shift_fused; the load multiplies the spectrum by the complex filter
+// c_p(k) (table, DFT order) instead of the separable phase factor.
+template <int N>
+__global__ __launch_bounds__(N * N) void k_filter_fused(const float2* __restrict__ vh,
+                                                        const float2* __restrict__ filt,
+                                                        float* __restrict__ sh,
+                                                        const int* __restrict__ bp_b,
+                                                        const int* __restrict__ bp_bb, int nbp,
+                                                        int msig, long nfields) {
+  __shared__ float L[Geo<N>::LDS];
+  constexpr int n = Geo<N>::n;
+  const int t = threadIdx.x;
+  const int u = t / N, w = t % N;
+  const int nf = (int)nfields;  // < 2^31 (checked by the host)
+  for (int f = blockIdx.x; f < nf; f += gridDim.x) {
+    const int p = f % nbp;
+    const int ib = f / nbp;
+    const float4* src = reinterpret_cast<const float4*>(vh + (long)ib * n + (u * N + w) * N);
+    const float4* cf = reinterpret_cast<const float4*>(filt + (long)p * n + (u * N + w) * N);
+    float re[N], im[N];
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const float4 v = src[j];
+      const float4 c = cf[j];
+      re[2 * j] = v.x * c.x - v.y * c.y;
+      im[2 * j] = v.x * c.y + v.y * c.x;
+      re[2 * j + 1] = v.z * c.z - v.w * c.w;
+      im[2 * j + 1] = v.z * c.w + v.w * c.z;
+    }
+    fft::dft<float, N, +1>(re, im);
+    exchange<N, 2, 1>(re, L, u, w);
+    exchange<N, 2, 1>(im, L, u, w);
+    fft::dft<float, N, +1>(re, im);
+    exchange<N, 1, 0>(re, L, u, w);
+    exchange<N, 1, 0>(im, L, u, w);
+    fft::dft<float, N, +1>(re, im);
+    const long base = ((long)ib * msig) * (long)n + t;
+    float* s1 = sh + base + (long)bp_b[p] * n;
+    float* s2 = sh + base + (long)bp_bb[p] * n;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      s1[j * N * N] = re[j] - im[j];
+      s2[j * N * N] = re[j] + im[j];
+    }
+  }
+}
+
 // ------------------------------------------------------------ sigma sums
 // All radial nodes in one launch (blockIdx.y = a); one thread per point.
 template <int G, bool DIAG>
@@ -627,6 +676,33 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   hipLaunchKernelGGL(k_final_fused<N>, dim3(P), dim3(N * N), 0, s, Wsp, Vp, Lam, didx, Q, P, ng, fa);
   BLR_CHECK_LAUNCH();
   timed_end(s);
+}
+
+// Carleman form, 3D FP32: the filtered fields of rb basis functions (the
+// generic path's filter transforms in one fused kernel).  False when the grid
+// has no fused kernel.
+bool carleman_filter_f32(blr_ctx ctx, const DevTables& tb, const float2* Vh, float* Sh, int rb) {
+  using namespace fastk;
+  const HostTables& h = tb.h;
+  if (h.d != 3 || !h.carleman || (h.N != 16 && h.N != 24 && h.N != 32)) return false;
+  hipStream_t s = ctx->stream;
+  const long nfields = (long)rb * h.nbp;
+  require(nfields < (1L << 31), "carleman filters: too many fields");
+  const long grid = std::min<long>(nfields, 2048);
+  auto launch = [&](auto Nc) {
+    constexpr int N = decltype(Nc)::value;
+    timed_begin("carl.filter_fused", (double)nfields * Geo<N>::n * 4.0 * sizeof(float), s);
+    hipLaunchKernelGGL(k_filter_fused<N>, dim3((unsigned)grid), dim3(N * N), 0, s, Vh,
+                       (const float2*)tb.filt, Sh, tb.bp_b, tb.bp_bb, h.nbp, h.msig, nfields);
+    BLR_CHECK_LAUNCH();
+    timed_end(s);
+  };
+  switch (h.N) {
+    case 16: launch(std::integral_constant<int, 16>{}); break;
+    case 24: launch(std::integral_constant<int, 24>{}); break;
+    case 32: launch(std::integral_constant<int, 32>{}); break;
+  }
+  return true;
 }
 
 // Basis spectra and loss fields come from the generic kernels (collision.hip).

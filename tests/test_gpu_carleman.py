@@ -133,3 +133,21 @@ def test_step_with_carleman_collisions_matches_oracle(ctx, d, N, nx, r, M):
     print("carleman step f rel err", e, flush=True)
     assert e < 1e-12
     assert abs(info.err - err) < 1e-10 * err
+
+
+@pytest.mark.parametrize("n", [16, 24, 32])
+def test_fused_filters_equal_generic(ctx, n):
+    """3D FP32: the fused filter kernel (one workgroup per field, the whole
+    transform in LDS) against the generic line passes (BLR_GENERIC_FFT)."""
+    spec = _spec(3, n, 38)
+    V = torch.tensor(synth.smooth_basis(4, spec, seed=21), dtype=torch.float32, device="cuda")
+    pairs = blr.upper_pairs(4)
+    a = ctx.collision_pairs(blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN), V, pairs)
+    b = ctx.collision_pairs(blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN | blr.BLR_GENERIC_FFT), V,
+                            pairs)
+    a, b = a.double().cpu().numpy(), b.double().cpu().numpy()
+    ref, gain = ca.q_pairs(V.double().cpu().numpy(), pairs, ca.setup_from_spec(spec))
+    for q in (a, b):
+        rel = np.linalg.norm(q - ref, axis=1) / np.linalg.norm(gain, axis=1)
+        assert rel.max() < 1e-5
+    assert np.abs(a - b).max() <= 1e-5 * np.abs(gain).max()
