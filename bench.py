@@ -60,6 +60,11 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving traces")
     ap.add_argument("--no-carleman", action="store_true",
                     help="skip the Carleman-form measurement")
+    ap.add_argument("--paper-shock", action="store_true",
+                    help="also solve the paper's Mach-1.4 shock shape (2D velocity, 32^2 on "
+                         "[-13.11, 13.11]^2, N_x = 1000) to steady state by the low-rank and the "
+                         "full-tensor method (about two minutes)")
+    ap.add_argument("--paper-tol", type=float, default=1e-6)
     ap.add_argument("--serve-count", type=int, default=8,
                     help="requests of the trace both paths run")
     ap.add_argument("--serve-steps", type=int, default=10,
@@ -253,6 +258,104 @@ def carleman_leg(args, blr, synth, torch, ctx, lib, spec, V, X, S, ini, nx, r, r
             "step_ms_p99": round(1e3 * pct(wall, 0.99), 4),
             "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                         for t in sorted(timers, key=lambda t: -t["ms"])[:6]]}
+
+
+def paper_shock_leg(args, blr, synth, torch, ctx):
+    """The normal shock of Sec. 5.2 at the paper's Mach-1.4 shape: d = 2,
+    Maxwell molecules B = 1/(2 pi) with the Carleman form (8 directions),
+    N_v = 32^2 on [-13.11, 13.11]^2, N_x = 1000 on [-30, 30], the tanh
+    initial profile (alpha = 0.5) without perturbation, dt = dx / (2 L_v).
+    Both methods run to err <= tol (err_ada for the low-rank method, adaptive
+    with c = 0.2; err_full for the full tensor); the macroscopic profiles of
+    the two steady states are compared, and the density with the Mott-Smith
+    logistic profile of Sec. 4 (alpha from the same pair operator)."""
+    import numpy as np
+    mach, nx, N, L = 1.4, 1000, 32, 13.11
+    dev = torch.device("cuda:0")
+    spec = synth.VGridSpec(d=2, n=N, L=L, gamma=0.0, C=1 / (2 * math.pi), m_rho=1, m_sigma=8)
+    ini = synth.shock_initial(mach, spec, nx, -30.0, 30.0, pert=0.0, pert_rank=0)
+    dx, dv = 60.0 / nx, 2 * L / N
+    dt = 0.5 * dx / L
+    vg = blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN)
+    fL = torch.tensor(ini["fL"], device=dev)
+    fR = torch.tensor(ini["fR"], device=dev)
+    pb = ctx.make_problem(vg, nx, -30.0, 30.0, fL, fR)
+    v = synth.vgrid_points(2, N, L).reshape(2, -1)
+
+    def macro(F):
+        w = dv * dv
+        rho = F.sum(axis=1) * w
+        u = (F * v[0]).sum(axis=1) * w / rho
+        E = 0.5 * (F * (v ** 2).sum(axis=0)).sum(axis=1) * w
+        T = (2 * E / rho - u * u) / 2
+        return rho, u, T
+
+    # low-rank steady solve (one library call)
+    r0, rc = 4, 32
+    X, S, V = synth.lowrank_state_sketch(ini["f0"], r0, dx, dv * dv, seed=1)
+    Xd = torch.zeros((rc, nx), dtype=torch.float64, device=dev)
+    Sd = torch.zeros((rc, rc), dtype=torch.float64, device=dev)
+    Vd = torch.zeros((rc, N * N), dtype=torch.float64, device=dev)
+    Xd[:r0] = torch.tensor(X.T, device=dev)
+    Sd[:r0, :r0] = torch.tensor(S, device=dev)
+    Vd[:r0] = torch.tensor(V, device=dev)
+    st = ctx.make_state(Xd, Sd, Vd, r0)
+    torch.cuda.synchronize()
+    sp = blr.SolveParams(blr.StepParams(dt, 0.2, 1e-10, 1, 30,
+                                        blr.BLR_STEP_ADD | blr.BLR_STEP_DROP), args.paper_tol,
+                         400000)
+    progress(f"paper shock: low-rank solve to {args.paper_tol}")
+    t0 = time.perf_counter()
+    li = ctx.steady_solve(pb, st, sp, allow_unconverged=True)
+    t_lr = time.perf_counter() - t0
+    r = st.r
+    F_lr = (Xd[:r].cpu().numpy().T @ Sd[:r, :r].cpu().numpy()) @ Vd[:r].cpu().numpy()
+    # full-tensor solve (one library call per step)
+    progress(f"paper shock: full-tensor solve to {args.paper_tol}")
+    F = torch.tensor(ini["f0"], device=dev)
+    t0 = time.perf_counter()
+    steps_full, e = 0, float("inf")
+    while e > args.paper_tol and steps_full < 400000 and time.perf_counter() - t0 < 600:
+        e = ctx.full_step(pb, F, dt, blr.BLR_FP32)
+        steps_full += 1
+    t_full = time.perf_counter() - t0
+    F_full = F.cpu().numpy()
+    m_lr, m_full = macro(F_lr), macro(F_full)
+    prof = {nm: float(np.abs(a - b).max() / np.abs(b).max())
+            for nm, a, b in zip(("rho", "u", "T"), m_lr, m_full)}
+    # Mott-Smith: alpha from the pair operator on (f_L, f_R), logistic profile
+    # centred where the low-rank density crosses the mean of the end states
+    Vb = torch.stack([fL, fR])
+    q = ctx.collision_pairs(blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN | blr.BLR_NO_CONSERVE),
+                            Vb, [(0, 1)]).cpu().numpy()[0]
+    alpha = float(2 * dv * dv * np.dot(v[0] ** 2, q))
+    (rl, ul, Tl), (rr, ur, Tr) = ini["states"]
+    beta = alpha / (1 * rl * ul * (Tl - Tr))
+    x = ini["x"]
+    rho = m_lr[0]
+    mid = 0.5 * (rl + rr)
+    kx = int(np.argmax(rho >= mid))
+    x0 = x[kx - 1] + (mid - rho[kx - 1]) * (x[kx] - x[kx - 1]) / (rho[kx] - rho[kx - 1])
+    a = 1.0 / (np.exp(beta * (x - x0)) + 1.0)
+    rho_ms = a * rl + (1 - a) * rr
+    # thickness: max density slope of each profile, over the jump
+    thick = lambda rr_: (rr - rl) / np.max(np.gradient(rr_, x))
+    return {"shape": "Mach 1.4, d=2 Maxwell molecules (Carleman form, 8 directions), N_v=32^2 "
+                     "on [-13.11,13.11]^2, N_x=1000 on [-30,30], dt=dx/(2 L_v), tanh initial "
+                     "profile, FP32 collisions",
+            "tol": args.paper_tol,
+            "low_rank": {"steps": int(li.steps), "converged": int(li.converged),
+                         "err_ada": li.err_ada, "rank": int(li.r), "seconds": round(t_lr, 2),
+                         "ms_per_step": round(1e3 * t_lr / max(1, li.steps), 4)},
+            "full_tensor": {"steps": steps_full, "converged": int(e <= args.paper_tol),
+                            "err_full": e, "seconds": round(t_full, 2),
+                            "ms_per_step": round(1e3 * t_full / max(1, steps_full), 4)},
+            "time_ratio_full_over_low_rank": round(t_full / t_lr, 2),
+            "profile_rel_diff_low_rank_vs_full": prof,
+            "mott_smith": {"alpha": alpha, "beta": beta,
+                           "density_max_rel_dev": float(np.abs(rho - rho_ms).max() / (rr - rl)),
+                           "thickness_numerical": float(thick(rho)),
+                           "thickness_mott_smith": float(thick(rho_ms))}}
 
 
 def serving_leg(args, blr, synth, torch, helper):
@@ -496,6 +599,10 @@ def main():
         carleman = carleman_leg(args, blr, synth, torch, ctx, lib, spec, V, X, S, ini, nx, r,
                                 r_cap, dt)
 
+    paper = None
+    if args.paper_shock:
+        paper = paper_shock_leg(args, blr, synth, torch, ctx)
+
     serving = None
     if args.mode == "step" and not args.no_serve:
         serving = serving_leg(args, blr, synth, torch, ctx)
@@ -542,6 +649,7 @@ def main():
         "latency": latency,
         "full_tensor": full,
         "carleman": carleman,
+        "paper_shock": paper,
         "serving": serving,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                     for t in sorted(timers, key=lambda t: -t["ms"])[:8]],
