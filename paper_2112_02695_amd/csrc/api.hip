@@ -173,12 +173,17 @@ DevTables::~DevTables() {
     if (p) (void)hipFree(p);
 }
 
+// Copies on the context's own stream (never the legacy default stream, which
+// another host thread's graph recording would forbid), then waits for it.
 template <typename T>
-static void* upload_vec(DevTables& t, const std::vector<T>& v) {
+static void* upload_vec(DevTables& t, const std::vector<T>& v, hipStream_t s) {
   void* p = nullptr;
   BLR_HIP(hipMalloc(&p, std::max<size_t>(v.size() * sizeof(T), 16)));
   t.owned.push_back(p);
-  if (!v.empty()) BLR_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (!v.empty()) {
+    BLR_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    BLR_HIP(hipStreamSynchronize(s));
+  }
   return p;
 }
 
@@ -201,22 +206,22 @@ const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
   std::vector<double> wbp(h.nbp);
   for (int p = 0; p < h.nbp; ++p) wbp[p] = h.wsig[h.bp_b[p]];
   if (prec == BLR_FP32) {
-    t->phase = upload_vec(*t, cast_vec<float>(h.phase));
-    t->fw = upload_vec(*t, cast_vec<float>(h.fw));
-    t->gloss = upload_vec(*t, cast_vec<float>(h.gloss));
-    t->wbp = upload_vec(*t, cast_vec<float>(wbp));
+    t->phase = upload_vec(*t, cast_vec<float>(h.phase), ctx->stream);
+    t->fw = upload_vec(*t, cast_vec<float>(h.fw), ctx->stream);
+    t->gloss = upload_vec(*t, cast_vec<float>(h.gloss), ctx->stream);
+    t->wbp = upload_vec(*t, cast_vec<float>(wbp), ctx->stream);
   } else {
-    t->phase = upload_vec(*t, h.phase);
-    t->fw = upload_vec(*t, h.fw);
-    t->gloss = upload_vec(*t, h.gloss);
-    t->wbp = upload_vec(*t, wbp);
+    t->phase = upload_vec(*t, h.phase, ctx->stream);
+    t->fw = upload_vec(*t, h.fw, ctx->stream);
+    t->gloss = upload_vec(*t, h.gloss, ctx->stream);
+    t->wbp = upload_vec(*t, wbp, ctx->stream);
   }
   if (h.carleman) {
-    if (prec == BLR_FP32) t->filt = upload_vec(*t, cast_vec<float>(h.filt));
-    else t->filt = upload_vec(*t, h.filt);
+    if (prec == BLR_FP32) t->filt = upload_vec(*t, cast_vec<float>(h.filt), ctx->stream);
+    else t->filt = upload_vec(*t, h.filt, ctx->stream);
   }
-  t->bp_b = (int*)upload_vec(*t, h.bp_b);
-  t->bp_bb = (int*)upload_vec(*t, h.bp_bb);
+  t->bp_b = (int*)upload_vec(*t, h.bp_b, ctx->stream);
+  t->bp_bb = (int*)upload_vec(*t, h.bp_bb, ctx->stream);
   auto& slot = ctx->tables[key];
   slot = std::move(t);
   return *slot;

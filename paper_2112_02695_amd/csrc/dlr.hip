@@ -310,28 +310,7 @@ __global__ void k_scale_copy(const double* __restrict__ in, long count, double s
   if (e < count) out[e] = scale * in[e];
 }
 
-__global__ void k_to_f32(const double* __restrict__ in, long count, float* __restrict__ out) {
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e < count) out[e] = (float)in[e];
-}
 
-// boundary rows F_b^T (column-major n x 2): left = f_L on v1 > 0 else K(x_0).V,
-// right = f_R on v1 < 0 else K(x_last).V
-__global__ void k_fb(const double* __restrict__ K, const double* __restrict__ V, int r, int nx,
-                     const double* __restrict__ fL, const double* __restrict__ fR, VGeo g,
-                     double* __restrict__ Fb) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.n) return;
-  double a = 0.0, b = 0.0;
-  for (int l = 0; l < r; ++l) {
-    const double v = V[(long)l * g.n + q];
-    a += K[(long)l * nx] * v;
-    b += K[(long)l * nx + nx - 1] * v;
-  }
-  const double v1 = g.v1(q);
-  Fb[q] = v1 > 0 ? fL[q] : a;
-  Fb[g.n + q] = v1 < 0 ? fR[q] : b;
-}
 
 // small dense algebra (one block)
 // S2 = S1 + dt (Dp Ap^T + Dm Am^T - T C^T);  dS = S2 - S1
@@ -429,13 +408,114 @@ __global__ void k_copy_S(const double* src, int lds_src, int r, double* dst, int
   dst[(t / r) * lds_dst + t % r] = src[(t / r) * lds_src + t % r];
 }
 
-// out (rk x rk, row-major) = [[S, 0], [0, 0]] with S r x r (leading dim r)
-__global__ void k_pad_S(const double* S, int r, int rk, double* out) {
-  for (int t = threadIdx.x; t < rk * rk; t += blockDim.x) {
-    const int i = t / rk, j = t % rk;
-    out[t] = (i < r && j < r) ? S[i * r + j] : 0.0;
+// Start of a step: S (leading dim lds) -> Sw (leading dim ldw), clear the
+// failure flags, and (Fb != 0)
+// the boundary rows F_b of the basis augmentation: with K_l = sum_i X_i S_il
+// at the two boundary cells, F_b[0] = f_L where v_1 > 0 else K(x_0).V and
+// F_b[1] = f_R where v_1 < 0 else K(x_{nx-1}).V (the sums in the order of
+// k_xmul).
+__global__ __launch_bounds__(256) void k_add_begin(const double* __restrict__ X, int r, int nx,
+                                                   const double* __restrict__ S, int lds,
+                                                   double* __restrict__ Sw, int ldw,
+                                                   int* __restrict__ flag,
+                                                   const double* __restrict__ V,
+                                                   const double* __restrict__ fL,
+                                                   const double* __restrict__ fR, VGeo g,
+                                                   double* __restrict__ Fb) {
+  __shared__ double kb[2][64];
+  const int t = threadIdx.x;
+  if (blockIdx.x == 0) {
+    for (int e = t; e < r * r; e += blockDim.x) Sw[(e / r) * ldw + e % r] = S[(e / r) * lds + e % r];
+    if (t < 2) flag[t] = 0;
+  }
+  if (!Fb) return;
+  if (t < 2 * r) {
+    const int side = t / r, l = t % r;
+    const int x = side ? nx - 1 : 0;
+    double s = 0.0;
+    for (int i = 0; i < r; ++i) s += X[(long)i * nx + x] * S[i * lds + l];
+    kb[side][l] = s;
+  }
+  __syncthreads();
+  const int q = blockIdx.x * blockDim.x + t;
+  if (q >= g.n) return;
+  double a = 0.0, b = 0.0;
+  for (int l = 0; l < r; ++l) {
+    const double v = V[(long)l * g.n + q];
+    a += kb[0][l] * v;
+    b += kb[1][l] * v;
+  }
+  const double v1 = g.v1(q);
+  Fb[q] = v1 > 0 ? fL[q] : a;
+  Fb[g.n + q] = v1 < 0 ? fR[q] : b;
+}
+
+// The added basis rows Vb_i = sum_l Ub[l][i] Fb_l (i < rb, k_rows_comb with
+// scale 1), zero rows r .. r+rb-1 of X, and the zero-padded S^ (rk = r + rb).
+__global__ __launch_bounds__(256) void k_add_rows(const double* __restrict__ Fb, long n,
+                                                  const double* __restrict__ Ub, int rb,
+                                                  double* __restrict__ Vb, double* __restrict__ Xz,
+                                                  long nxz, const double* __restrict__ Sw, int r,
+                                                  double* __restrict__ Shat) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (e < n) {
+    double s = 0.0;
+    for (int l = 0; l < 2; ++l) s += Ub[l * 2 + i] * Fb[(long)l * n + e];
+    Vb[(long)i * n + e] = 1.0 * s;
+  }
+  if (i == 0) {
+    for (long z = e; z < nxz; z += (long)gridDim.x * blockDim.x) Xz[z] = 0.0;
+    if (blockIdx.x == 0) {
+      const int rk = r + rb;
+      for (int t = threadIdx.x; t < rk * rk; t += blockDim.x) {
+        const int a = t / rk, b = t % rk;
+        Shat[t] = (a < r && b < r) ? Sw[a * r + b] : 0.0;
+      }
+    }
   }
 }
+
+// V (FP64) -> V32, and (src != 0) S^ -> Sw by the first block.
+__global__ void k_to_f32_copy_S(const double* __restrict__ in, long count, float* __restrict__ out,
+                                const double* __restrict__ src, int rs, double* __restrict__ dst,
+                                int lds) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < count) out[e] = (float)in[e];
+  if (src && blockIdx.x == 0)
+    for (int t = threadIdx.x; t < rs * rs; t += blockDim.x)
+      dst[(t / rs) * lds + t % rs] = src[(t / rs) * rs + t % rs];
+}
+
+// Commit after the drop decision: X_i = sum_l U[l][i] X1_l and V_i =
+// sum_l Wm[l][i] V1_l for i < keep (k_rows_comb), and S = diag(sig) (k_diag),
+// in one launch: grid.y = keep, x blocks over max(nx, n).
+__global__ __launch_bounds__(256) void k_commit(const double* __restrict__ X1, int r, long nx,
+                                                const double* __restrict__ U,
+                                                const double* __restrict__ V1, long n,
+                                                const double* __restrict__ Wm, int keep,
+                                                double* __restrict__ X, double* __restrict__ V,
+                                                const double* __restrict__ sig,
+                                                double* __restrict__ S, int lds) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (e < nx) {
+    double s = 0.0;
+    for (int l = 0; l < r; ++l) s += U[l * r + i] * X1[(long)l * nx + e];
+    X[(long)i * nx + e] = 1.0 * s;
+  }
+  if (e < n) {
+    double s = 0.0;
+    for (int l = 0; l < r; ++l) s += Wm[l * r + i] * V1[(long)l * n + e];
+    V[(long)i * n + e] = 1.0 * s;
+  }
+  if (blockIdx.x == 0 && i == 0)
+    for (int t = threadIdx.x; t < keep * keep; t += blockDim.x) {
+      const int a = t / keep, b = t % keep;
+      S[a * lds + b] = (a == b) ? sig[a] : 0.0;
+    }
+}
+
 
 // out = A B^T for r x r row-major A, B
 __global__ void k_mul_bt(const double* A, const double* B, int r, double* out) {
@@ -1062,9 +1142,6 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     Vw = w.get("Vw", (size_t)rc * n);
     BLR_HIP(hipMemcpyAsync(Vw, st->V, (size_t)r * n * 8, hipMemcpyDeviceToDevice, s));
   }
-  hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(r * r, 256)), dim3(256), 0, s, st->S, rc, r, Sw, r);
-  BLR_CHECK_LAUNCH();
-
   double* ginL = w.get("ginL", 64);
   double* ginR = w.get("ginR", 64);
   double* MoL = w.get("MoL", 64 * 64);
@@ -1072,7 +1149,14 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   double* gh = w.get("ghost", 128);
   double* K = w.get("K", (size_t)rc * nx);
   int* flag = (int*)ctx->buf("dlr.flag", 256);  // [0] projection failed, [1] Cholesky QR failed
-  fill<int>(s, flag, 2, 0);
+  // S -> Sw, flags cleared, and the boundary rows F_b of the augmentation
+  double* Fb = add ? w.get("Fb", (size_t)2 * n) : nullptr;
+  hipLaunchKernelGGL(dk::k_add_begin, dim3(add ? blocks(n, 256) : 1), dim3(256), 0, s, Xw, r, nx,
+                     st->S, rc, Sw, r, flag, Vw, pb->f_left, pb->f_right, w.g, Fb);
+  BLR_CHECK_LAUNCH();
+  // S^ still to be copied into Sw (projection variant), done with the FP32 cast
+  const double* pend_S = nullptr;
+  int pend_r = 0;
   const double* sbd = nullptr;
   // QR of sqrt(w) M with Q scaled back by 1/sqrt(w)
   auto qr = [&](const double* M, long ld, long rows, int rr, double* Qo, double* Ro, const char* tag,
@@ -1090,33 +1174,22 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   // new rows are U_b[:, :rb]^T F_b.  X gains zero rows: with S^ = [[S, 0],
   // [0, 0]] the product X^ S^ (all the step reads of X^n) is unchanged.
   if (add) {
-    hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nx, 256)), dim3(256), 0, s, Xw, r, nx, Sw, r,
-                       K);
-    BLR_CHECK_LAUNCH();
-    double* Fb = w.get("Fb", (size_t)2 * n);
-    hipLaunchKernelGGL(dk::k_fb, dim3(blocks(n, 256)), dim3(256), 0, s, K, Vw, r, nx, pb->f_left,
-                       pb->f_right, w.g, Fb);
-    BLR_CHECK_LAUNCH();
     double* RF = w.get("RF", 4);
     tsqr(ctx, Fb, n, n, 2, nullptr, 0, RF, "qr.fb");
-    double* RFt = w.get("RFt", 4);
-    hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(64), 0, s, RF, 2, RFt);
-    BLR_CHECK_LAUNCH();
     double* Ub = w.get("Ub", 4);
     double* sb = w.get("sb", 2);
     double* Wb = w.get("Wb", 4);
-    svd_small(ctx, RFt, 2, Ub, sb, Wb);  // F_b = R_F^T Q_F^T,  R_F^T = U_b Sig_b W_b^T
+    // F_b = R_F^T Q_F^T,  R_F^T = U_b Sig_b W_b^T (R_F read transposed)
+    svd_small(ctx, RF, 2, Ub, sb, Wb, true);
     sbd = sb;
     const int rb = at.rb;
     if (rb > 0) {
       double* Vb = Vw + (size_t)r * n;
-      hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), rb), dim3(256), 0, s, Fb, 2, (long)n,
-                         Ub, 2, rb, 1.0, Vb, (long)n);
-      BLR_CHECK_LAUNCH();
       const int rk = r + rb;
-      fill<double>(s, Xw + (size_t)r * nx, (long)rb * nx, 0.0);
       double* Shat = w.get("Shat", (size_t)rk * rk);
-      hipLaunchKernelGGL(dk::k_pad_S, dim3(1), dim3(256), 0, s, Sw, r, rk, Shat);
+      // Vb = U_b[:, :rb]^T F_b, zero rows of X, S^ = [[S, 0], [0, 0]]
+      hipLaunchKernelGGL(dk::k_add_rows, dim3(blocks(n, 256), rb), dim3(256), 0, s, Fb, (long)n, Ub,
+                         rb, Vb, Xw + (size_t)r * nx, (long)rb * nx, Sw, r, Shat);
       BLR_CHECK_LAUNCH();
       if (!at.householder) {
         // [V; Vb] with V orthonormal: two projection passes keep V and
@@ -1131,9 +1204,8 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
                              G, pass, flag);
           BLR_CHECK_LAUNCH();
         }
-        hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(rk * rk, 256)), dim3(256), 0, s, Shat, rk, rk, Sw,
-                           rk);
-        BLR_CHECK_LAUNCH();
+        pend_S = Shat;  // S^ -> Sw before the collisions
+        pend_r = rk;
       } else {
         // Householder QR of [V; Vb]^T (weighted): V^ = Sv^T V_q, S <- S^ Sv^T
         double* Sv = w.get("Sv", (size_t)rk * rk);
@@ -1165,12 +1237,17 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   void* Qs;
   if (rec_events) BLR_HIP(hipEventRecord(ctx->ev[1], s));
   if (fp64c) {
+    if (pend_S) {
+      hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks(pend_r * pend_r, 256)), dim3(256), 0, s, pend_S,
+                         pend_r, pend_r, Sw, pend_r);
+      BLR_CHECK_LAUNCH();
+    }
     Qs = w.get("Q64", (size_t)P * n);
     collision_pairs(ctx, pb->v, BLR_FP64, Vw, r, pairs.data(), P, Qs);
   } else {
     float* V32 = (float*)ctx->buf("dlr.V32", (size_t)r * n * sizeof(float));
-    hipLaunchKernelGGL(dk::k_to_f32, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, Vw, (long)r * n,
-                       V32);
+    hipLaunchKernelGGL(dk::k_to_f32_copy_S, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, Vw,
+                       (long)r * n, V32, pend_S, pend_r, Sw, pend_r);
     BLR_CHECK_LAUNCH();
     Qs = ctx->buf("dlr.Q32", (size_t)P * n * sizeof(float));
     collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
@@ -1610,13 +1687,8 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
     // err_ada^2 = err^2 - |Sigma_perp|^2 + 2 <f^n, D>
     inf.err_ada = std::sqrt(std::max(err * err - sp2 + 2.0 * fnD, 0.0));
     // commit: rotate and truncate straight into the state
-    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(nx, 256), keep), dim3(256), 0, s, o.X1, r, (long)nx,
-                       o.U, r, keep, 1.0, st->X, (long)nx);
-    BLR_CHECK_LAUNCH();
-    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), keep), dim3(256), 0, s, o.V1, r, (long)n,
-                       o.Wm, r, keep, 1.0, st->V, (long)n);
-    BLR_CHECK_LAUNCH();
-    hipLaunchKernelGGL(dk::k_diag, dim3(1), dim3(1024), 0, s, o.sgd, keep, st->S, rc);
+    hipLaunchKernelGGL(dk::k_commit, dim3(blocks(std::max(nx, n), 256), keep), dim3(256), 0, s, o.X1,
+                       r, (long)nx, o.U, o.V1, (long)n, o.Wm, keep, st->X, st->V, o.sgd, st->S, rc);
     BLR_CHECK_LAUNCH();
     r_out = keep;
   } else {

@@ -264,7 +264,7 @@ __device__ __forceinline__ double group_sum(double x, int lpp) {
 constexpr int SVS = 65;
 __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A, int r,
                                                    double* __restrict__ U, double* __restrict__ sig,
-                                                   double* __restrict__ W, int sweeps) {
+                                                   double* __restrict__ W, int sweeps, int trans) {
   __shared__ double B[64 * SVS];  // column c: B[c * SVS + i]
   __shared__ double V[64 * SVS];
   __shared__ double nrm[64];
@@ -282,7 +282,8 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
     for (int k = 0; k < 8; ++k) {
       const int e = e0 + 64 * k + t;
       if (e < r * r) {
-        const int row = e / r, c = e % r;
+        // A row-major, or its transpose when trans (A^T[row][c] = A[c][row])
+        const int row = trans ? e % r : e / r, c = trans ? e / r : e % r;
         B[c * SVS + row] = v[k];
         V[c * SVS + row] = (row == c) ? 1.0 : 0.0;
       }
@@ -844,9 +845,10 @@ void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q,
   }
 }
 
-void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W) {
+void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W, bool trans) {
   require(r >= 1 && r <= 64, "svd: r must be in [1, 64]");
-  hipLaunchKernelGGL(la::k_svd_jacobi, dim3(1), dim3(64), 0, ctx->stream, A, r, U, sig, W, 40);
+  hipLaunchKernelGGL(la::k_svd_jacobi, dim3(1), dim3(64), 0, ctx->stream, A, r, U, sig, W, 40,
+                     trans ? 1 : 0);
   BLR_CHECK_LAUNCH();
 }
 

@@ -26,6 +26,8 @@ void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q,
             int* flag);
 
 // A = U diag(sig) W^T for an r x r row-major A (U, W row-major; sig descending).
-void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W);
+// trans: factor A^T (A is read transposed)
+void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W,
+               bool trans = false);
 
 }  // namespace blr
