@@ -22,8 +22,10 @@
 //                  spectrum (k_2 <= N/2) per group
 //   k_final_fused  sum over the groups, 3D inverse DFT from the half
 //                  spectrum, minus the loss, FP64 moment projection, store
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "collision_common.hpp"
 
@@ -629,8 +631,13 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   }
   // sigma sums for every radial node
   {
+    // tile width: the fewest tiles of at most 12 basis functions, each as
+    // narrow as possible (a rank-10 basis is one 10-wide tile: no idle slots,
+    // 120 VGPRs, four waves per SIMD)
+    const int ngr = (rb + 11) / 12, per = (rb + ngr - 1) / ngr;
+    const int G = std::max(4, per);
     bool diag_only = false;
-    auto tiles = plan_tiles(rb, pl.li, pl.lj, 12, diag_only);
+    auto tiles = plan_tiles(rb, pl.li, pl.lj, G, diag_only);
     BpArgs bpa{};
     for (int p = 0; p < h.nbp && p < kMaxBp; ++p) {
       bpa.off_b[p] = h.bp_b[p] * n;
@@ -644,15 +651,29 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
       const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
       timed_begin("fast.reduce", (double)h.mrho * n * (nload * h.nbp + nvalid) * sizeof(float), s);
       const dim3 grid((n + 255) / 256, h.mrho);
-      if (diag && h.nbp <= kMaxBp)
-        hipLaunchKernelGGL((k_reduce_diag<12>), grid, dim3(256), 0, s, Sh, Pa, t, bpa, n, h.mrho,
-                           h.msig, h.nbp, P);
-      else if (diag)
-        hipLaunchKernelGGL((k_reduce_all<12, true>), grid, dim3(256), 0, s, Sh, Pa, t,
-                           (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
-      else
-        hipLaunchKernelGGL((k_reduce_all<12, false>), grid, dim3(256), 0, s, Sh, Pa, t,
-                           (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
+      auto launch = [&](auto Gc) {
+        constexpr int Gt = decltype(Gc)::value;
+        if (diag && h.nbp <= kMaxBp)
+          hipLaunchKernelGGL((k_reduce_diag<Gt>), grid, dim3(256), 0, s, Sh, Pa, t, bpa, n,
+                             h.mrho, h.msig, h.nbp, P);
+        else if (diag)
+          hipLaunchKernelGGL((k_reduce_all<Gt, true>), grid, dim3(256), 0, s, Sh, Pa, t,
+                             (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
+        else
+          hipLaunchKernelGGL((k_reduce_all<Gt, false>), grid, dim3(256), 0, s, Sh, Pa, t,
+                             (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
+      };
+      switch (G) {
+        case 4: launch(std::integral_constant<int, 4>{}); break;
+        case 5: launch(std::integral_constant<int, 5>{}); break;
+        case 6: launch(std::integral_constant<int, 6>{}); break;
+        case 7: launch(std::integral_constant<int, 7>{}); break;
+        case 8: launch(std::integral_constant<int, 8>{}); break;
+        case 9: launch(std::integral_constant<int, 9>{}); break;
+        case 10: launch(std::integral_constant<int, 10>{}); break;
+        case 11: launch(std::integral_constant<int, 11>{}); break;
+        default: launch(std::integral_constant<int, 12>{}); break;
+      }
       BLR_CHECK_LAUNCH();
       timed_end(s);
     }

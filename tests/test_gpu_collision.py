@@ -132,6 +132,27 @@ def test_fused_fp32_equals_generic_fp32(ctx, n):
     assert (num / den).max().item() < 5e-6
 
 
+@pytest.mark.parametrize("r", [2, 5, 8, 10, 12, 13, 20, 25])
+def test_fused_fp32_tile_widths(ctx, r):
+    """The sigma sums run in tiles of 4 to 12 basis functions chosen from the
+    rank (one or several diagonal tiles, off-diagonal tiles above 12): every
+    width and tiling against the generic FP32 pipeline, all pairs and a
+    scattered subset."""
+    print(f"tile widths r={r}", flush=True)
+    spec = _spec(3, 16, 4)
+    V = torch.tensor(synth.smooth_basis(r, spec, seed=40 + r), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(r)
+    full = blr.upper_pairs(r)
+    sub = [full[k] for k in sorted(rng.choice(len(full), size=max(1, len(full) // 3),
+                                              replace=False))]
+    for pairs in (full, sub):
+        a = ctx.collision_pairs(blr.vgrid_from_spec(spec), V, pairs)
+        b = ctx.collision_pairs(blr.vgrid_from_spec(spec, blr.BLR_GENERIC_FFT), V, pairs)
+        torch.cuda.synchronize()
+        rel = ((a - b).double().norm(dim=1) / b.double().norm(dim=1)).max().item()
+        assert rel < 5e-6, (len(pairs), rel)
+
+
 def _c3_basis():
     nx, r = 256, 10
     spec = synth.C3
