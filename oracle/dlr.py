@@ -9,7 +9,8 @@ Follows the paper:
   * first-order upwind "discretise then project" transport, v^+ D_+ with a
     backward and v^- D_- with a forward difference (eq. scheme:fullupwind);
   * ghost values of K from the projected boundary function f^b (eq. boundary
-    general), inflow Maxwellian on the inflow half, the outflow half taken
+    general), inflow Maxwellian (or a Maxwell diffusive wall with its density
+    set by zero net mass flux) on the inflow half, the outflow half taken
     from the adjacent interior cell (Sec. 2.3);
   * K-step, S-step, L-step with forward Euler and QR (Sec. 2.4), the
     collision terms written with the symmetrised pair values Q_s(V_m, V_n)
@@ -43,6 +44,11 @@ class Problem1D:
     fR: np.ndarray            # inflow Maxwellian at the right wall, (n,)
     conserve: bool = True     # conservation projection of each Q_s
     collision: object = None  # pair evaluator: (V, pairs, vs, conserve) -> (Q, Q+)
+    # Maxwell diffusive walls (Sec. 2.3): fL / fR then give the shape of the
+    # wall Maxwellian exp(-|v - u_w|^2 / 2 T_w) (any positive multiple), and
+    # its density rho_w is set by zero net mass flux through the wall
+    wall_left: bool = False
+    wall_right: bool = False
 
     @property
     def dx(self):
@@ -110,16 +116,45 @@ def transport_matrices(V: np.ndarray, prob: Problem1D):
     return prob.dvd * (V * vp) @ V.T, prob.dvd * (V * vm) @ V.T
 
 
+def wall_density(f_out: np.ndarray, M_w: np.ndarray, prob: Problem1D, side: int) -> float:
+    """rho_w of a Maxwell diffusive wall (Sec. 2.3): with n the outward normal
+    (-e1 at the left wall, +e1 at the right, wall velocity tangential),
+        rho_w = - int_{v.n >= 0} (v.n) f dv / int_{v.n < 0} (v.n) M_w dv,
+    f the distribution leaving the domain (the adjacent interior cell) and M_w
+    the wall Maxwellian shape; midpoint rule in v."""
+    vn = -prob.v1() if side == 0 else prob.v1()
+    out = vn >= 0
+    num = float(np.sum(vn[out] * f_out[out]))
+    den = float(np.sum(vn[~out] * M_w[~out]))
+    return -num / den
+
+
+def boundary_function(side: int, f_adj: np.ndarray, prob: Problem1D) -> np.ndarray:
+    """The incoming half of the boundary function f_bdy at one wall: the
+    prescribed inflow Maxwellian, or rho_w M_w at a diffusive wall with rho_w
+    from the outgoing flux of f_adj (the adjacent interior cell).  Values on
+    the outgoing half are not used by the callers."""
+    M = prob.fL if side == 0 else prob.fR
+    wall = prob.wall_left if side == 0 else prob.wall_right
+    if not wall:
+        return M
+    return wall_density(f_adj, M, prob, side) * M
+
+
 def ghosts(K: np.ndarray, V: np.ndarray, prob: Problem1D):
     """Ghost values of K_j at both walls from the projected boundary function:
     K_j = <f_bdy 1_in, V_j>_v + sum_l K_l(adjacent cell) <1_out V_l V_j>_v.
-    Left wall (outward normal -e1): inflow v1 > 0.  Right wall: inflow v1 < 0."""
+    Left wall (outward normal -e1): inflow v1 > 0.  Right wall: inflow v1 < 0.
+    At a diffusive wall f_bdy = rho_w M_w with rho_w from the extrapolated
+    outgoing distribution sum_l K_l(adjacent cell) V_l."""
     v1 = prob.v1()
     inL = (v1 > 0).astype(np.float64)
     inR = (v1 < 0).astype(np.float64)
     outL, outR = 1.0 - inL, 1.0 - inR
-    gl = prob.dvd * V @ (prob.fL * inL) + prob.dvd * ((V * outL) @ V.T) @ K[0]
-    gr = prob.dvd * V @ (prob.fR * inR) + prob.dvd * ((V * outR) @ V.T) @ K[-1]
+    fbL = boundary_function(0, K[0] @ V, prob)
+    fbR = boundary_function(1, K[-1] @ V, prob)
+    gl = prob.dvd * V @ (fbL * inL) + prob.dvd * ((V * outL) @ V.T) @ K[0]
+    gr = prob.dvd * V @ (fbR * inR) + prob.dvd * ((V * outR) @ V.T) @ K[-1]
     return gl, gr
 
 
@@ -219,8 +254,8 @@ def boundary_matrix(st: State, prob: Problem1D):
     K = st.X @ st.S
     fin = K[0] @ st.V
     fout = K[-1] @ st.V
-    left = np.where(v1 > 0, prob.fL, fin)
-    right = np.where(v1 < 0, prob.fR, fout)
+    left = np.where(v1 > 0, boundary_function(0, fin, prob), fin)
+    right = np.where(v1 < 0, boundary_function(1, fout, prob), fout)
     return np.vstack([left, right])
 
 
@@ -305,13 +340,14 @@ def full_step(F: np.ndarray, prob: Problem1D, dt: float):
     """One forward-Euler step of the full-tensor discretisation the low-rank
     equations are projected from: for every cell,
     f_p <- f_p - dt (v^+ D_+ f + v^- D_- f)_p + dt Q_s(f_p, f_p), the left ghost
-    being the inflow Maxwellian where v1 > 0 (the adjacent cell elsewhere) and
-    the right ghost likewise where v1 < 0.  F is (nx, n).  Returns (F_new,
-    err_full) with err_full = ||F_new - F||_{L2(x,v)} (eq. err full grid)."""
+    being the boundary function f_bdy where v1 > 0 (the adjacent cell
+    elsewhere) and the right ghost likewise where v1 < 0; f_bdy is the inflow
+    Maxwellian, or rho_w M_w at a diffusive wall.  F is (nx, n).  Returns
+    (F_new, err_full) with err_full = ||F_new - F||_{L2(x,v)} (eq. err full grid)."""
     v1 = prob.v1()
     vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
-    left = np.where(v1 > 0, prob.fL, F[0])
-    right = np.where(v1 < 0, prob.fR, F[-1])
+    left = np.where(v1 > 0, boundary_function(0, F[0], prob), F[0])
+    right = np.where(v1 < 0, boundary_function(1, F[-1], prob), F[-1])
     Q, _ = evaluate_pairs(F, [(p, p) for p in range(F.shape[0])], prob)
     Fn = F - dt * (vp * d_plus(F, left, prob.dx) + vm * d_minus(F, right, prob.dx)) + dt * Q
     err = math.sqrt(prob.dx * prob.dvd * float(((Fn - F) ** 2).sum()))

@@ -226,6 +226,49 @@ def shock_initial(mach: float, spec: VGridSpec, nx: int, x_lo: float = -30.0,
     return dict(f0=f0, fL=fL, fR=fR, states=((rl, ul, Tl), (rr, ur, Tr)), x=x)
 
 
+# Fourier flow (Sec. 5.3): x in [0, 2], 2D velocity 32^2 on [-7.86, 7.86]^2,
+# Maxwell diffusive walls at rest with T_w = 1 (x = 0) and 1.2 (x = 2),
+# initial Maxwellian rho = 1, u = 0, T = 1.
+FOURIER = VGridSpec(d=2, n=32, L=7.86, gamma=0.0, C=1.0 / (2.0 * math.pi), m_rho=16, m_sigma=8)
+
+
+def wall_initial(spec: VGridSpec, nx: int, x_lo: float = 0.0, x_hi: float = 2.0,
+                 T_walls=(1.0, 1.2), rho0: float = 1.0, T0: float = 1.0,
+                 pert: float = 0.0, pert_rank: int = 0, seed: int = 3):
+    """Gas between two diffusive walls at rest: a uniform Maxwellian (rho0, 0,
+    T0) in every cell plus, optionally, a seeded smooth rank-``pert_rank``
+    perturbation of relative size ``pert`` (x-profiles exp(-(x - xi)^2 /
+    (w^2/8)) on the interval's width w, velocity profiles a random quadratic
+    times the unit Maxwellian).  fL, fR are the normalised wall Maxwellians
+    (density 1, temperatures T_walls).  Returns dict(f0, fL, fR, x)."""
+    d = spec.d
+    x = xgrid_centres(nx, x_lo, x_hi)
+    v = vgrid_points(d, spec.n, spec.L)
+    n = spec.npts
+    m = maxwellian(v, rho0, (0.0,) * d, T0).reshape(-1)
+    f0 = np.tile(m, (nx, 1))
+    if pert > 0 and pert_rank > 0:
+        rng = np.random.default_rng(seed)
+        w = x_hi - x_lo
+        xi = rng.uniform(x_lo, x_hi, size=pert_rank)
+        A = np.exp(-((x[:, None] - xi[None, :]) ** 2) / (w * w / 8.0))
+        m0 = maxwellian(v, 1.0, (0.0,) * d, 1.0).reshape(-1)
+        Bv = []
+        for _ in range(pert_rank):
+            poly = rng.standard_normal() * np.ones(n)
+            for i in range(d):
+                poly += rng.standard_normal() * v[i].reshape(-1)
+            for i in range(d):
+                for j in range(i, d):
+                    poly += rng.standard_normal() * (v[i] * v[j]).reshape(-1)
+            Bv.append(m0 * poly)
+        P = A @ np.array(Bv)
+        f0 = f0 + pert * f0.max() * P / np.abs(P).max()
+    fL = maxwellian(v, 1.0, (0.0,) * d, T_walls[0]).reshape(-1)
+    fR = maxwellian(v, 1.0, (0.0,) * d, T_walls[1]).reshape(-1)
+    return dict(f0=f0, fL=fL, fR=fR, x=x)
+
+
 def lowrank_state(f0: np.ndarray, r: int, dx: float, dvd: float):
     """Rank-r factors (X, S, V) of f0 with <X_i,X_j>_x = <V_i,V_j>_v = delta_ij,
     where <a,b>_x = dx sum a b and <a,b>_v = dv^d sum a b.
