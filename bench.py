@@ -156,7 +156,9 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
             big = max((p for p in prepared if p["q"]["n"] == nv), key=lambda p: p["q"]["r0"])
             for _ in range(slots):
                 pb, st = device_request(big)
-                torch.cuda.synchronize()
+                # this thread's stream only: a slot may be recording a step graph,
+                # and HIP refuses a device-wide synchronize meanwhile
+                torch.cuda.current_stream().synchronize()
                 sv.submit(pb, st, params(big["q"], 2), tag)
                 tag -= 1
             got = 0

@@ -121,16 +121,28 @@ blr_status blr_collision_pairs(blr_ctx ctx, const blr_vgrid* vg, blr_precision p
 /* ------------------------------------------------------------------ DLR -- */
 
 /* One-dimensional physical space along the first velocity axis (the normal
- * shock geometry of Sec. 4 and 5.2).  Cells x_p = x_lo + (p + 1/2) dx,
- * dx = (x_hi - x_lo)/nx.  Inflow boundary values (Sec. 2.3): f_left is used
- * where v_1 > 0 at x_lo, f_right where v_1 < 0 at x_hi (device, n^d doubles
- * each); the outflow halves come from the adjacent interior cell. */
+ * shock geometry of Sec. 4 and 5.2, the Fourier flow of Sec. 5.3).  Cells
+ * x_p = x_lo + (p + 1/2) dx, dx = (x_hi - x_lo)/nx.  Boundary values
+ * (Sec. 2.3, eq. boundary general): at x_lo the boundary function is used
+ * where v_1 > 0, at x_hi where v_1 < 0 (device arrays f_left, f_right, n^d
+ * doubles each); the outflow halves come from the adjacent interior cell.
+ *   wall_left / wall_right = 0: inflow boundary, the boundary function is
+ *     the array itself (the prescribed inflow Maxwellian);
+ *   = 1: Maxwell diffusive wall at rest in x (any wall velocity tangential):
+ *     the array is the wall Maxwellian's shape exp(-|v - u_w|^2 / 2 T_w), any
+ *     positive multiple, and must be positive somewhere on the incoming
+ *     half; the boundary function is rho_w times it, with rho_w set by zero
+ *     net mass flux through the wall, from the distribution leaving the
+ *     domain (the adjacent cell) at each use: the ghost values of every
+ *     substep, the boundary rows of the basis augmentation, the full-tensor
+ *     step.  Other values: BLR_ERR_ARG. */
 typedef struct {
   int32_t nx;
   double x_lo, x_hi;
   const double* f_left;
   const double* f_right;
   blr_vgrid v;
+  int32_t wall_left, wall_right;
 } blr_problem;
 
 /* Low-rank state f = sum_ij X_i S_ij V_j (eq. lowrank decomposition) with
@@ -261,7 +273,10 @@ blr_status blr_full_step(blr_ctx ctx, const blr_problem* pb, blr_precision prec,
  * starts when one of them ends, not when all have).  An idle slot's
  * workspace is released when the budget needs the room.  Each solve runs the
  * same kernels in the same order as blr_steady_solve on a fresh context, so
- * its result does not depend on what else is running. */
+ * its result does not depend on what else is running.  Slots record their
+ * steps as HIP graphs: while a server runs, other threads of the process
+ * synchronize their own streams, not the whole device (HIP refuses
+ * hipDeviceSynchronize while any stream is being recorded). */
 typedef struct blr_server_t* blr_server;
 
 typedef struct {

@@ -55,7 +55,8 @@ class VGrid(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
-                ("f_left", ctypes.c_void_p), ("f_right", ctypes.c_void_p), ("v", VGrid)]
+                ("f_left", ctypes.c_void_p), ("f_right", ctypes.c_void_p), ("v", VGrid),
+                ("wall_left", ctypes.c_int32), ("wall_right", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
@@ -217,10 +218,15 @@ class Context:
         return out
 
     # -------------------------------------------------------------- DLR --
-    def make_problem(self, vg: VGrid, nx: int, x_lo: float, x_hi: float, fL, fR) -> Problem:
+    def make_problem(self, vg: VGrid, nx: int, x_lo: float, x_hi: float, fL, fR,
+                     wall_left: bool = False, wall_right: bool = False) -> Problem:
+        """fL / fR: float64 CUDA tensors of n^d values, the inflow Maxwellians, or
+        the wall Maxwellians' shapes where wall_left / wall_right is set
+        (Maxwell diffusive walls)."""
         assert fL.dtype.itemsize == 8 and fR.dtype.itemsize == 8
         pb = Problem(nx, float(x_lo), float(x_hi), ctypes.c_void_p(fL.data_ptr()),
-                     ctypes.c_void_p(fR.data_ptr()), vg)
+                     ctypes.c_void_p(fR.data_ptr()), vg, int(bool(wall_left)),
+                     int(bool(wall_right)))
         pb._keep = (fL, fR)
         return pb
 

@@ -18,6 +18,7 @@
 
 #include "collision_common.hpp"
 #include "linalg.hpp"
+#include "walls.hpp"
 
 namespace blr {
 namespace dk {
@@ -448,6 +449,63 @@ __global__ __launch_bounds__(256) void k_add_begin(const double* __restrict__ X,
   const double v1 = g.v1(q);
   Fb[q] = v1 > 0 ? fL[q] : a;
   Fb[g.n + q] = v1 < 0 ? fR[q] : b;
+}
+
+// Diffusive walls, boundary rows: k_add_begin leaves the wall Maxwellian's
+// shape on the incoming half of a wall's row and the adjacent cell on the
+// outgoing half; the incoming half is scaled by rho_w taken from the
+// outgoing half.  One block per side.
+__global__ __launch_bounds__(1024) void k_wall_rows(double* __restrict__ Fb,
+                                                    const double* __restrict__ fL,
+                                                    const double* __restrict__ fR, int wl, int wr,
+                                                    VGeo g) {
+  const int side = blockIdx.x;
+  if (!(side == 0 ? wl : wr)) return;
+  __shared__ double red[1024 / 64 + 1];
+  const double* M = side ? fR : fL;
+  double* row = Fb + (long)side * g.n;
+  const int plane = g.d == 3 ? g.N * g.N : g.N;
+  const double rho = wall::density<1024>(side, row, M, g.n, g.L, g.dv, plane, red);
+  for (int q = threadIdx.x; q < g.n; q += 1024)
+    if (wall::incoming(side, g.v1(q))) row[q] = rho * M[q];
+}
+
+// Diffusive walls, ghost values: rho_w = sum_l K_l(x_b) a_l / den is linear
+// in the adjacent cell's K (a_l = sum_q (v.n)_out V_l, den = sum_q
+// |v.n|_in M_w), so the ghost
+//   g_j = rho_w <M_w 1_in, V_j> + sum_l K_l <1_out V_l V_j>
+// is K times (Mo + (a / den) gin^T): the rank-one term is folded into the
+// outflow matrix Mo[l r + j] and the inflow vector gin is cleared.  One
+// block per side, one wave per sum (lanes strided, fixed order).
+__global__ __launch_bounds__(1024) void k_wall_fold(const double* __restrict__ V, int r,
+                                                    const double* __restrict__ fL,
+                                                    const double* __restrict__ fR, int wl, int wr,
+                                                    VGeo g, double* __restrict__ ginL,
+                                                    double* __restrict__ ginR,
+                                                    double* __restrict__ MoL,
+                                                    double* __restrict__ MoR) {
+  const int side = blockIdx.x;
+  if (!(side == 0 ? wl : wr)) return;
+  __shared__ double a[65];
+  const double* M = side ? fR : fL;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int l = wv; l <= r; l += 16) {
+    double sum = 0.0;
+    for (int q = lane; q < g.n; q += 64) {
+      const double v1 = g.v1(q);
+      sum += l < r ? wall::out_weight(side, v1) * V[(long)l * g.n + q]
+                   : wall::in_weight(side, v1) * M[q];
+    }
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+    if (lane == 0) a[l] = sum;
+  }
+  __syncthreads();
+  double* Mo = side ? MoR : MoL;
+  double* gin = side ? ginR : ginL;
+  const double den = a[r];
+  for (int e = threadIdx.x; e < r * r; e += 1024) Mo[e] += a[e / r] / den * gin[e % r];
+  __syncthreads();
+  if (threadIdx.x < r) gin[threadIdx.x] = 0.0;
 }
 
 // The added basis rows Vb_i = sum_l Ub[l][i] Fb_l (i < rb, k_rows_comb with
@@ -1082,6 +1140,8 @@ void validate_problem(const blr_problem* pb, const blr_state* st) {
   require(pb->nx >= 2 && pb->nx <= (1 << 20), "problem.nx must be in [2, 2^20]");
   require(pb->x_hi > pb->x_lo, "problem.x_hi must exceed x_lo");
   require(pb->f_left && pb->f_right, "null inflow boundary arrays");
+  require((pb->wall_left == 0 || pb->wall_left == 1) && (pb->wall_right == 0 || pb->wall_right == 1),
+          "problem.wall_left / wall_right must be 0 (inflow) or 1 (diffusive wall)");
   validate_vgrid(pb->v);
   require(st->X && st->S && st->V, "null state arrays");
   require(st->r_cap >= 1 && st->r_cap <= 64, "state.r_cap must be in [1, 64]");
@@ -1154,6 +1214,12 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   hipLaunchKernelGGL(dk::k_add_begin, dim3(add ? blocks(n, 256) : 1), dim3(256), 0, s, Xw, r, nx,
                      st->S, rc, Sw, r, flag, Vw, pb->f_left, pb->f_right, w.g, Fb);
   BLR_CHECK_LAUNCH();
+  const bool walls = pb->wall_left || pb->wall_right;
+  if (add && walls) {
+    hipLaunchKernelGGL(dk::k_wall_rows, dim3(2), dim3(1024), 0, s, Fb, pb->f_left, pb->f_right,
+                       pb->wall_left, pb->wall_right, w.g);
+    BLR_CHECK_LAUNCH();
+  }
   // S^ still to be copied into Sw (projection variant), done with the FP32 cast
   const double* pend_S = nullptr;
   int pend_r = 0;
@@ -1269,6 +1335,11 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     gj.add(Vw, r, pb->f_left, 1, false, dk::W_IN_LEFT, dvd, ginL);
     gj.add(Vw, r, pb->f_right, 1, false, dk::W_IN_RIGHT, dvd, ginR);
     gj.run(w);
+  }
+  if (walls) {
+    hipLaunchKernelGGL(dk::k_wall_fold, dim3(2), dim3(1024), 0, s, Vw, r, pb->f_left, pb->f_right,
+                       pb->wall_left, pb->wall_right, w.g, ginL, ginR, MoL, MoR);
+    BLR_CHECK_LAUNCH();
   }
 
   // ---------------------------------------------------------- K-step
@@ -1471,6 +1542,7 @@ std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_
     double x_lo, x_hi;
     const void *fl, *fr;
     blr_vgrid v;
+    int32_t wl, wr;
     int32_t r, r_cap;
     const void *X, *S, *V;
     blr_step_params p;
@@ -1483,6 +1555,8 @@ std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_
   k.fl = pb->f_left;
   k.fr = pb->f_right;
   k.v = pb->v;
+  k.wl = pb->wall_left;
+  k.wr = pb->wall_right;
   k.r = st->r;
   k.r_cap = st->r_cap;
   k.X = st->X;

@@ -12,22 +12,42 @@
 #include <vector>
 
 #include "collision_common.hpp"
+#include "walls.hpp"
 
 namespace blr {
 namespace fk {
 
 constexpr int kChunk = 64;  // cells per collision call (the pair pipeline's basis limit)
 
+// Boundary-function scale of each side: rho_w of a diffusive wall from the
+// cell next to it (Sec. 2.3), 1 for an inflow boundary.  One block per side.
+__global__ __launch_bounds__(1024) void k_full_wall_rho(const double* __restrict__ F, int nx, int n,
+                                                        const double* __restrict__ fL,
+                                                        const double* __restrict__ fR, int wl,
+                                                        int wr, double L, double dv, int plane,
+                                                        double* __restrict__ rho) {
+  const int side = blockIdx.x;
+  if (!(side == 0 ? wl : wr)) {
+    if (threadIdx.x == 0) rho[side] = 1.0;
+    return;
+  }
+  __shared__ double red[1024 / 64 + 1];
+  const double v = wall::density<1024>(side, F + (long)(side ? nx - 1 : 0) * n, side ? fR : fL, n,
+                                       L, dv, plane, red);
+  if (threadIdx.x == 0) rho[side] = v;
+}
+
 // F_new = F - dt (v1+ (F_p - F_{p-1}) + v1- (F_{p+1} - F_p)) / dx + dt Q_p for the
-// cells p0 .. p0 + gridDim.y - 1; the ghost F_{-1} is f_L where v1 > 0 and
-// F_{nx} is f_R where v1 < 0 (the outflow halves multiply a zero velocity
-// part).  Writes each block's sum of (F_new - F)^2 (wave sums, then the waves
-// in order) to part[p * gridDim.x + blockIdx.x].
+// cells p0 .. p0 + gridDim.y - 1; the ghost F_{-1} is rho[0] f_L where v1 > 0
+// and F_{nx} is rho[1] f_R where v1 < 0 (the outflow halves multiply a zero
+// velocity part).  Writes each block's sum of (F_new - F)^2 (wave sums, then
+// the waves in order) to part[p * gridDim.x + blockIdx.x].
 template <typename TQ>
 __global__ __launch_bounds__(256) void k_full_update(const double* __restrict__ F, int nx, int n,
                                                      int p0, const TQ* __restrict__ Q,
                                                      const double* __restrict__ fL,
-                                                     const double* __restrict__ fR, double dt,
+                                                     const double* __restrict__ fR,
+                                                     const double* __restrict__ rho, double dt,
                                                      double dx, double L, double dv, int plane,
                                                      double* __restrict__ Fn,
                                                      double* __restrict__ part) {
@@ -39,8 +59,8 @@ __global__ __launch_bounds__(256) void k_full_update(const double* __restrict__ 
     const double v1 = -L + (q / plane) * dv;
     const double* fp = F + (long)p * n + q;
     const double f = fp[0];
-    const double fm = p > 0 ? fp[-n] : (v1 > 0 ? fL[q] : f);
-    const double fn = p < nx - 1 ? fp[n] : (v1 < 0 ? fR[q] : f);
+    const double fm = p > 0 ? fp[-n] : (v1 > 0 ? rho[0] * fL[q] : f);
+    const double fn = p < nx - 1 ? fp[n] : (v1 < 0 ? rho[1] * fR[q] : f);
     const double vp = v1 > 0 ? v1 : 0.0, vm = v1 < 0 ? v1 : 0.0;
     const double d = -dt * (vp * (f - fm) + vm * (fn - f)) / dx +
                      dt * (double)Q[(long)blockIdx.y * n + q];
@@ -80,6 +100,8 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
   require(pb->nx >= 1, "nx must be >= 1");
   require(pb->x_hi > pb->x_lo, "x_hi must exceed x_lo");
   require(pb->f_left && pb->f_right, "null inflow function");
+  require((pb->wall_left == 0 || pb->wall_left == 1) && (pb->wall_right == 0 || pb->wall_right == 1),
+          "problem.wall_left / wall_right must be 0 (inflow) or 1 (diffusive wall)");
   require(prec == BLR_FP32 || prec == BLR_FP64, "bad precision");
   require(std::isfinite(dt) && dt >= 0.0, "dt must be finite and >= 0");
   const DevTables& tb = get_tables(ctx, pb->v, prec);
@@ -97,6 +119,11 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
   const unsigned nbx = nblocks(n, 256);
   double* part = (double*)ctx->buf("full.part", (size_t)nx * nbx * sizeof(double));
   double* err = (double*)ctx->buf("full.err", sizeof(double));
+  // rho_w from the cells next to the walls before any cell is updated
+  double* rho = (double*)ctx->buf("full.rho", 2 * sizeof(double));
+  hipLaunchKernelGGL(fk::k_full_wall_rho, dim3(2), dim3(1024), 0, s, F, nx, n, pb->f_left,
+                     pb->f_right, pb->wall_left, pb->wall_right, h.L, h.dv, plane, rho);
+  BLR_CHECK_LAUNCH();
   std::vector<int32_t> pairs(2 * chunk);
   for (int p0 = 0; p0 < nx; p0 += chunk) {
     const int np = std::min(chunk, nx - p0);
@@ -113,11 +140,11 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
     timed_begin("full.update", (double)np * n * 8.0 * (3.0 + 1.0) + (double)np * n * esz, s);
     if (prec == BLR_FP32)
       hipLaunchKernelGGL(fk::k_full_update<float>, dim3(nbx, np), dim3(256), 0, s, F, nx, n, p0,
-                         (const float*)Q, pb->f_left, pb->f_right, dt, dx, h.L, h.dv, plane, Fn,
+                         (const float*)Q, pb->f_left, pb->f_right, rho, dt, dx, h.L, h.dv, plane, Fn,
                          part);
     else
       hipLaunchKernelGGL(fk::k_full_update<double>, dim3(nbx, np), dim3(256), 0, s, F, nx, n, p0,
-                         (const double*)Q, pb->f_left, pb->f_right, dt, dx, h.L, h.dv, plane, Fn,
+                         (const double*)Q, pb->f_left, pb->f_right, rho, dt, dx, h.L, h.dv, plane, Fn,
                          part);
     BLR_CHECK_LAUNCH();
     timed_end(s);

@@ -43,6 +43,21 @@ def _setup(d, N, nx, r, m_rho, mach=1.5, pert=1e-2, pert_rank=3):
     return spec, prob, dlr.State(X, S, V), ini
 
 
+def _wall_setup(d, N, nx, r, m_rho, walls=(True, True)):
+    """Gas between Maxwell diffusive walls at rest (T_w = 1 at x = 0, 1.2 at
+    x = 2; a side without a wall takes that Maxwellian as inflow)."""
+    if d == 2:
+        spec = synth.VGridSpec(d=2, n=N, L=8.0, gamma=0.0, C=1 / (2 * math.pi), m_rho=m_rho, m_sigma=8)
+    else:
+        spec = synth.VGridSpec(d=3, n=N, L=8.0, gamma=1.0, C=1.0, m_rho=m_rho, m_sigma=38)
+    vs = oc.setup_from_spec(spec)
+    ini = synth.wall_initial(spec, nx, 0.0, 2.0, T_walls=(1.0, 1.2), pert=5e-2, pert_rank=3, seed=4)
+    prob = dlr.Problem1D(vs=vs, nx=nx, x_lo=0.0, x_hi=2.0, fL=ini["fL"], fR=ini["fR"],
+                         wall_left=walls[0], wall_right=walls[1])
+    X, S, V = synth.lowrank_state(ini["f0"], r, prob.dx, prob.dvd)
+    return spec, prob, dlr.State(X, S, V), ini
+
+
 class Gpu:
     def __init__(self, ctx, spec, prob, st, r_cap, flags=0):
         dev = "cuda"
@@ -58,7 +73,8 @@ class Gpu:
         self.fL = torch.tensor(prob.fL, device=dev)
         self.fR = torch.tensor(prob.fR, device=dev)
         self.vg = blr.vgrid_from_spec(spec, flags)
-        self.pb = ctx.make_problem(self.vg, prob.nx, prob.x_lo, prob.x_hi, self.fL, self.fR)
+        self.pb = ctx.make_problem(self.vg, prob.nx, prob.x_lo, prob.x_hi, self.fL, self.fR,
+                                   wall_left=prob.wall_left, wall_right=prob.wall_right)
         self.st = ctx.make_state(self.X, self.S, self.V, r, seed=11)
 
     def full(self):
@@ -142,6 +158,61 @@ def test_adaptive_steps_fp64(ctx, d, N, nx, r, m_rho):
         # the bound of Sec. 5.1 holds on the GPU too
         bound = math.sqrt(max(info.r_in + info.r_added - info.r_out, 0)) * info.drop_tol
         assert abs(info.err - info.err_ada) <= bound * (1 + 1e-12) + 1e-15
+
+
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(2, 16, 24, 4, 8), (3, 16, 40, 5, 2), (2, 16, 40, 17, 4)])
+def test_fixed_rank_step_with_walls_fp64(ctx, d, N, nx, r, m_rho):
+    """Maxwell diffusive walls on both sides: the ghosts of every substep
+    carry rho_w from the adjacent cell (r = 17 takes the general kernels)."""
+    print(f"walls fixed-rank d={d} N={N} nx={nx} r={r}", flush=True)
+    spec, prob, st, _ = _wall_setup(d, N, nx, r, m_rho)
+    if r > 8:
+        st = dlr.State(st.X, st.S + 1e-3 * np.abs(st.S).max() * np.eye(r), st.V)
+    g = Gpu(ctx, spec, prob, st, r_cap=max(8, r))
+    dt = 0.005
+    info = ctx.dlr_step(g.pb, g.st, _params(dt, blr.BLR_STEP_FP64_COLLISION))
+    new, err, _ = dlr.ksl_step(st, prob, dt)
+    f_ref = new.full()
+    e = np.abs(g.full() - f_ref).max() / np.abs(f_ref).max()
+    print("f rel err", e, "err", info.err, err, flush=True)
+    assert e < 1e-12
+    assert abs(info.err - err) < 1e-10 * err
+
+
+@pytest.mark.parametrize("walls", [(True, True), (True, False), (False, True)])
+@pytest.mark.parametrize("d,N,nx,r,m_rho", [(2, 16, 24, 3, 8), (3, 16, 40, 4, 2)])
+def test_adaptive_steps_with_walls_fp64(ctx, d, N, nx, r, m_rho, walls):
+    """The boundary rows of the basis augmentation carry rho_w M_w on a
+    wall's incoming half: the added functions, ranks and err_ada follow the
+    oracle step by step."""
+    print(f"walls adaptive d={d} N={N} walls={walls}", flush=True)
+    spec, prob, st, _ = _wall_setup(d, N, nx, r, m_rho, walls)
+    g = Gpu(ctx, spec, prob, st, r_cap=12)
+    flags = blr.BLR_STEP_FP64_COLLISION | blr.BLR_STEP_ADD | blr.BLR_STEP_DROP
+    cur = st
+    dt = 0.005
+    for k in range(3):
+        info = ctx.dlr_step(g.pb, g.st, _params(dt, flags, r_max=12))
+        cur, oinfo = dlr.adaptive_step(cur, prob, dt, c=0.2, r_max=12,
+                                       rng=np.random.default_rng(k))
+        print(k, "r", info.r_added, info.r_out, oinfo.r_added, oinfo.r_out, "err", info.err, oinfo.err,
+              "ada", info.err_ada, oinfo.err_ada, flush=True)
+        assert info.r_added == oinfo.r_added and info.r_out == oinfo.r_out
+        assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
+        assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
+        f_ref = cur.full()
+        assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+
+
+def test_wall_flags_are_checked(ctx):
+    spec, prob, st, _ = _wall_setup(2, 16, 24, 3, 8)
+    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    g.pb.wall_left = 2
+    before = g.full()
+    with pytest.raises(blr.BlrError) as ei:
+        ctx.dlr_step(g.pb, g.st, _params(0.005, blr.BLR_STEP_FP64_COLLISION))
+    assert ei.value.code == blr.BLR_ERR_ARG
+    assert np.array_equal(g.full(), before)
 
 
 @pytest.mark.parametrize("d,N,nx,r,m_rho", [(3, 16, 40, 4, 2)])

@@ -1,6 +1,7 @@
 """GPU parity of blr_full_step (the full-tensor reference step, eq.
 scheme:fullupwind of Sec. 2.2, walls of Sec. 2.3, err_full of eq. err full
-grid) against the oracle's full_step, on seeded shock-like inputs.
+grid) against the oracle's full_step, on seeded shock-like inputs and on gas
+between Maxwell diffusive walls.
 
 Error measure: ||dF_gpu - dF_ref|| / ||dF_ref|| for the update dF = F_new - F,
 bounded by 1e-12 with FP64 collisions.  With FP32 collisions the bound is the
@@ -41,19 +42,25 @@ def _spec(d, n, m_rho):
     return synth.VGridSpec(d=3, n=n, L=8.0, gamma=1.0, C=1.0, m_rho=m_rho, m_sigma=38)
 
 
-def _case(ctx, d, n, m_rho, nx, prec, dt=0.01, conserve=True, seed=5):
+def _case(ctx, d, n, m_rho, nx, prec, dt=0.01, conserve=True, seed=5, walls=(False, False)):
     spec = _spec(d, n, m_rho)
     vs = oc.setup_from_spec(spec)
-    ini = synth.shock_initial(1.5, spec, nx, -30.0, 30.0, pert=1e-2, pert_rank=3, seed=seed)
+    if any(walls):
+        lo, hi = 0.0, 2.0
+        ini = synth.wall_initial(spec, nx, lo, hi, T_walls=(1.0, 1.2), pert=5e-2, pert_rank=3,
+                                 seed=seed)
+    else:
+        lo, hi = -30.0, 30.0
+        ini = synth.shock_initial(1.5, spec, nx, lo, hi, pert=1e-2, pert_rank=3, seed=seed)
     F = ini["f0"]
-    prob = dlr.Problem1D(vs=vs, nx=nx, x_lo=-30.0, x_hi=30.0, fL=ini["fL"], fR=ini["fR"],
-                         conserve=conserve)
+    prob = dlr.Problem1D(vs=vs, nx=nx, x_lo=lo, x_hi=hi, fL=ini["fL"], fR=ini["fR"],
+                         conserve=conserve, wall_left=walls[0], wall_right=walls[1])
     Fref, eref = dlr.full_step(F, prob, dt)
     flags = 0 if conserve else blr.BLR_NO_CONSERVE
     vg = blr.vgrid_from_spec(spec, flags)
     fL = torch.tensor(ini["fL"], device="cuda")
     fR = torch.tensor(ini["fR"], device="cuda")
-    pb = ctx.make_problem(vg, nx, -30.0, 30.0, fL, fR)
+    pb = ctx.make_problem(vg, nx, lo, hi, fL, fR, wall_left=walls[0], wall_right=walls[1])
     Fd = torch.tensor(F, device="cuda")
     e = ctx.full_step(pb, Fd, dt, prec)
     torch.cuda.synchronize()
@@ -82,6 +89,17 @@ def test_full_step_fp32_two_chunks_matches_oracle(ctx):
     print("rel", rel, "err", e, eref, flush=True)
     assert rel < 1e-5
     assert abs(e - eref) < 1e-5 * eref
+
+
+@pytest.mark.parametrize("walls", [(True, True), (True, False), (False, True)])
+@pytest.mark.parametrize("d,n,m_rho,nx", [(2, 16, 8, 7), (3, 8, 8, 5)])
+def test_full_step_with_diffusive_walls_matches_oracle(ctx, d, n, m_rho, nx, walls):
+    """Maxwell diffusive walls (Sec. 2.3) on either or both sides, FP64."""
+    print(f"full step walls={walls} d={d} n={n} nx={nx}", flush=True)
+    rel, e, eref = _case(ctx, d, n, m_rho, nx, blr.BLR_FP64, dt=0.005, walls=walls)
+    print("rel", rel, "err", e, eref, flush=True)
+    assert rel < 1e-12
+    assert abs(e - eref) < 1e-12 * eref
 
 
 def test_full_step_without_projection(ctx):

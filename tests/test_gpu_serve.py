@@ -70,7 +70,9 @@ class Req:
         vg = blr.vgrid_from_spec(self.spec)
         pb = ctx_like.make_problem(vg, self.nx, -30.0, 30.0, fL, fR)
         st = ctx_like.make_state(X, S, V, self.r)
-        torch.cuda.synchronize()
+        # this thread's stream only: a server may be recording a step graph on
+        # another thread, and HIP refuses a device-wide synchronize meanwhile
+        torch.cuda.current_stream().synchronize()
         return pb, st, (X, S, V)
 
 
