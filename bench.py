@@ -65,6 +65,13 @@ def parse():
                          "[-13.11, 13.11]^2, N_x = 1000) to steady state by the low-rank and the "
                          "full-tensor method (about two minutes)")
     ap.add_argument("--paper-tol", type=float, default=1e-6)
+    ap.add_argument("--paper-fourier", action="store_true",
+                    help="also solve the paper's Fourier flow (diffusive walls at T = 1 and 1.2, "
+                         "N_x = 200, 2D velocity 32^2) to err <= --fourier-tol by the low-rank "
+                         "and the full-tensor method (minutes)")
+    ap.add_argument("--fourier-tol", type=float, default=2e-7)
+    ap.add_argument("--fourier-cap", type=float, default=420.0,
+                    help="wall-clock cap in seconds per method of the Fourier flow")
     ap.add_argument("--serve-count", type=int, default=8,
                     help="requests of the trace both paths run")
     ap.add_argument("--serve-steps", type=int, default=10,
@@ -360,6 +367,98 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
                            "thickness_mott_smith": float(thick(rho_ms))}}
 
 
+def fourier_leg(args, blr, synth, torch, ctx):
+    """The Fourier flow of Sec. 5.3: x in [0, 2] with N_x = 200, 2D velocity
+    32^2 on [-7.86, 7.86]^2, Maxwell diffusive walls at rest with T_w = 1
+    (x = 0) and 1.2 (x = 2), initial Maxwellian rho = 1, u = 0, T = 1; Maxwell
+    molecules B = 1/(2 pi) in the Carleman form (8 directions), FP32
+    collisions, dt = dx / (2 L_v).  Both methods run to err <= tol (the
+    paper's res_tol 2e-7): the adaptive low-rank method (c = 0.2) from the
+    rank-1 initial state, and the full tensor; the temperature profiles of the
+    two steady states are compared and the rank history reported."""
+    import numpy as np
+    spec = synth.FOURIER
+    nx, N, L = 200, spec.n, spec.L
+    dev = torch.device("cuda:0")
+    dx, dv = 2.0 / nx, 2 * L / N
+    dt = 0.5 * dx / L
+    tol = args.fourier_tol
+    ini = synth.wall_initial(spec, nx, 0.0, 2.0, T_walls=(1.0, 1.2))
+    vg = blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN)
+    fL = torch.tensor(ini["fL"], device=dev)
+    fR = torch.tensor(ini["fR"], device=dev)
+    pb = ctx.make_problem(vg, nx, 0.0, 2.0, fL, fR, wall_left=True, wall_right=True)
+    v = synth.vgrid_points(2, N, L).reshape(2, -1)
+
+    def temperature(F):
+        w = dv * dv
+        rho = F.sum(axis=1) * w
+        u1 = (F * v[0]).sum(axis=1) * w / rho
+        u2 = (F * v[1]).sum(axis=1) * w / rho
+        E = 0.5 * (F * (v ** 2).sum(axis=0)).sum(axis=1) * w
+        return (2 * E / rho - u1 * u1 - u2 * u2) / 2, rho
+
+    # low-rank: steady solves of `chunk` steps until converged (a progress
+    # line between chunks; the state and its rank carry over)
+    rc, chunk = 32, 10000
+    X, S, V = synth.lowrank_state(ini["f0"], 1, dx, dv * dv)
+    Xd = torch.zeros((rc, nx), dtype=torch.float64, device=dev)
+    Sd = torch.zeros((rc, rc), dtype=torch.float64, device=dev)
+    Vd = torch.zeros((rc, N * N), dtype=torch.float64, device=dev)
+    Xd[:1] = torch.tensor(X.T, device=dev)
+    Sd[:1, :1] = torch.tensor(S, device=dev)
+    Vd[:1] = torch.tensor(V, device=dev)
+    st = ctx.make_state(Xd, Sd, Vd, 1)
+    torch.cuda.synchronize()
+    sp = blr.SolveParams(blr.StepParams(dt, 0.2, 1e-10, 1, rc,
+                                        blr.BLR_STEP_ADD | blr.BLR_STEP_DROP), tol, chunk)
+    steps_lr, ranks, conv_lr, li = 0, [], False, None
+    t0 = time.perf_counter()
+    while not conv_lr and time.perf_counter() - t0 < args.fourier_cap:
+        li = ctx.steady_solve(pb, st, sp, allow_unconverged=True)
+        steps_lr += int(li.steps)
+        conv_lr = bool(li.converged)
+        ranks.append([steps_lr, int(li.r)])
+        progress(f"fourier: low-rank {steps_lr} steps, err_ada {li.err_ada:.3e}, rank {li.r}")
+    t_lr = time.perf_counter() - t0
+    r = st.r
+    F_lr = (Xd[:r].cpu().numpy().T @ Sd[:r, :r].cpu().numpy()) @ Vd[:r].cpu().numpy()
+    # full tensor: one library call per step
+    F = torch.tensor(ini["f0"], device=dev)
+    steps_full, e = 0, float("inf")
+    t0 = last = time.perf_counter()
+    while e > tol and time.perf_counter() - t0 < args.fourier_cap:
+        e = ctx.full_step(pb, F, dt, blr.BLR_FP32)
+        steps_full += 1
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            progress(f"fourier: full tensor {steps_full} steps, err_full {e:.3e}")
+    t_full = time.perf_counter() - t0
+    T_lr, rho_lr = temperature(F_lr)
+    T_full, rho_full = temperature(F.cpu().numpy())
+    conv_full = e <= tol
+    return {"shape": "Fourier flow: x in [0,2], N_x=200, 2D velocity 32^2 on [-7.86,7.86]^2, "
+                     "diffusive walls at rest T_w=1 (x=0) and 1.2 (x=2), initial Maxwellian "
+                     "rho=1 T=1, Maxwell molecules B=1/(2 pi) (Carleman form, 8 directions), "
+                     "FP32 collisions, dt=dx/(2 L_v)",
+            "tol": tol,
+            "low_rank": {"steps": steps_lr, "converged": int(conv_lr),
+                         "err_ada": li.err_ada if li else None, "rank": int(r),
+                         "rank_history": ranks, "seconds": round(t_lr, 2),
+                         "ms_per_step": round(1e3 * t_lr / max(1, steps_lr), 4)},
+            "full_tensor": {"steps": steps_full, "converged": int(conv_full), "err_full": e,
+                            "seconds": round(t_full, 2),
+                            "ms_per_step": round(1e3 * t_full / max(1, steps_full), 4)},
+            "time_ratio_full_over_low_rank": round(t_full / t_lr, 2) if conv_lr and conv_full
+            else None,
+            "T_rel_diff_low_rank_vs_full": float(np.abs(T_lr - T_full).max() / T_full.max()),
+            "rho_rel_diff_low_rank_vs_full": float(np.abs(rho_lr - rho_full).max() /
+                                                   rho_full.max()),
+            "T_profile_low_rank": [round(float(x), 5) for x in T_lr[::20]],
+            "T_profile_full": [round(float(x), 5) for x in T_full[::20]],
+            "T_next_to_walls_low_rank": [float(T_lr[0]), float(T_lr[-1])]}
+
+
 def serving_leg(args, blr, synth, torch, helper):
     """The serving trace on the batched FP32 path (slots solves at once) and on
     the plain FP64 per-pair path (one solve at a time, first in first out),
@@ -604,6 +703,9 @@ def main():
     paper = None
     if args.paper_shock:
         paper = paper_shock_leg(args, blr, synth, torch, ctx)
+    fourier = None
+    if args.paper_fourier:
+        fourier = fourier_leg(args, blr, synth, torch, ctx)
 
     serving = None
     if args.mode == "step" and not args.no_serve:
@@ -652,6 +754,7 @@ def main():
         "full_tensor": full,
         "carleman": carleman,
         "paper_shock": paper,
+        "paper_fourier": fourier,
         "serving": serving,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                     for t in sorted(timers, key=lambda t: -t["ms"])[:8]],

@@ -228,8 +228,9 @@ def shock_initial(mach: float, spec: VGridSpec, nx: int, x_lo: float = -30.0,
 
 # Fourier flow (Sec. 5.3): x in [0, 2], 2D velocity 32^2 on [-7.86, 7.86]^2,
 # Maxwell diffusive walls at rest with T_w = 1 (x = 0) and 1.2 (x = 2),
-# initial Maxwellian rho = 1, u = 0, T = 1.
-FOURIER = VGridSpec(d=2, n=32, L=7.86, gamma=0.0, C=1.0 / (2.0 * math.pi), m_rho=16, m_sigma=8)
+# initial Maxwellian rho = 1, u = 0, T = 1; 2D Maxwell molecules B = 1/(2 pi)
+# in the Carleman form with 8 directions (m_rho is not used by that form).
+FOURIER = VGridSpec(d=2, n=32, L=7.86, gamma=0.0, C=1.0 / (2.0 * math.pi), m_rho=1, m_sigma=8)
 
 
 def wall_initial(spec: VGridSpec, nx: int, x_lo: float = 0.0, x_hi: float = 2.0,
