@@ -55,6 +55,11 @@ class Problem1D:
         return (self.x_hi - self.x_lo) / self.nx
 
     @property
+    def wx(self):
+        """Weight of the x-side inner product <a, b>_x = wx sum a b."""
+        return self.dx
+
+    @property
     def dvd(self):
         return self.vs.dv ** self.vs.d
 
@@ -191,6 +196,8 @@ def evaluate_pairs(V, pairs, prob):
 # ----------------------------------------------------------------------------
 def ksl_step(st: State, prob: Problem1D, dt: float, Qs=None):
     """One K -> S -> L step with forward Euler; returns (new State, err, pieces)."""
+    if isinstance(prob, Problem2D):
+        return ksl_step_2d(st, prob, dt, Qs)
     X, S, V = st.X, st.S, st.V
     r = S.shape[0]
     dx, dvd = prob.dx, prob.dvd
@@ -250,6 +257,8 @@ def ksl_step(st: State, prob: Problem1D, dt: float, Qs=None):
 def boundary_matrix(st: State, prob: Problem1D):
     """F_b rows f^b(x_b, .) at the two walls: inflow half from the prescribed
     Maxwellian, outflow half from the adjacent interior cell."""
+    if isinstance(prob, Problem2D):
+        return boundary_matrix_2d(st, prob)
     v1 = prob.v1()
     K = st.X @ st.S
     fin = K[0] @ st.V
@@ -277,7 +286,7 @@ def add_boundary_basis(st: State, prob: Problem1D, add_tol: float = 1e-10,
     Vhat = np.vstack([st.V, Qbt[:rb]])
     Shat = np.zeros((st.r + rb, st.r + rb))
     Shat[:st.r, :st.r] = st.S
-    Xq, Sx = weighted_qr_cols(Xhat, prob.dx)
+    Xq, Sx = weighted_qr_cols(Xhat, prob.wx)
     Vq, Sv = weighted_qr_cols(Vhat.T, prob.dvd)
     return State(Xq, Sx @ Shat @ Sv.T, Vq.T), rb
 
@@ -312,7 +321,7 @@ def adaptive_step(st: State, prob: Problem1D, dt: float, c: float = 0.2,
     # err_ada^2 = err^2 - |Sigma_perp|^2 + 2 <f^n, D>,  D = X1 U_p Sig_p Q_p^T V1
     sp = s[keep:]
     M = U[:, keep:] @ np.diag(sp) @ Qt[keep:]
-    A = prob.dx * start.X.T @ new.X                       # <X^n_k, X1_i>
+    A = prob.wx * start.X.T @ new.X                       # <X^n_k, X1_i>
     B = prob.dvd * start.V @ new.V.T                      # <V^n_l, V1_j>
     fnD = (start.S * (A @ M @ B.T)).sum()
     e2 = err ** 2 - (sp ** 2).sum() + 2.0 * fnD
@@ -344,6 +353,8 @@ def full_step(F: np.ndarray, prob: Problem1D, dt: float):
     elsewhere) and the right ghost likewise where v1 < 0; f_bdy is the inflow
     Maxwellian, or rho_w M_w at a diffusive wall.  F is (nx, n).  Returns
     (F_new, err_full) with err_full = ||F_new - F||_{L2(x,v)} (eq. err full grid)."""
+    if isinstance(prob, Problem2D):
+        return full_step_2d(F, prob, dt)
     v1 = prob.v1()
     vp, vm = np.maximum(v1, 0.0), np.minimum(v1, 0.0)
     left = np.where(v1 > 0, boundary_function(0, F[0], prob), F[0])
@@ -351,6 +362,220 @@ def full_step(F: np.ndarray, prob: Problem1D, dt: float):
     Q, _ = evaluate_pairs(F, [(p, p) for p in range(F.shape[0])], prob)
     Fn = F - dt * (vp * d_plus(F, left, prob.dx) + vm * d_minus(F, right, prob.dx)) + dt * Q
     err = math.sqrt(prob.dx * prob.dvd * float(((Fn - F) ** 2).sum()))
+    return Fn, err
+
+
+# ----------------------------------------------------------------------------
+# two-dimensional physical space (Sec. 2.2: the upwind scheme on a rectangular
+# grid, one axis at a time; Sec. 2.3: the boundary on every face)
+# ----------------------------------------------------------------------------
+@dataclass
+class Problem2D:
+    """Rectangle [x_lo, x_hi] x [y_lo, y_hi] with nx x ny cells, cell p = ix ny
+    + iy; velocity axis 0 along x, axis 1 along y.  faces = four (f, wall)
+    pairs for x_lo, x_hi, y_lo, y_hi: f is the boundary function of the face,
+    one row per face cell (ny rows on the x faces, nx on the y faces) or one
+    row for all; wall=True makes it the shape of a Maxwell diffusive wall's
+    Maxwellian (density rho_w per face cell from zero net mass flux)."""
+    vs: oc.VelocitySetup
+    nx: int
+    ny: int
+    x_lo: float
+    x_hi: float
+    y_lo: float
+    y_hi: float
+    faces: list
+    conserve: bool = True
+    collision: object = None
+
+    @property
+    def dx(self):
+        return (self.x_hi - self.x_lo) / self.nx
+
+    @property
+    def dy(self):
+        return (self.y_hi - self.y_lo) / self.ny
+
+    @property
+    def wx(self):
+        return self.dx * self.dy
+
+    @property
+    def dvd(self):
+        return self.vs.dv ** self.vs.d
+
+    def vel(self, axis: int):
+        return oc.grid(self.vs)[axis].reshape(-1)
+
+    def face_cells(self, k: int) -> np.ndarray:
+        """Cells along face k (x_lo, x_hi, y_lo, y_hi), in order of the other
+        coordinate."""
+        ix = np.arange(self.nx)
+        iy = np.arange(self.ny)
+        if k == 0:
+            return iy
+        if k == 1:
+            return (self.nx - 1) * self.ny + iy
+        if k == 2:
+            return ix * self.ny
+        return ix * self.ny + self.ny - 1
+
+    def face_normal(self, k: int):
+        """(velocity axis, sign of the outward normal)."""
+        return (0 if k < 2 else 1), (-1.0 if k % 2 == 0 else 1.0)
+
+
+def _face_rows(prob: Problem2D, k: int) -> np.ndarray:
+    f = np.asarray(prob.faces[k][0], dtype=np.float64)
+    m = len(prob.face_cells(k))
+    return np.broadcast_to(f, (m, prob.vs.n)) if f.ndim == 1 else f
+
+
+def face_boundary_rows(prob: Problem2D, k: int, F_adj: np.ndarray) -> np.ndarray:
+    """The boundary function of face k at each of its cells (incoming half
+    used by the callers): the prescribed rows, or rho_w M_w with rho_w from
+    the outgoing flux of F_adj (the adjacent cells' distributions, one row per
+    face cell) through the face."""
+    M = _face_rows(prob, k)
+    if not prob.faces[k][1]:
+        return M
+    axis, sgn = prob.face_normal(k)
+    vn = sgn * prob.vel(axis)
+    out = vn >= 0
+    num = F_adj[:, out] @ vn[out]
+    den = M[:, ~out] @ vn[~out]
+    return (-num / den)[:, None] * M
+
+
+def _incoming(prob: Problem2D, k: int) -> np.ndarray:
+    axis, sgn = prob.face_normal(k)
+    return sgn * prob.vel(axis) < 0
+
+
+def ghosts_2d(K: np.ndarray, V: np.ndarray, prob: Problem2D):
+    """Ghost rows of K on every face cell (eq. boundary general):
+    K_j = <f_bdy 1_in, V_j>_v + sum_l K_l(adjacent cell) <1_out V_l V_j>_v."""
+    out = []
+    for k in range(4):
+        cells = prob.face_cells(k)
+        inc = _incoming(prob, k).astype(np.float64)
+        Kc = K[cells]
+        fb = face_boundary_rows(prob, k, Kc @ V)
+        Mo = prob.dvd * (V * (1.0 - inc)) @ V.T
+        out.append(prob.dvd * (fb * inc) @ V.T + Kc @ Mo)
+    return out
+
+
+def _shift(K: np.ndarray, prob: Problem2D, axis: int, step: int, ghost: np.ndarray):
+    """K at the neighbour p + step e_axis of every cell, the face ghost where
+    that neighbour lies outside."""
+    G = K.reshape(prob.nx, prob.ny, -1)
+    sh = np.roll(G, -step, axis=axis).copy()
+    if axis == 0:
+        sh[-1 if step > 0 else 0, :, :] = ghost
+    else:
+        sh[:, -1 if step > 0 else 0, :] = ghost
+    return sh.reshape(K.shape)
+
+
+def d_plus_2d(K, g, prob, axis):
+    """(K_p - K_{p - e_axis}) / h_axis with the low face's ghost."""
+    h = prob.dx if axis == 0 else prob.dy
+    return (K - _shift(K, prob, axis, -1, g[2 * axis])) / h
+
+
+def d_minus_2d(K, g, prob, axis):
+    """(K_{p + e_axis} - K_p) / h_axis with the high face's ghost."""
+    h = prob.dx if axis == 0 else prob.dy
+    return (_shift(K, prob, axis, 1, g[2 * axis + 1]) - K) / h
+
+
+def transport_matrices_2d(V, prob: Problem2D):
+    """[(A+, A-) for each axis], A+-_{jl} = <v_a^+- V_j V_l>_v."""
+    res = []
+    for a in range(2):
+        va = prob.vel(a)
+        res.append((prob.dvd * (V * np.maximum(va, 0.0)) @ V.T,
+                    prob.dvd * (V * np.minimum(va, 0.0)) @ V.T))
+    return res
+
+
+def ksl_step_2d(st: State, prob: Problem2D, dt: float, Qs=None):
+    """The K -> S -> L step of ksl_step with both axes' upwind terms."""
+    X, S, V = st.X, st.S, st.V
+    r = S.shape[0]
+    wx, dvd = prob.wx, prob.dvd
+    pairs = pair_list(r)
+    wts = np.array([1.0 if m == n else 2.0 for (m, n) in pairs])
+    if Qs is None:
+        Qs, _ = evaluate_pairs(V, pairs, prob)
+    A = transport_matrices_2d(V, prob)
+    Cj = collision_tensor(V, Qs, prob)
+
+    def transport_K(K):
+        g = ghosts_2d(K, V, prob)
+        return sum(d_plus_2d(K, g, prob, a) @ A[a][0].T + d_minus_2d(K, g, prob, a) @ A[a][1].T
+                   for a in range(2))
+
+    # K-step
+    K = X @ S
+    K1 = K + dt * (-transport_K(K) + pair_products(K, pairs, wts) @ Cj.T)
+    X1, S1 = weighted_qr_cols(K1, wx)
+    # S-step
+    Kn = X1 @ S1
+    g = ghosts_2d(Kn, V, prob)
+    acc = np.zeros((r, r))
+    for a in range(2):
+        acc += wx * X1.T @ d_plus_2d(Kn, g, prob, a) @ A[a][0].T
+        acc += wx * X1.T @ d_minus_2d(Kn, g, prob, a) @ A[a][1].T
+    T = wx * X1.T @ pair_products(Kn, pairs, wts)
+    S2 = S1 + dt * (acc - T @ Cj.T)
+    # L-step
+    L = S2 @ V
+    Kt = X1 @ S2
+    g = ghosts_2d(Kt, V, prob)
+    L1 = L + dt * (wx * X1.T @ pair_products(Kt, pairs, wts)) @ Qs
+    for a in range(2):
+        va = prob.vel(a)
+        L1 -= dt * (wx * X1.T @ d_plus_2d(Kt, g, prob, a) @ V) * np.maximum(va, 0.0)[None, :]
+        L1 -= dt * (wx * X1.T @ d_minus_2d(Kt, g, prob, a) @ V) * np.minimum(va, 0.0)[None, :]
+    Vq, R = weighted_qr_cols(L1.T, dvd)
+    # residual from the pieces (Sec. 5.1)
+    dK, dS, dL = K1 - K, S2 - S1, L1 - L
+    kx = wx * X1.T @ dK
+    lv = dvd * dL @ V.T
+    e2 = wx * (dK ** 2).sum() + (dS ** 2).sum() + dvd * (dL ** 2).sum() \
+        + 2.0 * (kx * dS).sum() + 2.0 * (lv * dS).sum() + 2.0 * (kx * lv).sum()
+    err = math.sqrt(max(e2, 0.0))
+    pieces = dict(K1=K1, S1=S1, S2=S2, L1=L1, X1=X1, Qs=Qs, Cj=Cj, e2=e2)
+    return State(X1, R.T, Vq.T), err, pieces
+
+
+def boundary_matrix_2d(st: State, prob: Problem2D):
+    """F_b: one row f^b(x_b, .) per face cell of every face (a corner cell
+    once per face): the boundary function on the incoming half, the adjacent
+    cell on the outgoing half."""
+    K = st.X @ st.S
+    rows = []
+    for k in range(4):
+        Fa = K[prob.face_cells(k)] @ st.V
+        rows.append(np.where(_incoming(prob, k)[None, :], face_boundary_rows(prob, k, Fa), Fa))
+    return np.vstack(rows)
+
+
+def full_step_2d(F: np.ndarray, prob: Problem2D, dt: float):
+    """Full-tensor step on the rectangle: f_p <- f_p - dt sum_a (v_a^+ D^a_+ f +
+    v_a^- D^a_- f)_p + dt Q_s(f_p, f_p), ghosts on every face cell the
+    boundary row (boundary function on the incoming half; the outgoing half
+    multiplies a zero velocity part)."""
+    g = [face_boundary_rows(prob, k, F[prob.face_cells(k)]) for k in range(4)]
+    Q, _ = evaluate_pairs(F, [(p, p) for p in range(F.shape[0])], prob)
+    Fn = F + dt * Q
+    for a in range(2):
+        va = prob.vel(a)
+        Fn = Fn - dt * (np.maximum(va, 0.0) * d_plus_2d(F, g, prob, a)
+                        + np.minimum(va, 0.0) * d_minus_2d(F, g, prob, a))
+    err = math.sqrt(prob.wx * prob.dvd * float(((Fn - F) ** 2).sum()))
     return Fn, err
 
 
