@@ -143,6 +143,25 @@ typedef struct {
   const double* f_right;
   blr_vgrid v;
   int32_t wall_left, wall_right;
+  /* Two-dimensional physical space (Sec. 2.2, the upwind scheme applied along
+   * each axis of a rectangular grid; Sec. 2.3 on every face) when ny >= 2:
+   * [x_lo, x_hi] x [y_lo, y_hi] with nx x ny cells, cell p = ix ny + iy (the
+   * row of F), velocity axis 0 along x and 1 along y.  f_bottom / f_top are
+   * the boundary functions of the faces y = y_lo / y_hi (v_2 > 0 / v_2 < 0
+   * incoming), wall_bottom / wall_top as wall_left / wall_right.  face_rows
+   * bit k (k = 0 x_lo, 1 x_hi, 2 y_lo, 3 y_hi) set: that face's array holds
+   * one row of n^d values per face cell (ny rows on an x face, nx on a y
+   * face, in order of the other coordinate), for boundary functions that vary
+   * along the face; clear: one row for the whole face.  A diffusive wall's
+   * rho_w is then set per face cell.  ny = 0 or 1: one-dimensional space
+   * (these fields are ignored).  In two dimensions only blr_full_step is
+   * available; the low-rank calls return BLR_ERR_UNSUPPORTED. */
+  int32_t ny;
+  double y_lo, y_hi;
+  const double* f_bottom;
+  const double* f_top;
+  int32_t wall_bottom, wall_top;
+  int32_t face_rows;
 } blr_problem;
 
 /* Low-rank state f = sum_ij X_i S_ij V_j (eq. lowrank decomposition) with

@@ -56,7 +56,11 @@ class VGrid(ctypes.Structure):
 class Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
                 ("f_left", ctypes.c_void_p), ("f_right", ctypes.c_void_p), ("v", VGrid),
-                ("wall_left", ctypes.c_int32), ("wall_right", ctypes.c_int32)]
+                ("wall_left", ctypes.c_int32), ("wall_right", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double),
+                ("f_bottom", ctypes.c_void_p), ("f_top", ctypes.c_void_p),
+                ("wall_bottom", ctypes.c_int32), ("wall_top", ctypes.c_int32),
+                ("face_rows", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
@@ -230,6 +234,27 @@ class Context:
         pb._keep = (fL, fR)
         return pb
 
+    def make_problem2d(self, vg: VGrid, nx: int, ny: int, x_lo: float, x_hi: float, y_lo: float,
+                       y_hi: float, faces) -> Problem:
+        """Rectangle with nx x ny cells (cell ix ny + iy).  faces: four (f, wall)
+        pairs for x_lo, x_hi, y_lo, y_hi; f a float64 CUDA tensor of n^d values
+        (one row for the face) or (face cells, n^d) (one row per face cell:
+        ny on an x face, nx on a y face); wall=True: a Maxwell diffusive wall
+        whose Maxwellian shape f is."""
+        assert len(faces) == 4
+        rows = 0
+        for k, (f, _) in enumerate(faces):
+            assert f.dtype.itemsize == 8 and f.is_contiguous()
+            if f.dim() == 2:
+                assert f.shape[0] == (ny if k < 2 else nx)
+                rows |= 1 << k
+        f = [ctypes.c_void_p(t.data_ptr()) for t, _ in faces]
+        w = [int(bool(x)) for _, x in faces]
+        pb = Problem(nx, float(x_lo), float(x_hi), f[0], f[1], vg, w[0], w[1], ny, float(y_lo),
+                     float(y_hi), f[2], f[3], w[2], w[3], rows)
+        pb._keep = tuple(t for t, _ in faces)
+        return pb
+
     def make_state(self, X, S, V, r: int, seed: int = 0) -> State:
         """X (r_cap, nx), S (r_cap, r_cap), V (r_cap, n^d): float64 CUDA tensors."""
         r_cap = X.shape[0]
@@ -261,9 +286,10 @@ class Context:
 
     # ------------------------------------------------------ full tensor --
     def full_step(self, pb: Problem, F, dt: float, prec: int = BLR_FP32) -> float:
-        """One full-tensor step of F (float64 CUDA tensor, nx x n^d, updated
-        in place); returns err_full."""
-        assert F.dtype.itemsize == 8 and F.is_contiguous() and F.shape[0] == pb.nx
+        """One full-tensor step of F (float64 CUDA tensor of nx (nx ny on a
+        rectangle) rows of n^d values, updated in place); returns err_full."""
+        cells = pb.nx * (pb.ny if pb.ny >= 2 else 1)
+        assert F.dtype.itemsize == 8 and F.is_contiguous() and F.shape[0] == cells
         err = ctypes.c_double()
         self._check(self.lib.blr_full_step(self.h, ctypes.byref(pb), prec,
                                            ctypes.c_void_p(F.data_ptr()), float(dt),

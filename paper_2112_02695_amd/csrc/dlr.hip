@@ -1142,6 +1142,9 @@ void validate_problem(const blr_problem* pb, const blr_state* st) {
   require(pb->f_left && pb->f_right, "null inflow boundary arrays");
   require((pb->wall_left == 0 || pb->wall_left == 1) && (pb->wall_right == 0 || pb->wall_right == 1),
           "problem.wall_left / wall_right must be 0 (inflow) or 1 (diffusive wall)");
+  require(pb->ny <= 1, "the low-rank step runs in one-dimensional space (problem.ny <= 1)",
+          BLR_ERR_UNSUPPORTED);
+  require(pb->face_rows == 0, "problem.face_rows: one-dimensional space takes one row per face");
   validate_vgrid(pb->v);
   require(st->X && st->S && st->V, "null state arrays");
   require(st->r_cap >= 1 && st->r_cap <= 64, "state.r_cap must be in [1, 64]");
@@ -1795,6 +1798,8 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
 void state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0, int r, blr_state* st) {
   require(pb && st && f0, "null argument");
   validate_vgrid(pb->v);
+  require(pb->ny <= 1, "state_from_full: one-dimensional space (problem.ny <= 1)",
+          BLR_ERR_UNSUPPORTED);
   require(st->r_cap >= r && r >= 1, "r must be in [1, r_cap]");
   require(pb->nx <= 64, "state_from_full: nx must be <= 64", BLR_ERR_UNSUPPORTED);
   const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;

@@ -73,6 +73,92 @@ __global__ __launch_bounds__(256) void k_full_update(const double* __restrict__ 
   if (threadIdx.x == 0) part[(long)p * gridDim.x + blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
+// ------------------------------------------------------------ 2D space
+// Boundary functions of the four faces (x_lo, x_hi, y_lo, y_hi); bit k of
+// `rows`: face k holds one row per face cell.
+struct Faces {
+  const double* f[4];
+  int rows;
+  __device__ __forceinline__ const double* row(int k, int c, int n) const {
+    return f[k] + (((rows >> k) & 1) ? (long)c * n : 0L);
+  }
+};
+
+// rho of every face cell (x_lo: ny cells, x_hi: ny, y_lo: nx, y_hi: nx, in
+// that order): rho_w of a diffusive wall from the adjacent cell's
+// distribution (Sec. 2.3), 1 on an inflow face.  One block per face cell.
+__global__ __launch_bounds__(1024) void k_full_face_rho2d(const double* __restrict__ F, int nx,
+                                                          int ny, int n, Faces fc, int walls,
+                                                          double L, double dv, int plane,
+                                                          int stride1, int N,
+                                                          double* __restrict__ rho) {
+  const int b = blockIdx.x;
+  int k, c;
+  if (b < ny) {
+    k = 0; c = b;
+  } else if (b < 2 * ny) {
+    k = 1; c = b - ny;
+  } else if (b < 2 * ny + nx) {
+    k = 2; c = b - 2 * ny;
+  } else {
+    k = 3; c = b - 2 * ny - nx;
+  }
+  if (!((walls >> k) & 1)) {
+    if (threadIdx.x == 0) rho[b] = 1.0;
+    return;
+  }
+  const long cell = k == 0 ? c : k == 1 ? (long)(nx - 1) * ny + c : k == 2 ? (long)c * ny
+                                                                         : (long)c * ny + ny - 1;
+  __shared__ double red[1024 / 64 + 1];
+  const double v = wall::density_face<1024>((k % 2 == 0) ? -1.0 : 1.0, F + cell * n,
+                                            fc.row(k, c, n), n, L, dv, k < 2 ? plane : stride1,
+                                            N, red);
+  if (threadIdx.x == 0) rho[b] = v;
+}
+
+// The update of k_full_update on the rectangle: cells p0 .. p0 + gridDim.y - 1
+// (p = ix ny + iy), upwind differences along x (v_1) and y (v_2), ghosts
+// rho f_face on the incoming half of a face (the cell itself elsewhere: that
+// half multiplies a zero velocity part).
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_full_update2d(const double* __restrict__ F, int nx,
+                                                       int ny, int n, long p0,
+                                                       const TQ* __restrict__ Q, Faces fc,
+                                                       const double* __restrict__ rho, double dt,
+                                                       double dx, double dy, double L, double dv,
+                                                       int plane, int stride1, int N,
+                                                       double* __restrict__ Fn,
+                                                       double* __restrict__ part) {
+  __shared__ double ws[4];
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  const long p = p0 + blockIdx.y;
+  const int ix = (int)(p / ny), iy = (int)(p % ny);
+  double e2 = 0.0;
+  if (q < n) {
+    const double v1 = -L + (q / plane) * dv;
+    const double v2 = -L + ((q / stride1) % N) * dv;
+    const double* fp = F + p * n + q;
+    const double f = fp[0];
+    const long sx = (long)ny * n;
+    const double fxm = ix > 0 ? fp[-sx] : (v1 > 0 ? rho[iy] * fc.row(0, iy, n)[q] : f);
+    const double fxp = ix < nx - 1 ? fp[sx] : (v1 < 0 ? rho[ny + iy] * fc.row(1, iy, n)[q] : f);
+    const double fym = iy > 0 ? fp[-n] : (v2 > 0 ? rho[2 * ny + ix] * fc.row(2, ix, n)[q] : f);
+    const double fyp =
+        iy < ny - 1 ? fp[n] : (v2 < 0 ? rho[2 * ny + nx + ix] * fc.row(3, ix, n)[q] : f);
+    const double v1p = v1 > 0 ? v1 : 0.0, v1m = v1 < 0 ? v1 : 0.0;
+    const double v2p = v2 > 0 ? v2 : 0.0, v2m = v2 < 0 ? v2 : 0.0;
+    const double d = -dt * ((v1p * (f - fxm) + v1m * (fxp - f)) / dx +
+                            (v2p * (f - fym) + v2m * (fyp - f)) / dy) +
+                     dt * (double)Q[(long)blockIdx.y * n + q];
+    Fn[p * n + q] = f + d;
+    e2 = d * d;
+  }
+  for (int off = 32; off > 0; off >>= 1) e2 += __shfl_down(e2, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) part[p * gridDim.x + blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
 // err = sqrt(w sum part) over cnt partials, one block, fixed order
 __global__ __launch_bounds__(256) void k_err_total(const double* __restrict__ part, long cnt,
                                                    double w, double* __restrict__ err) {
@@ -104,31 +190,58 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
           "problem.wall_left / wall_right must be 0 (inflow) or 1 (diffusive wall)");
   require(prec == BLR_FP32 || prec == BLR_FP64, "bad precision");
   require(std::isfinite(dt) && dt >= 0.0, "dt must be finite and >= 0");
+  const bool two_d = pb->ny >= 2;
+  if (two_d) {
+    require(pb->ny <= (1 << 20) && (long)pb->nx * pb->ny <= (1L << 22),
+            "problem.ny must be <= 2^20 and nx * ny <= 2^22");
+    require(pb->y_hi > pb->y_lo, "y_hi must exceed y_lo");
+    require(pb->f_bottom && pb->f_top, "null boundary function of a y face");
+    require((pb->wall_bottom == 0 || pb->wall_bottom == 1) &&
+                (pb->wall_top == 0 || pb->wall_top == 1),
+            "problem.wall_bottom / wall_top must be 0 (inflow) or 1 (diffusive wall)");
+    require(pb->face_rows >= 0 && pb->face_rows <= 15, "problem.face_rows must be in [0, 15]");
+  } else {
+    require(pb->ny >= 0, "problem.ny must be >= 0");
+    require(pb->face_rows == 0, "problem.face_rows: one-dimensional space takes one row per face");
+  }
   const DevTables& tb = get_tables(ctx, pb->v, prec);
   const HostTables& h = tb.h;
   hipStream_t s = ctx->stream;
-  const int nx = pb->nx, n = h.n;
-  const double dx = (pb->x_hi - pb->x_lo) / nx, dvd = std::pow(h.dv, h.d);
+  const int nx = pb->nx, ny = two_d ? pb->ny : 1, n = h.n;
+  const long ncells = (long)nx * ny;
+  const double dx = (pb->x_hi - pb->x_lo) / nx;
+  const double dy = two_d ? (pb->y_hi - pb->y_lo) / ny : 1.0;
+  const double dvd = std::pow(h.dv, h.d);
   const int plane = h.d == 3 ? h.N * h.N : h.N;
+  const int stride1 = h.d == 3 ? h.N : 1;  // velocity axis 1 (along y)
   const int esz = prec == BLR_FP32 ? 4 : 8;
-  const int chunk = std::min(nx, fk::kChunk);
-  double* Fn = (double*)ctx->buf("full.Fn", (size_t)nx * n * sizeof(double));
+  const int chunk = (int)std::min<long>(ncells, fk::kChunk);
+  double* Fn = (double*)ctx->buf("full.Fn", (size_t)ncells * n * sizeof(double));
   void* Q = ctx->buf("full.Q", (size_t)chunk * n * esz);
   float* F32 = prec == BLR_FP32 ? (float*)ctx->buf("full.F32", (size_t)chunk * n * sizeof(float))
                                 : nullptr;
   const unsigned nbx = nblocks(n, 256);
-  double* part = (double*)ctx->buf("full.part", (size_t)nx * nbx * sizeof(double));
+  double* part = (double*)ctx->buf("full.part", (size_t)ncells * nbx * sizeof(double));
   double* err = (double*)ctx->buf("full.err", sizeof(double));
   // rho_w from the cells next to the walls before any cell is updated
-  double* rho = (double*)ctx->buf("full.rho", 2 * sizeof(double));
-  hipLaunchKernelGGL(fk::k_full_wall_rho, dim3(2), dim3(1024), 0, s, F, nx, n, pb->f_left,
-                     pb->f_right, pb->wall_left, pb->wall_right, h.L, h.dv, plane, rho);
+  const int nrho = two_d ? 2 * (nx + ny) : 2;
+  double* rho = (double*)ctx->buf("full.rho", (size_t)nrho * sizeof(double));
+  fk::Faces fc{{pb->f_left, pb->f_right, pb->f_bottom, pb->f_top}, pb->face_rows};
+  if (two_d) {
+    const int walls = pb->wall_left | (pb->wall_right << 1) | (pb->wall_bottom << 2) |
+                      (pb->wall_top << 3);
+    hipLaunchKernelGGL(fk::k_full_face_rho2d, dim3(nrho), dim3(1024), 0, s, F, nx, ny, n, fc,
+                       walls, h.L, h.dv, plane, stride1, h.N, rho);
+  } else {
+    hipLaunchKernelGGL(fk::k_full_wall_rho, dim3(2), dim3(1024), 0, s, F, nx, n, pb->f_left,
+                       pb->f_right, pb->wall_left, pb->wall_right, h.L, h.dv, plane, rho);
+  }
   BLR_CHECK_LAUNCH();
   std::vector<int32_t> pairs(2 * chunk);
-  for (int p0 = 0; p0 < nx; p0 += chunk) {
-    const int np = std::min(chunk, nx - p0);
+  for (long p0 = 0; p0 < ncells; p0 += chunk) {
+    const int np = (int)std::min<long>(chunk, ncells - p0);
     for (int i = 0; i < np; ++i) pairs[2 * i] = pairs[2 * i + 1] = i;
-    const double* rows = F + (long)p0 * n;
+    const double* rows = F + p0 * n;
     if (prec == BLR_FP32) {
       hipLaunchKernelGGL(fk::k_cast_f32, dim3(nblocks((long)np * n, 256)), dim3(256), 0, s, rows,
                          (long)np * n, F32);
@@ -138,20 +251,31 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
       collision_pairs(ctx, pb->v, BLR_FP64, rows, np, pairs.data(), np, Q);
     }
     timed_begin("full.update", (double)np * n * 8.0 * (3.0 + 1.0) + (double)np * n * esz, s);
-    if (prec == BLR_FP32)
-      hipLaunchKernelGGL(fk::k_full_update<float>, dim3(nbx, np), dim3(256), 0, s, F, nx, n, p0,
-                         (const float*)Q, pb->f_left, pb->f_right, rho, dt, dx, h.L, h.dv, plane, Fn,
-                         part);
-    else
-      hipLaunchKernelGGL(fk::k_full_update<double>, dim3(nbx, np), dim3(256), 0, s, F, nx, n, p0,
-                         (const double*)Q, pb->f_left, pb->f_right, rho, dt, dx, h.L, h.dv, plane, Fn,
-                         part);
+    if (two_d) {
+      if (prec == BLR_FP32)
+        hipLaunchKernelGGL(fk::k_full_update2d<float>, dim3(nbx, np), dim3(256), 0, s, F, nx, ny,
+                           n, p0, (const float*)Q, fc, rho, dt, dx, dy, h.L, h.dv, plane, stride1,
+                           h.N, Fn, part);
+      else
+        hipLaunchKernelGGL(fk::k_full_update2d<double>, dim3(nbx, np), dim3(256), 0, s, F, nx, ny,
+                           n, p0, (const double*)Q, fc, rho, dt, dx, dy, h.L, h.dv, plane, stride1,
+                           h.N, Fn, part);
+    } else if (prec == BLR_FP32) {
+      hipLaunchKernelGGL(fk::k_full_update<float>, dim3(nbx, np), dim3(256), 0, s, F, nx, n,
+                         (int)p0, (const float*)Q, pb->f_left, pb->f_right, rho, dt, dx, h.L,
+                         h.dv, plane, Fn, part);
+    } else {
+      hipLaunchKernelGGL(fk::k_full_update<double>, dim3(nbx, np), dim3(256), 0, s, F, nx, n,
+                         (int)p0, (const double*)Q, pb->f_left, pb->f_right, rho, dt, dx, h.L,
+                         h.dv, plane, Fn, part);
+    }
     BLR_CHECK_LAUNCH();
     timed_end(s);
   }
-  hipLaunchKernelGGL(fk::k_err_total, dim3(1), dim3(256), 0, s, part, (long)nx * nbx, dx * dvd, err);
+  hipLaunchKernelGGL(fk::k_err_total, dim3(1), dim3(256), 0, s, part, ncells * nbx, dx * dy * dvd,
+                     err);
   BLR_CHECK_LAUNCH();
-  BLR_HIP(hipMemcpyAsync(F, Fn, (size_t)nx * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  BLR_HIP(hipMemcpyAsync(F, Fn, (size_t)ncells * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   double* hb = (double*)ctx->host_readback(sizeof(double));
   BLR_HIP(hipMemcpyAsync(hb, err, sizeof(double), hipMemcpyDeviceToHost, s));
   BLR_HIP(hipStreamSynchronize(s));

@@ -24,20 +24,23 @@ __device__ __forceinline__ bool incoming(int side, double v1) {
 }
 
 // rho_w from the outgoing half of `fadj` (n values) and the wall Maxwellian
-// shape M, summed by one block of NT threads in a fixed order (strided
-// per-thread sums, wave sums, then the waves in order); every thread
-// returns the value.  v_1 of point q is -L + (q / plane) dv.  `red` holds
-// NT / 64 + 1 doubles of shared memory.  Ends with a barrier.
+// shape M, for a face whose outward normal is sgn e_axis, with v_axis of point
+// q = -L + ((q / stride) % N) dv; summed by one block of NT threads in a fixed
+// order (strided per-thread sums, wave sums, then the waves in order); every
+// thread returns the value.  `red` holds NT / 64 + 1 doubles of shared
+// memory.  Ends with a barrier.
 template <int NT>
-__device__ double density(int side, const double* __restrict__ fadj,
-                          const double* __restrict__ M, int n, double L, double dv, int plane,
-                          double* red) {
+__device__ double density_face(double sgn, const double* __restrict__ fadj,
+                               const double* __restrict__ M, int n, double L, double dv,
+                               int stride, int N, double* red) {
   constexpr int NW = NT / 64;
   double num = 0.0, den = 0.0;
   for (int q = threadIdx.x; q < n; q += NT) {
-    const double v1 = -L + (q / plane) * dv;
-    num += out_weight(side, v1) * fadj[q];
-    den += in_weight(side, v1) * M[q];
+    const double vn = sgn * (-L + ((q / stride) % N) * dv);
+    if (vn >= 0.0)
+      num += vn * fadj[q];
+    else
+      den -= vn * M[q];
   }
   for (int off = 32; off > 0; off >>= 1) {
     num += __shfl_down(num, off, 64);
@@ -59,6 +62,15 @@ __device__ double density(int side, const double* __restrict__ fadj,
   }
   __syncthreads();
   return red[NW];
+}
+
+// The x faces of the one-dimensional space: side 0 = x_lo, 1 = x_hi, v_1 of
+// point q = -L + (q / plane) dv.
+template <int NT>
+__device__ double density(int side, const double* __restrict__ fadj,
+                          const double* __restrict__ M, int n, double L, double dv, int plane,
+                          double* red) {
+  return density_face<NT>(side == 0 ? -1.0 : 1.0, fadj, M, n, L, dv, plane, n / plane, red);
 }
 
 }  // namespace wall

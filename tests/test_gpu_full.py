@@ -1,7 +1,9 @@
 """GPU parity of blr_full_step (the full-tensor reference step, eq.
 scheme:fullupwind of Sec. 2.2, walls of Sec. 2.3, err_full of eq. err full
-grid) against the oracle's full_step, on seeded shock-like inputs and on gas
-between Maxwell diffusive walls.
+grid) against the oracle's full_step, on seeded shock-like inputs, on gas
+between Maxwell diffusive walls, and on a rectangle (two-dimensional space)
+with inflow and wall faces, some with boundary functions varying along the
+face.
 
 Error measure: ||dF_gpu - dF_ref|| / ||dF_ref|| for the update dF = F_new - F,
 bounded by 1e-12 with FP64 collisions.  With FP32 collisions the bound is the
@@ -119,3 +121,71 @@ def test_full_step_rejects_bad_arguments(ctx):
     before = F.clone()
     e = ctx.full_step(pb, F, 0.0, blr.BLR_FP64)   # dt = 0: nothing moves
     assert e == 0.0 and torch.equal(F, before)
+
+
+# ------------------------------------------------------------------ 2D space
+def _maxw(spec, rho, u, T):
+    v = synth.vgrid_points(spec.d, spec.n, spec.L)
+    return synth.maxwellian(v, rho, u, T).reshape(-1)
+
+
+def _rect_case(ctx, d, n, m_rho, nx, ny, prec, dt=0.004, seed=7):
+    """x_lo inflow, x_hi wall (T 1.2), y_lo wall moving along x, y_hi inflow
+    with one row per face cell (temperature varying along the face)."""
+    spec = _spec(d, n, m_rho)
+    vs = oc.setup_from_spec(spec)
+    z = (0.0,) * (d - 2)
+    rng = np.random.default_rng(seed)
+    F = np.array([_maxw(spec, 1.0 + 0.1 * rng.random(), (0.3 * rng.standard_normal(),
+                                                        0.2 * rng.standard_normal()) + z,
+                        1.0 + 0.2 * rng.random()) for _ in range(nx * ny)])
+    top = np.array([_maxw(spec, 0.9, (0.1, -0.2) + z, 1.0 + 0.05 * i) for i in range(nx)])
+    faces = [(_maxw(spec, 1.0, (0.4, 0.0) + z, 1.0), False), (_maxw(spec, 1.0, (0.0, 0.0) + z, 1.2), True),
+             (_maxw(spec, 1.0, (0.3, 0.0) + z, 1.0), True), (top, False)]
+    prob = dlr.Problem2D(vs=vs, nx=nx, ny=ny, x_lo=0.0, x_hi=1.0, y_lo=0.0, y_hi=0.8, faces=faces)
+    Fref, eref = dlr.full_step(F, prob, dt)
+    dev_faces = [(torch.tensor(f, device="cuda"), w) for f, w in faces]
+    pb = ctx.make_problem2d(blr.vgrid_from_spec(spec), nx, ny, 0.0, 1.0, 0.0, 0.8, dev_faces)
+    Fd = torch.tensor(F, device="cuda")
+    e = ctx.full_step(pb, Fd, dt, prec)
+    torch.cuda.synchronize()
+    Fg = Fd.cpu().numpy()
+    diff = np.linalg.norm((Fg - F) - (Fref - F))
+    rel = diff / np.linalg.norm(Fref - F)
+    if prec == blr.BLR_FP32:
+        _, gain = oc.q_pairs(F, [(p, p) for p in range(nx * ny)], vs, conserve=True)
+        rel = diff / (dt * np.linalg.norm(gain))
+    return rel, e, eref
+
+
+@pytest.mark.parametrize("d,n,m_rho,nx,ny", [(2, 16, 8, 4, 3), (3, 8, 4, 3, 4), (2, 16, 4, 1, 5)])
+def test_full_step_on_a_rectangle_fp64(ctx, d, n, m_rho, nx, ny):
+    print(f"full step 2D space d={d} n={n} {nx}x{ny}", flush=True)
+    rel, e, eref = _rect_case(ctx, d, n, m_rho, nx, ny, blr.BLR_FP64)
+    print("rel", rel, "err", e, eref, flush=True)
+    assert rel < 1e-12
+    assert abs(e - eref) < 1e-12 * eref
+
+
+def test_full_step_on_a_rectangle_fp32_two_chunks(ctx):
+    """9 x 8 = 72 cells: two collision calls (64 + 8)."""
+    print("full step 2D space fp32 9x8", flush=True)
+    rel, e, eref = _rect_case(ctx, 2, 16, 4, 9, 8, blr.BLR_FP32)
+    print("rel", rel, "err", e, eref, flush=True)
+    assert rel < 1e-5
+    assert abs(e - eref) < 1e-5 * eref
+
+
+def test_low_rank_calls_refuse_two_dimensional_space(ctx):
+    spec = _spec(2, 16, 4)
+    f = torch.tensor(_maxw(spec, 1.0, (0.0, 0.0), 1.0), device="cuda")
+    pb = ctx.make_problem2d(blr.vgrid_from_spec(spec), 3, 3, 0.0, 1.0, 0.0, 1.0,
+                            [(f, False)] * 4)
+    X = torch.zeros((4, 9), dtype=torch.float64, device="cuda")
+    S = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
+    V = torch.zeros((4, 256), dtype=torch.float64, device="cuda")
+    S[0, 0] = 1.0
+    st = ctx.make_state(X, S, V, 1)
+    with pytest.raises(blr.BlrError) as ei:
+        ctx.dlr_step(pb, st, blr.StepParams(0.001, 0.2, 1e-10, 1, 4, 0))
+    assert ei.value.code == blr.BLR_ERR_UNSUPPORTED
