@@ -154,8 +154,10 @@ typedef struct {
    * face, in order of the other coordinate), for boundary functions that vary
    * along the face; clear: one row for the whole face.  A diffusive wall's
    * rho_w is then set per face cell.  ny = 0 or 1: one-dimensional space
-   * (these fields are ignored).  In two dimensions only blr_full_step is
-   * available; the low-rank calls return BLR_ERR_UNSUPPORTED. */
+   * (these fields are ignored).  In two dimensions blr_full_step,
+   * blr_dlr_step and blr_steady_solve run fixed-rank steps (the state's X
+   * has rows of nx ny values); BLR_STEP_ADD / BLR_STEP_DROP and
+   * blr_state_from_full return BLR_ERR_UNSUPPORTED there. */
   int32_t ny;
   double y_lo, y_hi;
   const double* f_bottom;

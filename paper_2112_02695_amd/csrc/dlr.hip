@@ -24,7 +24,12 @@ namespace blr {
 namespace dk {
 
 // weight of mode m at velocity point q (v1 = first velocity coordinate)
-enum Mode { W_ONE = 0, W_VPLUS, W_VMINUS, W_OUT_LEFT, W_OUT_RIGHT, W_IN_LEFT, W_IN_RIGHT };
+// (modes from W_V2PLUS on weigh by v_2, the velocity along y of the
+// two-dimensional space: its faces y_lo = "bottom" and y_hi = "top")
+enum Mode {
+  W_ONE = 0, W_VPLUS, W_VMINUS, W_OUT_LEFT, W_OUT_RIGHT, W_IN_LEFT, W_IN_RIGHT,
+  W_V2PLUS, W_V2MINUS, W_OUT_BOTTOM, W_OUT_TOP, W_IN_BOTTOM, W_IN_TOP
+};
 
 struct VGeo {
   double L, dv;
@@ -33,18 +38,31 @@ struct VGeo {
     const int q0 = d == 3 ? q / (N * N) : q / N;
     return -L + q0 * dv;
   }
+  __device__ __forceinline__ double v2(int q) const {
+    const int q1 = d == 3 ? (q / N) % N : q % N;
+    return -L + q1 * dv;
+  }
 };
 
-__device__ __forceinline__ double weight(int mode, double v1) {
+__device__ __forceinline__ double weight(int mode, double v) {
   switch (mode) {
-    case W_VPLUS: return v1 > 0 ? v1 : 0.0;
-    case W_VMINUS: return v1 < 0 ? v1 : 0.0;
-    case W_OUT_LEFT: return v1 <= 0 ? 1.0 : 0.0;
-    case W_OUT_RIGHT: return v1 >= 0 ? 1.0 : 0.0;
-    case W_IN_LEFT: return v1 > 0 ? 1.0 : 0.0;
-    case W_IN_RIGHT: return v1 < 0 ? 1.0 : 0.0;
+    case W_VPLUS:
+    case W_V2PLUS: return v > 0 ? v : 0.0;
+    case W_VMINUS:
+    case W_V2MINUS: return v < 0 ? v : 0.0;
+    case W_OUT_LEFT:
+    case W_OUT_BOTTOM: return v <= 0 ? 1.0 : 0.0;
+    case W_OUT_RIGHT:
+    case W_OUT_TOP: return v >= 0 ? 1.0 : 0.0;
+    case W_IN_LEFT:
+    case W_IN_BOTTOM: return v > 0 ? 1.0 : 0.0;
+    case W_IN_RIGHT:
+    case W_IN_TOP: return v < 0 ? 1.0 : 0.0;
     default: return 1.0;
   }
+}
+__device__ __forceinline__ double weight(int mode, const VGeo& g, int q) {
+  return weight(mode, mode >= W_V2PLUS ? g.v2(q) : g.v1(q));
 }
 
 constexpr int GT = 16;  // output tile edge (rows of A x rows of B)
@@ -99,7 +117,7 @@ __global__ __launch_bounds__(256) void k_gram_batch(GramBatch gb, long n, int nc
     for (int u = 0; u < 8; ++u) {
       const long q = qb + 4 * u + kk;
       const bool in = q < w1;
-      xa[u] = (in && arow) ? pa[q] * weight(sg.mode, g.v1((int)q)) : 0.0;
+      xa[u] = (in && arow) ? pa[q] * weight(sg.mode, g, (int)q) : 0.0;
       yb[u] = (in && brow) ? (sg.bfloat ? (double)pbf[q] : pbd[q]) : 0.0;
     }
 #pragma unroll
@@ -1072,6 +1090,256 @@ __global__ __launch_bounds__(256) void k_fnD16(const double* S, const double* A,
   }
 }
 
+// ===================================================== two-dimensional space
+// Rectangle with nx x ny cells, cell p = ix ny + iy; arrays over cells are
+// rows of nc = nx ny values.  Faces 0 x_lo, 1 x_hi, 2 y_lo, 3 y_hi; the face
+// cells of all four faces are numbered b = [x_lo: ny][x_hi: ny][y_lo: nx]
+// [y_hi: nx], each face in order of the other coordinate.
+
+__device__ __forceinline__ void face_of(int b, int nx, int ny, int& k, int& c) {
+  if (b < ny) {
+    k = 0; c = b;
+  } else if (b < 2 * ny) {
+    k = 1; c = b - ny;
+  } else if (b < 2 * ny + nx) {
+    k = 2; c = b - 2 * ny;
+  } else {
+    k = 3; c = b - 2 * ny - nx;
+  }
+}
+__device__ __forceinline__ long face_cell(int k, int c, int nx, int ny) {
+  return k == 0 ? c : k == 1 ? (long)(nx - 1) * ny + c : k == 2 ? (long)c * ny
+                                                             : (long)c * ny + ny - 1;
+}
+
+// Velocity-side pieces of one face: Mo = <1_out V_l V_j> (r x r), gin =
+// <f_c 1_in, V_j> (r x rows, rows = 1 or one per face cell).  A diffusive
+// wall (wall = 1) also has a_l = sa sum_q (v.n)_out V_l and den_c = sd sum_q
+// |v.n|_in f_c, so that rho_w(c) = (sum_l K_l(c) a_l) / den_c.
+struct Face2 {
+  const double* Mo;
+  const double* gin;
+  const double* a;
+  const double* den;
+  int rows, wall;
+  double sa, sd;
+};
+struct Faces2 {
+  Face2 f[4];
+};
+
+// Ghost rows of K on every face cell (eq. boundary general):
+//   G[b][j] = sum_l K_l(c) Mo_lj + (inflow: gin_jc; wall: rho_w(c) gin_jc).
+__global__ void k_ghosts2d(const double* __restrict__ K, int r, int nx, int ny, Faces2 fs,
+                           double* __restrict__ G) {
+  const int b = blockIdx.x, j = threadIdx.x;
+  if (j >= r) return;
+  int k, c;
+  face_of(b, nx, ny, k, c);
+  const long nc = (long)nx * ny, p = face_cell(k, c, nx, ny);
+  const Face2& F = fs.f[k];
+  const int cr = F.rows > 1 ? c : 0;
+  double g = 0.0;
+  for (int l = 0; l < r; ++l) g += K[l * nc + p] * F.Mo[l * r + j];
+  if (F.wall) {
+    double ka = 0.0;
+    for (int l = 0; l < r; ++l) ka += K[l * nc + p] * F.a[l];
+    g += (F.sa * ka) / (F.sd * F.den[cr]) * F.gin[(long)j * F.rows + cr];
+  } else {
+    g += F.gin[(long)j * F.rows + cr];
+  }
+  G[(long)b * r + j] = g;
+}
+
+// K_l at the neighbour p + step e_axis (step = -1 or 1), the face ghost where
+// that neighbour lies outside
+__device__ __forceinline__ double nb2(const double* K, const double* G, int r, int nx, int ny,
+                                      int l, long p, int axis, int step) {
+  const long nc = (long)nx * ny;
+  const int ix = (int)(p / ny), iy = (int)(p % ny);
+  if (axis == 0) {
+    const int i = ix + step;
+    if (i >= 0 && i < nx) return K[l * nc + p + (long)step * ny];
+    return G[(long)(step < 0 ? iy : ny + iy) * r + l];
+  }
+  const int i = iy + step;
+  if (i >= 0 && i < ny) return K[l * nc + p + step];
+  return G[(long)(step < 0 ? 2 * ny + ix : 2 * ny + nx + ix) * r + l];
+}
+
+// D^a_+- K_l at cell p, k = 0 D1+, 1 D1-, 2 D2+, 3 D2- (backward / forward
+// differences along x, then y)
+__device__ __forceinline__ double dk2(const double* K, const double* G, int r, int nx, int ny,
+                                      int l, long p, int k, double dx, double dy) {
+  const double k0 = K[l * (long)nx * ny + p];
+  const int axis = k >> 1;
+  const double h = axis == 0 ? dx : dy;
+  return (k & 1) ? (nb2(K, G, r, nx, ny, l, p, axis, 1) - k0) / h
+                 : (k0 - nb2(K, G, r, nx, ny, l, p, axis, -1)) / h;
+}
+
+// K-step on the rectangle: K1 = K + dt (-sum_k sum_l A_k[j][l] D_k K_l + sum_p
+// C_jp w_p K_m K_n), A = [A1+, A1-, A2+, A2-] (r x r each); dK = K1 - K.
+__global__ void k_kstep2d(const double* __restrict__ K, const double* __restrict__ G, int r, int nx,
+                          int ny, double dx, double dy, double dt, const double* __restrict__ A,
+                          const double* __restrict__ C, int P, const int* __restrict__ pm,
+                          const int* __restrict__ pn, double* __restrict__ K1,
+                          double* __restrict__ dK) {
+  const long nc = (long)nx * ny;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= r * nc) return;
+  const int j = (int)(t / nc);
+  const long p = t % nc;
+  double rhs = 0.0;
+  for (int l = 0; l < r; ++l)
+    for (int k = 0; k < 4; ++k) rhs -= A[(long)k * r * r + j * r + l] * dk2(K, G, r, nx, ny, l, p, k, dx, dy);
+  for (int q = 0; q < P; ++q) {
+    const int m = pm[q], nn = pn[q];
+    rhs += C[(long)j * P + q] * ((m == nn) ? 1.0 : 2.0) * K[m * nc + p] * K[nn * nc + p];
+  }
+  const double k1 = K[t] + dt * rhs;
+  K1[t] = k1;
+  dK[t] = k1 - K[t];
+}
+
+// x-side reductions on the rectangle, one wavefront per output (i, c):
+//   c < 4r        : oD[c / r][i][c % r] = w sum_p X1_i D_(c/r) K_(c%r)
+//   c < 4r + P    : oT[i][c - 4r]      = w sum_p X1_i w_q K_m K_n
+//   c < 4r + P + nz: oZ[i][c - 4r - P] = w sum_p X1_i Z_(c-4r-P)
+__global__ __launch_bounds__(256) void k_xreduce2d(
+    const double* __restrict__ X1, int r, int nx, int ny, double dx, double dy, double w,
+    const double* __restrict__ K, const double* __restrict__ G, int P, const int* __restrict__ pm,
+    const int* __restrict__ pn, const double* __restrict__ Z, int nz, double* __restrict__ oD,
+    double* __restrict__ oT, double* __restrict__ oZ) {
+  const int lane = threadIdx.x & 63;
+  const int ncols = 4 * r + P + nz;
+  const long t = blockIdx.x * 4L + (threadIdx.x >> 6);
+  if (t >= (long)r * ncols) return;
+  const int i = (int)(t / ncols), c = (int)(t % ncols);
+  const long nc = (long)nx * ny;
+  double s = 0.0;
+  for (long p = lane; p < nc; p += 64) {
+    double y;
+    if (c < 4 * r) {
+      y = dk2(K, G, r, nx, ny, c % r, p, c / r, dx, dy);
+    } else if (c < 4 * r + P) {
+      const int q = c - 4 * r, m = pm[q], nn = pn[q];
+      y = ((m == nn) ? 1.0 : 2.0) * K[m * nc + p] * K[nn * nc + p];
+    } else {
+      y = Z[(long)(c - 4 * r - P) * nc + p];
+    }
+    s += X1[i * nc + p] * y;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane != 0) return;
+  s *= w;
+  if (c < 4 * r)
+    oD[(long)(c / r) * r * r + i * r + c % r] = s;
+  else if (c < 4 * r + P)
+    oT[(long)i * P + c - 4 * r] = s;
+  else
+    oZ[(long)i * nz + c - 4 * r - P] = s;
+}
+
+// S2 = S1 + dt (sum_k D_k A_k^T - T C^T), dS = S2 - S1 (r x r row-major)
+__global__ void k_supdate2d(const double* __restrict__ S1, int r, const double* __restrict__ D,
+                            const double* __restrict__ A, const double* __restrict__ T,
+                            const double* __restrict__ C, int P, double dt,
+                            double* __restrict__ S2, double* __restrict__ dS) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r * r) return;
+  const int i = t / r, j = t % r;
+  double acc = 0.0;
+  for (int k = 0; k < 4; ++k)
+    for (int l = 0; l < r; ++l) acc += D[(long)k * r * r + i * r + l] * A[(long)k * r * r + j * r + l];
+  for (int q = 0; q < P; ++q) acc -= T[(long)i * P + q] * C[(long)j * P + q];
+  const double s2 = S1[t] + dt * acc;
+  S2[t] = s2;
+  dS[t] = s2 - S1[t];
+}
+
+// L-step on the velocity grid: L = S2 V,
+//   L1 = L - dt sum_a (v_a^+ sum_l D_a+[i][l] V_l + v_a^- sum_l D_a-[i][l] V_l)
+//        + dt sum_p T_ip Q_p,   dL = L1 - L.
+template <typename TQ>
+__global__ void k_lstep2d(const double* __restrict__ V, int r, int n,
+                          const double* __restrict__ S2, const double* __restrict__ D,
+                          const double* __restrict__ T, const TQ* __restrict__ Q, int P,
+                          double dt, VGeo g, double* __restrict__ L1, double* __restrict__ dL) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)r * n) return;
+  const int i = (int)(t / n), q = (int)(t % n);
+  const double v1 = g.v1(q), v2 = g.v2(q);
+  const double wv[4] = {v1 > 0 ? v1 : 0.0, v1 < 0 ? v1 : 0.0, v2 > 0 ? v2 : 0.0,
+                        v2 < 0 ? v2 : 0.0};
+  double L = 0.0, tr = 0.0;
+  for (int l = 0; l < r; ++l) {
+    const double vl = V[(long)l * n + q];
+    L += S2[i * r + l] * vl;
+    for (int k = 0; k < 4; ++k) tr += wv[k] * D[(long)k * r * r + i * r + l] * vl;
+  }
+  double col = 0.0;
+  for (int p = 0; p < P; ++p) col += T[(long)i * P + p] * (double)Q[(long)p * n + q];
+  const double l1 = L - dt * tr + dt * col;
+  L1[t] = l1;
+  dL[t] = l1 - L;
+}
+
+// Sums of squares of a and b (counts na, nb) into part[0 .. 2 gridDim.x):
+// block sums (wave sums, waves in order) for a grid-stride split.
+__global__ __launch_bounds__(256) void k_sumsq2(const double* __restrict__ a, long na,
+                                                const double* __restrict__ b, long nb,
+                                                double* __restrict__ part) {
+  __shared__ double ws[2][4];
+  double sa = 0.0, sb = 0.0;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < na; e += gridDim.x * 256L) sa += a[e] * a[e];
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < nb; e += gridDim.x * 256L) sb += b[e] * b[e];
+  for (int off = 32; off > 0; off >>= 1) {
+    sa += __shfl_down(sa, off, 64);
+    sb += __shfl_down(sb, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    ws[0][threadIdx.x >> 6] = sa;
+    ws[1][threadIdx.x >> 6] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = ((ws[0][0] + ws[0][1]) + ws[0][2]) + ws[0][3];
+    part[gridDim.x + blockIdx.x] = ((ws[1][0] + ws[1][1]) + ws[1][2]) + ws[1][3];
+  }
+}
+
+// err of the step from its pieces (Sec. 5.1):
+//   e2 = wx |dK|^2 + |dS|^2 + dvd |dL|^2 + 2 <kx, dS> + 2 <lv, dS> + 2 <kx, lv>
+// kx[i][j] = <X1_i, dK_j>, lv[i][j] = <dL_i, V_j> (r x r); one thread.
+__global__ void k_err2d(const double* __restrict__ part, int nb, const double* __restrict__ dS,
+                        const double* __restrict__ kx, const double* __restrict__ lv, int r,
+                        double wx, double dvd, double* __restrict__ err) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double sK = 0.0, sL = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    sK += part[b];
+    sL += part[nb + b];
+  }
+  double sS = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  for (int e = 0; e < r * r; ++e) {
+    sS += dS[e] * dS[e];
+    c1 += kx[e] * dS[e];
+    c2 += lv[e] * dS[e];
+    c3 += kx[e] * lv[e];
+  }
+  const double e2 = wx * sK + sS + dvd * sL + 2.0 * c1 + 2.0 * c2 + 2.0 * c3;
+  err[0] = std::sqrt(e2 > 0.0 ? e2 : 0.0);
+}
+
+// S (leading dimension lds) = R^T for an r x r row-major R
+__global__ void k_store_RT(const double* __restrict__ R, int r, double* __restrict__ S, int lds) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= r * r) return;
+  const int i = t / r, j = t % r;
+  S[i * lds + j] = R[j * r + i];
+}
+
 }  // namespace dk
 
 // ------------------------------------------------------------------ host --
@@ -1142,8 +1410,7 @@ void validate_problem(const blr_problem* pb, const blr_state* st) {
   require(pb->f_left && pb->f_right, "null inflow boundary arrays");
   require((pb->wall_left == 0 || pb->wall_left == 1) && (pb->wall_right == 0 || pb->wall_right == 1),
           "problem.wall_left / wall_right must be 0 (inflow) or 1 (diffusive wall)");
-  require(pb->ny <= 1, "the low-rank step runs in one-dimensional space (problem.ny <= 1)",
-          BLR_ERR_UNSUPPORTED);
+  require(pb->ny <= 1, "one-dimensional space expected (problem.ny <= 1)", BLR_ERR_UNSUPPORTED);
   require(pb->face_rows == 0, "problem.face_rows: one-dimensional space takes one row per face");
   validate_vgrid(pb->v);
   require(st->X && st->S && st->V, "null state arrays");
@@ -1695,8 +1962,212 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
 
 }  // namespace
 
+// ----------------------------------------------------- two-dimensional space
+// One fixed-rank K -> S -> L step on the rectangle (Sec. 2.2 applied along
+// both axes, the boundary of Sec. 2.3 on every face cell), eager: the pair
+// collisions, the velocity-side products (with the faces' outflow matrices,
+// inflow vectors and the wall sums), the three substeps with their QRs, the
+// residual from its pieces (Sec. 5.1).  The state is written only once the
+// residual is known to be finite.
+static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
+                       const blr_step_params* sp, blr_step_info* info) {
+  require(st && sp, "null state or step params");
+  require(pb->nx >= 1 && pb->ny <= (1 << 20) && (long)pb->nx * pb->ny <= (1L << 22),
+          "problem.nx >= 1, ny <= 2^20 and nx * ny <= 2^22");
+  require(pb->x_hi > pb->x_lo && pb->y_hi > pb->y_lo, "empty rectangle");
+  require(pb->f_left && pb->f_right && pb->f_bottom && pb->f_top, "null boundary function");
+  const int wl[4] = {pb->wall_left, pb->wall_right, pb->wall_bottom, pb->wall_top};
+  for (int k = 0; k < 4; ++k) require(wl[k] == 0 || wl[k] == 1, "wall flags must be 0 or 1");
+  require(pb->face_rows >= 0 && pb->face_rows <= 15, "problem.face_rows must be in [0, 15]");
+  validate_vgrid(pb->v);
+  require(st->X && st->S && st->V, "null state arrays");
+  require(st->r_cap >= 1 && st->r_cap <= 64, "state.r_cap must be in [1, 64]");
+  require(st->r >= 1 && st->r <= st->r_cap, "state.r must be in [1, r_cap]");
+  require(sp->dt > 0 && std::isfinite(sp->dt), "step.dt must be positive");
+  require(!(sp->flags & (BLR_STEP_ADD | BLR_STEP_DROP)),
+          "two-dimensional space: fixed-rank steps only (no BLR_STEP_ADD / BLR_STEP_DROP)",
+          BLR_ERR_UNSUPPORTED);
+  const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;
+  hipStream_t s = ctx->stream;
+  const int nx = pb->nx, ny = pb->ny, n = h.n, r = st->r, rc = st->r_cap;
+  const long nc = (long)nx * ny;
+  const double dx = (pb->x_hi - pb->x_lo) / nx, dy = (pb->y_hi - pb->y_lo) / ny;
+  const double wx = dx * dy, dvd = std::pow(h.dv, h.d), dt = sp->dt;
+  StepWork w{ctx, s, {h.L, h.dv, h.N, h.d, h.n}, (int)nc, n, wx, dvd};
+  const int P = r * (r + 1) / 2;
+  std::vector<int32_t> pairs(2 * P);
+  std::vector<int> pidx(2 * P);
+  for (int m = 0, q = 0; m < r; ++m)
+    for (int nn = m; nn < r; ++nn, ++q) {
+      pidx[q] = pairs[2 * q] = m;
+      pidx[P + q] = pairs[2 * q + 1] = nn;
+    }
+  int* dpidx = (int*)ctx->upload("dlr.d2.pidx", pidx.data(), pidx.size() * sizeof(int));
+  // pair collisions of the current basis
+  const bool fp64c = (sp->flags & BLR_STEP_FP64_COLLISION) != 0;
+  void* Qs;
+  if (fp64c) {
+    Qs = w.get("d2.Q64", (size_t)P * n);
+    collision_pairs(ctx, pb->v, BLR_FP64, st->V, r, pairs.data(), P, Qs);
+  } else {
+    float* V32 = (float*)ctx->buf("dlr.d2.V32", (size_t)r * n * sizeof(float));
+    hipLaunchKernelGGL(dk::k_to_f32_copy_S, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, st->V,
+                       (long)r * n, V32, nullptr, 0, nullptr, 0);
+    BLR_CHECK_LAUNCH();
+    Qs = ctx->buf("dlr.d2.Q32", (size_t)P * n * sizeof(float));
+    collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
+  }
+  // velocity side
+  double* A = w.get("d2.A", (size_t)4 * r * r);   // A1+, A1-, A2+, A2-
+  double* Mo = w.get("d2.Mo", (size_t)4 * r * r);
+  double* C = w.get("d2.C", (size_t)r * P);
+  const double* fk[4] = {pb->f_left, pb->f_right, pb->f_bottom, pb->f_top};
+  static const int kOut[4] = {dk::W_OUT_LEFT, dk::W_OUT_RIGHT, dk::W_OUT_BOTTOM, dk::W_OUT_TOP};
+  static const int kIn[4] = {dk::W_IN_LEFT, dk::W_IN_RIGHT, dk::W_IN_BOTTOM, dk::W_IN_TOP};
+  // a_l: (v.n)_out = -v1 (x_lo), v1 (x_hi), -v2 (y_lo), v2 (y_hi) on the outgoing half;
+  // den: |v.n|_in = v1 (x_lo), -v1 (x_hi), v2 (y_lo), -v2 (y_hi) on the incoming half
+  static const int kA[4] = {dk::W_VMINUS, dk::W_VPLUS, dk::W_V2MINUS, dk::W_V2PLUS};
+  static const int kD[4] = {dk::W_VPLUS, dk::W_VMINUS, dk::W_V2PLUS, dk::W_V2MINUS};
+  static const double sA[4] = {-1.0, 1.0, -1.0, 1.0}, sD[4] = {1.0, -1.0, 1.0, -1.0};
+  const bool any_wall = wl[0] || wl[1] || wl[2] || wl[3];
+  double* ones = nullptr;
+  if (any_wall) {
+    ones = w.get("d2.ones", (size_t)n);
+    fill<double>(s, ones, n, 1.0);
+  }
+  dk::Faces2 fs{};
+  GramJob gj;
+  auto add = [&](const double* Aa, int ra, const void* B, int rb, bool bf, int mode, double* out) {
+    if (gj.gb.nseg == dk::MAXSEG) {
+      gj.run(w);
+      gj = GramJob{};
+    }
+    gj.add(Aa, ra, B, rb, bf, mode, dvd, out);
+  };
+  static const int kT[4] = {dk::W_VPLUS, dk::W_VMINUS, dk::W_V2PLUS, dk::W_V2MINUS};
+  for (int k = 0; k < 4; ++k) add(st->V, r, st->V, r, false, kT[k], A + (long)k * r * r);
+  add(st->V, r, Qs, P, !fp64c, dk::W_ONE, C);
+  for (int k = 0; k < 4; ++k) {
+    const int rows = ((pb->face_rows >> k) & 1) ? (k < 2 ? ny : nx) : 1;
+    const std::string tag = "d2.face" + std::to_string(k);
+    double* gin = w.get((tag + ".gin").c_str(), (size_t)r * rows);
+    add(st->V, r, st->V, r, false, kOut[k], Mo + (long)k * r * r);
+    add(st->V, r, fk[k], rows, false, kIn[k], gin);
+    dk::Face2& F = fs.f[k];
+    F.Mo = Mo + (long)k * r * r;
+    F.gin = gin;
+    F.rows = rows;
+    F.wall = wl[k];
+    F.sa = sA[k];
+    F.sd = sD[k];
+    if (wl[k]) {
+      double* a = w.get((tag + ".a").c_str(), (size_t)r);
+      double* den = w.get((tag + ".den").c_str(), (size_t)rows);
+      add(st->V, r, ones, 1, false, kA[k], a);
+      add(ones, 1, fk[k], rows, false, kD[k], den);
+      F.a = a;
+      F.den = den;
+    }
+  }
+  gj.run(w);
+  const int nface = 2 * (nx + ny);
+  double* G = w.get("d2.G", (size_t)nface * r);
+  auto ghosts = [&](const double* Kx) {
+    hipLaunchKernelGGL(dk::k_ghosts2d, dim3(nface), dim3(64), 0, s, Kx, r, nx, ny, fs, G);
+    BLR_CHECK_LAUNCH();
+  };
+  // K-step
+  double* K = w.get("d2.K", (size_t)r * nc);
+  double* K1 = w.get("d2.K1", (size_t)r * nc);
+  double* dK = w.get("d2.dK", (size_t)r * nc);
+  double* X1 = w.get("d2.X1", (size_t)r * nc);
+  double* S1 = w.get("d2.S1", (size_t)r * r);
+  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, st->X, r, (int)nc,
+                     st->S, rc, K);
+  BLR_CHECK_LAUNCH();
+  ghosts(K);
+  hipLaunchKernelGGL(dk::k_kstep2d, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, K, G, r, nx,
+                     ny, dx, dy, dt, A, C, P, dpidx, dpidx + P, K1, dK);
+  BLR_CHECK_LAUNCH();
+  tsqr(ctx, K1, nc, nc, r, X1, nc, S1, "qr2.k", std::sqrt(wx), 1.0 / std::sqrt(wx));
+  // S-step (K = X1 S1 and its ghosts); kx = <X1_i, dK_j> for the residual
+  double* D = w.get("d2.D", (size_t)4 * r * r);
+  double* T = w.get("d2.T", (size_t)r * P);
+  double* kx = w.get("d2.kx", (size_t)r * r);
+  double* S2 = w.get("d2.S2", (size_t)r * r);
+  double* dS = w.get("d2.dS", (size_t)r * r);
+  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, X1, r, (int)nc,
+                     S1, r, K);
+  BLR_CHECK_LAUNCH();
+  ghosts(K);
+  hipLaunchKernelGGL(dk::k_xreduce2d, dim3(blocks((long)r * (5 * r + P), 4)), dim3(256), 0, s, X1,
+                     r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, dK, r, D, T, kx);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_supdate2d, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, S1, r, D, A,
+                     T, C, P, dt, S2, dS);
+  BLR_CHECK_LAUNCH();
+  // L-step (K = X1 S2 and its ghosts)
+  double* Dt = w.get("d2.Dt", (size_t)4 * r * r);
+  double* Tt = w.get("d2.Tt", (size_t)r * P);
+  double* L1 = w.get("d2.L1", (size_t)r * n);
+  double* dL = w.get("d2.dL", (size_t)r * n);
+  double* V1 = w.get("d2.V1", (size_t)r * n);
+  double* R = w.get("d2.R", (size_t)r * r);
+  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, X1, r, (int)nc,
+                     S2, r, K);
+  BLR_CHECK_LAUNCH();
+  ghosts(K);
+  hipLaunchKernelGGL(dk::k_xreduce2d, dim3(blocks((long)r * (4 * r + P), 4)), dim3(256), 0, s, X1,
+                     r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, nullptr, 0, Dt, Tt, nullptr);
+  BLR_CHECK_LAUNCH();
+  if (fp64c)
+    hipLaunchKernelGGL(dk::k_lstep2d<double>, dim3(blocks((long)r * n, 256)), dim3(256), 0, s,
+                       st->V, r, n, S2, Dt, Tt, (const double*)Qs, P, dt, w.g, L1, dL);
+  else
+    hipLaunchKernelGGL(dk::k_lstep2d<float>, dim3(blocks((long)r * n, 256)), dim3(256), 0, s,
+                       st->V, r, n, S2, Dt, Tt, (const float*)Qs, P, dt, w.g, L1, dL);
+  BLR_CHECK_LAUNCH();
+  tsqr(ctx, L1, n, n, r, V1, n, R, "qr2.l", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
+  // residual
+  double* lv = w.get("d2.lv", (size_t)r * r);
+  {
+    GramJob g2;
+    g2.add(dL, r, st->V, r, false, dk::W_ONE, dvd, lv);
+    g2.run(w);
+  }
+  const int nbp = 256;
+  double* part = w.get("d2.part", (size_t)2 * nbp);
+  double* err = w.get("d2.err", 1);
+  hipLaunchKernelGGL(dk::k_sumsq2, dim3(nbp), dim3(256), 0, s, dK, (long)r * nc, dL, (long)r * n,
+                     part);
+  BLR_CHECK_LAUNCH();
+  hipLaunchKernelGGL(dk::k_err2d, dim3(1), dim3(64), 0, s, part, nbp, dS, kx, lv, r, wx, dvd, err);
+  BLR_CHECK_LAUNCH();
+  double* hb = (double*)ctx->host_readback(sizeof(double));
+  BLR_HIP(hipMemcpyAsync(hb, err, sizeof(double), hipMemcpyDeviceToHost, s));
+  BLR_HIP(hipStreamSynchronize(s));
+  const double e = hb[0];
+  require(std::isfinite(e), "two-dimensional step: non-finite residual", BLR_ERR_NUMERIC);
+  // commit: X = X1, S = R^T (L1^T = V1^T R), V = V1
+  BLR_HIP(hipMemcpyAsync(st->X, X1, (size_t)r * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(dk::k_store_RT, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, R, r, st->S, rc);
+  BLR_CHECK_LAUNCH();
+  BLR_HIP(hipMemcpyAsync(st->V, V1, (size_t)r * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  BLR_HIP(hipStreamSynchronize(s));
+  if (info) {
+    blr_step_info inf{};
+    inf.r_in = inf.r_out = r;
+    inf.err = inf.err_ada = e;
+    *info = inf;
+  }
+}
+
 void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_params* sp,
               blr_step_info* info) {
+  if (pb && pb->ny >= 2) {
+    dlr_step2d(ctx, pb, st, sp, info);
+    return;
+  }
   validate_problem(pb, st);
   require(sp != nullptr, "null step params");
   require(sp->dt > 0 && std::isfinite(sp->dt), "step.dt must be positive");

@@ -270,6 +270,28 @@ def wall_initial(spec: VGridSpec, nx: int, x_lo: float = 0.0, x_hi: float = 2.0,
     return dict(f0=f0, fL=fL, fR=fR, x=x)
 
 
+def rect_field(spec: VGridSpec, nx: int, ny: int, seed: int = 3, rank: int = 3,
+               pert: float = 5e-2) -> np.ndarray:
+    """Seeded smooth state on an nx x ny rectangle (cell ix ny + iy): a
+    Maxwellian whose temperature grows along x and y and whose bulk velocity
+    varies smoothly, plus a seeded rank-``rank`` perturbation (random
+    Gaussian-weighted velocity profiles) of relative size ``pert``."""
+    d = spec.d
+    v = vgrid_points(d, spec.n, spec.L)
+    rng = np.random.default_rng(seed)
+    F = np.empty((nx * ny, spec.npts))
+    z = (0.0,) * (d - 2)
+    for ix in range(nx):
+        for iy in range(ny):
+            T = 1.0 + 0.2 * ix / max(1, nx - 1) + 0.1 * iy / max(1, ny - 1)
+            u = (0.3 * math.sin(ix + 0.5 * iy), 0.2 * math.cos(iy - ix)) + z
+            F[ix * ny + iy] = maxwellian(v, 1.0 + 0.1 * rng.standard_normal() ** 2, u, T).reshape(-1)
+    m0 = maxwellian(v, 1.0, (0.0,) * d, 1.0).reshape(-1)
+    B = rng.standard_normal((rank, spec.npts)) * m0
+    A = rng.standard_normal((nx * ny, rank))
+    return F + pert * F.max() * (A @ B) / np.abs(A @ B).max()
+
+
 def lowrank_state(f0: np.ndarray, r: int, dx: float, dvd: float):
     """Rank-r factors (X, S, V) of f0 with <X_i,X_j>_x = <V_i,V_j>_v = delta_ij,
     where <a,b>_x = dx sum a b and <a,b>_v = dv^d sum a b.

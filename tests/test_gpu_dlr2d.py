@@ -1,0 +1,142 @@
+"""GPU parity of the low-rank step in two-dimensional space (a rectangle with
+inflow and Maxwell diffusive wall faces, boundary functions varying along a
+face) against the oracle's step on the rectangle (oracle/dlr.py, pinned by
+tests/test_oracle_dlr2d.py).
+
+FP64 collisions: f = X S V on the grid to 1e-12 of max |f| and err to 1e-10
+relative, step by step.  FP32 collisions: ||f_gpu - f_ref|| <= 1e-5 dt
+||sum K_m K_n Q+_mn|| (the pair operator's bound, as in one dimension).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import collision as oc
+from oracle import dlr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2112_02695_amd as blr  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = blr.Context(0)
+    yield c
+    c.close()
+
+
+def _spec(d, N, m_rho):
+    if d == 2:
+        return synth.VGridSpec(d=2, n=N, L=8.0, gamma=0.0, C=1 / (2 * math.pi), m_rho=m_rho,
+                               m_sigma=8)
+    return synth.VGridSpec(d=3, n=N, L=8.0, gamma=1.0, C=1.0, m_rho=m_rho, m_sigma=38)
+
+
+def _maxw(spec, rho, u, T):
+    v = synth.vgrid_points(spec.d, spec.n, spec.L)
+    return synth.maxwellian(v, rho, tuple(u) + (0.0,) * (spec.d - 2), T).reshape(-1)
+
+
+def _setup(d, N, m_rho, nx, ny, r, seed=3):
+    """x_lo inflow, x_hi wall (T 1.2), y_lo wall moving along x, y_hi inflow
+    with one row per face cell."""
+    spec = _spec(d, N, m_rho)
+    top = np.array([_maxw(spec, 0.9, (0.1, -0.2), 1.0 + 0.05 * i) for i in range(nx)])
+    faces = [(_maxw(spec, 1.0, (0.4, 0.0), 1.0), False), (_maxw(spec, 1.0, (0.0, 0.0), 1.2), True),
+             (_maxw(spec, 1.0, (0.3, 0.0), 1.0), True), (top, False)]
+    prob = dlr.Problem2D(vs=oc.setup_from_spec(spec), nx=nx, ny=ny, x_lo=0.0, x_hi=1.0,
+                         y_lo=0.0, y_hi=0.8, faces=faces)
+    F0 = synth.rect_field(spec, nx, ny, seed=seed)
+    X, S, V = synth.lowrank_state(F0, r, prob.wx, prob.dvd)
+    return spec, prob, dlr.State(X, S, V)
+
+
+class Gpu:
+    def __init__(self, ctx, spec, prob, st, r_cap):
+        dev = "cuda"
+        nc = prob.nx * prob.ny
+        self.X = torch.zeros((r_cap, nc), dtype=torch.float64, device=dev)
+        self.S = torch.zeros((r_cap, r_cap), dtype=torch.float64, device=dev)
+        self.V = torch.zeros((r_cap, prob.vs.n), dtype=torch.float64, device=dev)
+        r = st.r
+        self.X[:r] = torch.tensor(st.X.T, device=dev)
+        self.S[:r, :r] = torch.tensor(st.S, device=dev)
+        self.V[:r] = torch.tensor(st.V, device=dev)
+        faces = [(torch.tensor(np.ascontiguousarray(f), device=dev), w) for f, w in prob.faces]
+        self.pb = ctx.make_problem2d(blr.vgrid_from_spec(spec), prob.nx, prob.ny, prob.x_lo,
+                                     prob.x_hi, prob.y_lo, prob.y_hi, faces)
+        self.st = ctx.make_state(self.X, self.S, self.V, r)
+
+    def full(self):
+        r = self.st.r
+        return (self.X[:r].cpu().numpy().T @ self.S[:r, :r].cpu().numpy()) @ self.V[:r].cpu().numpy()
+
+
+@pytest.mark.parametrize("d,N,m_rho,nx,ny,r", [(2, 16, 8, 5, 4, 4), (3, 8, 4, 4, 3, 3),
+                                               (2, 16, 4, 6, 5, 7), (2, 16, 4, 1, 6, 3)])
+def test_fixed_rank_steps_fp64(ctx, d, N, m_rho, nx, ny, r):
+    print(f"2D-space step d={d} N={N} {nx}x{ny} r={r}", flush=True)
+    spec, prob, st = _setup(d, N, m_rho, nx, ny, r)
+    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    dt = 0.004
+    cur = st
+    for k in range(3):
+        info = ctx.dlr_step(g.pb, g.st, blr.StepParams(dt, 0.2, 1e-10, 1, 8,
+                                                       blr.BLR_STEP_FP64_COLLISION))
+        cur, err, _ = dlr.ksl_step(cur, prob, dt)
+        f_ref = cur.full()
+        e = np.abs(g.full() - f_ref).max() / np.abs(f_ref).max()
+        print(k, "f rel err", e, "err", info.err, err, flush=True)
+        assert e < 1e-12
+        assert abs(info.err - err) < 1e-10 * err
+        assert info.r_out == r
+
+
+def test_fixed_rank_step_fp32_collisions(ctx):
+    spec, prob, st = _setup(2, 16, 8, 5, 4, 4)
+    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    dt = 0.004
+    info = ctx.dlr_step(g.pb, g.st, blr.StepParams(dt, 0.2, 1e-10, 1, 8, 0))
+    new, err, _ = dlr.ksl_step(st, prob, dt)
+    pairs = dlr.pair_list(st.r)
+    wts = np.array([1.0 if m == n else 2.0 for (m, n) in pairs])
+    _, gains = oc.q_pairs(st.V, pairs, prob.vs, conserve=True)
+    gain_scale = np.linalg.norm(dlr.pair_products(st.X @ st.S, pairs, wts) @ gains)
+    e = np.linalg.norm(g.full() - new.full()) / (dt * gain_scale)
+    print("fp32 step error / (dt ||gain||)", e, flush=True)
+    assert e < 1e-5
+    assert abs(info.err - err) < 1e-3 * err
+
+
+def test_steady_solve_runs_steps_on_the_rectangle(ctx):
+    spec, prob, st = _setup(2, 16, 4, 4, 4, 3, seed=5)
+    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    dt = 0.004
+    sp = blr.SolveParams(blr.StepParams(dt, 0.2, 1e-10, 1, 8, blr.BLR_STEP_FP64_COLLISION),
+                         1e-30, 4)
+    info = ctx.steady_solve(g.pb, g.st, sp, allow_unconverged=True)
+    cur = st
+    for _ in range(4):
+        cur, err, _ = dlr.ksl_step(cur, prob, dt)
+    f_ref = cur.full()
+    assert info.steps == 4
+    assert np.abs(g.full() - f_ref).max() < 1e-12 * np.abs(f_ref).max()
+    assert abs(info.err_ada - err) < 1e-10 * err
+
+
+def test_adaptive_flags_are_refused_on_the_rectangle(ctx):
+    spec, prob, st = _setup(2, 16, 4, 3, 3, 2)
+    g = Gpu(ctx, spec, prob, st, r_cap=8)
+    before = g.full()
+    for fl in (blr.BLR_STEP_ADD, blr.BLR_STEP_DROP):
+        with pytest.raises(blr.BlrError) as ei:
+            ctx.dlr_step(g.pb, g.st, blr.StepParams(0.004, 0.2, 1e-10, 1, 8, fl))
+        assert ei.value.code == blr.BLR_ERR_UNSUPPORTED
+    assert np.array_equal(g.full(), before)

@@ -174,18 +174,3 @@ def test_full_step_on_a_rectangle_fp32_two_chunks(ctx):
     print("rel", rel, "err", e, eref, flush=True)
     assert rel < 1e-5
     assert abs(e - eref) < 1e-5 * eref
-
-
-def test_low_rank_calls_refuse_two_dimensional_space(ctx):
-    spec = _spec(2, 16, 4)
-    f = torch.tensor(_maxw(spec, 1.0, (0.0, 0.0), 1.0), device="cuda")
-    pb = ctx.make_problem2d(blr.vgrid_from_spec(spec), 3, 3, 0.0, 1.0, 0.0, 1.0,
-                            [(f, False)] * 4)
-    X = torch.zeros((4, 9), dtype=torch.float64, device="cuda")
-    S = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
-    V = torch.zeros((4, 256), dtype=torch.float64, device="cuda")
-    S[0, 0] = 1.0
-    st = ctx.make_state(X, S, V, 1)
-    with pytest.raises(blr.BlrError) as ei:
-        ctx.dlr_step(pb, st, blr.StepParams(0.001, 0.2, 1e-10, 1, 4, 0))
-    assert ei.value.code == blr.BLR_ERR_UNSUPPORTED
