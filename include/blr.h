@@ -155,9 +155,11 @@ typedef struct {
    * along the face; clear: one row for the whole face.  A diffusive wall's
    * rho_w is then set per face cell.  ny = 0 or 1: one-dimensional space
    * (these fields are ignored).  In two dimensions blr_full_step,
-   * blr_dlr_step and blr_steady_solve run fixed-rank steps (the state's X
-   * has rows of nx ny values); BLR_STEP_ADD / BLR_STEP_DROP and
-   * blr_state_from_full return BLR_ERR_UNSUPPORTED there. */
+   * blr_dlr_step and blr_steady_solve run on the rectangle (the state's X
+   * has rows of nx ny values; the rank is capped at nx ny); BLR_STEP_ADD
+   * takes one boundary row per face cell and needs 2 (nx + ny) <= 64, else
+   * BLR_ERR_UNSUPPORTED; steps there run eagerly (no recorded graph);
+   * blr_state_from_full is one-dimensional only. */
   int32_t ny;
   double y_lo, y_hi;
   const double* f_bottom;

@@ -1332,6 +1332,71 @@ __global__ void k_err2d(const double* __restrict__ part, int nb, const double* _
   err[0] = std::sqrt(e2 > 0.0 ? e2 : 0.0);
 }
 
+// Boundary functions of the four faces; bit k of rows: face k holds one row
+// per face cell
+struct FaceRows {
+  const double* f[4];
+  int rows;
+  __device__ __forceinline__ const double* row(int k, int c, int n) const {
+    return f[k] + (((rows >> k) & 1) ? (long)c * n : 0L);
+  }
+};
+
+// Boundary rows F_b of the augmentation on the rectangle, one per face cell
+// b (Sec. 3.1 with eq. boundary general): the face's boundary function on its
+// incoming half (a wall's shape, scaled by k_wall_rows2d), the adjacent
+// cell's sum_l K_l V_l on the outgoing half.
+__global__ void k_fb2d(const double* __restrict__ K, int r, int nx, int ny,
+                       const double* __restrict__ V, FaceRows fr, VGeo g, double* __restrict__ Fb) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+  if (q >= g.n) return;
+  int k, c;
+  face_of(b, nx, ny, k, c);
+  const long nc = (long)nx * ny, p = face_cell(k, c, nx, ny);
+  const double va = k < 2 ? g.v1(q) : g.v2(q);
+  const bool inc = (k % 2 == 0) ? va > 0 : va < 0;
+  double val = 0.0;
+  if (inc) {
+    val = fr.row(k, c, g.n)[q];
+  } else {
+    for (int l = 0; l < r; ++l) val += K[l * nc + p] * V[(long)l * g.n + q];
+  }
+  Fb[(long)b * g.n + q] = val;
+}
+
+// Diffusive walls: scale the incoming half of each wall row of F_b by rho_w
+// from the row's own outgoing half.  One block per face cell.
+__global__ __launch_bounds__(1024) void k_wall_rows2d(double* __restrict__ Fb, FaceRows fr,
+                                                      int walls, int nx, int ny, VGeo g) {
+  int k, c;
+  face_of(blockIdx.x, nx, ny, k, c);
+  if (!((walls >> k) & 1)) return;
+  __shared__ double red[1024 / 64 + 1];
+  double* row = Fb + (long)blockIdx.x * g.n;
+  const double* M = fr.row(k, c, g.n);
+  const int stride = k < 2 ? (g.d == 3 ? g.N * g.N : g.N) : (g.d == 3 ? g.N : 1);
+  const double rho =
+      wall::density_face<1024>((k % 2 == 0) ? -1.0 : 1.0, row, M, g.n, g.L, g.dv, stride, g.N, red);
+  for (int q = threadIdx.x; q < g.n; q += 1024) {
+    const double va = k < 2 ? g.v1(q) : g.v2(q);
+    if ((k % 2 == 0) ? va > 0 : va < 0) row[q] = rho * M[q];
+  }
+}
+
+// S_aug = S^ Rv^T with S^ = [[S, 0], [0, 0]] (r x r block S, leading dim
+// lds) and Rv (ra x ra row-major): the state after appending basis rows whose
+// QR is V^T = Vq^T Rv
+__global__ void k_saug(const double* __restrict__ S, int lds, int r, const double* __restrict__ Rv,
+                       int ra, double* __restrict__ Sa) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ra * ra) return;
+  const int i = t / ra, j = t % ra;
+  double v = 0.0;
+  if (i < r)
+    for (int l = 0; l < r; ++l) v += S[i * lds + l] * Rv[j * ra + l];
+  Sa[t] = v;
+}
+
 // S (leading dimension lds) = R^T for an r x r row-major R
 __global__ void k_store_RT(const double* __restrict__ R, int r, double* __restrict__ S, int lds) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1963,12 +2028,16 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
 }  // namespace
 
 // ----------------------------------------------------- two-dimensional space
-// One fixed-rank K -> S -> L step on the rectangle (Sec. 2.2 applied along
-// both axes, the boundary of Sec. 2.3 on every face cell), eager: the pair
-// collisions, the velocity-side products (with the faces' outflow matrices,
-// inflow vectors and the wall sums), the three substeps with their QRs, the
-// residual from its pieces (Sec. 5.1).  The state is written only once the
-// residual is known to be finite.
+// One K -> S -> L step on the rectangle (Sec. 2.2 applied along both axes,
+// the boundary of Sec. 2.3 on every face cell), eager, with the adaptivity of
+// Sec. 3: the boundary rows of every face cell added first (their SVD from a
+// QR of F_b^T and the SVD of its R factor, 2 (nx + ny) <= 64), the rank
+// decision on the SVD of the new S last, err_ada from the factors (Sec.
+// 5.1).  The substeps: the pair collisions, the velocity-side products (the
+// faces' outflow matrices and inflow vectors, at walls the flux sums that
+// make rho_w linear in the adjacent cell's K), K, S and L with their QRs, the
+// residual from its pieces.  The state is written only at the end, once the
+// residual is finite.
 static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
                        const blr_step_params* sp, blr_step_info* info) {
   require(st && sp, "null state or step params");
@@ -1984,16 +2053,92 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   require(st->r_cap >= 1 && st->r_cap <= 64, "state.r_cap must be in [1, 64]");
   require(st->r >= 1 && st->r <= st->r_cap, "state.r must be in [1, r_cap]");
   require(sp->dt > 0 && std::isfinite(sp->dt), "step.dt must be positive");
-  require(!(sp->flags & (BLR_STEP_ADD | BLR_STEP_DROP)),
-          "two-dimensional space: fixed-rank steps only (no BLR_STEP_ADD / BLR_STEP_DROP)",
-          BLR_ERR_UNSUPPORTED);
   const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;
   hipStream_t s = ctx->stream;
-  const int nx = pb->nx, ny = pb->ny, n = h.n, r = st->r, rc = st->r_cap;
+  const int nx = pb->nx, ny = pb->ny, n = h.n, rc = st->r_cap, r_in = st->r;
   const long nc = (long)nx * ny;
   const double dx = (pb->x_hi - pb->x_lo) / nx, dy = (pb->y_hi - pb->y_lo) / ny;
   const double wx = dx * dy, dvd = std::pow(h.dv, h.d), dt = sp->dt;
+  // the rank never exceeds the cell count (the X-side QR needs rows >= r)
+  require(r_in <= nc, "state.r must not exceed nx * ny");
+  const int r_max = (int)std::min<long>(std::min(sp->r_max > 0 ? sp->r_max : rc, rc), nc);
+  const int r_min = std::max(1, std::min(sp->r_min, r_max));
+  const bool add_on = (sp->flags & BLR_STEP_ADD) && r_in < r_max;
+  const bool drop_on = (sp->flags & BLR_STEP_DROP) != 0;
+  const int nface = 2 * (nx + ny);
+  if (add_on)
+    require(nface <= 64, "two-dimensional space: the basis augmentation needs 2 (nx + ny) <= 64",
+            BLR_ERR_UNSUPPORTED);
   StepWork w{ctx, s, {h.L, h.dv, h.N, h.d, h.n}, (int)nc, n, wx, dvd};
+  const dk::FaceRows fr{{pb->f_left, pb->f_right, pb->f_bottom, pb->f_top}, pb->face_rows};
+  const int walls = wl[0] | (wl[1] << 1) | (wl[2] << 2) | (wl[3] << 3);
+  auto dev2host = [&](const double* d, size_t count) {
+    std::vector<double> v(count);
+    BLR_HIP(hipMemcpyAsync(v.data(), d, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    BLR_HIP(hipStreamSynchronize(s));
+    return v;
+  };
+
+  // ------------------------------------------------ add (Sec. 3.1)
+  const double* Xw = st->X;  // working factors: rows of nc / n values
+  const double* Sw = st->S;
+  const double* Vw = st->V;
+  int lsw = rc, r = r_in, r_added = 0;
+  if (add_on) {
+    double* K = w.get("d2.K", (size_t)r * nc);
+    double* Fb = w.get("d2.Fb", (size_t)nface * n);
+    double* Qb = w.get("d2.Qb", (size_t)nface * n);
+    double* Rb = w.get("d2.Rb", (size_t)nface * nface);
+    double* Ub = w.get("d2.Ub", (size_t)nface * nface);
+    double* sb = w.get("d2.sb", (size_t)nface);
+    double* Wb = w.get("d2.Wb", (size_t)nface * nface);
+    hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, st->X, r,
+                       (int)nc, st->S, rc, K);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_fb2d, dim3(blocks(n, 256), nface), dim3(256), 0, s, K, r, nx, ny,
+                       st->V, fr, w.g, Fb);
+    BLR_CHECK_LAUNCH();
+    if (walls) {
+      hipLaunchKernelGGL(dk::k_wall_rows2d, dim3(nface), dim3(1024), 0, s, Fb, fr, walls, nx, ny,
+                         w.g);
+      BLR_CHECK_LAUNCH();
+    }
+    // F_b^T = Qb Rb, F_b = Rb^T Qb^T = Ub diag(sb) (Qb Wb)^T
+    tsqr(ctx, Fb, n, n, nface, Qb, n, Rb, "qr2.fb", 1.0, 1.0);
+    svd_small(ctx, Rb, nface, Ub, sb, Wb, true);
+    const std::vector<double> sig = dev2host(sb, nface);
+    int rb = 0;
+    for (int i = 0; i < nface; ++i) rb += sig[i] > sp->add_tol;
+    rb = std::min(rb, r_max - r);
+    if (rb > 0) {
+      const int ra = r + rb;
+      double* Vh = w.get("d2.Vh", (size_t)ra * n);
+      double* Vq = w.get("d2.Vq", (size_t)ra * n);
+      double* Rv = w.get("d2.Rv", (size_t)ra * ra);
+      double* Sa = w.get("d2.Sa", (size_t)ra * ra);
+      double* Xa = w.get("d2.Xa", (size_t)ra * nc);
+      BLR_HIP(hipMemcpyAsync(Vh, st->V, (size_t)r * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      // new rows U_b[:, :rb]^T F_b: the leading right singular vectors times sigma
+      hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), rb), dim3(256), 0, s, Fb, nface,
+                         (long)n, Ub, nface, rb, 1.0, Vh + (long)r * n, (long)n);
+      BLR_CHECK_LAUNCH();
+      tsqr(ctx, Vh, n, n, ra, Vq, n, Rv, "qr2.va", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
+      hipLaunchKernelGGL(dk::k_saug, dim3(blocks((long)ra * ra, 256)), dim3(256), 0, s, st->S, rc,
+                         r, Rv, ra, Sa);
+      BLR_CHECK_LAUNCH();
+      // X gains zero rows: X^ S^ (all the step reads of X^n) is unchanged
+      BLR_HIP(hipMemcpyAsync(Xa, st->X, (size_t)r * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+      fill<double>(s, Xa + (long)r * nc, (long)rb * nc, 0.0);
+      Xw = Xa;
+      Sw = Sa;
+      Vw = Vq;
+      lsw = ra;
+      r = ra;
+      r_added = rb;
+    }
+  }
+
+  // ------------------------------------------------ pair collisions
   const int P = r * (r + 1) / 2;
   std::vector<int32_t> pairs(2 * P);
   std::vector<int> pidx(2 * P);
@@ -2003,21 +2148,20 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
       pidx[P + q] = pairs[2 * q + 1] = nn;
     }
   int* dpidx = (int*)ctx->upload("dlr.d2.pidx", pidx.data(), pidx.size() * sizeof(int));
-  // pair collisions of the current basis
   const bool fp64c = (sp->flags & BLR_STEP_FP64_COLLISION) != 0;
   void* Qs;
   if (fp64c) {
     Qs = w.get("d2.Q64", (size_t)P * n);
-    collision_pairs(ctx, pb->v, BLR_FP64, st->V, r, pairs.data(), P, Qs);
+    collision_pairs(ctx, pb->v, BLR_FP64, Vw, r, pairs.data(), P, Qs);
   } else {
     float* V32 = (float*)ctx->buf("dlr.d2.V32", (size_t)r * n * sizeof(float));
-    hipLaunchKernelGGL(dk::k_to_f32_copy_S, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, st->V,
+    hipLaunchKernelGGL(dk::k_to_f32_copy_S, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, Vw,
                        (long)r * n, V32, nullptr, 0, nullptr, 0);
     BLR_CHECK_LAUNCH();
     Qs = ctx->buf("dlr.d2.Q32", (size_t)P * n * sizeof(float));
     collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
   }
-  // velocity side
+  // ------------------------------------------------ velocity side
   double* A = w.get("d2.A", (size_t)4 * r * r);   // A1+, A1-, A2+, A2-
   double* Mo = w.get("d2.Mo", (size_t)4 * r * r);
   double* C = w.get("d2.C", (size_t)r * P);
@@ -2029,9 +2173,9 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   static const int kA[4] = {dk::W_VMINUS, dk::W_VPLUS, dk::W_V2MINUS, dk::W_V2PLUS};
   static const int kD[4] = {dk::W_VPLUS, dk::W_VMINUS, dk::W_V2PLUS, dk::W_V2MINUS};
   static const double sA[4] = {-1.0, 1.0, -1.0, 1.0}, sD[4] = {1.0, -1.0, 1.0, -1.0};
-  const bool any_wall = wl[0] || wl[1] || wl[2] || wl[3];
+  static const int kT[4] = {dk::W_VPLUS, dk::W_VMINUS, dk::W_V2PLUS, dk::W_V2MINUS};
   double* ones = nullptr;
-  if (any_wall) {
+  if (walls) {
     ones = w.get("d2.ones", (size_t)n);
     fill<double>(s, ones, n, 1.0);
   }
@@ -2044,15 +2188,14 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     }
     gj.add(Aa, ra, B, rb, bf, mode, dvd, out);
   };
-  static const int kT[4] = {dk::W_VPLUS, dk::W_VMINUS, dk::W_V2PLUS, dk::W_V2MINUS};
-  for (int k = 0; k < 4; ++k) add(st->V, r, st->V, r, false, kT[k], A + (long)k * r * r);
-  add(st->V, r, Qs, P, !fp64c, dk::W_ONE, C);
+  for (int k = 0; k < 4; ++k) add(Vw, r, Vw, r, false, kT[k], A + (long)k * r * r);
+  add(Vw, r, Qs, P, !fp64c, dk::W_ONE, C);
   for (int k = 0; k < 4; ++k) {
     const int rows = ((pb->face_rows >> k) & 1) ? (k < 2 ? ny : nx) : 1;
     const std::string tag = "d2.face" + std::to_string(k);
     double* gin = w.get((tag + ".gin").c_str(), (size_t)r * rows);
-    add(st->V, r, st->V, r, false, kOut[k], Mo + (long)k * r * r);
-    add(st->V, r, fk[k], rows, false, kIn[k], gin);
+    add(Vw, r, Vw, r, false, kOut[k], Mo + (long)k * r * r);
+    add(Vw, r, fk[k], rows, false, kIn[k], gin);
     dk::Face2& F = fs.f[k];
     F.Mo = Mo + (long)k * r * r;
     F.gin = gin;
@@ -2063,50 +2206,59 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     if (wl[k]) {
       double* a = w.get((tag + ".a").c_str(), (size_t)r);
       double* den = w.get((tag + ".den").c_str(), (size_t)rows);
-      add(st->V, r, ones, 1, false, kA[k], a);
+      add(Vw, r, ones, 1, false, kA[k], a);
       add(ones, 1, fk[k], rows, false, kD[k], den);
       F.a = a;
       F.den = den;
     }
   }
   gj.run(w);
-  const int nface = 2 * (nx + ny);
   double* G = w.get("d2.G", (size_t)nface * r);
   auto ghosts = [&](const double* Kx) {
     hipLaunchKernelGGL(dk::k_ghosts2d, dim3(nface), dim3(64), 0, s, Kx, r, nx, ny, fs, G);
     BLR_CHECK_LAUNCH();
   };
-  // K-step
+  // ------------------------------------------------ K-step
   double* K = w.get("d2.K", (size_t)r * nc);
   double* K1 = w.get("d2.K1", (size_t)r * nc);
-  double* dK = w.get("d2.dK", (size_t)r * nc);
+  // dK and the working X^n side by side: both are Z rows of the S-pass reduction
+  double* Z = w.get("d2.Z", (size_t)2 * r * nc);
+  double* dK = Z;
   double* X1 = w.get("d2.X1", (size_t)r * nc);
   double* S1 = w.get("d2.S1", (size_t)r * r);
-  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, st->X, r, (int)nc,
-                     st->S, rc, K);
+  hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, Xw, r, (int)nc,
+                     Sw, lsw, K);
   BLR_CHECK_LAUNCH();
   ghosts(K);
   hipLaunchKernelGGL(dk::k_kstep2d, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, K, G, r, nx,
                      ny, dx, dy, dt, A, C, P, dpidx, dpidx + P, K1, dK);
   BLR_CHECK_LAUNCH();
   tsqr(ctx, K1, nc, nc, r, X1, nc, S1, "qr2.k", std::sqrt(wx), 1.0 / std::sqrt(wx));
-  // S-step (K = X1 S1 and its ghosts); kx = <X1_i, dK_j> for the residual
+  const int nz = drop_on ? 2 * r : r;
+  if (drop_on)
+    BLR_HIP(hipMemcpyAsync(Z + (long)r * nc, Xw, (size_t)r * nc * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  // ------------------------------------------------ S-step (K = X1 S1)
   double* D = w.get("d2.D", (size_t)4 * r * r);
   double* T = w.get("d2.T", (size_t)r * P);
-  double* kx = w.get("d2.kx", (size_t)r * r);
+  double* kz = w.get("d2.kz", (size_t)r * nz);   // [i][j]: <X1_i, dK_j>, then <X1_i, X^n_j>
   double* S2 = w.get("d2.S2", (size_t)r * r);
   double* dS = w.get("d2.dS", (size_t)r * r);
   hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, X1, r, (int)nc,
                      S1, r, K);
   BLR_CHECK_LAUNCH();
   ghosts(K);
-  hipLaunchKernelGGL(dk::k_xreduce2d, dim3(blocks((long)r * (5 * r + P), 4)), dim3(256), 0, s, X1,
-                     r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, dK, r, D, T, kx);
+  hipLaunchKernelGGL(dk::k_xreduce2d, dim3(blocks((long)r * (4 * r + P + nz), 4)), dim3(256), 0, s,
+                     X1, r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, Z, nz, D, T, kz);
   BLR_CHECK_LAUNCH();
   hipLaunchKernelGGL(dk::k_supdate2d, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, S1, r, D, A,
                      T, C, P, dt, S2, dS);
   BLR_CHECK_LAUNCH();
-  // L-step (K = X1 S2 and its ghosts)
+  // kx = <X1_i, dK_j> compact (r x r) for the residual
+  double* kx = w.get("d2.kx", (size_t)r * r);
+  hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, kz, nz, r, kx, r);
+  BLR_CHECK_LAUNCH();
+  // ------------------------------------------------ L-step (K = X1 S2)
   double* Dt = w.get("d2.Dt", (size_t)4 * r * r);
   double* Tt = w.get("d2.Tt", (size_t)r * P);
   double* L1 = w.get("d2.L1", (size_t)r * n);
@@ -2121,18 +2273,20 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
                      r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, nullptr, 0, Dt, Tt, nullptr);
   BLR_CHECK_LAUNCH();
   if (fp64c)
-    hipLaunchKernelGGL(dk::k_lstep2d<double>, dim3(blocks((long)r * n, 256)), dim3(256), 0, s,
-                       st->V, r, n, S2, Dt, Tt, (const double*)Qs, P, dt, w.g, L1, dL);
+    hipLaunchKernelGGL(dk::k_lstep2d<double>, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, Vw,
+                       r, n, S2, Dt, Tt, (const double*)Qs, P, dt, w.g, L1, dL);
   else
-    hipLaunchKernelGGL(dk::k_lstep2d<float>, dim3(blocks((long)r * n, 256)), dim3(256), 0, s,
-                       st->V, r, n, S2, Dt, Tt, (const float*)Qs, P, dt, w.g, L1, dL);
+    hipLaunchKernelGGL(dk::k_lstep2d<float>, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, Vw,
+                       r, n, S2, Dt, Tt, (const float*)Qs, P, dt, w.g, L1, dL);
   BLR_CHECK_LAUNCH();
   tsqr(ctx, L1, n, n, r, V1, n, R, "qr2.l", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
-  // residual
+  // ------------------------------------------------ residual (Sec. 5.1)
   double* lv = w.get("d2.lv", (size_t)r * r);
+  double* Bv = w.get("d2.Bv", (size_t)r * r);
   {
     GramJob g2;
-    g2.add(dL, r, st->V, r, false, dk::W_ONE, dvd, lv);
+    g2.add(dL, r, Vw, r, false, dk::W_ONE, dvd, lv);
+    if (drop_on) g2.add(Vw, r, V1, r, false, dk::W_ONE, dvd, Bv);   // <V^n_l, V1_j>
     g2.run(w);
   }
   const int nbp = 256;
@@ -2143,23 +2297,85 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   BLR_CHECK_LAUNCH();
   hipLaunchKernelGGL(dk::k_err2d, dim3(1), dim3(64), 0, s, part, nbp, dS, kx, lv, r, wx, dvd, err);
   BLR_CHECK_LAUNCH();
-  double* hb = (double*)ctx->host_readback(sizeof(double));
-  BLR_HIP(hipMemcpyAsync(hb, err, sizeof(double), hipMemcpyDeviceToHost, s));
-  BLR_HIP(hipStreamSynchronize(s));
-  const double e = hb[0];
+  const double e = dev2host(err, 1)[0];
   require(std::isfinite(e), "two-dimensional step: non-finite residual", BLR_ERR_NUMERIC);
-  // commit: X = X1, S = R^T (L1^T = V1^T R), V = V1
-  BLR_HIP(hipMemcpyAsync(st->X, X1, (size_t)r * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(dk::k_store_RT, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, R, r, st->S, rc);
-  BLR_CHECK_LAUNCH();
-  BLR_HIP(hipMemcpyAsync(st->V, V1, (size_t)r * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  BLR_HIP(hipStreamSynchronize(s));
-  if (info) {
-    blr_step_info inf{};
-    inf.r_in = inf.r_out = r;
-    inf.err = inf.err_ada = e;
-    *info = inf;
+  blr_step_info inf{};
+  inf.r_in = r_in;
+  inf.r_added = r_added;
+  inf.err = e;
+  // ------------------------------------------------ drop (Sec. 3.2) and commit
+  if (!drop_on) {
+    BLR_HIP(hipMemcpyAsync(st->X, X1, (size_t)r * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(dk::k_store_RT, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, R, r, st->S,
+                       rc);
+    BLR_CHECK_LAUNCH();
+    BLR_HIP(hipMemcpyAsync(st->V, V1, (size_t)r * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    inf.err_ada = e;
+    inf.r_out = r;
+    st->r = r;
+  } else {
+    double* Sn = w.get("d2.Snew", (size_t)r * r);
+    double* U2 = w.get("d2.U2", (size_t)r * r);
+    double* s2 = w.get("d2.s2", (size_t)r);
+    double* W2 = w.get("d2.W2", (size_t)r * r);
+    hipLaunchKernelGGL(dk::k_store_RT, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, R, r, Sn, r);
+    BLR_CHECK_LAUNCH();
+    svd_small(ctx, Sn, r, U2, s2, W2, false);
+    // small factors on the host: S^n (working), <X^n_k, X1_i>, <V^n_l, V1_j>, U, sigma, W
+    std::vector<double> Shn(r * r);
+    {
+      const std::vector<double> sw = dev2host(Sw, (size_t)(r - 1) * lsw + r);
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) Shn[i * r + j] = sw[(size_t)i * lsw + j];
+    }
+    const std::vector<double> kzh = dev2host(kz, (size_t)r * nz);
+    const std::vector<double> Bh = dev2host(Bv, (size_t)r * r);
+    const std::vector<double> Uh = dev2host(U2, (size_t)r * r);
+    const std::vector<double> sh = dev2host(s2, (size_t)r);
+    const std::vector<double> Wh = dev2host(W2, (size_t)r * r);
+    const double drop_tol = sp->c_drop * e;
+    int keep = 0;
+    for (int i = 0; i < r; ++i) keep += sh[i] >= drop_tol;
+    keep = std::max(std::min(std::min(keep, r_max), r), std::min(r_min, r));
+    // err_ada^2 = err^2 - |Sigma_p|^2 + 2 <f^n, D>,  D = X1 U_p Sigma_p W_p^T V1,
+    // <f^n, D> = sum_kl S^n_kl (A M B^T)_kl, A_ki = <X^n_k, X1_i>, B_lj = <V^n_l, V1_j>
+    std::vector<double> M(r * r, 0.0), AM(r * r, 0.0);
+    double sp2 = 0.0;
+    for (int c = keep; c < r; ++c) {
+      sp2 += sh[c] * sh[c];
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) M[i * r + j] += Uh[i * r + c] * sh[c] * Wh[j * r + c];
+    }
+    for (int k = 0; k < r; ++k)
+      for (int j = 0; j < r; ++j) {
+        double a = 0.0;
+        for (int i = 0; i < r; ++i) a += kzh[(size_t)i * nz + r + k] * M[i * r + j];
+        AM[k * r + j] = a;
+      }
+    double fnD = 0.0;
+    for (int k = 0; k < r; ++k)
+      for (int l = 0; l < r; ++l) {
+        double v = 0.0;
+        for (int j = 0; j < r; ++j) v += AM[k * r + j] * Bh[l * r + j];
+        fnD += Shn[k * r + l] * v;
+      }
+    const double e2 = e * e - sp2 + 2.0 * fnD;
+    inf.err_ada = std::sqrt(std::max(e2, 0.0));
+    inf.drop_tol = drop_tol;
+    inf.r_out = keep;
+    // X_i = sum_l U[l][i] X1_l, V_i = sum_l W[l][i] V1_l (i < keep), S = diag(sigma)
+    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(nc, 256), keep), dim3(256), 0, s, X1, r, nc, U2,
+                       r, keep, 1.0, st->X, nc);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), keep), dim3(256), 0, s, V1, r, (long)n,
+                       W2, r, keep, 1.0, st->V, (long)n);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_diag, dim3(1), dim3(256), 0, s, s2, keep, st->S, rc);
+    BLR_CHECK_LAUNCH();
+    st->r = keep;
   }
+  BLR_HIP(hipStreamSynchronize(s));
+  if (info) *info = inf;
 }
 
 void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_params* sp,

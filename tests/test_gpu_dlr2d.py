@@ -4,7 +4,9 @@ face) against the oracle's step on the rectangle (oracle/dlr.py, pinned by
 tests/test_oracle_dlr2d.py).
 
 FP64 collisions: f = X S V on the grid to 1e-12 of max |f| and err to 1e-10
-relative, step by step.  FP32 collisions: ||f_gpu - f_ref|| <= 1e-5 dt
+relative, step by step; with the adaptivity (boundary rows of every face
+cell added, the rank decision on S) the added counts and ranks are
+identical, err and err_ada to 1e-9 and f to 1e-11.  FP32 collisions: ||f_gpu - f_ref|| <= 1e-5 dt
 ||sum K_m K_n Q+_mn|| (the pair operator's bound, as in one dimension).
 """
 import math
@@ -131,12 +133,38 @@ def test_steady_solve_runs_steps_on_the_rectangle(ctx):
     assert abs(info.err_ada - err) < 1e-10 * err
 
 
-def test_adaptive_flags_are_refused_on_the_rectangle(ctx):
-    spec, prob, st = _setup(2, 16, 4, 3, 3, 2)
+@pytest.mark.parametrize("d,N,m_rho,nx,ny,r", [(2, 16, 8, 4, 3, 3), (3, 8, 4, 3, 3, 2),
+                                               (2, 16, 4, 5, 4, 4)])
+def test_adaptive_steps_fp64(ctx, d, N, m_rho, nx, ny, r):
+    """Add (one boundary row per face cell) and drop on the rectangle: the
+    added counts, ranks, err and err_ada follow the oracle step by step."""
+    print(f"2D-space adaptive d={d} N={N} {nx}x{ny} r={r}", flush=True)
+    spec, prob, st = _setup(d, N, m_rho, nx, ny, r, seed=9)
+    g = Gpu(ctx, spec, prob, st, r_cap=16)
+    dt = 0.004
+    flags = blr.BLR_STEP_FP64_COLLISION | blr.BLR_STEP_ADD | blr.BLR_STEP_DROP
+    r_max = min(16, nx * ny)          # the rank never exceeds the cell count
+    cur = st
+    for k in range(3):
+        info = ctx.dlr_step(g.pb, g.st, blr.StepParams(dt, 0.2, 1e-10, 1, r_max, flags))
+        cur, oinfo = dlr.adaptive_step(cur, prob, dt, c=0.2, r_max=r_max,
+                                       rng=np.random.default_rng(k))
+        print(k, "r", info.r_added, info.r_out, oinfo.r_added, oinfo.r_out, "err", info.err,
+              oinfo.err, "ada", info.err_ada, oinfo.err_ada, flush=True)
+        assert info.r_added == oinfo.r_added and info.r_out == oinfo.r_out
+        assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
+        assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
+        f_ref = cur.full()
+        assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+
+
+def test_augmentation_limit_is_refused(ctx):
+    """2 (nx + ny) > 64 face cells: the augmentation is refused before any
+    work, the state untouched."""
+    spec, prob, st = _setup(2, 16, 4, 20, 13, 2)
     g = Gpu(ctx, spec, prob, st, r_cap=8)
     before = g.full()
-    for fl in (blr.BLR_STEP_ADD, blr.BLR_STEP_DROP):
-        with pytest.raises(blr.BlrError) as ei:
-            ctx.dlr_step(g.pb, g.st, blr.StepParams(0.004, 0.2, 1e-10, 1, 8, fl))
-        assert ei.value.code == blr.BLR_ERR_UNSUPPORTED
+    with pytest.raises(blr.BlrError) as ei:
+        ctx.dlr_step(g.pb, g.st, blr.StepParams(0.004, 0.2, 1e-10, 1, 8, blr.BLR_STEP_ADD))
+    assert ei.value.code == blr.BLR_ERR_UNSUPPORTED
     assert np.array_equal(g.full(), before)
