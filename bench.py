@@ -70,6 +70,14 @@ def parse():
                          "N_x = 200, 2D velocity 32^2) to err <= --fourier-tol by the low-rank "
                          "and the full-tensor method (minutes)")
     ap.add_argument("--fourier-tol", type=float, default=2e-7)
+    ap.add_argument("--paper-cavity", action="store_true",
+                    help="also solve the paper's lid-driven cavity (all walls diffusive, lid "
+                         "u_w = (1, 0)) on 16 x 16 cells, 2D velocity 32^2, by the low-rank and "
+                         "the full-tensor method (minutes)")
+    ap.add_argument("--cavity-tol", type=float, default=2e-7)
+    ap.add_argument("--cavity-cap", type=float, default=300.0,
+                    help="wall-clock cap in seconds per method of the cavity")
+    ap.add_argument("--cavity-rmax", type=int, default=30)
     ap.add_argument("--fourier-cap", type=float, default=420.0,
                     help="wall-clock cap in seconds per method of the Fourier flow")
     ap.add_argument("--serve-count", type=int, default=8,
@@ -459,6 +467,96 @@ def fourier_leg(args, blr, synth, torch, ctx):
             "T_next_to_walls_low_rank": [float(T_lr[0]), float(T_lr[-1])]}
 
 
+def cavity_leg(args, blr, synth, torch, ctx):
+    """The lid-driven cavity of Sec. 5.4 at a reduced spatial grid: (x, y) in
+    [0, 0.5]^2 with 16 x 16 cells (the paper uses 100 x 100; 16 x 16 is the
+    largest square grid whose 2 (nx + ny) boundary rows the GPU augmentation
+    takes), 2D velocity 32^2 on [-7.86, 7.86]^2, Maxwell diffusive walls with
+    T_w = 1 everywhere and u_w = (1, 0) on the lid y = 0.5, initial Maxwellian
+    rho = 1, u = (1, 1), T = 1 (as in the paper); Maxwell molecules
+    B = 1/(2 pi) in the Carleman form (8 directions), FP32 collisions,
+    dt = dx / (2 L_v).  Both methods run to err <= tol (the paper's res_tol
+    2e-7) or the wall-clock cap; the adaptive low-rank method starts at rank
+    1 with r_max = --cavity-rmax."""
+    import numpy as np
+    spec = synth.FOURIER
+    nx = ny = 16
+    N, L = spec.n, spec.L
+    dev = torch.device("cuda:0")
+    dx, dv = 0.5 / nx, 2 * L / N
+    dt = 0.5 * dx / L
+    tol = args.cavity_tol
+    vg = blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN)
+    v = synth.vgrid_points(2, N, L)
+    wall = torch.tensor(synth.maxwellian(v, 1.0, (0.0, 0.0), 1.0).reshape(-1), device=dev)
+    lid = torch.tensor(synth.maxwellian(v, 1.0, (1.0, 0.0), 1.0).reshape(-1), device=dev)
+    faces = [(wall, True), (wall, True), (wall, True), (lid, True)]
+    pb = ctx.make_problem2d(vg, nx, ny, 0.0, 0.5, 0.0, 0.5, faces)
+    f0 = synth.maxwellian(v, 1.0, (1.0, 1.0), 1.0).reshape(-1)
+    F0 = np.tile(f0, (nx * ny, 1))
+    vv = v.reshape(2, -1)
+
+    def moments(F):
+        w = dv * dv
+        rho = F.sum(axis=1) * w
+        u1 = (F * vv[0]).sum(axis=1) * w / rho
+        u2 = (F * vv[1]).sum(axis=1) * w / rho
+        E = 0.5 * (F * (vv ** 2).sum(axis=0)).sum(axis=1) * w
+        return (2 * E / rho - u1 * u1 - u2 * u2) / 2, u1, u2
+
+    rc, chunk = max(2, args.cavity_rmax), 25
+    X, S, V = synth.lowrank_state(F0, 1, dx * dx, dv * dv)
+    Xd = torch.zeros((rc, nx * ny), dtype=torch.float64, device=dev)
+    Sd = torch.zeros((rc, rc), dtype=torch.float64, device=dev)
+    Vd = torch.zeros((rc, N * N), dtype=torch.float64, device=dev)
+    Xd[:1] = torch.tensor(X.T, device=dev)
+    Sd[:1, :1] = torch.tensor(S, device=dev)
+    Vd[:1] = torch.tensor(V, device=dev)
+    st = ctx.make_state(Xd, Sd, Vd, 1)
+    torch.cuda.synchronize()
+    sp = blr.SolveParams(blr.StepParams(dt, 0.2, 1e-10, 1, rc,
+                                        blr.BLR_STEP_ADD | blr.BLR_STEP_DROP), tol, chunk)
+    steps_lr, ranks, conv_lr, li = 0, [], False, None
+    t0 = time.perf_counter()
+    while not conv_lr and time.perf_counter() - t0 < args.cavity_cap:
+        li = ctx.steady_solve(pb, st, sp, allow_unconverged=True)
+        steps_lr += int(li.steps)
+        conv_lr = bool(li.converged)
+        if not ranks or ranks[-1][1] != int(li.r) or steps_lr % 500 == 0:
+            ranks.append([steps_lr, int(li.r)])
+        progress(f"cavity: low-rank {steps_lr} steps, err_ada {li.err_ada:.3e}, rank {li.r}")
+    t_lr = time.perf_counter() - t0
+    r = st.r
+    F_lr = (Xd[:r].cpu().numpy().T @ Sd[:r, :r].cpu().numpy()) @ Vd[:r].cpu().numpy()
+    F = torch.tensor(F0, device=dev)
+    steps_full, e = 0, float("inf")
+    t0 = last = time.perf_counter()
+    while e > tol and time.perf_counter() - t0 < args.cavity_cap:
+        e = ctx.full_step(pb, F, dt, blr.BLR_FP32)
+        steps_full += 1
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            progress(f"cavity: full tensor {steps_full} steps, err_full {e:.3e}")
+    t_full = time.perf_counter() - t0
+    m_lr, m_full = moments(F_lr), moments(F.cpu().numpy())
+    diffs = {nm: float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+             for nm, a, b in zip(("T", "u1", "u2"), m_lr, m_full)}
+    return {"shape": "lid-driven cavity: [0,0.5]^2 with 16x16 cells (paper: 100x100), 2D "
+                     "velocity 32^2 on [-7.86,7.86]^2, diffusive walls T_w=1, lid u_w=(1,0), "
+                     "initial Maxwellian rho=1 u=(1,1) T=1, Maxwell molecules B=1/(2 pi) "
+                     "(Carleman form, 8 directions), FP32 collisions, dt=dx/(2 L_v)",
+            "tol": tol, "r_max": rc,
+            "low_rank": {"steps": steps_lr, "converged": int(conv_lr),
+                         "err_ada": li.err_ada if li else None, "rank": int(r),
+                         "rank_history": ranks, "seconds": round(t_lr, 2),
+                         "ms_per_step": round(1e3 * t_lr / max(1, steps_lr), 4)},
+            "full_tensor": {"steps": steps_full, "converged": int(e <= tol), "err_full": e,
+                            "seconds": round(t_full, 2),
+                            "ms_per_step": round(1e3 * t_full / max(1, steps_full), 4)},
+            "max_rel_diff_low_rank_vs_full": diffs,
+            "u1_below_lid_full": [round(float(x), 5) for x in m_full[1][ny - 1::ny][::3]]}
+
+
 def serving_leg(args, blr, synth, torch, helper):
     """The serving trace on the batched FP32 path (slots solves at once) and on
     the plain FP64 per-pair path (one solve at a time, first in first out),
@@ -706,6 +804,9 @@ def main():
     fourier = None
     if args.paper_fourier:
         fourier = fourier_leg(args, blr, synth, torch, ctx)
+    cavity = None
+    if args.paper_cavity:
+        cavity = cavity_leg(args, blr, synth, torch, ctx)
 
     serving = None
     if args.mode == "step" and not args.no_serve:
@@ -755,6 +856,7 @@ def main():
         "carleman": carleman,
         "paper_shock": paper,
         "paper_fourier": fourier,
+        "paper_cavity": cavity,
         "serving": serving,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                     for t in sorted(timers, key=lambda t: -t["ms"])[:8]],

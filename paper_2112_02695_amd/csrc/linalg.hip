@@ -39,7 +39,12 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 constexpr int QT = 64;
 template <int RM>
 struct QRShape {
-  static constexpr int RPL = (48 / RM) < 1 ? 1 : ((48 / RM) > 4 ? 4 : (48 / RM));
+  // rows per lane: up to 4 for narrow panels, and at least 2 RM / QT so that a
+  // block holds twice as many rows as its R factor (each tree level halves
+  // the rows; with 64 rows for 64 columns the tree would never shrink)
+  static constexpr int RPL0 = (48 / RM) < 1 ? 1 : ((48 / RM) > 4 ? 4 : (48 / RM));
+  static constexpr int RMIN = (2 * RM + QT - 1) / QT;
+  static constexpr int RPL = RPL0 > RMIN ? RPL0 : RMIN;
   static constexpr int MBR = QT * RPL;  // rows per block
 };
 

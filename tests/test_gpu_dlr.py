@@ -94,11 +94,13 @@ def _params(dt, flags, r_max=30, r_min=1):
 
 
 @pytest.mark.parametrize("d,N,nx,r,m_rho", [(2, 16, 24, 4, 8), (3, 8, 16, 3, 4), (3, 16, 40, 5, 2),
-                                             (2, 16, 40, 17, 4), (2, 16, 300, 16, 4)])
+                                             (2, 16, 40, 17, 4), (2, 16, 300, 16, 4),
+                                             (2, 16, 300, 40, 2)])
 def test_fixed_rank_step_fp64(ctx, d, N, nx, r, m_rho):
     """r = 16 takes the widest fused x-side and Cholesky QR kernels, r = 17 the
     general ones (Householder QR, separate x-side kernels); nx = 300 spans
-    two cell blocks."""
+    two cell blocks; r = 40 takes the 64-column Householder tree (blocks of
+    128 rows)."""
     print(f"fixed-rank d={d} N={N} nx={nx} r={r}", flush=True)
     spec, prob, st, _ = _setup(d, N, nx, r, m_rho)
     if r > 8:
