@@ -2027,6 +2027,70 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
 
 }  // namespace
 
+// A = U diag(s) W^T for a small m x m row-major A on the host, by one-sided
+// (Hestenes) Jacobi: plane rotations of the columns of A W until every pair
+// of columns is orthogonal to rounding; s descending, U's columns the
+// normalised rotated columns (zero where s = 0).  Used by the two-dimensional
+// step, whose augmentation and rank decision factor matrices of up to 64 x 64
+// once per step and read them back anyway.
+static void host_svd(int m, const std::vector<double>& A, std::vector<double>& U,
+                     std::vector<double>& sv, std::vector<double>& W) {
+  std::vector<double> a(A);
+  std::vector<double> w((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) w[(size_t)i * m + i] = 1.0;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < m - 1; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = 0; i < m; ++i) {
+          const double x = a[(size_t)i * m + p], y = a[(size_t)i * m + q];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        if (ga == 0.0 || std::abs(ga) <= 1e-15 * std::sqrt(al * be)) continue;
+        rotated = true;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::abs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < m; ++i) {
+          double& x = a[(size_t)i * m + p];
+          double& y = a[(size_t)i * m + q];
+          const double xp = c * x - sn * y, yq = sn * x + c * y;
+          x = xp;
+          y = yq;
+          double& u = w[(size_t)i * m + p];
+          double& v = w[(size_t)i * m + q];
+          const double up = c * u - sn * v, vq = sn * u + c * v;
+          u = up;
+          v = vq;
+        }
+      }
+    if (!rotated) break;
+  }
+  std::vector<double> nrm(m);
+  std::vector<int> ord(m);
+  for (int j = 0; j < m; ++j) {
+    double s2 = 0.0;
+    for (int i = 0; i < m; ++i) s2 += a[(size_t)i * m + j] * a[(size_t)i * m + j];
+    nrm[j] = std::sqrt(s2);
+    ord[j] = j;
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
+  U.assign((size_t)m * m, 0.0);
+  W.assign((size_t)m * m, 0.0);
+  sv.assign(m, 0.0);
+  for (int k = 0; k < m; ++k) {
+    const int j = ord[k];
+    sv[k] = nrm[j];
+    for (int i = 0; i < m; ++i) {
+      U[(size_t)i * m + k] = nrm[j] > 0.0 ? a[(size_t)i * m + j] / nrm[j] : 0.0;
+      W[(size_t)i * m + k] = w[(size_t)i * m + j];
+    }
+  }
+}
+
 // ----------------------------------------------------- two-dimensional space
 // One K -> S -> L step on the rectangle (Sec. 2.2 applied along both axes,
 // the boundary of Sec. 2.3 on every face cell), eager, with the adaptivity of
@@ -2103,10 +2167,20 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
                          w.g);
       BLR_CHECK_LAUNCH();
     }
-    // F_b^T = Qb Rb, F_b = Rb^T Qb^T = Ub diag(sb) (Qb Wb)^T
+    // F_b^T = Qb Rb, F_b = Rb^T Qb^T = Ub diag(sig) (Qb Wb)^T; the small SVD on the host
     tsqr(ctx, Fb, n, n, nface, Qb, n, Rb, "qr2.fb", 1.0, 1.0);
-    svd_small(ctx, Rb, nface, Ub, sb, Wb, true);
-    const std::vector<double> sig = dev2host(sb, nface);
+    std::vector<double> sig, Uh, Wh;
+    {
+      const std::vector<double> R = dev2host(Rb, (size_t)nface * nface);
+      std::vector<double> RT((size_t)nface * nface);
+      for (int i = 0; i < nface; ++i)
+        for (int j = 0; j < nface; ++j) RT[(size_t)i * nface + j] = R[(size_t)j * nface + i];
+      host_svd(nface, RT, Uh, sig, Wh);
+      BLR_HIP(hipMemcpyAsync(Ub, Uh.data(), Uh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      BLR_HIP(hipStreamSynchronize(s));   // the host copy is read before it goes away
+    }
+    (void)sb;
+    (void)Wb;
     int rb = 0;
     for (int i = 0; i < nface; ++i) rb += sig[i] > sp->add_tol;
     rb = std::min(rb, r_max - r);
@@ -2318,10 +2392,21 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     double* U2 = w.get("d2.U2", (size_t)r * r);
     double* s2 = w.get("d2.s2", (size_t)r);
     double* W2 = w.get("d2.W2", (size_t)r * r);
-    hipLaunchKernelGGL(dk::k_store_RT, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, R, r, Sn, r);
-    BLR_CHECK_LAUNCH();
-    svd_small(ctx, Sn, r, U2, s2, W2, false);
-    // small factors on the host: S^n (working), <X^n_k, X1_i>, <V^n_l, V1_j>, U, sigma, W
+    (void)Sn;
+    // new S = R^T and its SVD on the host (uploaded for the commit kernels)
+    std::vector<double> Uh, sh, Wh;
+    {
+      const std::vector<double> Rh = dev2host(R, (size_t)r * r);
+      std::vector<double> Snh((size_t)r * r);
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) Snh[(size_t)i * r + j] = Rh[(size_t)j * r + i];
+      host_svd(r, Snh, Uh, sh, Wh);
+      BLR_HIP(hipMemcpyAsync(U2, Uh.data(), Uh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      BLR_HIP(hipMemcpyAsync(W2, Wh.data(), Wh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      BLR_HIP(hipMemcpyAsync(s2, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      BLR_HIP(hipStreamSynchronize(s));
+    }
+    // small factors on the host: S^n (working), <X^n_k, X1_i>, <V^n_l, V1_j>
     std::vector<double> Shn(r * r);
     {
       const std::vector<double> sw = dev2host(Sw, (size_t)(r - 1) * lsw + r);
@@ -2330,9 +2415,6 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     }
     const std::vector<double> kzh = dev2host(kz, (size_t)r * nz);
     const std::vector<double> Bh = dev2host(Bv, (size_t)r * r);
-    const std::vector<double> Uh = dev2host(U2, (size_t)r * r);
-    const std::vector<double> sh = dev2host(s2, (size_t)r);
-    const std::vector<double> Wh = dev2host(W2, (size_t)r * r);
     const double drop_tol = sp->c_drop * e;
     int keep = 0;
     for (int i = 0; i < r; ++i) keep += sh[i] >= drop_tol;
