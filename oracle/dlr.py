@@ -272,8 +272,15 @@ def add_boundary_basis(st: State, prob: Problem1D, add_tol: float = 1e-10,
                        r_max: int = 10 ** 9, rng=None):
     """Append the right singular vectors of F_b with sigma > add_tol (capped at
     r_max), a random X_h, zero-padded S; re-orthonormalise both sides by QR;
-    S_q = S_x S^ S_v^T.  Leaves f unchanged."""
+    S_q = S_x S^ S_v^T.  Leaves f unchanged.  On the rectangle F_b is first
+    projected onto the complement of span V (with every face cell's row the
+    rows far outnumber the room under the cap; the projection keeps that room
+    for new directions, and gives the same span when the cap does not bind)."""
     Fb = boundary_matrix(st, prob)
+    if isinstance(prob, Problem2D):
+        # on the rectangle the rows outnumber the room r_max - r: take the
+        # boundary information not yet in span V (rows projected onto V^perp)
+        Fb = Fb - prob.dvd * (Fb @ st.V.T) @ st.V
     _, sb, Qbt = np.linalg.svd(Fb, full_matrices=False)
     rb = int((sb > add_tol).sum())
     rb = max(0, min(rb, r_max - st.r))

@@ -1383,6 +1383,17 @@ __global__ __launch_bounds__(1024) void k_wall_rows2d(double* __restrict__ Fb, F
   }
 }
 
+// F_b[b] -= sum_l C[b][l] V_l (the rows projected onto V^perp, C = <F_b, V>)
+__global__ void k_proj_rows(double* __restrict__ Fb, int nb, long n, const double* __restrict__ C,
+                            int r, const double* __restrict__ V) {
+  const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (q >= n || b >= nb) return;
+  double s = 0.0;
+  for (int l = 0; l < r; ++l) s += C[b * r + l] * V[(long)l * n + q];
+  Fb[(long)b * n + q] -= s;
+}
+
 // S_aug = S^ Rv^T with S^ = [[S, 0], [0, 0]] (r x r block S, leading dim
 // lds) and Rv (ra x ra row-major): the state after appending basis rows whose
 // QR is V^T = Vq^T Rv
@@ -2165,6 +2176,18 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     if (walls) {
       hipLaunchKernelGGL(dk::k_wall_rows2d, dim3(nface), dim3(1024), 0, s, Fb, fr, walls, nx, ny,
                          w.g);
+      BLR_CHECK_LAUNCH();
+    }
+    // the rows outnumber the room r_max - r: keep that room for the boundary
+    // information not yet in span V (rows projected onto V^perp; the same span
+    // as the rows themselves when the cap does not bind)
+    {
+      double* Cb = w.get("d2.Cb", (size_t)nface * r);
+      GramJob gp;
+      gp.add(Fb, nface, st->V, r, false, dk::W_ONE, dvd, Cb);
+      gp.run(w);
+      hipLaunchKernelGGL(dk::k_proj_rows, dim3(blocks(n, 256), nface), dim3(256), 0, s, Fb, nface,
+                         (long)n, Cb, r, st->V);
       BLR_CHECK_LAUNCH();
     }
     // F_b^T = Qb Rb, F_b = Rb^T Qb^T = Ub diag(sig) (Qb Wb)^T; the small SVD on the host
