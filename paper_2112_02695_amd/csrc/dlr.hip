@@ -2165,8 +2165,6 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     double* Qb = w.get("d2.Qb", (size_t)nface * n);
     double* Rb = w.get("d2.Rb", (size_t)nface * nface);
     double* Ub = w.get("d2.Ub", (size_t)nface * nface);
-    double* sb = w.get("d2.sb", (size_t)nface);
-    double* Wb = w.get("d2.Wb", (size_t)nface * nface);
     hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, st->X, r,
                        (int)nc, st->S, rc, K);
     BLR_CHECK_LAUNCH();
@@ -2202,8 +2200,6 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
       BLR_HIP(hipMemcpyAsync(Ub, Uh.data(), Uh.size() * sizeof(double), hipMemcpyHostToDevice, s));
       BLR_HIP(hipStreamSynchronize(s));   // the host copy is read before it goes away
     }
-    (void)sb;
-    (void)Wb;
     int rb = 0;
     for (int i = 0; i < nface; ++i) rb += sig[i] > sp->add_tol;
     rb = std::min(rb, r_max - r);
@@ -2411,11 +2407,9 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     inf.r_out = r;
     st->r = r;
   } else {
-    double* Sn = w.get("d2.Snew", (size_t)r * r);
     double* U2 = w.get("d2.U2", (size_t)r * r);
     double* s2 = w.get("d2.s2", (size_t)r);
     double* W2 = w.get("d2.W2", (size_t)r * r);
-    (void)Sn;
     // new S = R^T and its SVD on the host (uploaded for the commit kernels)
     std::vector<double> Uh, sh, Wh;
     {
