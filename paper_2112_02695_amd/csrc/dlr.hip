@@ -2162,7 +2162,6 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   if (add_on) {
     double* K = w.get("d2.K", (size_t)r * nc);
     double* Fb = w.get("d2.Fb", (size_t)nface * n);
-    double* Qb = w.get("d2.Qb", (size_t)nface * n);
     double* Rb = w.get("d2.Rb", (size_t)nface * nface);
     double* Ub = w.get("d2.Ub", (size_t)nface * nface);
     hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, st->X, r,
@@ -2188,8 +2187,8 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
                          (long)n, Cb, r, st->V);
       BLR_CHECK_LAUNCH();
     }
-    // F_b^T = Qb Rb, F_b = Rb^T Qb^T = Ub diag(sig) (Qb Wb)^T; the small SVD on the host
-    tsqr(ctx, Fb, n, n, nface, Qb, n, Rb, "qr2.fb", 1.0, 1.0);
+    // F_b^T = Q Rb, F_b = Rb^T Q^T = Ub diag(sig) (Q Wb)^T; the small SVD on the host
+    tsqr(ctx, Fb, n, n, nface, nullptr, n, Rb, "qr2.fb", 1.0, 1.0);   // R only
     std::vector<double> sig, Uh, Wh;
     {
       const std::vector<double> R = dev2host(Rb, (size_t)nface * nface);
