@@ -168,3 +168,30 @@ def test_augmentation_limit_is_refused(ctx):
         ctx.dlr_step(g.pb, g.st, blr.StepParams(0.004, 0.2, 1e-10, 1, 8, blr.BLR_STEP_ADD))
     assert ei.value.code == blr.BLR_ERR_UNSUPPORTED
     assert np.array_equal(g.full(), before)
+
+
+def test_served_2d_solve_equals_the_direct_solve(ctx):
+    """A steady solve on the rectangle through the server (its own slot
+    context and stream) gives bitwise the factors of the same solve run
+    directly."""
+    spec, prob, st = _setup(2, 16, 4, 4, 4, 3, seed=6)
+    sp = blr.SolveParams(blr.StepParams(0.004, 0.2, 1e-10, 1, 8, blr.BLR_STEP_FP64_COLLISION),
+                         1e-30, 5)
+    a = Gpu(ctx, spec, prob, st, r_cap=8)
+    ia = ctx.steady_solve(a.pb, a.st, sp, allow_unconverged=True)
+    b = Gpu(ctx, spec, prob, st, r_cap=8)
+    torch.cuda.synchronize()
+    sv = blr.Server(0, slots=1)
+    try:
+        sv.submit(b.pb, b.st, sp, 1)
+        comps = []
+        while not comps:
+            got = sv.wait(timeout=120.0)
+            assert got, "no progress"
+            comps += got
+    finally:
+        sv.close()
+    c = comps[0]
+    assert c.status in (blr.BLR_OK, blr.BLR_ERR_NOT_CONVERGED), c.message
+    assert c.info.steps == ia.steps == 5
+    assert torch.equal(a.X, b.X) and torch.equal(a.S, b.S) and torch.equal(a.V, b.V)
