@@ -607,8 +607,9 @@ def serving_leg(args, blr, synth, torch, helper):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described "
-                                   "in DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "runs on one GPU only: sharding a solve across GPUs is not "
+                                   "implemented (independent requests can run one process per "
+                                   "GPU)", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
