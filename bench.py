@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["pairs", "step"], default="step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="skip the comparison with the oracle's stored values (tests/golden)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-full", action="store_true",
                     help="skip the full-tensor reference step (N_x collisions per step)")
@@ -604,6 +606,133 @@ def serving_leg(args, blr, synth, torch, helper):
     return out
 
 
+_CPU_VS = None
+
+
+def _cpu_worker_init(spec):
+    """Worker of the CPU baseline: one thread per process (the oracle's FFTs
+    and products are single-threaded; BLAS kept to one thread as well)."""
+    global _CPU_VS
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+    from oracle import collision as oc
+    _CPU_VS = oc.setup_from_spec(spec)
+
+
+def _cpu_pair(args):
+    from oracle import collision as oc
+    V, pair = args
+    q, _ = oc.q_pairs(V, [pair], _CPU_VS, conserve=True)
+    return q.shape
+
+
+def cpu_baseline_leg(spec, V, pairs):
+    """The float64 oracle (its FFT form) on all pairs of the rank-r basis at the
+    benchmark's grid, the pairs spread over one process per host core (each
+    pair is the oracle's own serial computation).  Runs before the GPU is
+    touched, so the worker processes are forked from a process without GPU
+    state.  Cores: the job's CPU share (OMP_NUM_THREADS where the job sets
+    it), at most os.cpu_count()."""
+    import multiprocessing as mp
+    ncpu = os.cpu_count() or 1
+    try:
+        share = int(os.environ.get("OMP_NUM_THREADS", ncpu))
+    except ValueError:
+        share = ncpu
+    workers = max(1, min(ncpu, share, len(pairs)))
+    with mp.get_context("fork").Pool(workers, initializer=_cpu_worker_init, initargs=(spec,)) as pool:
+        pool.map(_cpu_pair, [(V, pairs[0])] * workers)      # warm the workers
+        t0 = time.perf_counter()
+        pool.map(_cpu_pair, [(V, p) for p in pairs], chunksize=1)
+        t = time.perf_counter() - t0
+    return {"value": round(len(pairs) / t, 4), "unit": "pair evals/s", "cores": workers,
+            "kind": "oracle",
+            "sample": (f"all {len(pairs)} pairs Q_s(V_i,V_j) of the rank-10 basis on the full 32^3 "
+                       f"grid, float64 oracle (FFT form of the operator, numpy), one pair per task "
+                       f"over {workers} worker processes of one thread each"),
+            "seconds": round(t, 2), "os_cpu_count": ncpu}
+
+
+def parity_leg(blr, synth, torch, ctx):
+    """Errors of the library against the oracle's stored values (tests/golden,
+    written by scripts that call only the oracle): the benchmark's own 78
+    pair collisions and adaptive step, and single evaluations of the
+    homogeneous workloads.  Pair errors are ||Q - Q_ref|| / ||Q+_ref||."""
+    import numpy as np
+    gdir = os.path.join(ROOT, "tests", "golden")
+    out = {}
+    dev = "cuda"
+    try:
+        g = np.load(os.path.join(gdir, "c3_step.npz"))
+    except OSError:
+        g = None
+    if g is not None:
+        V32 = torch.tensor(np.ascontiguousarray(g["V_aug32"]), device=dev)
+        Q = ctx.collision_pairs(blr.vgrid_from_spec(synth.C3), V32, blr.upper_pairs(12))
+        torch.cuda.synchronize()
+        e = np.linalg.norm(Q.double().cpu().numpy() - g["q32"].astype(np.float64), axis=1) / \
+            g["qplus_norm"]
+        out["c3_78_pairs_fp32_max_err"] = float(e.max())
+        out["c3_78_pairs_fp32_median_err"] = float(np.median(e))
+        nx, r0, rm = int(g["nx"]), int(g["r_min"]), int(g["r_max"])
+        ini = synth.shock_initial(1.5, synth.C3, nx, -30.0, 30.0, pert=0.0, pert_rank=0)
+        fL, fR = torch.tensor(ini["fL"], device=dev), torch.tensor(ini["fR"], device=dev)
+        f_ref = (g["X1"] @ g["S1"]) @ g["V1"]
+        w = math.sqrt((60.0 / nx) * (2 * synth.C3.L / synth.C3.n) ** 3)
+        for name, fl in (("fp32", 0), ("fp64", blr.BLR_STEP_FP64_COLLISION)):
+            X = torch.zeros((rm, nx), dtype=torch.float64, device=dev)
+            S = torch.zeros((rm, rm), dtype=torch.float64, device=dev)
+            V = torch.zeros((rm, g["V0"].shape[1]), dtype=torch.float64, device=dev)
+            X[:r0] = torch.tensor(np.ascontiguousarray(g["X0"].T), device=dev)
+            S[:r0, :r0] = torch.tensor(np.ascontiguousarray(g["S0"]), device=dev)
+            V[:r0] = torch.tensor(np.ascontiguousarray(g["V0"]), device=dev)
+            pb = ctx.make_problem(blr.vgrid_from_spec(synth.C3), nx, -30.0, 30.0, fL, fR)
+            st = ctx.make_state(X, S, V, r0, seed=1)
+            sp = blr.StepParams(float(g["dt"]), 0.2, 1e-10, r0, rm,
+                                blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | fl)
+            info = ctx.dlr_step(pb, st, sp)
+            r = st.r
+            f = (X[:r].cpu().numpy().T @ S[:r, :r].cpu().numpy()) @ V[:r].cpu().numpy()
+            out[f"c3_step_{name}"] = {
+                "f_err_l2": float(w * np.linalg.norm(f - f_ref)),
+                "f_err_max_rel": float(np.abs(f - f_ref).max() / np.abs(f_ref).max()),
+                "fp32_bound_l2": float(1e-5 * float(g["dt"]) * float(g["gain_scale"])),
+                "ranks_match": bool(info.r_added == int(g["r_added"]) and
+                                    info.r_out == int(g["r_out"])),
+                "err_rel": float(abs(info.err - float(g["err"])) / float(g["err"]))}
+    try:
+        h = np.load(os.path.join(gdir, "c1_c2_q.npz"))
+    except OSError:
+        h = None
+    if h is not None:
+        bkw = synth.VGridSpec(d=3, n=32, L=8.0, gamma=0.0, C=1.0 / (4.0 * math.pi), m_rho=16,
+                              m_sigma=38)
+        for case, spec in (("c1", synth.C1), ("c2b", synth.C2), ("c2k", bkw)):
+            for dt in (torch.float64, torch.float32):
+                f = torch.tensor(np.ascontiguousarray(h[f"{case}_f"]).reshape(1, -1), dtype=dt,
+                                 device=dev)
+                q = ctx.collision_pairs(blr.vgrid_from_spec(spec, blr.BLR_NO_CONSERVE), f,
+                                        [(0, 0)])
+                torch.cuda.synchronize()
+                q = q.double().cpu().numpy()[0]
+                key = {"c1": "c1_2d_two_stream", "c2b": "c2_3d_bimaxwellian_hard_spheres",
+                       "c2k": "c2_3d_bkw_maxwell"}[case]
+                tag = "fp64" if dt == torch.float64 else "fp32"
+                out[f"{key}_{tag}_err"] = float(np.linalg.norm(q - h[f"{case}_q"]) /
+                                                float(h[f"{case}_gain_norm"]))
+                if case == "c2k":
+                    d = h["c2k_dfdt"]
+                    out[f"{key}_{tag}_vs_analytic_dfdt"] = float(np.abs(q - d).max() /
+                                                                 np.abs(d).max())
+    out["measure"] = ("pair / single evaluations: ||Q - Q_ref||_2 / ||Q+_ref||_2 (targets 1e-5 FP32, "
+                      "1e-12 FP64); step: L2(x,v) norm of f - f_ref against the FP32 collision "
+                      "bound 1e-5 dt ||sum K_m K_n Q+_mn||, and max |f - f_ref| / max |f_ref|")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -617,12 +746,6 @@ def main():
     import paper_2112_02695_amd as blr
     import synth
 
-    lib = blr.load_library()
-    lib.blr_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
-    lib.blr_timing_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
-                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
-                                    ctypes.POINTER(ctypes.c_double)]
-
     spec = synth.C3
     nx, r, r_cap = 256, 10, 12
     dt = 0.01
@@ -631,6 +754,16 @@ def main():
     dvd = (2 * spec.L / spec.n) ** 3
     X, S, V = synth.lowrank_state(ini["f0"], r, dx, dvd)
     pairs = blr.upper_pairs(r)
+    cpu = None
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle, all 55 pairs over the host cores)")
+        cpu = cpu_baseline_leg(spec, V, pairs)
+
+    lib = blr.load_library()
+    lib.blr_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.blr_timing_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_double)]
     P = len(pairs)
     flags = blr.BLR_GENERIC_FFT if args.generic else 0
     vg = blr.vgrid_from_spec(spec, flags)
@@ -837,18 +970,10 @@ def main():
     if args.mode == "step" and not args.no_serve:
         serving = serving_leg(args, blr, synth, torch, ctx)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        progress("cpu baseline (oracle)")
-        from oracle import collision as oc
-        vs = oc.setup_from_spec(spec)
-        tc = time.perf_counter()
-        oc.q_pairs(V, [pairs[1]], vs, conserve=True)
-        t_cpu = time.perf_counter() - tc
-        cpu = {"value": round(1.0 / t_cpu, 5), "unit": "pair evals/s", "cores": 1, "kind": "oracle",
-               "sample": "1 of the 55 pairs (Q_s(V_0,V_1)) on the full 32^3 grid, float64 oracle "
-                         "(FFT form of the operator, numpy, single thread)",
-               "seconds": round(t_cpu, 2)}
+    parity = None
+    if not args.no_parity:
+        progress("parity against the oracle's stored values")
+        parity = parity_leg(blr, synth, torch, ctx)
 
     line = {
         "metric": "Q(V_i,V_j) evals/s at N_v=32^3 + p50/p99 solve latency, batched vs plain",
@@ -875,6 +1000,7 @@ def main():
         "step": step_extra,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "parity": parity,
         "plain_fp64_pair_evals_per_s": round(plain, 2) if plain else None,
         "latency": latency,
         "full_tensor": full,

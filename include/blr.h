@@ -158,8 +158,7 @@ typedef struct {
    * blr_dlr_step and blr_steady_solve run on the rectangle (the state's X
    * has rows of nx ny values; the rank is capped at nx ny); BLR_STEP_ADD
    * takes one boundary row per face cell and needs 2 (nx + ny) <= 64, else
-   * BLR_ERR_UNSUPPORTED; steps there run eagerly (no recorded graph);
-   * blr_state_from_full is one-dimensional only. */
+   * BLR_ERR_UNSUPPORTED; steps there run eagerly (no recorded graph). */
   int32_t ny;
   double y_lo, y_hi;
   const double* f_bottom;
@@ -228,8 +227,18 @@ typedef struct {
   float ms_collision, ms_step;
 } blr_step_info;
 
-/* Truncated SVD of a full f0 (Sec. 2.4, first paragraph): f0 is device FP64,
- * nx rows of n^d values; writes rank-r factors into *state (state->r = r). */
+/* Truncated SVD of a full f0 (Sec. 2.4, first paragraph: the initial factors
+ * are the truncated SVD of f at t = 0).  f0: device FP64, caller-owned, one
+ * row of n^d values per cell (nx rows; nx ny on a rectangle, cell ix ny + iy),
+ * not modified.  Writes the rank-r factors of sqrt(wx dv^d) f0 = U Sigma W^T
+ * (wx = dx, or dx dy on a rectangle) into *state: X_i = U_i / sqrt(wx),
+ * V_i = W_i / sqrt(dv^d), S = diag(sigma_1 >= .. >= sigma_r); state->r = r.
+ * The SVD is one-sided Jacobi on the device (FP64; no Gram matrix), so every
+ * singular value keeps high relative accuracy.  1 <= r <= min(r_cap, cells,
+ * n^d), else BLR_ERR_ARG; at most 8192 cells (BLR_ERR_UNSUPPORTED); f0 of
+ * rank below r or not finite: BLR_ERR_NUMERIC.  Uses workspace of cells x
+ * (n^d + cells) doubles and waits for the result (one host wait per sweep of
+ * the Jacobi rotations). */
 blr_status blr_state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0,
                                int32_t r, blr_state* state);
 

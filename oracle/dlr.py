@@ -191,6 +191,18 @@ def evaluate_pairs(V, pairs, prob):
     return oc.q_pairs(V, pairs, prob.vs, conserve=prob.conserve)
 
 
+def initial_state(F0: np.ndarray, r: int, wx: float, dvd: float) -> State:
+    """Rank-r initial factors of a full f^0 (Sec. 2.4, first paragraph: the
+    initial values of X, S, V come from a truncated SVD of f^0).  The SVD is
+    taken of sqrt(wx dv^d) F0 (cells x n) so that the weights of the two
+    inner products are folded into the factors: X = U_r / sqrt(wx),
+    V = W_r^T / sqrt(dv^d), S = diag(sigma_1..sigma_r); then
+    f_r = X S V is the best rank-r approximation in the L2(x, v) norm."""
+    U, s, Wt = np.linalg.svd(math.sqrt(wx * dvd) * np.asarray(F0, dtype=np.float64),
+                             full_matrices=False)
+    return State(U[:, :r] / math.sqrt(wx), np.diag(s[:r]), Wt[:r] / math.sqrt(dvd))
+
+
 # ----------------------------------------------------------------------------
 # one fixed-rank step (Sec. 2.4)
 # ----------------------------------------------------------------------------

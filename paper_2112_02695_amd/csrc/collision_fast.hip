@@ -649,7 +649,8 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
       int nvalid = 0;
       for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
       const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
-      timed_begin("fast.reduce", (double)h.mrho * n * (nload * h.nbp + nvalid) * sizeof(float), s);
+      timed_begin("fast.reduce.g" + std::to_string(G),
+                  (double)h.mrho * n * (nload * h.nbp + nvalid) * sizeof(float), s);
       const dim3 grid((n + 255) / 256, h.mrho);
       auto launch = [&](auto Gc) {
         constexpr int Gt = decltype(Gc)::value;

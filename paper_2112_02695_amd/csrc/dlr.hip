@@ -331,6 +331,123 @@ __global__ void k_scale_copy(const double* __restrict__ in, long count, double s
 
 
 
+// ---- truncated SVD of a full f0 (state_from_full) ----------------------
+constexpr int SFF_BS = 256;
+
+__global__ void k_sff_load(const double* __restrict__ f0, long count, double w,
+                           double* __restrict__ Y) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < count) Y[e] = w * f0[e];
+}
+
+__global__ void k_sff_eye(double* __restrict__ W, int m) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < (long)m * m) W[e] = (e / m == e % m) ? 1.0 : 0.0;
+}
+
+__global__ void k_sff_flag(int* flag, int v) {
+  if (threadIdx.x == 0) flag[0] = v;
+}
+
+// fixed-order sum of SFF_BS values per component over the block (3 at once)
+__device__ __forceinline__ void sff_reduce3(double* sh, double& a, double& b, double& c) {
+  const int t = threadIdx.x;
+  sh[t] = a;
+  sh[SFF_BS + t] = b;
+  sh[2 * SFF_BS + t] = c;
+  __syncthreads();
+  for (int w = SFF_BS / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      sh[t] += sh[t + w];
+      sh[SFF_BS + t] += sh[SFF_BS + t + w];
+      sh[2 * SFF_BS + t] += sh[2 * SFF_BS + t + w];
+    }
+    __syncthreads();
+  }
+  a = sh[0];
+  b = sh[SFF_BS];
+  c = sh[2 * SFF_BS];
+}
+
+// One round of the round-robin schedule on mpad (even) indices: pair slot k
+// of round t is (mpad - 1, t) for k = 0 and ((t + k) mod (mpad - 1),
+// (t - k) mod (mpad - 1)) otherwise; indices >= m are padding.  The block
+// of slot k rotates rows p, q of Y (length n) and of W (length m) so that
+// <y_p, y_q> = 0, unless they already are orthogonal to tol.
+__global__ __launch_bounds__(SFF_BS) void k_sff_round(double* __restrict__ Y, long n,
+                                                      double* __restrict__ W, int m, int mpad,
+                                                      int round, double tol, int* flag) {
+  __shared__ double sh[3 * SFF_BS];
+  const int k = blockIdx.x, M1 = mpad - 1;
+  int p, q;
+  if (k == 0) {
+    p = M1;
+    q = round;
+  } else {
+    p = (round + k) % M1;
+    q = (round - k + M1) % M1;
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+  if (q >= m) return;
+  double* yp = Y + (long)p * n;
+  double* yq = Y + (long)q * n;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (long e = threadIdx.x; e < n; e += SFF_BS) {
+    const double x = yp[e], y = yq[e];
+    a += x * x;
+    b += y * y;
+    c += x * y;
+  }
+  sff_reduce3(sh, a, b, c);
+  if (!(fabs(c) > tol * sqrt(a) * sqrt(b))) return;
+  // rotation angle of one-sided Jacobi: t the smaller root of
+  // t^2 + 2 z t - 1 = 0, z = (b - a) / (2 c)
+  const double z = (b - a) / (2.0 * c);
+  const double t = (z >= 0 ? 1.0 : -1.0) / (fabs(z) + hypot(1.0, z));
+  const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+  for (long e = threadIdx.x; e < n; e += SFF_BS) {
+    const double x = yp[e], y = yq[e];
+    yp[e] = cs * x - sn * y;
+    yq[e] = sn * x + cs * y;
+  }
+  double* wp = W + (long)p * m;
+  double* wq = W + (long)q * m;
+  for (int e = threadIdx.x; e < m; e += SFF_BS) {
+    const double x = wp[e], y = wq[e];
+    wp[e] = cs * x - sn * y;
+    wq[e] = sn * x + cs * y;
+  }
+  if (threadIdx.x == 0) flag[0] = 1;
+}
+
+__global__ __launch_bounds__(SFF_BS) void k_sff_norms(const double* __restrict__ Y, long n,
+                                                      double* __restrict__ nrm) {
+  __shared__ double sh[3 * SFF_BS];
+  const double* y = Y + (long)blockIdx.x * n;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (long e = threadIdx.x; e < n; e += SFF_BS) a += y[e] * y[e];
+  sff_reduce3(sh, a, b, c);
+  if (threadIdx.x == 0) nrm[blockIdx.x] = sqrt(a);
+}
+
+// X_k = W[idx_k] / sqrt(wx), V_k = Y[idx_k] / (sigma_k sqrt(dv^d)), S = diag(sigma)
+__global__ void k_sff_store(const double* __restrict__ Y, long n, const double* __restrict__ W,
+                            int m, const double* __restrict__ nrm, const int* __restrict__ idx,
+                            int r, double sx, double sv, double* __restrict__ X,
+                            double* __restrict__ V, double* __restrict__ S, int r_cap) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  const int i = idx[k];
+  const double sg = nrm[i];
+  if (e < n) V[(long)k * n + e] = Y[(long)i * n + e] * (sv / sg);
+  if (e < m) X[(long)k * m + e] = W[(long)i * m + e] * sx;
+  if (e < r) S[(long)k * r_cap + e] = (e == k) ? sg : 0.0;
+}
+
 // small dense algebra (one block)
 // S2 = S1 + dt (Dp Ap^T + Dm Am^T - T C^T);  dS = S2 - S1
 __global__ void k_supdate(const double* S1, const double* Dp, const double* Dm, const double* T,
@@ -2575,50 +2692,84 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   if (info) *info = inf;
 }
 
-// Truncated SVD of f0 (nx x n, row-major) via the weighted Gram matrix
-// G = w f0 f0^T (nx x nx) is not used: the factors come from a QR of
-// sqrt(w) f0^T (n x nx) and an SVD of its nx x nx R factor, which needs
-// nx <= 64.  Larger nx is rejected (initial states are then built by the
-// caller).
+// Truncated SVD of f0 (Sec. 2.4, first paragraph) by one-sided Jacobi on the
+// rows of Y = sqrt(wx dv^d) f0 (cells x n, row-major): pairs of rows are
+// rotated until every pair is orthogonal to working precision, the same
+// rotations accumulated in W (cells x cells, from the identity).  Then
+// Y = W A with orthogonal rows, so A = W^T Y: the row norms of Y are the
+// singular values, the rows of W the left and the normalised rows of Y the
+// right singular vectors.  One-sided Jacobi keeps every singular value to
+// high relative accuracy (no Gram matrix is formed).  Each round rotates
+// cells/2 disjoint pairs (round-robin schedule, one workgroup per pair); a
+// sweep of cells - 1 rounds meets every pair once; sweeps repeat until one
+// applies no rotation.
 void state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0, int r, blr_state* st) {
   require(pb && st && f0, "null argument");
   validate_vgrid(pb->v);
-  require(pb->ny <= 1, "state_from_full: one-dimensional space (problem.ny <= 1)",
-          BLR_ERR_UNSUPPORTED);
+  const bool two_d = pb->ny >= 2;
+  require(pb->nx >= 1, "nx must be >= 1");
+  require(st->r_cap >= 1 && st->r_cap <= 64, "r_cap must be in [1, 64]");
   require(st->r_cap >= r && r >= 1, "r must be in [1, r_cap]");
-  require(pb->nx <= 64, "state_from_full: nx must be <= 64", BLR_ERR_UNSUPPORTED);
   const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;
-  const int nx = pb->nx, n = h.n;
-  const double dx = (pb->x_hi - pb->x_lo) / nx, dvd = std::pow(h.dv, h.d);
+  const int cells = pb->nx * (two_d ? pb->ny : 1);
+  const long n = h.n;
+  require(r <= cells && r <= n, "r must not exceed the number of cells nor of velocity points");
+  require(cells <= 8192, "state_from_full: at most 8192 cells", BLR_ERR_UNSUPPORTED);
+  const double dx = (pb->x_hi - pb->x_lo) / pb->nx;
+  const double wx = two_d ? dx * (pb->y_hi - pb->y_lo) / pb->ny : dx;
+  const double dvd = std::pow(h.dv, h.d);
+  require(wx > 0, "x_hi must exceed x_lo (and y_hi y_lo)");
   hipStream_t s = ctx->stream;
   auto get = [&](const char* nm, size_t c) {
     return (double*)ctx->buf(std::string("sff.") + nm, c * sizeof(double));
   };
-  // f0 row-major (nx x n) is column-major (n x nx) with ld n
-  double* Qf = get("Q", (size_t)nx * n);
-  double* Rf = get("R", (size_t)nx * nx);
-  double* Rt = get("Rt", (size_t)nx * nx);
-  tsqr(ctx, f0, n, n, nx, Qf, n, Rf, "qr.sff", std::sqrt(dx * dvd), 1.0);
-  // sqrt(w) f0 = R^T Q^T ; R^T = U Sig W^T -> left factors U, right Q W
-  hipLaunchKernelGGL(dk::k_transpose, dim3(1), dim3(1024), 0, s, Rf, nx, Rt);
+  double* Y = get("Y", (size_t)cells * n);
+  double* W = get("W", (size_t)cells * cells);
+  double* nrm = get("norm", cells);
+  int* flag = (int*)ctx->buf("sff.flag", sizeof(int));
+  int* hflag = (int*)ctx->host_readback(sizeof(double) * std::max(cells, 2));
+  hipLaunchKernelGGL(dk::k_sff_load, dim3(blocks((long)cells * n, 256)), dim3(256), 0, s, f0,
+                     (long)cells * n, std::sqrt(wx * dvd), Y);
   BLR_CHECK_LAUNCH();
-  double* U = get("U", (size_t)nx * nx);
-  double* sg = get("sig", nx);
-  double* W = get("W", (size_t)nx * nx);
-  svd_small(ctx, Rt, nx, U, sg, W);
-  // X_i = U[:, i] / sqrt(dx), V_i = (Q W)[:, i] / sqrt(dvd), S = diag(sig)
-  // U row-major (nx x nx): column i over rows x = rows combination of the identity
-  double* I = get("I", (size_t)nx * nx);
-  std::vector<double> eye((size_t)nx * nx, 0.0);
-  for (int i = 0; i < nx; ++i) eye[(size_t)i * nx + i] = 1.0;
-  BLR_HIP(hipMemcpyAsync(I, eye.data(), eye.size() * 8, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(nx, 256), r), dim3(256), 0, s, I, nx, (long)nx, U,
-                     nx, r, 1.0 / std::sqrt(dx), st->X, (long)nx);
+  hipLaunchKernelGGL(dk::k_sff_eye, dim3(blocks((long)cells * cells, 256)), dim3(256), 0, s, W,
+                     cells);
   BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), r), dim3(256), 0, s, Qf, nx, (long)n, W, nx,
-                     r, 1.0 / std::sqrt(dvd), st->V, (long)n);
+  if (cells > 1) {
+    const int mpad = cells + (cells & 1);
+    // rotate while |<y_p, y_q>| > tol |y_p| |y_q|: the rounding level of a dot
+    // product of n terms, so that a converged pair is not rotated again
+    const double tol = 2.0 * std::sqrt((double)n) * 2.220446049250313e-16;
+    bool done = false;
+    for (int sweep = 0; sweep < 60 && !done; ++sweep) {
+      hipLaunchKernelGGL(dk::k_sff_flag, dim3(1), dim3(64), 0, s, flag, 0);
+      BLR_CHECK_LAUNCH();
+      for (int round = 0; round < mpad - 1; ++round) {
+        hipLaunchKernelGGL(dk::k_sff_round, dim3(mpad / 2), dim3(dk::SFF_BS), 0, s, Y, n, W,
+                           cells, mpad, round, tol, flag);
+        BLR_CHECK_LAUNCH();
+      }
+      BLR_HIP(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      BLR_HIP(hipStreamSynchronize(s));
+      done = hflag[0] == 0;
+    }
+    require(done, "state_from_full: Jacobi SVD did not converge in 60 sweeps", BLR_ERR_NUMERIC);
+  }
+  hipLaunchKernelGGL(dk::k_sff_norms, dim3(cells), dim3(dk::SFF_BS), 0, s, Y, n, nrm);
   BLR_CHECK_LAUNCH();
-  hipLaunchKernelGGL(dk::k_diag, dim3(1), dim3(1024), 0, s, sg, r, st->S, st->r_cap);
+  double* hn = (double*)hflag;
+  BLR_HIP(hipMemcpyAsync(hn, nrm, sizeof(double) * cells, hipMemcpyDeviceToHost, s));
+  BLR_HIP(hipStreamSynchronize(s));
+  // the r largest singular values, in descending order (ties by index)
+  std::vector<int> order(cells);
+  for (int i = 0; i < cells; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hn[a] > hn[b]; });
+  for (int k = 0; k < r; ++k)
+    require(std::isfinite(hn[order[k]]), "state_from_full: f0 is not finite", BLR_ERR_NUMERIC);
+  require(hn[order[r - 1]] > 0.0, "state_from_full: f0 has rank below r", BLR_ERR_NUMERIC);
+  int* idx = (int*)ctx->upload("sff.idx", order.data(), sizeof(int) * r);
+  hipLaunchKernelGGL(dk::k_sff_store, dim3(blocks(std::max<long>(n, cells), 256), r), dim3(256),
+                     0, s, Y, n, W, cells, nrm, idx, r, 1.0 / std::sqrt(wx), 1.0 / std::sqrt(dvd),
+                     st->X, st->V, st->S, st->r_cap);
   BLR_CHECK_LAUNCH();
   BLR_HIP(hipStreamSynchronize(s));
   st->r = r;

@@ -42,8 +42,14 @@ def _spec(d, n, M):
     return synth.VGridSpec(d=3, n=n, L=8.0, gamma=1.0, C=1.0, m_rho=1, m_sigma=38)
 
 
+# 2D grids of 48 and 64 points per axis are switched off in the library (this
+# test at 64 points in FP64 ended in a GPU memory fault whose cause has not
+# been shown); the cases stay here, skipped, until it is.
+FAULTED_2D = pytest.mark.skip(reason="2D n = 48 / 64 switched off: a GPU run of this test at "
+                                     "64 points in FP64 faulted, cause not shown")
 CASES = [(2, 16, 8, 4), (2, 32, 16, 3), (2, 32, 6, 3), (3, 8, 38, 4), (3, 16, 38, 3),
-         (3, 24, 38, 3), (3, 32, 38, 2)]
+         (3, 24, 38, 3), (3, 32, 38, 2),
+         pytest.param(2, 48, 8, 3, marks=FAULTED_2D), pytest.param(2, 64, 16, 3, marks=FAULTED_2D)]
 
 
 @pytest.mark.parametrize("d,n,M,r", CASES)

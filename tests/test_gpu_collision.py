@@ -42,7 +42,13 @@ def _rel_err(q, qref, gref):
     return np.linalg.norm(q - qref, axis=1) / np.linalg.norm(gref, axis=1)
 
 
-CASES = [(3, 8, 8, 5), (3, 16, 4, 4), (2, 16, 8, 5), (2, 32, 16, 3), (3, 24, 2, 3)]
+# 2D grids of 48 and 64 points per axis are switched off in the library (a
+# GPU run of the 64-point FP64 line passes ended in a memory fault whose cause
+# has not been shown); their parity cases stay here, skipped, until it is.
+FAULTED_2D = pytest.mark.skip(reason="2D n = 48 / 64 switched off: a GPU run of the 64-point "
+                                     "FP64 line passes faulted, cause not shown")
+CASES = [(3, 8, 8, 5), (3, 16, 4, 4), (2, 16, 8, 5), (2, 32, 16, 3), (3, 24, 2, 3),
+         pytest.param(2, 48, 8, 3, marks=FAULTED_2D), pytest.param(2, 64, 8, 3, marks=FAULTED_2D)]
 
 
 @pytest.mark.parametrize("d,n,m_rho,r", CASES)

@@ -24,6 +24,23 @@ if not torch.cuda.is_available():
 import paper_2112_02695_amd as blr  # noqa: E402
 
 
+def _check_adaptive_fp64(f_gpu, f_ref):
+    """An adaptive FP64 step is held to 1e-12 of ||f|| in the L2 norm and to
+    1e-11 of max |f| pointwise.  The pointwise bound is looser because the
+    directions the basis augmentation adds are the boundary rows' parts
+    outside span V, which can be small (at the benchmark state 2e-6 and
+    5e-7 of the rows), so rounding fixes them only to about eps over that
+    size; two equivalent FP64 orthogonalisations of the oracle's own then
+    give steps 6e-12 apart in max |f|, in the tails of the velocity box, and
+    3.6e-13 apart in L2."""
+    d = f_gpu - f_ref
+    l2 = np.linalg.norm(d) / np.linalg.norm(f_ref)
+    mx = np.abs(d).max() / np.abs(f_ref).max()
+    print(f"  f: L2 rel {l2:.2e}, max rel {mx:.2e}", flush=True)
+    assert l2 < 1e-12
+    assert mx < 1e-11
+
+
 @pytest.fixture(scope="module")
 def ctx():
     c = blr.Context(0)
@@ -156,7 +173,7 @@ def test_adaptive_steps_fp64(ctx, d, N, nx, r, m_rho):
         assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
         assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
         f_ref = cur.full()
-        assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+        _check_adaptive_fp64(g.full(), f_ref)
         # the bound of Sec. 5.1 holds on the GPU too
         bound = math.sqrt(max(info.r_in + info.r_added - info.r_out, 0)) * info.drop_tol
         assert abs(info.err - info.err_ada) <= bound * (1 + 1e-12) + 1e-15
@@ -203,7 +220,7 @@ def test_adaptive_steps_with_walls_fp64(ctx, d, N, nx, r, m_rho, walls):
         assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
         assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
         f_ref = cur.full()
-        assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+        _check_adaptive_fp64(g.full(), f_ref)
 
 
 def test_wall_flags_are_checked(ctx):
@@ -284,7 +301,7 @@ def test_add_count_change_is_redone(ctx):
         assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
         assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
         f_ref = cur.full()
-        assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+        _check_adaptive_fp64(g.full(), f_ref)
 
 
 def test_graph_replay_matches_eager(ctx):

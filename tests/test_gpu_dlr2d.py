@@ -6,8 +6,10 @@ tests/test_oracle_dlr2d.py).
 FP64 collisions: f = X S V on the grid to 1e-12 of max |f| and err to 1e-10
 relative, step by step; with the adaptivity (boundary rows of every face
 cell added, the rank decision on S) the added counts and ranks are
-identical, err and err_ada to 1e-9 and f to 1e-11.  FP32 collisions: ||f_gpu - f_ref|| <= 1e-5 dt
-||sum K_m K_n Q+_mn|| (the pair operator's bound, as in one dimension).
+identical, err and err_ada to 1e-9, f to 1e-12 of ||f|| (L2) and 1e-11 of
+max |f| (see _check_adaptive_fp64).  FP32 collisions: ||f_gpu - f_ref|| <=
+1e-5 dt ||sum K_m K_n Q+_mn|| (the pair operator's bound, as in one
+dimension).
 """
 import math
 
@@ -25,6 +27,23 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_2112_02695_amd as blr  # noqa: E402
+
+
+def _check_adaptive_fp64(f_gpu, f_ref):
+    """An adaptive FP64 step is held to 1e-12 of ||f|| in the L2 norm and to
+    1e-11 of max |f| pointwise.  The pointwise bound is looser because the
+    directions the basis augmentation adds are the boundary rows' parts
+    outside span V, which can be small (at the benchmark state 2e-6 and
+    5e-7 of the rows), so rounding fixes them only to about eps over that
+    size; two equivalent FP64 orthogonalisations of the oracle's own then
+    give steps 6e-12 apart in max |f|, in the tails of the velocity box, and
+    3.6e-13 apart in L2."""
+    d = f_gpu - f_ref
+    l2 = np.linalg.norm(d) / np.linalg.norm(f_ref)
+    mx = np.abs(d).max() / np.abs(f_ref).max()
+    print(f"  f: L2 rel {l2:.2e}, max rel {mx:.2e}", flush=True)
+    assert l2 < 1e-12
+    assert mx < 1e-11
 
 
 @pytest.fixture(scope="module")
@@ -155,7 +174,7 @@ def test_adaptive_steps_fp64(ctx, d, N, m_rho, nx, ny, r):
         assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
         assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
         f_ref = cur.full()
-        assert np.abs(g.full() - f_ref).max() < 1e-11 * np.abs(f_ref).max()
+        _check_adaptive_fp64(g.full(), f_ref)
 
 
 def test_augmentation_limit_is_refused(ctx):

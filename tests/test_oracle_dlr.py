@@ -216,3 +216,28 @@ def test_macroscopic_from_factors_matches_inputs():
     (rl, ul, Tl), (rr, ur, Tr) = ini["states"]
     assert abs(rho[0] - rl) < 2e-2 and abs(rho[-1] - rr) < 2e-2
     assert abs(u[0] - ul) < 5e-2 and abs(T[0] - Tl) < 5e-2
+
+
+# -------------------------------------------------------- initial truncation
+def test_initial_state_is_the_best_rank_r_approximation():
+    """Sec. 2.4's initial truncated SVD: orthonormal factors in the weighted
+    inner products, and the truncation error in the L2(x, v) norm equals the
+    root sum of squares of the dropped singular values (Eckart-Young); an
+    input of exact rank r is reproduced."""
+    prob, ini = _problem()
+    F0 = ini["f0"]
+    w = prob.dx * prob.dvd
+    sv = np.linalg.svd(math.sqrt(w) * F0, compute_uv=False)
+    for r in (1, 4, 9):
+        st = dlr.initial_state(F0, r, prob.dx, prob.dvd)
+        assert np.abs(prob.dx * st.X.T @ st.X - np.eye(r)).max() < 1e-13
+        assert np.abs(prob.dvd * st.V @ st.V.T - np.eye(r)).max() < 1e-13
+        gap = math.sqrt(w * ((F0 - st.full()) ** 2).sum())
+        tail = math.sqrt((sv[r:] ** 2).sum())
+        assert abs(gap - tail) <= 1e-10 * tail + 1e-15 * sv[0]
+        assert np.all(np.diff(np.diag(st.S)) <= 0)
+    # exact rank 3: product of seeded factors
+    rng = np.random.default_rng(5)
+    F3 = rng.standard_normal((prob.nx, 3)) @ rng.standard_normal((3, F0.shape[1]))
+    st = dlr.initial_state(F3, 3, prob.dx, prob.dvd)
+    assert np.abs(st.full() - F3).max() < 1e-13 * np.abs(F3).max()
