@@ -118,6 +118,25 @@ blr_status blr_collision_pairs(blr_ctx ctx, const blr_vgrid* vg, blr_precision p
                                int32_t npairs, void* Q_out);
 /* npairs may be 0 (no work).  1 <= npairs <= 4096. */
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as blr_collision_pairs, same arguments and results, with every
+ * workspace buffer and the quadrature tables in a fixed device array that the
+ * library holds on each device it runs on (BLR_NOALLOC_SCRATCH_BYTES, from
+ * its first use there until the process ends) instead of in the context's
+ * workspace.  The call allocates no device or pinned host memory; it copies
+ * its tables and index arrays from pageable host memory on the context
+ * stream (such copies may wait for earlier work on that stream).
+ *   BLR_ERR_ARG when the call's workspace (shifted fields, products, spectra,
+ *   tables) would exceed BLR_NOALLOC_SCRATCH_BYTES; nothing is issued then.
+ * All calls on one device share that array: calls that overlap on a device
+ * (other contexts or streams included) race; serialise them.  Nothing left
+ * in the array by an earlier call is relied on. */
+#define BLR_NOALLOC_SCRATCH_BYTES (64u << 20)
+blr_status blr_collision_pairs_noalloc(blr_ctx ctx, const blr_vgrid* vg, blr_precision prec,
+                                       const void* V, int32_t r, const int32_t* pairs,
+                                       int32_t npairs, void* Q_out);
+
 /* ------------------------------------------------------------------ DLR -- */
 
 /* One-dimensional physical space along the first velocity axis (the normal

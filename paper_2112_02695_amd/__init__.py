@@ -36,7 +36,7 @@ STATUS = {0: "BLR_OK", 1: "BLR_ERR_ARG", 2: "BLR_ERR_NOMEM", 3: "BLR_ERR_HIP",
           4: "BLR_ERR_UNSUPPORTED", 5: "BLR_ERR_NUMERIC", 6: "BLR_ERR_NOT_CONVERGED"}
 
 EXPORTS = ["blr_create", "blr_destroy", "blr_last_error", "blr_workspace_bytes",
-           "blr_collision_pairs", "blr_state_from_full", "blr_dlr_step", "blr_steady_solve",
+           "blr_collision_pairs", "blr_collision_pairs_noalloc", "blr_state_from_full", "blr_dlr_step", "blr_steady_solve",
            "blr_full_step", "blr_server_create", "blr_server_submit", "blr_server_wait",
            "blr_server_load", "blr_server_clock", "blr_server_last_error", "blr_server_destroy"]
 
@@ -127,6 +127,8 @@ def load_library(path: str = LIB_PATH):
                                         ctypes.POINTER(ctypes.c_size_t)]
     lib.blr_collision_pairs.argtypes = [P, ctypes.POINTER(VGrid), ctypes.c_int, P, ctypes.c_int32,
                                         P, ctypes.c_int32, P]
+    if hasattr(lib, "blr_collision_pairs_noalloc"):
+        lib.blr_collision_pairs_noalloc.argtypes = lib.blr_collision_pairs.argtypes
     if hasattr(lib, "blr_dlr_step"):
         lib.blr_state_from_full.argtypes = [P, ctypes.POINTER(Problem), P, ctypes.c_int32,
                                             ctypes.POINTER(State)]
@@ -204,9 +206,11 @@ class Context:
                                                  ctypes.byref(out)))
         return out.value
 
-    def collision_pairs(self, vg: VGrid, V, pairs, out=None):
+    def collision_pairs(self, vg: VGrid, V, pairs, out=None, noalloc: bool = False):
         """Q_s(V_i, V_j) for each row (i, j) of ``pairs``; V is a CUDA tensor
-        (r, n^d) of float32 or float64.  Returns (npairs, n^d) on the stream."""
+        (r, n^d) of float32 or float64.  Returns (npairs, n^d) on the stream.
+        noalloc: call blr_collision_pairs_noalloc (workspace in the library's
+        fixed device array; ``out`` must then be given)."""
         import torch
         if not (V.is_cuda and V.dim() == 2 and V.is_contiguous()):
             raise ValueError("V must be a contiguous 2-D CUDA tensor (r, n^d)")
@@ -216,7 +220,8 @@ class Context:
         if out is None:
             out = torch.empty((npairs, V.shape[1]), dtype=V.dtype, device=V.device)
         assert out.is_contiguous() and out.dtype == V.dtype and out.shape[0] >= npairs
-        self._check(self.lib.blr_collision_pairs(
+        fn = self.lib.blr_collision_pairs_noalloc if noalloc else self.lib.blr_collision_pairs
+        self._check(fn(
             self.h, ctypes.byref(vg), prec, ctypes.c_void_p(V.data_ptr()), V.shape[0],
             pr.ctypes.data_as(ctypes.c_void_p), npairs, ctypes.c_void_p(out.data_ptr())))
         return out

@@ -1,11 +1,27 @@
 // C ABI entry points, context, workspace and table cache.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "collision_common.hpp"
 #include "internal.hpp"
 
+void* blr_ctx_t::arena_slice(const std::string& name, size_t bytes) {
+  const size_t need = (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
+  auto it = arena_slices.find(name);
+  if (it != arena_slices.end() && it->second.second >= need) return it->second.first;
+  if (need > arena_cap - arena_used)
+    throw blr::Error(BLR_ERR_ARG, "allocation-free call: workspace exceeds the static scratch (" +
+                                      std::to_string(arena_cap) + " bytes)");
+  void* p = arena_base + arena_used;
+  arena_used += need;
+  arena_slices[name] = {p, need};
+  return p;
+}
+
 void* blr_ctx_t::buf(const std::string& name, size_t bytes) {
+  if (arena_on) return arena_slice(name, bytes);
   if (bytes == 0) bytes = 256;
   auto& b = bufs[name];
   if (b.bytes < bytes) {
@@ -35,6 +51,11 @@ void* blr_ctx_t::upload(const std::string& name, const void* host, size_t bytes)
   const std::string key = name + "#" + std::to_string(bytes) + "#" + std::to_string(hsh);
   void* dst = buf(key, bytes);
   if (bytes == 0) return dst;
+  if (arena_on) {
+    // from pageable host memory: the copy has read the source when it returns
+    BLR_HIP(hipMemcpyAsync(dst, host, bytes, hipMemcpyHostToDevice, stream));
+    return dst;
+  }
   auto& last = uploaded[key];
   if (last.first == dst && last.second.size() == bytes && std::memcmp(last.second.data(), hb, bytes) == 0)
     return dst;
@@ -192,8 +213,55 @@ static std::vector<T> cast_vec(const std::vector<double>& v) {
   return std::vector<T>(v.begin(), v.end());
 }
 
+// Allocation-free mode: the host tables are built once per configuration and
+// copied into the context's arena at every call (the arena is shared by all
+// calls on the device, so nothing left there by an earlier call is trusted).
+const HostTables& arena_host_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
+  auto& t = ctx->arena_tables;
+  const blr_vgrid& o = t ? t->vg : vg;
+  const bool same = t && t->prec == prec && o.d == vg.d && o.n == vg.n && o.L == vg.L &&
+                    o.R == vg.R && o.C == vg.C && o.gamma == vg.gamma && o.m_rho == vg.m_rho &&
+                    o.m_sigma == vg.m_sigma &&
+                    (o.flags & BLR_CARLEMAN) == (vg.flags & BLR_CARLEMAN);
+  if (!same) {
+    t = std::make_unique<DevTables>();
+    t->h = build_tables(vg);
+    t->prec = prec;
+    t->vg = vg;
+  }
+  return t->h;
+}
+
+static const DevTables& arena_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
+  const HostTables& h = arena_host_tables(ctx, vg, prec);
+  DevTables* t = ctx->arena_tables.get();
+  auto put = [&](const char* nm, const void* data, size_t bytes) -> void* {
+    void* p = ctx->arena_slice(std::string("tab.") + nm, bytes);
+    if (bytes) BLR_HIP(hipMemcpyAsync(p, data, bytes, hipMemcpyHostToDevice, ctx->stream));
+    return p;
+  };
+  auto putv = [&](const char* nm, const std::vector<double>& v) -> void* {
+    if (prec == BLR_FP32) {
+      const std::vector<float> f(v.begin(), v.end());
+      return put(nm, f.data(), f.size() * sizeof(float));
+    }
+    return put(nm, v.data(), v.size() * sizeof(double));
+  };
+  std::vector<double> wbp(h.nbp);
+  for (int p = 0; p < h.nbp; ++p) wbp[p] = h.wsig[h.bp_b[p]];
+  t->phase = putv("phase", h.phase);
+  t->fw = putv("fw", h.fw);
+  t->gloss = putv("gloss", h.gloss);
+  t->wbp = putv("wbp", wbp);
+  t->filt = h.carleman ? putv("filt", h.filt) : nullptr;
+  t->bp_b = (int*)put("bp_b", h.bp_b.data(), h.bp_b.size() * sizeof(int));
+  t->bp_bb = (int*)put("bp_bb", h.bp_bb.data(), h.bp_bb.size() * sizeof(int));
+  return *t;
+}
+
 const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
   validate_vgrid(vg);
+  if (ctx->arena_on) return arena_tables(ctx, vg, prec);
   const int ms = vg.m_sigma ? vg.m_sigma : (vg.d == 2 ? 8 : 38);
   const int form = (vg.flags & BLR_CARLEMAN) ? 1 : 0;
   auto key = std::make_tuple(vg.d, vg.n, vg.L, vg.R, vg.C, vg.gamma, vg.m_rho, ms, prec, form);
@@ -229,6 +297,57 @@ const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
 
 }  // namespace blr
 
+// ------------------------------------------------- allocation-free calls --
+// The device region of blr_collision_pairs_noalloc: one array per device, part
+// of the library's code object (so it exists, on each device the library runs
+// on, from the library's first use there until the process ends).  Host code
+// never passes `scratch` itself (its host-side name is not a device address):
+// blr_create resolves the array's device address once per device, with that
+// device current, and calls use that address.
+static constexpr size_t kScratchBytes = (size_t)BLR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, std::pair<hipError_t, void*>> g_scratch_addr;  // device -> (status, address)
+
+// Resolves the scratch array's address on `device` (current) once.
+void resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr.count(device)) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  g_scratch_addr[device] = {e, e == hipSuccess ? ptr : nullptr};
+}
+
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  blr::require(it != g_scratch_addr.end(), "scratch address not resolved for this device",
+               BLR_ERR_HIP);
+  if (it->second.first != hipSuccess)
+    throw blr::Error(BLR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(it->second.first));
+  return it->second.second;
+}
+
+// Arena mode for the duration of one call (left on every exit path).
+struct ArenaScope {
+  blr_ctx c;
+  ArenaScope(blr_ctx ctx, void* base, size_t cap) : c(ctx) {
+    c->arena_on = true;
+    c->arena_base = (char*)base;
+    c->arena_cap = cap;
+    c->arena_used = 0;
+    c->arena_slices.clear();
+  }
+  ~ArenaScope() {
+    c->arena_on = false;
+    c->arena_slices.clear();
+  }
+};
+}  // namespace
+
 // ----------------------------------------------------------------- C ABI --
 template <class F>
 static blr_status guarded(blr_ctx ctx, F&& f) {
@@ -262,6 +381,7 @@ blr_status blr_create(int device, void* hip_stream, blr_ctx* out) {
   if (!c) return BLR_ERR_NOMEM;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  resolve_scratch(device);
   for (auto& e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) {
       delete c;
@@ -297,6 +417,30 @@ blr_status blr_collision_pairs(blr_ctx ctx, const blr_vgrid* vg, blr_precision p
   return guarded(ctx, [&] {
     blr::require(vg != nullptr, "null vgrid");
     blr::require(prec == BLR_FP32 || prec == BLR_FP64, "bad precision");
+    blr::collision_pairs(ctx, *vg, prec, V, r, pairs, npairs, Q_out);
+  });
+}
+
+blr_status blr_collision_pairs_noalloc(blr_ctx ctx, const blr_vgrid* vg, blr_precision prec,
+                                       const void* V, int32_t r, const int32_t* pairs,
+                                       int32_t npairs, void* Q_out) {
+  return guarded(ctx, [&] {
+    blr::require(vg != nullptr, "null vgrid");
+    blr::require(prec == BLR_FP32 || prec == BLR_FP64, "bad precision");
+    blr::require(r >= 1 && r <= 64, "r must be in [1, 64]");
+    blr::require(npairs >= 0 && npairs <= 4096, "npairs must be in [0, 4096]");
+    blr::require(npairs == 0 || (pairs && V && Q_out), "null pointer argument");
+    if (npairs == 0) return;
+    blr::validate_vgrid(*vg);
+    void* base = scratch_address(ctx->device);
+    // the whole call's workspace must fit before anything is issued
+    const blr::HostTables& h = blr::arena_host_tables(ctx, *vg, prec);
+    const size_t need = blr::collision_call_bytes(h, prec, r, pairs, npairs, vg->flags);
+    blr::require(need <= kScratchBytes,
+                 "allocation-free call needs " + std::to_string(need) +
+                     " bytes of workspace; the static scratch holds " +
+                     std::to_string(kScratchBytes));
+    ArenaScope scope(ctx, base, kScratchBytes);
     blr::collision_pairs(ctx, *vg, prec, V, r, pairs, npairs, Q_out);
   });
 }

@@ -898,6 +898,61 @@ static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const
   if (!(flags & BLR_NO_CONSERVE)) conserve_rows<T>(ctx, h, Q, npairs);
 }
 
+static size_t up256(size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; }
+
+size_t table_bytes(const HostTables& h, int prec) {
+  const size_t T = prec == BLR_FP32 ? 4 : 8;
+  size_t b = up256(h.phase.size() * T) + up256(h.fw.size() * T) + up256(h.gloss.size() * T) +
+             up256((size_t)h.nbp * T) + 2 * up256((size_t)h.nbp * sizeof(int));
+  if (h.carleman) b += up256(h.filt.size() * T);
+  return b;
+}
+
+// Mirrors the buf()/upload() requests of collision_pairs below (basis
+// spectra, shifts, products, spectra, index arrays, moment partial sums).
+size_t collision_call_bytes(const HostTables& h, int prec, int r, const int32_t* pairs, int npairs,
+                            uint32_t flags) {
+  if (npairs == 0) return 0;
+  const size_t T = prec == BLR_FP32 ? 4 : 8, T2 = 2 * T;
+  const size_t n = h.n;
+  size_t b = table_bytes(h, prec);
+  auto generic = [&](size_t rb, size_t P) {
+    size_t g = up256(rb * n * T2) + up256(2 * rb * n * T) + up256(2 * rb * n * T2);  // basis
+    const size_t shift_fields = rb * h.mrho * h.nbp;
+    const size_t batch = std::min<size_t>(shift_fields, 512);
+    g += up256(rb * h.mrho * h.msig * n * T);                                // shifts
+    g += up256(std::max(batch, std::max(P, 2 * rb)) * n * T2);              // transforms
+    g += up256(P * n * T);                                                   // products
+    if (!h.carleman) g += up256(P * n * T2);                                 // spectra
+    return g;
+  };
+  if (flags & BLR_PLAIN_SCHEDULE) {
+    // one pair at a time: one- and two-function calls reuse their slices;
+    // every pair uploads its own index array
+    b += generic(1, 1) + generic(2, 1) + (size_t)npairs * up256(3 * sizeof(int));
+  } else {
+    PairPlan pl = make_plan(r, pairs, npairs);
+    const size_t rb = pl.bidx.size(), P = pl.li.size();
+    const bool fast = prec == BLR_FP32 && !(flags & BLR_GENERIC_FFT) && !h.carleman && h.d == 3 &&
+                      (h.N == 16 || h.N == 24 || h.N == 32) && rb <= 64 && h.msig == 38;
+    if (fast) {
+      const size_t N = h.N, H = N / 2 + 1;
+      b += up256(rb * n * 8) + up256(2 * rb * n * 4) + up256(2 * rb * n * 8);  // basis
+      b += up256(rb * h.mrho * h.msig * n * 4);                                // shifts
+      b += up256((size_t)h.mrho * P * n * 4);                                  // products
+      b += up256(P * h.mrho * N * N * H * 8);  // half spectra: at most one group per node
+    } else {
+      b += generic(rb, P);
+    }
+    b += up256(3 * P * sizeof(int));
+  }
+  if (!(flags & BLR_NO_CONSERVE)) {
+    const size_t nb = (n + kMomChunk - 1) / kMomChunk;
+    b += up256((size_t)npairs * nb * 5 * sizeof(double));
+  }
+  return b;
+}
+
 void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
                      const int32_t* pairs, int npairs, void* Q) {
   g_timer = &ctx->timer;

@@ -74,6 +74,7 @@ struct DevTables {
   int* bp_b = nullptr;     // nbp
   int* bp_bb = nullptr;    // nbp
   void* filt = nullptr;    // T2 : nbp x n (Carleman form only)
+  blr_vgrid vg{};          // the grid these tables describe (allocation-free mode)
   std::vector<void*> owned;
   ~DevTables();
 };
@@ -162,6 +163,18 @@ struct blr_ctx_t {
   bool capture_broken = false;  // an operation that cannot be recorded was requested
   blr::KernelTimer timer;
 
+  // Allocation-free mode (blr_collision_pairs_noalloc): while arena_on, buf()
+  // and upload() hand out named 256-byte-aligned slices of the device region
+  // [arena_base, arena_base + arena_cap) instead of allocating, and
+  // get_tables() copies the tables into it (arena_tables).  A name asked for
+  // twice in one call gets the same slice.
+  bool arena_on = false;
+  char* arena_base = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  std::map<std::string, std::pair<void*, size_t>> arena_slices;
+  std::unique_ptr<blr::DevTables> arena_tables;
+  void* arena_slice(const std::string& name, size_t bytes);
+
   void* buf(const std::string& name, size_t bytes);  // grow-only named workspace
   // copy a small host array to a named device buffer, asynchronously
   void* upload(const std::string& name, const void* host, size_t bytes);
@@ -173,12 +186,20 @@ struct blr_ctx_t {
 namespace blr {
 
 const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec);
+// host tables of the allocation-free mode (cached in the context)
+const HostTables& arena_host_tables(blr_ctx ctx, const blr_vgrid& vg, int prec);
 void validate_vgrid(const blr_vgrid& vg);
 
 // collision pipeline (collision.hip)
 void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
                      const int32_t* pairs_dev, int npairs, void* Q);
 size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec);
+// Upper bound of the device bytes collision_pairs takes from buf()/upload()
+// and the tables for this call (each slice rounded up to 256 bytes).
+size_t collision_call_bytes(const HostTables& h, int prec, int r, const int32_t* pairs, int npairs,
+                            uint32_t flags);
+// Bytes of the device tables of one precision (rounded as above).
+size_t table_bytes(const HostTables& h, int prec);
 
 // DLR step and steady solve (dlr.hip)
 void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_params* sp,
