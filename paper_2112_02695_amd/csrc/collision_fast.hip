@@ -9,10 +9,12 @@
 // 132 KiB of LDS: one workgroup per CU, the FFT never leaves the CU.
 //
 // Kernels (same arithmetic as the generic pipeline in collision.hip):
-//   k_shift_fused  one antipodal shift pair S(b), S(bbar) of one basis
-//                  function at one radial node per workgroup iteration:
-//                  spectrum x (cos x - sin x) -> 3D inverse DFT -> two real
-//                  fields written coalesced (the only HBM-heavy output)
+//   k_shift_fused  one antipodal shift pair of one basis function at one
+//                  radial node per workgroup iteration: spectrum x
+//                  (cos x - sin x) -> 3D inverse DFT W; its real and
+//                  imaginary parts (S(b) = Re W - Im W, S(bbar) = Re W + Im W)
+//                  written coalesced with streaming stores (the only
+//                  HBM-heavy output)
 //   k_reduce_diag  sigma sums of all pair products for all radial nodes in
 //   k_reduce_all   one launch (thread per grid point, pairs in registers;
 //                  the diagonal tile with the sphere pairs in the arguments)
@@ -87,6 +89,11 @@ __global__ __launch_bounds__(N * N) void k_shift_fused(const float2* __restrict_
   const int u = t / N, w = t % N;
   // field count < 2^31 (checked by the host): 32-bit index arithmetic
   const int nf = (int)nfields;
+  // One workgroup per CU alternates a compute phase (transforms, LDS) with a
+  // store phase whose drain the next field's loads wait for; odd workgroups
+  // start about 3 us late so that half of the CUs store while the other half
+  // compute, instead of all of them storing at once.
+  if (blockIdx.x & 1) __builtin_amdgcn_s_sleep(127);
   for (int f = blockIdx.x; f < nf; f += gridDim.x) {
     const int p = f % nbp;
     const int a = (f / nbp) % mrho;
@@ -115,14 +122,16 @@ __global__ __launch_bounds__(N * N) void k_shift_fused(const float2* __restrict_
     exchange<N, 1, 0>(re, L, u, w);
     exchange<N, 1, 0>(im, L, u, w);
     fft::dft<float, N, +1>(re, im);
-    // thread (i1, i2) = (u, w) holds the line over i0: coalesced stores
+    // thread (i1, i2) = (u, w) holds the line over i0: coalesced stores of
+    // Re W into slot b and Im W into slot bbar (read once, by the sigma sums:
+    // streaming stores)
     const long base = (((long)ib * mrho + a) * msig) * (long)n + t;
     float* s1 = sh + base + (long)bp_b[p] * n;
     float* s2 = sh + base + (long)bp_bb[p] * n;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      s1[j * N * N] = re[j] - im[j];
-      s2[j * N * N] = re[j] + im[j];
+      __builtin_nontemporal_store(re[j], s1 + j * N * N);
+      __builtin_nontemporal_store(im[j], s2 + j * N * N);
     }
   }
 }
@@ -178,6 +187,9 @@ __global__ __launch_bounds__(N * N) void k_filter_fused(const float2* __restrict
 
 // ------------------------------------------------------------ sigma sums
 // All radial nodes in one launch (blockIdx.y = a); one thread per point.
+// The shift kernel leaves x = Re W in slot b and y = Im W in slot bbar of each
+// antipodal pair, S(b) = x - y and S(bbar) = x + y, so a pair's term
+//   w (S_i(b) S_j(bbar) + S_i(bbar) S_j(b)) = 2 w (x_i x_j - y_i y_j).
 template <int G, bool DIAG>
 __global__ __launch_bounds__(256) void k_reduce_all(const float* __restrict__ sh,
                                                     float* __restrict__ pa, ReduceTile tile,
@@ -194,7 +206,7 @@ __global__ __launch_bounds__(256) void k_reduce_all(const float* __restrict__ sh
   for (int p = 0; p < NP; ++p) acc[p] = 0.f;
   for (int bp = 0; bp < nbp; ++bp) {
     const int b = bp_b[bp], bb = bp_bb[bp];
-    const float wt = wbp[bp];
+    const float wt = 2.f * wbp[bp];
     float xi[G], yi[G], xj[G], yj[G];
 #pragma unroll
     for (int s = 0; s < G; ++s) {
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(256) void k_reduce_all(const float* __restrict__ sh
     for (int s = 0; s < G; ++s) {
 #pragma unroll
       for (int v = DIAG ? s : 0; v < G; ++v) {
-        acc[p] += xi[s] * yj[v] + yi[s] * xj[v];
+        acc[p] += xi[s] * xj[v] - yi[s] * yj[v];
         ++p;
       }
     }
@@ -286,7 +298,7 @@ __global__ __launch_bounds__(256) void k_reduce_diag(const float* __restrict__ s
       const float xs = wt * x[s], ys = wt * y[s];
 #pragma unroll
       for (int v = s; v < G; ++v) {
-        acc[p] += xs * y[v] + ys * x[v];
+        acc[p] += xs * x[v] - ys * y[v];
         ++p;
       }
     }
@@ -622,7 +634,9 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   // shifts: persistent-style grid, each workgroup loops over fields
   {
     require(nfields < (1L << 31), "fast collision: too many shift fields");
-    const long grid = std::min<long>(nfields, 2048);
+    // one persistent workgroup per CU (it holds a whole field: all of a CU's
+    // registers and 132 KiB of LDS)
+    const long grid = std::min<long>(nfields, ctx->cu_count());
     timed_begin("fast.shift", (double)nfields * n * (2 * sizeof(float)), s);
     hipLaunchKernelGGL(k_shift_fused<N>, dim3((unsigned)grid), dim3(N * N), 0, s, Vh,
                        (const float2*)tb.phase, Sh, tb.bp_b, tb.bp_bb, h.mrho, h.nbp, h.msig, nfields);
@@ -642,7 +656,7 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
     for (int p = 0; p < h.nbp && p < kMaxBp; ++p) {
       bpa.off_b[p] = h.bp_b[p] * n;
       bpa.off_bb[p] = h.bp_bb[p] * n;
-      bpa.w[p] = (float)h.wsig[h.bp_b[p]];
+      bpa.w[p] = (float)(2.0 * h.wsig[h.bp_b[p]]);  // see k_reduce_all
     }
     for (const auto& t : tiles) {
       const bool diag = t.bi[0] == t.bj[0];
