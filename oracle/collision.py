@@ -374,3 +374,104 @@ def conserve_project(q: np.ndarray, vs: VelocitySetup) -> np.ndarray:
     C = moment_matrix(vs)
     lam = np.linalg.solve(C @ C.T, C @ q.reshape(-1))
     return q.reshape(-1) - C.T @ lam
+
+
+# ----------------------------------------------------------------------------
+# the de-aliased convolution (reading of the Galerkin sum over l + m = k)
+# ----------------------------------------------------------------------------
+def qhat_direct_exact(gh: np.ndarray, fh: np.ndarray, vs: VelocitySetup, ks=None,
+                      parts: bool = False):
+    """Q^_k = sum_{l in K_N} [G+(l, k - l) - G-(l)] g^_l f^_{k - l} with l + m = k
+    exactly (no wrap: terms whose m = k - l leaves K_N are absent), for modes
+    k of K_N; G+(l, m) = sum_a w_a rho_a^{d-1} F(l + m, rho_a) E_a(l - m).
+    Modes with a component -N/2 of the output are set to 0 (the rule the
+    inputs follow), so the synthesis is real."""
+    N, d = vs.N, vs.d
+    kv = _flat_modes(vs)
+    n = kv.shape[0]
+    if ks is None:
+        ks = np.arange(n)
+    g = gh.reshape(-1)
+    f = fh.reshape(-1)
+    Ft = F_table(vs).reshape(len(vs.rho), -1)
+    E = E_table(vs).reshape(len(vs.rho), -1)
+    Gm = loss_weight(vs).reshape(-1)
+    cw = vs.wrho * vs.rho ** (d - 1)
+    strides = np.array([N ** (d - 1 - i) for i in range(d)])
+    estr = np.array([(2 * N - 1) ** (d - 1 - i) for i in range(d)])
+    out = np.zeros(len(ks), dtype=np.complex128)
+    outp = np.zeros(len(ks), dtype=np.complex128)
+    for t, kidx in enumerate(ks):
+        kc = kv[kidx]
+        if np.any(kc == -N // 2):
+            continue
+        mc = kc[None, :] - kv                                  # k - l, not wrapped
+        inside = np.all((mc >= -N // 2) & (mc < N // 2), axis=1)
+        mcl = mc[inside]
+        midx = ((mcl % N) * strides).sum(axis=1)
+        delta = kv[inside] - mcl
+        eidx = ((delta + N - 1) * estr).sum(axis=1)
+        prod = g[inside] * f[midx]
+        gplus = (cw[:, None] * Ft[:, kidx][:, None] * E[:, eidx]).sum(axis=0)
+        outp[t] = (gplus * prod).sum()
+        out[t] = outp[t] - (Gm[inside] * prod).sum()
+    if parts:
+        return out, outp
+    return out
+
+
+def q_direct_exact(g, f, vs: VelocitySetup, parts: bool = False):
+    gh, fh = coefficients(g, vs), coefficients(f, vs)
+    qh, qhp = qhat_direct_exact(gh, fh, vs, parts=True)
+    shape = (vs.N,) * vs.d
+    q, qp = synthesis(qh.reshape(shape), vs), synthesis(qhp.reshape(shape), vs)
+    if parts:
+        return q.real, qp.real, float(np.abs(q.imag).max())
+    return q.real
+
+
+def padded_setup(vs: VelocitySetup) -> VelocitySetup:
+    """The same box, truncation radius and quadrature with 2N points per axis."""
+    return VelocitySetup(vs.d, 2 * vs.N, vs.L, vs.R, vs.C, vs.gamma, vs.rho, vs.wrho, vs.sig,
+                         vs.wsig)
+
+
+def q_fft_dealiased(g, f, vs: VelocitySetup, parts: bool = False):
+    """The de-aliased operator through the FFT form on the padded grid: the
+    interpolants of g and f at the 2N-point nodes, q_fft there (no sum of two
+    input modes wraps), then the output coefficients of K_N without Nyquist
+    components, synthesised on the N-point grid."""
+    ws = padded_setup(vs)
+    N, d = vs.N, vs.d
+
+    def pad(h):
+        c = coefficients(h, vs)                       # Nyquist modes dropped
+        cf = np.zeros((2 * N,) * d, dtype=np.complex128)
+        k = centred(N)
+        idx = np.ix_(*([k % (2 * N)] * d))
+        cf[idx] = c
+        return synthesis(cf, ws).real
+
+    def restrict(hf):
+        cf = coefficients(hf, ws, zero_nyquist=False)
+        k = centred(N)
+        c = cf[np.ix_(*([k % (2 * N)] * d))]
+        return synthesis(c * nyquist_mask(vs), vs).real
+
+    q, qp = q_fft(pad(g), pad(f), ws, parts=True)
+    if parts:
+        return restrict(q), restrict(qp)
+    return restrict(q)
+
+
+def q_pairs_dealiased(V, pairs, vs: VelocitySetup, conserve: bool = True):
+    out, gains = [], []
+    for (i, j) in pairs:
+        a, ap = q_fft_dealiased(V[i], V[j], vs, parts=True)
+        b, bp = q_fft_dealiased(V[j], V[i], vs, parts=True)
+        q = 0.5 * (a + b).reshape(-1)
+        if conserve:
+            q = conserve_project(q, vs)
+        out.append(q)
+        gains.append(0.5 * (ap + bp).reshape(-1))
+    return np.array(out), np.array(gains)
