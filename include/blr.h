@@ -64,6 +64,16 @@ typedef enum { BLR_FP32 = 0, BLR_FP64 = 1 } blr_precision;
  * of the Lebedev rule, 19).  m_rho is not used.  BLR_ERR_ARG unless
  * gamma = d - 2. */
 #define BLR_CARLEMAN         0x8u
+/* De-aliased convolution: the Galerkin sum over l + m = k exactly instead of
+ * l + m = k mod n (the circular convolution an n-point transform computes).
+ * Evaluated on a grid of 2n points per axis (the band-limited interpolants
+ * of the inputs, n / 2 >= the 3n / 2 - n padding that keeps every sum l + m
+ * of two input modes off the wrap), then the output modes k in the n-point
+ * mode set are kept and every mode with a component -n/2 is dropped (the
+ * rule the inputs follow), so the output is real.  The projection (unless
+ * BLR_NO_CONSERVE) acts on that output.  3D n in {8, 16}, 2D n = 16; other
+ * grids BLR_ERR_UNSUPPORTED. */
+#define BLR_DEALIAS          0x10u
 
 /* Velocity discretisation and collision kernel.
  *   d       velocity dimension, 2 or 3
@@ -75,6 +85,20 @@ typedef enum { BLR_FP32 = 0, BLR_FP64 = 1 } blr_precision;
  *   m_rho   Gauss-Legendre nodes on [0, R] (1..64)
  *   m_sigma sphere nodes: 2D an even count of equispaced angles (2..64);
  *           3D must be 38 (Lebedev rule exact to degree 9); 0 = default 8 / 38
+ *   aniso_n, aniso
+ *           anisotropic kernel B(|q|, cos chi) = C |q|^gamma sum_{i < aniso_n}
+ *           aniso[i] Y_i(cos chi), cos chi = sigma . q^ the cosine of the
+ *           deflection angle, Y_i the Legendre polynomial P_i (3D) or the
+ *           Chebyshev polynomial T_i (2D), 1 <= aniso_n <= 5; aniso_n = 0 is
+ *           the isotropic kernel (aniso ignored).  The angular integral is then
+ *           no longer a closed-form radial factor: every antipodal sphere pair's
+ *           product is transformed and weighted on its own (Funk-Hecke factors
+ *           |S^{d-1}| (-1)^(i/2) Z_i(theta |k|) Y_i(sigma . k^), Z_i the
+ *           spherical Bessel j_i in 3D and J_i in 2D), which costs m_sigma / 2
+ *           times the pair transforms of the isotropic case.  Q_s is symmetric
+ *           under sigma -> -sigma, so only the even i enter it (odd aniso[i]
+ *           are accepted and do not change the result).  The loss carries
+ *           aniso[0].  Not with BLR_CARLEMAN.
  */
 typedef struct {
   int32_t d, n;
@@ -82,6 +106,8 @@ typedef struct {
   double C, gamma;
   int32_t m_rho, m_sigma;
   uint32_t flags;
+  int32_t aniso_n;
+  double aniso[5];
 } blr_vgrid;
 
 blr_status blr_create(int device, void* hip_stream, blr_ctx* out);
@@ -129,6 +155,7 @@ blr_status blr_collision_pairs(blr_ctx ctx, const blr_vgrid* vg, blr_precision p
  * stream (such copies may wait for earlier work on that stream).
  *   BLR_ERR_ARG when the call's workspace (shifted fields, products, spectra,
  *   tables) would exceed BLR_NOALLOC_SCRATCH_BYTES; nothing is issued then.
+ *   BLR_DEALIAS (a second grid and its tables) is BLR_ERR_UNSUPPORTED here.
  * All calls on one device share that array: calls that overlap on a device
  * (other contexts or streams included) race; serialise them.  Nothing left
  * in the array by an earlier call is relied on. */

@@ -23,6 +23,7 @@ BLR_NO_CONSERVE = 0x1
 BLR_PLAIN_SCHEDULE = 0x2
 BLR_GENERIC_FFT = 0x4
 BLR_CARLEMAN = 0x8
+BLR_DEALIAS = 0x10
 BLR_STEP_ADD = 0x1
 BLR_STEP_DROP = 0x2
 BLR_STEP_FP64_COLLISION = 0x4
@@ -50,7 +51,8 @@ class BlrError(RuntimeError):
 class VGrid(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("n", ctypes.c_int32), ("L", ctypes.c_double),
                 ("R", ctypes.c_double), ("C", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("m_rho", ctypes.c_int32), ("m_sigma", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("m_rho", ctypes.c_int32), ("m_sigma", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("aniso_n", ctypes.c_int32), ("aniso", ctypes.c_double * 5)]
 
 
 class Problem(ctypes.Structure):
@@ -159,13 +161,20 @@ def load_library(path: str = LIB_PATH):
 
 
 def make_vgrid(d: int, n: int, L: float, C: float = 1.0, gamma: float = 0.0, m_rho: int = 16,
-               m_sigma: int = 0, R: float = 0.0, flags: int = 0) -> VGrid:
-    return VGrid(d, n, float(L), float(R), float(C), float(gamma), m_rho, m_sigma, flags)
+               m_sigma: int = 0, R: float = 0.0, flags: int = 0, aniso=None) -> VGrid:
+    """aniso: the coefficients of the kernel's angular factor (Legendre in 3D,
+    Chebyshev in 2D), at most 5; None for the isotropic kernel."""
+    co = [float(x) for x in (aniso or ())]
+    if len(co) > 5:
+        raise ValueError("at most 5 angular coefficients")
+    arr = (ctypes.c_double * 5)(*(co + [0.0] * (5 - len(co))))
+    return VGrid(d, n, float(L), float(R), float(C), float(gamma), m_rho, m_sigma, flags,
+                 len(co), arr)
 
 
-def vgrid_from_spec(spec, flags: int = 0) -> VGrid:
+def vgrid_from_spec(spec, flags: int = 0, aniso=None) -> VGrid:
     return make_vgrid(spec.d, spec.n, spec.L, spec.C, spec.gamma, spec.m_rho, spec.m_sigma,
-                      flags=flags)
+                      flags=flags, aniso=aniso)
 
 
 class Context:

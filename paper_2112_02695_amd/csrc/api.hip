@@ -221,7 +221,8 @@ const HostTables& arena_host_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) 
   const blr_vgrid& o = t ? t->vg : vg;
   const bool same = t && t->prec == prec && o.d == vg.d && o.n == vg.n && o.L == vg.L &&
                     o.R == vg.R && o.C == vg.C && o.gamma == vg.gamma && o.m_rho == vg.m_rho &&
-                    o.m_sigma == vg.m_sigma &&
+                    o.m_sigma == vg.m_sigma && o.aniso_n == vg.aniso_n &&
+                    std::memcmp(o.aniso, vg.aniso, sizeof(double) * 5) == 0 &&
                     (o.flags & BLR_CARLEMAN) == (vg.flags & BLR_CARLEMAN);
   if (!same) {
     t = std::make_unique<DevTables>();
@@ -254,6 +255,7 @@ static const DevTables& arena_tables(blr_ctx ctx, const blr_vgrid& vg, int prec)
   t->gloss = putv("gloss", h.gloss);
   t->wbp = putv("wbp", wbp);
   t->filt = h.carleman ? putv("filt", h.filt) : nullptr;
+  t->atab = h.aniso_n > 0 ? putv("atab", h.atab) : nullptr;
   t->bp_b = (int*)put("bp_b", h.bp_b.data(), h.bp_b.size() * sizeof(int));
   t->bp_bb = (int*)put("bp_bb", h.bp_bb.data(), h.bp_bb.size() * sizeof(int));
   return *t;
@@ -264,7 +266,15 @@ const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
   if (ctx->arena_on) return arena_tables(ctx, vg, prec);
   const int ms = vg.m_sigma ? vg.m_sigma : (vg.d == 2 ? 8 : 38);
   const int form = (vg.flags & BLR_CARLEMAN) ? 1 : 0;
-  auto key = std::make_tuple(vg.d, vg.n, vg.L, vg.R, vg.C, vg.gamma, vg.m_rho, ms, prec, form);
+  // every field the tables depend on, doubles by their bit patterns
+  std::string key;
+  auto put = [&key](const void* p, size_t b) { key.append((const char*)p, b); };
+  const int ints[6] = {vg.d, vg.n, vg.m_rho, ms, prec, form};
+  const double dbl[4] = {vg.L, vg.R, vg.C, vg.gamma};
+  put(ints, sizeof(ints));
+  put(dbl, sizeof(dbl));
+  put(&vg.aniso_n, sizeof(vg.aniso_n));
+  put(vg.aniso, sizeof(double) * (vg.aniso_n > 0 ? vg.aniso_n : 0));
   auto it = ctx->tables.find(key);
   if (it != ctx->tables.end()) return *it->second;
   auto t = std::make_unique<DevTables>();
@@ -287,6 +297,10 @@ const DevTables& get_tables(blr_ctx ctx, const blr_vgrid& vg, int prec) {
   if (h.carleman) {
     if (prec == BLR_FP32) t->filt = upload_vec(*t, cast_vec<float>(h.filt), ctx->stream);
     else t->filt = upload_vec(*t, h.filt, ctx->stream);
+  }
+  if (h.aniso_n > 0) {
+    if (prec == BLR_FP32) t->atab = upload_vec(*t, cast_vec<float>(h.atab), ctx->stream);
+    else t->atab = upload_vec(*t, h.atab, ctx->stream);
   }
   t->bp_b = (int*)upload_vec(*t, h.bp_b, ctx->stream);
   t->bp_bb = (int*)upload_vec(*t, h.bp_bb, ctx->stream);
@@ -432,6 +446,8 @@ blr_status blr_collision_pairs_noalloc(blr_ctx ctx, const blr_vgrid* vg, blr_pre
     blr::require(npairs == 0 || (pairs && V && Q_out), "null pointer argument");
     if (npairs == 0) return;
     blr::validate_vgrid(*vg);
+    blr::require(!(vg->flags & BLR_DEALIAS), "allocation-free call: BLR_DEALIAS is not available",
+                 BLR_ERR_UNSUPPORTED);
     void* base = scratch_address(ctx->device);
     // the whole call's workspace must fit before anything is issued
     const blr::HostTables& h = blr::arena_host_tables(ctx, *vg, prec);

@@ -302,6 +302,29 @@ struct StAccumF {
   }
 };
 
+// accumulate tab(k) * value into the couple spectrum (anisotropic kernel:
+// the weight depends on the direction of k, one table per radial node and
+// antipodal pair)
+template <typename T>
+struct StAccumTab {
+  static constexpr int bpe = 5;  // algorithmic bytes per element / sizeof(T)
+  typename Vec2<T>::t* G;
+  const T* tab;  // n weights of this (radial node, pair)
+  int n;
+  template <int N>
+  __device__ void store(long c, int base, int stride, const T (&re)[N], const T (&im)[N]) const {
+    auto* g = G + c * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const T w = tab[base + j * stride];
+      auto v = g[(long)j * stride];
+      v.x += w * re[j];
+      v.y += w * im[j];
+      g[(long)j * stride] = v;
+    }
+  }
+};
+
 // Q = gain - loss for pair p
 template <typename T>
 struct StFinal {
@@ -799,7 +822,42 @@ struct Generic {
     const int Gt = sizeof(T) == 4 ? 12 : 8;
     auto tiles = plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
     g_stage = "gen.pairfft";
-    for (int a = 0; a < h.mrho; ++a) {
+    if (h.aniso_n > 0) {
+      // anisotropic kernel: each antipodal pair's product is transformed and
+      // weighted by its own table (the sigma sum happens in Fourier space)
+      const T* atab = (const T*)tb.atab;
+      for (int a = 0; a < h.mrho; ++a)
+        for (int bp = 0; bp < h.nbp; ++bp) {
+          for (const auto& t : tiles) {
+            const bool diag = t.bi[0] == t.bj[0];
+            const dim3 grid((n + 255) / 256);
+            int nvalid = 0;
+            for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
+            const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
+            TimedScope ts(s, "gen.sigma_pair", (double)n * (nload + nvalid) * sizeof(T));
+            const T* w1 = (const T*)tb.wbp + bp;
+            if (sizeof(T) == 4) {
+              if (diag)
+                hipLaunchKernelGGL((k_sigma_reduce<T, 12, true>), grid, dim3(256), 0, s, Sh, Pa, t,
+                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a);
+              else
+                hipLaunchKernelGGL((k_sigma_reduce<T, 12, false>), grid, dim3(256), 0, s, Sh, Pa,
+                                   t, w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a);
+            } else {
+              if (diag)
+                hipLaunchKernelGGL((k_sigma_reduce<T, 8, true>), grid, dim3(256), 0, s, Sh, Pa, t,
+                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a);
+              else
+                hipLaunchKernelGGL((k_sigma_reduce<T, 8, false>), grid, dim3(256), 0, s, Sh, Pa, t,
+                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a);
+            }
+            BLR_CHECK_LAUNCH();
+          }
+          transform<T, N, D, -1>(s, LdPair1<T>{Pa, n},
+                                 StAccumTab<T>{G, atab + ((size_t)a * h.nbp + bp) * n, n}, tmp, nc);
+        }
+    }
+    for (int a = 0; a < h.mrho && h.aniso_n == 0; ++a) {
       for (const auto& t : tiles) {
         const bool diag = t.bi[0] == t.bj[0];
         const int bs = 256;
@@ -855,6 +913,139 @@ static void dispatch_size(int d, int N, F&& f) {
 }
 
 
+// ------------------------------------------------------------ de-aliasing
+// Coarse plain-DFT spectra (N per axis) -> fine spectra (2N per axis): the
+// modes k with every component in [-N/2 + 1, N/2 - 1] (the Nyquist planes of
+// the coarse grid are dropped) keep their value times `scale`, the rest are 0.
+template <typename T, int N, int D>
+__global__ void k_pad_spec(const typename Vec2<T>::t* __restrict__ cs, typename Vec2<T>::t* __restrict__ fs,
+                           int rows, T scale) {
+  constexpr int NF = 2 * N;
+  constexpr long nf = D == 2 ? (long)NF * NF : (long)NF * NF * NF;
+  constexpr long nc = D == 2 ? (long)N * N : (long)N * N * N;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int row = blockIdx.y;
+  if (e >= nf || row >= rows) return;
+  long rem = e, src = 0, mul = 1;
+  bool in = true;
+  for (int ax = D - 1; ax >= 0; --ax) {
+    const int i = (int)(rem % NF);
+    rem /= NF;
+    const int k = i < N ? i : i - NF;  // centred fine mode
+    if (k <= -N / 2 || k >= N / 2) in = false;
+    src += (long)((k + N) % N) * mul;
+    mul *= N;
+  }
+  typename Vec2<T>::t v = make2<T>(T(0), T(0));
+  if (in) {
+    v = cs[(long)row * nc + src];
+    v.x *= scale;
+    v.y *= scale;
+  }
+  fs[(long)row * nf + e] = v;
+}
+
+// Fine plain-DFT spectra -> coarse: the coarse modes without a Nyquist
+// component take the fine value at the same centred mode times `scale`.
+template <typename T, int N, int D>
+__global__ void k_restrict_spec(const typename Vec2<T>::t* __restrict__ fs,
+                                typename Vec2<T>::t* __restrict__ cs, int rows, T scale) {
+  constexpr int NF = 2 * N;
+  constexpr long nf = D == 2 ? (long)NF * NF : (long)NF * NF * NF;
+  constexpr long nc = D == 2 ? (long)N * N : (long)N * N * N;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int row = blockIdx.y;
+  if (e >= nc || row >= rows) return;
+  long rem = e, src = 0, mul = 1;
+  bool nyq = false;
+  for (int ax = D - 1; ax >= 0; --ax) {
+    const int i = (int)(rem % N);
+    rem /= N;
+    const int k = i < N / 2 ? i : i - N;
+    if (k == -N / 2) nyq = true;
+    src += (long)((k + NF) % NF) * mul;
+    mul *= NF;
+  }
+  typename Vec2<T>::t v = make2<T>(T(0), T(0));
+  if (!nyq) {
+    v = fs[(long)row * nf + src];
+    v.x *= scale;
+    v.y *= scale;
+  }
+  cs[(long)row * nc + e] = v;
+}
+
+template <typename T>
+__global__ void k_scatter_rows(const T* __restrict__ src, const int* __restrict__ prow, long n,
+                               T* __restrict__ dst) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (e < n) dst[(long)prow[p] * n + e] = src[(long)p * n + e];
+}
+
+template <typename T>
+static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const int32_t* pairs,
+                      int npairs, T* Q, uint32_t flags);
+
+// BLR_DEALIAS: the band-limited interpolants of the basis functions on the
+// grid of 2N points per axis (same box, same quadrature), the pair operator
+// there without the projection (sums of two input modes never wrap on that
+// grid, so its circular convolution is the exact Galerkin sum), then the
+// output modes of the N-point mode set without Nyquist components.
+template <typename T, int N, int D>
+static void run_dealias(blr_ctx ctx, const blr_vgrid& vg, int prec, const DevTables& tb, const T* V,
+                        int r, const int32_t* pairs, int npairs, T* Q, uint32_t flags) {
+  using T2 = typename Vec2<T>::t;
+  constexpr int NF = 2 * N;
+  constexpr long n = D == 2 ? (long)N * N : (long)N * N * N;
+  constexpr long nf = D == 2 ? (long)NF * NF : (long)NF * NF * NF;
+  hipStream_t s = ctx->stream;
+  const PairPlan pl = make_plan(r, pairs, npairs);
+  const int rb = (int)pl.bidx.size(), P = (int)pl.li.size();
+  const std::string tag = std::string("dea") + (sizeof(T) == 4 ? "f" : "d");
+  T2* cs = (T2*)ctx->buf(tag + ".cs", (size_t)std::max(rb, P) * n * sizeof(T2));
+  T2* tc = (T2*)ctx->buf(tag + ".tc", (size_t)std::max(rb, P) * n * sizeof(T2));
+  T2* fs = (T2*)ctx->buf(tag + ".fs", (size_t)std::max(rb, P) * nf * sizeof(T2));
+  T2* tf = (T2*)ctx->buf(tag + ".tf", (size_t)std::max(rb, P) * nf * sizeof(T2));
+  T* Vf = (T*)ctx->buf(tag + ".Vf", (size_t)rb * nf * sizeof(T));
+  T* Qf = (T*)ctx->buf(tag + ".Qf", (size_t)P * nf * sizeof(T));
+  T* Qc = (T*)ctx->buf(tag + ".Qc", (size_t)P * n * sizeof(T));
+  Idx64 idx{};
+  for (int ib = 0; ib < rb; ++ib) idx.v[ib] = pl.bidx[ib];
+  g_stage = "dealias.pad";
+  transform<T, N, D, -1>(s, LdRealIdx<T>{V, (int)n, idx}, StComplex<T>{cs, (int)n}, tc, rb);
+  hipLaunchKernelGGL((k_pad_spec<T, N, D>), dim3((unsigned)((nf + 255) / 256), rb), dim3(256), 0, s,
+                     cs, fs, rb, T(1) / T(n));
+  BLR_CHECK_LAUNCH();
+  transform<T, NF, D, +1>(s, LdComplex<T>{fs, (int)nf}, StRe<T>{Vf, (int)nf}, tf, rb);
+  // the pair operator on the fine grid, compact pairs, no projection
+  blr_vgrid fg = vg;
+  fg.n = NF;
+  fg.R = tb.h.R;
+  fg.flags = (vg.flags & ~(uint32_t)BLR_DEALIAS) | BLR_NO_CONSERVE;
+  std::vector<int32_t> cp(2 * (size_t)P);
+  for (int p = 0; p < P; ++p) {
+    cp[2 * p] = pl.li[p];
+    cp[2 * p + 1] = pl.lj[p];
+  }
+  const DevTables& tbf = get_tables(ctx, fg, prec);
+  run_pairs<T>(ctx, tbf, Vf, rb, cp.data(), P, Qf, fg.flags);
+  g_stage = "dealias.restrict";
+  transform<T, NF, D, -1>(s, LdReal<T>{Qf, (int)nf}, StComplex<T>{fs, (int)nf}, tf, P);
+  hipLaunchKernelGGL((k_restrict_spec<T, N, D>), dim3((unsigned)((n + 255) / 256), P), dim3(256), 0,
+                     s, fs, cs, P, T(1) / T(nf));
+  BLR_CHECK_LAUNCH();
+  transform<T, N, D, +1>(s, LdComplex<T>{cs, (int)n}, StRe<T>{Qc, (int)n}, tc, P);
+  int* drow = (int*)ctx->upload(tag + ".row", pl.row.data(), pl.row.size() * sizeof(int));
+  hipLaunchKernelGGL((k_scatter_rows<T>), dim3((unsigned)((n + 255) / 256), P), dim3(256), 0, s, Qc,
+                     drow, n, Q);
+  BLR_CHECK_LAUNCH();
+  for (const auto& dp : pl.dup)
+    BLR_HIP(hipMemcpyAsync(Q + (size_t)dp.first * n, Q + (size_t)dp.second * n, (size_t)n * sizeof(T),
+                           hipMemcpyDeviceToDevice, s));
+  if (!(flags & BLR_NO_CONSERVE)) conserve_rows<T>(ctx, tb.h, Q, npairs);
+}
+
 template <typename T>
 static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const int32_t* pairs,
                       int npairs, T* Q, uint32_t flags) {
@@ -876,7 +1067,7 @@ static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const
     const std::vector<int>& prow = pl.row;
     bool done = false;
     if constexpr (sizeof(T) == 4) {
-      if (!(flags & BLR_GENERIC_FFT) && !h.carleman)
+      if (!(flags & BLR_GENERIC_FFT) && !h.carleman && h.aniso_n == 0)
         done = fast_collision_f32(ctx, tb, V, pl, prow, Q, !(flags & BLR_NO_CONSERVE));
     }
     if (!done) {
@@ -905,6 +1096,7 @@ size_t table_bytes(const HostTables& h, int prec) {
   size_t b = up256(h.phase.size() * T) + up256(h.fw.size() * T) + up256(h.gloss.size() * T) +
              up256((size_t)h.nbp * T) + 2 * up256((size_t)h.nbp * sizeof(int));
   if (h.carleman) b += up256(h.filt.size() * T);
+  if (h.aniso_n > 0) b += up256(h.atab.size() * T);
   return b;
 }
 
@@ -933,7 +1125,8 @@ size_t collision_call_bytes(const HostTables& h, int prec, int r, const int32_t*
   } else {
     PairPlan pl = make_plan(r, pairs, npairs);
     const size_t rb = pl.bidx.size(), P = pl.li.size();
-    const bool fast = prec == BLR_FP32 && !(flags & BLR_GENERIC_FFT) && !h.carleman && h.d == 3 &&
+    const bool fast = prec == BLR_FP32 && !(flags & BLR_GENERIC_FFT) && !h.carleman &&
+                      h.aniso_n == 0 && h.d == 3 &&
                       (h.N == 16 || h.N == 24 || h.N == 32) && rb <= 64 && h.msig == 38;
     if (fast) {
       const size_t N = h.N, H = N / 2 + 1;
@@ -960,6 +1153,22 @@ void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, 
   require(npairs >= 0 && npairs <= 4096, "npairs must be in [0, 4096]");
   require(npairs == 0 || (pairs && V && Q), "null pointer argument");
   const DevTables& tb = get_tables(ctx, vg, prec);
+  if ((vg.flags & BLR_DEALIAS) && npairs > 0) {
+    auto go = [&](auto Tc) {
+      using T = decltype(Tc);
+      if (vg.d == 3 && vg.n == 8)
+        run_dealias<T, 8, 3>(ctx, vg, prec, tb, (const T*)V, r, pairs, npairs, (T*)Q, vg.flags);
+      else if (vg.d == 3 && vg.n == 16)
+        run_dealias<T, 16, 3>(ctx, vg, prec, tb, (const T*)V, r, pairs, npairs, (T*)Q, vg.flags);
+      else if (vg.d == 2 && vg.n == 16)
+        run_dealias<T, 16, 2>(ctx, vg, prec, tb, (const T*)V, r, pairs, npairs, (T*)Q, vg.flags);
+      else
+        throw Error(BLR_ERR_UNSUPPORTED, "BLR_DEALIAS: grid not built");
+    };
+    if (prec == BLR_FP32) go(float{});
+    else go(double{});
+    return;
+  }
   if (prec == BLR_FP32)
     run_pairs<float>(ctx, tb, (const float*)V, r, pairs, npairs, (float*)Q, vg.flags);
   else

@@ -57,6 +57,13 @@ struct HostTables {
   // Re W + Im W; gloss holds beta(l, l); phase and fw are unused.
   bool carleman = false;
   std::vector<double> filt;                   // nbp x n x 2
+  // anisotropic kernel (aniso_n > 0): per radial node a and antipodal pair p
+  // the spectral weight cw_a (F_ab + F_abbar)(k) / (2 n) of the pair's product
+  // (real: only even angular components survive the symmetrisation); gloss
+  // carries aniso[0]; fw is unused.
+  int aniso_n = 0;
+  double aniso[5] = {0, 0, 0, 0, 0};
+  std::vector<double> atab;                   // mrho x nbp x n
 };
 
 HostTables build_tables(const blr_vgrid& vg);
@@ -74,6 +81,7 @@ struct DevTables {
   int* bp_b = nullptr;     // nbp
   int* bp_bb = nullptr;    // nbp
   void* filt = nullptr;    // T2 : nbp x n (Carleman form only)
+  void* atab = nullptr;    // T  : mrho x nbp x n (anisotropic kernel only)
   blr_vgrid vg{};          // the grid these tables describe (allocation-free mode)
   std::vector<void*> owned;
   ~DevTables();
@@ -115,9 +123,7 @@ struct blr_ctx_t {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  std::map<std::tuple<int, int, double, double, double, double, int, int, int, int>,
-           std::unique_ptr<blr::DevTables>>
-      tables;
+  std::map<std::string, std::unique_ptr<blr::DevTables>> tables;  // by grid, kernel and precision
   std::map<std::string, blr::Buffer> bufs;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   uint64_t calls = 0;

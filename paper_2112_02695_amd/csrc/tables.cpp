@@ -71,6 +71,43 @@ static double bessel_j1(double z) {
   return s / M;
 }
 
+// J_n(z) = (1/2pi) int_0^2pi cos(n t - z sin t) dt (trapezoid rule, as above).
+static double bessel_jn(int n, double z) {
+  const int M = 64 + 2 * (int)std::ceil(std::fabs(z)) + 2 * n;
+  double s = 0.0;
+  for (int j = 0; j < M; ++j) {
+    const double t = 2.0 * kPi * j / M;
+    s += std::cos(n * t - z * std::sin(t));
+  }
+  return s / M;
+}
+
+static double legendre_p(int n, double x) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) return 1.0;
+  for (int k = 2; k <= n; ++k) {
+    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// Spherical Bessel j_n(z) for even n: ((-1)^(n/2) / 2) int_-1^1 cos(z t) P_n(t) dt,
+// by Gauss-Legendre quadrature with more nodes than z (the integrand is
+// entire; the rule's error falls faster than geometrically past that).
+static double sph_bessel_even(int n, double z) {
+  const int M = 48 + (int)std::ceil(std::fabs(z)) + n;
+  std::vector<double> x, w;
+  gauss_legendre(M, 2.0, x, w);  // nodes on [0, 2] -> t = x - 1
+  double s = 0.0;
+  for (int i = 0; i < M; ++i) {
+    const double t = x[i] - 1.0;
+    s += w[i] * std::cos(z * t) * legendre_p(n, t);
+  }
+  return ((n / 2) % 2 ? -0.5 : 0.5) * s;
+}
+
 static void sphere_rule(int d, int msig, std::vector<double>& sig, std::vector<double>& w) {
   sig.clear();
   w.clear();
@@ -138,6 +175,15 @@ void validate_vgrid(const blr_vgrid& vg) {
   if (vg.flags & BLR_CARLEMAN)
     require(std::fabs(vg.gamma - (vg.d - 2)) < 1e-12,
             "the Carleman form needs gamma = d - 2 (2D Maxwell molecules, 3D hard spheres)");
+  require(vg.aniso_n >= 0 && vg.aniso_n <= 5, "vgrid.aniso_n must be in [0, 5]");
+  if (vg.aniso_n > 0) {
+    require(!(vg.flags & BLR_CARLEMAN), "an anisotropic kernel is not available in the Carleman form");
+    for (int i = 0; i < vg.aniso_n; ++i) require(std::isfinite(vg.aniso[i]), "vgrid.aniso must be finite");
+  }
+  if (vg.flags & BLR_DEALIAS)
+    require((vg.d == 3 && (vg.n == 8 || vg.n == 16)) || (vg.d == 2 && vg.n == 16),
+            "BLR_DEALIAS needs 3D n in {8, 16} or 2D n = 16 (the padded grid has 2n points)",
+            BLR_ERR_UNSUPPORTED);
 }
 
 // (C C^T)^-1 for the moment projection; C rows dv^d {1, v_1..v_d, |v|^2}
@@ -393,6 +439,52 @@ HostTables build_tables(const blr_vgrid& vg) {
       g += t.cw[a] * B * s;
     }
     t.gloss[q] = area * g;
+  }
+  if (vg.aniso_n > 0) {
+    // B(rho, c) = C rho^gamma sum_i aniso[i] Y_i(c): the loss keeps aniso[0];
+    // the gain weight of antipodal pair p = (b, bbar) at radial node a is the
+    // even part of the Funk-Hecke transform of the angular factor,
+    // (F_ab + F_abbar)(k) / 2 = C rho^gamma |S| sum_{i even} aniso[i]
+    // (-1)^(i/2) Z_i(theta |k|) Y_i(sigma_b . k^), times cw_a / n.
+    t.aniso_n = vg.aniso_n;
+    for (int i = 0; i < 5; ++i) t.aniso[i] = i < vg.aniso_n ? vg.aniso[i] : 0.0;
+    for (double& g : t.gloss) g *= t.aniso[0];
+    // radial factors Z_i(theta_a |k|) by (a, |k|^2)
+    std::vector<double> zt((size_t)t.mrho * t.nkk * 5, 0.0);
+    for (int a = 0; a < t.mrho; ++a) {
+      const double th = kPi * t.rho[a] / (2.0 * t.L);
+      for (int k2 = 0; k2 < t.nkk; ++k2) {
+        const double z = th * std::sqrt((double)k2);
+        for (int i = 0; i < t.aniso_n; i += 2)
+          zt[((size_t)a * t.nkk + k2) * 5 + i] = d == 3 ? sph_bessel_even(i, z) : bessel_jn(i, z);
+      }
+    }
+    t.atab.assign((size_t)t.mrho * t.nbp * t.n, 0.0);
+    for (int q = 0; q < t.n; ++q) {
+      double kc[3] = {0, 0, 0};
+      int rem = q;
+      for (int ax = d - 1; ax >= 0; --ax) {
+        kc[ax] = centred(rem % N);
+        rem /= N;
+      }
+      const int k2 = (int)std::lround(kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]);
+      const double kk = std::sqrt((double)k2);
+      for (int a = 0; a < t.mrho; ++a) {
+        const double* zi = &zt[((size_t)a * t.nkk + k2) * 5];
+        const double pref = t.cw[a] * t.C * std::pow(t.rho[a], t.gamma) * area / t.n;
+        for (int p = 0; p < t.nbp; ++p) {
+          const int b = t.bp_b[p];
+          const double c = kk > 0 ? (t.sig[3 * b] * kc[0] + t.sig[3 * b + 1] * kc[1] +
+                                     t.sig[3 * b + 2] * kc[2]) / kk : 1.0;
+          double s = 0.0;
+          for (int i = 0; i < t.aniso_n; i += 2) {
+            const double y = d == 3 ? legendre_p(i, c) : std::cos(i * std::acos(std::max(-1.0, std::min(1.0, c))));
+            s += t.aniso[i] * ((i / 2) % 2 ? -1.0 : 1.0) * zi[i] * y;
+          }
+          t.atab[((size_t)a * t.nbp + p) * t.n + q] = pref * s;
+        }
+      }
+    }
   }
   t.minv = moment_inverse(t);
   return t;
