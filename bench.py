@@ -67,6 +67,11 @@ def parse():
                          "[-13.11, 13.11]^2, N_x = 1000) to steady state by the low-rank and the "
                          "full-tensor method (about two minutes)")
     ap.add_argument("--paper-tol", type=float, default=1e-6)
+    ap.add_argument("--paper-shock-mach", type=float, default=1.4,
+                    help="Mach number of --paper-shock: 1.4 (L_v = 13.11) or 3.8 (L_v = 20.97), "
+                         "the paper's 32^2 shapes")
+    ap.add_argument("--paper-shock-lv", type=float, default=13.11,
+                    help="velocity half width for another Mach number")
     ap.add_argument("--paper-fourier", action="store_true",
                     help="also solve the paper's Fourier flow (diffusive walls at T = 1 and 1.2, "
                          "N_x = 200, 2D velocity 32^2) to err <= --fourier-tol by the low-rank "
@@ -93,6 +98,11 @@ def parse():
                     help="requests of the longer trace (batched path only; 0 skips it)")
     ap.add_argument("--serve-long-steps", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-conv-count", type=int, default=8,
+                    help="requests of the trace run to err_ada <= 1e-6 (2D velocity; 0 skips it)")
+    ap.add_argument("--serve-conv-plain", type=int, default=1,
+                    help="how many of them the plain FP64 FIFO serves")
+    ap.add_argument("--serve-conv-cap", type=int, default=40000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -126,11 +136,16 @@ def prepare_trace(trace, synth):
     its initial rank."""
     out = []
     for q in trace:
-        spec = synth.VGridSpec(d=3, n=q["n"], L=q["L"], gamma=1.0, C=1.0, m_rho=16, m_sigma=38)
+        d = q.get("d", 3)
+        if d == 3:
+            spec = synth.VGridSpec(d=3, n=q["n"], L=q["L"], gamma=1.0, C=1.0, m_rho=16, m_sigma=38)
+        else:
+            spec = synth.VGridSpec(d=2, n=q["n"], L=q["L"], gamma=0.0, C=1.0 / (2.0 * math.pi),
+                                   m_rho=8, m_sigma=8)
         ini = synth.shock_initial(q["mach"], spec, q["nx"], q["x_lo"], q["x_hi"], pert=1e-3,
-                                  pert_rank=10, seed=100 + q["index"])
+                                  pert_rank=10 if d == 3 else 3, seed=100 + q["index"])
         dx = (q["x_hi"] - q["x_lo"]) / q["nx"]
-        dvd = (2.0 * q["L"] / q["n"]) ** 3
+        dvd = (2.0 * q["L"] / q["n"]) ** d
         X, S, V = synth.lowrank_state_sketch(ini["f0"], q["r0"], dx, dvd, seed=q["index"])
         out.append(dict(q=q, spec=spec, X=X, S=S, V=V, fL=ini["fL"], fR=ini["fR"]))
     return out
@@ -292,7 +307,9 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
     the two steady states are compared, and the density with the Mott-Smith
     logistic profile of Sec. 4 (alpha from the same pair operator)."""
     import numpy as np
-    mach, nx, N, L = 1.4, 1000, 32, 13.11
+    # the paper's box half widths: 13.11 (Mach 1.4), 20.97 (Mach 3.8) at 32^2
+    mach, nx, N = args.paper_shock_mach, 1000, 32
+    L = {1.4: 13.11, 3.8: 20.97}.get(round(mach, 2), args.paper_shock_lv)
     dev = torch.device("cuda:0")
     spec = synth.VGridSpec(d=2, n=N, L=L, gamma=0.0, C=1 / (2 * math.pi), m_rho=1, m_sigma=8)
     ini = synth.shock_initial(mach, spec, nx, -30.0, 30.0, pert=0.0, pert_rank=0)
@@ -326,9 +343,18 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
     sp = blr.SolveParams(blr.StepParams(dt, 0.2, 1e-10, 1, 30,
                                         blr.BLR_STEP_ADD | blr.BLR_STEP_DROP), args.paper_tol,
                          400000)
-    progress(f"paper shock: low-rank solve to {args.paper_tol}")
+    progress(f"paper shock (Mach {mach}): low-rank solve to {args.paper_tol}")
     t0 = time.perf_counter()
-    li = ctx.steady_solve(pb, st, sp, allow_unconverged=True)
+    # in pieces of 20000 steps (a progress line per piece), up to 400000 steps
+    sp.max_steps = 20000
+    steps_lr = 0
+    while True:
+        li = ctx.steady_solve(pb, st, sp, allow_unconverged=True)
+        steps_lr += li.steps
+        progress(f"  low rank: {steps_lr} steps, err_ada {li.err_ada:.3e}, rank {li.r}")
+        if li.converged or steps_lr >= 400000:
+            break
+    li.steps = steps_lr
     t_lr = time.perf_counter() - t0
     r = st.r
     F_lr = (Xd[:r].cpu().numpy().T @ Sd[:r, :r].cpu().numpy()) @ Vd[:r].cpu().numpy()
@@ -337,9 +363,13 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
     F = torch.tensor(ini["f0"], device=dev)
     t0 = time.perf_counter()
     steps_full, e = 0, float("inf")
-    while e > args.paper_tol and steps_full < 400000 and time.perf_counter() - t0 < 600:
+    t_prog = t0
+    while e > args.paper_tol and steps_full < 400000 and time.perf_counter() - t0 < 900:
         e = ctx.full_step(pb, F, dt, blr.BLR_FP32)
         steps_full += 1
+        if time.perf_counter() - t_prog > 30:
+            t_prog = time.perf_counter()
+            progress(f"  full tensor: {steps_full} steps, err_full {e:.3e}")
     t_full = time.perf_counter() - t0
     F_full = F.cpu().numpy()
     m_lr, m_full = macro(F_lr), macro(F_full)
@@ -362,8 +392,8 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
     rho_ms = a * rl + (1 - a) * rr
     # thickness: max density slope of each profile, over the jump
     thick = lambda rr_: (rr - rl) / np.max(np.gradient(rr_, x))
-    return {"shape": "Mach 1.4, d=2 Maxwell molecules (Carleman form, 8 directions), N_v=32^2 "
-                     "on [-13.11,13.11]^2, N_x=1000 on [-30,30], dt=dx/(2 L_v), tanh initial "
+    return {"shape": f"Mach {mach}, d=2 Maxwell molecules (Carleman form, 8 directions), "
+                     f"N_v=32^2 on [-{L},{L}]^2, N_x=1000 on [-30,30], dt=dx/(2 L_v), tanh initial "
                      "profile, FP32 collisions",
             "tol": args.paper_tol,
             "low_rank": {"steps": int(li.steps), "converged": int(li.converged),
@@ -596,6 +626,26 @@ def serving_leg(args, blr, synth, torch, helper):
            "batched_fp32": batched, "plain_fp64_fifo": plain,
            "plain_over_batched_latency_p50": round(plain["latency_s_p50"] /
                                                    batched["latency_s_p50"], 1)}
+    if args.serve_conv_count > 0:
+        ct = synth.serving_trace_2d(count=args.serve_conv_count, seed=6, rate=4.0)
+        cp = prepare_trace(ct, synth)
+        nplain = min(args.serve_conv_plain, len(cp))
+        out["converged_trace"] = (
+            f"{len(cp)} steady normal-shock solves of the paper's own class (2D velocity 32^2 on "
+            "[-8,8]^2, Maxwell molecules B=1/(2 pi), M_rho=8 x M_sigma=8), seed 6, Poisson arrivals "
+            "4/s, Mach~U[1.2,2], N_x in {32,64} on [-30,30], initial rank U{4..8}, dt=0.4 dx/L_v, "
+            f"each run to err_ada<=1e-6 (cap {args.serve_conv_cap} steps); the plain FP64 FIFO on the "
+            f"first {nplain} of them")
+        out["converged_batched_fp32"] = run_trace(blr, torch, helper, cp, args.serve_slots, False,
+                                                  args.serve_conv_cap)
+        out["converged_plain_fp64_fifo"] = run_trace(blr, torch, helper, cp[:nplain], 1, True,
+                                                     args.serve_conv_cap)
+        if nplain:
+            b = run_trace(blr, torch, helper, cp[:nplain], args.serve_slots, False,
+                          args.serve_conv_cap)
+            out["converged_batched_fp32_same_subset"] = b
+            out["converged_plain_over_batched_latency_p50"] = round(
+                out["converged_plain_fp64_fifo"]["latency_s_p50"] / b["latency_s_p50"], 1)
     if args.serve_long_count > 0:
         long_trace = synth.serving_trace(count=args.serve_long_count, seed=5, rate=4.0)
         lp = prepare_trace(long_trace, synth)

@@ -21,7 +21,8 @@ import numpy as np
 __all__ = [
     "vgrid_points", "xgrid_centres", "maxwellian", "rh_downstream", "shock_states",
     "c1_distribution", "c2_bimaxwellian", "c2_bkw", "smooth_basis", "shock_initial",
-    "lowrank_state", "lowrank_state_sketch", "serving_trace", "VGridSpec", "C1", "C2", "C3",
+    "lowrank_state", "lowrank_state_sketch", "serving_trace", "serving_trace_2d", "VGridSpec",
+    "C1", "C2", "C3",
     "small_3d", "small_2d",
 ]
 
@@ -378,4 +379,28 @@ def serving_trace(count: int = 64, seed: int = 5, rate: float = 4.0, mach=(1.2, 
         dt = safety * min(cfl * dx / L, nu_frac / (4.0 * math.pi * C * R * rho_r))
         out.append(dict(index=k, arrival=t, mach=m, nx=nx, n=n, r0=r, L=L,
                         dt=dt, x_lo=x_lo, x_hi=x_hi))
+    return out
+
+
+def serving_trace_2d(count: int = 8, seed: int = 6, rate: float = 4.0, mach=(1.2, 2.0),
+                     nx_choices=(32, 64), n: int = 32, L: float = 8.0, r0=(4, 8),
+                     x_lo: float = -30.0, x_hi: float = 30.0, courant: float = 0.4):
+    """A stream of steady normal-shock solves in the paper's own velocity
+    dimension (2D velocity, Maxwell molecules B = 1/(2 pi), the Sec. 5.2
+    class): Poisson arrivals of the given rate (exponential gaps, first at
+    t = 0), Mach ~ U[mach], N_x drawn from the choices on [x_lo, x_hi],
+    N_v = n^2 on [-L, L]^2, initial rank ~ U{r0}; dt = courant dx / L.
+    Returns a list of dicts (same keys as serving_trace)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for k in range(count):
+        gap = float(rng.exponential(1.0 / rate))
+        t = 0.0 if k == 0 else t + gap
+        m = float(rng.uniform(*mach))
+        nx = int(rng.choice(nx_choices))
+        r = int(rng.integers(r0[0], r0[1] + 1))
+        dx = (x_hi - x_lo) / nx
+        out.append(dict(index=k, arrival=t, mach=m, nx=nx, n=n, r0=r, L=L, d=2,
+                        dt=courant * dx / L, x_lo=x_lo, x_hi=x_hi))
     return out
