@@ -229,3 +229,89 @@ def q_pairs(V: np.ndarray, pairs, cs: CarlemanSetup, conserve: bool = True, meth
         out.append(q)
         gains.append(0.5 * (ap + bp).reshape(-1))
     return np.array(out), np.array(gains)
+
+
+# ----------------------------------------------------------------------------
+# the de-aliased convolution (the Galerkin sum over l + m = k exactly)
+# ----------------------------------------------------------------------------
+def qhat_direct_exact(gh: np.ndarray, fh: np.ndarray, cs: CarlemanSetup, parts: bool = False):
+    """Q^_k = sum_l [beta(l, k - l) - beta(l, l)] g^_l f^_{k - l} with l + m = k
+    exactly: a term whose m = k - l leaves the N-point mode set is absent (the
+    circular form wraps it instead).  Output modes with a component -N/2 are
+    set to 0, the rule the inputs follow."""
+    Phi, Psi = filters(cs)
+    M = len(cs.wdir)
+    beta = cs.b0 * (Psi.reshape(M, -1).T * cs.wdir) @ Phi.reshape(M, -1)    # beta[l, m]
+    K = oc.mode_vectors(cs).reshape(cs.d, -1).T                            # centred, DFT order
+    N, n = cs.N, K.shape[0]
+    g, f = gh.reshape(-1), fh.reshape(-1)
+    dl = np.diag(beta)
+    gain = np.zeros(n, dtype=np.complex128)
+    loss = np.zeros_like(gain)
+    for kk in range(n):
+        if np.any(K[kk] == -N // 2):
+            continue
+        mc = K[kk][None, :] - K                                            # k - l, not wrapped
+        inside = np.all((mc >= -N // 2) & (mc < N // 2), axis=1)
+        ls = np.nonzero(inside)[0]
+        midx = np.ravel_multi_index(tuple(np.mod(mc[inside], N).T), (N,) * cs.d)
+        gain[kk] = np.sum(beta[ls, midx] * g[ls] * f[midx])
+        loss[kk] = np.sum(dl[ls] * g[ls] * f[midx])
+    shape = (N,) * cs.d
+    if parts:
+        return (gain - loss).reshape(shape), gain.reshape(shape), loss.reshape(shape)
+    return (gain - loss).reshape(shape)
+
+
+def q_direct_exact(g: np.ndarray, f: np.ndarray, cs: CarlemanSetup, parts: bool = False):
+    gh, fh = oc.coefficients(g, cs), oc.coefficients(f, cs)
+    q, qp, qm = qhat_direct_exact(gh, fh, cs, parts=True)
+    out = [oc.synthesis(x, cs) for x in (q, qp, qm)]
+    if parts:
+        return out[0].real, out[1].real, out[2].real, float(np.abs(out[0].imag).max())
+    return out[0].real
+
+
+def padded_setup(cs: CarlemanSetup) -> CarlemanSetup:
+    """The same box, truncation radius and directions with 2N points per axis."""
+    return CarlemanSetup(cs.d, 2 * cs.N, cs.L, cs.R, cs.C, cs.dirs, cs.wdir)
+
+
+def q_fft_dealiased(g: np.ndarray, f: np.ndarray, cs: CarlemanSetup, parts: bool = False):
+    """The de-aliased operator through the fast form on the padded grid: the
+    interpolants of g and f at the 2N-point nodes of the same box, q_fft there
+    (its products hold every mode l + m of two N-point input modes without a
+    wrap), then the output coefficients of the N-point mode set without
+    Nyquist components, synthesised on the N-point grid."""
+    ws = padded_setup(cs)
+    N, d = cs.N, cs.d
+    k = oc.centred(N)
+    idx = np.ix_(*([k % (2 * N)] * d))
+
+    def pad(h):
+        cf = np.zeros((2 * N,) * d, dtype=np.complex128)
+        cf[idx] = oc.coefficients(h, cs)              # Nyquist modes dropped
+        return oc.synthesis(cf, ws).real
+
+    def restrict(hf):
+        c = oc.coefficients(hf, ws, zero_nyquist=False)[idx]
+        return oc.synthesis(c * oc.nyquist_mask(cs), cs).real
+
+    q, qp, qm = q_fft(pad(g), pad(f), ws, parts=True)
+    if parts:
+        return restrict(q), restrict(qp), restrict(qm)
+    return restrict(q)
+
+
+def q_pairs_dealiased(V: np.ndarray, pairs, cs: CarlemanSetup, conserve: bool = True):
+    """q_pairs with the de-aliased operator."""
+    out, gains = [], []
+    for (i, j) in pairs:
+        a, ap, _ = q_fft_dealiased(V[i], V[j], cs, parts=True)
+        b, bp, _ = q_fft_dealiased(V[j], V[i], cs, parts=True)
+        q = 0.5 * (a + b).reshape(-1)
+        if conserve:
+            q = oc.conserve_project(q, cs)
+        out.append(q)
+        gains.append(0.5 * (ap + bp).reshape(-1))
+    return np.array(out), np.array(gains)
