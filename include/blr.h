@@ -65,14 +65,20 @@ typedef enum { BLR_FP32 = 0, BLR_FP64 = 1 } blr_precision;
  * gamma = d - 2. */
 #define BLR_CARLEMAN         0x8u
 /* De-aliased convolution: the Galerkin sum over l + m = k exactly instead of
- * l + m = k mod n (the circular convolution an n-point transform computes).
- * Evaluated on a grid of 2n points per axis (the band-limited interpolants
- * of the inputs, n / 2 >= the 3n / 2 - n padding that keeps every sum l + m
- * of two input modes off the wrap), then the output modes k in the n-point
- * mode set are kept and every mode with a component -n/2 is dropped (the
- * rule the inputs follow), so the output is real.  The projection (unless
- * BLR_NO_CONSERVE) acts on that output.  3D n in {8, 16}, 2D n = 16; other
- * grids BLR_ERR_UNSUPPORTED. */
+ * l + m = k mod n (the circular convolution an n-point transform computes),
+ * for every collision form (isotropic, anisotropic, Carleman).  Two inputs
+ * without Nyquist modes have products with modes |k_i| <= n - 2.  3D n in
+ * {8, 16} and 2D n = 16: the pipeline runs on the grid of 2n points per axis
+ * (the band-limited interpolants of the inputs; no sum of two input modes
+ * wraps there).  The other grids: the mean of 2^d runs of the pipeline on the
+ * interpolants sampled at v + s dv / 2 for every subset s of the axes, each
+ * output spectrum with its shift's phase removed; a wrap k + jn (|j_i| <= 1)
+ * enters with sign (-1)^(j.s), so only j = 0 survives the mean (2^d times the
+ * work of the circular operator, no grid of 2n points).  Either way the
+ * output modes k of the n-point mode set are kept and every mode with a
+ * component -n/2 is dropped (the rule the inputs follow), so the output is
+ * real.  The projection (unless BLR_NO_CONSERVE) acts on that output.  The
+ * two evaluations agree to rounding. */
 #define BLR_DEALIAS          0x10u
 
 /* Velocity discretisation and collision kernel.

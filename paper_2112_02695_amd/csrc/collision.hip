@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <unordered_map>
 
 #include "collision_common.hpp"
 
@@ -431,6 +432,26 @@ static void transform(hipStream_t s, const Ld& ld, const St& st, typename Vec2<T
   line_pass<T, N, D, DIR>(s, ldc, st, 0, nfields);
 }
 
+// transform of the rows bidx of V: directly when they are the rows 0..rb-1
+// (the full-tensor step's cells, up to kMaxSelfRows), else through an index
+// map of at most 64 rows
+template <typename T, int N, int D, int DIR, class St>
+static void transform_rows(hipStream_t s, const T* V, const std::vector<int>& bidx, const St& st,
+                           typename Vec2<T>::t* tmp) {
+  constexpr int n = (D == 2 ? N * N : N * N * N);
+  const int rb = (int)bidx.size();
+  bool ident = true;
+  for (int ib = 0; ib < rb; ++ib) ident = ident && bidx[ib] == ib;
+  if (ident) {
+    transform<T, N, D, DIR>(s, LdReal<T>{V, n}, st, tmp, rb);
+    return;
+  }
+  require(rb <= 64, "at most 64 distinct basis functions per call");
+  Idx64 idx{};
+  for (int ib = 0; ib < rb; ++ib) idx.v[ib] = bidx[ib];
+  transform<T, N, D, DIR>(s, LdRealIdx<T>{V, n, idx}, st, tmp, rb);
+}
+
 // ------------------------------------------------------------- sigma reduce
 // One thread per grid point; a tile of basis functions (ni on the left, nj on
 // the right, or one set of ni on both sides for a diagonal tile) whose pair
@@ -496,6 +517,29 @@ __global__ __launch_bounds__(256) void k_sigma_reduce(const T* __restrict__ sh, 
       ++p;
     }
   }
+}
+
+// The same sums for pairs (i, i) only (every pair of the full-tensor step):
+// one thread per (grid point, pair), P_ii = sum_b 2 w_b S_i(b) S_i(bbar).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sigma_self(const T* __restrict__ sh, T* __restrict__ pa,
+                                                    const int* __restrict__ pi,
+                                                    const T* __restrict__ wbp,
+                                                    const int* __restrict__ bp_b,
+                                                    const int* __restrict__ bp_bb, int n, int mrho,
+                                                    int msig, int nbp, int a) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (q >= n) return;
+  const long fi = ((long)pi[p] * mrho + a) * msig;
+  T acc = T(0);
+  for (int bp = 0; bp < nbp; ++bp) {
+    const T w = wbp[bp];
+    const T x = sh[(fi + bp_b[bp]) * n + q];
+    const T y = sh[(fi + bp_bb[bp]) * n + q];
+    acc += (w * x) * y + (w * y) * x;
+  }
+  pa[(long)p * n + q] = acc;
 }
 
 // ------------------------------------------------------------ utilities
@@ -656,11 +700,12 @@ static PairPlan make_plan(int r, const int32_t* pairs, int npairs) {
     }
   // each distinct unordered pair is evaluated once (Q_s is symmetric); a
   // repeated request copies the row of its first occurrence
-  std::vector<int> first((size_t)r * r, -1);
+  std::unordered_map<long, int> first;
+  first.reserve(2 * (size_t)npairs);
   for (int p = 0; p < npairs; ++p) {
     const int a = map[pairs[2 * p]], b = map[pairs[2 * p + 1]];
     const int lo = std::min(a, b), hi = std::max(a, b);
-    int& f = first[(size_t)lo * r + hi];
+    int& f = first.try_emplace((long)lo * r + hi, -1).first->second;
     if (f >= 0) {
       pl.dup.emplace_back(p, f);
       continue;
@@ -678,6 +723,22 @@ template <typename T, int N, int D>
 struct Generic {
   static constexpr int n = (D == 2 ? N * N : N * N * N);
   using T2 = typename Vec2<T>::t;
+
+  // every requested pair is (i, i): k_sigma_self instead of the tiles
+  static bool self_only(const PairPlan& pl) {
+    for (size_t p = 0; p < pl.li.size(); ++p)
+      if (pl.li[p] != pl.lj[p]) return false;
+    return !pl.li.empty();
+  }
+
+  static void sigma_self(hipStream_t s, const char* name, const T* Sh, T* Pa, const int* dli,
+                         const T* wbp, const int* bp_b, const int* bp_bb, int mrho, int msig,
+                         int nbp, int a, int P) {
+    TimedScope ts(s, name, (double)n * P * (2 * nbp + 1) * sizeof(T));
+    hipLaunchKernelGGL(k_sigma_self<T>, dim3((n + 255) / 256, P), dim3(256), 0, s, Sh, Pa, dli, wbp,
+                       bp_b, bp_bb, n, mrho, msig, nbp, a);
+    BLR_CHECK_LAUNCH();
+  }
 
   static size_t workspace(const HostTables& h, int rb, int P) {
     const long nc = P;
@@ -700,16 +761,12 @@ struct Generic {
     const HostTables& h = tb.h;
     hipStream_t s = ctx->stream;
     const int rb = (int)pl.bidx.size();
-    require(rb <= 64, "at most 64 distinct basis functions per call");
     const std::string tag = std::string("bas") + (sizeof(T) == 4 ? "f" : "d");
     T2* Vh = (T2*)ctx->buf(tag + ".Vh", (size_t)rb * n * sizeof(T2));
     T* Vp = (T*)ctx->buf(tag + ".VpLam", (size_t)2 * rb * n * sizeof(T));
     T2* tmp = (T2*)ctx->buf(tag + ".tmp", (size_t)2 * rb * n * sizeof(T2));
-    Idx64 idx{};
-    for (int ib = 0; ib < rb; ++ib) idx.v[ib] = pl.bidx[ib];
     g_stage = "basis";
-    transform<T, N, D, -1>(s, LdRealIdx<T>{Vsrc, n, idx}, StBasisSpec<T, N, D>{Vh, n, T(1) / T(n)},
-                           tmp, rb);
+    transform_rows<T, N, D, -1>(s, Vsrc, pl.bidx, StBasisSpec<T, N, D>{Vh, n, T(1) / T(n)}, tmp);
     transform<T, N, D, +1>(s, LdBasisMode<T>{Vh, (const T*)tb.gloss, n, rb}, StRe<T>{Vp, n}, tmp,
                            2 * rb);
     (void)h;
@@ -741,7 +798,11 @@ struct Generic {
     }
     bool diag_only = false;
     const int Gt = sizeof(T) == 4 ? 12 : 8;
-    auto tiles = plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
+    const bool self = self_only(pl);
+    if (self)
+      sigma_self(s, "carl.sigma_self", Sh, Pa, didx, (const T*)tb.wbp, tb.bp_b, tb.bp_bb, 1, h.msig,
+                 h.nbp, 0, P);
+    auto tiles = self ? std::vector<ReduceTile>{} : plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
     for (const auto& t : tiles) {
       const bool diag = t.bi[0] == t.bj[0];
       const int bs = 256;
@@ -820,7 +881,8 @@ struct Generic {
     fill<T>(s, (T*)G, 2 * nc * n, T(0));
     bool diag_only = false;
     const int Gt = sizeof(T) == 4 ? 12 : 8;
-    auto tiles = plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
+    const bool self = self_only(pl);
+    auto tiles = self ? std::vector<ReduceTile>{} : plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
     g_stage = "gen.pairfft";
     if (h.aniso_n > 0) {
       // anisotropic kernel: each antipodal pair's product is transformed and
@@ -828,6 +890,9 @@ struct Generic {
       const T* atab = (const T*)tb.atab;
       for (int a = 0; a < h.mrho; ++a)
         for (int bp = 0; bp < h.nbp; ++bp) {
+          if (self)
+            sigma_self(s, "gen.sigma_pair", Sh, Pa, didx, (const T*)tb.wbp + bp, tb.bp_b + bp,
+                       tb.bp_bb + bp, h.mrho, h.msig, 1, a, P);
           for (const auto& t : tiles) {
             const bool diag = t.bi[0] == t.bj[0];
             const dim3 grid((n + 255) / 256);
@@ -858,6 +923,9 @@ struct Generic {
         }
     }
     for (int a = 0; a < h.mrho && h.aniso_n == 0; ++a) {
+      if (self)
+        sigma_self(s, "gen.sigma_self", Sh, Pa, didx, (const T*)tb.wbp, tb.bp_b, tb.bp_bb, h.mrho,
+                   h.msig, h.nbp, a, P);
       for (const auto& t : tiles) {
         const bool diag = t.bi[0] == t.bj[0];
         const int bs = 256;
@@ -987,6 +1055,130 @@ template <typename T>
 static void run_pairs(blr_ctx ctx, const DevTables& tb, const T* V, int r, const int32_t* pairs,
                       int npairs, T* Q, uint32_t flags);
 
+__device__ __forceinline__ void sincospi_t(float x, float* sn, float* cs) { sincospif(x, sn, cs); }
+__device__ __forceinline__ void sincospi_t(double x, double* sn, double* cs) { sincospi(x, sn, cs); }
+
+// sum of the centred modes k_ax over the axes ax in the bit set s (bit ax set:
+// the grid is shifted by half a cell along axis ax; axis 0 outermost)
+template <int N, int D>
+__device__ __forceinline__ int shifted_mode_sum(int e, int sbits) {
+  int m = 0;
+#pragma unroll
+  for (int ax = D - 1; ax >= 0; --ax) {
+    if ((sbits >> ax) & 1) m += ctr<N>(e % N);
+    e /= N;
+  }
+  return m;
+}
+
+// V^_f exp(i pi (k.s) / N): the spectrum whose inverse transform samples the
+// interpolant at v_q + s dv / 2
+template <typename T, int N, int D>
+struct LdPhase {
+  static constexpr int bpe = 2;  // algorithmic bytes per element / sizeof(T)
+  const typename Vec2<T>::t* vh;
+  int n, sbits;
+  template <int NN>
+  __device__ void load(long f, int base, int stride, T (&re)[NN], T (&im)[NN]) const {
+    const auto* q = vh + f * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int m = shifted_mode_sum<N, D>(base + j * stride, sbits);
+      T sn, cs;
+      sincospi_t(T(m) / T(N), &sn, &cs);
+      const auto v = q[(long)j * stride];
+      re[j] = v.x * cs - v.y * sn;
+      im[j] = v.x * sn + v.y * cs;
+    }
+  }
+};
+
+// acc (+)= scale X_k exp(-i pi (k.s) / N); modes with a Nyquist component 0
+template <typename T, int N, int D>
+struct StDephase {
+  static constexpr int bpe = 4;  // algorithmic bytes per element / sizeof(T)
+  typename Vec2<T>::t* acc;
+  int n, sbits;
+  T scale;
+  int first;
+  template <int NN>
+  __device__ void store(long f, int base, int stride, const T (&re)[NN], const T (&im)[NN]) const {
+    auto* a = acc + f * n + base;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int e = base + j * stride;
+      bool nyq = false;
+      int r = e;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        nyq = nyq || (r % N == N / 2);
+        r /= N;
+      }
+      typename Vec2<T>::t v = make2<T>(T(0), T(0));
+      if (!nyq) {
+        T sn, cs;
+        sincospi_t(T(shifted_mode_sum<N, D>(e, sbits)) / T(N), &sn, &cs);
+        if (!first) v = a[(long)j * stride];
+        v.x += (re[j] * cs + im[j] * sn) * scale;
+        v.y += (im[j] * cs - re[j] * sn) * scale;
+      }
+      a[(long)j * stride] = v;
+    }
+  }
+};
+
+// BLR_DEALIAS from 2^D evaluations on the N-point grid: for every subset s of
+// the axes, the pipeline (circular products, no projection) run on the
+// samples of the interpolants at v_q + s dv / 2, whose output spectrum, once
+// the shift's phase is taken off, holds each exact mode k plus its wraps
+// k + jN weighted by (-1)^(j.s).  Two inputs without Nyquist modes give
+// products with |k_i| <= N - 2, so every wrap has |j_i| <= 1 and the mean over
+// the 2^D subsets keeps j = 0 alone: the exact Galerkin sum over l + m = k,
+// without a grid of 2N points.  Then the modes without Nyquist components,
+// back to the grid, and the optional projection.
+template <typename T, int N, int D>
+static void run_dealias_shift(blr_ctx ctx, const DevTables& tb, const T* V, int r,
+                              const int32_t* pairs, int npairs, T* Q, uint32_t flags) {
+  using T2 = typename Vec2<T>::t;
+  constexpr long n = D == 2 ? (long)N * N : (long)N * N * N;
+  hipStream_t s = ctx->stream;
+  const PairPlan pl = make_plan(r, pairs, npairs);
+  const int rb = (int)pl.bidx.size(), P = (int)pl.li.size();
+  const std::string tag = std::string("dsh") + (sizeof(T) == 4 ? "f" : "d");
+  T2* vh = (T2*)ctx->buf(tag + ".vh", (size_t)rb * n * sizeof(T2));
+  T2* tc = (T2*)ctx->buf(tag + ".tc", (size_t)std::max(rb, P) * n * sizeof(T2));
+  T2* acc = (T2*)ctx->buf(tag + ".acc", (size_t)P * n * sizeof(T2));
+  T* Vs = (T*)ctx->buf(tag + ".Vs", (size_t)rb * n * sizeof(T));
+  T* Qs = (T*)ctx->buf(tag + ".Qs", (size_t)P * n * sizeof(T));
+  g_stage = "dealias.spec";
+  transform_rows<T, N, D, -1>(s, V, pl.bidx, StBasisSpec<T, N, D>{vh, (int)n, T(1) / T(n)}, tc);
+  std::vector<int32_t> cp(2 * (size_t)P);
+  for (int p = 0; p < P; ++p) {
+    cp[2 * p] = pl.li[p];
+    cp[2 * p + 1] = pl.lj[p];
+  }
+  const uint32_t sub = (flags & ~(uint32_t)BLR_DEALIAS) | BLR_NO_CONSERVE;
+  const T scale = T(1) / (T(n) * T(1 << D));
+  for (int sb = 0; sb < (1 << D); ++sb) {
+    g_stage = "dealias.shift";
+    transform<T, N, D, +1>(s, LdPhase<T, N, D>{vh, (int)n, sb}, StRe<T>{Vs, (int)n}, tc, rb);
+    run_pairs<T>(ctx, tb, Vs, rb, cp.data(), P, Qs, sub);
+    g_stage = "dealias.unshift";
+    transform<T, N, D, -1>(s, LdReal<T>{Qs, (int)n}, StDephase<T, N, D>{acc, (int)n, sb, scale, sb == 0},
+                           tc, P);
+  }
+  g_stage = "dealias.out";
+  transform<T, N, D, +1>(s, LdComplex<T>{acc, (int)n}, StRe<T>{Qs, (int)n}, tc, P);
+  int* drow = (int*)ctx->upload(tag + ".row", pl.row.data(), pl.row.size() * sizeof(int));
+  hipLaunchKernelGGL((k_scatter_rows<T>), dim3((unsigned)((n + 255) / 256), P), dim3(256), 0, s, Qs,
+                     drow, n, Q);
+  BLR_CHECK_LAUNCH();
+  for (const auto& dp : pl.dup)
+    BLR_HIP(hipMemcpyAsync(Q + (size_t)dp.first * n, Q + (size_t)dp.second * n, (size_t)n * sizeof(T),
+                           hipMemcpyDeviceToDevice, s));
+  if (!(flags & BLR_NO_CONSERVE)) conserve_rows<T>(ctx, tb.h, Q, npairs);
+}
+
 // BLR_DEALIAS: the band-limited interpolants of the basis functions on the
 // grid of 2N points per axis (same box, same quadrature), the pair operator
 // there without the projection (sums of two input modes never wrap on that
@@ -1010,10 +1202,8 @@ static void run_dealias(blr_ctx ctx, const blr_vgrid& vg, int prec, const DevTab
   T* Vf = (T*)ctx->buf(tag + ".Vf", (size_t)rb * nf * sizeof(T));
   T* Qf = (T*)ctx->buf(tag + ".Qf", (size_t)P * nf * sizeof(T));
   T* Qc = (T*)ctx->buf(tag + ".Qc", (size_t)P * n * sizeof(T));
-  Idx64 idx{};
-  for (int ib = 0; ib < rb; ++ib) idx.v[ib] = pl.bidx[ib];
   g_stage = "dealias.pad";
-  transform<T, N, D, -1>(s, LdRealIdx<T>{V, (int)n, idx}, StComplex<T>{cs, (int)n}, tc, rb);
+  transform_rows<T, N, D, -1>(s, V, pl.bidx, StComplex<T>{cs, (int)n}, tc);
   hipLaunchKernelGGL((k_pad_spec<T, N, D>), dim3((unsigned)((nf + 255) / 256), rb), dim3(256), 0, s,
                      cs, fs, rb, T(1) / T(n));
   BLR_CHECK_LAUNCH();
@@ -1146,10 +1336,25 @@ size_t collision_call_bytes(const HostTables& h, int prec, int r, const int32_t*
   return b;
 }
 
+static void collision_pairs_impl(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
+                                 const int32_t* pairs, int npairs, void* Q);
+
 void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
                      const int32_t* pairs, int npairs, void* Q) {
-  g_timer = &ctx->timer;
   require(r >= 1 && r <= 64, "r must be in [1, 64]");
+  collision_pairs_impl(ctx, vg, prec, V, r, pairs, npairs, Q);
+}
+
+void collision_self(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int rows, void* Q) {
+  require(rows >= 1 && rows <= kMaxSelfRows, "collision_self: rows out of range");
+  std::vector<int32_t> pairs(2 * (size_t)rows);
+  for (int i = 0; i < rows; ++i) pairs[2 * i] = pairs[2 * i + 1] = i;
+  collision_pairs_impl(ctx, vg, prec, V, rows, pairs.data(), rows, Q);
+}
+
+static void collision_pairs_impl(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
+                                 const int32_t* pairs, int npairs, void* Q) {
+  g_timer = &ctx->timer;
   require(npairs >= 0 && npairs <= 4096, "npairs must be in [0, 4096]");
   require(npairs == 0 || (pairs && V && Q), "null pointer argument");
   const DevTables& tb = get_tables(ctx, vg, prec);
@@ -1163,7 +1368,10 @@ void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, 
       else if (vg.d == 2 && vg.n == 16)
         run_dealias<T, 16, 2>(ctx, vg, prec, tb, (const T*)V, r, pairs, npairs, (T*)Q, vg.flags);
       else
-        throw Error(BLR_ERR_UNSUPPORTED, "BLR_DEALIAS: grid not built");
+        dispatch_size<T>(vg.d, vg.n, [&](auto Nc, auto Dc) {
+          run_dealias_shift<T, decltype(Nc)::value, decltype(Dc)::value>(
+              ctx, tb, (const T*)V, r, pairs, npairs, (T*)Q, vg.flags);
+        });
     };
     if (prec == BLR_FP32) go(float{});
     else go(double{});

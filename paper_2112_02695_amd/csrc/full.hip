@@ -180,8 +180,8 @@ __global__ void k_cast_f32(const double* __restrict__ in, long count, float* __r
 
 static unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double dt,
-               double* err_out) {
+static void full_validate(const blr_problem* pb, int prec, const double* F, double dt,
+                          const double* err_out) {
   require(pb != nullptr && F != nullptr && err_out != nullptr, "null argument");
   require(pb->nx >= 1, "nx must be >= 1");
   require(pb->x_hi > pb->x_lo, "x_hi must exceed x_lo");
@@ -204,6 +204,12 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
     require(pb->ny >= 0, "problem.ny must be >= 0");
     require(pb->face_rows == 0, "problem.face_rows: one-dimensional space takes one row per face");
   }
+}
+
+// The device work of one step; err_full (the L2 norm of the change) lands in
+// the pinned read-back buffer, whose address is returned.
+static double* full_enqueue(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double dt) {
+  const bool two_d = pb->ny >= 2;
   const DevTables& tb = get_tables(ctx, pb->v, prec);
   const HostTables& h = tb.h;
   hipStream_t s = ctx->stream;
@@ -215,7 +221,10 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
   const int plane = h.d == 3 ? h.N * h.N : h.N;
   const int stride1 = h.d == 3 ? h.N : 1;  // velocity axis 1 (along y)
   const int esz = prec == BLR_FP32 ? 4 : 8;
-  const int chunk = (int)std::min<long>(ncells, fk::kChunk);
+  // cells per collision call: with 2D velocity all of them up to 1024 (the
+  // launches of a 32^2 grid are small, more cells per launch fill the chip);
+  // with 3D velocity 64 (the fused pair kernels' basis limit)
+  const int chunk = (int)std::min<long>(ncells, h.d == 2 ? kMaxSelfRows : fk::kChunk);
   double* Fn = (double*)ctx->buf("full.Fn", (size_t)ncells * n * sizeof(double));
   void* Q = ctx->buf("full.Q", (size_t)chunk * n * esz);
   float* F32 = prec == BLR_FP32 ? (float*)ctx->buf("full.F32", (size_t)chunk * n * sizeof(float))
@@ -237,18 +246,16 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
                        pb->f_right, pb->wall_left, pb->wall_right, h.L, h.dv, plane, rho);
   }
   BLR_CHECK_LAUNCH();
-  std::vector<int32_t> pairs(2 * chunk);
   for (long p0 = 0; p0 < ncells; p0 += chunk) {
     const int np = (int)std::min<long>(chunk, ncells - p0);
-    for (int i = 0; i < np; ++i) pairs[2 * i] = pairs[2 * i + 1] = i;
     const double* rows = F + p0 * n;
     if (prec == BLR_FP32) {
       hipLaunchKernelGGL(fk::k_cast_f32, dim3(nblocks((long)np * n, 256)), dim3(256), 0, s, rows,
                          (long)np * n, F32);
       BLR_CHECK_LAUNCH();
-      collision_pairs(ctx, pb->v, BLR_FP32, F32, np, pairs.data(), np, Q);
+      collision_self(ctx, pb->v, BLR_FP32, F32, np, Q);
     } else {
-      collision_pairs(ctx, pb->v, BLR_FP64, rows, np, pairs.data(), np, Q);
+      collision_self(ctx, pb->v, BLR_FP64, rows, np, Q);
     }
     timed_begin("full.update", (double)np * n * 8.0 * (3.0 + 1.0) + (double)np * n * esz, s);
     if (two_d) {
@@ -278,8 +285,100 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
   BLR_HIP(hipMemcpyAsync(F, Fn, (size_t)ncells * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   double* hb = (double*)ctx->host_readback(sizeof(double));
   BLR_HIP(hipMemcpyAsync(hb, err, sizeof(double), hipMemcpyDeviceToHost, s));
+  return hb;
+}
+
+// One step.  Unless kernels are timed, the device work is recorded as a graph
+// the second time a configuration (problem, F, dt, precision) is seen and
+// replayed from then on: at 2D grids of 32^2 points the step is a thousand
+// small launches, whose issue costs more than their work.
+void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double dt,
+               double* err_out) {
+  full_validate(pb, prec, F, dt, err_out);
+  hipStream_t s = ctx->stream;
+  auto eager = [&]() {
+    double* hb = full_enqueue(ctx, pb, prec, F, dt);
+    BLR_HIP(hipStreamSynchronize(s));
+    *err_out = hb[0];
+  };
+  if (ctx->timer.on) {
+    eager();
+    return;
+  }
+  std::string key = "full#";
+  key.append((const char*)pb, sizeof(*pb));
+  key.append((const char*)&F, sizeof(F));
+  key.append((const char*)&dt, sizeof(dt));
+  key.append((const char*)&prec, sizeof(prec));
+  auto& gs = ctx->graphs;
+  size_t gi = gs.size();
+  for (size_t k = 0; k < gs.size(); ++k)
+    if (gs[k].key == key) gi = k;
+  if (gi == gs.size()) {
+    if (gs.size() >= 8) {  // forget the oldest
+      if (gs.front().exec) (void)hipGraphExecDestroy(gs.front().exec);
+      gs.erase(gs.begin());
+    }
+    gs.push_back(blr_ctx_t::StepGraph{});
+    gi = gs.size() - 1;
+    gs[gi].key = key;
+  }
+  auto& g = gs[gi];
+  if (g.gen != ctx->buf_gen) {  // addresses moved: start over
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.seen = 0;
+    g.gen = ctx->buf_gen;
+  }
+  if (!g.exec && g.seen == 0) {
+    eager();
+    g.seen = 1;
+    g.gen = ctx->buf_gen;
+    return;
+  }
+  if (!g.exec) {
+    if (!ctx->cap_stream) BLR_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    const uint64_t gen0 = ctx->buf_gen;
+    ctx->stream = ctx->cap_stream;
+    ctx->capturing = true;
+    ctx->capture_broken = false;
+    hipGraph_t graph = nullptr;
+    double* hb = nullptr;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        hb = full_enqueue(ctx, pb, prec, F, dt);
+      } catch (...) {
+        (void)hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        ctx->stream = s;
+        ctx->capturing = false;
+        (void)hipGetLastError();
+        eager();  // the same kernels directly; an error of the step's own is reported there
+        g.gen = ctx->buf_gen;
+        return;
+      }
+      e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    }
+    ctx->stream = s;
+    ctx->capturing = false;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess && graph && !ctx->capture_broken && ctx->buf_gen == gen0)
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess || !exec) {
+      (void)hipGetLastError();
+      eager();  // not recordable this time: run it directly
+      g.gen = ctx->buf_gen;
+      return;
+    }
+    g.exec = exec;
+    g.gen = ctx->buf_gen;
+    g.hb = hb;
+  }
+  BLR_HIP(hipGraphLaunch(g.exec, s));
   BLR_HIP(hipStreamSynchronize(s));
-  *err_out = hb[0];
+  *err_out = g.hb[0];
 }
 
 }  // namespace blr

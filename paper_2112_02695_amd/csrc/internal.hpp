@@ -200,6 +200,11 @@ void validate_vgrid(const blr_vgrid& vg);
 void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
                      const int32_t* pairs_dev, int npairs, void* Q);
 size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec);
+// Q_s(V_i, V_i) for the rows i = 0..rows-1 of V into the rows of Q (the
+// full-tensor step's cells): the pipeline of collision_pairs without its
+// 64-row limit, since a pair list of rows (i, i) needs no pair tiles.
+constexpr int kMaxSelfRows = 1024;
+void collision_self(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int rows, void* Q);
 // Upper bound of the device bytes collision_pairs takes from buf()/upload()
 // and the tables for this call (each slice rounded up to 256 bytes).
 size_t collision_call_bytes(const HostTables& h, int prec, int r, const int32_t* pairs, int npairs,

@@ -180,10 +180,6 @@ void validate_vgrid(const blr_vgrid& vg) {
     require(!(vg.flags & BLR_CARLEMAN), "an anisotropic kernel is not available in the Carleman form");
     for (int i = 0; i < vg.aniso_n; ++i) require(std::isfinite(vg.aniso[i]), "vgrid.aniso must be finite");
   }
-  if (vg.flags & BLR_DEALIAS)
-    require((vg.d == 3 && (vg.n == 8 || vg.n == 16)) || (vg.d == 2 && vg.n == 16),
-            "BLR_DEALIAS needs 3D n in {8, 16} or 2D n = 16 (the padded grid has 2n points)",
-            BLR_ERR_UNSUPPORTED);
 }
 
 // (C C^T)^-1 for the moment projection; C rows dv^d {1, v_1..v_d, |v|^2}

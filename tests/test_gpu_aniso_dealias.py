@@ -18,6 +18,7 @@ import pytest
 
 import synth
 from oracle import aniso as oa
+from oracle import carleman as ca
 from oracle import collision as oc
 from oracle import dlr
 
@@ -91,12 +92,53 @@ def test_dealiased_pairs_match_oracle(ctx, d, n, m_rho, r, dtype, conserve):
     assert e.max() < TOL[dtype]
 
 
-def test_dealias_refused_where_not_built_and_in_the_allocation_free_call(ctx):
-    spec = _spec(3, 32, 2)
-    V = torch.zeros((1, spec.npts), dtype=torch.float32, device="cuda")
-    with pytest.raises(blr.BlrError) as ei:
-        ctx.collision_pairs(blr.vgrid_from_spec(spec, blr.BLR_DEALIAS), V, [(0, 0)])
-    assert ei.value.code == blr.BLR_ERR_UNSUPPORTED
+@pytest.mark.parametrize("d,n,m_rho,r", [(2, 32, 6, 4), (3, 24, 2, 2)])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("conserve", [True, False])
+def test_dealiased_pairs_from_shifted_grids_match_oracle(ctx, d, n, m_rho, r, dtype, conserve):
+    """Grids without the padded evaluation: the mean over the 2^d half-cell
+    shifted copies of the grid."""
+    print(f"dealias (shifted grids) d={d} n={n} r={r} {dtype} conserve={conserve}", flush=True)
+    spec = _spec(d, n, m_rho)
+    vs = oc.setup_from_spec(spec)
+    V = synth.smooth_basis(r, spec, seed=43 + n)
+    pairs = blr.upper_pairs(r) + [(1, 0)]
+    ref, gain = oc.q_pairs_dealiased(V, pairs, vs, conserve=conserve)
+    flags = blr.BLR_DEALIAS | (0 if conserve else blr.BLR_NO_CONSERVE)
+    q = _run(ctx, spec, V, pairs, dtype, flags)
+    e = np.linalg.norm(q - ref, axis=1) / np.linalg.norm(gain, axis=1)
+    print(f"  max rel {e.max():.3e}", flush=True)
+    assert e.max() < TOL[dtype]
+
+
+def _carleman_spec(n, L=8.0):
+    return synth.VGridSpec(d=2, n=n, L=L, gamma=0.0, C=1 / (2 * math.pi), m_rho=1, m_sigma=8)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("conserve", [True, False])
+def test_dealiased_carleman_pairs_match_oracle(ctx, n, dtype, conserve):
+    """The Carleman form de-aliased: n = 16 on the padded grid, n = 32 from the
+    shifted grids; at n = 32 the box of the Mach-3.8 shock (L_v = 20.97), where
+    these inputs are under-resolved and the wrap changes Q by about 9 %."""
+    print(f"dealias carleman n={n} {dtype} conserve={conserve}", flush=True)
+    spec = _carleman_spec(n, 8.0 if n == 16 else 20.97)
+    cs = ca.setup_from_spec(spec)
+    V = synth.smooth_basis(4, spec, seed=47 + n)
+    pairs = blr.upper_pairs(4)
+    ref, gain = ca.q_pairs_dealiased(V, pairs, cs, conserve=conserve)
+    flags = blr.BLR_CARLEMAN | blr.BLR_DEALIAS | (0 if conserve else blr.BLR_NO_CONSERVE)
+    q = _run(ctx, spec, V, pairs, dtype, flags)
+    e = np.linalg.norm(q - ref, axis=1) / np.linalg.norm(gain, axis=1)
+    print(f"  max rel {e.max():.3e}", flush=True)
+    assert e.max() < TOL[dtype]
+    # the wrap matters for these inputs
+    circ = _run(ctx, spec, V, pairs, dtype, flags & ~blr.BLR_DEALIAS)
+    assert (np.linalg.norm(circ - ref, axis=1) / np.linalg.norm(gain, axis=1)).max() > 1e-4
+
+
+def test_dealias_refused_in_the_allocation_free_call(ctx):
     spec = _spec(3, 8, 2)
     V = torch.zeros((1, spec.npts), dtype=torch.float32, device="cuda")
     out = torch.zeros_like(V)
@@ -104,6 +146,41 @@ def test_dealias_refused_where_not_built_and_in_the_allocation_free_call(ctx):
         ctx.collision_pairs(blr.vgrid_from_spec(spec, blr.BLR_DEALIAS), V, [(0, 0)], out=out,
                             noalloc=True)
     assert ei.value.code == blr.BLR_ERR_UNSUPPORTED
+
+
+def test_step_with_dealiased_carleman_collisions_matches_oracle(ctx):
+    """One fixed-rank K-S-L step (FP64, 2D 32^2) whose pair collisions use the
+    de-aliased Carleman form (shifted grids), against the oracle's step with
+    the oracle's de-aliased evaluator."""
+    spec = _carleman_spec(32, L=13.11)
+    cs = ca.setup_from_spec(spec)
+    nx, r = 24, 4
+    ini = synth.shock_initial(1.4, spec, nx, -30.0, 30.0, pert=1e-2, pert_rank=3, seed=3)
+    prob = dlr.Problem1D(vs=oc.setup(2, 32, spec.L, spec.C, 0.0, 1, 8), nx=nx, x_lo=-30.0,
+                         x_hi=30.0, fL=ini["fL"], fR=ini["fR"],
+                         collision=lambda V, pairs, vs_, conserve: ca.q_pairs_dealiased(
+                             V, pairs, cs, conserve))
+    X, S, V = synth.lowrank_state(ini["f0"], r, prob.dx, prob.dvd)
+    dev = "cuda"
+    Xd = torch.zeros((8, nx), dtype=torch.float64, device=dev)
+    Sd = torch.zeros((8, 8), dtype=torch.float64, device=dev)
+    Vd = torch.zeros((8, spec.npts), dtype=torch.float64, device=dev)
+    Xd[:r] = torch.tensor(X.T, device=dev)
+    Sd[:r, :r] = torch.tensor(S, device=dev)
+    Vd[:r] = torch.tensor(V, device=dev)
+    fL, fR = torch.tensor(ini["fL"], device=dev), torch.tensor(ini["fR"], device=dev)
+    pb = ctx.make_problem(blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN | blr.BLR_DEALIAS), nx,
+                          -30.0, 30.0, fL, fR)
+    st = ctx.make_state(Xd, Sd, Vd, r)
+    info = ctx.dlr_step(pb, st, blr.StepParams(0.05, 0.2, 1e-10, 1, 8, blr.BLR_STEP_FP64_COLLISION))
+    new, err, _ = dlr.ksl_step(dlr.State(X, S, V), prob, 0.05)
+    f_gpu = (Xd[:r].cpu().numpy().T @ Sd[:r, :r].cpu().numpy()) @ Vd[:r].cpu().numpy()
+    f_ref = new.full()
+    e = np.abs(f_gpu - f_ref).max() / np.abs(f_ref).max()
+    print(f"dealiased carleman step: f rel err {e:.2e}, err {info.err:.12e} vs {err:.12e}",
+          flush=True)
+    assert e < 1e-12
+    assert abs(info.err - err) < 1e-10 * err
 
 
 def test_step_with_anisotropic_collisions_matches_oracle(ctx):

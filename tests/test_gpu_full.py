@@ -12,6 +12,7 @@ part of every cell's Q_s(f_p, f_p) (transport is FP64 on both sides; near
 equilibrium Q_s is a small difference of large gain and loss terms).
 err_full to 1e-12 / 1e-5 relative.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -168,9 +169,73 @@ def test_full_step_on_a_rectangle_fp64(ctx, d, n, m_rho, nx, ny):
 
 
 def test_full_step_on_a_rectangle_fp32_two_chunks(ctx):
-    """9 x 8 = 72 cells: two collision calls (64 + 8)."""
-    print("full step 2D space fp32 9x8", flush=True)
-    rel, e, eref = _rect_case(ctx, 2, 16, 4, 9, 8, blr.BLR_FP32)
+    """33 x 32 = 1056 cells: two collision calls (1024 + 32)."""
+    print("full step 2D space fp32 33x32", flush=True)
+    rel, e, eref = _rect_case(ctx, 2, 16, 4, 33, 32, blr.BLR_FP32)
     print("rel", rel, "err", e, eref, flush=True)
     assert rel < 1e-5
     assert abs(e - eref) < 1e-5 * eref
+
+
+def _mach38_case(nx, seed=7):
+    """The Mach-3.8 shock's velocity box (2D 32^2 on [-20.97, 20.97]^2, Maxwell
+    molecules in the Carleman form, 8 directions) on nx cells of [-30, 30]."""
+    from oracle import carleman as ca
+    spec = synth.VGridSpec(d=2, n=32, L=20.97, gamma=0.0, C=1 / (2 * math.pi), m_rho=1,
+                           m_sigma=8)
+    ini = synth.shock_initial(3.8, spec, nx, -30.0, 30.0, pert=1e-2, pert_rank=3, seed=seed)
+    cs = ca.setup_from_spec(spec)
+    prob = dlr.Problem1D(vs=oc.setup(2, 32, spec.L, spec.C, 0.0, 1, 8), nx=nx, x_lo=-30.0,
+                         x_hi=30.0, fL=ini["fL"], fR=ini["fR"],
+                         collision=lambda V, pairs, vs_, conserve: ca.q_pairs_dealiased(
+                             V, pairs, cs, conserve))
+    return spec, ini, prob
+
+
+def test_full_step_dealiased_carleman_matches_oracle(ctx):
+    """FP64, 1030 cells (two collision calls of 1024 + 6 cells), the de-aliased
+    Carleman form from the shifted grids."""
+    nx, dt = 1030, 0.5 * (60.0 / 1030) / 20.97
+    spec, ini, prob = _mach38_case(nx)
+    F = ini["f0"]
+    Fref, eref = dlr.full_step(F, prob, dt)
+    vg = blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN | blr.BLR_DEALIAS)
+    pb = ctx.make_problem(vg, nx, -30.0, 30.0, torch.tensor(ini["fL"], device="cuda"),
+                          torch.tensor(ini["fR"], device="cuda"))
+    Fd = torch.tensor(F, device="cuda")
+    e = ctx.full_step(pb, Fd, dt, blr.BLR_FP64)
+    rel = np.linalg.norm((Fd.cpu().numpy() - F) - (Fref - F)) / np.linalg.norm(Fref - F)
+    print(f"dealiased carleman full step: rel {rel:.2e}, err {e:.12e} vs {eref:.12e}", flush=True)
+    assert rel < 1e-12
+    assert abs(e - eref) < 1e-12 * eref
+
+
+@pytest.mark.parametrize("prec", [blr.BLR_FP32, blr.BLR_FP64])
+def test_full_step_graph_replays_equal_direct_issue(prec):
+    """The step is recorded as a graph on its second call and replayed from the
+    third: six steps with graphs against six steps issued directly (kernel
+    timing on, which turns recording off), bitwise, with the program's own
+    device work and synchronisations between the steps."""
+    nx, dt = 80, 0.5 * (60.0 / 80) / 20.97
+    spec, ini, _ = _mach38_case(nx, seed=9)
+    vg = blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN | blr.BLR_DEALIAS)
+    out = []
+    for timed in (True, False):
+        c = blr.Context(0)
+        c.lib.blr_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        assert c.lib.blr_timing(c.h, 1 if timed else 0) == 0
+        pb = c.make_problem(vg, nx, -30.0, 30.0, torch.tensor(ini["fL"], device="cuda"),
+                            torch.tensor(ini["fR"], device="cuda"))
+        Fd = torch.tensor(ini["f0"], device="cuda")
+        hist = []
+        for k in range(6):
+            e = c.full_step(pb, Fd, dt, prec)
+            junk = torch.randn(4096, device="cuda").sum()   # eager work in between
+            torch.cuda.synchronize()
+            hist.append((e, Fd.cpu().numpy().copy(), float(junk)))
+        c.close()
+        out.append(hist)
+    for k, ((ea, Fa, _), (eb, Fb, _)) in enumerate(zip(*out)):
+        print(f"step {k}: err {ea:.6e} / {eb:.6e}, max |dF| {np.abs(Fa - Fb).max():.1e}", flush=True)
+        assert ea == eb
+        assert np.array_equal(Fa, Fb)
