@@ -63,15 +63,17 @@ def parse():
     ap.add_argument("--no-carleman", action="store_true",
                     help="skip the Carleman-form measurement")
     ap.add_argument("--paper-shock", action="store_true",
-                    help="also solve the paper's Mach-1.4 shock shape (2D velocity, 32^2 on "
-                         "[-13.11, 13.11]^2, N_x = 1000) to steady state by the low-rank and the "
-                         "full-tensor method (about two minutes)")
+                    help="also solve the paper's normal shock (2D velocity, 32^2, N_x = 1000; "
+                         "Mach from --paper-shock-mach) to steady state by the low-rank and the "
+                         "full-tensor method (minutes)")
     ap.add_argument("--paper-tol", type=float, default=1e-6)
     ap.add_argument("--paper-shock-mach", type=float, default=1.4,
                     help="Mach number of --paper-shock: 1.4 (L_v = 13.11) or 3.8 (L_v = 20.97), "
                          "the paper's 32^2 shapes")
     ap.add_argument("--paper-shock-lv", type=float, default=13.11,
                     help="velocity half width for another Mach number")
+    ap.add_argument("--paper-dealias", action="store_true",
+                    help="de-aliased collision products in --paper-shock (always at Mach >= 3)")
     ap.add_argument("--paper-fourier", action="store_true",
                     help="also solve the paper's Fourier flow (diffusive walls at T = 1 and 1.2, "
                          "N_x = 200, 2D velocity 32^2) to err <= --fourier-tol by the low-rank "
@@ -298,10 +300,11 @@ def carleman_leg(args, blr, synth, torch, ctx, lib, spec, V, X, S, ini, nx, r, r
 
 
 def paper_shock_leg(args, blr, synth, torch, ctx):
-    """The normal shock of Sec. 5.2 at the paper's Mach-1.4 shape: d = 2,
-    Maxwell molecules B = 1/(2 pi) with the Carleman form (8 directions),
-    N_v = 32^2 on [-13.11, 13.11]^2, N_x = 1000 on [-30, 30], the tanh
-    initial profile (alpha = 0.5) without perturbation, dt = dx / (2 L_v).
+    """The normal shock of Sec. 5.2 at the paper's shapes: d = 2, Maxwell
+    molecules B = 1/(2 pi) with the Carleman form (8 directions), N_v = 32^2
+    on [-L_v, L_v]^2 (L_v = 13.11 at Mach 1.4, 20.97 at Mach 3.8), N_x = 1000
+    on [-30, 30], the tanh initial profile (alpha = 0.5) without
+    perturbation, dt = dx / (2 L_v); de-aliased products at Mach >= 3.
     Both methods run to err <= tol (err_ada for the low-rank method, adaptive
     with c = 0.2; err_full for the full tensor); the macroscopic profiles of
     the two steady states are compared, and the density with the Mott-Smith
@@ -310,12 +313,17 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
     # the paper's box half widths: 13.11 (Mach 1.4), 20.97 (Mach 3.8) at 32^2
     mach, nx, N = args.paper_shock_mach, 1000, 32
     L = {1.4: 13.11, 3.8: 20.97}.get(round(mach, 2), args.paper_shock_lv)
+    # the circular products make the cold upstream Maxwellian of the strong
+    # shock (T = 1 on a grid of spacing 1.31) a growing mode of the discrete
+    # operator; the de-aliased (Galerkin) products do not
+    dealias = args.paper_dealias or mach >= 3.0
+    cflags = blr.BLR_CARLEMAN | (blr.BLR_DEALIAS if dealias else 0)
     dev = torch.device("cuda:0")
     spec = synth.VGridSpec(d=2, n=N, L=L, gamma=0.0, C=1 / (2 * math.pi), m_rho=1, m_sigma=8)
     ini = synth.shock_initial(mach, spec, nx, -30.0, 30.0, pert=0.0, pert_rank=0)
     dx, dv = 60.0 / nx, 2 * L / N
     dt = 0.5 * dx / L
-    vg = blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN)
+    vg = blr.vgrid_from_spec(spec, cflags)
     fL = torch.tensor(ini["fL"], device=dev)
     fR = torch.tensor(ini["fR"], device=dev)
     pb = ctx.make_problem(vg, nx, -30.0, 30.0, fL, fR)
@@ -378,7 +386,7 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
     # Mott-Smith: alpha from the pair operator on (f_L, f_R), logistic profile
     # centred where the low-rank density crosses the mean of the end states
     Vb = torch.stack([fL, fR])
-    q = ctx.collision_pairs(blr.vgrid_from_spec(spec, blr.BLR_CARLEMAN | blr.BLR_NO_CONSERVE),
+    q = ctx.collision_pairs(blr.vgrid_from_spec(spec, cflags | blr.BLR_NO_CONSERVE),
                             Vb, [(0, 1)]).cpu().numpy()[0]
     alpha = float(2 * dv * dv * np.dot(v[0] ** 2, q))
     (rl, ul, Tl), (rr, ur, Tr) = ini["states"]
@@ -392,7 +400,8 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
     rho_ms = a * rl + (1 - a) * rr
     # thickness: max density slope of each profile, over the jump
     thick = lambda rr_: (rr - rl) / np.max(np.gradient(rr_, x))
-    return {"shape": f"Mach {mach}, d=2 Maxwell molecules (Carleman form, 8 directions), "
+    return {"shape": f"Mach {mach}, d=2 Maxwell molecules (Carleman form, 8 directions"
+                     f"{', de-aliased products' if dealias else ''}), "
                      f"N_v=32^2 on [-{L},{L}]^2, N_x=1000 on [-30,30], dt=dx/(2 L_v), tanh initial "
                      "profile, FP32 collisions",
             "tol": args.paper_tol,
