@@ -56,23 +56,51 @@ __device__ __forceinline__ void coords(int u, int w, int j, int& i0, int& i1, in
   }
 }
 
-// Re-deal lines from a stage along axis AF to a stage along axis AT.
+// Ordering of LDS accesses among the lanes of one wavefront (a wave's LDS
+// instructions execute in issue order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// An exchange between the stages along axes 1 and 2 stays inside one wave
+// when a wave holds whole rows i0 = u (N divides 64: 64 / N values of u per
+// wave): both sides then touch only the rows i0 of their own threads.
+template <int N, int AF, int AT>
+constexpr bool wave_local_exchange() {
+  return 64 % N == 0 && AF != 0 && AT != 0;
+}
+
+// Re-deal lines from a stage along axis AF to a stage along axis AT.  Across
+// waves: a workgroup barrier after the writes and after the reads (the next
+// exchange's writes).  Inside a wave: no workgroup barrier; the LDS rows
+// written are the wave's own, which no other wave reads or writes between
+// the workgroup barriers around them.
 template <int N, int AF, int AT>
 __device__ __forceinline__ void exchange(float (&v)[N], float* L, int u, int w) {
+  constexpr bool local = wave_local_exchange<N, AF, AT>();
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     int i0, i1, i2;
     coords<AF>(u, w, j, i0, i1, i2);
     L[(i0 * N + i1) * (N + 1) + i2] = v[j];
   }
-  __syncthreads();
+  if constexpr (local)
+    wave_lds_sync();
+  else
+    __syncthreads();
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     int i0, i1, i2;
     coords<AT>(u, w, j, i0, i1, i2);
     v[j] = L[(i0 * N + i1) * (N + 1) + i2];
   }
-  __syncthreads();
+  if constexpr (local)
+    wave_lds_sync();
+  else
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ shifts
@@ -388,7 +416,9 @@ __global__ __launch_bounds__(N * N) void k_pair_spec(const float* __restrict__ p
     const float* fb = two ? fa + nkk : fa;
     const float hb = two ? 0.5f : 0.f;
     // Z(-k) for k2 = 0..H-1 is the partner's element (N - j) % N: each thread
-    // publishes its elements 0 and N/2 .. N-1
+    // publishes its elements 0 and N/2 .. N-1 (rows that overlap other
+    // waves' rows of the wave-local exchange just done: wait for all waves)
+    if constexpr (wave_local_exchange<N, 1, 2>()) __syncthreads();
     float* row = L + t * XR;
     const float* prow = L + partner * XR;
     row[0] = re[0];
