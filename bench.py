@@ -157,9 +157,11 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol=1e-6):
+def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol=1e-6,
+              moments_of=()):
     """Serve the requests at their arrival times; latency = completion time -
-    arrival (submit) time on the server's clock."""
+    arrival (submit) time on the server's clock.  For the request indices in
+    moments_of, the steady rho, u_1, T per cell are returned as well."""
     dev = torch.device("cuda:0")
 
     def device_request(p):
@@ -227,7 +229,21 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
         sv.close()
     lat = [c.t_done - c.t_submit for c in comps]
     ok = [c for c in comps if c.status in (blr.BLR_OK, blr.BLR_ERR_NOT_CONVERGED)]
-    return {"slots": slots, "requests": len(comps), "step_cap": cap,
+    moments = {}
+    import numpy as np
+    for i in moments_of:
+        st = reqs[i][1]
+        X, S, V = (t.cpu().numpy() for t in st._keep)
+        r = st.r
+        F = (X[:r].T @ S[:r, :r]) @ V[:r]
+        sp = prepared[i]["spec"]
+        v = synth_vgrid(sp).reshape(sp.d, -1)
+        w = (2.0 * sp.L / sp.n) ** sp.d
+        rho = F.sum(axis=1) * w
+        u = (F * v[0]).sum(axis=1) * w / rho
+        e2 = (F * (v ** 2).sum(axis=0)).sum(axis=1) * w / rho
+        moments[i] = (rho, u, (e2 - u * u) / sp.d)
+    out = {"slots": slots, "requests": len(comps), "step_cap": cap,
             "latency_s_p50": round(pct(lat, 0.50), 4), "latency_s_p99": round(pct(lat, 0.99), 4),
             "queue_wait_s_p50": round(pct([c.t_admit - c.t_submit for c in comps], 0.5), 4),
             "wall_s": round(wall, 3), "solves_per_s": round(len(comps) / wall, 3),
@@ -237,6 +253,14 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
             "converged": sum(1 for c in comps if c.status == blr.BLR_OK),
             "failed": len(comps) - len(ok),
             "final_rank_range": [min(c.info.r for c in ok), max(c.info.r for c in ok)] if ok else None}
+    if moments_of:
+        return out, moments
+    return out
+
+
+def synth_vgrid(spec):
+    import synth
+    return synth.vgrid_points(spec.d, spec.n, spec.L)
 
 
 def carleman_leg(args, blr, synth, torch, ctx, lib, spec, V, X, S, ini, nx, r, r_cap, dt):
@@ -623,6 +647,7 @@ def serving_leg(args, blr, synth, torch, helper):
     """The serving trace on the batched FP32 path (slots solves at once) and on
     the plain FP64 per-pair path (one solve at a time, first in first out),
     then a longer trace on the batched path."""
+    import numpy as np
     base = dict(count=args.serve_count, seed=5, rate=4.0)
     trace = synth.serving_trace(**base)
     prepared = prepare_trace(trace, synth)
@@ -647,14 +672,20 @@ def serving_leg(args, blr, synth, torch, helper):
             f"first {nplain} of them")
         out["converged_batched_fp32"] = run_trace(blr, torch, helper, cp, args.serve_slots, False,
                                                   args.serve_conv_cap)
-        out["converged_plain_fp64_fifo"] = run_trace(blr, torch, helper, cp[:nplain], 1, True,
-                                                     args.serve_conv_cap)
         if nplain:
-            b = run_trace(blr, torch, helper, cp[:nplain], args.serve_slots, False,
-                          args.serve_conv_cap)
+            out["converged_plain_fp64_fifo"], m64 = run_trace(
+                blr, torch, helper, cp[:nplain], 1, True, args.serve_conv_cap, moments_of=(0,))
+            b, m32 = run_trace(blr, torch, helper, cp[:nplain], args.serve_slots, False,
+                               args.serve_conv_cap, moments_of=(0,))
             out["converged_batched_fp32_same_subset"] = b
             out["converged_plain_over_batched_latency_p50"] = round(
                 out["converged_plain_fp64_fifo"]["latency_s_p50"] / b["latency_s_p50"], 1)
+            # steady moments of the first request: FP32 collisions (batched) against
+            # FP64 collisions (plain), each run to its own err_ada <= 1e-6
+            out["converged_fp32_vs_fp64_steady_moments"] = {
+                nm: float(np.abs(a - c).max() / np.abs(c).max())
+                for nm, a, c in zip(("rho", "u1", "T"), m32[0], m64[0])}
+            out["converged_fp32_vs_fp64_steady_moments"]["target"] = 1e-6
     if args.serve_long_count > 0:
         long_trace = synth.serving_trace(count=args.serve_long_count, seed=5, rate=4.0)
         lp = prepare_trace(long_trace, synth)
