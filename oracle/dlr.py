@@ -395,7 +395,17 @@ class Problem2D:
     pairs for x_lo, x_hi, y_lo, y_hi: f is the boundary function of the face,
     one row per face cell (ny rows on the x faces, nx on the y faces) or one
     row for all; wall=True makes it the shape of a Maxwell diffusive wall's
-    Maxwellian (density rho_w per face cell from zero net mass flux)."""
+    Maxwellian (density rho_w per face cell from zero net mass flux).
+
+    Obstacle (Sec. 2.3 applied to the faces of solid cells inside the
+    rectangle): solid is a boolean array of nx * ny cells (or None) and
+    obstacle the shape of its walls' Maxwellian.  Solid cells hold no gas.
+    Every face between a gas cell and a solid neighbour is a Maxwell diffusive
+    wall whose outward normal (seen from the gas) points at the solid cell:
+    its ghost on the incoming half is rho_w times the obstacle's Maxwellian,
+    rho_w from zero net mass flux through that face, and the gas cell itself
+    on the outgoing half.  These faces are listed cell by cell (p ascending),
+    and within a cell in the order -x, +x, -y, +y of the solid neighbour."""
     vs: oc.VelocitySetup
     nx: int
     ny: int
@@ -406,6 +416,8 @@ class Problem2D:
     faces: list
     conserve: bool = True
     collision: object = None
+    solid: object = None
+    obstacle: object = None
 
     @property
     def dx(self):
@@ -443,6 +455,25 @@ class Problem2D:
         """(velocity axis, sign of the outward normal)."""
         return (0 if k < 2 else 1), (-1.0 if k % 2 == 0 else 1.0)
 
+    def solid_mask(self) -> np.ndarray:
+        if self.solid is None:
+            return np.zeros(self.nx * self.ny, dtype=bool)
+        return np.asarray(self.solid, dtype=bool).reshape(-1)
+
+    def obstacle_faces(self):
+        """[(gas cell p, k)] for every gas cell whose neighbour in direction k
+        (0: -x, 1: +x, 2: -y, 3: +y, the face's outward normal) is solid."""
+        sol = self.solid_mask()
+        out = []
+        for p in range(self.nx * self.ny):
+            if sol[p]:
+                continue
+            ix, iy = divmod(p, self.ny)
+            for k, (jx, jy) in enumerate(((ix - 1, iy), (ix + 1, iy), (ix, iy - 1), (ix, iy + 1))):
+                if 0 <= jx < self.nx and 0 <= jy < self.ny and sol[jx * self.ny + jy]:
+                    out.append((p, k))
+        return out
+
 
 def _face_rows(prob: Problem2D, k: int) -> np.ndarray:
     f = np.asarray(prob.faces[k][0], dtype=np.float64)
@@ -471,6 +502,27 @@ def _incoming(prob: Problem2D, k: int) -> np.ndarray:
     return sgn * prob.vel(axis) < 0
 
 
+def obstacle_boundary_row(prob: Problem2D, k: int, f_adj: np.ndarray) -> np.ndarray:
+    """rho_w M_obs on an obstacle face with outward normal k, rho_w from the
+    outgoing flux of the adjacent gas cell's f_adj (zero net mass flux)."""
+    axis, sgn = prob.face_normal(k)
+    vn = sgn * prob.vel(axis)
+    out = vn >= 0
+    M = np.asarray(prob.obstacle, dtype=np.float64)
+    return (-(f_adj[out] @ vn[out]) / (M[~out] @ vn[~out])) * M
+
+
+def obstacle_ghosts(K: np.ndarray, V: np.ndarray, prob: Problem2D):
+    """Ghost rows of K on every obstacle face (same formula as ghosts_2d)."""
+    out = []
+    for (p, k) in prob.obstacle_faces():
+        inc = _incoming(prob, k).astype(np.float64)
+        fb = obstacle_boundary_row(prob, k, K[p] @ V)
+        Mo = prob.dvd * (V * (1.0 - inc)) @ V.T
+        out.append(prob.dvd * (fb * inc) @ V.T + K[p] @ Mo)
+    return np.array(out).reshape(-1, K.shape[1])
+
+
 def ghosts_2d(K: np.ndarray, V: np.ndarray, prob: Problem2D):
     """Ghost rows of K on every face cell (eq. boundary general):
     K_j = <f_bdy 1_in, V_j>_v + sum_l K_l(adjacent cell) <1_out V_l V_j>_v."""
@@ -485,28 +537,35 @@ def ghosts_2d(K: np.ndarray, V: np.ndarray, prob: Problem2D):
     return out
 
 
-def _shift(K: np.ndarray, prob: Problem2D, axis: int, step: int, ghost: np.ndarray):
+def _shift(K: np.ndarray, prob: Problem2D, axis: int, step: int, ghost: np.ndarray, og=None):
     """K at the neighbour p + step e_axis of every cell, the face ghost where
-    that neighbour lies outside."""
+    that neighbour lies outside, the obstacle face's ghost (og, rows in the
+    order of obstacle_faces) where it is solid."""
     G = K.reshape(prob.nx, prob.ny, -1)
     sh = np.roll(G, -step, axis=axis).copy()
     if axis == 0:
         sh[-1 if step > 0 else 0, :, :] = ghost
     else:
         sh[:, -1 if step > 0 else 0, :] = ghost
-    return sh.reshape(K.shape)
+    sh = sh.reshape(K.shape)
+    if og is not None:
+        kk = 2 * axis + (1 if step > 0 else 0)
+        for b, (p, k) in enumerate(prob.obstacle_faces()):
+            if k == kk:
+                sh[p] = og[b]
+    return sh
 
 
-def d_plus_2d(K, g, prob, axis):
+def d_plus_2d(K, g, prob, axis, og=None):
     """(K_p - K_{p - e_axis}) / h_axis with the low face's ghost."""
     h = prob.dx if axis == 0 else prob.dy
-    return (K - _shift(K, prob, axis, -1, g[2 * axis])) / h
+    return (K - _shift(K, prob, axis, -1, g[2 * axis], og)) / h
 
 
-def d_minus_2d(K, g, prob, axis):
+def d_minus_2d(K, g, prob, axis, og=None):
     """(K_{p + e_axis} - K_p) / h_axis with the high face's ghost."""
     h = prob.dx if axis == 0 else prob.dy
-    return (_shift(K, prob, axis, 1, g[2 * axis + 1]) - K) / h
+    return (_shift(K, prob, axis, 1, g[2 * axis + 1], og) - K) / h
 
 
 def transport_matrices_2d(V, prob: Problem2D):
@@ -531,33 +590,38 @@ def ksl_step_2d(st: State, prob: Problem2D, dt: float, Qs=None):
     A = transport_matrices_2d(V, prob)
     Cj = collision_tensor(V, Qs, prob)
 
-    def transport_K(K):
-        g = ghosts_2d(K, V, prob)
-        return sum(d_plus_2d(K, g, prob, a) @ A[a][0].T + d_minus_2d(K, g, prob, a) @ A[a][1].T
-                   for a in range(2))
+    gas = (~prob.solid_mask()).astype(np.float64)[:, None]
 
-    # K-step
+    def gh(K):
+        return ghosts_2d(K, V, prob), obstacle_ghosts(K, V, prob)
+
+    def transport_K(K):
+        g, og = gh(K)
+        return sum(d_plus_2d(K, g, prob, a, og) @ A[a][0].T +
+                   d_minus_2d(K, g, prob, a, og) @ A[a][1].T for a in range(2))
+
+    # K-step (solid cells hold no gas)
     K = X @ S
-    K1 = K + dt * (-transport_K(K) + pair_products(K, pairs, wts) @ Cj.T)
+    K1 = gas * (K + dt * (-transport_K(K) + pair_products(K, pairs, wts) @ Cj.T))
     X1, S1 = weighted_qr_cols(K1, wx)
     # S-step
     Kn = X1 @ S1
-    g = ghosts_2d(Kn, V, prob)
+    g, og = gh(Kn)
     acc = np.zeros((r, r))
     for a in range(2):
-        acc += wx * X1.T @ d_plus_2d(Kn, g, prob, a) @ A[a][0].T
-        acc += wx * X1.T @ d_minus_2d(Kn, g, prob, a) @ A[a][1].T
+        acc += wx * X1.T @ d_plus_2d(Kn, g, prob, a, og) @ A[a][0].T
+        acc += wx * X1.T @ d_minus_2d(Kn, g, prob, a, og) @ A[a][1].T
     T = wx * X1.T @ pair_products(Kn, pairs, wts)
     S2 = S1 + dt * (acc - T @ Cj.T)
     # L-step
     L = S2 @ V
     Kt = X1 @ S2
-    g = ghosts_2d(Kt, V, prob)
+    g, og = gh(Kt)
     L1 = L + dt * (wx * X1.T @ pair_products(Kt, pairs, wts)) @ Qs
     for a in range(2):
         va = prob.vel(a)
-        L1 -= dt * (wx * X1.T @ d_plus_2d(Kt, g, prob, a) @ V) * np.maximum(va, 0.0)[None, :]
-        L1 -= dt * (wx * X1.T @ d_minus_2d(Kt, g, prob, a) @ V) * np.minimum(va, 0.0)[None, :]
+        L1 -= dt * (wx * X1.T @ d_plus_2d(Kt, g, prob, a, og) @ V) * np.maximum(va, 0.0)[None, :]
+        L1 -= dt * (wx * X1.T @ d_minus_2d(Kt, g, prob, a, og) @ V) * np.minimum(va, 0.0)[None, :]
     Vq, R = weighted_qr_cols(L1.T, dvd)
     # residual from the pieces (Sec. 5.1)
     dK, dS, dL = K1 - K, S2 - S1, L1 - L
@@ -572,13 +636,21 @@ def ksl_step_2d(st: State, prob: Problem2D, dt: float, Qs=None):
 
 def boundary_matrix_2d(st: State, prob: Problem2D):
     """F_b: one row f^b(x_b, .) per face cell of every face (a corner cell
-    once per face): the boundary function on the incoming half, the adjacent
-    cell on the outgoing half."""
+    once per face; zero for a solid face cell), then one per obstacle face:
+    the boundary function on the incoming half, the adjacent gas cell on the
+    outgoing half."""
     K = st.X @ st.S
     rows = []
+    sol = prob.solid_mask()
     for k in range(4):
-        Fa = K[prob.face_cells(k)] @ st.V
-        rows.append(np.where(_incoming(prob, k)[None, :], face_boundary_rows(prob, k, Fa), Fa))
+        cells = prob.face_cells(k)
+        Fa = K[cells] @ st.V
+        Fk = np.where(_incoming(prob, k)[None, :], face_boundary_rows(prob, k, Fa), Fa)
+        Fk[sol[cells]] = 0.0        # a solid face cell is no gas boundary: a zero row
+        rows.append(Fk)
+    for (p, k) in prob.obstacle_faces():
+        fa = K[p] @ st.V
+        rows.append(np.where(_incoming(prob, k), obstacle_boundary_row(prob, k, fa), fa)[None, :])
     return np.vstack(rows)
 
 
@@ -588,12 +660,14 @@ def full_step_2d(F: np.ndarray, prob: Problem2D, dt: float):
     boundary row (boundary function on the incoming half; the outgoing half
     multiplies a zero velocity part)."""
     g = [face_boundary_rows(prob, k, F[prob.face_cells(k)]) for k in range(4)]
+    og = np.array([obstacle_boundary_row(prob, k, F[p]) for (p, k) in prob.obstacle_faces()])
     Q, _ = evaluate_pairs(F, [(p, p) for p in range(F.shape[0])], prob)
     Fn = F + dt * Q
     for a in range(2):
         va = prob.vel(a)
-        Fn = Fn - dt * (np.maximum(va, 0.0) * d_plus_2d(F, g, prob, a)
-                        + np.minimum(va, 0.0) * d_minus_2d(F, g, prob, a))
+        Fn = Fn - dt * (np.maximum(va, 0.0) * d_plus_2d(F, g, prob, a, og if len(og) else None)
+                        + np.minimum(va, 0.0) * d_minus_2d(F, g, prob, a, og if len(og) else None))
+    Fn = Fn * (~prob.solid_mask()).astype(np.float64)[:, None]   # solid cells hold no gas
     err = math.sqrt(prob.wx * prob.dvd * float(((Fn - F) ** 2).sum()))
     return Fn, err
 
