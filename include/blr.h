@@ -209,14 +209,33 @@ typedef struct {
    * (these fields are ignored).  In two dimensions blr_full_step,
    * blr_dlr_step and blr_steady_solve run on the rectangle (the state's X
    * has rows of nx ny values; the rank is capped at nx ny); BLR_STEP_ADD
-   * takes one boundary row per face cell and needs 2 (nx + ny) <= 64, else
-   * BLR_ERR_UNSUPPORTED; steps there run eagerly (no recorded graph). */
+   * takes one boundary row per face cell and needs 2 (nx + ny) (plus the
+   * obstacle's faces, below) <= 64, else BLR_ERR_UNSUPPORTED; steps there
+   * run eagerly (no recorded graph). */
   int32_t ny;
   double y_lo, y_hi;
   const double* f_bottom;
   const double* f_top;
   int32_t wall_bottom, wall_top;
   int32_t face_rows;
+  /* Obstacle (two-dimensional space only; Sec. 2.3 on the faces of solid
+   * cells inside the rectangle).  solid: host array of nx ny bytes (cell
+   * ix ny + iy), nonzero = solid, or NULL for none; read at every call.
+   * f_obstacle: device, n^d doubles, the shape of the obstacle walls'
+   * Maxwellian (any positive multiple, positive somewhere on every incoming
+   * half); needed when solid marks a cell.  Solid cells hold no gas: steps
+   * set their rows to zero.  Every face between a gas cell and a solid
+   * neighbour is a Maxwell diffusive wall whose outward normal points from
+   * the gas cell to the solid one: on the incoming half its ghost is rho_w
+   * times f_obstacle with rho_w from zero net mass flux through that face,
+   * on the outgoing half the gas cell itself.  These faces are numbered after
+   * the 2 (nx + ny) face cells of the rectangle, gas cell by gas cell (cell
+   * index ascending), within a cell in the order -x, +x, -y, +y of the solid
+   * neighbour; a solid cell on the rectangle's edge gives a zero boundary
+   * row.  BLR_STEP_ADD takes one boundary row per face: 2 (nx + ny) + the
+   * obstacle's faces <= 64. */
+  const uint8_t* solid;
+  const double* f_obstacle;
 } blr_problem;
 
 /* Low-rank state f = sum_ij X_i S_ij V_j (eq. lowrank decomposition) with

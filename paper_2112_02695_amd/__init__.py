@@ -62,7 +62,8 @@ class Problem(ctypes.Structure):
                 ("ny", ctypes.c_int32), ("y_lo", ctypes.c_double), ("y_hi", ctypes.c_double),
                 ("f_bottom", ctypes.c_void_p), ("f_top", ctypes.c_void_p),
                 ("wall_bottom", ctypes.c_int32), ("wall_top", ctypes.c_int32),
-                ("face_rows", ctypes.c_int32)]
+                ("face_rows", ctypes.c_int32), ("solid", ctypes.c_void_p),
+                ("f_obstacle", ctypes.c_void_p)]
 
 
 class State(ctypes.Structure):
@@ -249,12 +250,14 @@ class Context:
         return pb
 
     def make_problem2d(self, vg: VGrid, nx: int, ny: int, x_lo: float, x_hi: float, y_lo: float,
-                       y_hi: float, faces) -> Problem:
+                       y_hi: float, faces, solid=None, obstacle=None) -> Problem:
         """Rectangle with nx x ny cells (cell ix ny + iy).  faces: four (f, wall)
         pairs for x_lo, x_hi, y_lo, y_hi; f a float64 CUDA tensor of n^d values
         (one row for the face) or (face cells, n^d) (one row per face cell:
         ny on an x face, nx on a y face); wall=True: a Maxwell diffusive wall
-        whose Maxwellian shape f is."""
+        whose Maxwellian shape f is.  solid: optional host array of nx ny
+        cells (nonzero = solid); obstacle: the float64 CUDA tensor of n^d
+        values giving the shape of the obstacle walls' Maxwellian."""
         assert len(faces) == 4
         rows = 0
         for k, (f, _) in enumerate(faces):
@@ -264,9 +267,21 @@ class Context:
                 rows |= 1 << k
         f = [ctypes.c_void_p(t.data_ptr()) for t, _ in faces]
         w = [int(bool(x)) for _, x in faces]
+        keep = [t for t, _ in faces]
+        sp, op = None, None
+        if solid is not None:
+            import numpy as np
+            sm = np.ascontiguousarray(np.asarray(solid).reshape(-1) != 0, dtype=np.uint8)
+            assert sm.size == nx * ny
+            keep.append(sm)
+            sp = ctypes.c_void_p(sm.ctypes.data)
+        if obstacle is not None:
+            assert obstacle.dtype.itemsize == 8 and obstacle.is_contiguous()
+            keep.append(obstacle)
+            op = ctypes.c_void_p(obstacle.data_ptr())
         pb = Problem(nx, float(x_lo), float(x_hi), f[0], f[1], vg, w[0], w[1], ny, float(y_lo),
-                     float(y_hi), f[2], f[3], w[2], w[3], rows)
-        pb._keep = tuple(t for t, _ in faces)
+                     float(y_hi), f[2], f[3], w[2], w[3], rows, sp, op)
+        pb._keep = tuple(keep)
         return pb
 
     def make_state(self, X, S, V, r: int, seed: int = 0) -> State:

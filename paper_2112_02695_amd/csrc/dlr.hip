@@ -18,6 +18,7 @@
 
 #include "collision_common.hpp"
 #include "linalg.hpp"
+#include "obstacle.hpp"
 #include "walls.hpp"
 
 namespace blr {
@@ -1241,20 +1242,39 @@ struct Face2 {
   int rows, wall;
   double sa, sd;
 };
+// classes 0..3: the rectangle's faces; 4 + k: obstacle faces of outward normal k
 struct Faces2 {
-  Face2 f[4];
+  Face2 f[8];
 };
 
-// Ghost rows of K on every face cell (eq. boundary general):
+// face b: class cls, the gas cell p next to it and its boundary-function row c
+__device__ __forceinline__ void face_at(int b, int nx, int ny, const Obs2& ob, int& cls, long& p,
+                                        int& c) {
+  if (b < ob.nface) {
+    int k;
+    face_of(b, nx, ny, k, c);
+    cls = k;
+    p = face_cell(k, c, nx, ny);
+  } else {
+    const int i = b - ob.nface;
+    p = ob.face[2 * i];
+    cls = 4 + ob.face[2 * i + 1];
+    c = 0;
+  }
+}
+
+// Ghost rows of K on every face (the rectangle's face cells, then the
+// obstacle's faces; eq. boundary general):
 //   G[b][j] = sum_l K_l(c) Mo_lj + (inflow: gin_jc; wall: rho_w(c) gin_jc).
-__global__ void k_ghosts2d(const double* __restrict__ K, int r, int nx, int ny, Faces2 fs,
+__global__ void k_ghosts2d(const double* __restrict__ K, int r, int nx, int ny, Faces2 fs, Obs2 ob,
                            double* __restrict__ G) {
   const int b = blockIdx.x, j = threadIdx.x;
   if (j >= r) return;
-  int k, c;
-  face_of(b, nx, ny, k, c);
-  const long nc = (long)nx * ny, p = face_cell(k, c, nx, ny);
-  const Face2& F = fs.f[k];
+  int cls, c;
+  long p;
+  face_at(b, nx, ny, ob, cls, p, c);
+  const long nc = (long)nx * ny;
+  const Face2& F = fs.f[cls];
   const int cr = F.rows > 1 ? c : 0;
   double g = 0.0;
   for (int l = 0; l < r; ++l) g += K[l * nc + p] * F.Mo[l * r + j];
@@ -1269,47 +1289,60 @@ __global__ void k_ghosts2d(const double* __restrict__ K, int r, int nx, int ny, 
 }
 
 // K_l at the neighbour p + step e_axis (step = -1 or 1), the face ghost where
-// that neighbour lies outside
+// that neighbour lies outside or is solid
 __device__ __forceinline__ double nb2(const double* K, const double* G, int r, int nx, int ny,
-                                      int l, long p, int axis, int step) {
+                                      int l, long p, int axis, int step, const Obs2& ob) {
   const long nc = (long)nx * ny;
   const int ix = (int)(p / ny), iy = (int)(p % ny);
   if (axis == 0) {
     const int i = ix + step;
-    if (i >= 0 && i < nx) return K[l * nc + p + (long)step * ny];
+    if (i >= 0 && i < nx) {
+      const int b = ob.towards(p, step < 0 ? 0 : 1);
+      return b >= 0 ? G[(long)b * r + l] : K[l * nc + p + (long)step * ny];
+    }
     return G[(long)(step < 0 ? iy : ny + iy) * r + l];
   }
   const int i = iy + step;
-  if (i >= 0 && i < ny) return K[l * nc + p + step];
+  if (i >= 0 && i < ny) {
+    const int b = ob.towards(p, step < 0 ? 2 : 3);
+    return b >= 0 ? G[(long)b * r + l] : K[l * nc + p + step];
+  }
   return G[(long)(step < 0 ? 2 * ny + ix : 2 * ny + nx + ix) * r + l];
 }
 
 // D^a_+- K_l at cell p, k = 0 D1+, 1 D1-, 2 D2+, 3 D2- (backward / forward
 // differences along x, then y)
 __device__ __forceinline__ double dk2(const double* K, const double* G, int r, int nx, int ny,
-                                      int l, long p, int k, double dx, double dy) {
+                                      int l, long p, int k, double dx, double dy, const Obs2& ob) {
   const double k0 = K[l * (long)nx * ny + p];
   const int axis = k >> 1;
   const double h = axis == 0 ? dx : dy;
-  return (k & 1) ? (nb2(K, G, r, nx, ny, l, p, axis, 1) - k0) / h
-                 : (k0 - nb2(K, G, r, nx, ny, l, p, axis, -1)) / h;
+  return (k & 1) ? (nb2(K, G, r, nx, ny, l, p, axis, 1, ob) - k0) / h
+                 : (k0 - nb2(K, G, r, nx, ny, l, p, axis, -1, ob)) / h;
 }
 
 // K-step on the rectangle: K1 = K + dt (-sum_k sum_l A_k[j][l] D_k K_l + sum_p
 // C_jp w_p K_m K_n), A = [A1+, A1-, A2+, A2-] (r x r each); dK = K1 - K.
+// Solid cells hold no gas: K1 = 0 there.
 __global__ void k_kstep2d(const double* __restrict__ K, const double* __restrict__ G, int r, int nx,
                           int ny, double dx, double dy, double dt, const double* __restrict__ A,
                           const double* __restrict__ C, int P, const int* __restrict__ pm,
-                          const int* __restrict__ pn, double* __restrict__ K1,
+                          const int* __restrict__ pn, Obs2 ob, double* __restrict__ K1,
                           double* __restrict__ dK) {
   const long nc = (long)nx * ny;
   const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (t >= r * nc) return;
   const int j = (int)(t / nc);
   const long p = t % nc;
+  if (ob.is_solid(p)) {
+    K1[t] = 0.0;
+    dK[t] = -K[t];
+    return;
+  }
   double rhs = 0.0;
   for (int l = 0; l < r; ++l)
-    for (int k = 0; k < 4; ++k) rhs -= A[(long)k * r * r + j * r + l] * dk2(K, G, r, nx, ny, l, p, k, dx, dy);
+    for (int k = 0; k < 4; ++k)
+      rhs -= A[(long)k * r * r + j * r + l] * dk2(K, G, r, nx, ny, l, p, k, dx, dy, ob);
   for (int q = 0; q < P; ++q) {
     const int m = pm[q], nn = pn[q];
     rhs += C[(long)j * P + q] * ((m == nn) ? 1.0 : 2.0) * K[m * nc + p] * K[nn * nc + p];
@@ -1326,8 +1359,8 @@ __global__ void k_kstep2d(const double* __restrict__ K, const double* __restrict
 __global__ __launch_bounds__(256) void k_xreduce2d(
     const double* __restrict__ X1, int r, int nx, int ny, double dx, double dy, double w,
     const double* __restrict__ K, const double* __restrict__ G, int P, const int* __restrict__ pm,
-    const int* __restrict__ pn, const double* __restrict__ Z, int nz, double* __restrict__ oD,
-    double* __restrict__ oT, double* __restrict__ oZ) {
+    const int* __restrict__ pn, const double* __restrict__ Z, int nz, Obs2 ob,
+    double* __restrict__ oD, double* __restrict__ oT, double* __restrict__ oZ) {
   const int lane = threadIdx.x & 63;
   const int ncols = 4 * r + P + nz;
   const long t = blockIdx.x * 4L + (threadIdx.x >> 6);
@@ -1338,7 +1371,7 @@ __global__ __launch_bounds__(256) void k_xreduce2d(
   for (long p = lane; p < nc; p += 64) {
     double y;
     if (c < 4 * r) {
-      y = dk2(K, G, r, nx, ny, c % r, p, c / r, dx, dy);
+      y = dk2(K, G, r, nx, ny, c % r, p, c / r, dx, dy, ob);
     } else if (c < 4 * r + P) {
       const int q = c - 4 * r, m = pm[q], nn = pn[q];
       y = ((m == nn) ? 1.0 : 2.0) * K[m * nc + p] * K[nn * nc + p];
@@ -1459,22 +1492,27 @@ struct FaceRows {
   }
 };
 
-// Boundary rows F_b of the augmentation on the rectangle, one per face cell
-// b (Sec. 3.1 with eq. boundary general): the face's boundary function on its
-// incoming half (a wall's shape, scaled by k_wall_rows2d), the adjacent
-// cell's sum_l K_l V_l on the outgoing half.
+// Boundary rows F_b of the augmentation on the rectangle, one per face b
+// (Sec. 3.1 with eq. boundary general): the face's boundary function on its
+// incoming half (a wall's shape, scaled by k_wall_rows2d), the adjacent gas
+// cell's sum_l K_l V_l on the outgoing half; zero for a solid face cell.
 __global__ void k_fb2d(const double* __restrict__ K, int r, int nx, int ny,
-                       const double* __restrict__ V, FaceRows fr, VGeo g, double* __restrict__ Fb) {
+                       const double* __restrict__ V, FaceRows fr, Obs2 ob, VGeo g,
+                       double* __restrict__ Fb) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
   if (q >= g.n) return;
-  int k, c;
-  face_of(b, nx, ny, k, c);
-  const long nc = (long)nx * ny, p = face_cell(k, c, nx, ny);
+  int cls, c;
+  long p;
+  face_at(b, nx, ny, ob, cls, p, c);
+  const int k = cls & 3;
+  const long nc = (long)nx * ny;
   const double va = k < 2 ? g.v1(q) : g.v2(q);
   const bool inc = (k % 2 == 0) ? va > 0 : va < 0;
   double val = 0.0;
-  if (inc) {
-    val = fr.row(k, c, g.n)[q];
+  if (cls < 4 && ob.is_solid(p)) {
+    val = 0.0;
+  } else if (inc) {
+    val = cls < 4 ? fr.row(k, c, g.n)[q] : ob.f[q];
   } else {
     for (int l = 0; l < r; ++l) val += K[l * nc + p] * V[(long)l * g.n + q];
   }
@@ -1484,13 +1522,15 @@ __global__ void k_fb2d(const double* __restrict__ K, int r, int nx, int ny,
 // Diffusive walls: scale the incoming half of each wall row of F_b by rho_w
 // from the row's own outgoing half.  One block per face cell.
 __global__ __launch_bounds__(1024) void k_wall_rows2d(double* __restrict__ Fb, FaceRows fr,
-                                                      int walls, int nx, int ny, VGeo g) {
-  int k, c;
-  face_of(blockIdx.x, nx, ny, k, c);
-  if (!((walls >> k) & 1)) return;
+                                                      int walls, int nx, int ny, Obs2 ob, VGeo g) {
+  int cls, c;
+  long p;
+  face_at(blockIdx.x, nx, ny, ob, cls, p, c);
+  const int k = cls & 3;
+  if (cls < 4 && (!((walls >> k) & 1) || ob.is_solid(p))) return;
   __shared__ double red[1024 / 64 + 1];
   double* row = Fb + (long)blockIdx.x * g.n;
-  const double* M = fr.row(k, c, g.n);
+  const double* M = cls < 4 ? fr.row(k, c, g.n) : ob.f;
   const int stride = k < 2 ? (g.d == 3 ? g.N * g.N : g.N) : (g.d == 3 ? g.N : 1);
   const double rho =
       wall::density_face<1024>((k % 2 == 0) ? -1.0 : 1.0, row, M, g.n, g.L, g.dv, stride, g.N, red);
@@ -2254,12 +2294,31 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   // the rank never exceeds the cell count (the X-side QR needs rows >= r)
   require(r_in <= nc, "state.r must not exceed nx * ny");
   const int r_max = (int)std::min<long>(std::min(sp->r_max > 0 ? sp->r_max : rc, rc), nc);
-  const int r_min = std::max(1, std::min(sp->r_min, r_max));
-  const bool add_on = (sp->flags & BLR_STEP_ADD) && r_in < r_max;
+  // (capped by the gas cells below, once the obstacle is known)
   const bool drop_on = (sp->flags & BLR_STEP_DROP) != 0;
   const int nface = 2 * (nx + ny);
+  // the obstacle: its faces follow the rectangle's (one ghost row and one
+  // boundary row each); solid cells hold no gas, so the rank is capped by
+  // the gas cells
+  const ObstacleHost oh = obstacle_host(pb);
+  require(!oh.any || pb->f_obstacle, "problem.solid marks a cell: f_obstacle is needed");
+  const int nft = nface + oh.nob;
+  long gas = nc;
+  for (uint8_t b : oh.solid) gas -= b;
+  require(gas >= 1, "problem.solid: no gas cell");
+  require(r_in <= gas, "state.r must not exceed the gas cells");
+  Obs2 ob{nullptr, nullptr, nullptr, pb->f_obstacle, nface, oh.nob};
+  if (oh.any) {
+    ob.face = (const int*)ctx->upload("d2.ob.face", oh.face.data(), oh.face.size() * sizeof(int));
+    ob.nbmap = (const int*)ctx->upload("d2.ob.nb", oh.nbmap.data(), oh.nbmap.size() * sizeof(int));
+    ob.solid = (const uint8_t*)ctx->upload("d2.ob.solid", oh.solid.data(), oh.solid.size());
+  }
+  const int r_max_g = (int)std::min<long>(r_max, gas);
+  const int r_min = std::max(1, std::min(sp->r_min, r_max_g));
+  const bool add_on = (sp->flags & BLR_STEP_ADD) && r_in < r_max_g;
   if (add_on)
-    require(nface <= 64, "two-dimensional space: the basis augmentation needs 2 (nx + ny) <= 64",
+    require(nft <= 64,
+            "two-dimensional space: the basis augmentation needs 2 (nx + ny) + obstacle faces <= 64",
             BLR_ERR_UNSUPPORTED);
   StepWork w{ctx, s, {h.L, h.dv, h.N, h.d, h.n}, (int)nc, n, wx, dvd};
   const dk::FaceRows fr{{pb->f_left, pb->f_right, pb->f_bottom, pb->f_top}, pb->face_rows};
@@ -2278,17 +2337,17 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   int lsw = rc, r = r_in, r_added = 0;
   if (add_on) {
     double* K = w.get("d2.K", (size_t)r * nc);
-    double* Fb = w.get("d2.Fb", (size_t)nface * n);
-    double* Rb = w.get("d2.Rb", (size_t)nface * nface);
-    double* Ub = w.get("d2.Ub", (size_t)nface * nface);
+    double* Fb = w.get("d2.Fb", (size_t)nft * n);
+    double* Rb = w.get("d2.Rb", (size_t)nft * nft);
+    double* Ub = w.get("d2.Ub", (size_t)nft * nft);
     hipLaunchKernelGGL(dk::k_xmul, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, st->X, r,
                        (int)nc, st->S, rc, K);
     BLR_CHECK_LAUNCH();
-    hipLaunchKernelGGL(dk::k_fb2d, dim3(blocks(n, 256), nface), dim3(256), 0, s, K, r, nx, ny,
-                       st->V, fr, w.g, Fb);
+    hipLaunchKernelGGL(dk::k_fb2d, dim3(blocks(n, 256), nft), dim3(256), 0, s, K, r, nx, ny,
+                       st->V, fr, ob, w.g, Fb);
     BLR_CHECK_LAUNCH();
-    if (walls) {
-      hipLaunchKernelGGL(dk::k_wall_rows2d, dim3(nface), dim3(1024), 0, s, Fb, fr, walls, nx, ny,
+    if (walls || oh.any) {
+      hipLaunchKernelGGL(dk::k_wall_rows2d, dim3(nft), dim3(1024), 0, s, Fb, fr, walls, nx, ny, ob,
                          w.g);
       BLR_CHECK_LAUNCH();
     }
@@ -2296,29 +2355,29 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     // information not yet in span V (rows projected onto V^perp; the same span
     // as the rows themselves when the cap does not bind)
     {
-      double* Cb = w.get("d2.Cb", (size_t)nface * r);
+      double* Cb = w.get("d2.Cb", (size_t)nft * r);
       GramJob gp;
-      gp.add(Fb, nface, st->V, r, false, dk::W_ONE, dvd, Cb);
+      gp.add(Fb, nft, st->V, r, false, dk::W_ONE, dvd, Cb);
       gp.run(w);
-      hipLaunchKernelGGL(dk::k_proj_rows, dim3(blocks(n, 256), nface), dim3(256), 0, s, Fb, nface,
+      hipLaunchKernelGGL(dk::k_proj_rows, dim3(blocks(n, 256), nft), dim3(256), 0, s, Fb, nft,
                          (long)n, Cb, r, st->V);
       BLR_CHECK_LAUNCH();
     }
     // F_b^T = Q Rb, F_b = Rb^T Q^T = Ub diag(sig) (Q Wb)^T; the small SVD on the host
-    tsqr(ctx, Fb, n, n, nface, nullptr, n, Rb, "qr2.fb", 1.0, 1.0);   // R only
+    tsqr(ctx, Fb, n, n, nft, nullptr, n, Rb, "qr2.fb", 1.0, 1.0);   // R only
     std::vector<double> sig, Uh, Wh;
     {
-      const std::vector<double> R = dev2host(Rb, (size_t)nface * nface);
-      std::vector<double> RT((size_t)nface * nface);
-      for (int i = 0; i < nface; ++i)
-        for (int j = 0; j < nface; ++j) RT[(size_t)i * nface + j] = R[(size_t)j * nface + i];
-      host_svd(nface, RT, Uh, sig, Wh);
+      const std::vector<double> R = dev2host(Rb, (size_t)nft * nft);
+      std::vector<double> RT((size_t)nft * nft);
+      for (int i = 0; i < nft; ++i)
+        for (int j = 0; j < nft; ++j) RT[(size_t)i * nft + j] = R[(size_t)j * nft + i];
+      host_svd(nft, RT, Uh, sig, Wh);
       BLR_HIP(hipMemcpyAsync(Ub, Uh.data(), Uh.size() * sizeof(double), hipMemcpyHostToDevice, s));
       BLR_HIP(hipStreamSynchronize(s));   // the host copy is read before it goes away
     }
     int rb = 0;
-    for (int i = 0; i < nface; ++i) rb += sig[i] > sp->add_tol;
-    rb = std::min(rb, r_max - r);
+    for (int i = 0; i < nft; ++i) rb += sig[i] > sp->add_tol;
+    rb = std::min(rb, r_max_g - r);
     if (rb > 0) {
       const int ra = r + rb;
       double* Vh = w.get("d2.Vh", (size_t)ra * n);
@@ -2328,8 +2387,8 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
       double* Xa = w.get("d2.Xa", (size_t)ra * nc);
       BLR_HIP(hipMemcpyAsync(Vh, st->V, (size_t)r * n * sizeof(double), hipMemcpyDeviceToDevice, s));
       // new rows U_b[:, :rb]^T F_b: the leading right singular vectors times sigma
-      hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), rb), dim3(256), 0, s, Fb, nface,
-                         (long)n, Ub, nface, rb, 1.0, Vh + (long)r * n, (long)n);
+      hipLaunchKernelGGL(dk::k_rows_comb, dim3(blocks(n, 256), rb), dim3(256), 0, s, Fb, nft,
+                         (long)n, Ub, nft, rb, 1.0, Vh + (long)r * n, (long)n);
       BLR_CHECK_LAUNCH();
       tsqr(ctx, Vh, n, n, ra, Vq, n, Rv, "qr2.va", std::sqrt(dvd), 1.0 / std::sqrt(dvd));
       hipLaunchKernelGGL(dk::k_saug, dim3(blocks((long)ra * ra, 256)), dim3(256), 0, s, st->S, rc,
@@ -2384,7 +2443,7 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   static const double sA[4] = {-1.0, 1.0, -1.0, 1.0}, sD[4] = {1.0, -1.0, 1.0, -1.0};
   static const int kT[4] = {dk::W_VPLUS, dk::W_VMINUS, dk::W_V2PLUS, dk::W_V2MINUS};
   double* ones = nullptr;
-  if (walls) {
+  if (walls || oh.any) {
     ones = w.get("d2.ones", (size_t)n);
     fill<double>(s, ones, n, 1.0);
   }
@@ -2421,10 +2480,30 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
       F.den = den;
     }
   }
+  // obstacle faces of outward normal k: the same outgoing-half Gram matrix,
+  // the obstacle's Maxwellian on the incoming half, always a diffusive wall
+  for (int k = 0; k < 4 && oh.any; ++k) {
+    const std::string tag = "d2.obst" + std::to_string(k);
+    double* gin = w.get((tag + ".gin").c_str(), (size_t)r);
+    double* a = w.get((tag + ".a").c_str(), (size_t)r);
+    double* den = w.get((tag + ".den").c_str(), 1);
+    add(Vw, r, pb->f_obstacle, 1, false, kIn[k], gin);
+    add(Vw, r, ones, 1, false, kA[k], a);
+    add(ones, 1, pb->f_obstacle, 1, false, kD[k], den);
+    dk::Face2& F = fs.f[4 + k];
+    F.Mo = Mo + (long)k * r * r;
+    F.gin = gin;
+    F.rows = 1;
+    F.wall = 1;
+    F.sa = sA[k];
+    F.sd = sD[k];
+    F.a = a;
+    F.den = den;
+  }
   gj.run(w);
-  double* G = w.get("d2.G", (size_t)nface * r);
+  double* G = w.get("d2.G", (size_t)nft * r);
   auto ghosts = [&](const double* Kx) {
-    hipLaunchKernelGGL(dk::k_ghosts2d, dim3(nface), dim3(64), 0, s, Kx, r, nx, ny, fs, G);
+    hipLaunchKernelGGL(dk::k_ghosts2d, dim3(nft), dim3(64), 0, s, Kx, r, nx, ny, fs, ob, G);
     BLR_CHECK_LAUNCH();
   };
   // ------------------------------------------------ K-step
@@ -2440,7 +2519,7 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   BLR_CHECK_LAUNCH();
   ghosts(K);
   hipLaunchKernelGGL(dk::k_kstep2d, dim3(blocks((long)r * nc, 256)), dim3(256), 0, s, K, G, r, nx,
-                     ny, dx, dy, dt, A, C, P, dpidx, dpidx + P, K1, dK);
+                     ny, dx, dy, dt, A, C, P, dpidx, dpidx + P, ob, K1, dK);
   BLR_CHECK_LAUNCH();
   tsqr(ctx, K1, nc, nc, r, X1, nc, S1, "qr2.k", std::sqrt(wx), 1.0 / std::sqrt(wx));
   const int nz = drop_on ? 2 * r : r;
@@ -2458,7 +2537,7 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   BLR_CHECK_LAUNCH();
   ghosts(K);
   hipLaunchKernelGGL(dk::k_xreduce2d, dim3(blocks((long)r * (4 * r + P + nz), 4)), dim3(256), 0, s,
-                     X1, r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, Z, nz, D, T, kz);
+                     X1, r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, Z, nz, ob, D, T, kz);
   BLR_CHECK_LAUNCH();
   hipLaunchKernelGGL(dk::k_supdate2d, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, S1, r, D, A,
                      T, C, P, dt, S2, dS);
@@ -2479,7 +2558,8 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   BLR_CHECK_LAUNCH();
   ghosts(K);
   hipLaunchKernelGGL(dk::k_xreduce2d, dim3(blocks((long)r * (4 * r + P), 4)), dim3(256), 0, s, X1,
-                     r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, nullptr, 0, Dt, Tt, nullptr);
+                     r, nx, ny, dx, dy, wx, K, G, P, dpidx, dpidx + P, nullptr, 0, ob, Dt, Tt,
+                     nullptr);
   BLR_CHECK_LAUNCH();
   if (fp64c)
     hipLaunchKernelGGL(dk::k_lstep2d<double>, dim3(blocks((long)r * n, 256)), dim3(256), 0, s, Vw,
@@ -2551,7 +2631,7 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     const double drop_tol = sp->c_drop * e;
     int keep = 0;
     for (int i = 0; i < r; ++i) keep += sh[i] >= drop_tol;
-    keep = std::max(std::min(std::min(keep, r_max), r), std::min(r_min, r));
+    keep = std::max(std::min(std::min(keep, r_max_g), r), std::min(r_min, r));
     // err_ada^2 = err^2 - |Sigma_p|^2 + 2 <f^n, D>,  D = X1 U_p Sigma_p W_p^T V1,
     // <f^n, D> = sum_kl S^n_kl (A M B^T)_kl, A_ki = <X^n_k, X1_i>, B_lj = <V^n_l, V1_j>
     std::vector<double> M(r * r, 0.0), AM(r * r, 0.0);

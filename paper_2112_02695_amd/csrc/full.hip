@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "collision_common.hpp"
+#include "obstacle.hpp"
 #include "walls.hpp"
 
 namespace blr {
@@ -85,14 +86,25 @@ struct Faces {
 };
 
 // rho of every face cell (x_lo: ny cells, x_hi: ny, y_lo: nx, y_hi: nx, in
-// that order): rho_w of a diffusive wall from the adjacent cell's
-// distribution (Sec. 2.3), 1 on an inflow face.  One block per face cell.
+// that order, then the obstacle's faces): rho_w of a diffusive wall from the
+// adjacent gas cell's distribution (Sec. 2.3), 1 on an inflow face.  One
+// block per face.
 __global__ __launch_bounds__(1024) void k_full_face_rho2d(const double* __restrict__ F, int nx,
                                                           int ny, int n, Faces fc, int walls,
-                                                          double L, double dv, int plane,
+                                                          Obs2 ob, double L, double dv, int plane,
                                                           int stride1, int N,
                                                           double* __restrict__ rho) {
   const int b = blockIdx.x;
+  __shared__ double red[1024 / 64 + 1];
+  if (b >= ob.nface) {
+    const int i = b - ob.nface;
+    const long cell = ob.face[2 * i];
+    const int k = ob.face[2 * i + 1];
+    const double v = wall::density_face<1024>((k % 2 == 0) ? -1.0 : 1.0, F + cell * n, ob.f, n, L,
+                                              dv, k < 2 ? plane : stride1, N, red);
+    if (threadIdx.x == 0) rho[b] = v;
+    return;
+  }
   int k, c;
   if (b < ny) {
     k = 0; c = b;
@@ -109,7 +121,10 @@ __global__ __launch_bounds__(1024) void k_full_face_rho2d(const double* __restri
   }
   const long cell = k == 0 ? c : k == 1 ? (long)(nx - 1) * ny + c : k == 2 ? (long)c * ny
                                                                          : (long)c * ny + ny - 1;
-  __shared__ double red[1024 / 64 + 1];
+  if (ob.is_solid(cell)) {    // no gas next to this face cell
+    if (threadIdx.x == 0) rho[b] = 0.0;
+    return;
+  }
   const double v = wall::density_face<1024>((k % 2 == 0) ? -1.0 : 1.0, F + cell * n,
                                             fc.row(k, c, n), n, L, dv, k < 2 ? plane : stride1,
                                             N, red);
@@ -119,11 +134,13 @@ __global__ __launch_bounds__(1024) void k_full_face_rho2d(const double* __restri
 // The update of k_full_update on the rectangle: cells p0 .. p0 + gridDim.y - 1
 // (p = ix ny + iy), upwind differences along x (v_1) and y (v_2), ghosts
 // rho f_face on the incoming half of a face (the cell itself elsewhere: that
-// half multiplies a zero velocity part).
+// half multiplies a zero velocity part), also where the neighbour is solid
+// (rho of that obstacle face times the obstacle's Maxwellian).  Solid cells
+// hold no gas: F_new = 0 there.
 template <typename TQ>
 __global__ __launch_bounds__(256) void k_full_update2d(const double* __restrict__ F, int nx,
                                                        int ny, int n, long p0,
-                                                       const TQ* __restrict__ Q, Faces fc,
+                                                       const TQ* __restrict__ Q, Faces fc, Obs2 ob,
                                                        const double* __restrict__ rho, double dt,
                                                        double dx, double dy, double L, double dv,
                                                        int plane, int stride1, int N,
@@ -140,16 +157,22 @@ __global__ __launch_bounds__(256) void k_full_update2d(const double* __restrict_
     const double* fp = F + p * n + q;
     const double f = fp[0];
     const long sx = (long)ny * n;
-    const double fxm = ix > 0 ? fp[-sx] : (v1 > 0 ? rho[iy] * fc.row(0, iy, n)[q] : f);
-    const double fxp = ix < nx - 1 ? fp[sx] : (v1 < 0 ? rho[ny + iy] * fc.row(1, iy, n)[q] : f);
-    const double fym = iy > 0 ? fp[-n] : (v2 > 0 ? rho[2 * ny + ix] * fc.row(2, ix, n)[q] : f);
-    const double fyp =
-        iy < ny - 1 ? fp[n] : (v2 < 0 ? rho[2 * ny + nx + ix] * fc.row(3, ix, n)[q] : f);
+    const int bxm = ob.towards(p, 0), bxp = ob.towards(p, 1);
+    const int bym = ob.towards(p, 2), byp = ob.towards(p, 3);
+    const double fxm = ix > 0 ? (bxm >= 0 ? (v1 > 0 ? rho[bxm] * ob.f[q] : f) : fp[-sx])
+                              : (v1 > 0 ? rho[iy] * fc.row(0, iy, n)[q] : f);
+    const double fxp = ix < nx - 1 ? (bxp >= 0 ? (v1 < 0 ? rho[bxp] * ob.f[q] : f) : fp[sx])
+                                   : (v1 < 0 ? rho[ny + iy] * fc.row(1, iy, n)[q] : f);
+    const double fym = iy > 0 ? (bym >= 0 ? (v2 > 0 ? rho[bym] * ob.f[q] : f) : fp[-n])
+                              : (v2 > 0 ? rho[2 * ny + ix] * fc.row(2, ix, n)[q] : f);
+    const double fyp = iy < ny - 1 ? (byp >= 0 ? (v2 < 0 ? rho[byp] * ob.f[q] : f) : fp[n])
+                                   : (v2 < 0 ? rho[2 * ny + nx + ix] * fc.row(3, ix, n)[q] : f);
     const double v1p = v1 > 0 ? v1 : 0.0, v1m = v1 < 0 ? v1 : 0.0;
     const double v2p = v2 > 0 ? v2 : 0.0, v2m = v2 < 0 ? v2 : 0.0;
-    const double d = -dt * ((v1p * (f - fxm) + v1m * (fxp - f)) / dx +
-                            (v2p * (f - fym) + v2m * (fyp - f)) / dy) +
-                     dt * (double)Q[(long)blockIdx.y * n + q];
+    const double d = ob.is_solid(p) ? -f
+                                    : -dt * ((v1p * (f - fxm) + v1m * (fxp - f)) / dx +
+                                             (v2p * (f - fym) + v2m * (fyp - f)) / dy) +
+                                          dt * (double)Q[(long)blockIdx.y * n + q];
     Fn[p * n + q] = f + d;
     e2 = d * d;
   }
@@ -232,15 +255,24 @@ static double* full_enqueue(blr_ctx ctx, const blr_problem* pb, int prec, double
   const unsigned nbx = nblocks(n, 256);
   double* part = (double*)ctx->buf("full.part", (size_t)ncells * nbx * sizeof(double));
   double* err = (double*)ctx->buf("full.err", sizeof(double));
+  // the obstacle (two-dimensional space): faces after the rectangle's
+  const ObstacleHost oh = two_d ? obstacle_host(pb) : ObstacleHost{};
+  require(!oh.any || pb->f_obstacle, "problem.solid marks a cell: f_obstacle is needed");
+  Obs2 ob{nullptr, nullptr, nullptr, pb->f_obstacle, two_d ? 2 * (nx + ny) : 2, oh.nob};
+  if (oh.any) {
+    ob.face = (const int*)ctx->upload("full.ob.face", oh.face.data(), oh.face.size() * sizeof(int));
+    ob.nbmap = (const int*)ctx->upload("full.ob.nb", oh.nbmap.data(), oh.nbmap.size() * sizeof(int));
+    ob.solid = (const uint8_t*)ctx->upload("full.ob.solid", oh.solid.data(), oh.solid.size());
+  }
   // rho_w from the cells next to the walls before any cell is updated
-  const int nrho = two_d ? 2 * (nx + ny) : 2;
+  const int nrho = two_d ? 2 * (nx + ny) + oh.nob : 2;
   double* rho = (double*)ctx->buf("full.rho", (size_t)nrho * sizeof(double));
   fk::Faces fc{{pb->f_left, pb->f_right, pb->f_bottom, pb->f_top}, pb->face_rows};
   if (two_d) {
     const int walls = pb->wall_left | (pb->wall_right << 1) | (pb->wall_bottom << 2) |
                       (pb->wall_top << 3);
     hipLaunchKernelGGL(fk::k_full_face_rho2d, dim3(nrho), dim3(1024), 0, s, F, nx, ny, n, fc,
-                       walls, h.L, h.dv, plane, stride1, h.N, rho);
+                       walls, ob, h.L, h.dv, plane, stride1, h.N, rho);
   } else {
     hipLaunchKernelGGL(fk::k_full_wall_rho, dim3(2), dim3(1024), 0, s, F, nx, n, pb->f_left,
                        pb->f_right, pb->wall_left, pb->wall_right, h.L, h.dv, plane, rho);
@@ -261,12 +293,12 @@ static double* full_enqueue(blr_ctx ctx, const blr_problem* pb, int prec, double
     if (two_d) {
       if (prec == BLR_FP32)
         hipLaunchKernelGGL(fk::k_full_update2d<float>, dim3(nbx, np), dim3(256), 0, s, F, nx, ny,
-                           n, p0, (const float*)Q, fc, rho, dt, dx, dy, h.L, h.dv, plane, stride1,
-                           h.N, Fn, part);
+                           n, p0, (const float*)Q, fc, ob, rho, dt, dx, dy, h.L, h.dv, plane,
+                           stride1, h.N, Fn, part);
       else
         hipLaunchKernelGGL(fk::k_full_update2d<double>, dim3(nbx, np), dim3(256), 0, s, F, nx, ny,
-                           n, p0, (const double*)Q, fc, rho, dt, dx, dy, h.L, h.dv, plane, stride1,
-                           h.N, Fn, part);
+                           n, p0, (const double*)Q, fc, ob, rho, dt, dx, dy, h.L, h.dv, plane,
+                           stride1, h.N, Fn, part);
     } else if (prec == BLR_FP32) {
       hipLaunchKernelGGL(fk::k_full_update<float>, dim3(nbx, np), dim3(256), 0, s, F, nx, n,
                          (int)p0, (const float*)Q, pb->f_left, pb->f_right, rho, dt, dx, h.L,
@@ -310,6 +342,10 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
   key.append((const char*)&F, sizeof(F));
   key.append((const char*)&dt, sizeof(dt));
   key.append((const char*)&prec, sizeof(prec));
+  if (pb->ny >= 2) {   // the mask's content (a host array read at every call)
+    const uint64_t oh = obstacle_host(pb).hash;
+    key.append((const char*)&oh, sizeof(oh));
+  }
   auto& gs = ctx->graphs;
   size_t gi = gs.size();
   for (size_t k = 0; k < gs.size(); ++k)
