@@ -79,6 +79,10 @@ def parse():
                          "N_x = 200, 2D velocity 32^2) to err <= --fourier-tol by the low-rank "
                          "and the full-tensor method (minutes)")
     ap.add_argument("--fourier-tol", type=float, default=2e-7)
+    ap.add_argument("--c4", action="store_true",
+                    help="also run the 2D-space x 3D-velocity adaptive workload with an obstacle at "
+                         "12 x 12 cells (24^3 velocity) by the low-rank and the full-tensor method")
+    ap.add_argument("--c4-steps", type=int, default=200)
     ap.add_argument("--paper-cavity", action="store_true",
                     help="also solve the paper's lid-driven cavity (all walls diffusive, lid "
                          "u_w = (1, 0)) on 16 x 16 cells, 2D velocity 32^2, by the low-rank and "
@@ -441,6 +445,104 @@ def paper_shock_leg(args, blr, synth, torch, ctx):
                            "density_max_rel_dev": float(np.abs(rho - rho_ms).max() / (rr - rl)),
                            "thickness_numerical": float(thick(rho)),
                            "thickness_mott_smith": float(thick(rho_ms))}}
+
+
+def c4_leg(args, blr, synth, torch, ctx):
+    """The 2D-space x 3D-velocity adaptive workload with an obstacle (the
+    rectangle of Sec. 2.2, the walls of Sec. 2.3 on the obstacle's faces) at
+    a reduced grid: [0, 1]^2 with 12 x 12 cells (the full 64 x 64 would need
+    256 boundary rows in the augmentation, which takes 64; here 2 (12 + 12)
+    + the obstacle's 12 faces = 60).  A square obstacle of 3 x 3 cells whose
+    lower-left cell is drawn from [4, 6]^2 (seed 4), its faces Maxwell
+    diffusive walls at T_w = 2; inflow Mach 2 on every outer face, (rho, u_1,
+    T) = (1, 2 sqrt(5/3), 1); 3D velocity 24^3 on [-8, 8]^3, hard spheres
+    (C = 1), M_rho = 16 x M_sigma = 38, FP32 collisions; the free stream at
+    rank 1 to start, adaptive with r_max = 30, c = 0.2; dt = 1/2 min(0.35 dx
+    / L_v, 1.5 / nu), nu = 4 pi C R rho_max with rho_max = 3.  The low-rank
+    method and the full tensor run the same number of steps; their
+    macroscopic fields are compared at the end."""
+    import numpy as np
+    nx = ny = 12
+    spec = synth.VGridSpec(d=3, n=24, L=8.0, gamma=1.0, C=1.0, m_rho=16, m_sigma=38)
+    rng = np.random.default_rng(4)
+    i0, j0 = (int(x) for x in rng.integers(4, 7, size=2))
+    solid = np.zeros((nx, ny), dtype=bool)
+    solid[i0:i0 + 3, j0:j0 + 3] = True
+    dev = torch.device("cuda:0")
+    v = synth.vgrid_points(3, spec.n, spec.L)
+    u_in = 2.0 * math.sqrt(5.0 / 3.0)
+    f_in = synth.maxwellian(v, 1.0, (u_in, 0.0, 0.0), 1.0).reshape(-1)
+    f_w = synth.maxwellian(v, 1.0, (0.0, 0.0, 0.0), 2.0).reshape(-1)
+    dx = 1.0 / nx
+    R = 4.0 * spec.L / (3.0 + math.sqrt(2.0))
+    dt = 0.5 * min(0.35 * dx / spec.L, 1.5 / (4.0 * math.pi * 1.0 * R * 3.0))
+    fin = torch.tensor(f_in, device=dev)
+    obs = torch.tensor(f_w, device=dev)
+    vg = blr.vgrid_from_spec(spec)
+    pb = ctx.make_problem2d(vg, nx, ny, 0.0, 1.0, 0.0, 1.0, [(fin, False)] * 4, solid=solid,
+                            obstacle=obs)
+    gas = ~solid.reshape(-1)
+    F0 = np.outer(gas.astype(np.float64), f_in)
+    vv = v.reshape(3, -1)
+    w = (2 * spec.L / spec.n) ** 3
+
+    def macro(F):
+        rho = F.sum(axis=1) * w
+        safe = np.where(rho > 0, rho, 1.0)
+        u1 = (F * vv[0]).sum(axis=1) * w / safe
+        e2 = (F * (vv ** 2).sum(axis=0)).sum(axis=1) * w / safe
+        return rho, u1, (e2 - u1 * u1) / 3.0
+
+    rc = 30
+    X, S, V = synth.lowrank_state(F0, 1, dx * dx, w)
+    Xd = torch.zeros((rc, nx * ny), dtype=torch.float64, device=dev)
+    Sd = torch.zeros((rc, rc), dtype=torch.float64, device=dev)
+    Vd = torch.zeros((rc, spec.npts), dtype=torch.float64, device=dev)
+    Xd[:1] = torch.tensor(X.T, device=dev)
+    Sd[:1, :1] = torch.tensor(S, device=dev)
+    Vd[:1] = torch.tensor(V, device=dev)
+    st = ctx.make_state(Xd, Sd, Vd, 1)
+    torch.cuda.synchronize()
+    sp = blr.StepParams(dt, 0.2, 1e-10, 1, rc, blr.BLR_STEP_ADD | blr.BLR_STEP_DROP)
+    nsteps = args.c4_steps
+    ranks, pairs, times = [], 0, []
+    progress(f"C4 reduced: {nsteps} low-rank steps (12 x 12 cells, 24^3, obstacle at {i0},{j0})")
+    t0 = time.perf_counter()
+    for k in range(nsteps):
+        ts = time.perf_counter()
+        info = ctx.dlr_step(pb, st, sp)
+        times.append(time.perf_counter() - ts)
+        rk = info.r_in + info.r_added
+        pairs += rk * (rk + 1) // 2
+        ranks.append(int(info.r_out))
+        if k % 50 == 0 or k == nsteps - 1:
+            progress(f"  step {k}: err_ada {info.err_ada:.3e}, rank {info.r_in}+{info.r_added}->"
+                     f"{info.r_out}")
+    t_lr = time.perf_counter() - t0
+    r = st.r
+    F_lr = (Xd[:r].cpu().numpy().T @ Sd[:r, :r].cpu().numpy()) @ Vd[:r].cpu().numpy()
+    progress(f"C4 reduced: {nsteps} full-tensor steps")
+    F = torch.tensor(F0, device=dev)
+    t0 = time.perf_counter()
+    for k in range(nsteps):
+        e = ctx.full_step(pb, F, dt, blr.BLR_FP32)
+    t_full = time.perf_counter() - t0
+    m_lr, m_full = macro(F_lr), macro(F.cpu().numpy())
+    diffs = {nm: float(np.abs(a[gas] - b[gas]).max() / np.abs(b[gas]).max())
+             for nm, a, b in zip(("rho", "u1", "T"), m_lr, m_full)}
+    times.sort()
+    return {"shape": f"[0,1]^2 with 12 x 12 cells, 3x3 obstacle at cells ({i0},{j0}) (diffusive wall "
+                     "T_w=2), inflow Mach 2 on every outer face, 3D velocity 24^3 on [-8,8]^3, hard "
+                     "spheres M_rho=16 x M_sigma=38, FP32 collisions, adaptive r_max=30, c=0.2",
+            "dt": dt, "steps": nsteps,
+            "low_rank": {"seconds": round(t_lr, 3), "ms_per_step": round(1e3 * t_lr / nsteps, 3),
+                         "step_ms_p50": round(1e3 * times[len(times) // 2], 3),
+                         "pair_evals": pairs, "pair_evals_per_s": round(pairs / t_lr, 1),
+                         "final_rank": int(r), "rank_max": max(ranks),
+                         "err_ada_last": info.err_ada},
+            "full_tensor": {"seconds": round(t_full, 3),
+                            "ms_per_step": round(1e3 * t_full / nsteps, 3), "err_full_last": e},
+            "low_rank_vs_full_max_rel_diff": diffs}
 
 
 def fourier_leg(args, blr, synth, torch, ctx):
@@ -1055,6 +1157,9 @@ def main():
     thermal = None
     if args.paper_thermal:
         thermal = cavity_leg(args, blr, synth, torch, ctx, "thermal")
+    c4 = None
+    if args.c4:
+        c4 = c4_leg(args, blr, synth, torch, ctx)
 
     serving = None
     if args.mode == "step" and not args.no_serve:
@@ -1099,6 +1204,7 @@ def main():
         "paper_fourier": fourier,
         "paper_cavity": cavity,
         "paper_thermal_cavity": thermal,
+        "c4_reduced": c4,
         "serving": serving,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
                     for t in sorted(timers, key=lambda t: -t["ms"])[:8]],
