@@ -214,3 +214,33 @@ def test_served_2d_solve_equals_the_direct_solve(ctx):
     assert c.status in (blr.BLR_OK, blr.BLR_ERR_NOT_CONVERGED), c.message
     assert c.info.steps == ia.steps == 5
     assert torch.equal(a.X, b.X) and torch.equal(a.S, b.S) and torch.equal(a.V, b.V)
+
+
+def test_adaptive_step_at_the_rank_cap_fp64(ctx):
+    """The regime of the lid-driven cavity's err_ada rise: rank 52 on 16 x 16
+    cells, all four walls diffusive with a moving lid, so the 64 boundary rows
+    (projected onto V^perp) offer far more directions than the room r_max - r
+    = 8.  One adaptive step with FP64 collisions against the oracle's: the
+    cap binds on both sides, ranks and counts identical, f, err and err_ada
+    to the adaptive bounds.  The input is a seeded rank-52 state of a
+    Maxwellian field plus smooth perturbations (16^2 velocity)."""
+    spec = _spec(2, 16, 4)
+    nx = ny = 16
+    wall = _maxw(spec, 1.0, (0.0, 0.0), 1.0)
+    lid = _maxw(spec, 1.0, (1.0, 0.0), 1.0)
+    faces = [(wall, True), (wall, True), (wall, True), (lid, True)]
+    prob = dlr.Problem2D(vs=oc.setup_from_spec(spec), nx=nx, ny=ny, x_lo=0.0, x_hi=0.5,
+                         y_lo=0.0, y_hi=0.5, faces=faces)
+    F0 = synth.rect_field(spec, nx, ny, seed=11, rank=60, pert=0.2)
+    st = dlr.initial_state(F0, 52, prob.wx, prob.dvd)
+    g = Gpu(ctx, spec, prob, st, r_cap=64)
+    flags = blr.BLR_STEP_FP64_COLLISION | blr.BLR_STEP_ADD | blr.BLR_STEP_DROP
+    info = ctx.dlr_step(g.pb, g.st, blr.StepParams(0.004, 0.2, 1e-10, 1, 60, flags))
+    new, oinfo = dlr.adaptive_step(st, prob, 0.004, c=0.2, r_max=60)
+    print("r", info.r_added, info.r_out, oinfo.r_added, oinfo.r_out, "err", info.err, oinfo.err,
+          "ada", info.err_ada, oinfo.err_ada, flush=True)
+    assert oinfo.r_added == 8 and info.r_added == 8
+    assert info.r_out == oinfo.r_out
+    assert abs(info.err - oinfo.err) < 1e-9 * oinfo.err
+    assert abs(info.err_ada - oinfo.err_ada) < 1e-9 * oinfo.err_ada
+    _check_adaptive_fp64(g.full(), new.full())
