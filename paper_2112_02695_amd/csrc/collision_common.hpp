@@ -1,6 +1,8 @@
 // Shared device helpers of the collision kernels.
 #pragma once
 
+#include <algorithm>
+#include <cstring>
 #include <utility>
 
 #include "fft.hpp"
@@ -59,8 +61,35 @@ struct PairPlan {
   bool generic_only = false;             // BLR_GENERIC_FFT: no fused kernels
 };
 
-std::vector<ReduceTile> plan_tiles(int rb, const std::vector<int>& li, const std::vector<int>& lj,
-                                   int G, bool& diag_only);
+// Tiles of the pair products: compact basis indices grouped by G; one tile per
+// (group, group) block that holds at least one requested pair.
+inline std::vector<ReduceTile> plan_tiles(int rb, const std::vector<int>& li, const std::vector<int>& lj,
+                                          int G, bool& diag_only) {
+  std::vector<ReduceTile> tiles;
+  const int ng = (rb + G - 1) / G;
+  diag_only = (ng == 1);
+  for (int g1 = 0; g1 < ng; ++g1)
+    for (int g2 = g1; g2 < ng; ++g2) {
+      ReduceTile t;
+      std::memset(&t, 0, sizeof(t));
+      for (int k = 0; k < 256; ++k) t.out[k] = -1;
+      t.ni = std::min(G, rb - g1 * G);
+      t.nj = std::min(G, rb - g2 * G);
+      for (int u = 0; u < t.ni; ++u) t.bi[u] = g1 * G + u;
+      for (int v = 0; v < t.nj; ++v) t.bj[v] = g2 * G + v;
+      bool any = false;
+      for (size_t p = 0; p < li.size(); ++p) {
+        int i = std::min(li[p], lj[p]), j = std::max(li[p], lj[p]);
+        if (i / G == g1 && j / G == g2) {
+          t.out[(i - g1 * G) * G + (j - g2 * G)] = (int)p;
+          any = true;
+        }
+      }
+      if (any) tiles.push_back(t);
+    }
+  return tiles;
+}
+
 template <typename T>
 void fill(hipStream_t s, T* p, long count, T v);
 void timed_begin(const std::string& name, double bytes, hipStream_t s);
