@@ -298,6 +298,19 @@ typedef struct {
   float ms_collision, ms_step;
 } blr_step_info;
 
+/* SVD of a small square FP64 matrix on the device: A = U diag(sig) W^T
+ * (trans != 0: of A^T).  The rank truncation of Sec. 3.2 factors the step's
+ * new S (r x r) with it, and the augmentation of Sec. 3.1 the R factor of the
+ * boundary rows.  A, U, W: device, r x r row-major; sig: device, r values,
+ * descending; all caller-owned, A not modified, outputs must not overlap A.
+ * One-sided Jacobi on one wavefront (columns of A rotated until every pair is
+ * orthogonal to rounding, at most 40 sweeps).  complete != 0: the columns of U
+ * whose sigma underflows (<= 1e-14 sigma_1) are completed to an orthonormal
+ * U; complete == 0: they are left as computed (zero where sigma is 0).
+ * 1 <= r <= 64, else BLR_ERR_ARG.  Asynchronous on the context's stream. */
+blr_status blr_svd_small(blr_ctx ctx, const double* A, int32_t r, int32_t trans, int32_t complete,
+                         double* U, double* sig, double* W);
+
 /* Truncated SVD of a full f0 (Sec. 2.4, first paragraph: the initial factors
  * are the truncated SVD of f at t = 0).  f0: device FP64, caller-owned, one
  * row of n^d values per cell (nx rows; nx ny on a rectangle, cell ix ny + iy),

@@ -135,6 +135,7 @@ def load_library(path: str = LIB_PATH):
     if hasattr(lib, "blr_dlr_step"):
         lib.blr_state_from_full.argtypes = [P, ctypes.POINTER(Problem), P, ctypes.c_int32,
                                             ctypes.POINTER(State)]
+        lib.blr_svd_small.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
         lib.blr_dlr_step.argtypes = [P, ctypes.POINTER(Problem), ctypes.POINTER(State),
                                      ctypes.POINTER(StepParams), ctypes.POINTER(StepInfo)]
         lib.blr_steady_solve.argtypes = [P, ctypes.POINTER(Problem), ctypes.POINTER(State),
@@ -292,6 +293,22 @@ class Context:
                    ctypes.c_void_p(V.data_ptr()), 0, seed)
         st._keep = (X, S, V)
         return st
+
+    def svd_small(self, A, trans: bool = False, complete: bool = True):
+        """A = U diag(sig) W^T (of A^T when trans) for a square float64 CUDA
+        tensor of at most 64 x 64; returns (U, sig, W) on the stream."""
+        import torch
+        assert A.is_cuda and A.dtype == torch.float64 and A.is_contiguous() and A.dim() == 2
+        r = A.shape[0]
+        assert A.shape[1] == r
+        U = torch.empty((r, r), dtype=torch.float64, device=A.device)
+        W = torch.empty((r, r), dtype=torch.float64, device=A.device)
+        sig = torch.empty((r,), dtype=torch.float64, device=A.device)
+        self._check(self.lib.blr_svd_small(self.h, ctypes.c_void_p(A.data_ptr()), r, int(bool(trans)),
+                                           int(bool(complete)), ctypes.c_void_p(U.data_ptr()),
+                                           ctypes.c_void_p(sig.data_ptr()),
+                                           ctypes.c_void_p(W.data_ptr())))
+        return U, sig, W
 
     def state_from_full(self, pb: Problem, f0, r: int, st: State):
         self._check(self.lib.blr_state_from_full(self.h, ctypes.byref(pb),

@@ -810,6 +810,25 @@ __global__ void k_pack(const double* res, const int* flag, const double* sb, con
   }
 }
 
+// Read-back record of the two-dimensional step: the residual, then (r > 0)
+// the singular values of the new S and the drop terms g.
+__global__ void k_pack2d(const double* err, const double* sg, const double* g, int r, double* out) {
+  const int t = threadIdx.x;
+  if (t == 0) out[0] = err[0];
+  for (int i = t; i < r; i += blockDim.x) {
+    out[1 + i] = sg[i];
+    out[1 + r + i] = g[i];
+  }
+}
+
+// dst[k][i] = src[i][off + k] (r x r, src leading dimension lds)
+__global__ void k_gather_T(const double* src, int lds, int off, int r, double* dst) {
+  const int t = threadIdx.x + blockIdx.x * blockDim.x;
+  if (t >= r * r) return;
+  const int k = t / r, i = t % r;
+  dst[t] = src[(long)i * lds + off + k];
+}
+
 // L-step on the FP64 matrix cores, for r <= 16: each wavefront takes 16
 // velocity points q0..q0+15 and forms the 16 x 16 tiles (rows i < 16)
 //   l = S2 V,  dp = Dp V,  dm = Dm V   (sum over m < r)
@@ -2195,69 +2214,6 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
 
 }  // namespace
 
-// A = U diag(s) W^T for a small m x m row-major A on the host, by one-sided
-// (Hestenes) Jacobi: plane rotations of the columns of A W until every pair
-// of columns is orthogonal to rounding; s descending, U's columns the
-// normalised rotated columns (zero where s = 0).  Used by the two-dimensional
-// step, whose augmentation and rank decision factor matrices of up to 64 x 64
-// once per step and read them back anyway.
-static void host_svd(int m, const std::vector<double>& A, std::vector<double>& U,
-                     std::vector<double>& sv, std::vector<double>& W) {
-  std::vector<double> a(A);
-  std::vector<double> w((size_t)m * m, 0.0);
-  for (int i = 0; i < m; ++i) w[(size_t)i * m + i] = 1.0;
-  for (int sweep = 0; sweep < 80; ++sweep) {
-    bool rotated = false;
-    for (int p = 0; p < m - 1; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = 0; i < m; ++i) {
-          const double x = a[(size_t)i * m + p], y = a[(size_t)i * m + q];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        if (ga == 0.0 || std::abs(ga) <= 1e-15 * std::sqrt(al * be)) continue;
-        rotated = true;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::abs(zeta) + std::sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
-        for (int i = 0; i < m; ++i) {
-          double& x = a[(size_t)i * m + p];
-          double& y = a[(size_t)i * m + q];
-          const double xp = c * x - sn * y, yq = sn * x + c * y;
-          x = xp;
-          y = yq;
-          double& u = w[(size_t)i * m + p];
-          double& v = w[(size_t)i * m + q];
-          const double up = c * u - sn * v, vq = sn * u + c * v;
-          u = up;
-          v = vq;
-        }
-      }
-    if (!rotated) break;
-  }
-  std::vector<double> nrm(m);
-  std::vector<int> ord(m);
-  for (int j = 0; j < m; ++j) {
-    double s2 = 0.0;
-    for (int i = 0; i < m; ++i) s2 += a[(size_t)i * m + j] * a[(size_t)i * m + j];
-    nrm[j] = std::sqrt(s2);
-    ord[j] = j;
-  }
-  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
-  U.assign((size_t)m * m, 0.0);
-  W.assign((size_t)m * m, 0.0);
-  sv.assign(m, 0.0);
-  for (int k = 0; k < m; ++k) {
-    const int j = ord[k];
-    sv[k] = nrm[j];
-    for (int i = 0; i < m; ++i) {
-      U[(size_t)i * m + k] = nrm[j] > 0.0 ? a[(size_t)i * m + j] / nrm[j] : 0.0;
-      W[(size_t)i * m + k] = w[(size_t)i * m + j];
-    }
-  }
-}
 
 // ----------------------------------------------------- two-dimensional space
 // One K -> S -> L step on the rectangle (Sec. 2.2 applied along both axes,
@@ -2363,18 +2319,13 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
                          (long)n, Cb, r, st->V);
       BLR_CHECK_LAUNCH();
     }
-    // F_b^T = Q Rb, F_b = Rb^T Q^T = Ub diag(sig) (Q Wb)^T; the small SVD on the host
+    // F_b^T = Q Rb, F_b = Rb^T Q^T = Ub diag(sig) (Q Wb)^T: the small SVD of
+    // Rb^T on the device, its singular values read back for the count
     tsqr(ctx, Fb, n, n, nft, nullptr, n, Rb, "qr2.fb", 1.0, 1.0);   // R only
-    std::vector<double> sig, Uh, Wh;
-    {
-      const std::vector<double> R = dev2host(Rb, (size_t)nft * nft);
-      std::vector<double> RT((size_t)nft * nft);
-      for (int i = 0; i < nft; ++i)
-        for (int j = 0; j < nft; ++j) RT[(size_t)i * nft + j] = R[(size_t)j * nft + i];
-      host_svd(nft, RT, Uh, sig, Wh);
-      BLR_HIP(hipMemcpyAsync(Ub, Uh.data(), Uh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      BLR_HIP(hipStreamSynchronize(s));   // the host copy is read before it goes away
-    }
+    double* sbd = w.get("d2.sb", (size_t)nft);
+    double* Wb = w.get("d2.Wb", (size_t)nft * nft);
+    svd_small(ctx, Rb, nft, Ub, sbd, Wb, true, false);   // only columns with sig > add_tol are used
+    const std::vector<double> sig = dev2host(sbd, (size_t)nft);
     int rb = 0;
     for (int i = 0; i < nft; ++i) rb += sig[i] > sp->add_tol;
     rb = std::min(rb, r_max_g - r);
@@ -2586,7 +2537,36 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   BLR_CHECK_LAUNCH();
   hipLaunchKernelGGL(dk::k_err2d, dim3(1), dim3(64), 0, s, part, nbp, dS, kx, lv, r, wx, dvd, err);
   BLR_CHECK_LAUNCH();
-  const double e = dev2host(err, 1)[0];
+  // drop ingredients on the device: the SVD of the new S = R^T and the terms
+  // g_c = sigma_c <A U_c, S^n B W_c> of <f^n, D> (A_ki = <X^n_k, X1_i>,
+  // B_lj = <V^n_l, V1_j>), read back with the residual in one record
+  double* U2 = nullptr;
+  double* s2 = nullptr;
+  double* W2 = nullptr;
+  double* gt = nullptr;
+  if (drop_on) {
+    U2 = w.get("d2.U2", (size_t)r * r);
+    s2 = w.get("d2.s2", (size_t)r);
+    W2 = w.get("d2.W2", (size_t)r * r);
+    svd_small(ctx, R, r, U2, s2, W2, true);
+    double* Sc = w.get("d2.Sc", (size_t)r * r);
+    double* Ac = w.get("d2.Ac", (size_t)r * r);
+    gt = w.get("d2.gt", (size_t)r);
+    hipLaunchKernelGGL(dk::k_copy_S, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, Sw, lsw, r,
+                       Sc, r);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_gather_T, dim3(blocks((long)r * r, 256)), dim3(256), 0, s, kz, nz, r, r,
+                       Ac);
+    BLR_CHECK_LAUNCH();
+    hipLaunchKernelGGL(dk::k_fnD_terms, dim3(1), dim3(256), 0, s, Sc, Ac, U2, s2, W2, Bv, r, gt);
+    BLR_CHECK_LAUNCH();
+  }
+  const int nrb = drop_on ? r : 0;
+  double* pk = w.get("d2.pack", (size_t)1 + 2 * 64);
+  hipLaunchKernelGGL(dk::k_pack2d, dim3(1), dim3(64), 0, s, err, s2, gt, nrb, pk);
+  BLR_CHECK_LAUNCH();
+  const std::vector<double> rec = dev2host(pk, (size_t)1 + 2 * nrb);
+  const double e = rec[0];
   require(std::isfinite(e), "two-dimensional step: non-finite residual", BLR_ERR_NUMERIC);
   blr_step_info inf{};
   inf.r_in = r_in;
@@ -2603,57 +2583,19 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     inf.r_out = r;
     st->r = r;
   } else {
-    double* U2 = w.get("d2.U2", (size_t)r * r);
-    double* s2 = w.get("d2.s2", (size_t)r);
-    double* W2 = w.get("d2.W2", (size_t)r * r);
-    // new S = R^T and its SVD on the host (uploaded for the commit kernels)
-    std::vector<double> Uh, sh, Wh;
-    {
-      const std::vector<double> Rh = dev2host(R, (size_t)r * r);
-      std::vector<double> Snh((size_t)r * r);
-      for (int i = 0; i < r; ++i)
-        for (int j = 0; j < r; ++j) Snh[(size_t)i * r + j] = Rh[(size_t)j * r + i];
-      host_svd(r, Snh, Uh, sh, Wh);
-      BLR_HIP(hipMemcpyAsync(U2, Uh.data(), Uh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      BLR_HIP(hipMemcpyAsync(W2, Wh.data(), Wh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      BLR_HIP(hipMemcpyAsync(s2, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      BLR_HIP(hipStreamSynchronize(s));
-    }
-    // small factors on the host: S^n (working), <X^n_k, X1_i>, <V^n_l, V1_j>
-    std::vector<double> Shn(r * r);
-    {
-      const std::vector<double> sw = dev2host(Sw, (size_t)(r - 1) * lsw + r);
-      for (int i = 0; i < r; ++i)
-        for (int j = 0; j < r; ++j) Shn[i * r + j] = sw[(size_t)i * lsw + j];
-    }
-    const std::vector<double> kzh = dev2host(kz, (size_t)r * nz);
-    const std::vector<double> Bh = dev2host(Bv, (size_t)r * r);
+    const double* sh = rec.data() + 1;
+    const double* g = rec.data() + 1 + r;
     const double drop_tol = sp->c_drop * e;
     int keep = 0;
     for (int i = 0; i < r; ++i) keep += sh[i] >= drop_tol;
     keep = std::max(std::min(std::min(keep, r_max_g), r), std::min(r_min, r));
-    // err_ada^2 = err^2 - |Sigma_p|^2 + 2 <f^n, D>,  D = X1 U_p Sigma_p W_p^T V1,
-    // <f^n, D> = sum_kl S^n_kl (A M B^T)_kl, A_ki = <X^n_k, X1_i>, B_lj = <V^n_l, V1_j>
-    std::vector<double> M(r * r, 0.0), AM(r * r, 0.0);
-    double sp2 = 0.0;
+    // err_ada^2 = err^2 - |Sigma_p|^2 + 2 <f^n, D>,  D = X1 U_p Sigma_p W_p^T V1:
+    // <f^n, D> is the sum of g_c over the dropped c
+    double sp2 = 0.0, fnD = 0.0;
     for (int c = keep; c < r; ++c) {
       sp2 += sh[c] * sh[c];
-      for (int i = 0; i < r; ++i)
-        for (int j = 0; j < r; ++j) M[i * r + j] += Uh[i * r + c] * sh[c] * Wh[j * r + c];
+      fnD += g[c];
     }
-    for (int k = 0; k < r; ++k)
-      for (int j = 0; j < r; ++j) {
-        double a = 0.0;
-        for (int i = 0; i < r; ++i) a += kzh[(size_t)i * nz + r + k] * M[i * r + j];
-        AM[k * r + j] = a;
-      }
-    double fnD = 0.0;
-    for (int k = 0; k < r; ++k)
-      for (int l = 0; l < r; ++l) {
-        double v = 0.0;
-        for (int j = 0; j < r; ++j) v += AM[k * r + j] * Bh[l * r + j];
-        fnD += Shn[k * r + l] * v;
-      }
     const double e2 = e * e - sp2 + 2.0 * fnD;
     inf.err_ada = std::sqrt(std::max(e2, 0.0));
     inf.drop_tol = drop_tol;
@@ -2933,6 +2875,14 @@ static blr_status guarded_dlr(blr_ctx ctx, F&& f) {
 }
 
 extern "C" {
+
+blr_status blr_svd_small(blr_ctx ctx, const double* A, int32_t r, int32_t trans, int32_t complete,
+                         double* U, double* sig, double* W) {
+  return guarded_dlr(ctx, [&] {
+    blr::require(A && U && sig && W, "null pointer argument");
+    blr::svd_small(ctx, A, r, U, sig, W, trans != 0, complete != 0);
+  });
+}
 
 blr_status blr_state_from_full(blr_ctx ctx, const blr_problem* pb, const double* f0, int32_t r,
                                blr_state* state) {

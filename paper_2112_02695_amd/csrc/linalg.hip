@@ -258,6 +258,114 @@ __device__ __forceinline__ double group_sum(double x, int lpp) {
   return x;
 }
 
+// Orders the LDS accesses of one wavefront (its DS instructions execute in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int SVS = 65;  // LDS column stride of the Jacobi SVD (doubles)
+
+// The end of the Jacobi SVD on one wavefront (lanes t < 64): column norms,
+// descending order (ties by index), the outputs, and U's completion.
+__device__ void svd_finish(const double* __restrict__ B, double* __restrict__ V,
+                           double* __restrict__ nrm, int* __restrict__ order, int r,
+                           double* __restrict__ U, double* __restrict__ sig,
+                           double* __restrict__ W, int complete, int t) {
+  if (t < r) {
+    double s = 0;
+    for (int i = 0; i < r; ++i) s += B[t * SVS + i] * B[t * SVS + i];
+    nrm[t] = sqrt(s);
+  }
+  wave_sync();
+  // descending, ties by index: column t goes to position rank(t)
+  if (t < r) {
+    const double mine = nrm[t];
+    int rank = 0;
+    for (int c = 0; c < r; ++c) {
+      const double o = nrm[c];
+      rank += (o > mine || (o == mine && c < t)) ? 1 : 0;
+    }
+    order[rank] = t;
+  }
+  wave_sync();
+  // U columns (normalised), W columns, sigma; row-major outputs.  The
+  // normalised columns also go to LDS (over V, once W is out) for the
+  // completion below.
+  double s_mine = 0.0;
+  int src = 0;
+  if (t < r) {
+    src = order[t];
+    s_mine = nrm[src];
+    sig[t] = s_mine;
+    const double inv = s_mine > 0 ? 1.0 / s_mine : 0.0;
+    for (int i = 0; i < r; ++i) {
+      U[i * r + t] = B[src * SVS + i] * inv;
+      W[i * r + t] = V[src * SVS + i];
+    }
+  }
+  // complete U where sigma underflows (tiny or zero columns): each such
+  // column j, in order, becomes the normalised part of a unit vector
+  // orthogonal to the other (non-small, or earlier completed) columns.  Lane
+  // i holds entry i of the candidate; the dot products are wavefront sums.
+  const double s0 = __shfl(s_mine, 0, 64);
+  const bool small = t < r && !(s_mine > 1e-300 && s_mine > 1e-14 * s0);
+  if (!complete || !__any(small)) return;
+  wave_sync();
+  if (t < r) {
+    const double inv = s_mine > 0 ? 1.0 / s_mine : 0.0;
+    for (int i = 0; i < r; ++i) V[t * SVS + i] = small ? 0.0 : B[src * SVS + i] * inv;
+    nrm[t] = small ? 0.0 : 1.0;  // 1: column t is in the basis
+  }
+  wave_sync();
+  auto wsum = [](double x) { return wave_allsum(x); };
+  // part of the unit vector e orthogonal to the basis columns other than j
+  // (two Gram-Schmidt passes); returns its norm
+  auto orth = [&](int e, int j, double& v) {
+    v = (t == e) ? 1.0 : 0.0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int k = 0; k < r; ++k) {
+        if (k == j || nrm[k] == 0.0) continue;
+        const double u = t < r ? V[k * SVS + t] : 0.0;
+        v -= wsum(u * v) * u;
+      }
+    return sqrt(wsum(v * v));
+  };
+  // candidates are tried from the one after the last accepted (the earlier
+  // unit vectors are mostly in the span already); the first with a part of
+  // norm > 1/2 is taken, else the one with the largest part (at least
+  // r^(-1/2): the parts' squared norms over all e sum to at least 1)
+  int e_next = 0;
+  for (int j = 0; j < r; ++j) {
+    if (nrm[j] != 0.0) continue;  // uniform: LDS read by every lane
+    double v = 0.0, nn = 0.0, best_nn = -1.0;
+    int e = 0, best_e = 0;
+    for (int att = 0; att < r; ++att) {
+      e = (e_next + att) % r;
+      nn = orth(e, j, v);
+      if (nn > 0.5) break;
+      if (nn > best_nn) {
+        best_nn = nn;
+        best_e = e;
+      }
+    }
+    if (!(nn > 0.5)) {
+      e = best_e;
+      nn = orth(e, j, v);
+    }
+    if (t < r) {
+      V[j * SVS + t] = v / nn;
+      U[t * r + j] = v / nn;
+    }
+    wave_sync();
+    if (t == 0) nrm[j] = 1.0;
+    wave_sync();
+    e_next = e + 1;
+  }
+}
+
 // One-sided Jacobi on the columns of B = A (r x r row-major): B W = U Sigma.
 // Columns live in LDS (stride 65 doubles: the column pairs of one round sit
 // in different banks).  Each round rotates rr/2 disjoint column pairs
@@ -266,22 +374,24 @@ __device__ __forceinline__ double group_sum(double x, int lpp) {
 // column sums are completed inside the group by DPP, so every lane of the
 // group computes the same rotation.  One wavefront: the rounds are ordered
 // by wavefront barriers.
-constexpr int SVS = 65;
 __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A, int r,
                                                    double* __restrict__ U, double* __restrict__ sig,
-                                                   double* __restrict__ W, int sweeps, int trans) {
+                                                   double* __restrict__ W, int sweeps, int trans,
+                                                   int complete) {
   __shared__ double B[64 * SVS];  // column c: B[c * SVS + i]
   __shared__ double V[64 * SVS];
   __shared__ double nrm[64];
   __shared__ int order[64];
   const int t = threadIdx.x;
   // all r^2 loads in flight at once (lane t: entries t, t + 64, ..)
+  double fro2 = 0.0;
   for (int e0 = 0; e0 < r * r; e0 += 64 * 8) {
     double v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int e = e0 + 64 * k + t;
       v[k] = e < r * r ? A[e] : 0.0;
+      fro2 += v[k] * v[k];
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -295,6 +405,17 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
     }
   }
   __syncthreads();
+  // |A|_F^2; a pair with a column of squared norm below (1e-15 |A|_F)^2 is
+  // not rotated.  Such a column ends among the zero singular values (below
+  // 1e-14 sigma_1, as sigma_1 >= |A|_F / 8), whose directions the rounding of
+  // the other columns' sums keeps turning without end; the other column of
+  // the pair would move by less than 1e-15 of its norm.
+  fro2 = wave_allsum(fro2);
+  const double tiny2 = 1e-30 * fro2;
+  // a pair counts as orthogonal once |cos| <= max(1e-15, 4.5e-16 sqrt(r)):
+  // the rounding of an r-term column sum of orthogonal columns alone reaches
+  // about sqrt(r) 1.1e-16, and a tighter test keeps rotating on it
+  const double tol2 = fmax(1e-30, 2e-31 * r);
   const int rr = (r % 2) ? r + 1 : r;
   const int np = rr / 2;
   const int lpp = np <= 8 ? 8 : (np <= 16 ? 4 : 2);
@@ -331,7 +452,8 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
       al = group_sum(al, lpp);
       be = group_sum(be, lpp);
       ga = group_sum(ga, lpp);
-      if (live && fabs(ga) > 1e-300 && ga * ga > 1e-30 * (al * be)) {
+      if (live && al >= tiny2 && be >= tiny2 && fabs(ga) > 1e-300 &&
+          ga * ga > tol2 * (al * be)) {
         // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = tau / g2, written
         // without dividing by g2: t = sign(tau) g2 / (|tau| + sqrt(tau^2 + g2^2))
         const double tau = be - al, g2 = 2.0 * ga;
@@ -351,78 +473,93 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
     }
     if (!__any(rotated)) break;
   }
-  if (t < r) {
-    double s = 0;
-    for (int i = 0; i < r; ++i) s += B[t * SVS + i] * B[t * SVS + i];
-    nrm[t] = sqrt(s);
-  }
-  __syncthreads();
-  // descending, ties by index: column t goes to position rank(t)
-  if (t < r) {
-    const double mine = nrm[t];
-    int rank = 0;
-    for (int c = 0; c < r; ++c) {
-      const double o = nrm[c];
-      rank += (o > mine || (o == mine && c < t)) ? 1 : 0;
-    }
-    order[rank] = t;
-  }
-  __syncthreads();
-  // U columns (normalised), W columns, sigma; row-major outputs
-  double s_mine = 0.0;
-  if (t < r) {
-    const int src = order[t];
-    s_mine = nrm[src];
-    sig[t] = s_mine;
-    const double inv = s_mine > 0 ? 1.0 / s_mine : 0.0;
-    for (int i = 0; i < r; ++i) {
-      U[i * r + t] = B[src * SVS + i] * inv;
-      W[i * r + t] = V[src * SVS + i];
-    }
-  }
-  // complete U where sigma underflows (tiny or zero columns); rare
-  const double s0 = __shfl(s_mine, 0, 64);
-  const bool small = t < r && !(s_mine > 1e-300 && s_mine > 1e-14 * s0);
-  if (!__any(small)) return;
-  __syncthreads();
-  if (t == 0) {
-    const double tiny = 1e-300;
-    for (int j = 0; j < r; ++j) {
-      if (sig[j] > tiny && sig[j] > 1e-14 * sig[0]) continue;
-      for (int e = 0; e < r; ++e) {
-        double v[64];
-        for (int i = 0; i < r; ++i) v[i] = (i == e) ? 1.0 : 0.0;
-        for (int pass = 0; pass < 2; ++pass)
-          for (int k = 0; k < r; ++k) {
-            if (k == j) continue;
-            if (k > j && !(sig[k] > tiny && sig[k] > 1e-14 * sig[0])) continue;
-            double d = 0;
-            for (int i = 0; i < r; ++i) d += U[i * r + k] * v[i];
-            for (int i = 0; i < r; ++i) v[i] -= d * U[i * r + k];
-          }
-        double nn = 0;
-        for (int i = 0; i < r; ++i) nn += v[i] * v[i];
-        nn = sqrt(nn);
-        if (nn > 0.5) {
-          for (int i = 0; i < r; ++i) U[i * r + j] = v[i] / nn;
-          break;
-        }
-      }
-    }
-  }
+  svd_finish(B, V, nrm, order, r, U, sig, W, complete, t);
 }
 
+// The same Jacobi SVD for r > 16 on 16 wavefronts: each round's column pairs
+// are dealt to the wavefronts (pair slot k to wavefront k mod 16), a pair's
+// rows to the lanes (lane i holds row i), its three column sums are
+// wavefront sums; the rounds are ordered by workgroup barriers.  The same
+// circle-method pairing, rotation and stopping rule as k_svd_jacobi.
+__global__ __launch_bounds__(1024) void k_svd_jacobi_wide(const double* __restrict__ A, int r,
+                                                         double* __restrict__ U,
+                                                         double* __restrict__ sig,
+                                                         double* __restrict__ W, int sweeps,
+                                                         int trans, int complete) {
+  __shared__ double B[64 * SVS];  // column c: B[c * SVS + i]
+  __shared__ double V[64 * SVS];
+  __shared__ double nrm[64];
+  __shared__ int order[64];
+  __shared__ double part[16];
+  const int t = threadIdx.x, wv = t / 64, lane = t % 64;
+  auto wsum = [](double x) { return wave_allsum(x); };
+  double fro2 = 0.0;
+  for (int e = t; e < r * r; e += blockDim.x) {
+    const double v = A[e];
+    fro2 += v * v;
+    const int row = trans ? e % r : e / r, c = trans ? e / r : e % r;
+    B[c * SVS + row] = v;
+  }
+  for (int e = t; e < r * r; e += blockDim.x) {
+    const int row = e / r, c = e % r;
+    V[c * SVS + row] = (row == c) ? 1.0 : 0.0;
+  }
+  fro2 = wsum(fro2);
+  if (lane == 0) part[wv] = fro2;
+  __syncthreads();
+  fro2 = 0.0;
+  for (int k = 0; k < 16; ++k) fro2 += part[k];
+  const double tiny2 = 1e-30 * fro2;  // see k_svd_jacobi
+  const double tol2 = fmax(1e-30, 2e-31 * r);
+  const int rr = (r % 2) ? r + 1 : r;
+  const int np = rr / 2;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    int rotated = 0;
+    for (int round = 0; round < rr - 1; ++round) {
+      for (int slot = wv; slot < np; slot += 16) {
+        int p, q;
+        if (slot == 0) {
+          p = rr - 1;
+          q = round;
+        } else {
+          p = round + slot;
+          if (p >= rr - 1) p -= rr - 1;
+          q = round - slot;
+          if (q < 0) q += rr - 1;
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        if (q >= r) continue;  // the dummy column of an odd r
+        const double x = lane < r ? B[p * SVS + lane] : 0.0;
+        const double y = lane < r ? B[q * SVS + lane] : 0.0;
+        const double al = wsum(x * x), be = wsum(y * y), ga = wsum(x * y);
+        if (al >= tiny2 && be >= tiny2 && fabs(ga) > 1e-300 && ga * ga > tol2 * (al * be)) {
+          const double tau = be - al, g2 = 2.0 * ga;
+          const double tt = (tau >= 0 ? g2 : -g2) / (fabs(tau) + sqrt(tau * tau + g2 * g2));
+          const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
+          if (lane < r) {
+            B[p * SVS + lane] = c * x - sn * y;
+            B[q * SVS + lane] = sn * x + c * y;
+            const double vx = V[p * SVS + lane], vy = V[q * SVS + lane];
+            V[p * SVS + lane] = c * vx - sn * vy;
+            V[q * SVS + lane] = sn * vx + c * vy;
+          }
+          rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  if (wv == 0) svd_finish(B, V, nrm, order, r, U, sig, W, complete, lane);
+}
 
 // ------------------------------------------------------- Cholesky QR --
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Orders the LDS accesses of one wavefront (its DS instructions execute in
-// order; this keeps the compiler from moving them across).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Cholesky R^T R = G + shift I of the leading r x r block of G (16 x 16,
 // row-major, in LDS; overwritten), on one wavefront, in outer-product form:
@@ -850,10 +987,15 @@ void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q,
   }
 }
 
-void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W, bool trans) {
+void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W, bool trans,
+               bool complete) {
   require(r >= 1 && r <= 64, "svd: r must be in [1, 64]");
-  hipLaunchKernelGGL(la::k_svd_jacobi, dim3(1), dim3(64), 0, ctx->stream, A, r, U, sig, W, 40,
-                     trans ? 1 : 0);
+  if (r <= 16)
+    hipLaunchKernelGGL(la::k_svd_jacobi, dim3(1), dim3(64), 0, ctx->stream, A, r, U, sig, W, 40,
+                       trans ? 1 : 0, complete ? 1 : 0);
+  else
+    hipLaunchKernelGGL(la::k_svd_jacobi_wide, dim3(1), dim3(1024), 0, ctx->stream, A, r, U, sig, W,
+                       40, trans ? 1 : 0, complete ? 1 : 0);
   BLR_CHECK_LAUNCH();
 }
 

@@ -26,8 +26,9 @@ void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q,
             int* flag);
 
 // A = U diag(sig) W^T for an r x r row-major A (U, W row-major; sig descending).
-// trans: factor A^T (A is read transposed)
+// trans: factor A^T (A is read transposed).  complete: U's columns of
+// underflowing sigma are completed to an orthonormal U (else left zero).
 void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W,
-               bool trans = false);
+               bool trans = false, bool complete = true);
 
 }  // namespace blr
