@@ -162,7 +162,7 @@ def progress(msg):
 
 
 def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol=1e-6,
-              moments_of=()):
+              moments_of=(), batch=False):
     """Serve the requests at their arrival times; latency = completion time -
     arrival (submit) time on the server's clock.  For the request indices in
     moments_of, the steady rho, u_1, T per cell are returned as well."""
@@ -189,8 +189,11 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
         return blr.SolveParams(blr.StepParams(q["dt"], 0.2, 1e-10, 1, r_cap, flags), res_tol, steps)
 
     progress(f"serving trace: {len(prepared)} requests, {slots} slot(s), "
-             f"{'plain fp64' if plain else 'batched fp32'}, cap {cap} steps")
-    sv = blr.Server(0, slots=slots)
+             f"{'plain fp64' if plain else 'batched fp32'}"
+             f"{', collisions of all live solves in shared launches' if batch else ''}, "
+             f"cap {cap} steps")
+    sv = blr.Server(0, slots=slots, batch_collisions=batch)
+    bstats = (0, 0)
     try:
         # warm-up (untimed): every slot runs two steps of the largest-rank
         # request of each velocity grid (allocations, tables, recorded graphs)
@@ -229,6 +232,7 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
                     raise RuntimeError("serving trace made no progress")
                 comps += got
         wall = time.perf_counter() - t0
+        bstats = sv.batch_stats()
     finally:
         sv.close()
     lat = [c.t_done - c.t_submit for c in comps]
@@ -257,6 +261,10 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
             "converged": sum(1 for c in comps if c.status == blr.BLR_OK),
             "failed": len(comps) - len(ok),
             "final_rank_range": [min(c.info.r for c in ok), max(c.info.r for c in ok)] if ok else None}
+    if batch:
+        # the warm-up's batches included
+        out["collision_batches"] = bstats[0]
+        out["step_collisions_in_batches"] = bstats[1]
     if moments_of:
         return out, moments
     return out
@@ -754,12 +762,16 @@ def serving_leg(args, blr, synth, torch, helper):
     trace = synth.serving_trace(**base)
     prepared = prepare_trace(trace, synth)
     batched = run_trace(blr, torch, helper, prepared, args.serve_slots, False, args.serve_steps)
+    fused = run_trace(blr, torch, helper, prepared, args.serve_slots, False, args.serve_steps,
+                      batch=True)
     plain = run_trace(blr, torch, helper, prepared, 1, True, args.serve_steps)
     out = {"trace": (f"{args.serve_count} steady normal-shock solves, seed 5, Poisson arrivals 4/s, "
                      "Mach~U[1.2,3], N_x in {128,256,512}, N_v in {24^3 (L=8), 32^3 (L=10)}, "
                      "initial rank U{5..25}, r_max 30, hard spheres M_rho=16 x M_sigma=38, "
                      f"each to err_ada<=1e-6 or {args.serve_steps} steps"),
-           "batched_fp32": batched, "plain_fp64_fifo": plain,
+           "batched_fp32": batched,
+           "batched_fp32_shared_collision_launches": fused,
+           "plain_fp64_fifo": plain,
            "plain_over_batched_latency_p50": round(plain["latency_s_p50"] /
                                                    batched["latency_s_p50"], 1)}
     if args.serve_conv_count > 0:

@@ -399,6 +399,18 @@ typedef struct {
   int32_t slots;        /* solves on the device at once, 1..16 */
   int64_t hbm_budget;   /* bytes of device workspace the slots may hold;
                            <= 0: no limit */
+  int32_t batch_collisions; /* nonzero: the FP32 pair collisions of every live
+                           solve on the fused grids (3D velocity, n = 16, 24
+                           or 32, 38 directions, one-dimensional space) run
+                           together: each step hands its collisions in, and
+                           once every such live solve has, they run as one
+                           launch sequence over all their bases and pairs,
+                           recorded as a HIP graph per composition.  The steps
+                           themselves then run unrecorded.  A pair's result is
+                           the same in any batch, alone included; it can
+                           differ from an unbatched solve's in the last bits
+                           (the pair transforms group the radial nodes two by
+                           two).  0: each solve runs on its own. */
 } blr_server_params;
 
 typedef struct {
@@ -445,6 +457,10 @@ blr_status blr_server_load(blr_server sv, int64_t* queued, int64_t* running);
 /* Seconds since blr_server_create on the server's clock (the clock of the
  * completion times). */
 blr_status blr_server_clock(blr_server sv, double* t);
+
+/* With batch_collisions: the batches run so far and the step collisions
+ * (one per solve and step attempt) they held; both 0 otherwise. */
+blr_status blr_server_batch_stats(blr_server sv, int64_t* rounds, int64_t* jobs);
 
 /* Message of the last failed blr_server_submit (valid until the next one). */
 const char* blr_server_last_error(blr_server sv);

@@ -94,7 +94,8 @@ class SolveInfo(ctypes.Structure):
 
 
 class ServerParams(ctypes.Structure):
-    _fields_ = [("slots", ctypes.c_int32), ("hbm_budget", ctypes.c_int64)]
+    _fields_ = [("slots", ctypes.c_int32), ("hbm_budget", ctypes.c_int64),
+                ("batch_collisions", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -152,6 +153,8 @@ def load_library(path: str = LIB_PATH):
         lib.blr_server_load.argtypes = [P, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64)]
         lib.blr_server_clock.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+        lib.blr_server_batch_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int64)]
         lib.blr_server_last_error.argtypes = [P]
         lib.blr_server_destroy.argtypes = [P]
     for name in EXPORTS:
@@ -349,17 +352,29 @@ class Server:
     in, first out as slots and the device-memory budget allow.
 
     ``submit`` keeps the problem, the state and their tensors alive until the
-    request's completion has been returned by ``wait``."""
+    request's completion has been returned by ``wait``.  batch_collisions: the
+    FP32 pair collisions of all live solves on the fused grids run together,
+    one launch sequence per step (see blr_server_params)."""
 
-    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0):
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0,
+                 batch_collisions: bool = False):
         self.lib = load_library()
         h = ctypes.c_void_p()
-        rc = self.lib.blr_server_create(device, ctypes.byref(ServerParams(slots, hbm_budget)),
-                                        ctypes.byref(h))
+        rc = self.lib.blr_server_create(
+            device, ctypes.byref(ServerParams(slots, hbm_budget, int(bool(batch_collisions)))),
+            ctypes.byref(h))
         if rc != 0:
             raise BlrError(rc, "blr_server_create failed")
         self.h = h
         self._live = {}
+
+    def batch_stats(self):
+        """(batches run, step collisions they held) with batch_collisions."""
+        r, j = ctypes.c_int64(), ctypes.c_int64()
+        rc = self.lib.blr_server_batch_stats(self.h, ctypes.byref(r), ctypes.byref(j))
+        if rc != 0:
+            raise BlrError(rc, "blr_server_batch_stats failed")
+        return r.value, j.value
 
     def submit(self, pb: Problem, st: State, sp: SolveParams, tag: int):
         if tag in self._live:

@@ -919,6 +919,57 @@ void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, 
   collision_pairs_impl(ctx, vg, prec, V, r, pairs, npairs, Q);
 }
 
+bool fused_f32_grid(const blr_vgrid& vg) {
+  const int ms = vg.m_sigma ? vg.m_sigma : (vg.d == 2 ? 8 : 38);
+  return vg.d == 3 && (vg.n == 16 || vg.n == 24 || vg.n == 32) && ms == 38 && vg.aniso_n == 0 &&
+         !(vg.flags & (BLR_CARLEMAN | BLR_DEALIAS | BLR_GENERIC_FFT | BLR_PLAIN_SCHEDULE));
+}
+
+void collision_batch(blr_ctx ctx, const blr_vgrid& vg, const std::vector<BatchJob>& jobs) {
+  const HostTables& h = get_tables(ctx, vg, BLR_FP32).h;
+  const size_t n = h.n;
+  hipStream_t s = ctx->stream;
+  size_t j0 = 0;
+  while (j0 < jobs.size()) {
+    // the next jobs whose bases and pairs fit one launch sequence
+    size_t j1 = j0;
+    int rt = 0, pt = 0;
+    while (j1 < jobs.size()) {
+      const int r = jobs[j1].r, P = (int)jobs[j1].pairs.size() / 2;
+      require(r >= 1 && r <= 64 && P >= 1 && P <= 4096, "collision batch: job out of range");
+      if (j1 > j0 && (rt + r > 64 || pt + P > 4096)) break;
+      rt += r;
+      pt += P;
+      ++j1;
+    }
+    float* Vc = (float*)ctx->buf("bat.V", (size_t)rt * n * sizeof(float));
+    float* Qc = (float*)ctx->buf("bat.Q", (size_t)pt * n * sizeof(float));
+    std::vector<int32_t> pc;
+    pc.reserve(2 * (size_t)pt);
+    int roff = 0;
+    for (size_t j = j0; j < j1; ++j) {
+      const BatchJob& b = jobs[j];
+      BLR_HIP(hipMemcpyAsync(Vc + (size_t)roff * n, b.V, (size_t)b.r * n * sizeof(float),
+                             hipMemcpyDeviceToDevice, s));
+      for (size_t k = 0; k < b.pairs.size(); ++k) {
+        require(b.pairs[k] >= 0 && b.pairs[k] < b.r, "collision batch: pair index out of range");
+        pc.push_back(b.pairs[k] + roff);
+      }
+      roff += b.r;
+    }
+    collision_pairs(ctx, vg, BLR_FP32, Vc, rt, pc.data(), pt, Qc);
+    int poff = 0;
+    for (size_t j = j0; j < j1; ++j) {
+      const BatchJob& b = jobs[j];
+      const int P = (int)b.pairs.size() / 2;
+      BLR_HIP(hipMemcpyAsync(b.Q, Qc + (size_t)poff * n, (size_t)P * n * sizeof(float),
+                             hipMemcpyDeviceToDevice, s));
+      poff += P;
+    }
+    j0 = j1;
+  }
+}
+
 void collision_self(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int rows, void* Q) {
   require(rows >= 1 && rows <= kMaxSelfRows, "collision_self: rows out of range");
   std::vector<int32_t> pairs(2 * (size_t)rows);

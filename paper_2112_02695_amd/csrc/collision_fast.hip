@@ -623,6 +623,50 @@ __global__ __launch_bounds__(N * N) void k_final_fused(const float2* __restrict_
 }  // namespace fastk
 
 
+// Tile width of the sigma sums for a served batch: the candidates (the rule
+// of run_fast, 12, 8, 6) timed once on the call's own data when a shape is
+// first seen (not while a graph is recorded), the fastest kept per shape.
+// Every width computes each pair's sum with the same operations in the same
+// order, so the choice changes the time only, never a result.
+template <class F>
+static int tuned_tile_width(blr_ctx ctx, int N, int rb, const PairPlan& pl, int G0, F&& run) {
+  std::string key = std::to_string(N) + ":" + std::to_string(rb) + ":";
+  uint64_t hsh = 1469598103934665603ull;
+  for (size_t p = 0; p < pl.li.size(); ++p) {
+    hsh = (hsh ^ (uint64_t)(pl.li[p] * 131 + pl.lj[p])) * 1099511628211ull;
+  }
+  key += std::to_string(hsh);
+  auto it = ctx->tuned_tile.find(key);
+  if (it != ctx->tuned_tile.end()) return it->second;
+  if (ctx->capturing) return G0;
+  hipStream_t s = ctx->stream;
+  std::vector<int> cand{G0};
+  for (int g : {12, 8, 6})
+    if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
+  hipEvent_t e0, e1;
+  BLR_HIP(hipEventCreate(&e0));
+  BLR_HIP(hipEventCreate(&e1));
+  int best = G0;
+  float best_ms = 1e30f;
+  for (int g : cand) {
+    run(g);  // warm
+    BLR_HIP(hipEventRecord(e0, s));
+    run(g);
+    BLR_HIP(hipEventRecord(e1, s));
+    BLR_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BLR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tuned_tile[key] = best;
+  return best;
+}
+
 template <int N>
 static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const std::vector<int>& prow,
                      const float2* Vh, const float* Vp, const float* Lam, float* Q, bool conserve) {
@@ -640,7 +684,11 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
   // transforms (two nodes per transform); each extra group costs the final
   // kernel one more half-spectrum read
   int ga = 1;
-  {
+  if (ctx->batch_mode) {
+    // served batches: two nodes per transform whatever the pair count, so a
+    // pair's sums run in the same order alone and in any batch
+    ga = std::min(2, h.mrho);
+  } else {
     double best = 1e300;
     for (int g = 1; g <= h.mrho; ++g) {
       const int ngc = (h.mrho + g - 1) / g;
@@ -679,49 +727,56 @@ static void run_fast(blr_ctx ctx, const DevTables& tb, const PairPlan& pl, const
     // narrow as possible (a rank-10 basis is one 10-wide tile: no idle slots,
     // 120 VGPRs, four waves per SIMD)
     const int ngr = (rb + 11) / 12, per = (rb + ngr - 1) / ngr;
-    const int G = std::max(4, per);
-    bool diag_only = false;
-    auto tiles = plan_tiles(rb, pl.li, pl.lj, G, diag_only);
+    int G = std::max(4, per);
     BpArgs bpa{};
     for (int p = 0; p < h.nbp && p < kMaxBp; ++p) {
       bpa.off_b[p] = h.bp_b[p] * n;
       bpa.off_bb[p] = h.bp_bb[p] * n;
       bpa.w[p] = (float)(2.0 * h.wsig[h.bp_b[p]]);  // see k_reduce_all
     }
-    for (const auto& t : tiles) {
-      const bool diag = t.bi[0] == t.bj[0];
-      int nvalid = 0;
-      for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
-      const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
-      timed_begin("fast.reduce.g" + std::to_string(G),
-                  (double)h.mrho * n * (nload * h.nbp + nvalid) * sizeof(float), s);
-      const dim3 grid((n + 255) / 256, h.mrho);
-      auto launch = [&](auto Gc) {
-        constexpr int Gt = decltype(Gc)::value;
-        if (diag && h.nbp <= kMaxBp)
-          hipLaunchKernelGGL((k_reduce_diag<Gt>), grid, dim3(256), 0, s, Sh, Pa, t, bpa, n,
-                             h.mrho, h.msig, h.nbp, P);
-        else if (diag)
-          hipLaunchKernelGGL((k_reduce_all<Gt, true>), grid, dim3(256), 0, s, Sh, Pa, t,
-                             (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
-        else
-          hipLaunchKernelGGL((k_reduce_all<Gt, false>), grid, dim3(256), 0, s, Sh, Pa, t,
-                             (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, P);
-      };
-      switch (G) {
-        case 4: launch(std::integral_constant<int, 4>{}); break;
-        case 5: launch(std::integral_constant<int, 5>{}); break;
-        case 6: launch(std::integral_constant<int, 6>{}); break;
-        case 7: launch(std::integral_constant<int, 7>{}); break;
-        case 8: launch(std::integral_constant<int, 8>{}); break;
-        case 9: launch(std::integral_constant<int, 9>{}); break;
-        case 10: launch(std::integral_constant<int, 10>{}); break;
-        case 11: launch(std::integral_constant<int, 11>{}); break;
-        default: launch(std::integral_constant<int, 12>{}); break;
+    // every tile of width Gw over the requested pairs
+    auto reduce_all_tiles = [&](int Gw) {
+      bool diag_only = false;
+      const auto tiles = plan_tiles(rb, pl.li, pl.lj, Gw, diag_only);
+      for (const auto& t : tiles) {
+        const bool diag = t.bi[0] == t.bj[0];
+        int nvalid = 0;
+        for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
+        const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
+        timed_begin("fast.reduce.g" + std::to_string(Gw),
+                    (double)h.mrho * n * (nload * h.nbp + nvalid) * sizeof(float), s);
+        const dim3 grid((n + 255) / 256, h.mrho);
+        auto launch = [&](auto Gc) {
+          constexpr int Gt = decltype(Gc)::value;
+          if (diag && h.nbp <= kMaxBp)
+            hipLaunchKernelGGL((k_reduce_diag<Gt>), grid, dim3(256), 0, s, Sh, Pa, t, bpa, n,
+                               h.mrho, h.msig, h.nbp, P);
+          else if (diag)
+            hipLaunchKernelGGL((k_reduce_all<Gt, true>), grid, dim3(256), 0, s, Sh, Pa, t,
+                               (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp,
+                               P);
+          else
+            hipLaunchKernelGGL((k_reduce_all<Gt, false>), grid, dim3(256), 0, s, Sh, Pa, t,
+                               (const float*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp,
+                               P);
+        };
+        switch (Gw) {
+          case 4: launch(std::integral_constant<int, 4>{}); break;
+          case 5: launch(std::integral_constant<int, 5>{}); break;
+          case 6: launch(std::integral_constant<int, 6>{}); break;
+          case 7: launch(std::integral_constant<int, 7>{}); break;
+          case 8: launch(std::integral_constant<int, 8>{}); break;
+          case 9: launch(std::integral_constant<int, 9>{}); break;
+          case 10: launch(std::integral_constant<int, 10>{}); break;
+          case 11: launch(std::integral_constant<int, 11>{}); break;
+          default: launch(std::integral_constant<int, 12>{}); break;
+        }
+        BLR_CHECK_LAUNCH();
+        timed_end(s);
       }
-      BLR_CHECK_LAUNCH();
-      timed_end(s);
-    }
+    };
+    if (ctx->batch_mode) G = tuned_tile_width(ctx, N, rb, pl, G, reduce_all_tiles);
+    reduce_all_tiles(G);
   }
   // transforms of the pair products with the radial weights
   timed_begin("fast.pair_spec",

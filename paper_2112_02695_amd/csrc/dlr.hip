@@ -1838,7 +1838,10 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
                        (long)r * n, V32, pend_S, pend_r, Sw, pend_r);
     BLR_CHECK_LAUNCH();
     Qs = ctx->buf("dlr.Q32", (size_t)P * n * sizeof(float));
-    collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
+    if (ctx->collide_hook)
+      ctx->collide_hook->collide(ctx, pb->v, V32, r, pairs, (float*)Qs);
+    else
+      collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
   }
   if (rec_events) BLR_HIP(hipEventRecord(ctx->ev[2], s));
   o.timed_collision = rec_events;
@@ -2098,7 +2101,9 @@ std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_
 void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const blr_step_params* sp,
                   const HostTables& h, bool add, Attempt at, Outcome& o) {
   hipStream_t s = ctx->stream;
-  const bool graphs = !(sp->flags & BLR_STEP_EAGER) && !ctx->timer.on;
+  // (a step whose collisions are batched with other solves' runs directly:
+  // it waits on work outside its own stream)
+  const bool graphs = !(sp->flags & BLR_STEP_EAGER) && !ctx->timer.on && !ctx->collide_hook;
   auto eager = [&]() {
     step_enqueue(ctx, pb, st, sp, h, add, at, o, true);
     BLR_HIP(hipStreamSynchronize(s));

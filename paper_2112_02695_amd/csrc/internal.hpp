@@ -181,6 +181,21 @@ struct blr_ctx_t {
   std::unique_ptr<blr::DevTables> arena_tables;
   void* arena_slice(const std::string& name, size_t bytes);
 
+  // Served batches (blr_server with batch_collisions): the fused FP32 path
+  // fixes its radial-node grouping of the pair transforms (so a pair's result
+  // does not depend on how many pairs share the launch) and picks the
+  // sigma-sum tile width by timing the candidates once per shape.
+  bool batch_mode = false;
+  std::map<std::string, int> tuned_tile;
+  // When set, the FP32 collisions of a step go through this hook (a served
+  // solve's collisions batched with those of the other live solves).
+  struct CollideHook {
+    virtual void collide(blr_ctx ctx, const blr_vgrid& vg, const float* V, int r,
+                         const std::vector<int32_t>& pairs, float* Q) = 0;
+    virtual ~CollideHook() = default;
+  };
+  CollideHook* collide_hook = nullptr;
+
   void* buf(const std::string& name, size_t bytes);  // grow-only named workspace
   // copy a small host array to a named device buffer, asynchronously
   void* upload(const std::string& name, const void* host, size_t bytes);
@@ -200,6 +215,19 @@ void validate_vgrid(const blr_vgrid& vg);
 void collision_pairs(blr_ctx ctx, const blr_vgrid& vg, int prec, const void* V, int r,
                      const int32_t* pairs_dev, int npairs, void* Q);
 size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec);
+// The FP32 pair collisions of several bases on one velocity grid in shared
+// launches: the bases are laid side by side (at most 64 functions and 4096
+// pairs per launch sequence) and each job's rows copied back to its Q.
+struct BatchJob {
+  const float* V;
+  int r;
+  std::vector<int32_t> pairs;  // 2 P indices into the job's own basis
+  float* Q;                    // P rows of n
+};
+void collision_batch(blr_ctx ctx, const blr_vgrid& vg, const std::vector<BatchJob>& jobs);
+// the fused FP32 path takes this grid (3D, n in {16, 24, 32}, 38 directions,
+// the (rho, sigma) form with an isotropic kernel, no de-aliasing)
+bool fused_f32_grid(const blr_vgrid& vg);
 // Q_s(V_i, V_i) for the rows i = 0..rows-1 of V into the rows of Q (the
 // full-tensor step's cells): the pipeline of collision_pairs without its
 // 64-row limit, since a pair list of rows (i, i) needs no pair tiles.

@@ -8,7 +8,9 @@
 //
 // A solve in a slot is blr_steady_solve on that slot's context: the same
 // kernels in the same order as alone, with reductions of fixed order, so its
-// result does not depend on what runs beside it.
+// result does not depend on what runs beside it.  With batch_collisions the
+// FP32 pair collisions of all live solves on the fused grids run together
+// (Batcher below): per step, one launch sequence over all their bases.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -56,6 +58,223 @@ void copy_message(char* dst, size_t cap, const char* msg) {
   std::snprintf(dst, cap, "%s", msg ? msg : "");
 }
 
+// Collisions of the live solves in shared launches.  A solve that batches
+// (join) hands each step's FP32 pair collisions to collide() and waits.  When
+// every joined solve has handed in a step's collisions (or left), the thread
+// that completes the set runs them all: on the batcher's own context and
+// stream, after each solve's inputs are ready (an event on its stream), as
+// blr::collision_batch per velocity grid; every solve's stream then waits on
+// the end of the batch.  The batch's device work is recorded as a HIP graph
+// the second time a composition (grids, bases, pair lists, addresses) is
+// seen and replayed from then on.
+struct Batcher : blr_ctx_t::CollideHook {
+  struct Pending {
+    blr_vgrid vg{};
+    blr::BatchJob job;
+    hipEvent_t ready = nullptr;
+    bool done = false;
+    blr_status code = BLR_OK;
+    std::string err;
+  };
+  struct Graph {
+    std::string key;
+    int seen = 0;
+    uint64_t gen = 0;
+    hipGraphExec_t exec = nullptr;
+  };
+
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  int active = 0;
+  bool stopping = false;
+  std::vector<Pending*> pending;
+  std::map<blr_ctx, hipEvent_t> ready;  // one per solve context, reused every step
+  blr_ctx bctx = nullptr;
+  hipStream_t bstream = nullptr;
+  hipEvent_t done_ev = nullptr;
+  std::vector<Graph> graphs;
+  int64_t rounds = 0, jobs = 0;
+
+  ~Batcher() {
+    if (bstream) (void)hipStreamSynchronize(bstream);
+    for (auto& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (auto& kv : ready) (void)hipEventDestroy(kv.second);
+    if (done_ev) (void)hipEventDestroy(done_ev);
+    if (bctx) (void)blr_destroy(bctx);
+    if (bstream) (void)hipStreamDestroy(bstream);
+  }
+
+  void join() {
+    std::lock_guard<std::mutex> lk(mu);
+    ++active;
+  }
+  void leave() {
+    std::unique_lock<std::mutex> lk(mu);
+    --active;
+    if (!stopping && !pending.empty() && (int)pending.size() >= active) run_round(lk);
+  }
+  void stop() {
+    std::lock_guard<std::mutex> lk(mu);
+    stopping = true;
+    cv.notify_all();
+  }
+
+  void collide(blr_ctx ctx, const blr_vgrid& vg, const float* V, int r,
+               const std::vector<int32_t>& pairs, float* Q) override {
+    Pending p;
+    p.vg = vg;
+    p.job = blr::BatchJob{V, r, pairs, Q};
+    std::unique_lock<std::mutex> lk(mu);
+    if (stopping) throw blr::Error(BLR_ERR_ARG, "server stopping");
+    hipEvent_t& ev = ready[ctx];
+    if (!ev) BLR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    BLR_HIP(hipEventRecord(ev, ctx->stream));
+    p.ready = ev;
+    pending.push_back(&p);
+    if ((int)pending.size() >= active) run_round(lk);
+    // a job a round has taken is waited for to the end (the round holds it)
+    auto queued = [&] { return std::find(pending.begin(), pending.end(), &p) != pending.end(); };
+    cv.wait(lk, [&] { return p.done || (stopping && queued()); });
+    if (!p.done) {
+      // stopping before a round took the job: take it back out
+      pending.erase(std::remove(pending.begin(), pending.end(), &p), pending.end());
+      throw blr::Error(BLR_ERR_ARG, "server stopping");
+    }
+    if (p.code != BLR_OK) throw blr::Error(p.code, p.err);
+    BLR_HIP(hipStreamWaitEvent(ctx->stream, done_ev, 0));
+  }
+
+ private:
+  // Runs the pending jobs (mu held on entry and on return; released while the
+  // work is enqueued, when every joined solve is waiting in collide()).
+  void run_round(std::unique_lock<std::mutex>& lk) {
+    std::vector<Pending*> batch;
+    batch.swap(pending);
+    ++rounds;
+    jobs += (int64_t)batch.size();
+    lk.unlock();
+    blr_status code = BLR_OK;
+    std::string err;
+    try {
+      launch(batch);
+    } catch (const blr::Error& e) {
+      code = e.code;
+      err = e.what();
+    } catch (const std::exception& e) {
+      code = BLR_ERR_HIP;
+      err = e.what();
+    }
+    lk.lock();
+    for (Pending* p : batch) {
+      p->done = true;
+      p->code = code;
+      p->err = err;
+    }
+    cv.notify_all();
+  }
+
+  void enqueue(const std::vector<std::pair<blr_vgrid, std::vector<blr::BatchJob>>>& groups) {
+    for (const auto& g : groups) blr::collision_batch(bctx, g.first, g.second);
+  }
+
+  void launch(const std::vector<Pending*>& batch) {
+    if (!bctx) {
+      BLR_HIP(hipSetDevice(device));
+      BLR_HIP(hipStreamCreateWithFlags(&bstream, hipStreamNonBlocking));
+      BLR_HIP(hipEventCreateWithFlags(&done_ev, hipEventDisableTiming));
+      const blr_status rc = blr_create(device, bstream, &bctx);
+      if (rc != BLR_OK) throw blr::Error(rc, "server: batch context creation failed");
+      bctx->batch_mode = true;
+    }
+    // jobs grouped by velocity grid, in order of first appearance
+    std::vector<std::pair<blr_vgrid, std::vector<blr::BatchJob>>> groups;
+    std::string key;
+    for (Pending* p : batch) {
+      BLR_HIP(hipStreamWaitEvent(bstream, p->ready, 0));
+      size_t gi = groups.size();
+      for (size_t k = 0; k < groups.size(); ++k)
+        if (std::memcmp(&groups[k].first, &p->vg, sizeof(blr_vgrid)) == 0) gi = k;
+      if (gi == groups.size()) groups.push_back({p->vg, {}});
+      groups[gi].second.push_back(p->job);
+    }
+    for (const auto& g : groups) {
+      key.append((const char*)&g.first, sizeof(blr_vgrid));
+      for (const auto& j : g.second) {
+        key.append((const char*)&j.V, sizeof(j.V));
+        key.append((const char*)&j.Q, sizeof(j.Q));
+        key.append((const char*)&j.r, sizeof(j.r));
+        key.append((const char*)j.pairs.data(), j.pairs.size() * sizeof(int32_t));
+        key.push_back('|');
+      }
+    }
+    Graph* g = nullptr;
+    for (auto& x : graphs)
+      if (x.key == key) g = &x;
+    if (!g) {
+      if (graphs.size() >= 16) {
+        if (graphs.front().exec) (void)hipGraphExecDestroy(graphs.front().exec);
+        graphs.erase(graphs.begin());
+      }
+      graphs.push_back(Graph{key, 0, 0, nullptr});
+      g = &graphs.back();
+    }
+    if (g->exec && g->gen != bctx->buf_gen) {  // addresses moved
+      (void)hipGraphExecDestroy(g->exec);
+      g->exec = nullptr;
+      g->seen = 0;
+    }
+    if (!g->exec && g->seen >= 1) {
+      g->exec = record(groups);
+      g->gen = bctx->buf_gen;
+    }
+    if (g->exec) {
+      BLR_HIP(hipGraphLaunch(g->exec, bstream));
+    } else {
+      enqueue(groups);  // first sight, or not recordable: directly
+      g->seen = 1;
+      g->gen = bctx->buf_gen;
+    }
+    BLR_HIP(hipEventRecord(done_ev, bstream));
+  }
+
+  // The batch's work recorded on a capture stream (nullptr if it cannot be)
+  hipGraphExec_t record(const std::vector<std::pair<blr_vgrid, std::vector<blr::BatchJob>>>& groups) {
+    if (!bctx->cap_stream)
+      BLR_HIP(hipStreamCreateWithFlags(&bctx->cap_stream, hipStreamNonBlocking));
+    const uint64_t gen0 = bctx->buf_gen;
+    hipGraph_t graph = nullptr;
+    hipStream_t s = bctx->stream;
+    bctx->stream = bctx->cap_stream;
+    bctx->capturing = true;
+    bctx->capture_broken = false;
+    hipError_t e = hipStreamBeginCapture(bctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        enqueue(groups);
+      } catch (...) {
+        (void)hipStreamEndCapture(bctx->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph = nullptr;
+        e = hipErrorUnknown;
+      }
+      if (e == hipSuccess) e = hipStreamEndCapture(bctx->cap_stream, &graph);
+    }
+    bctx->stream = s;
+    bctx->capturing = false;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess && graph && !bctx->capture_broken && bctx->buf_gen == gen0)
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return exec;
+  }
+};
+
 }  // namespace
 
 struct blr_server_t {
@@ -70,6 +289,7 @@ struct blr_server_t {
   std::atomic<bool> stop{false};
   Clock::time_point t0 = Clock::now();
   std::string err;
+  std::unique_ptr<Batcher> batcher;  // batch_collisions
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
@@ -146,7 +366,26 @@ struct blr_server_t {
           sl->ctx = cx;
         }
         blr_problem pb = job.req.problem;
-        blr::steady_solve(sl->ctx, &pb, job.req.state, &job.req.solve, &c.info, &stop);
+        // this solve's collisions join the batch when they take the fused path
+        const bool batched = batcher && pb.ny < 2 && blr::fused_f32_grid(pb.v) &&
+                             !(job.req.solve.step.flags & BLR_STEP_FP64_COLLISION);
+        if (batched) {
+          sl->ctx->collide_hook = batcher.get();
+          batcher->join();
+        }
+        try {
+          blr::steady_solve(sl->ctx, &pb, job.req.state, &job.req.solve, &c.info, &stop);
+        } catch (...) {
+          if (batched) {
+            batcher->leave();
+            sl->ctx->collide_hook = nullptr;
+          }
+          throw;
+        }
+        if (batched) {
+          batcher->leave();
+          sl->ctx->collide_hook = nullptr;
+        }
         status = c.info.converged ? BLR_OK : BLR_ERR_NOT_CONVERGED;
       } catch (const blr::Error& e) {
         status = e.code;
@@ -188,6 +427,10 @@ blr_status blr_server_create(int device, const blr_server_params* params, blr_se
   if (!sv) return BLR_ERR_NOMEM;
   sv->device = device;
   sv->budget = params->hbm_budget;
+  if (params->batch_collisions) {
+    sv->batcher = std::make_unique<Batcher>();
+    sv->batcher->device = device;
+  }
   for (int k = 0; k < params->slots; ++k) {
     auto s = std::make_unique<Slot>();
     s->index = k;
@@ -278,6 +521,17 @@ blr_status blr_server_clock(blr_server sv, double* t) {
   return BLR_OK;
 }
 
+blr_status blr_server_batch_stats(blr_server sv, int64_t* rounds, int64_t* jobs) {
+  if (!sv || !rounds || !jobs) return BLR_ERR_ARG;
+  *rounds = *jobs = 0;
+  if (sv->batcher) {
+    std::lock_guard<std::mutex> lk(sv->batcher->mu);
+    *rounds = sv->batcher->rounds;
+    *jobs = sv->batcher->jobs;
+  }
+  return BLR_OK;
+}
+
 const char* blr_server_last_error(blr_server sv) { return sv ? sv->err.c_str() : "null server"; }
 
 blr_status blr_server_destroy(blr_server sv) {
@@ -288,6 +542,7 @@ blr_status blr_server_destroy(blr_server sv) {
     sv->queue.clear();
   }
   sv->cv_slot.notify_all();
+  if (sv->batcher) sv->batcher->stop();
   for (auto& s : sv->slots)
     if (s->th.joinable()) s->th.join();
   (void)hipSetDevice(sv->device);
