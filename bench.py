@@ -261,6 +261,10 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
             "converged": sum(1 for c in comps if c.status == blr.BLR_OK),
             "failed": len(comps) - len(ok),
             "final_rank_range": [min(c.info.r for c in ok), max(c.info.r for c in ok)] if ok else None}
+    if len(comps) <= 16:
+        # per request: index, slot, submit, admit and done times (s), steps
+        out["requests_detail"] = [[c.tag, c.slot, round(c.t_submit, 4), round(c.t_admit, 4),
+                                   round(c.t_done, 4), c.info.steps] for c in comps]
     if batch:
         # the warm-up's batches included
         out["collision_batches"] = bstats[0]
@@ -807,6 +811,15 @@ def serving_leg(args, blr, synth, torch, helper):
                             f"each to err_ada<=1e-6 or {args.serve_long_steps} steps"
         out["long_batched_fp32"] = run_trace(blr, torch, helper, lp, args.serve_slots, False,
                                              args.serve_long_steps)
+        out["long_batched_fp32_shared_collision_launches"] = run_trace(
+            blr, torch, helper, lp, args.serve_slots, False, args.serve_long_steps, batch=True)
+        # the same requests all arriving at once (every slot busy from the start)
+        burst = [dict(p, q=dict(p["q"], arrival=0.0)) for p in lp]
+        out["burst_trace"] = "the long trace's requests, all arriving at t = 0"
+        out["burst_batched_fp32"] = run_trace(blr, torch, helper, burst, args.serve_slots, False,
+                                              args.serve_long_steps)
+        out["burst_batched_fp32_shared_collision_launches"] = run_trace(
+            blr, torch, helper, burst, args.serve_slots, False, args.serve_long_steps, batch=True)
     return out
 
 

@@ -126,8 +126,10 @@ void blr_ctx_t::release_all() {
   if (readback) (void)hipHostFree(readback);
   readback = nullptr;
   readback_bytes = 0;
-  for (auto& g : graphs)
+  for (auto& g : graphs) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.exec2) (void)hipGraphExecDestroy(g.exec2);
+  }
   graphs.clear();
   if (cap_stream) {
     (void)hipStreamDestroy(cap_stream);

@@ -17,8 +17,10 @@
 // serves every size and both precisions; the fused FP32 kernels in
 // collision_fast.hip replace steps 2-5 for the 3D grids when they apply.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <unordered_map>
 
 #include "collision_common.hpp"
@@ -1016,7 +1018,26 @@ void basis_spectra_f32(blr_ctx ctx, const DevTables& tb, const float* V, const P
 }
 
 size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec) {
-  HostTables h = build_tables(vg);
+  // the estimate needs only the tables' shapes, but building them takes the
+  // host a good fraction of a second at 32^3: one build per grid (a server
+  // estimates every request it admits)
+  static std::mutex mu;
+  static std::map<std::string, std::array<int, 5>> shapes;  // d, N, mrho, msig, nbp
+  std::string key((const char*)&vg, sizeof(vg));
+  HostTables h;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = shapes.find(key);
+    if (it == shapes.end()) {
+      const HostTables t = build_tables(vg);
+      it = shapes.emplace(key, std::array<int, 5>{t.d, t.N, t.mrho, t.msig, t.nbp}).first;
+    }
+    h.d = it->second[0];
+    h.N = it->second[1];
+    h.mrho = it->second[2];
+    h.msig = it->second[3];
+    h.nbp = it->second[4];
+  }
   const int P = r * (r + 1) / 2;
   size_t out = 0;
   auto f = [&](auto Tc) {

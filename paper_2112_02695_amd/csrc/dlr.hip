@@ -1838,7 +1838,17 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
                        (long)r * n, V32, pend_S, pend_r, Sw, pend_r);
     BLR_CHECK_LAUNCH();
     Qs = ctx->buf("dlr.Q32", (size_t)P * n * sizeof(float));
-    if (ctx->collide_hook)
+    if (ctx->collide_hook && ctx->capturing) {
+      // recording: the graph ends here, the collisions run between it and the
+      // graph of the rest of the step (recorded from here on)
+      BLR_HIP(hipStreamEndCapture(ctx->stream, &ctx->split_g1));
+      ctx->split_vg = pb->v;
+      ctx->split_V = V32;
+      ctx->split_r = r;
+      ctx->split_pairs = pairs;
+      ctx->split_Q = (float*)Qs;
+      BLR_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    } else if (ctx->collide_hook)
       ctx->collide_hook->collide(ctx, pb->v, V32, r, pairs, (float*)Qs);
     else
       collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
@@ -2101,9 +2111,7 @@ std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_
 void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const blr_step_params* sp,
                   const HostTables& h, bool add, Attempt at, Outcome& o) {
   hipStream_t s = ctx->stream;
-  // (a step whose collisions are batched with other solves' runs directly:
-  // it waits on work outside its own stream)
-  const bool graphs = !(sp->flags & BLR_STEP_EAGER) && !ctx->timer.on && !ctx->collide_hook;
+  const bool graphs = !(sp->flags & BLR_STEP_EAGER) && !ctx->timer.on;
   auto eager = [&]() {
     step_enqueue(ctx, pb, st, sp, h, add, at, o, true);
     BLR_HIP(hipStreamSynchronize(s));
@@ -2113,7 +2121,8 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     eager();
     return;
   }
-  const std::string key = step_key(pb, st, sp, add, at);
+  // (with collide_hook the recording is split around the collisions)
+  const std::string key = step_key(pb, st, sp, add, at) + (ctx->collide_hook ? "h" : "");
   auto& gs = ctx->graphs;
   size_t gi = gs.size();
   for (size_t k = 0; k < gs.size(); ++k)
@@ -2121,6 +2130,7 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   if (gi == gs.size()) {
     if (gs.size() >= 8) {  // forget the oldest
       if (gs.front().exec) (void)hipGraphExecDestroy(gs.front().exec);
+      if (gs.front().exec2) (void)hipGraphExecDestroy(gs.front().exec2);
       gs.erase(gs.begin());
     }
     gs.push_back(blr_ctx_t::StepGraph{});
@@ -2130,7 +2140,9 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   auto& g = gs[gi];
   if (g.gen != ctx->buf_gen) {  // addresses moved: start over
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.exec2) (void)hipGraphExecDestroy(g.exec2);
     g.exec = nullptr;
+    g.exec2 = nullptr;
     g.seen = 0;
     g.gen = ctx->buf_gen;
   }
@@ -2147,12 +2159,18 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     ctx->stream = ctx->cap_stream;
     ctx->capturing = true;
     ctx->capture_broken = false;
+    ctx->split_g1 = nullptr;
+    auto drop_split = [&] {
+      if (ctx->split_g1) (void)hipGraphDestroy(ctx->split_g1);
+      ctx->split_g1 = nullptr;
+    };
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       try {
         step_enqueue(ctx, pb, st, sp, h, add, at, o, false);
       } catch (const Error&) {
+        drop_split();
         // The recording failed: a device-wide operation of another host
         // thread (a device synchronisation, an allocation or free) can
         // invalidate it or make a recorded launch report an error.  The step
@@ -2167,6 +2185,7 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
         g.gen = ctx->buf_gen;
         return;
       } catch (...) {
+        drop_split();
         (void)hipStreamEndCapture(ctx->cap_stream, &graph);
         if (graph) (void)hipGraphDestroy(graph);
         ctx->stream = s;
@@ -2177,17 +2196,35 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     }
     ctx->stream = s;
     ctx->capturing = false;
-    hipGraphExec_t exec = nullptr;
-    if (e == hipSuccess && graph && !ctx->capture_broken && ctx->buf_gen == gen0)
-      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphExec_t exec = nullptr, exec2 = nullptr;
+    const bool split = ctx->split_g1 != nullptr;
+    if (e == hipSuccess && graph && !ctx->capture_broken && ctx->buf_gen == gen0) {
+      if (split) {
+        e = hipGraphInstantiate(&exec, ctx->split_g1, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec2, graph, nullptr, nullptr, 0);
+      } else {
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      }
+    }
     if (graph) (void)hipGraphDestroy(graph);
-    if (e != hipSuccess || !exec) {
+    drop_split();
+    if (e != hipSuccess || !exec || (split && !exec2) || (!split && ctx->collide_hook)) {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (exec2) (void)hipGraphExecDestroy(exec2);
       (void)hipGetLastError();
       eager();  // not recordable this time: run it directly
       g.gen = ctx->buf_gen;
       return;
     }
     g.exec = exec;
+    g.exec2 = exec2;
+    if (split) {
+      g.cvg = ctx->split_vg;
+      g.cV = ctx->split_V;
+      g.cr = ctx->split_r;
+      g.cpairs = ctx->split_pairs;
+      g.cQ = ctx->split_Q;
+    }
     g.gen = ctx->buf_gen;
     g.r = o.r;
     g.nrb = o.nrb;
@@ -2211,6 +2248,10 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   }
   BLR_HIP(hipEventRecord(ctx->ev[0], s));
   BLR_HIP(hipGraphLaunch(g.exec, s));
+  if (g.exec2) {
+    ctx->collide_hook->collide(ctx, g.cvg, g.cV, g.cr, g.cpairs, g.cQ);
+    BLR_HIP(hipGraphLaunch(g.exec2, s));
+  }
   BLR_HIP(hipEventRecord(ctx->ev[3], s));
   BLR_HIP(hipStreamSynchronize(s));
   o.timed_collision = false;

@@ -353,6 +353,7 @@ void full_step(blr_ctx ctx, const blr_problem* pb, int prec, double* F, double d
   if (gi == gs.size()) {
     if (gs.size() >= 8) {  // forget the oldest
       if (gs.front().exec) (void)hipGraphExecDestroy(gs.front().exec);
+      if (gs.front().exec2) (void)hipGraphExecDestroy(gs.front().exec2);
       gs.erase(gs.begin());
     }
     gs.push_back(blr_ctx_t::StepGraph{});

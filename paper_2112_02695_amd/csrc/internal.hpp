@@ -162,6 +162,14 @@ struct blr_ctx_t {
     int r = 0, nrb = 0;
     double *X1 = nullptr, *V1 = nullptr, *Snew = nullptr, *U = nullptr, *Wm = nullptr,
            *sgd = nullptr, *hb = nullptr;
+    // a step whose collisions go through collide_hook is two graphs: exec up
+    // to the collisions, exec2 after them; the collisions' arguments
+    hipGraphExec_t exec2 = nullptr;
+    blr_vgrid cvg{};
+    const float* cV = nullptr;
+    int cr = 0;
+    std::vector<int32_t> cpairs;
+    float* cQ = nullptr;
   };
   std::vector<StepGraph> graphs;
   hipStream_t cap_stream = nullptr;
@@ -195,6 +203,14 @@ struct blr_ctx_t {
     virtual ~CollideHook() = default;
   };
   CollideHook* collide_hook = nullptr;
+  // while a step with collide_hook is recorded: the graph up to its
+  // collisions (the recording then continues after them) and their arguments
+  hipGraph_t split_g1 = nullptr;
+  blr_vgrid split_vg{};
+  const float* split_V = nullptr;
+  int split_r = 0;
+  std::vector<int32_t> split_pairs;
+  float* split_Q = nullptr;
 
   void* buf(const std::string& name, size_t bytes);  // grow-only named workspace
   // copy a small host array to a named device buffer, asynchronously
