@@ -85,6 +85,7 @@ struct Batcher : blr_ctx_t::CollideHook {
 
   int device = 0;
   std::mutex mu;
+  std::mutex launch_mu;  // one round's launches at a time (the batch context is not shared)
   std::condition_variable cv;
   int active = 0;
   bool stopping = false;
@@ -158,6 +159,9 @@ struct Batcher : blr_ctx_t::CollideHook {
     blr_status code = BLR_OK;
     std::string err;
     try {
+      // (a round can only start once every joined solve waits in collide(),
+      // so rounds do not overlap; the lock keeps it that way regardless)
+      std::lock_guard<std::mutex> lg(launch_mu);
       launch(batch);
     } catch (const blr::Error& e) {
       code = e.code;
