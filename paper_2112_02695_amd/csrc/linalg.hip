@@ -476,23 +476,44 @@ __global__ __launch_bounds__(64) void k_svd_jacobi(const double* __restrict__ A,
   svd_finish(B, V, nrm, order, r, U, sig, W, complete, t);
 }
 
+// Sum over each half (32 lanes) of the wavefront, returned to the lanes of
+// that half: row sums as in wave_allsum, then row_bcast:15 adds row 0's sum
+// into row 1 and row 2's into row 3, read back from lanes 31 and 63.
+__device__ __forceinline__ double half_allsum(double x) {
+  x += dpp_move<0xb1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_move<0x4e>(x);   // quad_perm [2,3,0,1]
+  x += dpp_move<0x124>(x);  // row_ror:4
+  x += dpp_move<0x128>(x);  // row_ror:8
+  x += dpp_move<0x142>(x);  // row_bcast:15
+  const long long b = __double_as_longlong(x);
+  const int l0 = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 31);
+  const int h0 = __builtin_amdgcn_readlane((int)(b >> 32), 31);
+  const int l1 = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int h1 = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  const bool upper = (threadIdx.x & 63) >= 32;
+  return __longlong_as_double(((long long)(upper ? h1 : h0) << 32) | (unsigned int)(upper ? l1 : l0));
+}
+
 // The same Jacobi SVD for r > 16 on 16 wavefronts: each round's column pairs
-// are dealt to the wavefronts (pair slot k to wavefront k mod 16), a pair's
-// rows to the lanes (lane i holds row i), its three column sums are
-// wavefront sums; the rounds are ordered by workgroup barriers.  The same
-// circle-method pairing, rotation and stopping rule as k_svd_jacobi.
+// are dealt to groups of GL lanes (a wavefront, GL = 64, or half of one,
+// GL = 32; pair slot k to group k mod 1024 / GL), a pair's rows to the lanes
+// of its group (64 / GL rows each), its three column sums are group sums;
+// the rounds are ordered by workgroup barriers.  The same circle-method
+// pairing, rotation and stopping rule as k_svd_jacobi.
+template <int GL>
 __global__ __launch_bounds__(1024) void k_svd_jacobi_wide(const double* __restrict__ A, int r,
                                                          double* __restrict__ U,
                                                          double* __restrict__ sig,
                                                          double* __restrict__ W, int sweeps,
                                                          int trans, int complete) {
+  constexpr int NG = 1024 / GL, RPL = 64 / GL;
   __shared__ double B[64 * SVS];  // column c: B[c * SVS + i]
   __shared__ double V[64 * SVS];
   __shared__ double nrm[64];
   __shared__ int order[64];
   __shared__ double part[16];
-  const int t = threadIdx.x, wv = t / 64, lane = t % 64;
-  auto wsum = [](double x) { return wave_allsum(x); };
+  const int t = threadIdx.x, wv = t / 64, grp = t / GL, lane = t % GL;
+  auto gsum = [](double x) { return GL == 64 ? wave_allsum(x) : half_allsum(x); };
   double fro2 = 0.0;
   for (int e = t; e < r * r; e += blockDim.x) {
     const double v = A[e];
@@ -504,8 +525,8 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi_wide(const double* __restri
     const int row = e / r, c = e % r;
     V[c * SVS + row] = (row == c) ? 1.0 : 0.0;
   }
-  fro2 = wsum(fro2);
-  if (lane == 0) part[wv] = fro2;
+  fro2 = wave_allsum(fro2);
+  if ((t & 63) == 0) part[wv] = fro2;
   __syncthreads();
   fro2 = 0.0;
   for (int k = 0; k < 16; ++k) fro2 += part[k];
@@ -516,8 +537,11 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi_wide(const double* __restri
   for (int sw = 0; sw < sweeps; ++sw) {
     int rotated = 0;
     for (int round = 0; round < rr - 1; ++round) {
-      for (int slot = wv; slot < np; slot += 16) {
-        int p, q;
+      // every group runs the same number of slots (dead ones with zero
+      // columns), so the group sums never see a half-active wavefront
+      for (int s0 = 0; s0 < np; s0 += NG) {
+        const int slot = s0 + grp;
+        int p = 0, q = 0;
         if (slot == 0) {
           p = rr - 1;
           q = round;
@@ -532,20 +556,33 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi_wide(const double* __restri
           p = q;
           q = tmp;
         }
-        if (q >= r) continue;  // the dummy column of an odd r
-        const double x = lane < r ? B[p * SVS + lane] : 0.0;
-        const double y = lane < r ? B[q * SVS + lane] : 0.0;
-        const double al = wsum(x * x), be = wsum(y * y), ga = wsum(x * y);
-        if (al >= tiny2 && be >= tiny2 && fabs(ga) > 1e-300 && ga * ga > tol2 * (al * be)) {
+        const bool live = slot < np && q < r;  // (q = r: the dummy column of an odd r)
+        double x[RPL], y[RPL];
+        double sxx = 0.0, syy = 0.0, sxy = 0.0;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int i = lane + k * GL;
+          x[k] = live && i < r ? B[p * SVS + i] : 0.0;
+          y[k] = live && i < r ? B[q * SVS + i] : 0.0;
+          sxx += x[k] * x[k];
+          syy += y[k] * y[k];
+          sxy += x[k] * y[k];
+        }
+        const double al = gsum(sxx), be = gsum(syy), ga = gsum(sxy);
+        if (live && al >= tiny2 && be >= tiny2 && fabs(ga) > 1e-300 && ga * ga > tol2 * (al * be)) {
           const double tau = be - al, g2 = 2.0 * ga;
           const double tt = (tau >= 0 ? g2 : -g2) / (fabs(tau) + sqrt(tau * tau + g2 * g2));
           const double c = rsqrt(1.0 + tt * tt), sn = c * tt;
-          if (lane < r) {
-            B[p * SVS + lane] = c * x - sn * y;
-            B[q * SVS + lane] = sn * x + c * y;
-            const double vx = V[p * SVS + lane], vy = V[q * SVS + lane];
-            V[p * SVS + lane] = c * vx - sn * vy;
-            V[q * SVS + lane] = sn * vx + c * vy;
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) {
+            const int i = lane + k * GL;
+            if (i < r) {
+              B[p * SVS + i] = c * x[k] - sn * y[k];
+              B[q * SVS + i] = sn * x[k] + c * y[k];
+              const double vx = V[p * SVS + i], vy = V[q * SVS + i];
+              V[p * SVS + i] = c * vx - sn * vy;
+              V[q * SVS + i] = sn * vx + c * vy;
+            }
           }
           rotated = 1;
         }
@@ -554,7 +591,7 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi_wide(const double* __restri
     }
     if (!__syncthreads_or(rotated)) break;
   }
-  if (wv == 0) svd_finish(B, V, nrm, order, r, U, sig, W, complete, lane);
+  if (wv == 0) svd_finish(B, V, nrm, order, r, U, sig, W, complete, t);
 }
 
 // ------------------------------------------------------- Cholesky QR --
@@ -993,9 +1030,12 @@ void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, doub
   if (r <= 16)
     hipLaunchKernelGGL(la::k_svd_jacobi, dim3(1), dim3(64), 0, ctx->stream, A, r, U, sig, W, 40,
                        trans ? 1 : 0, complete ? 1 : 0);
+  else if (r <= 32)
+    hipLaunchKernelGGL(la::k_svd_jacobi_wide<64>, dim3(1), dim3(1024), 0, ctx->stream, A, r, U, sig,
+                       W, 40, trans ? 1 : 0, complete ? 1 : 0);
   else
-    hipLaunchKernelGGL(la::k_svd_jacobi_wide, dim3(1), dim3(1024), 0, ctx->stream, A, r, U, sig, W,
-                       40, trans ? 1 : 0, complete ? 1 : 0);
+    hipLaunchKernelGGL(la::k_svd_jacobi_wide<32>, dim3(1), dim3(1024), 0, ctx->stream, A, r, U, sig,
+                       W, 40, trans ? 1 : 0, complete ? 1 : 0);
   BLR_CHECK_LAUNCH();
 }
 
