@@ -75,10 +75,41 @@ __device__ __forceinline__ double wave_allsum(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Orders the LDS accesses of one wavefront (its DS instructions execute in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sums over the 64 lanes of a one-wavefront block, returned to every lane.
+// A few values: DPP sums.  Many (the Householder panels' column products):
+// through LDS, lane t writing its NV values as row t of a padded 64 x NV
+// table and lane c < NV summing column c in lane order, so the NV sums run
+// side by side instead of as NV dependent DPP chains.
 template <int NV>
 __device__ __forceinline__ void block_sums(double (&v)[NV], double*) {
+  if constexpr (NV < 8) {
 #pragma unroll
-  for (int c = 0; c < NV; ++c) v[c] = wave_allsum(v[c]);
+    for (int c = 0; c < NV; ++c) v[c] = wave_allsum(v[c]);
+  } else {
+    __shared__ double red[64 * (NV + 1)];
+    __shared__ double tot[NV];
+    const int t = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) red[t * (NV + 1) + c] = v[c];
+    wave_sync();
+    if (t < NV) {
+      double acc = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < 64; ++k) acc += red[k * (NV + 1) + t];
+      tot[t] = acc;
+    }
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] = tot[c];
+  }
 }
 
 // Factor block b of a column-major matrix A (rows x r, leading dim lda),
@@ -258,13 +289,6 @@ __device__ __forceinline__ double group_sum(double x, int lpp) {
   return x;
 }
 
-// Orders the LDS accesses of one wavefront (its DS instructions execute in
-// order; this keeps the compiler from moving them across).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 constexpr int SVS = 65;  // LDS column stride of the Jacobi SVD (doubles)
 
