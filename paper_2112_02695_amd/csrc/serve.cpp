@@ -20,6 +20,7 @@
 #include <thread>
 
 #include "internal.hpp"
+#include "rendezvous.hpp"
 
 namespace {
 
@@ -72,9 +73,6 @@ struct Batcher : blr_ctx_t::CollideHook {
     blr_vgrid vg{};
     blr::BatchJob job;
     hipEvent_t ready = nullptr;
-    bool done = false;
-    blr_status code = BLR_OK;
-    std::string err;
   };
   struct Graph {
     std::string key;
@@ -84,18 +82,14 @@ struct Batcher : blr_ctx_t::CollideHook {
   };
 
   int device = 0;
-  std::mutex mu;
-  std::mutex launch_mu;  // one round's launches at a time (the batch context is not shared)
-  std::condition_variable cv;
-  int active = 0;
-  bool stopping = false;
-  std::vector<Pending*> pending;
+  blr::Rendezvous<Pending> rv{[this](const std::vector<Pending*>& b) { return run(b); }};
+  std::mutex ev_mu;
   std::map<blr_ctx, hipEvent_t> ready;  // one per solve context, reused every step
+  // the round's state (used by one round at a time)
   blr_ctx bctx = nullptr;
   hipStream_t bstream = nullptr;
   hipEvent_t done_ev = nullptr;
   std::vector<Graph> graphs;
-  int64_t rounds = 0, jobs = 0;
 
   ~Batcher() {
     if (bstream) (void)hipStreamSynchronize(bstream);
@@ -107,76 +101,39 @@ struct Batcher : blr_ctx_t::CollideHook {
     if (bstream) (void)hipStreamDestroy(bstream);
   }
 
-  void join() {
-    std::lock_guard<std::mutex> lk(mu);
-    ++active;
-  }
-  void leave() {
-    std::unique_lock<std::mutex> lk(mu);
-    --active;
-    if (!stopping && !pending.empty() && (int)pending.size() >= active) run_round(lk);
-  }
-  void stop() {
-    std::lock_guard<std::mutex> lk(mu);
-    stopping = true;
-    cv.notify_all();
-  }
+  void join() { rv.join(); }
+  void leave() { rv.leave(); }
+  void stop() { rv.stop(); }
 
   void collide(blr_ctx ctx, const blr_vgrid& vg, const float* V, int r,
                const std::vector<int32_t>& pairs, float* Q) override {
     Pending p;
     p.vg = vg;
     p.job = blr::BatchJob{V, r, pairs, Q};
-    std::unique_lock<std::mutex> lk(mu);
-    if (stopping) throw blr::Error(BLR_ERR_ARG, "server stopping");
-    hipEvent_t& ev = ready[ctx];
-    if (!ev) BLR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    BLR_HIP(hipEventRecord(ev, ctx->stream));
-    p.ready = ev;
-    pending.push_back(&p);
-    if ((int)pending.size() >= active) run_round(lk);
-    // a job a round has taken is waited for to the end (the round holds it)
-    auto queued = [&] { return std::find(pending.begin(), pending.end(), &p) != pending.end(); };
-    cv.wait(lk, [&] { return p.done || (stopping && queued()); });
-    if (!p.done) {
-      // stopping before a round took the job: take it back out
-      pending.erase(std::remove(pending.begin(), pending.end(), &p), pending.end());
-      throw blr::Error(BLR_ERR_ARG, "server stopping");
+    {
+      std::lock_guard<std::mutex> lk(ev_mu);
+      hipEvent_t& ev = ready[ctx];
+      if (!ev) BLR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      p.ready = ev;
     }
-    if (p.code != BLR_OK) throw blr::Error(p.code, p.err);
+    // the step's inputs are ready where this solve's stream stands now
+    BLR_HIP(hipEventRecord(p.ready, ctx->stream));
+    blr::Rendezvous<Pending>::Outcome o;
+    if (!rv.submit(&p, &o)) throw blr::Error(BLR_ERR_ARG, "server stopping");
+    if (o.code != 0) throw blr::Error(o.code > 0 ? (blr_status)o.code : BLR_ERR_HIP, o.err);
     BLR_HIP(hipStreamWaitEvent(ctx->stream, done_ev, 0));
   }
 
  private:
-  // Runs the pending jobs (mu held on entry and on return; released while the
-  // work is enqueued, when every joined solve is waiting in collide()).
-  void run_round(std::unique_lock<std::mutex>& lk) {
-    std::vector<Pending*> batch;
-    batch.swap(pending);
-    ++rounds;
-    jobs += (int64_t)batch.size();
-    lk.unlock();
-    blr_status code = BLR_OK;
-    std::string err;
+  blr::Rendezvous<Pending>::Outcome run(const std::vector<Pending*>& batch) {
+    blr::Rendezvous<Pending>::Outcome o;
     try {
-      // (a round can only start once every joined solve waits in collide(),
-      // so rounds do not overlap; the lock keeps it that way regardless)
-      std::lock_guard<std::mutex> lg(launch_mu);
       launch(batch);
     } catch (const blr::Error& e) {
-      code = e.code;
-      err = e.what();
-    } catch (const std::exception& e) {
-      code = BLR_ERR_HIP;
-      err = e.what();
+      o.code = e.code;
+      o.err = e.what();
     }
-    lk.lock();
-    for (Pending* p : batch) {
-      p->done = true;
-      p->code = code;
-      p->err = err;
-    }
-    cv.notify_all();
+    return o;
   }
 
   void enqueue(const std::vector<std::pair<blr_vgrid, std::vector<blr::BatchJob>>>& groups) {
@@ -529,9 +486,8 @@ blr_status blr_server_batch_stats(blr_server sv, int64_t* rounds, int64_t* jobs)
   if (!sv || !rounds || !jobs) return BLR_ERR_ARG;
   *rounds = *jobs = 0;
   if (sv->batcher) {
-    std::lock_guard<std::mutex> lk(sv->batcher->mu);
-    *rounds = sv->batcher->rounds;
-    *jobs = sv->batcher->jobs;
+    *rounds = sv->batcher->rv.rounds();
+    *jobs = sv->batcher->rv.items();
   }
   return BLR_OK;
 }
