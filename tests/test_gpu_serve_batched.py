@@ -129,3 +129,48 @@ def test_stopping_a_busy_batching_server_returns(helper):
         t0 = time.perf_counter()
         sv.close()   # must return
         print(f"close took {time.perf_counter() - t0:.3f} s", flush=True)
+
+
+def test_batches_beyond_64_basis_functions(helper):
+    """Four solves entering at rank 18-20 (22 with the added boundary
+    functions): a batch holds more than 64 basis functions and runs as
+    several launch sequences.  Each result is still the same alone and in the
+    mix."""
+    reqs = [(3, 16, 4, 24, 18 + k % 3, 1.4 + 0.2 * k, 20 + k, 0.01, 3) for k in range(4)]
+
+    def serve(jobs, slots):
+        sv = blr.Server(0, slots=slots, batch_collisions=True)
+        keep, comps = {}, []
+        try:
+            for k in jobs:
+                d, n, m_rho, nx, r, mach, seed, dt, steps = reqs[k]
+                pb, st, arrs = Req(d, n, m_rho, nx, r, mach, seed, r_cap=24).device(helper)
+                sv.submit(pb, st, _solve_params(dt, steps, r_max=24), k)
+                keep[k] = (st, arrs)
+            while len(comps) < len(jobs):
+                got = sv.wait(timeout=120.0)
+                assert got, "server made no progress"
+                comps.extend(got)
+            stats = sv.batch_stats()
+        finally:
+            sv.close()
+        out = {}
+        for c in comps:
+            st, arrs = keep[c.tag]
+            assert c.status == blr.BLR_ERR_NOT_CONVERGED, c.message
+            out[c.tag] = (c.info.steps, c.info.r, c.info.err_ada, _factors(st, arrs))
+        return out, stats
+
+    print("batched server: 4 solves of rank 18-20, alone then together", flush=True)
+    alone = {}
+    for k in range(4):
+        alone.update(serve([k], 1)[0])
+    mix, (rounds, jobs) = serve(list(range(4)), 4)
+    print(f"batches {rounds}, collisions {jobs}", flush=True)
+    assert jobs > rounds
+    for k in range(4):
+        steps, r, err_ada, fac = mix[k]
+        a_steps, a_r, a_err, a_fac = alone[k]
+        assert steps == a_steps and r == a_r and err_ada == a_err
+        for x, y in zip(fac, a_fac):
+            assert np.array_equal(x, y)
