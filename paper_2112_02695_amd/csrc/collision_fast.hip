@@ -397,11 +397,12 @@ __global__ __launch_bounds__(N * N) void k_pair_spec(const float* __restrict__ p
     const float* src = pa + ((long)a * P + p) * n;
     const float* src2 = two ? src + (long)P * n : src;
     float re[N], im[N];
+    // (the products are read once: streaming loads)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const int o = j * N * N + t;
-      re[j] = src[o];
-      const float v = src2[o];
+      re[j] = __builtin_nontemporal_load(src + o);
+      const float v = __builtin_nontemporal_load(src2 + o);
       im[j] = two ? v : 0.f;
     }
     fft::dft<float, N, -1>(re, im);
@@ -495,11 +496,14 @@ __global__ __launch_bounds__(N * N) void k_final_fused(const float2* __restrict_
         re[j] = 0.f;
         im[j] = 0.f;
       }
+      // (each group's half spectrum is read once: streaming loads)
+      typedef float f2v __attribute__((ext_vector_type(2)));
       for (int g = 0; g < ng; ++g) {
-        const float2* src = wsp + ((long)p * ng + g) * N * N * H + (long)k1 * H + k2;
+        const f2v* src = reinterpret_cast<const f2v*>(wsp + ((long)p * ng + g) * N * N * H +
+                                                      (long)k1 * H + k2);
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-          const float2 v = src[(long)j * N * H];
+          const f2v v = __builtin_nontemporal_load(src + (long)j * N * H);
           re[j] += v.x;
           im[j] += v.y;
         }
