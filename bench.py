@@ -109,6 +109,9 @@ def parse():
     ap.add_argument("--serve-conv-plain", type=int, default=1,
                     help="how many of them the plain FP64 FIFO serves")
     ap.add_argument("--serve-conv-cap", type=int, default=40000)
+    ap.add_argument("--steady-compare", type=int, default=0,
+                    help="also run the converged trace's first solve for this many steps with FP32 "
+                         "and with FP64 collisions (no stopping rule) and compare the moments")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -162,7 +165,7 @@ def progress(msg):
 
 
 def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol=1e-6,
-              moments_of=(), batch=False):
+              moments_of=(), batch=False, fp64=False):
     """Serve the requests at their arrival times; latency = completion time -
     arrival (submit) time on the server's clock.  For the request indices in
     moments_of, the steady rho, u_1, T per cell are returned as well."""
@@ -185,11 +188,12 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
         return pb, st
 
     def params(q, steps):
-        flags = blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | (blr.BLR_STEP_FP64_COLLISION if plain else 0)
+        flags = blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | (
+            blr.BLR_STEP_FP64_COLLISION if (plain or fp64) else 0)
         return blr.SolveParams(blr.StepParams(q["dt"], 0.2, 1e-10, 1, r_cap, flags), res_tol, steps)
 
     progress(f"serving trace: {len(prepared)} requests, {slots} slot(s), "
-             f"{'plain fp64' if plain else 'batched fp32'}"
+             f"{'plain fp64' if plain else ('batched fp64' if fp64 else 'batched fp32')}"
              f"{', collisions of all live solves in shared launches' if batch else ''}, "
              f"cap {cap} steps")
     sv = blr.Server(0, slots=slots, batch_collisions=batch)
@@ -260,7 +264,8 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
             "pair_evals_per_s": round(sum(c.info.pair_evals for c in comps) / wall, 1),
             "converged": sum(1 for c in comps if c.status == blr.BLR_OK),
             "failed": len(comps) - len(ok),
-            "final_rank_range": [min(c.info.r for c in ok), max(c.info.r for c in ok)] if ok else None}
+            "final_rank_range": [min(c.info.r for c in ok), max(c.info.r for c in ok)] if ok else None,
+            "final_err_ada": max(c.info.err_ada for c in ok) if ok else None}
     if len(comps) <= 16:
         # per request: index, slot, submit, admit and done times (s), steps
         out["requests_detail"] = [[c.tag, c.slot, round(c.t_submit, 4), round(c.t_admit, 4),
@@ -804,6 +809,21 @@ def serving_leg(args, blr, synth, torch, helper):
                 nm: float(np.abs(a - c).max() / np.abs(c).max())
                 for nm, a, c in zip(("rho", "u1", "T"), m32[0], m64[0])}
             out["converged_fp32_vs_fp64_steady_moments"]["target"] = 1e-6
+    if args.steady_compare > 0:
+        # the same solve marched a fixed number of steps past the stopping rule in
+        # both precisions: the steady state itself, not where err_ada first dips
+        ct = synth.serving_trace_2d(count=1, seed=6, rate=4.0)
+        cp = prepare_trace(ct, synth)
+        n = args.steady_compare
+        r32, m32 = run_trace(blr, torch, helper, cp, 1, False, n, res_tol=0.0, moments_of=(0,))
+        r64, m64 = run_trace(blr, torch, helper, cp, 1, False, n, res_tol=0.0, moments_of=(0,),
+                             fp64=True)
+        out["fixed_steps_fp32_vs_fp64"] = {
+            "steps": n, "fp32_err_ada": r32.get("final_err_ada"), "fp64_err_ada": r64.get("final_err_ada"),
+            "fp32_wall_s": r32["wall_s"], "fp64_wall_s": r64["wall_s"],
+            "moments_max_rel_diff": {nm: float(np.abs(a - c).max() / np.abs(c).max())
+                                     for nm, a, c in zip(("rho", "u1", "T"), m32[0], m64[0])},
+            "target": 1e-6}
     if args.serve_long_count > 0:
         long_trace = synth.serving_trace(count=args.serve_long_count, seed=5, rate=4.0)
         lp = prepare_trace(long_trace, synth)

@@ -277,6 +277,25 @@ typedef struct {
  * configuration -- shapes, arrays, parameters -- is seen, and replayed from
  * then on; kernel timing turns graphs off).  Results are identical. */
 #define BLR_STEP_EAGER           0x20u
+/* FP32 pair collisions with an FP64 defect correction (1D space only, r_cap
+ * <= 32, not with BLR_STEP_FP64_COLLISION).  A refresh step evaluates its
+ * pairs in FP64 and in FP32, steps with the FP64 ones, and keeps on the
+ * context their difference D_mn = Q_s^64(V_m, V_n) - Q_s^32(V_m, V_n) with the
+ * basis V.  Every other step adds to its FP32 pairs the kept defect carried
+ * to its own basis W through the bilinearity of Q_s:
+ *   Q_ab = Q_s^32(W_a, W_b) + sum_mn R_am R_bn D_mn,   R_am = <W_a, V_m>,
+ * and steps with Q_ab in FP64.  Most of the FP32 error of Q_s stays the same
+ * while the basis changes little; near a steady state (Sec. 5.1) that part
+ * piles up in slowly relaxing modes and shifts the steady state, and the
+ * correction removes it.  What is left is the part of the FP32 rounding that
+ * changes from step to step.  A refresh step costs one FP64 and one FP32
+ * evaluation of the pairs.  A step with this flag refreshes by itself when
+ * the context keeps no defect for this velocity grid; blr_steady_solve
+ * refreshes on its first step and every blr_solve_params.defect_every
+ * steps. */
+#define BLR_STEP_FP64_DEFECT     0x40u
+/* With BLR_STEP_FP64_DEFECT: make this step a refresh step. */
+#define BLR_STEP_DEFECT_REFRESH  0x80u
 
 typedef struct {
   double dt;
@@ -339,6 +358,9 @@ typedef struct {
   blr_step_params step;
   double res_tol;     /* stop when err_ada <= res_tol (Sec. 5.1)  */
   int64_t max_steps;
+  int32_t defect_every; /* with BLR_STEP_FP64_DEFECT: steps between refreshes
+                           (<= 0: 4) */
+  int32_t reserved;     /* 0 */
 } blr_solve_params;
 
 typedef struct {

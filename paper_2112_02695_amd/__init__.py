@@ -30,6 +30,8 @@ BLR_STEP_FP64_COLLISION = 0x4
 BLR_STEP_HOUSEHOLDER_ADD = 0x8
 BLR_STEP_HOUSEHOLDER_QR = 0x10
 BLR_STEP_EAGER = 0x20
+BLR_STEP_FP64_DEFECT = 0x40
+BLR_STEP_DEFECT_REFRESH = 0x80
 
 (BLR_OK, BLR_ERR_ARG, BLR_ERR_NOMEM, BLR_ERR_HIP, BLR_ERR_UNSUPPORTED, BLR_ERR_NUMERIC,
  BLR_ERR_NOT_CONVERGED) = range(7)
@@ -84,7 +86,8 @@ class StepInfo(ctypes.Structure):
 
 
 class SolveParams(ctypes.Structure):
-    _fields_ = [("step", StepParams), ("res_tol", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+    _fields_ = [("step", StepParams), ("res_tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
+                ("defect_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

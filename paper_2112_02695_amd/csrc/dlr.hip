@@ -681,6 +681,84 @@ __global__ void k_to_f32_copy_S(const double* __restrict__ in, long count, float
       dst[(t / rs) * lds + t % rs] = src[(t / rs) * rs + t % rs];
 }
 
+// ------------------------------------------------ FP64 defect correction
+// Basis functions the defect correction carries (r_cap bound of the flag).
+constexpr int DEFECT_MAX = 32;
+
+// Index of the pair (a, b), a <= b, among the pairs of r functions in the
+// step's order (a-major, b from a up).
+__device__ __forceinline__ int pair_index(int a, int b, int r) {
+  return a * r - a * (a - 1) / 2 + (b - a);
+}
+
+// D = Q64 - Q32, element by element (the FP64 defect of the FP32 pairs).
+__global__ void k_defect_store(const double* __restrict__ Q64, const float* __restrict__ Q32,
+                               long count, double* __restrict__ D) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < count) D[e] = Q64[e] - (double)Q32[e];
+}
+
+// R (r x rr, row-major) into LDS with row stride DM, zeros elsewhere, so
+// that the fixed-length loops below read zeros past rr.
+template <int DM>
+__device__ __forceinline__ void load_rot(double* Rs, const double* __restrict__ R, int r, int rr) {
+  for (int i = threadIdx.x; i < DM * DM; i += blockDim.x) {
+    const int a = i / DM, m = i % DM;
+    Rs[i] = (a < r && m < rr) ? R[a * rr + m] : 0.0;
+  }
+  __syncthreads();
+}
+
+// First half of carrying the kept defect to the step's basis: for every
+// velocity point v, T[a][n](v) = sum_m R[a][m] D_mn(v) with D symmetric in
+// (m, n) and stored once per pair of the rr kept functions.  One thread per v.
+template <int DM>
+__global__ __launch_bounds__(64) void k_defect_carry1(const double* __restrict__ D, int rr,
+                                                      const double* __restrict__ R, int r, long nv,
+                                                      double* __restrict__ T) {
+  __shared__ double Rs[DM * DM];
+  load_rot<DM>(Rs, R, r, rr);
+  const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  for (int n = 0; n < rr; ++n) {
+    double col[DM];
+#pragma unroll
+    for (int m = 0; m < DM; ++m)
+      col[m] = m < rr ? D[(long)pair_index(m < n ? m : n, m < n ? n : m, rr) * nv + v] : 0.0;
+    for (int a = 0; a < r; ++a) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < DM; ++m) acc += Rs[a * DM + m] * col[m];
+      T[((long)a * rr + n) * nv + v] = acc;
+    }
+  }
+}
+
+// Second half: Q[p](v) = Q32[p](v) + sum_n R[b][n] T[a][n](v) for every pair
+// p = (a, b), a <= b, of the step's r functions.  One thread per v.
+template <int DM>
+__global__ __launch_bounds__(64) void k_defect_carry2(const double* __restrict__ T, int rr,
+                                                      const double* __restrict__ R, int r, long nv,
+                                                      const float* __restrict__ Q32,
+                                                      double* __restrict__ Q) {
+  __shared__ double Rs[DM * DM];
+  load_rot<DM>(Rs, R, r, rr);
+  const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  int p = 0;
+  for (int a = 0; a < r; ++a) {
+    double row[DM];
+#pragma unroll
+    for (int n = 0; n < DM; ++n) row[n] = n < rr ? T[((long)a * rr + n) * nv + v] : 0.0;
+    for (int b = a; b < r; ++b, ++p) {
+      double acc = 0.0;
+#pragma unroll
+      for (int n = 0; n < DM; ++n) acc += Rs[b * DM + n] * row[n];
+      Q[(long)p * nv + v] = (double)Q32[(long)p * nv + v] + acc;
+    }
+  }
+}
+
 // Commit after the drop decision: X_i = sum_l U[l][i] X1_l and V_i =
 // sum_l Wm[l][i] V1_l for i < keep (k_rows_comb), and S = diag(sig) (k_diag),
 // in one launch: grid.y = keep, x blocks over max(nx, n).
@@ -1822,6 +1900,12 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   }
   int* dpidx = (int*)ctx->upload("dlr.pidx", pidx.data(), pidx.size() * sizeof(int));
   const bool fp64c = (sp->flags & BLR_STEP_FP64_COLLISION) != 0;
+  // FP64 defect correction: a refresh step (FP64 pairs used, the defect kept)
+  // or a corrected step (FP32 pairs plus the kept defect); either steps with
+  // FP64 pair fields
+  const bool refresh = !fp64c && (sp->flags & BLR_STEP_DEFECT_REFRESH) != 0;
+  const bool corrected = !fp64c && !refresh && (sp->flags & BLR_STEP_FP64_DEFECT) != 0;
+  const bool q64 = fp64c || refresh || corrected;
   void* Qs;
   if (rec_events) BLR_HIP(hipEventRecord(ctx->ev[1], s));
   if (fp64c) {
@@ -1852,6 +1936,46 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
       ctx->collide_hook->collide(ctx, pb->v, V32, r, pairs, (float*)Qs);
     else
       collision_pairs(ctx, pb->v, BLR_FP32, V32, r, pairs.data(), P, Qs);
+    if (refresh) {
+      // the same pairs in FP64 drive this step; their difference from the
+      // FP32 ones is kept with the basis they were taken on
+      const int rc2 = rc * (rc + 1) / 2;
+      double* Q64 = w.get("Q64", (size_t)P * n);
+      collision_pairs(ctx, pb->v, BLR_FP64, Vw, r, pairs.data(), P, Q64);
+      double* Dk = (double*)ctx->buf("dlr.defect.D", (size_t)rc2 * n * 8);
+      double* Vk = (double*)ctx->buf("dlr.defect.V", (size_t)rc * n * 8);
+      hipLaunchKernelGGL(dk::k_defect_store, dim3(blocks((long)P * n, 256)), dim3(256), 0, s, Q64,
+                         (const float*)Qs, (long)P * n, Dk);
+      BLR_CHECK_LAUNCH();
+      BLR_HIP(hipMemcpyAsync(Vk, Vw, (size_t)r * n * 8, hipMemcpyDeviceToDevice, s));
+      Qs = Q64;
+    } else if (corrected) {
+      const int rr = ctx->defect_r;
+      require(rr >= 1 && rr <= dk::DEFECT_MAX && r <= dk::DEFECT_MAX, "defect correction: bad rank");
+      const int rc2 = rc * (rc + 1) / 2;
+      double* Dk = (double*)ctx->buf("dlr.defect.D", (size_t)rc2 * n * 8);
+      double* Vk = (double*)ctx->buf("dlr.defect.V", (size_t)rc * n * 8);
+      double* Rk = w.get("defect.R", (size_t)dk::DEFECT_MAX * dk::DEFECT_MAX);
+      double* Tk = w.get("defect.T", (size_t)rc * dk::DEFECT_MAX * n);
+      double* Qc = w.get("Q64", (size_t)P * n);
+      GramJob gj;
+      gj.add(Vw, r, Vk, rr, false, dk::W_ONE, dvd, Rk);  // R[a][m] = <W_a, V_m>
+      gj.run(w);
+      const dim3 grid(blocks(n, 64));
+      if (rr <= 16 && r <= 16) {
+        hipLaunchKernelGGL(dk::k_defect_carry1<16>, grid, dim3(64), 0, s, Dk, rr, Rk, r, (long)n, Tk);
+        BLR_CHECK_LAUNCH();
+        hipLaunchKernelGGL(dk::k_defect_carry2<16>, grid, dim3(64), 0, s, Tk, rr, Rk, r, (long)n,
+                           (const float*)Qs, Qc);
+      } else {
+        hipLaunchKernelGGL(dk::k_defect_carry1<32>, grid, dim3(64), 0, s, Dk, rr, Rk, r, (long)n, Tk);
+        BLR_CHECK_LAUNCH();
+        hipLaunchKernelGGL(dk::k_defect_carry2<32>, grid, dim3(64), 0, s, Tk, rr, Rk, r, (long)n,
+                           (const float*)Qs, Qc);
+      }
+      BLR_CHECK_LAUNCH();
+      Qs = Qc;
+    }
   }
   if (rec_events) BLR_HIP(hipEventRecord(ctx->ev[2], s));
   o.timed_collision = rec_events;
@@ -1866,7 +1990,7 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     gj.add(Vw, r, Vw, r, false, dk::W_VMINUS, dvd, Am);
     gj.add(Vw, r, Vw, r, false, dk::W_OUT_LEFT, dvd, MoL);
     gj.add(Vw, r, Vw, r, false, dk::W_OUT_RIGHT, dvd, MoR);
-    gj.add(Vw, r, Qs, P, !fp64c, dk::W_ONE, dvd, Cj);
+    gj.add(Vw, r, Qs, P, !q64, dk::W_ONE, dvd, Cj);
     gj.add(Vw, r, pb->f_left, 1, false, dk::W_IN_LEFT, dvd, ginL);
     gj.add(Vw, r, pb->f_right, 1, false, dk::W_IN_RIGHT, dvd, ginR);
     gj.run(w);
@@ -1971,7 +2095,7 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   if (r <= 16) {
     timed_begin("dlr.lstep", (double)n * (r + P + 2 * r) * 8.0, s);
     const dim3 grid(blocks(n, 64));
-    if (fp64c)
+    if (q64)
       hipLaunchKernelGGL(dk::k_lstep_mfma<double>, grid, dim3(256), 0, s, Vw, r, n, S2, Dp, Dm, T,
                          (const double*)Qs, P, dt, w.g, L1, dL);
     else
@@ -1982,7 +2106,7 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
   } else {
     const dim3 grid(blocks(n, 256), (r + 7) / 8);
     timed_begin("dlr.lstep", (double)n * (r + P + 2 * r) * 8.0, s);
-    if (fp64c)
+    if (q64)
       hipLaunchKernelGGL(dk::k_lstep<double>, grid, dim3(256), 0, s, Vw, r, n, S2, Dp, Dm, T,
                          (const double*)Qs, P, dt, w.g, L1, dL);
     else
@@ -2071,7 +2195,7 @@ void step_parse(Outcome& o) {
 
 // Key of a step attempt: every input that shapes the recorded work.
 std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_params* sp, bool add,
-                     const Attempt& at) {
+                     const Attempt& at, int defect_r) {
   struct {
     int32_t nx;
     double x_lo, x_hi;
@@ -2081,7 +2205,7 @@ std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_
     int32_t r, r_cap;
     const void *X, *S, *V;
     blr_step_params p;
-    int32_t add, rb, hh, hq;
+    int32_t add, rb, hh, hq, dr;
   } k;
   std::memset(&k, 0, sizeof(k));
   k.nx = pb->nx;
@@ -2102,6 +2226,7 @@ std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_
   k.rb = at.rb;
   k.hh = at.householder;
   k.hq = at.householder_qr;
+  k.dr = defect_r;
   return std::string((const char*)&k, sizeof(k));
 }
 
@@ -2111,7 +2236,10 @@ std::string step_key(const blr_problem* pb, const blr_state* st, const blr_step_
 void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const blr_step_params* sp,
                   const HostTables& h, bool add, Attempt at, Outcome& o) {
   hipStream_t s = ctx->stream;
-  const bool graphs = !(sp->flags & BLR_STEP_EAGER) && !ctx->timer.on;
+  // (a refresh step runs its FP32 pairs through the collide hook directly,
+  // so with a hook it is not recorded)
+  const bool graphs = !(sp->flags & BLR_STEP_EAGER) && !ctx->timer.on &&
+                      !((sp->flags & BLR_STEP_DEFECT_REFRESH) && ctx->collide_hook);
   auto eager = [&]() {
     step_enqueue(ctx, pb, st, sp, h, add, at, o, true);
     BLR_HIP(hipStreamSynchronize(s));
@@ -2122,7 +2250,10 @@ void step_attempt(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
     return;
   }
   // (with collide_hook the recording is split around the collisions)
-  const std::string key = step_key(pb, st, sp, add, at) + (ctx->collide_hook ? "h" : "");
+  // a corrected step's launches depend on the rank of the kept defect
+  const bool corrected = (sp->flags & BLR_STEP_FP64_DEFECT) && !(sp->flags & BLR_STEP_DEFECT_REFRESH);
+  const std::string key =
+      step_key(pb, st, sp, add, at, corrected ? ctx->defect_r : 0) + (ctx->collide_hook ? "h" : "");
   auto& gs = ctx->graphs;
   size_t gi = gs.size();
   for (size_t k = 0; k < gs.size(); ++k)
@@ -2287,6 +2418,8 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
   require(st->r_cap >= 1 && st->r_cap <= 64, "state.r_cap must be in [1, 64]");
   require(st->r >= 1 && st->r <= st->r_cap, "state.r must be in [1, r_cap]");
   require(sp->dt > 0 && std::isfinite(sp->dt), "step.dt must be positive");
+  require(!(sp->flags & (BLR_STEP_FP64_DEFECT | BLR_STEP_DEFECT_REFRESH)),
+          "the FP64 defect correction is for 1D space only", BLR_ERR_UNSUPPORTED);
   const HostTables& h = get_tables(ctx, pb->v, BLR_FP64).h;
   hipStream_t s = ctx->stream;
   const int nx = pb->nx, ny = pb->ny, n = h.n, rc = st->r_cap, r_in = st->r;
@@ -2678,6 +2811,23 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   blr_step_info inf{};
   inf.r_in = st->r;
 
+  // FP64 defect correction: refresh when asked, or when the context keeps no
+  // defect for this velocity grid
+  blr_step_params spx = *sp;
+  const bool defect = (sp->flags & BLR_STEP_FP64_DEFECT) != 0;
+  require(defect || !(sp->flags & BLR_STEP_DEFECT_REFRESH),
+          "BLR_STEP_DEFECT_REFRESH needs BLR_STEP_FP64_DEFECT");
+  if (defect) {
+    require(!(sp->flags & BLR_STEP_FP64_COLLISION),
+            "BLR_STEP_FP64_DEFECT corrects FP32 collisions: not with BLR_STEP_FP64_COLLISION");
+    require(rc <= dk::DEFECT_MAX, "BLR_STEP_FP64_DEFECT needs state.r_cap <= 32");
+    if (ctx->defect_r == 0 || std::memcmp(&ctx->defect_vg, &pb->v, sizeof(blr_vgrid)) != 0)
+      spx.flags |= BLR_STEP_DEFECT_REFRESH;
+    // a refresh that does not finish leaves no usable defect
+    if (spx.flags & BLR_STEP_DEFECT_REFRESH) ctx->defect_r = 0;
+  }
+  sp = &spx;
+
   // The number of boundary functions to add is known only from the singular
   // values of F_b on the device.  The step runs with the count of the
   // previous step (2 at first) and is repeated, from the unchanged state,
@@ -2714,6 +2864,10 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
   }
   inf.r_added = at.rb;
   const int r = o.r;
+  if (spx.flags & BLR_STEP_DEFECT_REFRESH) {
+    ctx->defect_r = r;
+    ctx->defect_vg = pb->v;
+  }
 
   const double err = std::sqrt(std::max(o.res[0], 0.0));
   require(std::isfinite(err), "non-finite residual", BLR_ERR_NUMERIC);
@@ -2862,11 +3016,17 @@ void steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state, const bl
       (void)hipEventDestroy(b);
     }
   } guard{e0, e1};
+  // FP64 defect correction: a refresh on the first step and every
+  // defect_every steps
+  const bool defect = (p->step.flags & BLR_STEP_FP64_DEFECT) != 0;
+  const int64_t every = p->defect_every > 0 ? p->defect_every : 4;
   BLR_HIP(hipEventRecord(e0, ctx->stream));
   for (int64_t k = 0; k < p->max_steps; ++k) {
     if (cancel && cancel->load(std::memory_order_relaxed)) break;
     blr_step_info si{};
-    dlr_step(ctx, pb, state, &p->step, &si);
+    blr_step_params spk = p->step;
+    if (defect && k % every == 0) spk.flags |= BLR_STEP_DEFECT_REFRESH;
+    dlr_step(ctx, pb, state, &spk, &si);
     const int64_t rk = si.r_in + si.r_added;
     info->pair_evals += rk * (rk + 1) / 2;
     info->steps = k + 1;
@@ -2888,7 +3048,8 @@ void steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state, const bl
 // workspace at r_cap plus the step's named buffers (velocity-side arrays of
 // r_cap rows: working copy, L-step result and update, new basis, QR scratch;
 // the pair collisions; x-side arrays).  An estimate used for admission.
-size_t solve_workspace_bytes(const blr_vgrid& vg, int nx, int r_cap, bool fp64_collision) {
+size_t solve_workspace_bytes(const blr_vgrid& vg, int nx, int r_cap, bool fp64_collision,
+                             bool defect) {
   validate_vgrid(vg);
   require(nx >= 1 && r_cap >= 1 && r_cap <= 64, "bad solve shape");
   const size_t n = (size_t)std::llround(std::pow((double)vg.n, vg.d));
@@ -2897,6 +3058,13 @@ size_t solve_workspace_bytes(const blr_vgrid& vg, int nx, int r_cap, bool fp64_c
   b += (size_t)r_cap * n * 8 * 6;
   b += fp64_collision ? P * n * 8 : P * n * 4 + (size_t)r_cap * n * 4;
   b += (size_t)r_cap * nx * 8 * 8 + (size_t)P * r_cap * 8 * 4 + (8u << 20);
+  if (defect && !fp64_collision) {
+    // FP64 pairs and the FP64 collision workspace; the kept defect and basis;
+    // the carried halves
+    b += P * n * 8 + collision_workspace_bytes(vg, r_cap, BLR_FP64);
+    b += P * n * 8 + (size_t)r_cap * n * 8;
+    b += (size_t)r_cap * std::min(r_cap, 32) * n * 8;
+  }
   return b;
 }
 

@@ -145,6 +145,12 @@ struct blr_ctx_t {
   size_t readback_bytes = 0;
   // number of boundary basis functions added by the previous adaptive step
   int add_hint = -1;
+  // FP64 defect of the FP32 pair collisions kept by the last refresh step
+  // (BLR_STEP_FP64_DEFECT): the basis rank at its collisions (0: none kept)
+  // and its velocity grid; the defect and the basis live in the buffers
+  // "dlr.defect.D" and "dlr.defect.V"
+  int defect_r = 0;
+  blr_vgrid defect_vg{};
   // compute units of the device (queried once)
   int ncu = 0;
   int cu_count();
@@ -261,6 +267,7 @@ void dlr_step(blr_ctx ctx, const blr_problem* pb, blr_state* st, const blr_step_
               blr_step_info* info);
 void steady_solve(blr_ctx ctx, const blr_problem* pb, blr_state* state, const blr_solve_params* p,
                   blr_solve_info* info, const std::atomic<bool>* cancel = nullptr);
-size_t solve_workspace_bytes(const blr_vgrid& vg, int nx, int r_cap, bool fp64_collision);
+size_t solve_workspace_bytes(const blr_vgrid& vg, int nx, int r_cap, bool fp64_collision,
+                             bool defect = false);
 
 }  // namespace blr

@@ -426,7 +426,9 @@ blr_status blr_server_submit(blr_server sv, const blr_request* req) {
     // cells: nx, or nx ny on a rectangle (the x-side arrays scale with them)
     const long cells = (long)req->problem.nx * (req->problem.ny >= 2 ? req->problem.ny : 1);
     if (cells > (1L << 22)) throw blr::Error(BLR_ERR_ARG, "problem.nx * ny must be <= 2^22");
-    const size_t need = blr::solve_workspace_bytes(req->problem.v, (int)cells, st->r_cap, fp64c);
+    const bool defect = (req->solve.step.flags & BLR_STEP_FP64_DEFECT) != 0;
+    const size_t need =
+        blr::solve_workspace_bytes(req->problem.v, (int)cells, st->r_cap, fp64c, defect);
     blr::require(sv->budget <= 0 || need <= (size_t)sv->budget,
                  "request needs " + std::to_string(need) + " bytes of device memory, more than the "
                  "server's budget of " + std::to_string(sv->budget), BLR_ERR_NOMEM);
