@@ -165,7 +165,7 @@ def progress(msg):
 
 
 def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol=1e-6,
-              moments_of=(), batch=False, fp64=False):
+              moments_of=(), batch=False, fp64=False, defect=False):
     """Serve the requests at their arrival times; latency = completion time -
     arrival (submit) time on the server's clock.  For the request indices in
     moments_of, the steady rho, u_1, T per cell are returned as well."""
@@ -189,11 +189,15 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
 
     def params(q, steps):
         flags = blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | (
-            blr.BLR_STEP_FP64_COLLISION if (plain or fp64) else 0)
-        return blr.SolveParams(blr.StepParams(q["dt"], 0.2, 1e-10, 1, r_cap, flags), res_tol, steps)
+            blr.BLR_STEP_FP64_COLLISION if (plain or fp64) else 0) | (
+            blr.BLR_STEP_FP64_DEFECT if defect else 0)
+        p = blr.SolveParams(blr.StepParams(q["dt"], 0.2, 1e-10, 1, r_cap, flags), res_tol, steps)
+        p.defect_every = 4
+        return p
 
     progress(f"serving trace: {len(prepared)} requests, {slots} slot(s), "
              f"{'plain fp64' if plain else ('batched fp64' if fp64 else 'batched fp32')}"
+             f"{' with the fp64 defect correction' if defect else ''}"
              f"{', collisions of all live solves in shared launches' if batch else ''}, "
              f"cap {cap} steps")
     sv = blr.Server(0, slots=slots, batch_collisions=batch)
@@ -762,6 +766,29 @@ def cavity_leg(args, blr, synth, torch, ctx, kind="lid"):
             "max_rel_diff_low_rank_vs_full": diffs}
 
 
+def steady_compare_leg(args, blr, synth, torch, helper):
+    """One solve of the 2D-velocity converged-trace recipe marched a fixed
+    number of steps past the stopping rule with FP32, corrected FP32 and FP64
+    collisions; the steady moments of the first two against the third."""
+    import numpy as np
+    ct = synth.serving_trace_2d(count=1, seed=6, rate=4.0)
+    cp = prepare_trace(ct, synth)
+    n = args.steady_compare
+    legs = {}
+    for name, kw in (("fp32", {}), ("fp32_defect", {"defect": True}), ("fp64", {"fp64": True})):
+        rr, mm = run_trace(blr, torch, helper, cp, 1, False, n, res_tol=0.0, moments_of=(0,), **kw)
+        legs[name] = (rr, mm[0])
+    return {
+        "steps": n, "target": 1e-6,
+        **{name: {"err_ada": legs[name][0].get("final_err_ada"), "wall_s": legs[name][0]["wall_s"],
+                  "moments_max_rel_diff": {
+                      nm: float(np.abs(a - c).max() / np.abs(c).max())
+                      for nm, a, c in zip(("rho", "u1", "T"), legs[name][1], legs["fp64"][1])}}
+           for name in ("fp32", "fp32_defect")},
+        "fp64": {"err_ada": legs["fp64"][0].get("final_err_ada"),
+                 "wall_s": legs["fp64"][0]["wall_s"]}}
+
+
 def serving_leg(args, blr, synth, torch, helper):
     """The serving trace on the batched FP32 path (slots solves at once) and on
     the plain FP64 per-pair path (one solve at a time, first in first out),
@@ -809,21 +836,13 @@ def serving_leg(args, blr, synth, torch, helper):
                 nm: float(np.abs(a - c).max() / np.abs(c).max())
                 for nm, a, c in zip(("rho", "u1", "T"), m32[0], m64[0])}
             out["converged_fp32_vs_fp64_steady_moments"]["target"] = 1e-6
-    if args.steady_compare > 0:
-        # the same solve marched a fixed number of steps past the stopping rule in
-        # both precisions: the steady state itself, not where err_ada first dips
-        ct = synth.serving_trace_2d(count=1, seed=6, rate=4.0)
-        cp = prepare_trace(ct, synth)
-        n = args.steady_compare
-        r32, m32 = run_trace(blr, torch, helper, cp, 1, False, n, res_tol=0.0, moments_of=(0,))
-        r64, m64 = run_trace(blr, torch, helper, cp, 1, False, n, res_tol=0.0, moments_of=(0,),
-                             fp64=True)
-        out["fixed_steps_fp32_vs_fp64"] = {
-            "steps": n, "fp32_err_ada": r32.get("final_err_ada"), "fp64_err_ada": r64.get("final_err_ada"),
-            "fp32_wall_s": r32["wall_s"], "fp64_wall_s": r64["wall_s"],
-            "moments_max_rel_diff": {nm: float(np.abs(a - c).max() / np.abs(c).max())
-                                     for nm, a, c in zip(("rho", "u1", "T"), m32[0], m64[0])},
-            "target": 1e-6}
+            # the same with the FP64 defect correction of the FP32 pairs
+            bd, md = run_trace(blr, torch, helper, cp[:nplain], args.serve_slots, False,
+                               args.serve_conv_cap, moments_of=(0,), defect=True)
+            out["converged_fp32_defect_same_subset"] = bd
+            out["converged_fp32_defect_vs_fp64_steady_moments"] = {
+                nm: float(np.abs(a - c).max() / np.abs(c).max())
+                for nm, a, c in zip(("rho", "u1", "T"), md[0], m64[0])}
     if args.serve_long_count > 0:
         long_trace = synth.serving_trace(count=args.serve_long_count, seed=5, rate=4.0)
         lp = prepare_trace(long_trace, synth)
@@ -1152,6 +1171,37 @@ def main():
                         "plain_samples": len(pw),
                         "plain_over_batched_p50": round(pct(pw, 0.5) / pct(step_wall, 0.5), 1)})
 
+    # the same step with FP64 collisions on the fast schedule, and with the
+    # FP64 defect correction of the FP32 pairs (a refresh step: FP64 and FP32
+    # pairs; a corrected step: FP32 pairs plus the carried defect)
+    if args.mode == "step" and not args.no_plain:
+        progress("fp64 and defect-corrected steps")
+        ms = {}
+        for name, fl in (("fp64_collision", blr.BLR_STEP_FP64_COLLISION),
+                         ("defect_refresh", blr.BLR_STEP_FP64_DEFECT | blr.BLR_STEP_DEFECT_REFRESH),
+                         ("defect_corrected", blr.BLR_STEP_FP64_DEFECT)):
+            Xq, Sq, Vq = Xd.clone(), Sd.clone(), Vd.clone()
+            Xq.zero_(); Sq.zero_(); Vq.zero_()
+            Xq[:r] = torch.tensor(X.T, device=dev)
+            Sq[:r, :r] = torch.tensor(S, device=dev)
+            Vq[:r] = torch.tensor(V, device=dev)
+            stq = ctx.make_state(Xq, Sq, Vq, r, seed=1)
+            spq = blr.StepParams(dt, 0.2, 1e-10, r, r_cap, blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | fl)
+            for _ in range(2):   # the first recording of the step graph
+                ctx.dlr_step(pb, stq, spq)
+            torch.cuda.synchronize()
+            tw = []
+            for _ in range(5):
+                ts = time.perf_counter()
+                ctx.dlr_step(pb, stq, spq)
+                tw.append(time.perf_counter() - ts)
+            ms[name] = round(1e3 * pct(tw, 0.5), 3)
+        latency.update({"fp64_collision_step_ms_p50": ms["fp64_collision"],
+                        "defect_refresh_step_ms_p50": ms["defect_refresh"],
+                        "defect_corrected_step_ms_p50": ms["defect_corrected"],
+                        "defect_every_4_step_ms": round(
+                            (ms["defect_refresh"] + 3 * ms["defect_corrected"]) / 4, 3)})
+
     # the full-tensor reference step on the same grid (Q(f(x_p), f(x_p)) for
     # all N_x cells plus upwind transport), FP32 collisions as in the step
     full = None
@@ -1209,6 +1259,9 @@ def main():
     serving = None
     if args.mode == "step" and not args.no_serve:
         serving = serving_leg(args, blr, synth, torch, ctx)
+    if args.steady_compare > 0:
+        serving = dict(serving or {})
+        serving["fixed_steps_vs_fp64"] = steady_compare_leg(args, blr, synth, torch, ctx)
 
     parity = None
     if not args.no_parity:
