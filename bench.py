@@ -258,7 +258,9 @@ def run_trace(blr, torch, helper, prepared, slots, plain, cap, r_cap=30, res_tol
         rho = F.sum(axis=1) * w
         u = (F * v[0]).sum(axis=1) * w / rho
         e2 = (F * (v ** 2).sum(axis=0)).sum(axis=1) * w / rho
-        moments[i] = (rho, u, (e2 - u * u) / sp.d)
+        # |u|^2 over every velocity component
+        uu = sum(((F * v[k]).sum(axis=1) * w / rho) ** 2 for k in range(sp.d))
+        moments[i] = (rho, u, (e2 - uu) / sp.d)
     out = {"slots": slots, "requests": len(comps), "step_cap": cap,
             "latency_s_p50": round(pct(lat, 0.50), 4), "latency_s_p99": round(pct(lat, 0.99), 4),
             "queue_wait_s_p50": round(pct([c.t_admit - c.t_submit for c in comps], 0.5), 4),
@@ -983,6 +985,49 @@ def parity_leg(blr, synth, torch, ctx):
                     d = h["c2k_dfdt"]
                     out[f"{key}_{tag}_vs_analytic_dfdt"] = float(np.abs(q - d).max() /
                                                                  np.abs(d).max())
+    try:
+        gs = np.load(os.path.join(gdir, "steady_shock_2d.npz"))
+    except OSError:
+        gs = None
+    if gs is not None:
+        # the oracle's steady solve of a small Mach-1.4 shock (2D velocity 32^2,
+        # Maxwell molecules, 32 cells, dt 0.1, err_ada <= 1e-6) against the
+        # library's in each collision precision: rho, u_1, T per cell
+        spec = synth.VGridSpec(d=2, n=32, L=8.0, gamma=0.0, C=1.0 / (2.0 * math.pi), m_rho=8,
+                               m_sigma=8)
+        nx, r0, rc = 32, 6, 16
+        ini = synth.shock_initial(1.4, spec, nx, -30.0, 30.0, pert=1e-3, pert_rank=3, seed=7)
+        dvd = (2.0 * spec.L / spec.n) ** 2
+        X0, S0, V0 = synth.lowrank_state(ini["f0"], r0, 60.0 / nx, dvd)
+        v = synth.vgrid_points(2, spec.n, spec.L).reshape(2, -1)
+        fL, fR = torch.tensor(ini["fL"], device=dev), torch.tensor(ini["fR"], device=dev)
+        pb = ctx.make_problem(blr.vgrid_from_spec(spec), nx, -30.0, 30.0, fL, fR)
+        res = {"oracle_steps": int(gs["steps"])}
+        for name, fl in (("fp32", 0), ("fp32_defect", blr.BLR_STEP_FP64_DEFECT),
+                         ("fp64", blr.BLR_STEP_FP64_COLLISION)):
+            X = torch.zeros((rc, nx), dtype=torch.float64, device=dev)
+            S = torch.zeros((rc, rc), dtype=torch.float64, device=dev)
+            V = torch.zeros((rc, spec.n ** 2), dtype=torch.float64, device=dev)
+            X[:r0] = torch.tensor(np.ascontiguousarray(X0.T), device=dev)
+            S[:r0, :r0] = torch.tensor(S0, device=dev)
+            V[:r0] = torch.tensor(V0, device=dev)
+            st = ctx.make_state(X, S, V, r0)
+            sp = blr.SolveParams(blr.StepParams(0.1, 0.2, 1e-10, 1, 16,
+                                                blr.BLR_STEP_ADD | blr.BLR_STEP_DROP | fl),
+                                 1e-6, 8000)
+            sp.defect_every = 4
+            info = ctx.steady_solve(pb, st, sp)
+            r = st.r
+            F = (X[:r].cpu().numpy().T @ S[:r, :r].cpu().numpy()) @ V[:r].cpu().numpy()
+            rho = F.sum(axis=1) * dvd
+            u = (F * v[0]).sum(axis=1) * dvd / rho
+            u2 = (F * v[1]).sum(axis=1) * dvd / rho
+            T = ((F * (v ** 2).sum(axis=0)).sum(axis=1) * dvd / rho - u * u - u2 * u2) / 2.0
+            res[name] = {"steps": int(info.steps), "moments_max_rel_err": max(
+                float(np.abs(a - b).max() / np.abs(b).max())
+                for a, b in ((rho, gs["rho"]), (u, gs["u"]), (T, gs["T"])))}
+        res["target"] = 1e-6
+        out["steady_shock_2d_moments_vs_oracle"] = res
     out["measure"] = ("pair / single evaluations: ||Q - Q_ref||_2 / ||Q+_ref||_2 (targets 1e-5 FP32, "
                       "1e-12 FP64); step: L2(x,v) norm of f - f_ref against the FP32 collision "
                       "bound 1e-5 dt ||sum K_m K_n Q+_mn||, and max |f - f_ref| / max |f_ref|")

@@ -162,7 +162,8 @@ def _moments(req, st, arrs):
     rho = f.sum(axis=1) * w
     u = (f * v[0]).sum(axis=1) * w / rho
     e2 = (f * (v ** 2).sum(axis=0)).sum(axis=1) * w / rho
-    return rho, u, (e2 - u * u) / sp.d
+    uu = sum(((f * v[k]).sum(axis=1) * w / rho) ** 2 for k in range(sp.d))
+    return rho, u, (e2 - uu) / sp.d
 
 
 @pytest.mark.slow
