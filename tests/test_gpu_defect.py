@@ -195,11 +195,15 @@ def test_long_solve_follows_the_fp64_solve(ctx):
     assert gaps["corr"] <= 0.05 * gaps["fp32"]
 
 
-def test_served_alone_and_in_the_mix(ctx):
+@pytest.mark.parametrize("batch", [False, True])
+def test_served_alone_and_in_the_mix(ctx, batch):
+    """With batch_collisions the FP32 pairs of the corrected steps and of the
+    refresh steps go through the shared launches (a refresh step then runs
+    without a recorded graph)."""
     reqs = [Req(3, 16, 4, 24, 3 + k, 1.4 + 0.2 * k, 30 + k) for k in range(3)]
 
     def serve(jobs, slots):
-        sv = blr.Server(0, slots=slots)
+        sv = blr.Server(0, slots=slots, batch_collisions=batch)
         keep, comps = {}, []
         try:
             for k in jobs:
@@ -223,7 +227,7 @@ def test_served_alone_and_in_the_mix(ctx):
             out[c.tag] = (c.info.steps, c.info.r, c.info.err_ada, _f(st, arrs))
         return out
 
-    print("defect: 3 served solves alone, then together", flush=True)
+    print(f"defect: 3 served solves alone, then together (shared launches: {batch})", flush=True)
     alone = {}
     for k in range(3):
         alone.update(serve([k], 1))
