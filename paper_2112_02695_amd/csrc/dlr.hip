@@ -711,7 +711,8 @@ __device__ __forceinline__ void load_rot(double* Rs, const double* __restrict__ 
 
 // First half of carrying the kept defect to the step's basis: for every
 // velocity point v, T[a][n](v) = sum_m R[a][m] D_mn(v) with D symmetric in
-// (m, n) and stored once per pair of the rr kept functions.  One thread per v.
+// (m, n) and stored once per pair of the rr kept functions.  One thread per
+// (v, n): grid (velocity blocks, rr).
 template <int DM>
 __global__ __launch_bounds__(64) void k_defect_carry1(const double* __restrict__ D, int rr,
                                                       const double* __restrict__ R, int r, long nv,
@@ -719,23 +720,23 @@ __global__ __launch_bounds__(64) void k_defect_carry1(const double* __restrict__
   __shared__ double Rs[DM * DM];
   load_rot<DM>(Rs, R, r, rr);
   const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
   if (v >= nv) return;
-  for (int n = 0; n < rr; ++n) {
-    double col[DM];
+  double col[DM];
 #pragma unroll
-    for (int m = 0; m < DM; ++m)
-      col[m] = m < rr ? D[(long)pair_index(m < n ? m : n, m < n ? n : m, rr) * nv + v] : 0.0;
-    for (int a = 0; a < r; ++a) {
-      double acc = 0.0;
+  for (int m = 0; m < DM; ++m)
+    col[m] = m < rr ? D[(long)pair_index(m < n ? m : n, m < n ? n : m, rr) * nv + v] : 0.0;
+  for (int a = 0; a < r; ++a) {
+    double acc = 0.0;
 #pragma unroll
-      for (int m = 0; m < DM; ++m) acc += Rs[a * DM + m] * col[m];
-      T[((long)a * rr + n) * nv + v] = acc;
-    }
+    for (int m = 0; m < DM; ++m) acc += Rs[a * DM + m] * col[m];
+    T[((long)a * rr + n) * nv + v] = acc;
   }
 }
 
 // Second half: Q[p](v) = Q32[p](v) + sum_n R[b][n] T[a][n](v) for every pair
-// p = (a, b), a <= b, of the step's r functions.  One thread per v.
+// p = (a, b), a <= b, of the step's r functions.  One thread per (v, a):
+// grid (velocity blocks, r).
 template <int DM>
 __global__ __launch_bounds__(64) void k_defect_carry2(const double* __restrict__ T, int rr,
                                                       const double* __restrict__ R, int r, long nv,
@@ -744,18 +745,17 @@ __global__ __launch_bounds__(64) void k_defect_carry2(const double* __restrict__
   __shared__ double Rs[DM * DM];
   load_rot<DM>(Rs, R, r, rr);
   const long v = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
   if (v >= nv) return;
-  int p = 0;
-  for (int a = 0; a < r; ++a) {
-    double row[DM];
+  double row[DM];
 #pragma unroll
-    for (int n = 0; n < DM; ++n) row[n] = n < rr ? T[((long)a * rr + n) * nv + v] : 0.0;
-    for (int b = a; b < r; ++b, ++p) {
-      double acc = 0.0;
+  for (int n = 0; n < DM; ++n) row[n] = n < rr ? T[((long)a * rr + n) * nv + v] : 0.0;
+  for (int b = a; b < r; ++b) {
+    const long p = pair_index(a, b, r);
+    double acc = 0.0;
 #pragma unroll
-      for (int n = 0; n < DM; ++n) acc += Rs[b * DM + n] * row[n];
-      Q[(long)p * nv + v] = (double)Q32[(long)p * nv + v] + acc;
-    }
+    for (int n = 0; n < DM; ++n) acc += Rs[b * DM + n] * row[n];
+    Q[p * nv + v] = (double)Q32[p * nv + v] + acc;
   }
 }
 
@@ -1961,16 +1961,16 @@ void step_enqueue(blr_ctx ctx, const blr_problem* pb, const blr_state* st, const
       GramJob gj;
       gj.add(Vw, r, Vk, rr, false, dk::W_ONE, dvd, Rk);  // R[a][m] = <W_a, V_m>
       gj.run(w);
-      const dim3 grid(blocks(n, 64));
+      const dim3 g1(blocks(n, 64), rr), g2(blocks(n, 64), r);
       if (rr <= 16 && r <= 16) {
-        hipLaunchKernelGGL(dk::k_defect_carry1<16>, grid, dim3(64), 0, s, Dk, rr, Rk, r, (long)n, Tk);
+        hipLaunchKernelGGL(dk::k_defect_carry1<16>, g1, dim3(64), 0, s, Dk, rr, Rk, r, (long)n, Tk);
         BLR_CHECK_LAUNCH();
-        hipLaunchKernelGGL(dk::k_defect_carry2<16>, grid, dim3(64), 0, s, Tk, rr, Rk, r, (long)n,
+        hipLaunchKernelGGL(dk::k_defect_carry2<16>, g2, dim3(64), 0, s, Tk, rr, Rk, r, (long)n,
                            (const float*)Qs, Qc);
       } else {
-        hipLaunchKernelGGL(dk::k_defect_carry1<32>, grid, dim3(64), 0, s, Dk, rr, Rk, r, (long)n, Tk);
+        hipLaunchKernelGGL(dk::k_defect_carry1<32>, g1, dim3(64), 0, s, Dk, rr, Rk, r, (long)n, Tk);
         BLR_CHECK_LAUNCH();
-        hipLaunchKernelGGL(dk::k_defect_carry2<32>, grid, dim3(64), 0, s, Tk, rr, Rk, r, (long)n,
+        hipLaunchKernelGGL(dk::k_defect_carry2<32>, g2, dim3(64), 0, s, Tk, rr, Rk, r, (long)n,
                            (const float*)Qs, Qc);
       }
       BLR_CHECK_LAUNCH();
