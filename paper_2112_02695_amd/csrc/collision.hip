@@ -85,15 +85,79 @@ static void line_pass(hipStream_t s, const Ld& ld, const St& st, int axis, long 
   BLR_CHECK_LAUNCH();
 }
 
-// full D-dimensional transform: first axis (D-1) uses ld, last (0) uses st
+// The first two axes of a 3D transform in one launch (axis 2 loaded through
+// `ld`, axis 1 stored through `st`): each group of N threads takes one plane
+// i0 of one field, one line per thread, and the plane passes through LDS
+// between the two axes.  The line transforms are those of two line passes;
+// only the round trip of the plane through memory is gone.
+template <int N>
+constexpr int planes_per_block() {
+  return 64 / N > 0 ? 64 / N : 1;
+}
+
+template <typename T, int N, int DIR, class Ld, class St>
+__global__ __launch_bounds__(64) void k_plane_pass(Ld ld, St st, long nplanes) {
+  constexpr int PPB = planes_per_block<N>();
+  // one component at a time through one array (half the LDS, so that more
+  // workgroups fit a CU)
+  __shared__ T pl[PPB][N][N + 1];
+  const int q = threadIdx.x / N, u = threadIdx.x % N;
+  const long g = blockIdx.x * (long)PPB + q;
+  const bool ok = g < nplanes;
+  const long f = g / N;
+  const int i0 = (int)(g % N);
+  T re[N], im[N];
+  if (ok) {
+    // line (i0, i1 = u) along axis 2
+    ld.template load<N>(f, (i0 * N + u) * N, 1, re, im);
+    fft::dft<T, N, DIR>(re, im);
+#pragma unroll
+    for (int j = 0; j < N; ++j) pl[q][u][j] = re[j];
+  }
+  __syncthreads();
+  // line (i0, i2 = u) along axis 1
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) re[j] = pl[q][j][u];
+  }
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) pl[q][u][j] = im[j];
+  }
+  __syncthreads();
+  if (!ok) return;
+#pragma unroll
+  for (int j = 0; j < N; ++j) im[j] = pl[q][j][u];
+  fft::dft<T, N, DIR>(re, im);
+  st.template store<N>(f, i0 * N * N + u, N, re, im);
+}
+
+template <typename T, int N, int DIR, class Ld, class St>
+static void plane_pass(hipStream_t s, const Ld& ld, const St& st, long nfields) {
+  constexpr int PPB = planes_per_block<N>();
+  const long np = nfields * N;
+  const long nb = (np + PPB - 1) / PPB;
+  constexpr int n = N * N * N;
+  TimedScope ts(s, std::string(g_stage) + ".axis21",
+                (double)nfields * n * (Ld::bpe + St::bpe) * sizeof(T));
+  hipLaunchKernelGGL((k_plane_pass<T, N, DIR, Ld, St>), dim3((unsigned)nb), dim3(PPB * N), 0, s,
+                     ld, st, np);
+  BLR_CHECK_LAUNCH();
+}
+
+// full D-dimensional transform: first axis (D-1) uses ld, last (0) uses st;
+// in 3D the axes 2 and 1 in one plane pass
 template <typename T, int N, int D, int DIR, class Ld, class St>
 static void transform(hipStream_t s, const Ld& ld, const St& st, typename Vec2<T>::t* tmp,
                       long nfields) {
   constexpr int n = (D == 2 ? N * N : N * N * N);
   StComplex<T> stc{tmp, n};
   LdComplex<T> ldc{tmp, n};
-  line_pass<T, N, D, DIR>(s, ld, stc, D - 1, nfields);
-  if constexpr (D == 3) line_pass<T, N, D, DIR>(s, ldc, stc, 1, nfields);
+  if constexpr (D == 3)
+    plane_pass<T, N, DIR>(s, ld, stc, nfields);
+  else
+    line_pass<T, N, D, DIR>(s, ld, stc, D - 1, nfields);
   line_pass<T, N, D, DIR>(s, ldc, st, 0, nfields);
 }
 
@@ -381,7 +445,7 @@ struct Generic {
     auto tiles = self ? std::vector<ReduceTile>{} : plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
     for (const auto& t : tiles) {
       const bool diag = t.bi[0] == t.bj[0];
-      const int bs = 256;
+      const int bs = 64;
       const dim3 grid((n + bs - 1) / bs);
       int nvalid = 0;
       for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
@@ -504,7 +568,7 @@ struct Generic {
                    h.msig, h.nbp, a, P);
       for (const auto& t : tiles) {
         const bool diag = t.bi[0] == t.bj[0];
-        const int bs = 256;
+        const int bs = 64;  // more workgroups than CUs even at 32^3
         const dim3 grid((n + bs - 1) / bs);
         int nvalid = 0;
         for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
