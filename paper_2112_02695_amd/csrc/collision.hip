@@ -146,19 +146,52 @@ static void plane_pass(hipStream_t s, const Ld& ld, const St& st, long nfields) 
   BLR_CHECK_LAUNCH();
 }
 
-// full D-dimensional transform: first axis (D-1) uses ld, last (0) uses st;
-// in 3D the axes 2 and 1 in one plane pass
+// every axis of a D-dimensional transform but the last (0): axis D-1 loaded
+// through ld, the result stored through st; in 3D the axes 2 and 1 in one
+// plane pass
+template <typename T, int N, int D, int DIR, class Ld, class St>
+static void first_axes(hipStream_t s, const Ld& ld, const St& st, long nfields) {
+  if constexpr (D == 3)
+    plane_pass<T, N, DIR>(s, ld, st, nfields);
+  else
+    line_pass<T, N, D, DIR>(s, ld, st, D - 1, nfields);
+}
+
+// full D-dimensional transform: first axis (D-1) uses ld, last (0) uses st
 template <typename T, int N, int D, int DIR, class Ld, class St>
 static void transform(hipStream_t s, const Ld& ld, const St& st, typename Vec2<T>::t* tmp,
                       long nfields) {
   constexpr int n = (D == 2 ? N * N : N * N * N);
   StComplex<T> stc{tmp, n};
   LdComplex<T> ldc{tmp, n};
-  if constexpr (D == 3)
-    plane_pass<T, N, DIR>(s, ld, stc, nfields);
-  else
-    line_pass<T, N, D, DIR>(s, ld, stc, D - 1, nfields);
+  first_axes<T, N, D, DIR>(s, ld, stc, nfields);
   line_pass<T, N, D, DIR>(s, ldc, st, 0, nfields);
+}
+
+// The last axis of the pair transforms of na radial nodes (fields k P + p of
+// tmp, k = a - a0), each accumulated with its radial weights into pair p's
+// couple spectrum G[p]: one thread per line of a pair, the nodes in turn.
+template <typename T, int N, int D>
+__global__ __launch_bounds__(128) void k_accum_radial(const typename Vec2<T>::t* __restrict__ tmp,
+                                                      typename Vec2<T>::t* __restrict__ G,
+                                                      const T* __restrict__ fw, int nkk, long P,
+                                                      int a0, int na, long nlines) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= nlines) return;
+  accum_radial_thread<T, N, D>(t, tmp, G, fw, nkk, P, a0, na);
+}
+
+template <typename T, int N, int D>
+static void accum_radial(hipStream_t s, const typename Vec2<T>::t* tmp, typename Vec2<T>::t* G,
+                         const T* fw, int nkk, long P, int a0, int na) {
+  constexpr int lines = (D == 2 ? N : N * N);
+  constexpr int n = (D == 2 ? N * N : N * N * N);
+  const long nl = P * lines;
+  const int bs = 128;
+  TimedScope ts(s, std::string(g_stage) + ".axis0", (double)P * n * na * 6 * sizeof(T));
+  hipLaunchKernelGGL((k_accum_radial<T, N, D>), dim3((unsigned)((nl + bs - 1) / bs)), dim3(bs), 0,
+                     s, tmp, G, fw, nkk, P, a0, na, nl);
+  BLR_CHECK_LAUNCH();
 }
 
 // transform of the rows bidx of V: directly when they are the rows 0..rb-1
@@ -191,10 +224,13 @@ __global__ __launch_bounds__(256) void k_sigma_reduce(const T* __restrict__ sh, 
                                                       ReduceTile tile, const T* __restrict__ wbp,
                                                       const int* __restrict__ bp_b,
                                                       const int* __restrict__ bp_bb, int n,
-                                                      int mrho, int msig, int nbp, int a) {
+                                                      int mrho, int msig, int nbp, int a0,
+                                                      long pstride) {
+  // radial node a0 + blockIdx.y, its products at pa + blockIdx.y pstride
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
-  sigma_reduce_point<T, G, DIAG>(q, sh, pa, tile, wbp, bp_b, bp_bb, n, mrho, msig, nbp, a);
+  sigma_reduce_point<T, G, DIAG>(q, sh, pa + blockIdx.y * pstride, tile, wbp, bp_b, bp_bb, n, mrho,
+                                 msig, nbp, a0 + (int)blockIdx.y);
 }
 
 // The same sums for pairs (i, i) only (every pair of the full-tensor step):
@@ -205,11 +241,13 @@ __global__ __launch_bounds__(256) void k_sigma_self(const T* __restrict__ sh, T*
                                                     const T* __restrict__ wbp,
                                                     const int* __restrict__ bp_b,
                                                     const int* __restrict__ bp_bb, int n, int mrho,
-                                                    int msig, int nbp, int a) {
+                                                    int msig, int nbp, int a0, long pstride) {
+  // radial node a0 + blockIdx.z, its products at pa + blockIdx.z pstride
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
   if (q >= n) return;
-  sigma_self_point<T>(q, p, sh, pa, pi, wbp, bp_b, bp_bb, n, mrho, msig, nbp, a);
+  sigma_self_point<T>(q, p, sh, pa + blockIdx.z * pstride, pi, wbp, bp_b, bp_bb, n, mrho, msig, nbp,
+                      a0 + (int)blockIdx.z);
 }
 
 // ------------------------------------------------------------ utilities
@@ -371,12 +409,13 @@ struct Generic {
     return !pl.li.empty();
   }
 
+  // radial nodes a0 .. a0 + na - 1, node k's products at Pa + k P n
   static void sigma_self(hipStream_t s, const char* name, const T* Sh, T* Pa, const int* dli,
                          const T* wbp, const int* bp_b, const int* bp_bb, int mrho, int msig,
-                         int nbp, int a, int P) {
-    TimedScope ts(s, name, (double)n * P * (2 * nbp + 1) * sizeof(T));
-    hipLaunchKernelGGL(k_sigma_self<T>, dim3((n + 255) / 256, P), dim3(256), 0, s, Sh, Pa, dli, wbp,
-                       bp_b, bp_bb, n, mrho, msig, nbp, a);
+                         int nbp, int a0, int P, int na = 1) {
+    TimedScope ts(s, name, (double)n * P * na * (2 * nbp + 1) * sizeof(T));
+    hipLaunchKernelGGL(k_sigma_self<T>, dim3((n + 255) / 256, P, na), dim3(256), 0, s, Sh, Pa, dli,
+                       wbp, bp_b, bp_bb, n, mrho, msig, nbp, a0, (long)P * n);
     BLR_CHECK_LAUNCH();
   }
 
@@ -389,8 +428,9 @@ struct Generic {
     b += (size_t)rb * n * sizeof(T2);                      // Vh
     b += (size_t)2 * rb * n * sizeof(T);                   // Vp, Lam
     b += (size_t)rb * h.mrho * h.msig * n * sizeof(T);     // shifts
-    b += (size_t)std::max<long>(batch, std::max<long>(nc, 2 * rb)) * n * sizeof(T2);  // tmp
-    b += (size_t)P * n * sizeof(T);                        // Pa
+    const long cr = (h.carleman || h.aniso_n > 0) ? 1 : radial_chunk(h.mrho, nc, n, sizeof(T));
+    b += (size_t)std::max<long>(batch, std::max<long>(cr * nc, 2 * rb)) * n * sizeof(T2);  // tmp
+    b += (size_t)cr * P * n * sizeof(T);                   // Pa
     b += (size_t)nc * n * sizeof(T2);                      // G
     return b;
   }
@@ -454,17 +494,17 @@ struct Generic {
       if (sizeof(T) == 4) {
         if (diag)
           hipLaunchKernelGGL((k_sigma_reduce<T, 12, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
-                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0);
+                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0, 0L);
         else
           hipLaunchKernelGGL((k_sigma_reduce<T, 12, false>), grid, dim3(bs), 0, s, Sh, Pa, t,
-                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0);
+                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0, 0L);
       } else {
         if (diag)
           hipLaunchKernelGGL((k_sigma_reduce<T, 8, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
-                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0);
+                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0, 0L);
         else
           hipLaunchKernelGGL((k_sigma_reduce<T, 8, false>), grid, dim3(bs), 0, s, Sh, Pa, t,
-                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0);
+                             (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, 1, h.msig, h.nbp, 0, 0L);
       }
       BLR_CHECK_LAUNCH();
     }
@@ -486,9 +526,11 @@ struct Generic {
     const long batch = std::min<long>(shift_fields, 512);
     const std::string tag = std::string("gen") + (sizeof(T) == 4 ? "f" : "d");
     T* Sh = (T*)ctx->buf(tag + ".Sh", (size_t)rb * h.mrho * h.msig * n * sizeof(T));
-    T2* tmp = (T2*)ctx->buf(tag + ".tmp",
-                            (size_t)std::max<long>(batch, std::max<long>(nc, 2 * rb)) * n * sizeof(T2));
-    T* Pa = (T*)ctx->buf(tag + ".Pa", (size_t)P * n * sizeof(T));
+    // the isotropic form keeps the products of a chunk of radial nodes
+    const long cr = (h.carleman || h.aniso_n > 0) ? 1 : radial_chunk(h.mrho, nc, n, sizeof(T));
+    T2* tmp = (T2*)ctx->buf(
+        tag + ".tmp", (size_t)std::max<long>(batch, std::max<long>(cr * nc, 2 * rb)) * n * sizeof(T2));
+    T* Pa = (T*)ctx->buf(tag + ".Pa", (size_t)cr * P * n * sizeof(T));
     T2* G = h.carleman ? nullptr : (T2*)ctx->buf(tag + ".G", (size_t)nc * n * sizeof(T2));
     // per-call index arrays (pi, pj, prow) through the pinned stage
     std::vector<int> idx(3 * P);
@@ -544,17 +586,17 @@ struct Generic {
             if (sizeof(T) == 4) {
               if (diag)
                 hipLaunchKernelGGL((k_sigma_reduce<T, 12, true>), grid, dim3(256), 0, s, Sh, Pa, t,
-                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a);
+                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a, 0L);
               else
                 hipLaunchKernelGGL((k_sigma_reduce<T, 12, false>), grid, dim3(256), 0, s, Sh, Pa,
-                                   t, w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a);
+                                   t, w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a, 0L);
             } else {
               if (diag)
                 hipLaunchKernelGGL((k_sigma_reduce<T, 8, true>), grid, dim3(256), 0, s, Sh, Pa, t,
-                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a);
+                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a, 0L);
               else
                 hipLaunchKernelGGL((k_sigma_reduce<T, 8, false>), grid, dim3(256), 0, s, Sh, Pa, t,
-                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a);
+                                   w1, tb.bp_b + bp, tb.bp_bb + bp, n, h.mrho, h.msig, 1, a, 0L);
             }
             BLR_CHECK_LAUNCH();
           }
@@ -562,37 +604,48 @@ struct Generic {
                                  StAccumTab<T>{G, atab + ((size_t)a * h.nbp + bp) * n, n}, tmp, nc);
         }
     }
-    for (int a = 0; a < h.mrho && h.aniso_n == 0; ++a) {
+    // radial nodes in chunks of ca: the sums of a chunk in one launch per
+    // tile, the first axes of its pair transforms in one pass, the last axis
+    // with the radial weights node after node in one more
+    const int ca = radial_chunk(h.mrho, nc, n, sizeof(T));
+    for (int a0 = 0; a0 < h.mrho && h.aniso_n == 0; a0 += ca) {
+      const int na = std::min(ca, h.mrho - a0);
       if (self)
         sigma_self(s, "gen.sigma_self", Sh, Pa, didx, (const T*)tb.wbp, tb.bp_b, tb.bp_bb, h.mrho,
-                   h.msig, h.nbp, a, P);
+                   h.msig, h.nbp, a0, P, na);
       for (const auto& t : tiles) {
         const bool diag = t.bi[0] == t.bj[0];
         const int bs = 64;  // more workgroups than CUs even at 32^3
-        const dim3 grid((n + bs - 1) / bs);
+        const dim3 grid((n + bs - 1) / bs, na);
+        const long ps = (long)P * n;
         int nvalid = 0;
         for (int k = 0; k < 256; ++k) nvalid += t.out[k] >= 0;
         const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
-        TimedScope ts(s, "gen.sigma_reduce", (double)n * (nload * h.nbp + nvalid) * sizeof(T));
+        TimedScope ts(s, "gen.sigma_reduce",
+                      (double)n * na * (nload * h.nbp + nvalid) * sizeof(T));
         if (sizeof(T) == 4) {
           if (diag)
             hipLaunchKernelGGL((k_sigma_reduce<T, 12, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
-                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a);
+                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a0,
+                               ps);
           else
             hipLaunchKernelGGL((k_sigma_reduce<T, 12, false>), grid, dim3(bs), 0, s, Sh, Pa, t,
-                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a);
+                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a0,
+                               ps);
         } else {
           if (diag)
             hipLaunchKernelGGL((k_sigma_reduce<T, 8, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
-                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a);
+                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a0,
+                               ps);
           else
             hipLaunchKernelGGL((k_sigma_reduce<T, 8, false>), grid, dim3(bs), 0, s, Sh, Pa, t,
-                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a);
+                               (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a0,
+                               ps);
         }
         BLR_CHECK_LAUNCH();
       }
-      transform<T, N, D, -1>(s, LdPair1<T>{Pa, n}, StAccumF<T, N, D>{G, fw + (size_t)a * h.nkk, n},
-                             tmp, nc);
+      first_axes<T, N, D, -1>(s, LdPair1<T>{Pa, n}, StComplex<T>{tmp, n}, (long)na * nc);
+      accum_radial<T, N, D>(s, tmp, G, fw, h.nkk, nc, a0, na);
     }
     // 5. back to velocity space, minus the loss
     g_stage = "gen.final";
@@ -943,8 +996,10 @@ size_t collision_call_bytes(const HostTables& h, int prec, int r, const int32_t*
     const size_t shift_fields = rb * h.mrho * h.nbp;
     const size_t batch = std::min<size_t>(shift_fields, 512);
     g += up256(rb * h.mrho * h.msig * n * T);                                // shifts
-    g += up256(std::max(batch, std::max(P, 2 * rb)) * n * T2);              // transforms
-    g += up256(P * n * T);                                                   // products
+    const size_t cr =
+        (h.carleman || h.aniso_n > 0) ? 1 : (size_t)radial_chunk(h.mrho, (long)P, (long)n, T);
+    g += up256(std::max(batch, std::max(cr * P, 2 * rb)) * n * T2);         // transforms
+    g += up256(cr * P * n * T);                                              // products
     if (!h.carleman) g += up256(P * n * T2);                                 // spectra
     return g;
   };

@@ -63,6 +63,15 @@ struct PairPlan {
 
 // Tiles of the pair products: compact basis indices grouped by G; one tile per
 // (group, group) block that holds at least one requested pair.
+// Radial nodes whose sigma sums and pair transforms one pass of the general
+// path takes together (the products of all of them and their transforms are
+// held at once: P n values and P n complex values per node, up to 256 MB).
+inline int radial_chunk(int mrho, long P, long n, size_t tbytes) {
+  const double per = (double)P * (double)n * 3.0 * (double)tbytes;
+  const long c = (long)((256.0 * 1024 * 1024) / per);
+  return (int)std::max<long>(1, std::min<long>(mrho, c));
+}
+
 inline std::vector<ReduceTile> plan_tiles(int rb, const std::vector<int>& li, const std::vector<int>& lj,
                                           int G, bool& diag_only) {
   std::vector<ReduceTile> tiles;

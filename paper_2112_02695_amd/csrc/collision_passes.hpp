@@ -457,4 +457,29 @@ __host__ __device__ __forceinline__ void line_pass_thread(long t, const Ld& ld, 
   st.template store<N>(f, base, stride, re, im);
 }
 
+// One thread of the last axis of the pair transforms with the radial
+// weights: line t of the pairs (P of them) along axis 0, for the na radial
+// nodes a0.. in turn: the node's transformed product (field k P + p of tmp,
+// k = a - a0) is transformed and accumulated, weighted, into pair p's couple
+// spectrum.  Node after node, the same order of accumulation as one pass per
+// node.
+template <typename T, int N, int D>
+__host__ __device__ __forceinline__ void accum_radial_thread(long t,
+                                                             const typename Vec2<T>::t* tmp,
+                                                             typename Vec2<T>::t* G, const T* fw,
+                                                             int nkk, long P, int a0, int na) {
+  constexpr int lines = (D == 2 ? N : N * N);
+  constexpr int n = (D == 2 ? N * N : N * N * N);
+  const long p = t / lines;
+  const int base = (int)(t % lines);  // axis 0: stride = lines
+  const LdComplex<T> ld{tmp, n};
+  for (int k = 0; k < na; ++k) {
+    T re[N], im[N];
+    ld.template load<N>((long)k * P + p, base, lines, re, im);
+    fft::dft<T, N, -1>(re, im);
+    const StAccumF<T, N, D> st{G, fw + (size_t)(a0 + k) * nkk, n};
+    st.template store<N>(p, base, lines, re, im);
+  }
+}
+
 }  // namespace blr

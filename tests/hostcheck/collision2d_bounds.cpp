@@ -124,8 +124,10 @@ static void run_case(const blr_vgrid& vg, int r, bool conserve) {
   const long shift_fields = (long)rb * h.mrho * h.nbp;
   const long batch = std::min<long>(shift_fields, 512);
   T* Sh = exact<T>((size_t)rb * h.mrho * h.msig * n, "Sh");
-  T2* tmp = exact<T2>((size_t)std::max<long>(batch, std::max<long>(nc, 2 * rb)) * n, "tmp");
-  T* Pa = exact<T>((size_t)P * n, "Pa");
+  // the isotropic form keeps the products of a chunk of radial nodes
+  const long cr = h.carleman ? 1 : radial_chunk(h.mrho, nc, n, sizeof(T));
+  T2* tmp = exact<T2>((size_t)std::max<long>(batch, std::max<long>(cr * nc, 2 * rb)) * n, "tmp");
+  T* Pa = exact<T>((size_t)cr * P * n, "Pa");
   T2* G = h.carleman ? nullptr : exact<T2>((size_t)nc * n, "G");
   int* didx = exact<int>(3 * P, "idx");
   for (int p = 0; p < P; ++p) { didx[p] = li[p]; didx[P + p] = lj[p]; didx[2 * P + p] = prow[p]; }
@@ -139,15 +141,18 @@ static void run_case(const blr_vgrid& vg, int r, bool conserve) {
   bool diag_only = false;
   const int Gt = sizeof(T) == 4 ? 12 : 8;
   auto tiles = plan_tiles(rb, li, lj, Gt, diag_only);
-  auto reduce = [&](const ReduceTile& t, const T* w, const int* b1, const int* b2, int nbp, int a) {
+  // node a's products at Pa + k P n (k = a - a0, grid.y of the launch)
+  auto reduce = [&](const ReduceTile& t, const T* w, const int* b1, const int* b2, int nbp, int a,
+                    int k) {
     const bool diag = t.bi[0] == t.bj[0];
+    T* pk = Pa + (size_t)k * P * n;
     for (int q = 0; q < n; ++q) {
       if (sizeof(T) == 4) {
-        if (diag) sigma_reduce_point<T, 12, true>(q, Sh, Pa, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
-        else sigma_reduce_point<T, 12, false>(q, Sh, Pa, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
+        if (diag) sigma_reduce_point<T, 12, true>(q, Sh, pk, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
+        else sigma_reduce_point<T, 12, false>(q, Sh, pk, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
       } else {
-        if (diag) sigma_reduce_point<T, 8, true>(q, Sh, Pa, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
-        else sigma_reduce_point<T, 8, false>(q, Sh, Pa, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
+        if (diag) sigma_reduce_point<T, 8, true>(q, Sh, pk, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
+        else sigma_reduce_point<T, 8, false>(q, Sh, pk, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
       }
     }
   };
@@ -177,9 +182,18 @@ static void run_case(const blr_vgrid& vg, int r, bool conserve) {
                              StShiftSplit<T>{Sh, bp_b, bp_bb, n, h.mrho, h.nbp, h.msig, f0}, tmp, nb);
     }
     for (long i = 0; i < 2 * nc * n; ++i) ((T*)G)[i] = T(0);
-    for (int a = 0; a < h.mrho; ++a) {
-      for (const auto& t : tiles) reduce(t, wbp, bp_b, bp_bb, h.nbp, a);
-      transform<T, N, D, -1>(LdPair1<T>{Pa, n}, StAccumF<T, N, D>{G, fw + (size_t)a * h.nkk, n}, tmp, nc);
+    for (int a0 = 0; a0 < h.mrho; a0 += (int)cr) {
+      const int na = std::min((int)cr, h.mrho - a0);
+      for (int k = 0; k < na; ++k)
+        for (const auto& t : tiles) reduce(t, wbp, bp_b, bp_bb, h.nbp, a0 + k, k);
+      // first axes of the chunk's pair transforms, then the last axis with
+      // the radial weights
+      line_pass<T, N, D, -1>(LdPair1<T>{Pa, n}, StComplex<T>{tmp, n}, D - 1, (long)na * nc);
+      constexpr int lines = (D == 2 ? N : N * N);
+      for (long t = 0; t < nc * lines; ++t) {
+        accum_radial_thread<T, N, D>(t, tmp, G, fw, h.nkk, nc, a0, na);
+        ++g_threads;
+      }
     }
     transform<T, N, D, +1>(LdComplex<T>{G, n}, StFinal<T>{Q, Vp, Lam, didx, didx + P, didx + 2 * P, n},
                            tmp, nc);
