@@ -146,6 +146,42 @@ static void plane_pass(hipStream_t s, const Ld& ld, const St& st, long nfields) 
   BLR_CHECK_LAUNCH();
 }
 
+// A whole 2D transform in one launch: each group of N threads takes one
+// field, one row (axis 1) per thread, then one column (axis 0) per thread,
+// the field passing through LDS in between (one component at a time).  The
+// line transforms are those of two line passes.
+template <typename T, int N, int DIR, class Ld, class St>
+__global__ __launch_bounds__(64) void k_field2d_pass(Ld ld, St st, long nfields) {
+  constexpr int PPB = planes_per_block<N>();
+  __shared__ T pl[PPB][N][N + 1];
+  const int q = threadIdx.x / N, u = threadIdx.x % N;
+  const long f = blockIdx.x * (long)PPB + q;
+  const bool ok = f < nfields;
+  T re[N], im[N];
+  if (ok) {
+    ld.template load<N>(f, u * N, 1, re, im);  // row u along axis 1
+    fft::dft<T, N, DIR>(re, im);
+#pragma unroll
+    for (int j = 0; j < N; ++j) pl[q][u][j] = re[j];
+  }
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) re[j] = pl[q][j][u];
+  }
+  __syncthreads();
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) pl[q][u][j] = im[j];
+  }
+  __syncthreads();
+  if (!ok) return;
+#pragma unroll
+  for (int j = 0; j < N; ++j) im[j] = pl[q][j][u];
+  fft::dft<T, N, DIR>(re, im);  // column u along axis 0
+  st.template store<N>(f, u, N, re, im);
+}
+
 // every axis of a D-dimensional transform but the last (0): axis D-1 loaded
 // through ld, the result stored through st; in 3D the axes 2 and 1 in one
 // plane pass
@@ -162,6 +198,18 @@ template <typename T, int N, int D, int DIR, class Ld, class St>
 static void transform(hipStream_t s, const Ld& ld, const St& st, typename Vec2<T>::t* tmp,
                       long nfields) {
   constexpr int n = (D == 2 ? N * N : N * N * N);
+  if constexpr (D == 2) {
+    // the whole field in one pass
+    constexpr int PPB = planes_per_block<N>();
+    TimedScope ts(s, std::string(g_stage) + ".axis10",
+                  (double)nfields * n * (Ld::bpe + St::bpe) * sizeof(T));
+    hipLaunchKernelGGL((k_field2d_pass<T, N, DIR, Ld, St>),
+                       dim3((unsigned)((nfields + PPB - 1) / PPB)), dim3(PPB * N), 0, s, ld, st,
+                       nfields);
+    BLR_CHECK_LAUNCH();
+    (void)tmp;
+    return;
+  }
   StComplex<T> stc{tmp, n};
   LdComplex<T> ldc{tmp, n};
   first_axes<T, N, D, DIR>(s, ld, stc, nfields);
