@@ -995,15 +995,19 @@ void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q,
   // shift of the first pass: 11 (rows r + r (r + 1)) u ||A||_F^2 (shifted CholeskyQR3)
   const double u53 = std::ldexp(1.0, -53);
   const double shift0 = 11.0 * ((double)rows * r + (double)r * (r + 1)) * u53;
-  if (rows <= 512) {
-    // short matrices: all three passes in one workgroup
+  if (rows <= 1024) {
+    // short matrices (up to a 32^2 velocity grid): all three passes in one
+    // workgroup
     auto small = [&](auto rm) {
       constexpr int RM = decltype(rm)::value;
       if (rows <= 256)
         hipLaunchKernelGGL((la::k_cqr_small<RM, 1>), dim3(1), dim3(256), 0, s, A, lda, rows, r,
                            in_scale, out_scale, shift0, Q, ldq, R_rowmajor, flag);
-      else
+      else if (rows <= 512)
         hipLaunchKernelGGL((la::k_cqr_small<RM, 2>), dim3(1), dim3(256), 0, s, A, lda, rows, r,
+                           in_scale, out_scale, shift0, Q, ldq, R_rowmajor, flag);
+      else
+        hipLaunchKernelGGL((la::k_cqr_small<RM, 4>), dim3(1), dim3(256), 0, s, A, lda, rows, r,
                            in_scale, out_scale, shift0, Q, ldq, R_rowmajor, flag);
       BLR_CHECK_LAUNCH();
     };
