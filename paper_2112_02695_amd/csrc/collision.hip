@@ -262,6 +262,12 @@ static void transform_rows(hipStream_t s, const T* V, const std::vector<int>& bi
   transform<T, N, D, DIR>(s, LdRealIdx<T>{V, n, idx}, st, tmp, rb);
 }
 
+// FP64 sigma sums of the isotropic general path: up to 12 basis functions in
+// one diagonal 12-wide tile (one pass over the shifts instead of three 8-wide
+// tiles); more functions keep 8-wide tiles (the 12-wide off-diagonal tile
+// fits only one wave per SIMD).
+inline bool wide_tiles64(int rb) { return rb <= 12; }
+
 // ------------------------------------------------------------- sigma reduce
 // One thread per grid point; a tile of basis functions (ni on the left, nj on
 // the right, or one set of ni on both sides for a diagonal tile) whose pair
@@ -610,7 +616,7 @@ struct Generic {
     // 3-4. sigma sums, transforms and radial weights, one radial node at a time
     fill<T>(s, (T*)G, 2 * nc * n, T(0));
     bool diag_only = false;
-    const int Gt = sizeof(T) == 4 ? 12 : 8;
+    const int Gt = (sizeof(T) == 4 || (h.aniso_n == 0 && wide_tiles64(rb))) ? 12 : 8;
     const bool self = self_only(pl);
     auto tiles = self ? std::vector<ReduceTile>{} : plan_tiles(rb, pl.li, pl.lj, Gt, diag_only);
     g_stage = "gen.pairfft";
@@ -671,7 +677,7 @@ struct Generic {
         const int nload = diag ? 2 * t.ni : 2 * (t.ni + t.nj);
         TimedScope ts(s, "gen.sigma_reduce",
                       (double)n * na * (nload * h.nbp + nvalid) * sizeof(T));
-        if (sizeof(T) == 4) {
+        if (Gt == 12) {
           if (diag)
             hipLaunchKernelGGL((k_sigma_reduce<T, 12, true>), grid, dim3(bs), 0, s, Sh, Pa, t,
                                (const T*)tb.wbp, tb.bp_b, tb.bp_bb, n, h.mrho, h.msig, h.nbp, a0,

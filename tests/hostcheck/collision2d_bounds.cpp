@@ -139,15 +139,19 @@ static void run_case(const blr_vgrid& vg, int r, bool conserve) {
   transform<T, N, D, +1>(LdBasisMode<T>{Vh, gloss, n, rb}, StRe<T>{Vp, n}, btmp, 2 * rb);
   T* Lam = Vp + (size_t)rb * n;
   bool diag_only = false;
+  // the Carleman form's tiles; the isotropic form's (12 wide in FP64 too up
+  // to 12 basis functions) below
   const int Gt = sizeof(T) == 4 ? 12 : 8;
   auto tiles = plan_tiles(rb, li, lj, Gt, diag_only);
+  const int Gi = (sizeof(T) == 4 || rb <= 12) ? 12 : 8;
+  auto tiles_iso = plan_tiles(rb, li, lj, Gi, diag_only);
   // node a's products at Pa + k P n (k = a - a0, grid.y of the launch)
   auto reduce = [&](const ReduceTile& t, const T* w, const int* b1, const int* b2, int nbp, int a,
                     int k) {
     const bool diag = t.bi[0] == t.bj[0];
     T* pk = Pa + (size_t)k * P * n;
     for (int q = 0; q < n; ++q) {
-      if (sizeof(T) == 4) {
+      if (Gi == 12) {
         if (diag) sigma_reduce_point<T, 12, true>(q, Sh, pk, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
         else sigma_reduce_point<T, 12, false>(q, Sh, pk, t, w, b1, b2, n, h.mrho, h.msig, nbp, a);
       } else {
@@ -185,7 +189,7 @@ static void run_case(const blr_vgrid& vg, int r, bool conserve) {
     for (int a0 = 0; a0 < h.mrho; a0 += (int)cr) {
       const int na = std::min((int)cr, h.mrho - a0);
       for (int k = 0; k < na; ++k)
-        for (const auto& t : tiles) reduce(t, wbp, bp_b, bp_bb, h.nbp, a0 + k, k);
+        for (const auto& t : tiles_iso) reduce(t, wbp, bp_b, bp_bb, h.nbp, a0 + k, k);
       // first axes of the chunk's pair transforms, then the last axis with
       // the radial weights
       line_pass<T, N, D, -1>(LdPair1<T>{Pa, n}, StComplex<T>{tmp, n}, D - 1, (long)na * nc);
