@@ -1195,7 +1195,8 @@ size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec) {
   // host a good fraction of a second at 32^3: one build per grid (a server
   // estimates every request it admits)
   static std::mutex mu;
-  static std::map<std::string, std::array<int, 5>> shapes;  // d, N, mrho, msig, nbp
+  // d, N, mrho, msig, nbp, carleman, aniso_n
+  static std::map<std::string, std::array<int, 7>> shapes;
   std::string key((const char*)&vg, sizeof(vg));
   HostTables h;
   {
@@ -1203,13 +1204,16 @@ size_t collision_workspace_bytes(const blr_vgrid& vg, int r, int prec) {
     auto it = shapes.find(key);
     if (it == shapes.end()) {
       const HostTables t = build_tables(vg);
-      it = shapes.emplace(key, std::array<int, 5>{t.d, t.N, t.mrho, t.msig, t.nbp}).first;
+      it = shapes.emplace(key, std::array<int, 7>{t.d, t.N, t.mrho, t.msig, t.nbp,
+                                                  t.carleman ? 1 : 0, t.aniso_n}).first;
     }
     h.d = it->second[0];
     h.N = it->second[1];
     h.mrho = it->second[2];
     h.msig = it->second[3];
     h.nbp = it->second[4];
+    h.carleman = it->second[5] != 0;
+    h.aniso_n = it->second[6];
   }
   const int P = r * (r + 1) / 2;
   size_t out = 0;
