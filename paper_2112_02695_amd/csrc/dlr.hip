@@ -2503,8 +2503,21 @@ static void dlr_step2d(blr_ctx ctx, const blr_problem* pb, blr_state* st,
     tsqr(ctx, Fb, n, n, nft, nullptr, n, Rb, "qr2.fb", 1.0, 1.0);   // R only
     double* sbd = w.get("d2.sb", (size_t)nft);
     double* Wb = w.get("d2.Wb", (size_t)nft * nft);
-    svd_small(ctx, Rb, nft, Ub, sbd, Wb, true, false);   // only columns with sig > add_tol are used
+    // Rb = Wq diag(sig) Ub^T, so Ub (the left singular vectors of Rb^T) comes
+    // out as the right singular vectors of Rb; they are coordinates over the
+    // boundary rows, which change little from step to step, so the rotations
+    // start from the previous step's (any orthogonal start gives the same
+    // factorisation; a fresh start every 64 steps keeps the start's rounding
+    // from piling up).  Only the columns with sig > add_tol are used.
+    double* Ww = w.get("d2.Wwarm", (size_t)64 * 64);
+    const bool warm = ctx->bsvd_n == nft && ctx->bsvd_age < 64;
+    svd_small(ctx, Rb, nft, Wb, sbd, Ub, false, false, warm ? Ww : nullptr);
+    BLR_HIP(hipMemcpyAsync(Ww, Ub, (size_t)nft * nft * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ctx->bsvd_n = nft;
+    ctx->bsvd_age = warm ? ctx->bsvd_age + 1 : 0;
     const std::vector<double> sig = dev2host(sbd, (size_t)nft);
+    for (double v : sig)
+      if (!std::isfinite(v)) ctx->bsvd_n = 0;  // no start kept from a failed factorisation
     int rb = 0;
     for (int i = 0; i < nft; ++i) rb += sig[i] > sp->add_tol;
     rb = std::min(rb, r_max_g - r);

@@ -151,6 +151,9 @@ struct blr_ctx_t {
   // "dlr.defect.D" and "dlr.defect.V"
   int defect_r = 0;
   blr_vgrid defect_vg{};
+  // the 2D step's boundary-factor SVD: the size of the right singular vectors
+  // kept in "dlr.d2.Wwarm" (0: none) and the steps since a fresh start
+  int bsvd_n = 0, bsvd_age = 0;
   // compute units of the device (queried once)
   int ncu = 0;
   int cu_count();

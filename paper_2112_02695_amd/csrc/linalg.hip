@@ -523,13 +523,18 @@ __device__ __forceinline__ double half_allsum(double x) {
 // GL = 32; pair slot k to group k mod 1024 / GL), a pair's rows to the lanes
 // of its group (64 / GL rows each), its three column sums are group sums;
 // the rounds are ordered by workgroup barriers.  The same circle-method
-// pairing, rotation and stopping rule as k_svd_jacobi.
+// pairing, rotation and stopping rule as k_svd_jacobi.  With W0 (r x r
+// orthogonal, row-major like W) the rotations start from B = A W0, V = W0
+// instead of A and the identity: any orthogonal start gives the SVD of A,
+// and a start near A's right singular vectors (the previous step's, for a
+// matrix that changes little from step to step) leaves few rotations.
 template <int GL>
 __global__ __launch_bounds__(1024) void k_svd_jacobi_wide(const double* __restrict__ A, int r,
                                                          double* __restrict__ U,
                                                          double* __restrict__ sig,
                                                          double* __restrict__ W, int sweeps,
-                                                         int trans, int complete) {
+                                                         int trans, int complete,
+                                                         const double* __restrict__ W0) {
   constexpr int NG = 1024 / GL, RPL = 64 / GL;
   __shared__ double B[64 * SVS];  // column c: B[c * SVS + i]
   __shared__ double V[64 * SVS];
@@ -554,6 +559,22 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi_wide(const double* __restri
   __syncthreads();
   fro2 = 0.0;
   for (int k = 0; k < 16; ++k) fro2 += part[k];
+  if (W0) {
+    // B <- B W0 (through V), then V <- W0
+    for (int e = t; e < r * r; e += blockDim.x) {
+      const int c = e / r, row = e % r;
+      double s = 0.0;
+      for (int k = 0; k < r; ++k) s += B[k * SVS + row] * W0[k * r + c];
+      V[c * SVS + row] = s;
+    }
+    __syncthreads();
+    for (int e = t; e < r * r; e += blockDim.x) {
+      const int c = e / r, row = e % r;
+      B[c * SVS + row] = V[c * SVS + row];
+      V[c * SVS + row] = W0[row * r + c];
+    }
+    __syncthreads();
+  }
   const double tiny2 = 1e-30 * fro2;  // see k_svd_jacobi
   const double tol2 = fmax(1e-30, 2e-31 * r);
   const int rr = (r % 2) ? r + 1 : r;
@@ -1053,17 +1074,17 @@ void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q,
 }
 
 void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W, bool trans,
-               bool complete) {
+               bool complete, const double* W0) {
   require(r >= 1 && r <= 64, "svd: r must be in [1, 64]");
   if (r <= 16)
     hipLaunchKernelGGL(la::k_svd_jacobi, dim3(1), dim3(64), 0, ctx->stream, A, r, U, sig, W, 40,
                        trans ? 1 : 0, complete ? 1 : 0);
   else if (r <= 32)
     hipLaunchKernelGGL(la::k_svd_jacobi_wide<64>, dim3(1), dim3(1024), 0, ctx->stream, A, r, U, sig,
-                       W, 40, trans ? 1 : 0, complete ? 1 : 0);
+                       W, 40, trans ? 1 : 0, complete ? 1 : 0, W0);
   else
     hipLaunchKernelGGL(la::k_svd_jacobi_wide<32>, dim3(1), dim3(1024), 0, ctx->stream, A, r, U, sig,
-                       W, 40, trans ? 1 : 0, complete ? 1 : 0);
+                       W, 40, trans ? 1 : 0, complete ? 1 : 0, W0);
   BLR_CHECK_LAUNCH();
 }
 

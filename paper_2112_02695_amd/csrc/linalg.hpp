@@ -28,7 +28,9 @@ void cholqr(blr_ctx ctx, const double* A, long lda, long rows, int r, double* Q,
 // A = U diag(sig) W^T for an r x r row-major A (U, W row-major; sig descending).
 // trans: factor A^T (A is read transposed).  complete: U's columns of
 // underflowing sigma are completed to an orthonormal U (else left zero).
+// W0 (used for r > 16; nullptr: the identity): an orthogonal r x r start for
+// the right singular vectors, row-major like W.
 void svd_small(blr_ctx ctx, const double* A, int r, double* U, double* sig, double* W,
-               bool trans = false, bool complete = true);
+               bool trans = false, bool complete = true, const double* W0 = nullptr);
 
 }  // namespace blr
